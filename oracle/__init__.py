@@ -1,0 +1,253 @@
+"""CPU oracle for the best-hit path -- TEST INFRASTRUCTURE ONLY.
+
+Thin ctypes wrapper around ``pdp_oracle.c`` (a plain C rendering of the
+paper's definitions: k rule, Alg. 1 multiplicity vectors, Eq. jaccard_k,
+Eq. best_hit with ties, Eq. bidirectional_best_hit and Alg. 3), plus
+``brute`` (the same definitions on Python strings, for tiny inputs).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this package.  It shares no code with the GPU library and never loads it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pdp_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libpdp_oracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no vectorisation tricks)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    lib = C.CDLL(build())
+    u32, u64, i64, vp = C.c_uint32, C.c_uint64, C.c_int64, C.c_void_p
+    P = C.POINTER
+    sig = {
+        "orc_k_rule": (C.c_int, [u64, u32, C.c_int, P(u32)]),
+        "orc_n_windows": (i64, [i64, u32]),
+        "orc_mv": (i64, [C.c_char_p, i64, u32, P(u64), P(u32), P(i64)]),
+        "orc_genome_new": (vp, [vp, vp, u32, u32, P(i64)]),
+        "orc_genome_free": (None, [vp]),
+        "orc_genome_n": (u32, [vp]),
+        "orc_genome_entries": (u64, [vp]),
+        "orc_genome_ptr": (P(u64), [vp]),
+        "orc_genome_ids": (P(u64), [vp]),
+        "orc_genome_cnt": (P(u32), [vp]),
+        "orc_genome_nwin": (P(u64), [vp]),
+        "orc_jaccard_terms": (None, [P(u64), P(u32), u64, P(u64), P(u32), u64, P(u64), P(u64)]),
+        "orc_compare_j": (C.c_int, [u64, u64, u64, u64]),
+        "orc_pair_terms": (None, [vp, u32, vp, u32, P(u64), P(u64)]),
+        "orc_bh_rows": (vp, [vp, vp, vp, u32, C.c_int]),
+        "orc_bh_free": (None, [vp]),
+        "orc_bh_nrows": (u32, [vp]),
+        "orc_bh_ptr": (P(u64), [vp]),
+        "orc_bh_col": (P(u32), [vp]),
+        "orc_bh_num": (P(u64), [vp]),
+        "orc_bh_den": (P(u64), [vp]),
+        "orc_bbh": (vp, [vp, vp]),
+        "orc_bbh_alg3": (vp, [vp, vp, vp, vp]),
+        "orc_pairs_free": (None, [vp]),
+        "orc_pairs_n": (u64, [vp]),
+        "orc_pairs_a": (P(u32), [vp]),
+        "orc_pairs_b": (P(u32), [vp]),
+        "orc_pairs_num": (P(u64), [vp]),
+        "orc_pairs_den": (P(u64), [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _arr(ptr, n, dtype):
+    if n == 0:
+        return np.zeros(0, dtype=dtype)
+    return np.ctypeslib.as_array(ptr, shape=(n,)).astype(dtype, copy=True)
+
+
+def default_threads() -> int:
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except Exception:  # pragma: no cover
+        return max(1, os.cpu_count() or 1)
+
+
+def k_rule(total: int, alphabet: int = 20, mode: int = 0) -> int:
+    """Eq. k_length in integers: mode 0 = smallest k with alphabet^k >= total, 1 = largest k with alphabet^k <= total."""
+    k = C.c_uint32(0)
+    if _load().orc_k_rule(int(total), int(alphabet), int(mode), C.byref(k)) != 0:
+        raise ValueError("alphabet must be >= 2")
+    return int(k.value)
+
+
+def n_windows(length: int, k: int) -> int:
+    return int(_load().orc_n_windows(int(length), int(k)))
+
+
+def mv(gene: bytes, k: int):
+    """Alg. 1 for one gene: (ids ascending, multiplicities); ids are base-20 values of the windows."""
+    lib = _load()
+    nw = max(1, n_windows(len(gene), k))
+    ids = (C.c_uint64 * nw)()
+    cnt = (C.c_uint32 * nw)()
+    bad = C.c_int64(-1)
+    d = lib.orc_mv(gene, len(gene), int(k), ids, cnt, C.byref(bad))
+    if d < 0:
+        raise ValueError(f"byte outside the alphabet at offset {bad.value}")
+    return np.array(ids[:d], dtype=np.uint64), np.array(cnt[:d], dtype=np.uint32)
+
+
+def decode_id(i: int, k: int) -> str:
+    """k-mer string of a base-20 identifier (for comparing dictionaries by content)."""
+    alpha = "ACDEFGHIKLMNPQRSTVWY"
+    s = []
+    for _ in range(k):
+        s.append(alpha[i % 20])
+        i //= 20
+    return "".join(reversed(s))
+
+
+class OracleGenome:
+    """Multiplicity vectors of every gene of one genome (residues + offsets)."""
+
+    def __init__(self, genome, k: int):
+        lib = _load()
+        self.k = int(k)
+        self._res = np.ascontiguousarray(genome.residues, dtype=np.uint8)
+        self._off = np.ascontiguousarray(genome.offsets, dtype=np.uint64)
+        n = int(self._off.shape[0] - 1)
+        bad = C.c_int64(-1)
+        h = lib.orc_genome_new(self._res.ctypes.data, self._off.ctypes.data, n, self.k, C.byref(bad))
+        if not h:
+            raise ValueError(f"byte outside the alphabet at residue offset {bad.value}")
+        self._h = h
+        self.n = n
+        e = int(lib.orc_genome_entries(h))
+        self.ptr = _arr(lib.orc_genome_ptr(h), n + 1, np.uint64)
+        self.ids = _arr(lib.orc_genome_ids(h), e, np.uint64)
+        self.cnt = _arr(lib.orc_genome_cnt(h), e, np.uint32)
+        self.nwin = _arr(lib.orc_genome_nwin(h), n, np.uint64)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_genome_free(h)
+            self._h = None
+
+    @property
+    def entries(self) -> int:
+        return int(self.ptr[-1])
+
+    def mv(self, i: int):
+        a, b = int(self.ptr[i]), int(self.ptr[i + 1])
+        return self.ids[a:b], self.cnt[a:b]
+
+    def terms(self, a: int, other: "OracleGenome", b: int):
+        """(sum of minima over the intersection, sum of maxima over the union) for genes a, b."""
+        m = C.c_uint64(0)
+        d = C.c_uint64(0)
+        _load().orc_pair_terms(self._h, int(a), other._h, int(b), C.byref(m), C.byref(d))
+        return int(m.value), int(d.value)
+
+
+def compare_j(m1: int, d1: int, m2: int, d2: int) -> int:
+    return int(_load().orc_compare_j(m1, d1, m2, d2))
+
+
+@dataclass
+class BH:
+    """Best hits in CSR form: row r's hits are col[ptr[r]:ptr[r+1]] ascending, with
+    num = sum of minima, den = sum of maxima of each hit."""
+
+    rows: np.ndarray
+    ptr: np.ndarray
+    col: np.ndarray
+    num: np.ndarray
+    den: np.ndarray
+    _h: Optional[int] = None
+
+    def row(self, r: int):
+        a, b = int(self.ptr[r]), int(self.ptr[r + 1])
+        return self.col[a:b], self.num[a:b], self.den[a:b]
+
+    def __del__(self):
+        if self._h and _lib is not None:
+            _lib.orc_bh_free(self._h)
+            self._h = None
+
+
+def bh(q: OracleGenome, t: OracleGenome, rows: Optional[Sequence[int]] = None, threads: Optional[int] = None) -> BH:
+    """Eq. best_hit for the given rows of q (all rows when None) against genome t."""
+    lib = _load()
+    th = default_threads() if threads is None else int(threads)
+    if rows is None:
+        rws = np.arange(q.n, dtype=np.uint32)
+        h = lib.orc_bh_rows(q._h, t._h, None, 0, th)
+    else:
+        rws = np.ascontiguousarray(rows, dtype=np.uint32)
+        h = lib.orc_bh_rows(q._h, t._h, rws.ctypes.data, int(rws.shape[0]), th)
+    nr = int(lib.orc_bh_nrows(h))
+    ptr = _arr(lib.orc_bh_ptr(h), nr + 1, np.uint64)
+    nnz = int(ptr[-1])
+    return BH(rws, ptr, _arr(lib.orc_bh_col(h), nnz, np.uint32), _arr(lib.orc_bh_num(h), nnz, np.uint64),
+              _arr(lib.orc_bh_den(h), nnz, np.uint64), h)
+
+
+@dataclass
+class Pairs:
+    a: np.ndarray
+    b: np.ndarray
+    num: np.ndarray
+    den: np.ndarray
+
+
+def _pairs(h) -> Pairs:
+    lib = _load()
+    n = int(lib.orc_pairs_n(h))
+    p = Pairs(_arr(lib.orc_pairs_a(h), n, np.uint32), _arr(lib.orc_pairs_b(h), n, np.uint32),
+              _arr(lib.orc_pairs_num(h), n, np.uint64), _arr(lib.orc_pairs_den(h), n, np.uint64))
+    lib.orc_pairs_free(h)
+    return p
+
+
+def bbh(ab: BH, ba: BH) -> Pairs:
+    """Eq. bidirectional_best_hit (second condition taken in G_i); ab and ba must hold every row."""
+    return _pairs(_load().orc_bbh(ab._h, ba._h))
+
+
+def bbh_alg3(gi: OracleGenome, gj: OracleGenome, ab: BH, ba: BH) -> Pairs:
+    """Alg. 3's column-maximum procedure; must agree with bbh()."""
+    return _pairs(_load().orc_bbh_alg3(gi._h, gj._h, ab._h, ba._h))
+
+
+def all_pairs(genomes, k: int, threads: Optional[int] = None, pairs=None):
+    """BH both ways and BBH for every unordered genome pair i<j (or the given pairs)."""
+    og = [OracleGenome(g, k) for g in genomes]
+    if pairs is None:
+        pairs = [(i, j) for i in range(len(og)) for j in range(i + 1, len(og))]
+    out = {}
+    for i, j in pairs:
+        ab = bh(og[i], og[j], threads=threads)
+        ba = bh(og[j], og[i], threads=threads)
+        out[(i, j)] = (ab, ba, bbh(ab, ba))
+    return og, out

@@ -1,0 +1,234 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each pin is independent of the oracle's own code: hand-derived values
+(tests/golden/hand_examples.json), a brute-force restatement on Python strings,
+closed forms (k = 1 is the weighted Jaccard of residue counts; multiplicity-1
+dictionaries give the set Jaccard), and invariants (symmetry, J(g,g) = 1,
+sum of minima + sum of maxima = n_a + n_b, BBH inside both BH sets, the two
+BBH procedures agreeing, relabelling equivariance).
+"""
+import random
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from synth import genome_from_strings, make_config
+
+ALPHA = "ACDEFGHIKLMNPQRSTVWY"
+
+
+def _og(genes, k):
+    return oracle.OracleGenome(genome_from_strings(genes), k)
+
+
+def _bh_rows(bh):
+    return [[(int(c), int(n), int(d)) for c, n, d in zip(*bh.row(r))] for r in range(len(bh.rows))]
+
+
+# ----------------------------------------------------------------- hand values
+
+def test_windows_and_mv(golden):
+    for w in golden["windows"]:
+        k = w["k"]
+        assert oracle.n_windows(len(w["gene"]), k) == w["n"], w["id"]
+        ids, cnt = oracle.mv(w["gene"].encode(), k)
+        got = [[oracle.decode_id(int(i), k), int(c)] for i, c in zip(ids, cnt)]
+        assert got == w["mv"], w["id"]
+        assert int(cnt.sum()) == w["n"]
+
+
+def test_jaccard_hand_values(golden):
+    for e in golden["jaccard"]:
+        a, b = _og([e["a"]], e["k"]), _og([e["b"]], e["k"])
+        assert a.terms(0, b, 0) == (e["num"], e["den"]), e["id"]
+        assert brute.terms(e["a"], e["b"], e["k"]) == (e["num"], e["den"]), e["id"]
+
+
+def test_best_hits_hand_values(golden):
+    for e in golden["best_hits"]:
+        k = e["k"]
+        gi, gj = _og(e["gi"], k), _og(e["gj"], k)
+        ab, ba = oracle.bh(gi, gj, threads=2), oracle.bh(gj, gi, threads=2)
+        want_ij = [[tuple(x) for x in row] for row in e["bh_ij"]]
+        want_ji = [[tuple(x) for x in row] for row in e["bh_ji"]]
+        assert _bh_rows(ab) == want_ij, e["id"]
+        assert _bh_rows(ba) == want_ji, e["id"]
+        p = oracle.bbh(ab, ba)
+        assert [[int(x), int(y)] for x, y in zip(p.a, p.b)] == e["bbh"], e["id"]
+        p3 = oracle.bbh_alg3(gi, gj, ab, ba)
+        assert [[int(x), int(y)] for x, y in zip(p3.a, p3.b)] == e["bbh"], e["id"]
+        assert [list(t) for t in brute.bbh(e["gi"], e["gj"], k)] == e["bbh"], e["id"]
+
+
+def test_k_rule_hand_values(golden):
+    for e in golden["k_rule"]:
+        assert oracle.k_rule(e["total"], e["alphabet"], 0) == e["ceil"], e["id"]
+        assert oracle.k_rule(e["total"], e["alphabet"], 1) == e["floor"], e["id"]
+
+
+def test_k_rule_powers():
+    # exact powers and their neighbours, against integer arithmetic written independently
+    for a in (2, 4, 20):
+        for j in range(1, 14):
+            p = a ** j
+            assert oracle.k_rule(p, a, 0) == j and oracle.k_rule(p, a, 1) == j
+            assert oracle.k_rule(p + 1, a, 0) == j + 1 and oracle.k_rule(p + 1, a, 1) == j
+            if j >= 2:
+                assert oracle.k_rule(p - 1, a, 0) == j and oracle.k_rule(p - 1, a, 1) == j - 1
+
+
+def test_invalid_residue_is_reported():
+    with pytest.raises(ValueError):
+        oracle.mv(b"MKXLA", 2)
+    with pytest.raises(ValueError):
+        _og(["MKVLA", "ACDBQ"], 2)
+
+
+# ------------------------------------------------------------- brute force
+
+def _random_genes(rng, n, alpha, lo=0, hi=40):
+    return ["".join(rng.choice(alpha) for _ in range(rng.randint(lo, hi))) for _ in range(n)]
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_brute_force_tiny(seed):
+    rng = random.Random(1000 + seed)
+    alpha = ALPHA[: rng.choice([2, 3, 4, 20])]
+    k = rng.choice([1, 2, 3])
+    gi = _random_genes(rng, rng.randint(1, 8), alpha)
+    gj = _random_genes(rng, rng.randint(1, 8), alpha)
+    # duplicates force exact ties
+    if rng.random() < 0.5 and gj:
+        gj.append(gj[0])
+    oi, oj = _og(gi, k), _og(gj, k)
+    ab, ba = oracle.bh(oi, oj, threads=3), oracle.bh(oj, oi, threads=3)
+    want_ab = brute.all_best_hits(gi, gj, k)
+    want_ba = brute.all_best_hits(gj, gi, k)
+    assert _bh_rows(ab) == [want_ab[r] for r in range(len(gi))]
+    assert _bh_rows(ba) == [want_ba[r] for r in range(len(gj))]
+    p = oracle.bbh(ab, ba)
+    assert list(zip(p.a.tolist(), p.b.tolist())) == brute.bbh(gi, gj, k)
+    p3 = oracle.bbh_alg3(oi, oj, ab, ba)
+    assert list(zip(p3.a.tolist(), p3.b.tolist())) == brute.bbh(gi, gj, k)
+    for a in range(len(gi)):
+        for b in range(len(gj)):
+            assert oi.terms(a, oj, b) == brute.terms(gi[a], gj[b], k)
+
+
+# --------------------------------------------------------------- invariants
+
+def _hist(s):
+    return np.bincount([ALPHA.index(c) for c in s], minlength=20) if s else np.zeros(20, int)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_k1_is_weighted_jaccard_of_residue_counts(seed):
+    rng = random.Random(seed)
+    gi = _random_genes(rng, 5, ALPHA[:6], 1, 30)
+    gj = _random_genes(rng, 5, ALPHA[:6], 1, 30)
+    oi, oj = _og(gi, 1), _og(gj, 1)
+    for a in range(5):
+        for b in range(5):
+            ha, hb = _hist(gi[a]), _hist(gj[b])
+            assert oi.terms(a, oj, b) == (int(np.minimum(ha, hb).sum()), int(np.maximum(ha, hb).sum()))
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_multiplicity_one_is_set_jaccard(seed):
+    rng = random.Random(50 + seed)
+    k = 4
+    # random 20-letter genes of length <= 12 almost never repeat a 4-mer; skip any that do
+    genes = []
+    while len(genes) < 8:
+        s = "".join(rng.choice(ALPHA) for _ in range(rng.randint(4, 12)))
+        w = [s[p:p + k] for p in range(len(s) - k + 1)]
+        if len(set(w)) == len(w):
+            genes.append(s)
+    genes[1] = genes[0][:2] + genes[1][2:] if len(genes[1]) > 2 else genes[1]
+    og = _og(genes, k)
+    for a in range(len(genes)):
+        for b in range(len(genes)):
+            sa = {genes[a][p:p + k] for p in range(len(genes[a]) - k + 1)}
+            sb = {genes[b][p:p + k] for p in range(len(genes[b]) - k + 1)}
+            if len(sa) == len(genes[a]) - k + 1 and len(sb) == len(genes[b]) - k + 1:
+                assert og.terms(a, og, b) == (len(sa & sb), len(sa | sb))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_invariants(seed):
+    rng = random.Random(200 + seed)
+    alpha = ALPHA[: rng.choice([3, 5, 20])]
+    k = rng.choice([1, 2, 3])
+    gi = _random_genes(rng, 12, alpha, 0, 60)
+    gj = _random_genes(rng, 10, alpha, 0, 60)
+    oi, oj = _og(gi, k), _og(gj, k)
+    for a in range(len(gi)):
+        na = int(oi.nwin[a])
+        if na:
+            assert oi.terms(a, oi, a) == (na, na)  # J(g, g) = 1
+        for b in range(len(gj)):
+            m, d = oi.terms(a, oj, b)
+            assert (m, d) == oj.terms(b, oi, a)  # symmetry
+            assert m + d == na + int(oj.nwin[b])  # min + max = x + y, summed
+            assert 0 <= m <= d
+    ab, ba = oracle.bh(oi, oj), oracle.bh(oj, oi)
+    p = oracle.bbh(ab, ba)
+    for a, b in zip(p.a, p.b):
+        assert b in ab.row(a)[0] and a in ba.row(b)[0]
+    # BBH(A, B) is the transpose of BBH(B, A)
+    q = oracle.bbh(ba, ab)
+    assert sorted(zip(p.a.tolist(), p.b.tolist())) == sorted(zip(q.b.tolist(), q.a.tolist()))
+
+
+def test_relabelling_permutes_results():
+    rng = random.Random(7)
+    k = 2
+    gi = _random_genes(rng, 9, ALPHA[:4], 2, 30)
+    gj = _random_genes(rng, 7, ALPHA[:4], 2, 30)
+    pi = list(range(len(gi)))
+    pj = list(range(len(gj)))
+    rng.shuffle(pi)
+    rng.shuffle(pj)
+    oi, oj = _og(gi, k), _og(gj, k)
+    si, sj = _og([gi[x] for x in pi], k), _og([gj[x] for x in pj], k)
+    p = oracle.bbh(oracle.bh(oi, oj), oracle.bh(oj, oi))
+    s = oracle.bbh(oracle.bh(si, sj), oracle.bh(sj, si))
+    base = set(zip(p.a.tolist(), p.b.tolist()))
+    moved = {(pi[a], pj[b]) for a, b in zip(s.a.tolist(), s.b.tolist())}
+    assert base == moved
+
+
+def test_threads_do_not_change_results():
+    ds = make_config(2, genomes=2, genes=120)
+    k = 4
+    a, b = (oracle.OracleGenome(g, k) for g in ds.genomes)
+    r1, r8 = oracle.bh(a, b, threads=1), oracle.bh(a, b, threads=8)
+    for f in ("ptr", "col", "num", "den"):
+        assert np.array_equal(getattr(r1, f), getattr(r8, f))
+
+
+def test_row_subset_matches_full():
+    ds = make_config(2, genomes=2, genes=150)
+    k = 4
+    a, b = (oracle.OracleGenome(g, k) for g in ds.genomes)
+    full = oracle.bh(a, b)
+    rows = [5, 0, 149, 77]
+    part = oracle.bh(a, b, rows=rows)
+    for i, r in enumerate(rows):
+        for x, y in zip(part.row(i), full.row(r)):
+            assert np.array_equal(x, y)
+
+
+def test_planted_homologs_are_recovered():
+    """Sanity, not parity: on the tiny planted workload almost every planted pair is a BBH."""
+    ds = make_config(1)
+    k = oracle.k_rule(ds.total_residues(), 20, 0)
+    assert k == 4
+    og, res = oracle.all_pairs(ds.genomes, k)
+    ab, ba, p = res[(0, 1)]
+    got = set(zip(p.a.tolist(), p.b.tolist()))
+    planted = {(int(a), int(b)) for a, b in ds.meta["planted"]}
+    assert len(planted & got) >= 140
