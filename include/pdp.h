@@ -1,0 +1,267 @@
+/*
+ * pdp.h -- C-ABI of the MI355X (gfx950) best-hit library for PanDelos-plus.
+ *
+ * The library computes, for pairs of genomes, the generalised Jaccard
+ * similarity of every gene pair (Eq. jaccard_k), each gene's best hits in the
+ * other genome with ties kept (Eq. best_hit, the jagged array of Alg. 2) and
+ * the bidirectional best hits (Eq. bidirectional_best_hit, Alg. 3).  The
+ * problem statement it follows is the paper's Basic notions section: a
+ * genome is an ordered list of genes, a gene is a string over the amino-acid
+ * alphabet, and k is chosen by phase (a) (Eq. k_length).
+ *
+ * Conventions shared by every entry point
+ *  - Device buffers are allocated and owned by the caller.  The library never
+ *    frees caller memory and keeps no caller pointer after a call returns;
+ *    a pdp_plan keeps copies of the dictionary descriptors it was created
+ *    from, so those dictionaries must stay alive while the plan is used.
+ *  - "device" below means memory of the current HIP device; "host" means
+ *    ordinary process memory.
+ *  - Calls that take a stream only enqueue work on it (the stream is a
+ *    hipStream_t passed as void*, NULL = the default stream) and return after
+ *    synchronous validation.  Conditions found while the kernels run go to a
+ *    caller-provided device pdp_status, to be read after the stream has
+ *    synchronised.
+ *  - Return codes: PDP_OK (0) or a negative PDP_E_* code.  No C++ exception
+ *    crosses this boundary.  pdp_last_error() gives a message for the last
+ *    failing call on the calling thread.
+ *  - Integer results are exact; nothing on the path uses floating point.
+ */
+#ifndef PDP_H
+#define PDP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PDP_ABI_VERSION 1u
+
+/* Largest k: 5-bit residue codes of k <= 12 residues fit in 60 bits. */
+#define PDP_K_MAX 12u
+/* A gene may have at most this many k-mer windows (|g| - k + 1); longer genes
+ * are rejected with PDP_E_LIMIT in the device status.  Every multiplicity and
+ * every sum of minima then fits in 16 bits. */
+#define PDP_MAX_WINDOWS 65535u
+/* A genome may hold at most this many genes (column indices are 24-bit). */
+#define PDP_MAX_GENES 16777215u
+
+enum pdp_code {
+    PDP_OK = 0,
+    PDP_E_INVAL = -1,     /* null pointer, inconsistent sizes, k differs inside a pair */
+    PDP_E_KRANGE = -2,    /* k == 0 or k > PDP_K_MAX */
+    PDP_E_WORKSPACE = -3, /* workspace or arena smaller than the size functions require */
+    PDP_E_CAPACITY = -4,  /* device: an output or scratch array was too small; needed holds the size */
+    PDP_E_ALPHABET = -5,  /* device: a residue outside ACDEFGHIKLMNPQRSTVWY; where holds its offset */
+    PDP_E_HIP = -6,       /* a HIP runtime call failed */
+    PDP_E_BUDGET = -7,    /* serving: a request cannot fit the admission budget */
+    PDP_E_LIMIT = -8,     /* a size beyond PDP_MAX_WINDOWS / PDP_MAX_GENES / 2^32 entries */
+    PDP_E_UNIMPL = -9
+};
+
+/* Device-side status, written by the kernels of one call.  code is the first
+ * error raised (0 if none); needed is the size that would have fitted
+ * (PDP_E_CAPACITY, the largest over the arrays that overflowed) or the
+ * offending size (PDP_E_LIMIT); where is the smallest residue offset
+ * (PDP_E_ALPHABET), the gene index (PDP_E_LIMIT, PDP_E_INVAL) or, for
+ * PDP_E_CAPACITY, the first array that overflowed in pipeline order
+ * (0: shared-k-mer incidences, 1: best-hit entries, 2: BBH pairs); else
+ * UINT64_MAX.  On any error the call's outputs are unspecified. */
+typedef struct pdp_status {
+    int32_t code;
+    uint32_t reserved;
+    uint64_t needed;
+    uint64_t where;
+} pdp_status;
+
+uint32_t pdp_abi_version(void);
+const char *pdp_strerror(int32_t code);
+const char *pdp_last_error(void);
+
+/* ------------------------------------------------------------- phase (a) */
+
+/* Eq. k_length: k = log_|alphabet| (total), computed in integers.  mode 0
+ * rounds up (smallest k with alphabet^k >= total), mode 1 rounds down (largest
+ * k with alphabet^k <= total); k is at least 1.  The paper sums the sizes of
+ * the genomes; this library's callers pass the total number of residues.
+ * Host only.  Errors: PDP_E_INVAL (alphabet < 2, k_out NULL, bad mode). */
+int32_t pdp_k_rule(uint64_t total, uint32_t alphabet, int32_t mode, uint32_t *k_out);
+
+/* ------------------------------------------------- k-mer dictionary build */
+
+/* One genome on the device: gene i is residues[gene_off[i] .. gene_off[i+1]),
+ * ASCII upper-case letters.  gene_off has n_genes+1 entries, gene_off[0] = 0,
+ * non-decreasing, gene_off[n_genes] == n_residues (host copy of the last
+ * offset, which the library trusts for sizing). */
+typedef struct pdp_genome {
+    const uint8_t *residues;   /* device, n_residues bytes */
+    const uint64_t *gene_off;  /* device, n_genes + 1 */
+    uint32_t n_genes;
+    uint32_t reserved;
+    uint64_t n_residues;
+} pdp_genome;
+
+/* The k-mer dictionary of one genome: the multiplicity vector of every gene
+ * (Multiplicity vector building phase, Alg. 1) and an inverted index from
+ * k-mer to (gene, multiplicity).  A k-mer's code packs its residues 5 bits
+ * each, first residue most significant, with A=0, C=1, ..., Y=19 in the order
+ * ACDEFGHIKLMNPQRSTVWY, so codes sort like the k-mer strings.
+ * All arrays are device memory carved by pdp_dict_bind from one arena.
+ * The host fields are set by pdp_dict_bind and must not be changed. */
+typedef struct pdp_dict {
+    uint32_t n_genes;
+    uint32_t k;
+    uint64_t capacity;    /* entries every per-entry array can hold (>= total windows) */
+    uint32_t n_buckets;   /* index directory size: 20^min(k,4) leading-residue buckets */
+    uint32_t reserved;
+    uint32_t *nwin;       /* [n_genes] windows per gene, max(0, |g|-k+1) */
+    uint32_t *mv_ptr;     /* [n_genes+1] CSR offsets; mv_ptr[n_genes] = entries E */
+    uint64_t *mv_code;    /* [capacity] codes, strictly ascending inside a gene */
+    uint32_t *mv_cnt;     /* [capacity] multiplicity of each code in its gene */
+    uint32_t *ix_dir;     /* [n_buckets+1] first index entry of each bucket */
+    uint64_t *ix_code;    /* [capacity] all entries ordered by (code, gene) */
+    uint32_t *ix_gene;    /* [capacity] gene of each index entry */
+    uint32_t *ix_cnt;     /* [capacity] multiplicity of the code in that gene */
+    pdp_status *status;   /* device status of the last pdp_dict_build */
+} pdp_dict;
+
+/* Bytes of the device arena that pdp_dict_bind carves, and of the scratch
+ * workspace that pdp_dict_build needs, for a genome of n_genes genes and
+ * n_residues residues.  Host only.  Errors: PDP_E_KRANGE, PDP_E_LIMIT
+ * (n_genes > PDP_MAX_GENES or n_residues >= 2^32), PDP_E_INVAL. */
+int32_t pdp_dict_size(uint32_t n_genes, uint64_t n_residues, uint32_t k,
+                      uint64_t *arena_bytes, uint64_t *ws_bytes);
+
+/* Points the arrays of *out into a caller-allocated device arena (256-byte
+ * aligned, at least pdp_dict_size's arena_bytes).  Enqueues nothing.
+ * Errors: PDP_E_INVAL, PDP_E_WORKSPACE (arena too small), as pdp_dict_size. */
+int32_t pdp_dict_bind(void *arena, uint64_t arena_bytes, uint32_t n_genes, uint64_t n_residues,
+                      uint32_t k, pdp_dict *out);
+
+/* Builds the dictionary of genome g into d (bound with the same n_genes,
+ * n_residues and k).  ws is device scratch of pdp_dict_size's ws_bytes.
+ * Gene i keeps index i.  Device errors (in d->status): PDP_E_ALPHABET,
+ * PDP_E_LIMIT (a gene with more than PDP_MAX_WINDOWS windows).
+ * Errors: PDP_E_INVAL (sizes differ from the bind), PDP_E_WORKSPACE, PDP_E_HIP. */
+int32_t pdp_dict_build(const pdp_genome *g, pdp_dict *d, void *ws, uint64_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------- best hits, BBH */
+
+/* Best hits in CSR form (the jagged array A_ij of Alg. 2): row r's hits are
+ * col[ptr[r] .. ptr[r+1]) in ascending column order; num is the sum of minima
+ * and den the sum of maxima of Eq. jaccard_k for that gene pair, so J =
+ * num/den exactly.  A row is empty exactly when its gene shares no k-mer with
+ * the other genome (a best hit needs a maximum above zero).  All device. */
+typedef struct pdp_bh_out {
+    uint32_t n_rows;      /* rows the ptr array covers */
+    uint32_t reserved;
+    uint64_t capacity;    /* entries col/num/den can hold */
+    uint32_t *ptr;        /* [n_rows+1] */
+    uint32_t *col;        /* [capacity] */
+    uint32_t *num;        /* [capacity] */
+    uint32_t *den;        /* [capacity] */
+} pdp_bh_out;
+
+/* Bidirectional best hits (Eq. bidirectional_best_hit): pairs (a[i], b[i])
+ * in ascending (a, b) order with their num/den; ptr is a CSR over the genes
+ * of the first genome (pairs of gene a are ptr[a] .. ptr[a+1]).  All device. */
+typedef struct pdp_bbh_out {
+    uint32_t n_rows;
+    uint32_t reserved;
+    uint64_t capacity;
+    uint32_t *ptr;        /* [n_rows+1] */
+    uint32_t *a;          /* [capacity] */
+    uint32_t *b;          /* [capacity] */
+    uint32_t *num;        /* [capacity] */
+    uint32_t *den;        /* [capacity] */
+} pdp_bbh_out;
+
+/* Tuning knobs; zero means "choose automatically". */
+typedef struct pdp_params {
+    uint64_t inc_capacity;   /* shared-k-mer incidences the scratch can hold (0: from the dictionary sizes) */
+    uint32_t tile_rows;      /* query genes per LDS accumulation tile */
+    uint32_t join_entries;   /* target index entries per join work-group */
+    uint32_t lds_budget;     /* bytes of LDS for one accumulation tile */
+    uint32_t reserved;
+} pdp_params;
+
+/* One unit of work: genomes a and b (same k).  flags select the outputs. */
+#define PDP_TASK_AB 1u   /* best hits of a's genes in b */
+#define PDP_TASK_BA 2u   /* best hits of b's genes in a */
+#define PDP_TASK_BBH 4u  /* bidirectional best hits of (a, b); needs AB and BA */
+typedef struct pdp_task {
+    const pdp_dict *a;
+    const pdp_dict *b;
+    uint32_t flags;
+    uint32_t reserved;
+} pdp_task;
+
+/* A plan: the host-side schedule of many tasks (join work-groups,
+ * accumulation tiles, output row ranges) computed once from host-known sizes,
+ * plus the workspace layout.  Opaque; host memory owned by the library. */
+typedef struct pdp_plan pdp_plan;
+
+typedef struct pdp_plan_info {
+    uint64_t ws_bytes;        /* device workspace pdp_plan_run needs */
+    uint64_t inc_capacity;    /* incidences the workspace holds */
+    uint32_t bh_rows;         /* rows of the combined best-hit output */
+    uint32_t bbh_rows;        /* rows of the combined BBH output */
+    uint32_t n_tasks;
+    uint32_t join_groups;     /* join work-groups per run */
+    uint32_t tiles;           /* accumulation tiles per run */
+    uint32_t tile_lds;        /* LDS bytes per accumulation tile */
+} pdp_plan_info;
+
+/* Builds a plan for n_tasks tasks.  Best-hit rows of the combined output are
+ * laid out task by task: first a's genes (if AB), then b's genes (if BA); BBH
+ * rows are a's genes of every task with PDP_TASK_BBH, task by task.
+ * pdp_plan_rows gives each task's first row in both outputs.  Host only.
+ * Errors: PDP_E_INVAL (null, k mismatch, BBH without AB|BA), PDP_E_LIMIT. */
+int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_params *params, pdp_plan **out);
+int32_t pdp_plan_info_get(const pdp_plan *plan, pdp_plan_info *info);
+/* For task t: first row of its AB rows, of its BA rows (in bh), and of its BBH
+ * rows (in bbh); UINT32_MAX where the task has no such output. */
+int32_t pdp_plan_rows(const pdp_plan *plan, uint32_t t, uint32_t *ab_row, uint32_t *ba_row, uint32_t *bbh_row);
+void pdp_plan_destroy(pdp_plan *plan);
+
+/* Copies the plan's device tables into ws (once per workspace, or after the
+ * workspace was overwritten).  Enqueues host-to-device copies on stream. */
+int32_t pdp_plan_upload(const pdp_plan *plan, void *ws, uint64_t ws_bytes, void *stream);
+
+/* Enqueues the whole best-hit path for every task of the plan: shared-k-mer
+ * join, LDS accumulation of the sums of minima, best hits with ties, BBH.
+ * Enqueues only kernels (no allocation, no host copies, no memset), so it can
+ * be captured in a HIP graph.  bh must cover info.bh_rows rows, bbh
+ * info.bbh_rows rows (bbh may be NULL if no task asks for BBH).  status is
+ * device memory.  Device errors: PDP_E_CAPACITY (needed = required
+ * incidences, best-hit entries or BBH pairs; retry with more).
+ * Errors: PDP_E_INVAL, PDP_E_WORKSPACE, PDP_E_HIP. */
+int32_t pdp_plan_launch(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *status,
+                        void *ws, uint64_t ws_bytes, void *stream);
+
+/* Upload + launch. */
+int32_t pdp_plan_run(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *status,
+                     void *ws, uint64_t ws_bytes, void *stream);
+
+/* Convenience form of one task: best hits of every gene of q in t (Eq.
+ * best_hit, Alg. 2); out->n_rows must equal q->n_genes.  The workspace size
+ * comes from pdp_bh_ws_size.  The plan tables are uploaded and the stream is
+ * synchronised once before the kernels are enqueued, so this call is not for
+ * graph capture (use a plan for that). */
+int32_t pdp_bh_ws_size(const pdp_dict *q, const pdp_dict *t, const pdp_params *params, uint64_t *ws_bytes);
+int32_t pdp_bh(const pdp_dict *q, const pdp_dict *t, const pdp_params *params, pdp_bh_out *out,
+               pdp_status *status, void *ws, uint64_t ws_bytes, void *stream);
+
+/* BBH from two best-hit outputs (Alg. 3's cross-check of A_ij against A_ji):
+ * ab has one row per gene of genome i, ba one row per gene of genome j.
+ * out->n_rows must equal ab->n_rows.  Device errors: PDP_E_CAPACITY.
+ * ws: device scratch of pdp_bbh_ws_size bytes. */
+int32_t pdp_bbh_ws_size(uint32_t n_rows, uint64_t *ws_bytes);
+int32_t pdp_bbh(const pdp_bh_out *ab, const pdp_bh_out *ba, pdp_bbh_out *out, pdp_status *status,
+                void *ws, uint64_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDP_H */

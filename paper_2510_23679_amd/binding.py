@@ -1,0 +1,127 @@
+"""ctypes binding of libpdp.so with the C-ABI's names.
+
+Only argument marshalling lives here: every step of the path runs in the HIP
+kernels behind the C-ABI.  PyTorch provides device memory (``torch.empty`` on
+the ROCm device) and streams (``torch.cuda.current_stream().cuda_stream``).
+If the library is missing this module raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpdp.so")
+
+u32, u64, i32, vp = C.c_uint32, C.c_uint64, C.c_int32, C.c_void_p
+
+PDP_OK = 0
+PDP_E_INVAL = -1
+PDP_E_KRANGE = -2
+PDP_E_WORKSPACE = -3
+PDP_E_CAPACITY = -4
+PDP_E_ALPHABET = -5
+PDP_E_HIP = -6
+PDP_E_BUDGET = -7
+PDP_E_LIMIT = -8
+PDP_E_UNIMPL = -9
+
+PDP_TASK_AB = 1
+PDP_TASK_BA = 2
+PDP_TASK_BBH = 4
+PDP_K_MAX = 12
+PDP_MAX_WINDOWS = 65535
+
+
+class pdp_status(C.Structure):
+    _fields_ = [("code", i32), ("reserved", u32), ("needed", u64), ("where", u64)]
+
+
+class pdp_genome(C.Structure):
+    _fields_ = [("residues", vp), ("gene_off", vp), ("n_genes", u32), ("reserved", u32), ("n_residues", u64)]
+
+
+class pdp_dict(C.Structure):
+    _fields_ = [("n_genes", u32), ("k", u32), ("capacity", u64), ("n_buckets", u32), ("reserved", u32),
+                ("nwin", vp), ("mv_ptr", vp), ("mv_code", vp), ("mv_cnt", vp), ("ix_dir", vp),
+                ("ix_code", vp), ("ix_gene", vp), ("ix_cnt", vp), ("status", vp)]
+
+
+class pdp_bh_out(C.Structure):
+    _fields_ = [("n_rows", u32), ("reserved", u32), ("capacity", u64), ("ptr", vp), ("col", vp), ("num", vp),
+                ("den", vp)]
+
+
+class pdp_bbh_out(C.Structure):
+    _fields_ = [("n_rows", u32), ("reserved", u32), ("capacity", u64), ("ptr", vp), ("a", vp), ("b", vp),
+                ("num", vp), ("den", vp)]
+
+
+class pdp_params(C.Structure):
+    _fields_ = [("inc_capacity", u64), ("tile_rows", u32), ("join_entries", u32), ("lds_budget", u32),
+                ("reserved", u32)]
+
+
+class pdp_task(C.Structure):
+    _fields_ = [("a", C.POINTER(pdp_dict)), ("b", C.POINTER(pdp_dict)), ("flags", u32), ("reserved", u32)]
+
+
+class pdp_plan_info(C.Structure):
+    _fields_ = [("ws_bytes", u64), ("inc_capacity", u64), ("bh_rows", u32), ("bbh_rows", u32), ("n_tasks", u32),
+                ("join_groups", u32), ("tiles", u32), ("tile_lds", u32)]
+
+
+# name -> (restype, argtypes); the same names as include/pdp.h
+SIGNATURES = {
+    "pdp_abi_version": (u32, []),
+    "pdp_strerror": (C.c_char_p, [i32]),
+    "pdp_last_error": (C.c_char_p, []),
+    "pdp_k_rule": (i32, [u64, u32, i32, C.POINTER(u32)]),
+    "pdp_dict_size": (i32, [u32, u64, u32, C.POINTER(u64), C.POINTER(u64)]),
+    "pdp_dict_bind": (i32, [vp, u64, u32, u64, u32, C.POINTER(pdp_dict)]),
+    "pdp_dict_build": (i32, [C.POINTER(pdp_genome), C.POINTER(pdp_dict), vp, u64, vp]),
+    "pdp_plan_create": (i32, [C.POINTER(pdp_task), u32, C.POINTER(pdp_params), C.POINTER(vp)]),
+    "pdp_plan_info_get": (i32, [vp, C.POINTER(pdp_plan_info)]),
+    "pdp_plan_rows": (i32, [vp, u32, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]),
+    "pdp_plan_destroy": (None, [vp]),
+    "pdp_plan_upload": (i32, [vp, vp, u64, vp]),
+    "pdp_plan_launch": (i32, [vp, C.POINTER(pdp_bh_out), C.POINTER(pdp_bbh_out), vp, vp, u64, vp]),
+    "pdp_plan_run": (i32, [vp, C.POINTER(pdp_bh_out), C.POINTER(pdp_bbh_out), vp, vp, u64, vp]),
+    "pdp_bh_ws_size": (i32, [C.POINTER(pdp_dict), C.POINTER(pdp_dict), C.POINTER(pdp_params), C.POINTER(u64)]),
+    "pdp_bh": (i32, [C.POINTER(pdp_dict), C.POINTER(pdp_dict), C.POINTER(pdp_params), C.POINTER(pdp_bh_out), vp, vp,
+                     u64, vp]),
+    "pdp_bbh_ws_size": (i32, [u32, C.POINTER(u64)]),
+    "pdp_bbh": (i32, [C.POINTER(pdp_bh_out), C.POINTER(pdp_bh_out), C.POINTER(pdp_bbh_out), vp, vp, u64, vp]),
+}
+
+_lib = None
+
+
+class PdpError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{message} (code {code})")
+        self.code = code
+
+
+def lib():
+    """The loaded libpdp.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(the best-hit path has no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc: int, what: str = "") -> None:
+    if rc != PDP_OK:
+        L = lib()
+        msg = L.pdp_strerror(rc).decode()
+        detail = L.pdp_last_error().decode()
+        raise PdpError(rc, f"{what}: {msg}" + (f" ({detail})" if detail else ""))

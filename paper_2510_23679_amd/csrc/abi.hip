@@ -1,0 +1,403 @@
+// C-ABI entry points: argument validation, planning, workspace layout and
+// error reporting around the gfx950 kernels.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace pdp;
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+int32_t fail(int32_t code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int32_t fail(int32_t code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int32_t hip_fail(hipError_t e, const char *what) {
+    return fail(PDP_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int32_t ok() {
+    g_last_error[0] = '\0';
+    return PDP_OK;
+}
+
+}  // namespace
+
+struct pdp_plan {
+    std::vector<DevTask> tasks;
+    std::vector<DevTile> tiles;
+    std::vector<uint32_t> ab_row, ba_row, bbh_row;
+    PlanShape shape;
+    uint64_t ws_bytes;
+};
+
+extern "C" {
+
+uint32_t pdp_abi_version(void) { return PDP_ABI_VERSION; }
+
+const char *pdp_strerror(int32_t code) {
+    switch (code) {
+    case PDP_OK: return "ok";
+    case PDP_E_INVAL: return "invalid argument";
+    case PDP_E_KRANGE: return "k out of range (1..12)";
+    case PDP_E_WORKSPACE: return "workspace or arena too small";
+    case PDP_E_CAPACITY: return "output or scratch capacity too small";
+    case PDP_E_ALPHABET: return "residue outside the 20 amino acids";
+    case PDP_E_HIP: return "HIP runtime error";
+    case PDP_E_BUDGET: return "request exceeds the admission budget";
+    case PDP_E_LIMIT: return "size beyond a documented limit";
+    case PDP_E_UNIMPL: return "not implemented";
+    default: return "unknown error";
+    }
+}
+
+const char *pdp_last_error(void) { return g_last_error; }
+
+int32_t pdp_k_rule(uint64_t total, uint32_t alphabet, int32_t mode, uint32_t *k_out) {
+    if (!k_out || alphabet < 2 || (mode != 0 && mode != 1)) return fail(PDP_E_INVAL, "pdp_k_rule: bad argument");
+    // Powers are compared in 128-bit integers so no power near 2^64 overflows.
+    unsigned __int128 p = 1;
+    uint32_t k = 0;
+    if (mode == 0) {
+        while (p < total) {
+            p *= alphabet;
+            ++k;
+        }
+    } else {
+        while (p * alphabet <= total) {
+            p *= alphabet;
+            ++k;
+        }
+    }
+    *k_out = k < 1 ? 1 : k;
+    return ok();
+}
+
+// ------------------------------------------------------------ dictionary
+
+static int32_t dict_check(uint32_t n_genes, uint64_t n_residues, uint32_t k) {
+    if (k == 0 || k > PDP_K_MAX) return fail(PDP_E_KRANGE, "k = %u outside 1..%u", k, PDP_K_MAX);
+    if (n_genes > PDP_MAX_GENES) return fail(PDP_E_LIMIT, "%u genes exceed %u", n_genes, PDP_MAX_GENES);
+    if (n_residues >= (1ull << 32)) return fail(PDP_E_LIMIT, "%llu residues exceed 2^32 - 1", (unsigned long long)n_residues);
+    return PDP_OK;
+}
+
+static uint64_t dict_arena_bytes(uint32_t n_genes, uint64_t n_residues, uint32_t k) {
+    const uint64_t A = 256, cap = n_residues + 1, nb = n_buckets_for(k);
+    uint64_t s = 0;
+    s += align_up(4 * (uint64_t(n_genes) + 1), A);  // nwin
+    s += align_up(4 * (uint64_t(n_genes) + 1), A);  // mv_ptr
+    s += align_up(8 * cap, A);                      // mv_code
+    s += align_up(4 * cap, A);                      // mv_cnt
+    s += align_up(4 * (nb + 1), A);                 // ix_dir
+    s += align_up(8 * cap, A);                      // ix_code
+    s += align_up(4 * cap, A);                      // ix_gene
+    s += align_up(4 * cap, A);                      // ix_cnt
+    s += align_up(sizeof(pdp_status), A);           // status
+    return s;
+}
+
+int32_t pdp_dict_size(uint32_t n_genes, uint64_t n_residues, uint32_t k, uint64_t *arena_bytes, uint64_t *ws_bytes) {
+    int32_t rc = dict_check(n_genes, n_residues, k);
+    if (rc) return rc;
+    if (arena_bytes) *arena_bytes = dict_arena_bytes(n_genes, n_residues, k);
+    if (ws_bytes) *ws_bytes = dict_ws_bytes(n_genes, n_residues, k);
+    return ok();
+}
+
+int32_t pdp_dict_bind(void *arena, uint64_t arena_bytes, uint32_t n_genes, uint64_t n_residues, uint32_t k, pdp_dict *out) {
+    if (!arena || !out) return fail(PDP_E_INVAL, "pdp_dict_bind: null pointer");
+    if (reinterpret_cast<uintptr_t>(arena) % 256) return fail(PDP_E_INVAL, "pdp_dict_bind: arena not 256-byte aligned");
+    int32_t rc = dict_check(n_genes, n_residues, k);
+    if (rc) return rc;
+    const uint64_t need = dict_arena_bytes(n_genes, n_residues, k);
+    if (arena_bytes < need) return fail(PDP_E_WORKSPACE, "arena %llu < %llu bytes", (unsigned long long)arena_bytes, (unsigned long long)need);
+    const uint64_t A = 256, cap = n_residues + 1, nb = n_buckets_for(k);
+    char *p = static_cast<char *>(arena);
+    auto take = [&](uint64_t bytes) {
+        char *q = p;
+        p += align_up(bytes, A);
+        return q;
+    };
+    pdp_dict d;
+    std::memset(&d, 0, sizeof(d));
+    d.n_genes = n_genes;
+    d.k = k;
+    d.capacity = cap;
+    d.n_buckets = static_cast<uint32_t>(nb);
+    d.nwin = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(n_genes) + 1)));
+    d.mv_ptr = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(n_genes) + 1)));
+    d.mv_code = reinterpret_cast<uint64_t *>(take(8 * cap));
+    d.mv_cnt = reinterpret_cast<uint32_t *>(take(4 * cap));
+    d.ix_dir = reinterpret_cast<uint32_t *>(take(4 * (nb + 1)));
+    d.ix_code = reinterpret_cast<uint64_t *>(take(8 * cap));
+    d.ix_gene = reinterpret_cast<uint32_t *>(take(4 * cap));
+    d.ix_cnt = reinterpret_cast<uint32_t *>(take(4 * cap));
+    d.status = reinterpret_cast<pdp_status *>(take(sizeof(pdp_status)));
+    *out = d;
+    return ok();
+}
+
+int32_t pdp_dict_build(const pdp_genome *g, pdp_dict *d, void *ws, uint64_t ws_bytes, void *stream) {
+    if (!g || !d || !ws) return fail(PDP_E_INVAL, "pdp_dict_build: null pointer");
+    if (g->n_genes && (!g->residues || !g->gene_off)) return fail(PDP_E_INVAL, "pdp_dict_build: null genome arrays");
+    if (!g->gene_off) return fail(PDP_E_INVAL, "pdp_dict_build: gene_off is null");
+    int32_t rc = dict_check(g->n_genes, g->n_residues, d->k);
+    if (rc) return rc;
+    if (g->n_genes != d->n_genes || g->n_residues + 1 > d->capacity)
+        return fail(PDP_E_INVAL, "genome (%u genes, %llu residues) does not match the bound dictionary (%u genes, capacity %llu)",
+                    g->n_genes, (unsigned long long)g->n_residues, d->n_genes, (unsigned long long)d->capacity);
+    const uint64_t need = dict_ws_bytes(g->n_genes, g->n_residues, d->k);
+    if (ws_bytes < need) return fail(PDP_E_WORKSPACE, "workspace %llu < %llu bytes", (unsigned long long)ws_bytes, (unsigned long long)need);
+    DictBuildWs w = dict_ws_carve(ws, g->n_genes, g->n_residues, d->k);
+    hipError_t e = launch_dict_build(g, d, w, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "pdp_dict_build");
+    return ok();
+}
+
+// ------------------------------------------------------------------ plans
+
+static DevDict dev_dict(const pdp_dict *d) {
+    DevDict x;
+    x.ix_code = d->ix_code;
+    x.ix_gene = d->ix_gene;
+    x.ix_cnt = d->ix_cnt;
+    x.ix_dir = d->ix_dir;
+    x.nwin = d->nwin;
+    x.n_genes = d->n_genes;
+    x.n_buckets = d->n_buckets;
+    x.k = d->k;
+    x.reserved = 0;
+    return x;
+}
+
+int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_params *params, pdp_plan **out) {
+    if (!out || (n_tasks && !tasks)) return fail(PDP_E_INVAL, "pdp_plan_create: null pointer");
+    *out = nullptr;
+    if (n_tasks == 0) return fail(PDP_E_INVAL, "pdp_plan_create: no tasks");
+    pdp_params prm;
+    std::memset(&prm, 0, sizeof(prm));
+    if (params) prm = *params;
+    const uint32_t lds_budget = prm.lds_budget ? prm.lds_budget : kDefaultLdsBudget;
+    const uint32_t join_entries = prm.join_entries ? prm.join_entries : kJoinLdsCap / 2;
+    if (lds_budget > 64 * 1024) return fail(PDP_E_INVAL, "lds_budget above 64 KiB");
+    if (join_entries > kJoinLdsCap) return fail(PDP_E_INVAL, "join_entries above %u", kJoinLdsCap);
+    if (prm.tile_rows > kTileMaxRows) return fail(PDP_E_INVAL, "tile_rows above %u", kTileMaxRows);
+
+    pdp_plan *P = new (std::nothrow) pdp_plan();
+    if (!P) return fail(PDP_E_INVAL, "out of host memory");
+    uint64_t chunks = 0, tiles = 0, bh_rows = 0, bbh_rows = 0, inc_est = 0;
+    uint32_t tile_lds = 4;
+    for (uint32_t t = 0; t < n_tasks; ++t) {
+        const pdp_task &tk = tasks[t];
+        if (!tk.a || !tk.b) {
+            delete P;
+            return fail(PDP_E_INVAL, "task %u: null dictionary", t);
+        }
+        if (tk.a->k != tk.b->k || tk.a->n_buckets != tk.b->n_buckets) {
+            delete P;
+            return fail(PDP_E_INVAL, "task %u: dictionaries built with different k (%u, %u)", t, tk.a->k, tk.b->k);
+        }
+        uint32_t flags = tk.flags & (PDP_TASK_AB | PDP_TASK_BA | PDP_TASK_BBH);
+        if (flags & PDP_TASK_BBH) flags |= PDP_TASK_AB | PDP_TASK_BA;
+        if (!flags) {
+            delete P;
+            return fail(PDP_E_INVAL, "task %u: no output selected", t);
+        }
+        DevTask d;
+        std::memset(&d, 0, sizeof(d));
+        d.a = dev_dict(tk.a);
+        d.b = dev_dict(tk.b);
+        d.flags = flags;
+        const uint32_t nb = tk.a->n_buckets;
+        const uint64_t e_max = std::max<uint64_t>(std::max(tk.a->capacity, tk.b->capacity), 1);
+        uint64_t bpw = uint64_t(join_entries) * nb / e_max;
+        bpw = std::min<uint64_t>(std::max<uint64_t>(bpw, 1), nb);
+        d.bpw = static_cast<uint32_t>(bpw);
+        d.n_chunks = static_cast<uint32_t>((nb + bpw - 1) / bpw);
+        d.chunk_base = static_cast<uint32_t>(chunks);
+        chunks += d.n_chunks;
+        for (uint32_t dir = 0; dir < 2; ++dir) {
+            d.row_base[dir] = UINT32_MAX;
+            d.tile_base[dir] = static_cast<uint32_t>(tiles);
+            d.tile_rows[dir] = 1;
+            if (!(flags & (1u << dir))) continue;
+            const pdp_dict *R = dir == 0 ? tk.a : tk.b;
+            const pdp_dict *C = dir == 0 ? tk.b : tk.a;
+            const uint64_t W = std::max<uint64_t>((uint64_t(C->n_genes) + 1) / 2, 1);
+            uint64_t T = lds_budget / (4 * W);
+            if (T == 0) {
+                delete P;
+                return fail(PDP_E_LIMIT, "task %u: %u target genes do not fit an LDS tile of %u bytes", t, C->n_genes, lds_budget);
+            }
+            T = std::min<uint64_t>(T, prm.tile_rows ? prm.tile_rows : kTileMaxRows);
+            T = std::max<uint64_t>(std::min<uint64_t>(T, std::max<uint32_t>(R->n_genes, 1)), 1);
+            d.tile_rows[dir] = static_cast<uint32_t>(T);
+            d.row_base[dir] = static_cast<uint32_t>(bh_rows);
+            bh_rows += R->n_genes;
+            tile_lds = std::max<uint32_t>(tile_lds, static_cast<uint32_t>(T * W * 4));
+            for (uint32_t r0 = 0; r0 < R->n_genes; r0 += static_cast<uint32_t>(T)) {
+                DevTile tl;
+                tl.task = t;
+                tl.dir = dir;
+                tl.row0 = r0;
+                tl.nrows = std::min<uint32_t>(static_cast<uint32_t>(T), R->n_genes - r0);
+                P->tiles.push_back(tl);
+            }
+            tiles = P->tiles.size();
+        }
+        d.bbh_row_base = static_cast<uint32_t>(bbh_rows);
+        if (flags & PDP_TASK_BBH) bbh_rows += tk.a->n_genes;
+        inc_est += (tk.a->capacity + tk.b->capacity) / 2 + 4096;
+        P->tasks.push_back(d);
+        P->ab_row.push_back(d.row_base[0]);
+        P->ba_row.push_back(d.row_base[1]);
+        P->bbh_row.push_back((flags & PDP_TASK_BBH) ? d.bbh_row_base : UINT32_MAX);
+        if (chunks > UINT32_MAX || bh_rows >= UINT32_MAX || tiles >= UINT32_MAX) {
+            delete P;
+            return fail(PDP_E_LIMIT, "plan too large for 32-bit indices");
+        }
+    }
+    P->shape.n_tasks = n_tasks;
+    P->shape.total_chunks = static_cast<uint32_t>(chunks);
+    P->shape.total_tiles = static_cast<uint32_t>(tiles);
+    P->shape.bh_rows = static_cast<uint32_t>(bh_rows);
+    P->shape.bbh_rows = static_cast<uint32_t>(bbh_rows);
+    P->shape.tile_lds = tile_lds;
+    P->shape.inc_cap = prm.inc_capacity ? prm.inc_capacity : inc_est;
+    P->ws_bytes = pair_ws_bytes(P->shape);
+    *out = P;
+    return ok();
+}
+
+int32_t pdp_plan_info_get(const pdp_plan *plan, pdp_plan_info *info) {
+    if (!plan || !info) return fail(PDP_E_INVAL, "pdp_plan_info_get: null pointer");
+    info->ws_bytes = plan->ws_bytes;
+    info->inc_capacity = plan->shape.inc_cap;
+    info->bh_rows = plan->shape.bh_rows;
+    info->bbh_rows = plan->shape.bbh_rows;
+    info->n_tasks = plan->shape.n_tasks;
+    info->join_groups = plan->shape.total_chunks;
+    info->tiles = plan->shape.total_tiles;
+    info->tile_lds = plan->shape.tile_lds;
+    return ok();
+}
+
+int32_t pdp_plan_rows(const pdp_plan *plan, uint32_t t, uint32_t *ab_row, uint32_t *ba_row, uint32_t *bbh_row) {
+    if (!plan) return fail(PDP_E_INVAL, "pdp_plan_rows: null plan");
+    if (t >= plan->shape.n_tasks) return fail(PDP_E_INVAL, "task %u out of range", t);
+    if (ab_row) *ab_row = plan->ab_row[t];
+    if (ba_row) *ba_row = plan->ba_row[t];
+    if (bbh_row) *bbh_row = plan->bbh_row[t];
+    return ok();
+}
+
+void pdp_plan_destroy(pdp_plan *plan) { delete plan; }
+
+int32_t pdp_plan_upload(const pdp_plan *plan, void *ws, uint64_t ws_bytes, void *stream) {
+    if (!plan || !ws) return fail(PDP_E_INVAL, "pdp_plan_upload: null pointer");
+    if (ws_bytes < plan->ws_bytes) return fail(PDP_E_WORKSPACE, "workspace %llu < %llu bytes", (unsigned long long)ws_bytes, (unsigned long long)plan->ws_bytes);
+    PairWs w = pair_ws_carve(ws, plan->shape);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(w.tasks, plan->tasks.data(), sizeof(DevTask) * plan->tasks.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "pdp_plan_upload");
+    if (!plan->tiles.empty()) {
+        e = hipMemcpyAsync(w.tiles, plan->tiles.data(), sizeof(DevTile) * plan->tiles.size(), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "pdp_plan_upload");
+    }
+    return ok();
+}
+
+static int32_t check_outputs(const pdp_plan *plan, const pdp_bh_out *bh, const pdp_bbh_out *bbh, const pdp_status *st) {
+    if (!bh || !st) return fail(PDP_E_INVAL, "null output or status");
+    if (bh->n_rows != plan->shape.bh_rows || !bh->ptr || (bh->capacity && (!bh->col || !bh->num || !bh->den)))
+        return fail(PDP_E_INVAL, "best-hit output: %u rows given, plan has %u", bh->n_rows, plan->shape.bh_rows);
+    if (plan->shape.bbh_rows) {
+        if (!bbh) return fail(PDP_E_INVAL, "plan has BBH rows but no BBH output was given");
+        if (bbh->n_rows != plan->shape.bbh_rows || !bbh->ptr || (bbh->capacity && (!bbh->a || !bbh->b || !bbh->num || !bbh->den)))
+            return fail(PDP_E_INVAL, "BBH output: %u rows given, plan has %u", bbh->n_rows, plan->shape.bbh_rows);
+    }
+    return PDP_OK;
+}
+
+int32_t pdp_plan_launch(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *status, void *ws,
+                        uint64_t ws_bytes, void *stream) {
+    if (!plan || !ws) return fail(PDP_E_INVAL, "pdp_plan_launch: null pointer");
+    int32_t rc = check_outputs(plan, bh, bbh, status);
+    if (rc) return rc;
+    if (ws_bytes < plan->ws_bytes) return fail(PDP_E_WORKSPACE, "workspace %llu < %llu bytes", (unsigned long long)ws_bytes, (unsigned long long)plan->ws_bytes);
+    PairWs w = pair_ws_carve(ws, plan->shape);
+    hipError_t e = launch_pairs(plan->shape, w, bh, plan->shape.bbh_rows ? bbh : nullptr, status, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "pdp_plan_launch");
+    return ok();
+}
+
+int32_t pdp_plan_run(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *status, void *ws, uint64_t ws_bytes,
+                     void *stream) {
+    int32_t rc = pdp_plan_upload(plan, ws, ws_bytes, stream);
+    if (rc) return rc;
+    return pdp_plan_launch(plan, bh, bbh, status, ws, ws_bytes, stream);
+}
+
+// ------------------------------------------------------- single-task forms
+
+int32_t pdp_bh_ws_size(const pdp_dict *q, const pdp_dict *t, const pdp_params *params, uint64_t *ws_bytes) {
+    if (!ws_bytes) return fail(PDP_E_INVAL, "pdp_bh_ws_size: null output");
+    pdp_task task = {q, t, PDP_TASK_AB, 0};
+    pdp_plan *P = nullptr;
+    int32_t rc = pdp_plan_create(&task, 1, params, &P);
+    if (rc) return rc;
+    *ws_bytes = P->ws_bytes;
+    delete P;
+    return ok();
+}
+
+int32_t pdp_bh(const pdp_dict *q, const pdp_dict *t, const pdp_params *params, pdp_bh_out *out, pdp_status *status, void *ws,
+               uint64_t ws_bytes, void *stream) {
+    pdp_task task = {q, t, PDP_TASK_AB, 0};
+    pdp_plan *P = nullptr;
+    int32_t rc = pdp_plan_create(&task, 1, params, &P);
+    if (rc) return rc;
+    rc = pdp_plan_upload(P, ws, ws_bytes, stream);
+    if (!rc) {
+        // the plan's host tables must outlive the copy
+        hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) rc = hip_fail(e, "pdp_bh");
+    }
+    if (!rc) rc = pdp_plan_launch(P, out, nullptr, status, ws, ws_bytes, stream);
+    delete P;
+    return rc;
+}
+
+int32_t pdp_bbh_ws_size(uint32_t n_rows, uint64_t *ws_bytes) {
+    if (!ws_bytes) return fail(PDP_E_INVAL, "pdp_bbh_ws_size: null output");
+    *ws_bytes = align_up(4ull * scan_partials(n_rows), 256);
+    return ok();
+}
+
+int32_t pdp_bbh(const pdp_bh_out *ab, const pdp_bh_out *ba, pdp_bbh_out *out, pdp_status *status, void *ws, uint64_t ws_bytes,
+                void *stream) {
+    if (!ab || !ba || !out || !status || !ws) return fail(PDP_E_INVAL, "pdp_bbh: null pointer");
+    if (out->n_rows != ab->n_rows) return fail(PDP_E_INVAL, "pdp_bbh: output has %u rows, input %u", out->n_rows, ab->n_rows);
+    if (!ab->ptr || !ba->ptr || !out->ptr) return fail(PDP_E_INVAL, "pdp_bbh: null row pointers");
+    uint64_t need = 0;
+    pdp_bbh_ws_size(ab->n_rows, &need);
+    if (ws_bytes < need) return fail(PDP_E_WORKSPACE, "workspace %llu < %llu bytes", (unsigned long long)ws_bytes, (unsigned long long)need);
+    hipError_t e = launch_bbh_standalone(ab, ba, out, status, static_cast<uint32_t *>(ws), static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "pdp_bbh");
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Device helpers shared by the gfx950 kernels of the best-hit library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pdp.h"
+
+namespace pdp {
+
+constexpr uint32_t kWave = 64;
+constexpr uint32_t kInvalidSym = 0xFFu;
+
+// Residue letter -> 5-bit symbol (A=0 ... Y=19 in the order ACDEFGHIKLMNPQRSTVWY), 0xFF otherwise.
+struct SymTable {
+    uint8_t v[256];
+};
+constexpr SymTable make_sym_table() {
+    SymTable t{};
+    for (int i = 0; i < 256; ++i) t.v[i] = 0xFF;
+    const char letters[] = "ACDEFGHIKLMNPQRSTVWY";
+    for (int i = 0; i < 20; ++i) t.v[static_cast<uint8_t>(letters[i])] = static_cast<uint8_t>(i);
+    return t;
+}
+static __constant__ constexpr SymTable kSym = make_sym_table();
+
+// Leading-residue bucket of a k-mer code: the first min(k,4) residues read as a base-20 number.
+__device__ __forceinline__ uint32_t bucket_of(uint64_t code, uint32_t k, uint32_t lead) {
+    uint32_t b = 0;
+    for (uint32_t i = 0; i < lead; ++i) b = b * 20u + static_cast<uint32_t>((code >> (5u * (k - 1u - i))) & 31u);
+    return b;
+}
+
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+// Number of set bits of mask in lanes below this lane.
+__device__ __forceinline__ uint32_t mask_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (uint32_t d = 1; d < kWave; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+#pragma unroll
+    for (uint32_t d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+}
+
+// Reserves n slots per lane from a global 64-bit counter with one atomic per wave;
+// returns this lane's first slot.  Every lane of the wave must call it.
+__device__ __forceinline__ unsigned long long wave_reserve(uint32_t n, unsigned long long *counter) {
+    const uint32_t incl = wave_inclusive_sum(n);
+    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+    unsigned long long base = 0;
+    if (lane_id() == kWave - 1 && total) base = atomicAdd(counter, static_cast<unsigned long long>(total));
+    base = __shfl(base, kWave - 1, kWave);
+    return base + (incl - n);
+}
+
+// Exclusive scan over a work-group of NT threads; tmp needs NT/64 + 1 words of LDS.
+// Returns this thread's exclusive prefix; *total receives the sum.  Contains barriers.
+template <uint32_t NT>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *tmp, uint32_t *total) {
+    constexpr uint32_t NW = NT / kWave;
+    const uint32_t lane = lane_id();
+    const uint32_t w = threadIdx.x / kWave;
+    const uint32_t incl = wave_inclusive_sum(x);
+    if (lane == kWave - 1) tmp[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (uint32_t i = 0; i < NW; ++i) {
+            uint32_t t = tmp[i];
+            tmp[i] = run;
+            run += t;
+        }
+        tmp[NW] = run;
+    }
+    __syncthreads();
+    const uint32_t r = tmp[w] + incl - x;
+    *total = tmp[NW];
+    __syncthreads();
+    return r;
+}
+
+// Comparator network sort of n items by one work-group, ascending, for any n.
+// It is the bitonic network in its "flip" form: every comparator (lo, hi) with
+// lo < hi leaves the smaller item at lo, so the missing items past n act as +inf
+// and comparators that reach past n are skipped.  cmpswap(lo, hi) orders one
+// pair; the items may live in LDS or in global memory (the barriers order both
+// within the work-group).
+template <typename CmpSwap>
+__device__ void wg_network_sort(uint32_t n, CmpSwap cmpswap) {
+    if (n < 2) return;
+    uint32_t p2 = 1;
+    while (p2 < n) p2 <<= 1;
+    const uint32_t half_n = p2 >> 1;  // comparators per step
+    for (uint32_t size = 2; size <= p2; size <<= 1) {
+        const uint32_t half = size >> 1;
+        const uint32_t lh = 31u - __builtin_clz(half);
+        for (uint32_t i = threadIdx.x; i < half_n; i += blockDim.x) {
+            const uint32_t blk = i >> lh, pos = i & (half - 1u);
+            const uint32_t lo = blk * size + pos;
+            const uint32_t hi = blk * size + size - 1u - pos;
+            if (hi < n) cmpswap(lo, hi);
+        }
+        __syncthreads();
+        for (uint32_t stride = half >> 1; stride > 0; stride >>= 1) {
+            const uint32_t ls = 31u - __builtin_clz(stride);
+            for (uint32_t i = threadIdx.x; i < half_n; i += blockDim.x) {
+                const uint32_t blk = i >> ls, pos = i & (stride - 1u);
+                const uint32_t lo = blk * 2u * stride + pos;
+                const uint32_t hi = lo + stride;
+                if (hi < n) cmpswap(lo, hi);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Status reporting from device code: the first error code wins.
+__device__ __forceinline__ void raise_status(pdp_status *st, int32_t code, uint64_t needed, uint64_t where) {
+    atomicCAS(&st->code, 0, code);
+    if (needed) atomicMax(reinterpret_cast<unsigned long long *>(&st->needed), static_cast<unsigned long long>(needed));
+    if (where != ~0ull) atomicMin(reinterpret_cast<unsigned long long *>(&st->where), static_cast<unsigned long long>(where));
+}
+
+}  // namespace pdp

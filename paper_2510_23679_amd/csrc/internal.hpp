@@ -1,0 +1,110 @@
+// Host/device declarations shared by the translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pdp.h"
+
+namespace pdp {
+
+// ---------------------------------------------------------------- sizes
+constexpr uint32_t kScanItems = 4096;        // elements per scan work-group (256 threads x 16)
+constexpr uint32_t kMvSortCap = 2048;        // windows a gene may have to be sorted in LDS
+constexpr uint32_t kBucketSmall = 32;        // buckets up to this size are sorted by one thread
+constexpr uint32_t kBucketLdsCap = 4096;     // larger buckets up to this size are sorted in LDS
+constexpr uint32_t kJoinLdsCap = 2048;       // target-side index entries staged in LDS per join group
+constexpr uint32_t kTileMaxRows = 64;        // rows per accumulation tile
+constexpr uint32_t kTileThreads = 256;
+constexpr uint32_t kDefaultLdsBudget = 48 * 1024;
+constexpr uint32_t kKeyShift = 40;           // J key = floor(m * 2^40 / d), exact order for d < 2^20
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+inline uint32_t lead_residues(uint32_t k) { return k < 4 ? k : 4; }
+inline uint32_t n_buckets_for(uint32_t k) {
+    uint32_t nb = 1;
+    for (uint32_t i = 0; i < lead_residues(k); ++i) nb *= 20;
+    return nb;
+}
+inline uint32_t scan_partials(uint64_t n) { return static_cast<uint32_t>((n + kScanItems - 1) / kScanItems) + 1; }
+
+// --------------------------------------------------------- device tables
+struct DevDict {
+    const uint64_t *ix_code;
+    const uint32_t *ix_gene;
+    const uint32_t *ix_cnt;
+    const uint32_t *ix_dir;
+    const uint32_t *nwin;
+    uint32_t n_genes;
+    uint32_t n_buckets;
+    uint32_t k;
+    uint32_t reserved;
+};
+
+struct DevTask {
+    DevDict a, b;
+    uint32_t flags;
+    uint32_t bpw;           // buckets per join group
+    uint32_t chunk_base;    // first join group of the task
+    uint32_t n_chunks;
+    uint32_t tile_rows[2];  // rows per tile, direction 0 (a rows) and 1 (b rows)
+    uint32_t tile_base[2];  // first tile of each direction
+    uint32_t row_base[2];   // first best-hit row of each direction (UINT32_MAX: none)
+    uint32_t bbh_row_base;  // first BBH row (UINT32_MAX: none)
+    uint32_t reserved;
+};
+
+struct DevTile {
+    uint32_t task;
+    uint32_t dir;
+    uint32_t row0;
+    uint32_t nrows;
+};
+
+// ------------------------------------------------------------- launchers
+// All return hipError_t of the launch.
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_status_init(pdp_status *st, hipStream_t s);
+// Exclusive scan of n values: out[0..n] with out[n] = total.  out may equal in
+// (then in needs n+1 slots).  partials: scan_partials(n) words of scratch.
+hipError_t launch_scan(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *partials, hipStream_t s);
+
+struct DictBuildWs {
+    uint64_t *slot_code;   // n_residues: per-gene sorted distinct codes at slot gene_off[g]
+    uint32_t *slot_cnt;    // n_residues
+    uint64_t *long_tmp;    // n_residues: windows of genes too long for LDS
+    uint32_t *dcnt;        // n_genes + 1
+    uint32_t *bcount;      // n_buckets + 1
+    uint32_t *long_list;   // n_genes
+    uint32_t *big_list;    // n_buckets
+    uint32_t *counters;    // [0] long genes, [1] big buckets
+    uint32_t *partials;    // scan scratch
+};
+uint64_t dict_ws_bytes(uint32_t n_genes, uint64_t n_residues, uint32_t k);
+DictBuildWs dict_ws_carve(void *ws, uint32_t n_genes, uint64_t n_residues, uint32_t k);
+hipError_t launch_dict_build(const pdp_genome *g, pdp_dict *d, const DictBuildWs &w, hipStream_t s);
+
+struct PairWs {
+    DevTask *tasks;
+    DevTile *tiles;
+    uint4 *inc;                   // incidences (task, row gene of a, gene of b, min count)
+    unsigned long long *counters; // [0] incidences
+    uint32_t *tile_cnt;           // tiles + 1 (scanned in place into offsets)
+    uint32_t *tile_fill;          // tiles
+    uint2 *recs;                  // incidences bucketed by tile: ((row<<24)|col, v); 2x capacity
+    uint2 *bh_best;               // best (m, d) per best-hit row
+    uint32_t *partials;
+};
+
+struct PlanShape {
+    uint32_t n_tasks, total_chunks, total_tiles, bh_rows, bbh_rows, tile_lds;
+    uint64_t inc_cap;
+};
+uint64_t pair_ws_bytes(const PlanShape &p);
+PairWs pair_ws_carve(void *ws, const PlanShape &p);
+hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp_bbh_out *bbh,
+                        pdp_status *st, hipStream_t s);
+hipError_t launch_bbh_standalone(const pdp_bh_out *ab, const pdp_bh_out *ba, pdp_bbh_out *out,
+                                 pdp_status *st, uint32_t *partials, hipStream_t s);
+
+}  // namespace pdp

@@ -1,0 +1,433 @@
+// Best hits and bidirectional best hits for many genome pairs on gfx950.
+//
+// For a genome pair (A, B) the similarity of Eq. jaccard_k needs, for every
+// gene pair, m = sum over shared k-mers of min(mult_a, mult_b); the sum of
+// maxima over the union is then n_a + n_b - m (max + min = x + y per k-mer).
+// The path never forms the |A| x |B| matrix in HBM:
+//  1. k_join: both genomes' inverted indexes are sorted by code and split into
+//     the same leading-residue bucket ranges; one work-group joins one range
+//     (target side staged in LDS) and emits an incidence (a, b, min count) per
+//     shared (k-mer, gene a, gene b).  Reads are sequential in both indexes.
+//  2. k_inc_bucket: incidences are grouped by accumulation tile (T rows of the
+//     query genome) with a counting sort; each pair contributes to the tiles
+//     of both directions.
+//  3. k_tile: one work-group per tile accumulates m for its T rows against all
+//     columns in LDS (two 16-bit sums per 32-bit word), then one wave per row
+//     finds the row maximum of J = m/d by exact cross-multiplication and
+//     counts or writes every column that reaches it (ties kept, ascending
+//     column order; an all-zero row has no best hit), following Eq. best_hit
+//     and the per-row work of Alg. 2.
+//  4. k_bbh: each best hit (a, b) is kept when a is among b's best hits
+//     (Eq. bidirectional_best_hit, the cross-check of Alg. 3).
+// Counts, scans and writes keep every output in a canonical order, so results
+// do not depend on scheduling.
+#include <algorithm>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace pdp {
+
+constexpr uint32_t kJoinThreads = 256;
+constexpr uint32_t kBucketGroups = 1024;
+
+__device__ __forceinline__ uint32_t find_task(const DevTask *tasks, uint32_t n_tasks, uint32_t chunk) {
+    uint32_t lo = 0, hi = n_tasks - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (tasks[mid].chunk_base <= chunk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <bool STAGED>
+__device__ __forceinline__ void join_range(const DevTask &T, uint32_t task, uint32_t a0, uint32_t a1, const uint64_t *bc,
+                                           const uint32_t *bg, const uint32_t *bn, uint32_t nbe, uint4 *inc, uint64_t inc_cap,
+                                           unsigned long long *inc_count) {
+    const uint64_t *ac = T.a.ix_code;
+    for (uint32_t base = a0; base < a1; base += kJoinThreads) {
+        const uint32_t i = base + threadIdx.x;
+        const bool valid = i < a1;
+        const uint64_t code = valid ? ac[i] : 0;
+        uint32_t lo = 0, hi = valid ? nbe : 0;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (bc[mid] < code) lo = mid + 1;
+            else hi = mid;
+        }
+        uint32_t m = 0;
+        if (valid)
+            while (lo + m < nbe && bc[lo + m] == code) ++m;
+        const unsigned long long slot = wave_reserve(m, inc_count);
+        if (m) {
+            const uint32_t ag = T.a.ix_gene[i], an = T.a.ix_cnt[i];
+            for (uint32_t t = 0; t < m; ++t) {
+                if (slot + t < inc_cap) {
+                    const uint32_t v = min(an, bn[lo + t]);
+                    inc[slot + t] = make_uint4(task, ag, bg[lo + t], v);
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kJoinThreads) void k_join(const DevTask *__restrict__ tasks, uint32_t n_tasks,
+                                                       uint4 *__restrict__ inc, uint64_t inc_cap,
+                                                       unsigned long long *__restrict__ inc_count) {
+    __shared__ uint64_t s_code[kJoinLdsCap];
+    __shared__ uint32_t s_gene[kJoinLdsCap];
+    __shared__ uint32_t s_cnt[kJoinLdsCap];
+    __shared__ uint32_t s_task;
+    const uint32_t chunk = blockIdx.x;
+    if (threadIdx.x == 0) s_task = find_task(tasks, n_tasks, chunk);
+    __syncthreads();
+    const uint32_t task = s_task;
+    const DevTask &T = tasks[task];
+    const uint32_t c = chunk - T.chunk_base;
+    const uint32_t nb = T.a.n_buckets;
+    const uint32_t bl = c * T.bpw;
+    const uint32_t bh = min(nb, bl + T.bpw);
+    const uint32_t a0 = T.a.ix_dir[bl], a1 = T.a.ix_dir[bh];
+    const uint32_t b0 = T.b.ix_dir[bl], b1 = T.b.ix_dir[bh];
+    if (a0 == a1 || b0 == b1) return;
+    const uint32_t nbe = b1 - b0;
+    if (nbe <= kJoinLdsCap) {
+        for (uint32_t i = threadIdx.x; i < nbe; i += kJoinThreads) {
+            s_code[i] = T.b.ix_code[b0 + i];
+            s_gene[i] = T.b.ix_gene[b0 + i];
+            s_cnt[i] = T.b.ix_cnt[b0 + i];
+        }
+        __syncthreads();
+        join_range<true>(T, task, a0, a1, s_code, s_gene, s_cnt, nbe, inc, inc_cap, inc_count);
+    } else {
+        join_range<false>(T, task, a0, a1, T.b.ix_code + b0, T.b.ix_gene + b0, T.b.ix_cnt + b0, nbe, inc, inc_cap,
+                          inc_count);
+    }
+}
+
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void k_inc_bucket(const DevTask *__restrict__ tasks, const uint4 *__restrict__ inc,
+                                                    const unsigned long long *__restrict__ inc_count, uint64_t inc_cap,
+                                                    uint32_t *__restrict__ tile_cnt, const uint32_t *__restrict__ tile_off,
+                                                    uint32_t *__restrict__ tile_fill, uint2 *__restrict__ recs,
+                                                    pdp_status *st) {
+    const unsigned long long total = *inc_count;
+    if (!SCATTER && blockIdx.x == 0 && threadIdx.x == 0 && total > inc_cap) raise_status(st, PDP_E_CAPACITY, total, 0);
+    const uint64_t n = total < inc_cap ? total : inc_cap;
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint4 r = inc[i];
+        const DevTask &T = tasks[r.x];
+#pragma unroll
+        for (uint32_t d = 0; d < 2; ++d) {
+            if (!(T.flags & (1u << d))) continue;
+            const uint32_t row = d == 0 ? r.y : r.z;
+            const uint32_t col = d == 0 ? r.z : r.y;
+            const uint32_t tr = T.tile_rows[d];
+            const uint32_t q = row / tr;
+            const uint32_t tile = T.tile_base[d] + q;
+            if (!SCATTER) {
+                atomicAdd(&tile_cnt[tile], 1u);
+            } else {
+                const uint32_t pos = tile_off[tile] + atomicAdd(&tile_fill[tile], 1u);
+                recs[pos] = make_uint2(((row - q * tr) << 24) | col, r.w);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ bool j_greater(uint32_t m1, uint32_t d1, uint32_t m2, uint32_t d2) {
+    return static_cast<uint64_t>(m1) * d2 > static_cast<uint64_t>(m2) * d1;
+}
+__device__ __forceinline__ bool j_equal(uint32_t m1, uint32_t d1, uint32_t m2, uint32_t d2) {
+    return static_cast<uint64_t>(m1) * d2 == static_cast<uint64_t>(m2) * d1;
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(kTileThreads) void k_tile(const DevTask *__restrict__ tasks, const DevTile *__restrict__ tiles,
+                                                       const uint32_t *__restrict__ tile_off, const uint2 *__restrict__ recs,
+                                                       uint32_t *__restrict__ bh_ptr, uint2 *__restrict__ bh_best,
+                                                       uint32_t *__restrict__ bh_col, uint32_t *__restrict__ bh_num,
+                                                       uint32_t *__restrict__ bh_den, uint64_t bh_cap, uint32_t bh_rows,
+                                                       pdp_status *st) {
+    extern __shared__ uint32_t acc[];
+    const DevTile tl = tiles[blockIdx.x];
+    const DevTask &T = tasks[tl.task];
+    const DevDict &R = tl.dir == 0 ? T.a : T.b;
+    const DevDict &C = tl.dir == 0 ? T.b : T.a;
+    const uint32_t ncols = C.n_genes;
+    const uint32_t W = (ncols + 1) >> 1;
+    if (WRITE && blockIdx.x == 0 && threadIdx.x == 0 && bh_ptr[bh_rows] > bh_cap)
+        raise_status(st, PDP_E_CAPACITY, bh_ptr[bh_rows], 1);
+    for (uint32_t i = threadIdx.x; i < tl.nrows * W; i += kTileThreads) acc[i] = 0;
+    __syncthreads();
+    const uint32_t r0 = tile_off[blockIdx.x], r1 = tile_off[blockIdx.x + 1];
+    for (uint32_t i = r0 + threadIdx.x; i < r1; i += kTileThreads) {
+        const uint2 r = recs[i];
+        const uint32_t rl = r.x >> 24, c = r.x & 0xFFFFFFu;
+        atomicAdd(&acc[rl * W + (c >> 1)], r.y << ((c & 1u) << 4));
+    }
+    __syncthreads();
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    for (uint32_t rl = wave; rl < tl.nrows; rl += kTileThreads / kWave) {
+        const uint32_t row = tl.row0 + rl;
+        const uint32_t grow = T.row_base[tl.dir] + row;
+        const uint32_t nr = R.nwin[row];
+        const uint32_t *arow = acc + rl * W;
+        if (!WRITE) {
+            uint32_t bm = 0, bd = 1;
+            for (uint32_t w = lane; w < W; w += kWave) {
+                const uint32_t v = arow[w];
+                const uint32_t m0 = v & 0xFFFFu, m1 = v >> 16;
+                if (m0) {
+                    const uint32_t d = nr + C.nwin[2 * w] - m0;
+                    if (j_greater(m0, d, bm, bd)) { bm = m0; bd = d; }
+                }
+                if (m1) {
+                    const uint32_t d = nr + C.nwin[2 * w + 1] - m1;
+                    if (j_greater(m1, d, bm, bd)) { bm = m1; bd = d; }
+                }
+            }
+#pragma unroll
+            for (uint32_t o = kWave / 2; o > 0; o >>= 1) {
+                const uint32_t om = __shfl_xor(bm, o, kWave), od = __shfl_xor(bd, o, kWave);
+                if (j_greater(om, od, bm, bd)) { bm = om; bd = od; }
+            }
+            uint32_t cnt = 0;
+            if (bm) {
+                for (uint32_t w = lane; w < W; w += kWave) {
+                    const uint32_t v = arow[w];
+                    const uint32_t m0 = v & 0xFFFFu, m1 = v >> 16;
+                    if (m0 && j_equal(m0, nr + C.nwin[2 * w] - m0, bm, bd)) ++cnt;
+                    if (m1 && j_equal(m1, nr + C.nwin[2 * w + 1] - m1, bm, bd)) ++cnt;
+                }
+            }
+            cnt = wave_sum(cnt);
+            if (lane == 0) {
+                bh_ptr[grow] = cnt;
+                bh_best[grow] = make_uint2(bm, bd);
+            }
+        } else {
+            const uint2 best = bh_best[grow];
+            const uint32_t bm = best.x, bd = best.y;
+            if (bm == 0) continue;
+            uint32_t pos = bh_ptr[grow];
+            for (uint32_t wb = 0; wb < W; wb += kWave) {
+                const uint32_t w = wb + lane;
+                const uint32_t v = w < W ? arow[w] : 0u;
+                const uint32_t m0 = v & 0xFFFFu, m1 = v >> 16;
+                const uint32_t d0 = m0 ? nr + C.nwin[2 * w] - m0 : 1u;
+                const uint32_t d1 = m1 ? nr + C.nwin[2 * w + 1] - m1 : 1u;
+                const bool x0 = m0 && j_equal(m0, d0, bm, bd);
+                const bool x1 = m1 && j_equal(m1, d1, bm, bd);
+                const uint64_t b0 = __ballot(x0), b1 = __ballot(x1);
+                const uint32_t p = pos + mask_below(b0) + mask_below(b1);
+                if (x0 && p < bh_cap) {
+                    bh_col[p] = 2 * w;
+                    bh_num[p] = m0;
+                    bh_den[p] = d0;
+                }
+                if (x1) {
+                    const uint32_t p1 = p + (x0 ? 1u : 0u);
+                    if (p1 < bh_cap) {
+                        bh_col[p1] = 2 * w + 1;
+                        bh_num[p1] = m1;
+                        bh_den[p1] = d1;
+                    }
+                }
+                pos += __popcll(b0) + __popcll(b1);
+            }
+        }
+    }
+}
+
+// BBH of one row: keep each best hit (a, b) whose reverse row contains a.
+template <bool WRITE>
+__device__ __forceinline__ void bbh_row(uint32_t a, uint32_t grow, uint32_t rab, uint32_t ba_base, const uint32_t *ab_ptr,
+                                        const uint32_t *ab_col, const uint32_t *ab_num, const uint32_t *ab_den,
+                                        const uint32_t *ba_ptr, const uint32_t *ba_col, uint32_t *out_ptr, uint32_t *out_a,
+                                        uint32_t *out_b, uint32_t *out_num, uint32_t *out_den, uint64_t cap) {
+    uint32_t pos = WRITE ? out_ptr[grow] : 0u;
+    for (uint32_t p = ab_ptr[rab]; p < ab_ptr[rab + 1]; ++p) {
+        const uint32_t b = ab_col[p];
+        const uint32_t rba = ba_base + b;
+        bool found = false;
+        for (uint32_t q = ba_ptr[rba]; q < ba_ptr[rba + 1]; ++q) {
+            const uint32_t x = ba_col[q];
+            if (x >= a) {
+                found = x == a;
+                break;
+            }
+        }
+        if (found) {
+            if (WRITE && pos < cap) {
+                out_a[pos] = a;
+                out_b[pos] = b;
+                out_num[pos] = ab_num[p];
+                out_den[pos] = ab_den[p];
+            }
+            ++pos;
+        }
+    }
+    if (!WRITE) out_ptr[grow] = pos;
+}
+
+__device__ __forceinline__ uint32_t find_bbh_task(const DevTask *tasks, uint32_t n_tasks, uint32_t row) {
+    uint32_t lo = 0, hi = n_tasks - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (tasks[mid].bbh_row_base <= row) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(256) void k_bbh(const DevTask *__restrict__ tasks, uint32_t n_tasks, uint32_t bbh_rows,
+                                             const uint32_t *__restrict__ bh_ptr, const uint32_t *__restrict__ bh_col,
+                                             const uint32_t *__restrict__ bh_num, const uint32_t *__restrict__ bh_den,
+                                             uint32_t *__restrict__ out_ptr, uint32_t *__restrict__ out_a,
+                                             uint32_t *__restrict__ out_b, uint32_t *__restrict__ out_num,
+                                             uint32_t *__restrict__ out_den, uint64_t cap, pdp_status *st) {
+    const uint32_t grow = blockIdx.x * blockDim.x + threadIdx.x;
+    if (WRITE && grow == 0 && out_ptr[bbh_rows] > cap) raise_status(st, PDP_E_CAPACITY, out_ptr[bbh_rows], 2);
+    if (grow >= bbh_rows) return;
+    const DevTask &T = tasks[find_bbh_task(tasks, n_tasks, grow)];
+    const uint32_t a = grow - T.bbh_row_base;
+    bbh_row<WRITE>(a, grow, T.row_base[0] + a, T.row_base[1], bh_ptr, bh_col, bh_num, bh_den, bh_ptr, bh_col, out_ptr,
+                   out_a, out_b, out_num, out_den, cap);
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(256) void k_bbh_pair(uint32_t rows, const uint32_t *__restrict__ ab_ptr,
+                                                  const uint32_t *__restrict__ ab_col, const uint32_t *__restrict__ ab_num,
+                                                  const uint32_t *__restrict__ ab_den, const uint32_t *__restrict__ ba_ptr,
+                                                  const uint32_t *__restrict__ ba_col, uint32_t ba_rows,
+                                                  uint32_t *__restrict__ out_ptr, uint32_t *__restrict__ out_a,
+                                                  uint32_t *__restrict__ out_b, uint32_t *__restrict__ out_num,
+                                                  uint32_t *__restrict__ out_den, uint64_t cap, pdp_status *st) {
+    const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (WRITE && a == 0 && out_ptr[rows] > cap) raise_status(st, PDP_E_CAPACITY, out_ptr[rows], 2);
+    if (a >= rows) return;
+    // a column index past the reverse output's rows cannot name a best hit there
+    for (uint32_t p = ab_ptr[a]; p < ab_ptr[a + 1]; ++p) {
+        if (ab_col[p] >= ba_rows) {
+            raise_status(st, PDP_E_INVAL, 0, a);
+            if (!WRITE) out_ptr[a] = 0;
+            return;
+        }
+    }
+    bbh_row<WRITE>(a, a, a, 0, ab_ptr, ab_col, ab_num, ab_den, ba_ptr, ba_col, out_ptr, out_a, out_b, out_num, out_den, cap);
+}
+
+// ------------------------------------------------------------------ host
+
+uint64_t pair_ws_bytes(const PlanShape &p) {
+    const uint64_t A = 256;
+    uint64_t s = 0;
+    s += align_up(sizeof(DevTask) * std::max<uint64_t>(p.n_tasks, 1), A);
+    s += align_up(sizeof(DevTile) * std::max<uint64_t>(p.total_tiles, 1), A);
+    s += align_up(16 * std::max<uint64_t>(p.inc_cap, 1), A);
+    s += align_up(16, A);
+    s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
+    s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
+    s += align_up(8 * 2 * std::max<uint64_t>(p.inc_cap, 1), A);
+    s += align_up(8 * (uint64_t(p.bh_rows) + 1), A);
+    const uint64_t np = std::max({scan_partials(p.total_tiles), scan_partials(p.bh_rows), scan_partials(p.bbh_rows)});
+    s += align_up(4 * np, A);
+    return s;
+}
+
+PairWs pair_ws_carve(void *ws, const PlanShape &p) {
+    const uint64_t A = 256;
+    char *q = static_cast<char *>(ws);
+    auto take = [&](uint64_t bytes) {
+        char *r = q;
+        q += align_up(bytes, A);
+        return r;
+    };
+    PairWs w;
+    w.tasks = reinterpret_cast<DevTask *>(take(sizeof(DevTask) * std::max<uint64_t>(p.n_tasks, 1)));
+    w.tiles = reinterpret_cast<DevTile *>(take(sizeof(DevTile) * std::max<uint64_t>(p.total_tiles, 1)));
+    w.inc = reinterpret_cast<uint4 *>(take(16 * std::max<uint64_t>(p.inc_cap, 1)));
+    w.counters = reinterpret_cast<unsigned long long *>(take(16));
+    w.tile_cnt = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
+    w.tile_fill = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
+    w.recs = reinterpret_cast<uint2 *>(take(8 * 2 * std::max<uint64_t>(p.inc_cap, 1)));
+    w.bh_best = reinterpret_cast<uint2 *>(take(8 * (uint64_t(p.bh_rows) + 1)));
+    const uint64_t np = std::max({scan_partials(p.total_tiles), scan_partials(p.bh_rows), scan_partials(p.bbh_rows)});
+    w.partials = reinterpret_cast<uint32_t *>(take(4 * np));
+    return w;
+}
+
+#define PDP_TRY(x)                              \
+    do {                                        \
+        hipError_t e_ = (x);                    \
+        if (e_ != hipSuccess) return e_;        \
+    } while (0)
+
+hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *st,
+                        hipStream_t s) {
+    PDP_TRY(launch_status_init(st, s));
+    PDP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(w.counters), 4, 0u, s));
+    PDP_TRY(launch_fill_u32(w.tile_cnt, uint64_t(p.total_tiles) + 1, 0u, s));
+    PDP_TRY(launch_fill_u32(w.tile_fill, uint64_t(p.total_tiles) + 1, 0u, s));
+    if (p.total_chunks) {
+        hipLaunchKernelGGL(k_join, dim3(p.total_chunks), dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.inc, p.inc_cap,
+                           w.counters);
+        PDP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_inc_bucket<false>, dim3(kBucketGroups), dim3(256), 0, s, w.tasks, w.inc, w.counters, p.inc_cap,
+                       w.tile_cnt, w.tile_cnt, w.tile_fill, w.recs, st);
+    PDP_TRY(hipGetLastError());
+    PDP_TRY(launch_scan(w.tile_cnt, w.tile_cnt, p.total_tiles, w.partials, s));
+    hipLaunchKernelGGL(k_inc_bucket<true>, dim3(kBucketGroups), dim3(256), 0, s, w.tasks, w.inc, w.counters, p.inc_cap,
+                       w.tile_cnt, w.tile_cnt, w.tile_fill, w.recs, st);
+    PDP_TRY(hipGetLastError());
+    if (p.total_tiles) {
+        hipLaunchKernelGGL(k_tile<false>, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
+                           w.tile_cnt, w.recs, bh->ptr, w.bh_best, bh->col, bh->num, bh->den, bh->capacity, p.bh_rows, st);
+        PDP_TRY(hipGetLastError());
+    }
+    PDP_TRY(launch_scan(bh->ptr, bh->ptr, p.bh_rows, w.partials, s));
+    if (p.total_tiles) {
+        hipLaunchKernelGGL(k_tile<true>, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
+                           w.tile_cnt, w.recs, bh->ptr, w.bh_best, bh->col, bh->num, bh->den, bh->capacity, p.bh_rows, st);
+        PDP_TRY(hipGetLastError());
+    }
+    if (p.bbh_rows && bbh) {
+        const uint32_t g = (p.bbh_rows + 255) / 256;
+        hipLaunchKernelGGL(k_bbh<false>, dim3(g), dim3(256), 0, s, w.tasks, p.n_tasks, p.bbh_rows, bh->ptr, bh->col,
+                           bh->num, bh->den, bbh->ptr, bbh->a, bbh->b, bbh->num, bbh->den, bbh->capacity, st);
+        PDP_TRY(hipGetLastError());
+        PDP_TRY(launch_scan(bbh->ptr, bbh->ptr, p.bbh_rows, w.partials, s));
+        hipLaunchKernelGGL(k_bbh<true>, dim3(g), dim3(256), 0, s, w.tasks, p.n_tasks, p.bbh_rows, bh->ptr, bh->col,
+                           bh->num, bh->den, bbh->ptr, bbh->a, bbh->b, bbh->num, bbh->den, bbh->capacity, st);
+        PDP_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_bbh_standalone(const pdp_bh_out *ab, const pdp_bh_out *ba, pdp_bbh_out *out, pdp_status *st,
+                                 uint32_t *partials, hipStream_t s) {
+    PDP_TRY(launch_status_init(st, s));
+    const uint32_t rows = ab->n_rows;
+    if (rows) {
+        const uint32_t g = (rows + 255) / 256;
+        hipLaunchKernelGGL(k_bbh_pair<false>, dim3(g), dim3(256), 0, s, rows, ab->ptr, ab->col, ab->num, ab->den, ba->ptr,
+                           ba->col, ba->n_rows, out->ptr, out->a, out->b, out->num, out->den, out->capacity, st);
+        PDP_TRY(hipGetLastError());
+    }
+    PDP_TRY(launch_scan(out->ptr, out->ptr, rows, partials, s));
+    if (rows) {
+        const uint32_t g = (rows + 255) / 256;
+        hipLaunchKernelGGL(k_bbh_pair<true>, dim3(g), dim3(256), 0, s, rows, ab->ptr, ab->col, ab->num, ab->den, ba->ptr,
+                           ba->col, ba->n_rows, out->ptr, out->a, out->b, out->num, out->den, out->capacity, st);
+        PDP_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
+}  // namespace pdp

@@ -1,0 +1,86 @@
+"""Shared test helpers: comparing the GPU path's outputs with the CPU oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+LEAD = 4
+
+
+def gpu_code_to_base20(codes: np.ndarray, k: int) -> np.ndarray:
+    """The GPU packs residues 5 bits each; the oracle numbers k-mers in base 20.  Both are injective
+    on k-mers, so translating one into the other lets the two dictionaries be compared by content."""
+    codes = codes.astype(np.uint64)
+    out = np.zeros(codes.shape, dtype=np.uint64)
+    for i in range(k):
+        sym = (codes >> np.uint64(5 * (k - 1 - i))) & np.uint64(31)
+        assert np.all(sym < 20), "a 5-bit residue symbol outside 0..19"
+        out = out * np.uint64(20) + sym
+    return out
+
+
+def check_dictionary(host: dict, og: oracle.OracleGenome) -> None:
+    """Every array of a GPU dictionary against the oracle's multiplicity vectors."""
+    k = og.k
+    assert np.array_equal(host["nwin"].astype(np.uint64), og.nwin), "windows per gene"
+    assert np.array_equal(host["mv_ptr"].astype(np.uint64), og.ptr), "distinct k-mers per gene"
+    assert np.array_equal(gpu_code_to_base20(host["mv_code"], k), og.ids), "multiplicity-vector k-mers"
+    assert np.array_equal(host["mv_cnt"], og.cnt), "multiplicities"
+    # inverted index: every (k-mer, gene, count) ordered by k-mer then gene
+    genes = np.repeat(np.arange(og.n, dtype=np.uint32), np.diff(og.ptr).astype(np.int64))
+    order = np.lexsort((genes, og.ids))
+    assert np.array_equal(gpu_code_to_base20(host["ix_code"], k), og.ids[order]), "index codes"
+    assert np.array_equal(host["ix_gene"], genes[order]), "index genes"
+    assert np.array_equal(host["ix_cnt"], og.cnt[order]), "index counts"
+    lead = min(k, LEAD)
+    bucket = (og.ids // np.uint64(20 ** (k - lead))).astype(np.int64)
+    dir_ = np.zeros(20 ** lead + 1, dtype=np.int64)
+    np.add.at(dir_, bucket + 1, 1)
+    assert np.array_equal(host["ix_dir"].astype(np.int64), np.cumsum(dir_)), "index directory"
+
+
+def check_bh(got, want: oracle.BH, rows=None) -> None:
+    """got = (ptr, col, num, den) of every row; want = oracle BH of all rows, or of ``rows``."""
+    ptr, col, num, den = got
+    if rows is None:
+        assert np.array_equal(ptr.astype(np.uint64), want.ptr), "best-hit counts per row"
+        assert np.array_equal(col, want.col), "best-hit columns"
+        assert np.array_equal(num.astype(np.uint64), want.num), "sums of minima"
+        assert np.array_equal(den.astype(np.uint64), want.den), "sums of maxima"
+        return
+    for i, r in enumerate(rows):
+        lo, hi = int(ptr[r]), int(ptr[r + 1])
+        wc, wn, wd = want.row(i)
+        assert np.array_equal(col[lo:hi], wc), f"row {r}: columns"
+        assert np.array_equal(num[lo:hi].astype(np.uint64), wn), f"row {r}: sums of minima"
+        assert np.array_equal(den[lo:hi].astype(np.uint64), wd), f"row {r}: sums of maxima"
+
+
+def check_bbh(got, want: oracle.Pairs) -> None:
+    a, b, num, den = got
+    assert np.array_equal(a, want.a) and np.array_equal(b, want.b), "BBH pairs"
+    assert np.array_equal(num.astype(np.uint64), want.num) and np.array_equal(den.astype(np.uint64), want.den)
+
+
+def check_bh_properties(bh_ab, bh_ba, bbh, n_a: int, n_b: int) -> None:
+    """Properties that hold at any size: CSR well-formed, columns ascending and in range,
+    0 < num <= den, ties equal in value, BBH inside both best-hit sets and in (a, b) order."""
+    for (ptr, col, num, den), ncols in ((bh_ab, n_b), (bh_ba, n_a)):
+        p = ptr.astype(np.int64)
+        assert p[0] == 0 and np.all(np.diff(p) >= 0)
+        assert np.all(col < ncols)
+        assert np.all(num > 0) and np.all(num <= den)
+        for r in np.nonzero(np.diff(p) > 1)[0]:
+            lo, hi = p[r], p[r + 1]
+            assert np.all(np.diff(col[lo:hi].astype(np.int64)) > 0), "columns ascending"
+            x = num[lo:hi].astype(np.uint64) * den[lo].astype(np.uint64)
+            y = num[lo].astype(np.uint64) * den[lo:hi].astype(np.uint64)
+            assert np.array_equal(x, y), "ties share one value"
+    a, b, num, den = bbh
+    key = a.astype(np.int64) * (n_b + 1) + b
+    assert np.all(np.diff(key) > 0), "BBH in (a, b) order"
+    pab, cab = bh_ab[0].astype(np.int64), bh_ab[1]
+    pba, cba = bh_ba[0].astype(np.int64), bh_ba[1]
+    for x, y in zip(a.tolist(), b.tolist()):
+        assert y in cab[pab[x]:pab[x + 1]] and x in cba[pba[y]:pba[y + 1]]

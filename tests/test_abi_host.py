@@ -1,0 +1,140 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every
+function include/pdp.h declares, and its host-only logic (k rule, sizes, bind,
+planning, validation) behaves as documented."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import oracle
+import paper_2510_23679_amd as pdp
+from paper_2510_23679_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pdp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pdp_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = pdp.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(B.SIGNATURES), "binding and header list different functions"
+
+
+def test_abi_version_matches_header():
+    m = re.search(r"#define PDP_ABI_VERSION (\d+)u", open(HEADER).read())
+    assert pdp.abi_version() == int(m.group(1))
+
+
+def test_strerror_covers_codes():
+    L = pdp.lib()
+    for code in range(0, -10, -1):
+        assert L.pdp_strerror(code).decode() not in ("", "unknown error")
+    assert L.pdp_strerror(-99).decode() == "unknown error"
+
+
+def test_k_rule_matches_oracle():
+    totals = [0, 1, 2, 19, 20, 21, 399, 400, 401, 160000, 160001, 10212983, 64 * 10 ** 6, 71 * 10 ** 6,
+              20 ** 12, 20 ** 12 + 1, 2 ** 64 - 1]
+    for t in totals:
+        for a in (4, 20):
+            for mode in (0, 1):
+                assert pdp.k_rule(t, a, mode) == oracle.k_rule(t, a, mode), (t, a, mode)
+    with pytest.raises(pdp.PdpError):
+        pdp.k_rule(100, 1)
+
+
+def test_dict_size_validation():
+    arena, ws = pdp.dict_size(3000, 10 ** 6, 6)
+    assert arena > 12 * 10 ** 6 * 2 and ws > 8 * 10 ** 6
+    for k in (0, 13):
+        with pytest.raises(pdp.PdpError) as e:
+            pdp.dict_size(10, 100, k)
+        assert e.value.code == pdp.PDP_E_KRANGE
+    with pytest.raises(pdp.PdpError) as e:
+        pdp.dict_size(10, 2 ** 32, 6)
+    assert e.value.code == pdp.PDP_E_LIMIT
+
+
+def _fake_dict(n_genes, n_residues, k, base=1 << 20):
+    """Binds a dictionary to a fake (never dereferenced) aligned address: binding and
+    planning only do host arithmetic on the pointers."""
+    arena, _ = pdp.dict_size(n_genes, n_residues, k)
+    d = B.pdp_dict()
+    B.check(pdp.lib().pdp_dict_bind(base, arena, n_genes, n_residues, k, C.byref(d)), "bind")
+    return d
+
+
+def test_bind_checks_alignment_and_size():
+    arena, _ = pdp.dict_size(10, 100, 3)
+    d = B.pdp_dict()
+    assert pdp.lib().pdp_dict_bind(4096 + 8, arena, 10, 100, 3, C.byref(d)) == pdp.PDP_E_INVAL
+    assert pdp.lib().pdp_dict_bind(4096, arena - 1, 10, 100, 3, C.byref(d)) == pdp.PDP_E_WORKSPACE
+    assert pdp.lib().pdp_dict_bind(4096, arena, 10, 100, 3, C.byref(d)) == 0
+    assert d.n_buckets == 20 ** 3 and d.capacity == 101
+    assert d.nwin % 256 == 0 and d.ix_code > d.mv_code > d.nwin
+
+
+def _plan(tasks, prm=None):
+    arr = (B.pdp_task * len(tasks))()
+    for i, (a, b, f) in enumerate(tasks):
+        arr[i].a = C.pointer(a)
+        arr[i].b = C.pointer(b)
+        arr[i].flags = f
+    h = B.vp()
+    rc = pdp.lib().pdp_plan_create(arr, len(tasks), C.byref(prm or pdp.params()), C.byref(h))
+    return rc, h
+
+
+def test_plan_layout():
+    a, b, c = _fake_dict(300, 90000, 5), _fake_dict(200, 60000, 5), _fake_dict(50, 9000, 5)
+    rc, h = _plan([(a, b, pdp.PDP_TASK_BBH), (a, c, pdp.PDP_TASK_AB), (c, b, pdp.PDP_TASK_BA)],
+                  pdp.params(tile_rows=16))
+    assert rc == 0
+    L = pdp.lib()
+    info = B.pdp_plan_info()
+    assert L.pdp_plan_info_get(h, C.byref(info)) == 0
+    assert info.bh_rows == 300 + 200 + 300 + 200
+    assert info.bbh_rows == 300
+    assert info.tiles == 19 + 13 + 19 + 13
+    rows = []
+    for t in range(3):
+        x, y, z = B.u32(), B.u32(), B.u32()
+        assert L.pdp_plan_rows(h, t, C.byref(x), C.byref(y), C.byref(z)) == 0
+        rows.append((x.value, y.value, z.value))
+    none = 2 ** 32 - 1
+    assert rows == [(0, 300, 0), (500, none, none), (none, 800, none)]
+    assert L.pdp_plan_rows(h, 3, None, None, None) == pdp.PDP_E_INVAL
+    L.pdp_plan_destroy(h)
+
+
+def test_plan_rejects_bad_tasks():
+    a5, b6 = _fake_dict(10, 900, 5), _fake_dict(10, 900, 6)
+    assert _plan([(a5, b6, pdp.PDP_TASK_AB)])[0] == pdp.PDP_E_INVAL
+    assert _plan([(a5, a5, 0)])[0] == pdp.PDP_E_INVAL
+    big = _fake_dict(30000, 9 * 10 ** 6, 5)
+    assert _plan([(a5, big, pdp.PDP_TASK_AB)])[0] == pdp.PDP_E_LIMIT
+    assert _plan([(a5, big, pdp.PDP_TASK_BA)])[0] == 0  # the big genome as rows fits
+    assert _plan([(a5, a5, 1)], pdp.params(lds_budget=1 << 20))[0] == pdp.PDP_E_INVAL
+
+
+def test_launch_validates_outputs():
+    a = _fake_dict(10, 900, 5)
+    rc, h = _plan([(a, a, pdp.PDP_TASK_BBH)])
+    assert rc == 0
+    out = B.pdp_bh_out(19, 0, 0, 4096, 0, 0, 0)  # wrong row count (plan has 20)
+    rc = pdp.lib().pdp_plan_launch(h, C.byref(out), None, 4096, 4096, 1 << 30, None)
+    assert rc == pdp.PDP_E_INVAL
+    out = B.pdp_bh_out(20, 0, 0, 4096, 0, 0, 0)
+    rc = pdp.lib().pdp_plan_launch(h, C.byref(out), None, 4096, 4096, 1 << 30, None)
+    assert rc == pdp.PDP_E_INVAL  # BBH requested, no BBH output
+    pdp.lib().pdp_plan_destroy(h)

@@ -1,0 +1,258 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle, element by element.
+
+Every integer output must be bit-exact: dictionaries, best-hit sets with their
+(sum of minima, sum of maxima), and BBH pairs.  Each test prints its case
+before touching the GPU.
+"""
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import check_bbh, check_bh, check_bh_properties, check_dictionary
+from synth import genome_from_strings, make_config
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU collection
+    pytest.skip("needs the GPU", allow_module_level=True)
+
+import paper_2510_23679_amd as pdp  # noqa: E402
+
+ALPHA = "ACDEFGHIKLMNPQRSTVWY"
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def run_all(genomes, k, prm=None, flags=pdp.PDP_TASK_BBH, pairs=None):
+    dicts = [pdp.Dictionary.build_from(g, k) for g in genomes]
+    runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts, pairs, flags), prm)
+    runner.run()
+    for d in dicts:
+        d.check_status()
+    return dicts, runner.results()
+
+
+def compare_all(genomes, k, res, pairs=None):
+    og, want = oracle.all_pairs(genomes, k, pairs=pairs)
+    keys = list(want.keys())
+    for t, key in enumerate(keys):
+        ab, ba, bb = want[key]
+        check_bh(res.best_hits(t, 0), ab)
+        check_bh(res.best_hits(t, 1), ba)
+        check_bbh(res.bbh_pairs(t), bb)
+    return og
+
+
+# ------------------------------------------------------------ hand examples
+
+def test_hand_examples(golden):
+    for e in golden["best_hits"]:
+        say("hand example", e["id"])
+        gi, gj = genome_from_strings(e["gi"]), genome_from_strings(e["gj"])
+        _, res = run_all([gi, gj], e["k"])
+        for direction, key in ((0, "bh_ij"), (1, "bh_ji")):
+            ptr, col, num, den = res.best_hits(0, direction)
+            got = [[(int(col[p]), int(num[p]), int(den[p])) for p in range(ptr[r], ptr[r + 1])]
+                   for r in range(len(ptr) - 1)]
+            assert got == [[tuple(x) for x in row] for row in e[key]], e["id"]
+        a, b, _, _ = res.bbh_pairs(0)
+        assert [[int(x), int(y)] for x, y in zip(a, b)] == e["bbh"], e["id"]
+
+
+def test_jaccard_examples(golden):
+    for e in golden["jaccard"]:
+        if e["num"] == 0:
+            continue
+        say("jaccard example", e["id"])
+        _, res = run_all([genome_from_strings([e["a"]]), genome_from_strings([e["b"]])], e["k"])
+        ptr, col, num, den = res.best_hits(0, 0)
+        assert (int(num[0]), int(den[0])) == (e["num"], e["den"]), e["id"]
+
+
+def test_windows_examples(golden):
+    for w in golden["windows"]:
+        say("window example", w["id"])
+        g = genome_from_strings([w["gene"]])
+        d = pdp.Dictionary.build_from(g, w["k"])
+        d.check_status()
+        check_dictionary(d.host(), oracle.OracleGenome(g, w["k"]))
+
+
+# ------------------------------------------------------------- dictionaries
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 12])
+def test_dictionary_parity(k):
+    say("dictionary parity k =", k)
+    ds = make_config(2, genomes=1, genes=300)
+    g = ds.genomes[0]
+    d = pdp.Dictionary.build_from(g, k)
+    d.check_status()
+    check_dictionary(d.host(), oracle.OracleGenome(g, k))
+
+
+def test_dictionary_long_genes_and_big_buckets():
+    # genes longer than the LDS sort (2048 windows) and leading-residue buckets far above
+    # the per-thread insertion sort and the LDS bucket sort (low-complexity prefixes)
+    rng = random.Random(3)
+    genes = ["A" * 5000 + "".join(rng.choice(ALPHA) for _ in range(300))]
+    genes += ["".join(rng.choice("AC") for _ in range(3000))]
+    genes += ["AAAA" + "".join(rng.choice(ALPHA) for _ in range(rng.randint(4, 30))) for _ in range(3000)]
+    genes += ["", "M", "MK"]
+    g = genome_from_strings(genes)
+    for k in (4, 6):
+        say("long genes / big buckets, k =", k)
+        d = pdp.Dictionary.build_from(g, k)
+        d.check_status()
+        check_dictionary(d.host(), oracle.OracleGenome(g, k))
+
+
+def test_dictionary_rejects_bad_residue():
+    say("alphabet error")
+    g = genome_from_strings(["MKVLA", "ACDXE", "MKB"])
+    d = pdp.Dictionary.build_from(g, 2)
+    code, needed, where = d.status()
+    assert code == pdp.PDP_E_ALPHABET and where == 8
+
+
+def test_dictionary_rejects_too_many_windows():
+    say("window limit")
+    g = genome_from_strings(["A" * 70000, "MKV"])
+    d = pdp.Dictionary.build_from(g, 3)
+    code, needed, where = d.status()
+    assert code == pdp.PDP_E_LIMIT and where == 0 and needed == 70000 - 3 + 1
+
+
+# ----------------------------------------------------------- best hits, BBH
+
+def test_planted_pair_full():
+    say("planted pair, 2 x 200 genes")
+    ds = make_config(1)
+    k = pdp.k_rule(ds.total_residues())
+    assert k == oracle.k_rule(ds.total_residues()) == 4
+    dicts, res = run_all(ds.genomes, k)
+    for d, g in zip(dicts, ds.genomes):
+        check_dictionary(d.host(), oracle.OracleGenome(g, k))
+    compare_all(ds.genomes, k, res)
+
+
+@pytest.mark.parametrize("k", [4, 5, 6])
+def test_family_model_small_all_pairs(k):
+    say("family model, 4 genomes x 400 genes, k =", k)
+    ds = make_config(2, genomes=4, genes=400)
+    _, res = run_all(ds.genomes, k)
+    compare_all(ds.genomes, k, res)
+
+
+def test_paralog_ties():
+    say("paralog copies (exact ties), 3 genomes")
+    ds = make_config(3, genomes=3, genes_lo=300, genes_hi=500, core=150)
+    k = 5
+    _, res = run_all(ds.genomes, k)
+    compare_all(ds.genomes, k, res)
+    ptr = res.best_hits(0, 0)[0].astype(np.int64)
+    assert np.any(np.diff(ptr) > 1), "the workload should produce tied best hits"
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_tiny_with_ties(seed):
+    rng = random.Random(seed)
+    alpha = ALPHA[: rng.choice([2, 3, 4, 20])]
+    k = rng.choice([1, 2, 3])
+    gens = []
+    for _ in range(3):
+        genes = ["".join(rng.choice(alpha) for _ in range(rng.randint(0, 40))) for _ in range(rng.randint(1, 30))]
+        genes += genes[: rng.randint(0, 3)]  # duplicates force ties
+        gens.append(genome_from_strings(genes))
+    say("random tiny, seed", seed, "alphabet", len(alpha), "k", k)
+    _, res = run_all(gens, k)
+    compare_all(gens, k, res)
+
+
+def test_genome_without_genes():
+    say("empty genome")
+    a = genome_from_strings(["MKVLA", "MKVIA"])
+    b = genome_from_strings([])
+    _, res = run_all([a, b], 2)
+    ptr, col, _, _ = res.best_hits(0, 0)
+    assert list(ptr) == [0, 0, 0] and len(col) == 0
+    assert len(res.best_hits(0, 1)[0]) == 1
+    assert len(res.bbh_pairs(0)[0]) == 0
+
+
+@pytest.mark.parametrize("prm", [dict(tile_rows=1), dict(tile_rows=7, join_entries=64),
+                                 dict(lds_budget=8192, join_entries=2048), dict(inc_capacity=100)])
+def test_tuning_knobs_do_not_change_results(prm):
+    say("tuning", prm)
+    ds = make_config(2, genomes=3, genes=300)
+    k = 5
+    _, res = run_all(ds.genomes, k, pdp.params(**prm))
+    compare_all(ds.genomes, k, res)
+
+
+def test_join_global_search_path():
+    # one leading-residue bucket holding more target entries than the join stages in LDS
+    rng = random.Random(11)
+    a = genome_from_strings(["WWWW" + "".join(rng.choice(ALPHA) for _ in range(8)) for _ in range(300)])
+    b = genome_from_strings(["WWWW" + "".join(rng.choice(ALPHA) for _ in range(6)) for _ in range(3000)])
+    say("join with a bucket past the LDS stage")
+    _, res = run_all([a, b], 6, pdp.params(join_entries=16))
+    compare_all([a, b], 6, res)
+
+
+def test_single_direction_and_standalone_bbh():
+    say("pdp_bh both ways + pdp_bbh")
+    ds = make_config(2, genomes=2, genes=350)
+    k = 5
+    da, db = (pdp.Dictionary.build_from(g, k) for g in ds.genomes)
+    ab = pdp.bh(da, db)
+    ba = pdp.bh(db, da)
+    out = pdp.bbh(ab, ba)
+    oa, ob = (oracle.OracleGenome(g, k) for g in ds.genomes)
+    wab, wba = oracle.bh(oa, ob), oracle.bh(ob, oa)
+    check_bh(ab.host(), wab)
+    check_bh(ba.host(), wba)
+    ptr, a, b, num, den = out.host()
+    check_bbh((a, b, num, den), oracle.bbh(wab, wba))
+
+
+def test_repeat_runs_identical():
+    say("determinism across runs")
+    ds = make_config(2, genomes=3, genes=300)
+    dicts = [pdp.Dictionary.build_from(g, 5) for g in ds.genomes]
+    runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts))
+    runner.run()
+    first = runner.results()
+    for _ in range(3):
+        runner.run()
+        again = runner.results()
+        for x, y in zip(first.bh + first.bbh, again.bh + again.bbh):
+            assert np.array_equal(x, y)
+
+
+def test_full_size_family_model_sampled():
+    """All 45 pairs of the 10 x 3000-gene workload in one launch (the benchmark's configuration);
+    sampled rows against the oracle, every output against the any-size properties."""
+    ds = make_config(2)
+    k = pdp.k_rule(ds.total_residues())
+    assert k == 6
+    say("full-size 10 x 3000 workload, k =", k)
+    dicts = [pdp.Dictionary.build_from(g, k) for g in ds.genomes]
+    runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts))
+    runner.run()
+    res = runner.results()
+    og = [oracle.OracleGenome(g, k) for g in ds.genomes]
+    rng = np.random.default_rng(7)
+    for t, (i, j) in enumerate(ds.pairs()):
+        ab, ba, bb = res.best_hits(t, 0), res.best_hits(t, 1), res.bbh_pairs(t)
+        check_bh_properties(ab, ba, bb, ds.genomes[i].n_genes, ds.genomes[j].n_genes)
+        if t % 5 == 0:
+            rows = np.sort(rng.choice(ds.genomes[i].n_genes, 24, replace=False))
+            rows = np.concatenate([[0], rows, [ds.genomes[i].n_genes - 1]])
+            check_bh(ab, oracle.bh(og[i], og[j], rows=rows), rows=rows)
+            cols = np.sort(rng.choice(ds.genomes[j].n_genes, 24, replace=False))
+            check_bh(ba, oracle.bh(og[j], og[i], rows=cols), rows=cols)
