@@ -239,6 +239,24 @@ int32_t pdp_plan_upload(const pdp_plan *plan, void *ws, uint64_t ws_bytes, void 
 int32_t pdp_plan_launch(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *status,
                         void *ws, uint64_t ws_bytes, void *stream);
 
+/* Kernels of a plan launch, for pdp_plan_timer_start. */
+#define PDP_KERNEL_JOIN 0        /* shared-k-mer join of the two indexes */
+#define PDP_KERNEL_BUCKET 1      /* incidences grouped by tile (count and scatter passes together) */
+#define PDP_KERNEL_TILE_COUNT 2  /* LDS accumulation, row maxima and tie counts */
+#define PDP_KERNEL_TILE_WRITE 3  /* LDS accumulation and best-hit output */
+#define PDP_KERNEL_BBH 4         /* BBH count and write passes together */
+#define PDP_KERNEL_ALL 5         /* the whole launch */
+
+/* Measurement hook: from now on every pdp_plan_launch of this plan records a
+ * pair of HIP events (owned by the plan) on its stream around the given
+ * kernel, for at most max_launches launches.  pdp_plan_timer_read waits for
+ * the recorded events and returns the summed milliseconds and the number of
+ * timed launches; pdp_plan_timer_stop releases the events.  Host only apart
+ * from the event records.  Errors: PDP_E_INVAL, PDP_E_HIP. */
+int32_t pdp_plan_timer_start(pdp_plan *plan, int32_t kernel, uint32_t max_launches);
+int32_t pdp_plan_timer_read(pdp_plan *plan, double *total_ms, uint32_t *launches);
+int32_t pdp_plan_timer_stop(pdp_plan *plan);
+
 /* Upload + launch. */
 int32_t pdp_plan_run(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *status,
                      void *ws, uint64_t ws_bytes, void *stream);

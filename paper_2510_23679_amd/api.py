@@ -265,6 +265,18 @@ class Plan:
         self.upload(ws, stream)
         self.launch(bh, bbh, status, ws, stream)
 
+    def timer_start(self, kernel: int, max_launches: int) -> None:
+        """HIP events around one kernel of each later launch, on the launch's own stream."""
+        check(lib().pdp_plan_timer_start(self.h, int(kernel), int(max_launches)), "pdp_plan_timer_start")
+
+    def timer_read(self) -> Tuple[float, int]:
+        ms, n = C.c_double(0), B.u32(0)
+        check(lib().pdp_plan_timer_read(self.h, C.byref(ms), C.byref(n)), "pdp_plan_timer_read")
+        return float(ms.value), int(n.value)
+
+    def timer_stop(self) -> None:
+        check(lib().pdp_plan_timer_stop(self.h), "pdp_plan_timer_stop")
+
 
 @dataclass
 class PairResults:

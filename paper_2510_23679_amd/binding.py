@@ -32,6 +32,9 @@ PDP_TASK_BBH = 4
 PDP_K_MAX = 12
 PDP_MAX_WINDOWS = 65535
 
+# kernels that pdp_plan_timer_start can time
+KERNELS = {"join": 0, "bucket": 1, "tile_count": 2, "tile_write": 3, "bbh": 4, "all": 5}
+
 
 class pdp_status(C.Structure):
     _fields_ = [("code", i32), ("reserved", u32), ("needed", u64), ("where", u64)]
@@ -87,7 +90,10 @@ SIGNATURES = {
     "pdp_plan_upload": (i32, [vp, vp, u64, vp]),
     "pdp_plan_launch": (i32, [vp, C.POINTER(pdp_bh_out), C.POINTER(pdp_bbh_out), vp, vp, u64, vp]),
     "pdp_plan_run": (i32, [vp, C.POINTER(pdp_bh_out), C.POINTER(pdp_bbh_out), vp, vp, u64, vp]),
-    "pdp_bh_ws_size": (i32, [C.POINTER(pdp_dict), C.POINTER(pdp_dict), C.POINTER(pdp_params), C.POINTER(u64)]),
+    "pdp_plan_timer_start": (i32, [vp, i32, u32]),
+    "pdp_plan_timer_read": (i32, [vp, C.POINTER(C.c_double), C.POINTER(u32)]),
+    "pdp_plan_timer_stop": (i32, [vp]),
+    "pdp_bh_ws_size":(i32, [C.POINTER(pdp_dict), C.POINTER(pdp_dict), C.POINTER(pdp_params), C.POINTER(u64)]),
     "pdp_bh": (i32, [C.POINTER(pdp_dict), C.POINTER(pdp_dict), C.POINTER(pdp_params), C.POINTER(pdp_bh_out), vp, vp,
                      u64, vp]),
     "pdp_bbh_ws_size": (i32, [u32, C.POINTER(u64)]),

@@ -41,6 +41,21 @@ struct pdp_plan {
     std::vector<uint32_t> ab_row, ba_row, bbh_row;
     PlanShape shape;
     uint64_t ws_bytes;
+    // measurement hook: event pairs owned by the plan, one per timed launch
+    mutable int32_t timer_kernel = -1;
+    mutable uint32_t timer_used = 0;
+    mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_events;
+
+    void timer_release() const {
+        for (auto &e : timer_events) {
+            hipEventDestroy(e.first);
+            hipEventDestroy(e.second);
+        }
+        timer_events.clear();
+        timer_kernel = -1;
+        timer_used = 0;
+    }
+    ~pdp_plan() { timer_release(); }
 };
 
 extern "C" {
@@ -339,8 +354,58 @@ int32_t pdp_plan_launch(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, 
     if (rc) return rc;
     if (ws_bytes < plan->ws_bytes) return fail(PDP_E_WORKSPACE, "workspace %llu < %llu bytes", (unsigned long long)ws_bytes, (unsigned long long)plan->ws_bytes);
     PairWs w = pair_ws_carve(ws, plan->shape);
-    hipError_t e = launch_pairs(plan->shape, w, bh, plan->shape.bbh_rows ? bbh : nullptr, status, static_cast<hipStream_t>(stream));
+    KernelTimer timer{-1, nullptr, nullptr};
+    if (plan->timer_kernel >= 0 && plan->timer_used < plan->timer_events.size()) {
+        timer.kernel = plan->timer_kernel;
+        timer.start = plan->timer_events[plan->timer_used].first;
+        timer.stop = plan->timer_events[plan->timer_used].second;
+        plan->timer_used++;
+    }
+    hipError_t e = launch_pairs(plan->shape, w, bh, plan->shape.bbh_rows ? bbh : nullptr, status,
+                                static_cast<hipStream_t>(stream), timer.kernel >= 0 ? &timer : nullptr);
     if (e != hipSuccess) return hip_fail(e, "pdp_plan_launch");
+    return ok();
+}
+
+int32_t pdp_plan_timer_start(pdp_plan *plan, int32_t kernel, uint32_t max_launches) {
+    if (!plan || kernel < PDP_KERNEL_JOIN || kernel > PDP_KERNEL_ALL || max_launches == 0)
+        return fail(PDP_E_INVAL, "pdp_plan_timer_start: bad argument");
+    plan->timer_release();
+    for (uint32_t i = 0; i < max_launches; ++i) {
+        hipEvent_t a, b;
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return hip_fail(e, "pdp_plan_timer_start");
+        e = hipEventCreate(&b);
+        if (e != hipSuccess) {
+            hipEventDestroy(a);
+            return hip_fail(e, "pdp_plan_timer_start");
+        }
+        plan->timer_events.emplace_back(a, b);
+    }
+    plan->timer_kernel = kernel;
+    plan->timer_used = 0;
+    return ok();
+}
+
+int32_t pdp_plan_timer_read(pdp_plan *plan, double *total_ms, uint32_t *launches) {
+    if (!plan || !total_ms || !launches) return fail(PDP_E_INVAL, "pdp_plan_timer_read: null pointer");
+    double sum = 0;
+    for (uint32_t i = 0; i < plan->timer_used; ++i) {
+        hipError_t e = hipEventSynchronize(plan->timer_events[i].second);
+        if (e != hipSuccess) return hip_fail(e, "pdp_plan_timer_read");
+        float ms = 0;
+        e = hipEventElapsedTime(&ms, plan->timer_events[i].first, plan->timer_events[i].second);
+        if (e != hipSuccess) return hip_fail(e, "pdp_plan_timer_read");
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = plan->timer_used;
+    return ok();
+}
+
+int32_t pdp_plan_timer_stop(pdp_plan *plan) {
+    if (!plan) return fail(PDP_E_INVAL, "pdp_plan_timer_stop: null plan");
+    plan->timer_release();
     return ok();
 }
 

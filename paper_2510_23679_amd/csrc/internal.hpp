@@ -102,8 +102,13 @@ struct PlanShape {
 };
 uint64_t pair_ws_bytes(const PlanShape &p);
 PairWs pair_ws_carve(void *ws, const PlanShape &p);
+// Optional events recorded around one kernel of a launch (kernel < 0: none).
+struct KernelTimer {
+    int32_t kernel;
+    hipEvent_t start, stop;
+};
 hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp_bbh_out *bbh,
-                        pdp_status *st, hipStream_t s);
+                        pdp_status *st, hipStream_t s, const KernelTimer *timer);
 hipError_t launch_bbh_standalone(const pdp_bh_out *ab, const pdp_bh_out *ba, pdp_bbh_out *out,
                                  pdp_status *st, uint32_t *partials, hipStream_t s);
 

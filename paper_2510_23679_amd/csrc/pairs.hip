@@ -369,16 +369,24 @@ PairWs pair_ws_carve(void *ws, const PlanShape &p) {
     } while (0)
 
 hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *st,
-                        hipStream_t s) {
+                        hipStream_t s, const KernelTimer *timer) {
+    auto mark = [&](int32_t kernel, bool begin) -> hipError_t {
+        if (!timer || timer->kernel != kernel) return hipSuccess;
+        return hipEventRecord(begin ? timer->start : timer->stop, s);
+    };
+    PDP_TRY(mark(PDP_KERNEL_ALL, true));
     PDP_TRY(launch_status_init(st, s));
     PDP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(w.counters), 4, 0u, s));
     PDP_TRY(launch_fill_u32(w.tile_cnt, uint64_t(p.total_tiles) + 1, 0u, s));
     PDP_TRY(launch_fill_u32(w.tile_fill, uint64_t(p.total_tiles) + 1, 0u, s));
+    PDP_TRY(mark(PDP_KERNEL_JOIN, true));
     if (p.total_chunks) {
         hipLaunchKernelGGL(k_join, dim3(p.total_chunks), dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.inc, p.inc_cap,
                            w.counters);
         PDP_TRY(hipGetLastError());
     }
+    PDP_TRY(mark(PDP_KERNEL_JOIN, false));
+    PDP_TRY(mark(PDP_KERNEL_BUCKET, true));
     hipLaunchKernelGGL(k_inc_bucket<false>, dim3(kBucketGroups), dim3(256), 0, s, w.tasks, w.inc, w.counters, p.inc_cap,
                        w.tile_cnt, w.tile_cnt, w.tile_fill, w.recs, st);
     PDP_TRY(hipGetLastError());
@@ -386,17 +394,23 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     hipLaunchKernelGGL(k_inc_bucket<true>, dim3(kBucketGroups), dim3(256), 0, s, w.tasks, w.inc, w.counters, p.inc_cap,
                        w.tile_cnt, w.tile_cnt, w.tile_fill, w.recs, st);
     PDP_TRY(hipGetLastError());
+    PDP_TRY(mark(PDP_KERNEL_BUCKET, false));
+    PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, true));
     if (p.total_tiles) {
         hipLaunchKernelGGL(k_tile<false>, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
                            w.tile_cnt, w.recs, bh->ptr, w.bh_best, bh->col, bh->num, bh->den, bh->capacity, p.bh_rows, st);
         PDP_TRY(hipGetLastError());
     }
+    PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, false));
     PDP_TRY(launch_scan(bh->ptr, bh->ptr, p.bh_rows, w.partials, s));
+    PDP_TRY(mark(PDP_KERNEL_TILE_WRITE, true));
     if (p.total_tiles) {
         hipLaunchKernelGGL(k_tile<true>, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
                            w.tile_cnt, w.recs, bh->ptr, w.bh_best, bh->col, bh->num, bh->den, bh->capacity, p.bh_rows, st);
         PDP_TRY(hipGetLastError());
     }
+    PDP_TRY(mark(PDP_KERNEL_TILE_WRITE, false));
+    PDP_TRY(mark(PDP_KERNEL_BBH, true));
     if (p.bbh_rows && bbh) {
         const uint32_t g = (p.bbh_rows + 255) / 256;
         hipLaunchKernelGGL(k_bbh<false>, dim3(g), dim3(256), 0, s, w.tasks, p.n_tasks, p.bbh_rows, bh->ptr, bh->col,
@@ -407,6 +421,8 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
                            bh->num, bh->den, bbh->ptr, bbh->a, bbh->b, bbh->num, bbh->den, bbh->capacity, st);
         PDP_TRY(hipGetLastError());
     }
+    PDP_TRY(mark(PDP_KERNEL_BBH, false));
+    PDP_TRY(mark(PDP_KERNEL_ALL, false));
     return hipSuccess;
 }
 
