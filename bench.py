@@ -38,6 +38,7 @@ def parse():
     p.add_argument("--cpu-rows", type=int, default=128, help="rows per direction per pair in the CPU-oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--breakdown", action="store_true", help="also time every kernel group (extra launches)")
+    p.add_argument("--calibrate-copy", action="store_true", help="only run a copy of known size (counter calibration)")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                    help="measured HBM traffic per kernel (from rocprofv3 counters), used when its source hash matches")
     return p.parse_args()
@@ -95,8 +96,26 @@ def cpu_baseline(ds, k, rows_per_dir):
             "seconds": dt}
 
 
+def calibrate_copy(mib: int = 1024) -> None:
+    """A plain elementwise copy of known size (reads and writes mib MiB once each), for scaling
+    rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "elementwise int32 copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                      "launches": 3}), flush=True)
+
+
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the path shards genome pairs "
                                    "across GPUs by design but no multi-GPU run is part of this build",
@@ -119,10 +138,9 @@ def main():
 
     # residues and offsets resident in HBM before anything is timed
     dev = [pdp.DeviceGenome.of(g) for g in ds.genomes]
-    dicts = [pdp.Dictionary(g.n_genes, g.n_residues, k) for g in dev]
-    dws = pdp.Workspace(max(d.ws_bytes for d in dicts))
-    for d, g in zip(dicts, dev):
-        d.build(g, dws)
+    batch = pdp.DictionaryBatch(dev, k)  # all ten dictionaries in one pdp_dict_build_many
+    dicts = batch.dicts
+    batch.build()
     runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts))
     runner.run()  # sizes the scratch and outputs
     for d in dicts:
@@ -130,8 +148,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        for d, g in zip(dicts, dev):
-            d.build(g, dws)
+        batch.build()
         runner.launch()
 
     for _ in range(args.warmup):
@@ -148,8 +165,7 @@ def main():
     t0 = time.perf_counter()
     for s in range(args.steps):
         dict_ev[s][0].record(stream)
-        for d, g in zip(dicts, dev):
-            d.build(g, dws)
+        batch.build()
         dict_ev[s][1].record(stream)
         runner.launch()
     torch.cuda.synchronize()

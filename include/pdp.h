@@ -145,6 +145,18 @@ int32_t pdp_dict_bind(void *arena, uint64_t arena_bytes, uint32_t n_genes, uint6
  * Errors: PDP_E_INVAL (sizes differ from the bind), PDP_E_WORKSPACE, PDP_E_HIP. */
 int32_t pdp_dict_build(const pdp_genome *g, pdp_dict *d, void *ws, uint64_t ws_bytes, void *stream);
 
+/* Builds n dictionaries in one set of launches (the kernels number the genes
+ * and buckets of all genomes consecutively), so the launch count does not grow
+ * with n.  genomes[i] goes into *dicts[i]; each dictionary keeps its own k and
+ * status.  Enqueues only kernels (the per-genome descriptors travel as kernel
+ * arguments), so it can be captured in a HIP graph.  ws: device scratch of
+ * pdp_dict_build_many_ws_size bytes.  Errors as pdp_dict_build, plus
+ * PDP_E_LIMIT when the genes or buckets of all genomes pass 2^32 - 1. */
+int32_t pdp_dict_build_many_ws_size(const pdp_genome *genomes, pdp_dict *const *dicts, uint32_t n,
+                                    uint64_t *ws_bytes);
+int32_t pdp_dict_build_many(const pdp_genome *genomes, pdp_dict *const *dicts, uint32_t n, void *ws,
+                            uint64_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------- best hits, BBH */
 
 /* Best hits in CSR form (the jagged array A_ij of Alg. 2): row r's hits are

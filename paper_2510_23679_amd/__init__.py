@@ -9,6 +9,6 @@ from .binding import (  # noqa: F401
     LIB_PATH, PdpError, lib,
 )
 from .api import (  # noqa: F401
-    BBHOut, BHOut, DeviceGenome, Dictionary, PairResults, PairRunner, Plan, Workspace, abi_version,
+    BBHOut, BHOut, DeviceGenome, Dictionary, DictionaryBatch, PairResults, PairRunner, Plan, Workspace, abi_version,
     all_pairs_tasks, bbh, bh, dict_size, k_rule, new_status, params, read_status,
 )

@@ -162,6 +162,31 @@ class Dictionary:
         return out
 
 
+class DictionaryBatch:
+    """Many dictionaries built by one pdp_dict_build_many call per build()."""
+
+    def __init__(self, genomes: Sequence[DeviceGenome], k, ws: Optional[Workspace] = None):
+        ks = list(k) if isinstance(k, (list, tuple)) else [int(k)] * len(genomes)
+        self.genomes = list(genomes)
+        self.dicts = [Dictionary(g.n_genes, g.n_residues, kk) for g, kk in zip(self.genomes, ks)]
+        n = len(self.genomes)
+        self._g = (B.pdp_genome * n)(*[g.struct() for g in self.genomes])
+        self._d = (C.POINTER(B.pdp_dict) * n)(*[C.pointer(d.d) for d in self.dicts])
+        need = B.u64(0)
+        check(lib().pdp_dict_build_many_ws_size(self._g, self._d, n, C.byref(need)), "pdp_dict_build_many_ws_size")
+        self.ws = (ws or Workspace()).ensure(need.value)
+
+    def build(self, stream=None) -> None:
+        check(lib().pdp_dict_build_many(self._g, self._d, len(self.dicts), self.ws.ptr, self.ws.nbytes,
+                                        _stream_handle(stream)), "pdp_dict_build_many")
+        for d, g in zip(self.dicts, self.genomes):
+            d.genome = g
+
+    def check_status(self) -> None:
+        for d in self.dicts:
+            d.check_status()
+
+
 class BHOut:
     """Combined best-hit CSR output (device)."""
 

@@ -83,6 +83,8 @@ SIGNATURES = {
     "pdp_dict_size": (i32, [u32, u64, u32, C.POINTER(u64), C.POINTER(u64)]),
     "pdp_dict_bind": (i32, [vp, u64, u32, u64, u32, C.POINTER(pdp_dict)]),
     "pdp_dict_build": (i32, [C.POINTER(pdp_genome), C.POINTER(pdp_dict), vp, u64, vp]),
+    "pdp_dict_build_many_ws_size": (i32, [C.POINTER(pdp_genome), C.POINTER(C.POINTER(pdp_dict)), u32, C.POINTER(u64)]),
+    "pdp_dict_build_many": (i32, [C.POINTER(pdp_genome), C.POINTER(C.POINTER(pdp_dict)), u32, vp, u64, vp]),
     "pdp_plan_create": (i32, [C.POINTER(pdp_task), u32, C.POINTER(pdp_params), C.POINTER(vp)]),
     "pdp_plan_info_get": (i32, [vp, C.POINTER(pdp_plan_info)]),
     "pdp_plan_rows": (i32, [vp, u32, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]),

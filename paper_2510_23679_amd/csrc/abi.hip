@@ -48,8 +48,8 @@ struct pdp_plan {
 
     void timer_release() const {
         for (auto &e : timer_events) {
-            hipEventDestroy(e.first);
-            hipEventDestroy(e.second);
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
         }
         timer_events.clear();
         timer_kernel = -1;
@@ -128,7 +128,10 @@ int32_t pdp_dict_size(uint32_t n_genes, uint64_t n_residues, uint32_t k, uint64_
     int32_t rc = dict_check(n_genes, n_residues, k);
     if (rc) return rc;
     if (arena_bytes) *arena_bytes = dict_arena_bytes(n_genes, n_residues, k);
-    if (ws_bytes) *ws_bytes = dict_ws_bytes(n_genes, n_residues, k);
+    if (ws_bytes) {
+        BuildShape s{1, n_genes, n_buckets_for(k), n_residues + 1};
+        *ws_bytes = build_ws_bytes(s);
+    }
     return ok();
 }
 
@@ -165,21 +168,49 @@ int32_t pdp_dict_bind(void *arena, uint64_t arena_bytes, uint32_t n_genes, uint6
     return ok();
 }
 
-int32_t pdp_dict_build(const pdp_genome *g, pdp_dict *d, void *ws, uint64_t ws_bytes, void *stream) {
-    if (!g || !d || !ws) return fail(PDP_E_INVAL, "pdp_dict_build: null pointer");
-    if (g->n_genes && (!g->residues || !g->gene_off)) return fail(PDP_E_INVAL, "pdp_dict_build: null genome arrays");
-    if (!g->gene_off) return fail(PDP_E_INVAL, "pdp_dict_build: gene_off is null");
-    int32_t rc = dict_check(g->n_genes, g->n_residues, d->k);
+static int32_t build_check(const pdp_genome *genomes, pdp_dict *const *dicts, uint32_t n) {
+    if (n == 0 || !genomes || !dicts) return fail(PDP_E_INVAL, "dictionary build: no genomes");
+    uint64_t genes = 0, buckets = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const pdp_genome *g = &genomes[i];
+        const pdp_dict *d = dicts[i];
+        if (!d) return fail(PDP_E_INVAL, "dictionary %u is null", i);
+        if (!g->gene_off || (g->n_residues && !g->residues)) return fail(PDP_E_INVAL, "genome %u: null arrays", i);
+        int32_t rc = dict_check(g->n_genes, g->n_residues, d->k);
+        if (rc) return rc;
+        if (g->n_genes != d->n_genes || g->n_residues + 1 > d->capacity)
+            return fail(PDP_E_INVAL, "genome %u (%u genes, %llu residues) does not match its dictionary (%u genes, capacity %llu)",
+                        i, g->n_genes, (unsigned long long)g->n_residues, d->n_genes, (unsigned long long)d->capacity);
+        genes += g->n_genes;
+        buckets += d->n_buckets;
+    }
+    if (genes >= UINT32_MAX || buckets >= UINT32_MAX) return fail(PDP_E_LIMIT, "build too large for 32-bit indices");
+    return PDP_OK;
+}
+
+int32_t pdp_dict_build_many_ws_size(const pdp_genome *genomes, pdp_dict *const *dicts, uint32_t n, uint64_t *ws_bytes) {
+    if (!ws_bytes) return fail(PDP_E_INVAL, "pdp_dict_build_many_ws_size: null output");
+    int32_t rc = build_check(genomes, dicts, n);
     if (rc) return rc;
-    if (g->n_genes != d->n_genes || g->n_residues + 1 > d->capacity)
-        return fail(PDP_E_INVAL, "genome (%u genes, %llu residues) does not match the bound dictionary (%u genes, capacity %llu)",
-                    g->n_genes, (unsigned long long)g->n_residues, d->n_genes, (unsigned long long)d->capacity);
-    const uint64_t need = dict_ws_bytes(g->n_genes, g->n_residues, d->k);
-    if (ws_bytes < need) return fail(PDP_E_WORKSPACE, "workspace %llu < %llu bytes", (unsigned long long)ws_bytes, (unsigned long long)need);
-    DictBuildWs w = dict_ws_carve(ws, g->n_genes, g->n_residues, d->k);
-    hipError_t e = launch_dict_build(g, d, w, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return hip_fail(e, "pdp_dict_build");
+    *ws_bytes = build_ws_bytes(build_shape(genomes, dicts, n));
     return ok();
+}
+
+int32_t pdp_dict_build_many(const pdp_genome *genomes, pdp_dict *const *dicts, uint32_t n, void *ws, uint64_t ws_bytes,
+                            void *stream) {
+    if (!ws) return fail(PDP_E_INVAL, "dictionary build: null workspace");
+    int32_t rc = build_check(genomes, dicts, n);
+    if (rc) return rc;
+    const uint64_t need = build_ws_bytes(build_shape(genomes, dicts, n));
+    if (ws_bytes < need) return fail(PDP_E_WORKSPACE, "workspace %llu < %llu bytes", (unsigned long long)ws_bytes, (unsigned long long)need);
+    hipError_t e = launch_dict_build_many(genomes, dicts, n, ws, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dictionary build");
+    return ok();
+}
+
+int32_t pdp_dict_build(const pdp_genome *g, pdp_dict *d, void *ws, uint64_t ws_bytes, void *stream) {
+    if (!g || !d) return fail(PDP_E_INVAL, "pdp_dict_build: null pointer");
+    return pdp_dict_build_many(g, &d, 1, ws, ws_bytes, stream);
 }
 
 // ------------------------------------------------------------------ plans
@@ -251,8 +282,10 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
             if (!(flags & (1u << dir))) continue;
             const pdp_dict *R = dir == 0 ? tk.a : tk.b;
             const pdp_dict *C = dir == 0 ? tk.b : tk.a;
-            const uint64_t W = std::max<uint64_t>((uint64_t(C->n_genes) + 1) / 2, 1);
-            uint64_t T = lds_budget / (4 * W);
+            // per row: the packed 16-bit sums plus one bitmap bit per 32-bit word
+            const uint64_t W = (uint64_t(C->n_genes) + 1) / 2;
+            const uint64_t row_words = std::max<uint64_t>(W + (W + 31) / 32, 1);
+            uint64_t T = lds_budget / (4 * row_words);
             if (T == 0) {
                 delete P;
                 return fail(PDP_E_LIMIT, "task %u: %u target genes do not fit an LDS tile of %u bytes", t, C->n_genes, lds_budget);
@@ -262,7 +295,7 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
             d.tile_rows[dir] = static_cast<uint32_t>(T);
             d.row_base[dir] = static_cast<uint32_t>(bh_rows);
             bh_rows += R->n_genes;
-            tile_lds = std::max<uint32_t>(tile_lds, static_cast<uint32_t>(T * W * 4));
+            tile_lds = std::max<uint32_t>(tile_lds, static_cast<uint32_t>(align_up(T * row_words * 4, 16)));
             for (uint32_t r0 = 0; r0 < R->n_genes; r0 += static_cast<uint32_t>(T)) {
                 DevTile tl;
                 tl.task = t;
@@ -377,7 +410,7 @@ int32_t pdp_plan_timer_start(pdp_plan *plan, int32_t kernel, uint32_t max_launch
         if (e != hipSuccess) return hip_fail(e, "pdp_plan_timer_start");
         e = hipEventCreate(&b);
         if (e != hipSuccess) {
-            hipEventDestroy(a);
+            (void)hipEventDestroy(a);
             return hip_fail(e, "pdp_plan_timer_start");
         }
         plan->timer_events.emplace_back(a, b);

@@ -17,7 +17,7 @@ constexpr uint32_t kJoinLdsCap = 2048;       // target-side index entries staged
 constexpr uint32_t kTileMaxRows = 64;        // rows per accumulation tile
 constexpr uint32_t kTileThreads = 256;
 constexpr uint32_t kDefaultLdsBudget = 48 * 1024;
-constexpr uint32_t kKeyShift = 40;           // J key = floor(m * 2^40 / d), exact order for d < 2^20
+constexpr uint32_t kSlab = 4;                // best hits per row kept by the first tile pass
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 inline uint32_t lead_residues(uint32_t k) { return k < 4 ? k : 4; }
@@ -69,20 +69,30 @@ hipError_t launch_status_init(pdp_status *st, hipStream_t s);
 // (then in needs n+1 slots).  partials: scan_partials(n) words of scratch.
 hipError_t launch_scan(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *partials, hipStream_t s);
 
-struct DictBuildWs {
-    uint64_t *slot_code;   // n_residues: per-gene sorted distinct codes at slot gene_off[g]
-    uint32_t *slot_cnt;    // n_residues
-    uint64_t *long_tmp;    // n_residues: windows of genes too long for LDS
-    uint32_t *dcnt;        // n_genes + 1
-    uint32_t *bcount;      // n_buckets + 1
-    uint32_t *long_list;   // n_genes
-    uint32_t *big_list;    // n_buckets
-    uint32_t *counters;    // [0] long genes, [1] big buckets
-    uint32_t *partials;    // scan scratch
+// One genome of a dictionary build: input, outputs and its slices of the
+// workspace.  Genes and buckets of all genomes of a build are numbered
+// consecutively from gene_base / bucket_base.
+struct DevBuild {
+    const uint8_t *res;
+    const uint64_t *off;
+    uint64_t n_residues;
+    uint32_t n_genes, k, nb, lead, gene_base, bucket_base;
+    uint32_t *nwin, *mv_ptr;
+    uint64_t *mv_code;
+    uint32_t *mv_cnt, *ix_dir;
+    uint64_t *ix_code;
+    uint32_t *ix_gene, *ix_cnt;
+    pdp_status *status;
+    uint64_t *slot_code;  // per gene g: sorted distinct codes at offset gene_off[g]
+    uint32_t *slot_cnt;
+    uint64_t *long_tmp;   // windows of genes too long for LDS
 };
-uint64_t dict_ws_bytes(uint32_t n_genes, uint64_t n_residues, uint32_t k);
-DictBuildWs dict_ws_carve(void *ws, uint32_t n_genes, uint64_t n_residues, uint32_t k);
-hipError_t launch_dict_build(const pdp_genome *g, pdp_dict *d, const DictBuildWs &w, hipStream_t s);
+struct BuildShape {
+    uint64_t n_genomes, total_genes, total_buckets, total_residues;
+};
+BuildShape build_shape(const pdp_genome *g, const pdp_dict *const *d, uint32_t n);
+uint64_t build_ws_bytes(const BuildShape &s);
+hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint32_t n, void *ws, hipStream_t s);
 
 struct PairWs {
     DevTask *tasks;
@@ -92,7 +102,9 @@ struct PairWs {
     uint32_t *tile_cnt;           // tiles + 1 (scanned in place into offsets)
     uint32_t *tile_fill;          // tiles
     uint2 *recs;                  // incidences bucketed by tile: ((row<<24)|col, v); 2x capacity
-    uint2 *bh_best;               // best (m, d) per best-hit row
+    uint4 *slab;                  // kSlab (column, m, d, -) per best-hit row
+    uint32_t *overflow_tiles;     // tiles holding a row with more than kSlab ties
+    uint32_t *overflow_count;     // = counters word 2
     uint32_t *partials;
 };
 

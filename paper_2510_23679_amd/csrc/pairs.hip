@@ -144,29 +144,45 @@ __device__ __forceinline__ bool j_equal(uint32_t m1, uint32_t d1, uint32_t m2, u
     return static_cast<uint64_t>(m1) * d2 == static_cast<uint64_t>(m2) * d1;
 }
 
+// One accumulation tile: T rows of one direction of one task against every
+// column of the other genome.  LDS holds the sums of minima (two 16-bit sums
+// per 32-bit word) and a bitmap with one bit per word that has been touched,
+// so a row's maximum and ties cost time in proportion to its touched columns.
+// One wave per row: pass 1 finds the exact maximum of m/d (64-bit
+// cross-multiplication); pass 2 emits every column at the maximum in
+// ascending order (lanes own ascending, disjoint column ranges; a wave prefix
+// sum gives positions).  In the first launch (WRITE = false) the ties go to a
+// per-row slab of kSlab entries and the row's count to cnt[row]; a row with
+// more ties marks its tile, and the second launch (WRITE = true) recomputes
+// only the marked tiles and writes their rows straight into the CSR output.
 template <bool WRITE>
-__global__ __launch_bounds__(kTileThreads) void k_tile(const DevTask *__restrict__ tasks, const DevTile *__restrict__ tiles,
-                                                       const uint32_t *__restrict__ tile_off, const uint2 *__restrict__ recs,
-                                                       uint32_t *__restrict__ bh_ptr, uint2 *__restrict__ bh_best,
-                                                       uint32_t *__restrict__ bh_col, uint32_t *__restrict__ bh_num,
-                                                       uint32_t *__restrict__ bh_den, uint64_t bh_cap, uint32_t bh_rows,
-                                                       pdp_status *st) {
-    extern __shared__ uint32_t acc[];
-    const DevTile tl = tiles[blockIdx.x];
+__device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__restrict__ tasks,
+                                             const DevTile *__restrict__ tiles, const uint32_t *__restrict__ tile_off,
+                                             const uint2 *__restrict__ recs, uint32_t *__restrict__ bh_ptr,
+                                             uint4 *__restrict__ slab, uint32_t *__restrict__ bh_col,
+                                             uint32_t *__restrict__ bh_num, uint32_t *__restrict__ bh_den,
+                                             uint64_t bh_cap, uint32_t *overflow_tiles, uint32_t *overflow_count,
+                                             uint32_t *lds, uint32_t *s_flag) {
+    const DevTile tl = tiles[tile_id];
     const DevTask &T = tasks[tl.task];
     const DevDict &R = tl.dir == 0 ? T.a : T.b;
     const DevDict &C = tl.dir == 0 ? T.b : T.a;
     const uint32_t ncols = C.n_genes;
-    const uint32_t W = (ncols + 1) >> 1;
-    if (WRITE && blockIdx.x == 0 && threadIdx.x == 0 && bh_ptr[bh_rows] > bh_cap)
-        raise_status(st, PDP_E_CAPACITY, bh_ptr[bh_rows], 1);
-    for (uint32_t i = threadIdx.x; i < tl.nrows * W; i += kTileThreads) acc[i] = 0;
+    const uint32_t W = (ncols + 1) >> 1;   // accumulator words per row
+    const uint32_t WB = (W + 31) >> 5;     // bitmap words per row
+    uint32_t *acc = lds;
+    uint32_t *bits = lds + tl.nrows * W;
+    const uint32_t words = tl.nrows * (W + WB);
+    uint4 *lds4 = reinterpret_cast<uint4 *>(lds);
+    for (uint32_t i = threadIdx.x; i < (words + 3) / 4; i += kTileThreads) lds4[i] = make_uint4(0, 0, 0, 0);
+    if (threadIdx.x == 0) *s_flag = 0;
     __syncthreads();
-    const uint32_t r0 = tile_off[blockIdx.x], r1 = tile_off[blockIdx.x + 1];
+    const uint32_t r0 = tile_off[tile_id], r1 = tile_off[tile_id + 1];
     for (uint32_t i = r0 + threadIdx.x; i < r1; i += kTileThreads) {
         const uint2 r = recs[i];
-        const uint32_t rl = r.x >> 24, c = r.x & 0xFFFFFFu;
-        atomicAdd(&acc[rl * W + (c >> 1)], r.y << ((c & 1u) << 4));
+        const uint32_t rl = r.x >> 24, c = r.x & 0xFFFFFFu, w = c >> 1;
+        const uint32_t old = atomicAdd(&acc[rl * W + w], r.y << ((c & 1u) << 4));
+        if (old == 0) atomicOr(&bits[rl * WB + (w >> 5)], 1u << (w & 31u));
     }
     __syncthreads();
     const uint32_t wave = threadIdx.x / kWave;
@@ -176,9 +192,13 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const DevTask *__restrict
         const uint32_t grow = T.row_base[tl.dir] + row;
         const uint32_t nr = R.nwin[row];
         const uint32_t *arow = acc + rl * W;
-        if (!WRITE) {
-            uint32_t bm = 0, bd = 1;
-            for (uint32_t w = lane; w < W; w += kWave) {
+        const uint32_t *brow = bits + rl * WB;
+        uint32_t bm = 0, bd = 1;
+        for (uint32_t bw = lane; bw < WB; bw += kWave) {
+            uint32_t m = brow[bw];
+            while (m) {
+                const uint32_t w = (bw << 5) + (__ffs(m) - 1);
+                m &= m - 1;
                 const uint32_t v = arow[w];
                 const uint32_t m0 = v & 0xFFFFu, m1 = v >> 16;
                 if (m0) {
@@ -190,56 +210,110 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const DevTask *__restrict
                     if (j_greater(m1, d, bm, bd)) { bm = m1; bd = d; }
                 }
             }
+        }
 #pragma unroll
-            for (uint32_t o = kWave / 2; o > 0; o >>= 1) {
-                const uint32_t om = __shfl_xor(bm, o, kWave), od = __shfl_xor(bd, o, kWave);
-                if (j_greater(om, od, bm, bd)) { bm = om; bd = od; }
-            }
-            uint32_t cnt = 0;
-            if (bm) {
-                for (uint32_t w = lane; w < W; w += kWave) {
+        for (uint32_t o = kWave / 2; o > 0; o >>= 1) {
+            const uint32_t om = __shfl_xor(bm, o, kWave), od = __shfl_xor(bd, o, kWave);
+            if (j_greater(om, od, bm, bd)) { bm = om; bd = od; }
+        }
+        uint32_t pos = WRITE ? bh_ptr[grow] : 0u;
+        if (bm) {
+            for (uint32_t b0 = 0; b0 < WB; b0 += kWave) {
+                const uint32_t bw = b0 + lane;
+                const uint32_t mask = bw < WB ? brow[bw] : 0u;
+                uint32_t cnt = 0;
+                for (uint32_t m = mask; m;) {
+                    const uint32_t w = (bw << 5) + (__ffs(m) - 1);
+                    m &= m - 1;
                     const uint32_t v = arow[w];
                     const uint32_t m0 = v & 0xFFFFu, m1 = v >> 16;
                     if (m0 && j_equal(m0, nr + C.nwin[2 * w] - m0, bm, bd)) ++cnt;
                     if (m1 && j_equal(m1, nr + C.nwin[2 * w + 1] - m1, bm, bd)) ++cnt;
                 }
-            }
-            cnt = wave_sum(cnt);
-            if (lane == 0) {
-                bh_ptr[grow] = cnt;
-                bh_best[grow] = make_uint2(bm, bd);
-            }
-        } else {
-            const uint2 best = bh_best[grow];
-            const uint32_t bm = best.x, bd = best.y;
-            if (bm == 0) continue;
-            uint32_t pos = bh_ptr[grow];
-            for (uint32_t wb = 0; wb < W; wb += kWave) {
-                const uint32_t w = wb + lane;
-                const uint32_t v = w < W ? arow[w] : 0u;
-                const uint32_t m0 = v & 0xFFFFu, m1 = v >> 16;
-                const uint32_t d0 = m0 ? nr + C.nwin[2 * w] - m0 : 1u;
-                const uint32_t d1 = m1 ? nr + C.nwin[2 * w + 1] - m1 : 1u;
-                const bool x0 = m0 && j_equal(m0, d0, bm, bd);
-                const bool x1 = m1 && j_equal(m1, d1, bm, bd);
-                const uint64_t b0 = __ballot(x0), b1 = __ballot(x1);
-                const uint32_t p = pos + mask_below(b0) + mask_below(b1);
-                if (x0 && p < bh_cap) {
-                    bh_col[p] = 2 * w;
-                    bh_num[p] = m0;
-                    bh_den[p] = d0;
-                }
-                if (x1) {
-                    const uint32_t p1 = p + (x0 ? 1u : 0u);
-                    if (p1 < bh_cap) {
-                        bh_col[p1] = 2 * w + 1;
-                        bh_num[p1] = m1;
-                        bh_den[p1] = d1;
+                const uint32_t incl = wave_inclusive_sum(cnt);
+                const uint32_t total = __shfl(incl, kWave - 1, kWave);
+                uint32_t p = pos + incl - cnt;
+                for (uint32_t m = cnt ? mask : 0u; m;) {
+                    const uint32_t w = (bw << 5) + (__ffs(m) - 1);
+                    m &= m - 1;
+                    const uint32_t v = arow[w];
+#pragma unroll
+                    for (uint32_t h = 0; h < 2; ++h) {
+                        const uint32_t mm = h ? v >> 16 : v & 0xFFFFu;
+                        if (!mm) continue;
+                        const uint32_t c = 2 * w + h;
+                        const uint32_t d = nr + C.nwin[c] - mm;
+                        if (!j_equal(mm, d, bm, bd)) continue;
+                        if (WRITE) {
+                            if (p < bh_cap) {
+                                bh_col[p] = c;
+                                bh_num[p] = mm;
+                                bh_den[p] = d;
+                            }
+                        } else if (p < kSlab) {
+                            slab[static_cast<uint64_t>(grow) * kSlab + p] = make_uint4(c, mm, d, 0);
+                        }
+                        ++p;
                     }
                 }
-                pos += __popcll(b0) + __popcll(b1);
+                pos += total;
             }
         }
+        if (!WRITE && lane == 0) {
+            bh_ptr[grow] = pos;
+            if (pos > kSlab) *s_flag = 1;
+        }
+    }
+    __syncthreads();
+    if (!WRITE && threadIdx.x == 0 && *s_flag) overflow_tiles[atomicAdd(overflow_count, 1u)] = tile_id;
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_tile_count(const DevTask *__restrict__ tasks,
+                                                             const DevTile *__restrict__ tiles,
+                                                             const uint32_t *__restrict__ tile_off,
+                                                             const uint2 *__restrict__ recs, uint32_t *__restrict__ bh_ptr,
+                                                             uint4 *__restrict__ slab, uint32_t *overflow_tiles,
+                                                             uint32_t *overflow_count) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t s_flag;
+    tile_process<false>(blockIdx.x, tasks, tiles, tile_off, recs, bh_ptr, slab, nullptr, nullptr, nullptr, 0,
+                        overflow_tiles, overflow_count, lds, &s_flag);
+}
+
+// Rows with more ties than the slab holds: their tiles again, written to the CSR output.
+__global__ __launch_bounds__(kTileThreads) void k_tile_write(const DevTask *__restrict__ tasks,
+                                                             const DevTile *__restrict__ tiles,
+                                                             const uint32_t *__restrict__ tile_off,
+                                                             const uint2 *__restrict__ recs, uint32_t *__restrict__ bh_ptr,
+                                                             uint32_t *__restrict__ bh_col, uint32_t *__restrict__ bh_num,
+                                                             uint32_t *__restrict__ bh_den, uint64_t bh_cap,
+                                                             const uint32_t *__restrict__ overflow_tiles,
+                                                             const uint32_t *__restrict__ overflow_count) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t s_flag;
+    const uint32_t n = *overflow_count;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
+        tile_process<true>(overflow_tiles[i], tasks, tiles, tile_off, recs, bh_ptr, nullptr, bh_col, bh_num, bh_den,
+                           bh_cap, nullptr, nullptr, lds, &s_flag);
+}
+
+// One thread per best-hit row: the slab entries of a row with at most kSlab ties go to the CSR output.
+__global__ __launch_bounds__(256) void k_slab_copy(uint32_t bh_rows, const uint32_t *__restrict__ bh_ptr,
+                                                   const uint4 *__restrict__ slab, uint32_t *__restrict__ bh_col,
+                                                   uint32_t *__restrict__ bh_num, uint32_t *__restrict__ bh_den,
+                                                   uint64_t bh_cap, pdp_status *st) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0 && bh_ptr[bh_rows] > bh_cap) raise_status(st, PDP_E_CAPACITY, bh_ptr[bh_rows], 1);
+    if (r >= bh_rows) return;
+    const uint32_t p = bh_ptr[r], n = bh_ptr[r + 1] - p;
+    if (n > kSlab) return;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (p + i >= bh_cap) break;
+        const uint4 e = slab[static_cast<uint64_t>(r) * kSlab + i];
+        bh_col[p + i] = e.x;
+        bh_num[p + i] = e.y;
+        bh_den[p + i] = e.z;
     }
 }
 
@@ -334,7 +408,8 @@ uint64_t pair_ws_bytes(const PlanShape &p) {
     s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
     s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
     s += align_up(8 * 2 * std::max<uint64_t>(p.inc_cap, 1), A);
-    s += align_up(8 * (uint64_t(p.bh_rows) + 1), A);
+    s += align_up(16 * kSlab * (uint64_t(p.bh_rows) + 1), A);
+    s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
     const uint64_t np = std::max({scan_partials(p.total_tiles), scan_partials(p.bh_rows), scan_partials(p.bbh_rows)});
     s += align_up(4 * np, A);
     return s;
@@ -353,10 +428,12 @@ PairWs pair_ws_carve(void *ws, const PlanShape &p) {
     w.tiles = reinterpret_cast<DevTile *>(take(sizeof(DevTile) * std::max<uint64_t>(p.total_tiles, 1)));
     w.inc = reinterpret_cast<uint4 *>(take(16 * std::max<uint64_t>(p.inc_cap, 1)));
     w.counters = reinterpret_cast<unsigned long long *>(take(16));
+    w.overflow_count = reinterpret_cast<uint32_t *>(w.counters) + 2;
     w.tile_cnt = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
     w.tile_fill = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
     w.recs = reinterpret_cast<uint2 *>(take(8 * 2 * std::max<uint64_t>(p.inc_cap, 1)));
-    w.bh_best = reinterpret_cast<uint2 *>(take(8 * (uint64_t(p.bh_rows) + 1)));
+    w.slab = reinterpret_cast<uint4 *>(take(16 * kSlab * (uint64_t(p.bh_rows) + 1)));
+    w.overflow_tiles = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
     const uint64_t np = std::max({scan_partials(p.total_tiles), scan_partials(p.bh_rows), scan_partials(p.bbh_rows)});
     w.partials = reinterpret_cast<uint32_t *>(take(4 * np));
     return w;
@@ -376,7 +453,7 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     };
     PDP_TRY(mark(PDP_KERNEL_ALL, true));
     PDP_TRY(launch_status_init(st, s));
-    PDP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(w.counters), 4, 0u, s));
+    PDP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(w.counters), 4, 0u, s));  // incidences, overflow tiles
     PDP_TRY(launch_fill_u32(w.tile_cnt, uint64_t(p.total_tiles) + 1, 0u, s));
     PDP_TRY(launch_fill_u32(w.tile_fill, uint64_t(p.total_tiles) + 1, 0u, s));
     PDP_TRY(mark(PDP_KERNEL_JOIN, true));
@@ -397,16 +474,23 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     PDP_TRY(mark(PDP_KERNEL_BUCKET, false));
     PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, true));
     if (p.total_tiles) {
-        hipLaunchKernelGGL(k_tile<false>, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
-                           w.tile_cnt, w.recs, bh->ptr, w.bh_best, bh->col, bh->num, bh->den, bh->capacity, p.bh_rows, st);
+        hipLaunchKernelGGL(k_tile_count, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
+                           w.tile_cnt, w.recs, bh->ptr, w.slab, w.overflow_tiles, w.overflow_count);
         PDP_TRY(hipGetLastError());
     }
     PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, false));
     PDP_TRY(launch_scan(bh->ptr, bh->ptr, p.bh_rows, w.partials, s));
     PDP_TRY(mark(PDP_KERNEL_TILE_WRITE, true));
+    if (p.bh_rows) {
+        hipLaunchKernelGGL(k_slab_copy, dim3((p.bh_rows + 255) / 256), dim3(256), 0, s, p.bh_rows, bh->ptr, w.slab,
+                           bh->col, bh->num, bh->den, bh->capacity, st);
+        PDP_TRY(hipGetLastError());
+    }
     if (p.total_tiles) {
-        hipLaunchKernelGGL(k_tile<true>, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
-                           w.tile_cnt, w.recs, bh->ptr, w.bh_best, bh->col, bh->num, bh->den, bh->capacity, p.bh_rows, st);
+        const uint32_t g = p.total_tiles < 256 ? p.total_tiles : 256;
+        hipLaunchKernelGGL(k_tile_write, dim3(g), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles, w.tile_cnt,
+                           w.recs, bh->ptr, bh->col, bh->num, bh->den, bh->capacity, w.overflow_tiles,
+                           w.overflow_count);
         PDP_TRY(hipGetLastError());
     }
     PDP_TRY(mark(PDP_KERNEL_TILE_WRITE, false));

@@ -256,3 +256,20 @@ def test_full_size_family_model_sampled():
             check_bh(ab, oracle.bh(og[i], og[j], rows=rows), rows=rows)
             cols = np.sort(rng.choice(ds.genomes[j].n_genes, 24, replace=False))
             check_bh(ba, oracle.bh(og[j], og[i], rows=cols), rows=cols)
+
+
+def test_build_many_mixed_k_and_empty_genomes():
+    say("pdp_dict_build_many: 5 genomes, mixed k, an empty genome")
+    ds = make_config(2, genomes=3, genes=200)
+    gens = [ds.genomes[0], genome_from_strings([]), ds.genomes[1], genome_from_strings(["", "MK", "A" * 3000]),
+            ds.genomes[2]]
+    ks = [5, 4, 6, 3, 1]
+    batch = pdp.DictionaryBatch([pdp.DeviceGenome.of(g) for g in gens], ks)
+    batch.build()
+    batch.check_status()
+    for d, g, k in zip(batch.dicts, gens, ks):
+        check_dictionary(d.host(), oracle.OracleGenome(g, k))
+    batch.build()  # the same workspace again
+    batch.check_status()
+    for d, g, k in zip(batch.dicts, gens, ks):
+        check_dictionary(d.host(), oracle.OracleGenome(g, k))
