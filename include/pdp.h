@@ -193,9 +193,13 @@ typedef struct pdp_params {
     uint64_t inc_capacity;   /* shared-k-mer incidences the scratch can hold (0: from the dictionary sizes) */
     uint32_t tile_rows;      /* query genes per LDS accumulation tile */
     uint32_t join_entries;   /* target index entries per join work-group */
-    uint32_t lds_budget;     /* bytes of LDS for one accumulation tile */
-    uint32_t reserved;
+    uint32_t lds_budget;     /* bytes of LDS for one accumulation tile (at most 159 KiB) */
+    uint32_t flags;          /* PDP_PARAM_* */
 } pdp_params;
+/* The join and the first tile pass run as persistent kernels: a grid sized to
+ * the device pulls work items from a counter (largest tasks first) instead of
+ * one work-group per item. */
+#define PDP_PARAM_PERSISTENT 1u
 
 /* One unit of work: genomes a and b (same k).  flags select the outputs. */
 #define PDP_TASK_AB 1u   /* best hits of a's genes in b */

@@ -236,8 +236,10 @@ class BBHOut:
                 self.num[:n].cpu().numpy().view(np.uint32), self.den[:n].cpu().numpy().view(np.uint32))
 
 
-def params(inc_capacity: int = 0, tile_rows: int = 0, join_entries: int = 0, lds_budget: int = 0) -> B.pdp_params:
-    return B.pdp_params(int(inc_capacity), int(tile_rows), int(join_entries), int(lds_budget), 0)
+def params(inc_capacity: int = 0, tile_rows: int = 0, join_entries: int = 0, lds_budget: int = 0,
+           persistent: bool = False) -> B.pdp_params:
+    return B.pdp_params(int(inc_capacity), int(tile_rows), int(join_entries), int(lds_budget),
+                        B.PDP_PARAM_PERSISTENT if persistent else 0)
 
 
 class Plan:
@@ -353,7 +355,8 @@ class PairRunner:
 
     def _grow(self, where: int, needed: int) -> None:
         if where == 0:
-            self.prm = params(int(needed * 1.25) + 1024, self.prm.tile_rows, self.prm.join_entries, self.prm.lds_budget)
+            self.prm = params(int(needed * 1.25) + 1024, self.prm.tile_rows, self.prm.join_entries, self.prm.lds_budget,
+                              bool(self.prm.flags & B.PDP_PARAM_PERSISTENT))
             self.plan = Plan(self.tasks, self.prm)
             self.ws = Workspace(self.plan.info.ws_bytes)
             self.uploaded = False
@@ -411,7 +414,8 @@ def bh(q: Dictionary, t: Dictionary, prm: Optional[B.pdp_params] = None, capacit
                            _stream_handle(stream)), "pdp_bh")
         code, needed, where = read_status(st)
         if code == B.PDP_E_CAPACITY and where == 0:
-            prm = params(int(needed * 1.25) + 1024, prm.tile_rows, prm.join_entries, prm.lds_budget)
+            prm = params(int(needed * 1.25) + 1024, prm.tile_rows, prm.join_entries, prm.lds_budget,
+                         bool(prm.flags & B.PDP_PARAM_PERSISTENT))
             check(lib().pdp_bh_ws_size(C.byref(q.d), C.byref(t.d), C.byref(prm), C.byref(ws_bytes)), "pdp_bh_ws_size")
             ws = Workspace(ws_bytes.value)
             continue

@@ -29,6 +29,7 @@ PDP_E_UNIMPL = -9
 PDP_TASK_AB = 1
 PDP_TASK_BA = 2
 PDP_TASK_BBH = 4
+PDP_PARAM_PERSISTENT = 1
 PDP_K_MAX = 12
 PDP_MAX_WINDOWS = 65535
 
@@ -62,7 +63,7 @@ class pdp_bbh_out(C.Structure):
 
 class pdp_params(C.Structure):
     _fields_ = [("inc_capacity", u64), ("tile_rows", u32), ("join_entries", u32), ("lds_budget", u32),
-                ("reserved", u32)]
+                ("flags", u32)]
 
 
 class pdp_task(C.Structure):

@@ -39,8 +39,12 @@ struct pdp_plan {
     std::vector<DevTask> tasks;
     std::vector<DevTile> tiles;
     std::vector<uint32_t> ab_row, ba_row, bbh_row;
+    std::vector<uint32_t> order;  // order[t]: position of caller task t in the task table
     PlanShape shape;
     uint64_t ws_bytes;
+    bool persistent = false;
+    mutable bool device_ready = false;  // persistent grids and LDS limit set up on the device
+    mutable uint32_t join_grid = 0, tile_grid = 0;
     // measurement hook: event pairs owned by the plan, one per timed launch
     mutable int32_t timer_kernel = -1;
     mutable uint32_t timer_used = 0;
@@ -238,31 +242,31 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     if (params) prm = *params;
     const uint32_t lds_budget = prm.lds_budget ? prm.lds_budget : kDefaultLdsBudget;
     const uint32_t join_entries = prm.join_entries ? prm.join_entries : kJoinLdsCap / 2;
-    if (lds_budget > 64 * 1024) return fail(PDP_E_INVAL, "lds_budget above 64 KiB");
+    if (lds_budget > kMaxTileLds) return fail(PDP_E_INVAL, "lds_budget above %u bytes", kMaxTileLds);
     if (join_entries > kJoinLdsCap) return fail(PDP_E_INVAL, "join_entries above %u", kJoinLdsCap);
     if (prm.tile_rows > kTileMaxRows) return fail(PDP_E_INVAL, "tile_rows above %u", kTileMaxRows);
+    if (prm.flags & ~PDP_PARAM_PERSISTENT) return fail(PDP_E_INVAL, "unknown parameter flags 0x%x", prm.flags);
 
     pdp_plan *P = new (std::nothrow) pdp_plan();
     if (!P) return fail(PDP_E_INVAL, "out of host memory");
-    uint64_t chunks = 0, tiles = 0, bh_rows = 0, bbh_rows = 0, inc_est = 0;
-    uint32_t tile_lds = 4;
+    auto bail = [&](int32_t rc) {
+        delete P;
+        return rc;
+    };
+    // Pass 1, in the caller's order: validation, output row layout, tile height per direction.
+    uint64_t bh_rows = 0, bbh_rows = 0, inc_est = 0;
+    uint32_t tile_lds = 16;
+    std::vector<DevTask> caller(n_tasks);
+    std::vector<uint64_t> cost(n_tasks);
     for (uint32_t t = 0; t < n_tasks; ++t) {
         const pdp_task &tk = tasks[t];
-        if (!tk.a || !tk.b) {
-            delete P;
-            return fail(PDP_E_INVAL, "task %u: null dictionary", t);
-        }
-        if (tk.a->k != tk.b->k || tk.a->n_buckets != tk.b->n_buckets) {
-            delete P;
-            return fail(PDP_E_INVAL, "task %u: dictionaries built with different k (%u, %u)", t, tk.a->k, tk.b->k);
-        }
+        if (!tk.a || !tk.b) return bail(fail(PDP_E_INVAL, "task %u: null dictionary", t));
+        if (tk.a->k != tk.b->k || tk.a->n_buckets != tk.b->n_buckets)
+            return bail(fail(PDP_E_INVAL, "task %u: dictionaries built with different k (%u, %u)", t, tk.a->k, tk.b->k));
         uint32_t flags = tk.flags & (PDP_TASK_AB | PDP_TASK_BA | PDP_TASK_BBH);
         if (flags & PDP_TASK_BBH) flags |= PDP_TASK_AB | PDP_TASK_BA;
-        if (!flags) {
-            delete P;
-            return fail(PDP_E_INVAL, "task %u: no output selected", t);
-        }
-        DevTask d;
+        if (!flags) return bail(fail(PDP_E_INVAL, "task %u: no output selected", t));
+        DevTask &d = caller[t];
         std::memset(&d, 0, sizeof(d));
         d.a = dev_dict(tk.a);
         d.b = dev_dict(tk.b);
@@ -273,11 +277,8 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         bpw = std::min<uint64_t>(std::max<uint64_t>(bpw, 1), nb);
         d.bpw = static_cast<uint32_t>(bpw);
         d.n_chunks = static_cast<uint32_t>((nb + bpw - 1) / bpw);
-        d.chunk_base = static_cast<uint32_t>(chunks);
-        chunks += d.n_chunks;
         for (uint32_t dir = 0; dir < 2; ++dir) {
             d.row_base[dir] = UINT32_MAX;
-            d.tile_base[dir] = static_cast<uint32_t>(tiles);
             d.tile_rows[dir] = 1;
             if (!(flags & (1u << dir))) continue;
             const pdp_dict *R = dir == 0 ? tk.a : tk.b;
@@ -286,45 +287,66 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
             const uint64_t W = (uint64_t(C->n_genes) + 1) / 2;
             const uint64_t row_words = std::max<uint64_t>(W + (W + 31) / 32, 1);
             uint64_t T = lds_budget / (4 * row_words);
-            if (T == 0) {
-                delete P;
-                return fail(PDP_E_LIMIT, "task %u: %u target genes do not fit an LDS tile of %u bytes", t, C->n_genes, lds_budget);
-            }
+            if (T == 0)
+                return bail(fail(PDP_E_LIMIT, "task %u: %u target genes do not fit an LDS tile of %u bytes", t,
+                                 C->n_genes, lds_budget));
             T = std::min<uint64_t>(T, prm.tile_rows ? prm.tile_rows : kTileMaxRows);
             T = std::max<uint64_t>(std::min<uint64_t>(T, std::max<uint32_t>(R->n_genes, 1)), 1);
             d.tile_rows[dir] = static_cast<uint32_t>(T);
             d.row_base[dir] = static_cast<uint32_t>(bh_rows);
             bh_rows += R->n_genes;
             tile_lds = std::max<uint32_t>(tile_lds, static_cast<uint32_t>(align_up(T * row_words * 4, 16)));
-            for (uint32_t r0 = 0; r0 < R->n_genes; r0 += static_cast<uint32_t>(T)) {
-                DevTile tl;
-                tl.task = t;
-                tl.dir = dir;
-                tl.row0 = r0;
-                tl.nrows = std::min<uint32_t>(static_cast<uint32_t>(T), R->n_genes - r0);
-                P->tiles.push_back(tl);
-            }
-            tiles = P->tiles.size();
         }
         d.bbh_row_base = static_cast<uint32_t>(bbh_rows);
         if (flags & PDP_TASK_BBH) bbh_rows += tk.a->n_genes;
         inc_est += (tk.a->capacity + tk.b->capacity) / 2 + 4096;
-        P->tasks.push_back(d);
+        cost[t] = tk.a->capacity + tk.b->capacity;
         P->ab_row.push_back(d.row_base[0]);
         P->ba_row.push_back(d.row_base[1]);
         P->bbh_row.push_back((flags & PDP_TASK_BBH) ? d.bbh_row_base : UINT32_MAX);
-        if (chunks > UINT32_MAX || bh_rows >= UINT32_MAX || tiles >= UINT32_MAX) {
-            delete P;
-            return fail(PDP_E_LIMIT, "plan too large for 32-bit indices");
+        if (bh_rows >= UINT32_MAX) return bail(fail(PDP_E_LIMIT, "plan too large for 32-bit indices"));
+    }
+    // Pass 2, largest tasks first: join items and tiles are numbered in this order, so work-groups
+    // (and the persistent kernels' counters) take the long items early.
+    std::vector<uint32_t> by_cost(n_tasks);
+    for (uint32_t t = 0; t < n_tasks; ++t) by_cost[t] = t;
+    std::stable_sort(by_cost.begin(), by_cost.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
+    P->order.assign(n_tasks, 0);
+    uint64_t chunks = 0;
+    for (uint32_t i = 0; i < n_tasks; ++i) {
+        const uint32_t t = by_cost[i];
+        P->order[t] = i;
+        DevTask d = caller[t];
+        d.chunk_base = static_cast<uint32_t>(chunks);
+        chunks += d.n_chunks;
+        for (uint32_t dir = 0; dir < 2; ++dir) {
+            d.tile_base[dir] = static_cast<uint32_t>(P->tiles.size());
+            if (!(d.flags & (1u << dir))) continue;
+            const uint32_t nrows = dir == 0 ? d.a.n_genes : d.b.n_genes;
+            const uint32_t T = d.tile_rows[dir];
+            for (uint32_t r0 = 0; r0 < nrows; r0 += T) {
+                DevTile tl;
+                tl.task = i;
+                tl.dir = dir;
+                tl.row0 = r0;
+                tl.nrows = std::min<uint32_t>(T, nrows - r0);
+                P->tiles.push_back(tl);
+            }
         }
+        P->tasks.push_back(d);
+        if (chunks > UINT32_MAX || P->tiles.size() >= UINT32_MAX)
+            return bail(fail(PDP_E_LIMIT, "plan too large for 32-bit indices"));
     }
     P->shape.n_tasks = n_tasks;
     P->shape.total_chunks = static_cast<uint32_t>(chunks);
-    P->shape.total_tiles = static_cast<uint32_t>(tiles);
+    P->shape.total_tiles = static_cast<uint32_t>(P->tiles.size());
     P->shape.bh_rows = static_cast<uint32_t>(bh_rows);
     P->shape.bbh_rows = static_cast<uint32_t>(bbh_rows);
     P->shape.tile_lds = tile_lds;
     P->shape.inc_cap = prm.inc_capacity ? prm.inc_capacity : inc_est;
+    P->shape.join_grid = 0;
+    P->shape.tile_grid = 0;
+    P->persistent = (prm.flags & PDP_PARAM_PERSISTENT) != 0;
     P->ws_bytes = pair_ws_bytes(P->shape);
     *out = P;
     return ok();
@@ -361,6 +383,8 @@ int32_t pdp_plan_upload(const pdp_plan *plan, void *ws, uint64_t ws_bytes, void 
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(w.tasks, plan->tasks.data(), sizeof(DevTask) * plan->tasks.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "pdp_plan_upload");
+    e = hipMemcpyAsync(w.order, plan->order.data(), sizeof(uint32_t) * plan->order.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "pdp_plan_upload");
     if (!plan->tiles.empty()) {
         e = hipMemcpyAsync(w.tiles, plan->tiles.data(), sizeof(DevTile) * plan->tiles.size(), hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "pdp_plan_upload");
@@ -387,6 +411,18 @@ int32_t pdp_plan_launch(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, 
     if (rc) return rc;
     if (ws_bytes < plan->ws_bytes) return fail(PDP_E_WORKSPACE, "workspace %llu < %llu bytes", (unsigned long long)ws_bytes, (unsigned long long)plan->ws_bytes);
     PairWs w = pair_ws_carve(ws, plan->shape);
+    PlanShape shape = plan->shape;
+    if (!plan->device_ready) {
+        hipError_t e = allow_tile_lds(plan->shape.tile_lds);
+        if (e != hipSuccess) return hip_fail(e, "pdp_plan_launch");
+        if (plan->persistent) {
+            plan->join_grid = persistent_join_grid();
+            plan->tile_grid = persistent_tile_grid(plan->shape.tile_lds);
+        }
+        plan->device_ready = true;
+    }
+    shape.join_grid = plan->join_grid;
+    shape.tile_grid = plan->tile_grid;
     KernelTimer timer{-1, nullptr, nullptr};
     if (plan->timer_kernel >= 0 && plan->timer_used < plan->timer_events.size()) {
         timer.kernel = plan->timer_kernel;
@@ -394,7 +430,7 @@ int32_t pdp_plan_launch(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, 
         timer.stop = plan->timer_events[plan->timer_used].second;
         plan->timer_used++;
     }
-    hipError_t e = launch_pairs(plan->shape, w, bh, plan->shape.bbh_rows ? bbh : nullptr, status,
+    hipError_t e = launch_pairs(shape, w, bh, plan->shape.bbh_rows ? bbh : nullptr, status,
                                 static_cast<hipStream_t>(stream), timer.kernel >= 0 ? &timer : nullptr);
     if (e != hipSuccess) return hip_fail(e, "pdp_plan_launch");
     return ok();

@@ -398,12 +398,6 @@ uint64_t build_ws_bytes(const BuildShape &s) {
 
 BuildShape build_shape(const pdp_genome *g, const pdp_dict *const *d, uint32_t n) { return shape_of(g, d, n); }
 
-#define PDP_TRY(x)                              \
-    do {                                        \
-        hipError_t e_ = (x);                    \
-        if (e_ != hipSuccess) return e_;        \
-    } while (0)
-
 hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint32_t n, void *ws, hipStream_t s) {
     const BuildShape sh = shape_of(g, d, n);
     const uint64_t A = 256;

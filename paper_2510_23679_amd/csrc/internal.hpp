@@ -8,6 +8,13 @@
 
 namespace pdp {
 
+// Returns a failing hipError_t from the enclosing launcher.
+#define PDP_TRY(x)                              \
+    do {                                        \
+        hipError_t e_ = (x);                    \
+        if (e_ != hipSuccess) return e_;        \
+    } while (0)
+
 // ---------------------------------------------------------------- sizes
 constexpr uint32_t kScanItems = 4096;        // elements per scan work-group (256 threads x 16)
 constexpr uint32_t kMvSortCap = 2048;        // windows a gene may have to be sorted in LDS
@@ -17,6 +24,7 @@ constexpr uint32_t kJoinLdsCap = 2048;       // target-side index entries staged
 constexpr uint32_t kTileMaxRows = 64;        // rows per accumulation tile
 constexpr uint32_t kTileThreads = 256;
 constexpr uint32_t kDefaultLdsBudget = 48 * 1024;
+constexpr uint32_t kMaxTileLds = 160 * 1024 - 1024;  // gfx950 LDS per work-group, less the static part
 constexpr uint32_t kSlab = 4;                // best hits per row kept by the first tile pass
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
@@ -104,14 +112,22 @@ struct PairWs {
     uint2 *recs;                  // incidences bucketed by tile: ((row<<24)|col, v); 2x capacity
     uint4 *slab;                  // kSlab (column, m, d, -) per best-hit row
     uint32_t *overflow_tiles;     // tiles holding a row with more than kSlab ties
-    uint32_t *overflow_count;     // = counters word 2
+    uint32_t *overflow_count;     // counters word 2
+    uint32_t *next_join;          // counters word 3: next item of the persistent join
+    uint32_t *next_tile;          // counters word 4: next tile of the persistent tile pass
+    uint32_t *order;              // task table indices in the caller's order
     uint32_t *partials;
 };
 
 struct PlanShape {
     uint32_t n_tasks, total_chunks, total_tiles, bh_rows, bbh_rows, tile_lds;
     uint64_t inc_cap;
+    uint32_t join_grid, tile_grid;  // persistent grids (0: one work-group per item)
 };
+// Work-groups of the persistent kernels that fit the current device at once.
+uint32_t persistent_join_grid();
+uint32_t persistent_tile_grid(uint32_t tile_lds);
+hipError_t allow_tile_lds(uint32_t tile_lds);
 uint64_t pair_ws_bytes(const PlanShape &p);
 PairWs pair_ws_carve(void *ws, const PlanShape &p);
 // Optional events recorded around one kernel of a launch (kernel < 0: none).

@@ -72,17 +72,22 @@ __device__ __forceinline__ void join_range(const DevTask &T, uint32_t task, uint
     }
 }
 
-__global__ __launch_bounds__(kJoinThreads) void k_join(const DevTask *__restrict__ tasks, uint32_t n_tasks,
-                                                       uint4 *__restrict__ inc, uint64_t inc_cap,
-                                                       unsigned long long *__restrict__ inc_count) {
-    __shared__ uint64_t s_code[kJoinLdsCap];
-    __shared__ uint32_t s_gene[kJoinLdsCap];
-    __shared__ uint32_t s_cnt[kJoinLdsCap];
-    __shared__ uint32_t s_task;
-    const uint32_t chunk = blockIdx.x;
-    if (threadIdx.x == 0) s_task = find_task(tasks, n_tasks, chunk);
+struct JoinLds {
+    uint64_t code[kJoinLdsCap];
+    uint32_t gene[kJoinLdsCap];
+    uint32_t cnt[kJoinLdsCap];
+    uint32_t task;
+    uint32_t next;
+};
+
+// One join work item: a range of leading-residue buckets of one task.  Ends with a
+// barrier so the LDS can take the next item.
+__device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__restrict__ tasks, uint32_t n_tasks,
+                                           uint4 *__restrict__ inc, uint64_t inc_cap,
+                                           unsigned long long *__restrict__ inc_count, JoinLds &L) {
+    if (threadIdx.x == 0) L.task = find_task(tasks, n_tasks, chunk);
     __syncthreads();
-    const uint32_t task = s_task;
+    const uint32_t task = L.task;
     const DevTask &T = tasks[task];
     const uint32_t c = chunk - T.chunk_base;
     const uint32_t nb = T.a.n_buckets;
@@ -90,19 +95,45 @@ __global__ __launch_bounds__(kJoinThreads) void k_join(const DevTask *__restrict
     const uint32_t bh = min(nb, bl + T.bpw);
     const uint32_t a0 = T.a.ix_dir[bl], a1 = T.a.ix_dir[bh];
     const uint32_t b0 = T.b.ix_dir[bl], b1 = T.b.ix_dir[bh];
-    if (a0 == a1 || b0 == b1) return;
-    const uint32_t nbe = b1 - b0;
-    if (nbe <= kJoinLdsCap) {
-        for (uint32_t i = threadIdx.x; i < nbe; i += kJoinThreads) {
-            s_code[i] = T.b.ix_code[b0 + i];
-            s_gene[i] = T.b.ix_gene[b0 + i];
-            s_cnt[i] = T.b.ix_cnt[b0 + i];
+    if (a0 != a1 && b0 != b1) {
+        const uint32_t nbe = b1 - b0;
+        if (nbe <= kJoinLdsCap) {
+            for (uint32_t i = threadIdx.x; i < nbe; i += kJoinThreads) {
+                L.code[i] = T.b.ix_code[b0 + i];
+                L.gene[i] = T.b.ix_gene[b0 + i];
+                L.cnt[i] = T.b.ix_cnt[b0 + i];
+            }
+            __syncthreads();
+            join_range<true>(T, task, a0, a1, L.code, L.gene, L.cnt, nbe, inc, inc_cap, inc_count);
+        } else {
+            join_range<false>(T, task, a0, a1, T.b.ix_code + b0, T.b.ix_gene + b0, T.b.ix_cnt + b0, nbe, inc, inc_cap,
+                              inc_count);
         }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kJoinThreads) void k_join(const DevTask *__restrict__ tasks, uint32_t n_tasks,
+                                                       uint4 *__restrict__ inc, uint64_t inc_cap,
+                                                       unsigned long long *__restrict__ inc_count) {
+    __shared__ JoinLds L;
+    join_chunk(blockIdx.x, tasks, n_tasks, inc, inc_cap, inc_count, L);
+}
+
+// Persistent form: a fixed grid pulls join items from a counter until none are left.
+__global__ __launch_bounds__(kJoinThreads) void k_join_persistent(const DevTask *__restrict__ tasks, uint32_t n_tasks,
+                                                                  uint32_t total_chunks, uint4 *__restrict__ inc,
+                                                                  uint64_t inc_cap,
+                                                                  unsigned long long *__restrict__ inc_count,
+                                                                  uint32_t *__restrict__ next) {
+    __shared__ JoinLds L;
+    for (;;) {
+        if (threadIdx.x == 0) L.next = atomicAdd(next, 1u);
         __syncthreads();
-        join_range<true>(T, task, a0, a1, s_code, s_gene, s_cnt, nbe, inc, inc_cap, inc_count);
-    } else {
-        join_range<false>(T, task, a0, a1, T.b.ix_code + b0, T.b.ix_gene + b0, T.b.ix_cnt + b0, nbe, inc, inc_cap,
-                          inc_count);
+        const uint32_t chunk = L.next;
+        __syncthreads();
+        if (chunk >= total_chunks) break;
+        join_chunk(chunk, tasks, n_tasks, inc, inc_cap, inc_count, L);
     }
 }
 
@@ -281,6 +312,24 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count(const DevTask *__re
                         overflow_tiles, overflow_count, lds, &s_flag);
 }
 
+// Persistent form: a fixed grid pulls tiles from a counter until none are left.
+__global__ __launch_bounds__(kTileThreads) void k_tile_count_persistent(
+    const DevTask *__restrict__ tasks, const DevTile *__restrict__ tiles, uint32_t total_tiles,
+    const uint32_t *__restrict__ tile_off, const uint2 *__restrict__ recs, uint32_t *__restrict__ bh_ptr,
+    uint4 *__restrict__ slab, uint32_t *overflow_tiles, uint32_t *overflow_count, uint32_t *__restrict__ next) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t s_flag, s_next;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = atomicAdd(next, 1u);
+        __syncthreads();
+        const uint32_t t = s_next;
+        __syncthreads();
+        if (t >= total_tiles) break;
+        tile_process<false>(t, tasks, tiles, tile_off, recs, bh_ptr, slab, nullptr, nullptr, nullptr, 0, overflow_tiles,
+                            overflow_count, lds, &s_flag);
+    }
+}
+
 // Rows with more ties than the slab holds: their tiles again, written to the CSR output.
 __global__ __launch_bounds__(kTileThreads) void k_tile_write(const DevTask *__restrict__ tasks,
                                                              const DevTile *__restrict__ tiles,
@@ -348,18 +397,22 @@ __device__ __forceinline__ void bbh_row(uint32_t a, uint32_t grow, uint32_t rab,
     if (!WRITE) out_ptr[grow] = pos;
 }
 
-__device__ __forceinline__ uint32_t find_bbh_task(const DevTask *tasks, uint32_t n_tasks, uint32_t row) {
+// The task table is stored in processing order (largest tasks first); order[]
+// lists it in the caller's order, in which BBH row bases increase.
+__device__ __forceinline__ uint32_t find_bbh_task(const DevTask *tasks, const uint32_t *order, uint32_t n_tasks,
+                                                  uint32_t row) {
     uint32_t lo = 0, hi = n_tasks - 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) >> 1;
-        if (tasks[mid].bbh_row_base <= row) lo = mid;
+        if (tasks[order[mid]].bbh_row_base <= row) lo = mid;
         else hi = mid - 1;
     }
-    return lo;
+    return order[lo];
 }
 
 template <bool WRITE>
-__global__ __launch_bounds__(256) void k_bbh(const DevTask *__restrict__ tasks, uint32_t n_tasks, uint32_t bbh_rows,
+__global__ __launch_bounds__(256) void k_bbh(const DevTask *__restrict__ tasks, const uint32_t *__restrict__ order,
+                                             uint32_t n_tasks, uint32_t bbh_rows,
                                              const uint32_t *__restrict__ bh_ptr, const uint32_t *__restrict__ bh_col,
                                              const uint32_t *__restrict__ bh_num, const uint32_t *__restrict__ bh_den,
                                              uint32_t *__restrict__ out_ptr, uint32_t *__restrict__ out_a,
@@ -368,7 +421,7 @@ __global__ __launch_bounds__(256) void k_bbh(const DevTask *__restrict__ tasks, 
     const uint32_t grow = blockIdx.x * blockDim.x + threadIdx.x;
     if (WRITE && grow == 0 && out_ptr[bbh_rows] > cap) raise_status(st, PDP_E_CAPACITY, out_ptr[bbh_rows], 2);
     if (grow >= bbh_rows) return;
-    const DevTask &T = tasks[find_bbh_task(tasks, n_tasks, grow)];
+    const DevTask &T = tasks[find_bbh_task(tasks, order, n_tasks, grow)];
     const uint32_t a = grow - T.bbh_row_base;
     bbh_row<WRITE>(a, grow, T.row_base[0] + a, T.row_base[1], bh_ptr, bh_col, bh_num, bh_den, bh_ptr, bh_col, out_ptr,
                    out_a, out_b, out_num, out_den, cap);
@@ -398,11 +451,45 @@ __global__ __launch_bounds__(256) void k_bbh_pair(uint32_t rows, const uint32_t 
 
 // ------------------------------------------------------------------ host
 
+static uint32_t device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+    return cus > 0 ? static_cast<uint32_t>(cus) : 1u;
+}
+
+uint32_t persistent_join_grid() {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_join_persistent, kJoinThreads, 0) != hipSuccess || per < 1)
+        per = 1;
+    return device_cus() * static_cast<uint32_t>(per);
+}
+
+uint32_t persistent_tile_grid(uint32_t tile_lds) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tile_count_persistent, kTileThreads, tile_lds) != hipSuccess ||
+        per < 1)
+        per = 1;
+    return device_cus() * static_cast<uint32_t>(per);
+}
+
+// Tiles above 64 KiB of dynamic LDS need the kernels' limit raised (gfx950 has 160 KiB per work-group).
+hipError_t allow_tile_lds(uint32_t tile_lds) {
+    if (tile_lds <= 64 * 1024) return hipSuccess;
+    const int v = static_cast<int>(tile_lds);
+    PDP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_count), hipFuncAttributeMaxDynamicSharedMemorySize, v));
+    PDP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_count_persistent),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, v));
+    PDP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_write), hipFuncAttributeMaxDynamicSharedMemorySize, v));
+    return hipSuccess;
+}
+
 uint64_t pair_ws_bytes(const PlanShape &p) {
     const uint64_t A = 256;
     uint64_t s = 0;
     s += align_up(sizeof(DevTask) * std::max<uint64_t>(p.n_tasks, 1), A);
     s += align_up(sizeof(DevTile) * std::max<uint64_t>(p.total_tiles, 1), A);
+    s += align_up(4 * std::max<uint64_t>(p.n_tasks, 1), A);
     s += align_up(16 * std::max<uint64_t>(p.inc_cap, 1), A);
     s += align_up(16, A);
     s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
@@ -426,9 +513,12 @@ PairWs pair_ws_carve(void *ws, const PlanShape &p) {
     PairWs w;
     w.tasks = reinterpret_cast<DevTask *>(take(sizeof(DevTask) * std::max<uint64_t>(p.n_tasks, 1)));
     w.tiles = reinterpret_cast<DevTile *>(take(sizeof(DevTile) * std::max<uint64_t>(p.total_tiles, 1)));
+    w.order = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(p.n_tasks, 1)));
     w.inc = reinterpret_cast<uint4 *>(take(16 * std::max<uint64_t>(p.inc_cap, 1)));
-    w.counters = reinterpret_cast<unsigned long long *>(take(16));
+    w.counters = reinterpret_cast<unsigned long long *>(take(32));
     w.overflow_count = reinterpret_cast<uint32_t *>(w.counters) + 2;
+    w.next_join = reinterpret_cast<uint32_t *>(w.counters) + 3;
+    w.next_tile = reinterpret_cast<uint32_t *>(w.counters) + 4;
     w.tile_cnt = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
     w.tile_fill = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
     w.recs = reinterpret_cast<uint2 *>(take(8 * 2 * std::max<uint64_t>(p.inc_cap, 1)));
@@ -439,12 +529,6 @@ PairWs pair_ws_carve(void *ws, const PlanShape &p) {
     return w;
 }
 
-#define PDP_TRY(x)                              \
-    do {                                        \
-        hipError_t e_ = (x);                    \
-        if (e_ != hipSuccess) return e_;        \
-    } while (0)
-
 hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *st,
                         hipStream_t s, const KernelTimer *timer) {
     auto mark = [&](int32_t kernel, bool begin) -> hipError_t {
@@ -453,11 +537,16 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     };
     PDP_TRY(mark(PDP_KERNEL_ALL, true));
     PDP_TRY(launch_status_init(st, s));
-    PDP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(w.counters), 4, 0u, s));  // incidences, overflow tiles
+    // counters: incidences (64-bit), overflow tiles, next join item, next tile
+    PDP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(w.counters), 8, 0u, s));
     PDP_TRY(launch_fill_u32(w.tile_cnt, uint64_t(p.total_tiles) + 1, 0u, s));
     PDP_TRY(launch_fill_u32(w.tile_fill, uint64_t(p.total_tiles) + 1, 0u, s));
     PDP_TRY(mark(PDP_KERNEL_JOIN, true));
-    if (p.total_chunks) {
+    if (p.total_chunks && p.join_grid) {
+        hipLaunchKernelGGL(k_join_persistent, dim3(std::min(p.join_grid, p.total_chunks)), dim3(kJoinThreads), 0, s,
+                           w.tasks, p.n_tasks, p.total_chunks, w.inc, p.inc_cap, w.counters, w.next_join);
+        PDP_TRY(hipGetLastError());
+    } else if (p.total_chunks) {
         hipLaunchKernelGGL(k_join, dim3(p.total_chunks), dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.inc, p.inc_cap,
                            w.counters);
         PDP_TRY(hipGetLastError());
@@ -473,7 +562,12 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     PDP_TRY(hipGetLastError());
     PDP_TRY(mark(PDP_KERNEL_BUCKET, false));
     PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, true));
-    if (p.total_tiles) {
+    if (p.total_tiles && p.tile_grid) {
+        hipLaunchKernelGGL(k_tile_count_persistent, dim3(std::min(p.tile_grid, p.total_tiles)), dim3(kTileThreads),
+                           p.tile_lds, s, w.tasks, w.tiles, p.total_tiles, w.tile_cnt, w.recs, bh->ptr, w.slab,
+                           w.overflow_tiles, w.overflow_count, w.next_tile);
+        PDP_TRY(hipGetLastError());
+    } else if (p.total_tiles) {
         hipLaunchKernelGGL(k_tile_count, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
                            w.tile_cnt, w.recs, bh->ptr, w.slab, w.overflow_tiles, w.overflow_count);
         PDP_TRY(hipGetLastError());
@@ -497,11 +591,11 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     PDP_TRY(mark(PDP_KERNEL_BBH, true));
     if (p.bbh_rows && bbh) {
         const uint32_t g = (p.bbh_rows + 255) / 256;
-        hipLaunchKernelGGL(k_bbh<false>, dim3(g), dim3(256), 0, s, w.tasks, p.n_tasks, p.bbh_rows, bh->ptr, bh->col,
+        hipLaunchKernelGGL(k_bbh<false>, dim3(g), dim3(256), 0, s, w.tasks, w.order, p.n_tasks, p.bbh_rows, bh->ptr, bh->col,
                            bh->num, bh->den, bbh->ptr, bbh->a, bbh->b, bbh->num, bbh->den, bbh->capacity, st);
         PDP_TRY(hipGetLastError());
         PDP_TRY(launch_scan(bbh->ptr, bbh->ptr, p.bbh_rows, w.partials, s));
-        hipLaunchKernelGGL(k_bbh<true>, dim3(g), dim3(256), 0, s, w.tasks, p.n_tasks, p.bbh_rows, bh->ptr, bh->col,
+        hipLaunchKernelGGL(k_bbh<true>, dim3(g), dim3(256), 0, s, w.tasks, w.order, p.n_tasks, p.bbh_rows, bh->ptr, bh->col,
                            bh->num, bh->den, bbh->ptr, bbh->a, bbh->b, bbh->num, bbh->den, bbh->capacity, st);
         PDP_TRY(hipGetLastError());
     }
