@@ -277,6 +277,43 @@ int32_t pdp_plan_timer_stop(pdp_plan *plan);
 int32_t pdp_plan_run(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *status,
                      void *ws, uint64_t ws_bytes, void *stream);
 
+/* ----------------------------------------------- batching: graphs, tuning */
+
+/* HIP graphs of library work (many instances and genome pairs replayed as one
+ * launch): pdp_capture_begin starts capturing everything enqueued on stream
+ * (thread-local capture mode; not the NULL stream), pdp_capture_end stops and
+ * instantiates it, pdp_graph_launch replays it on any stream.  Capture only
+ * calls that enqueue kernels (pdp_dict_build_many, pdp_plan_launch): upload
+ * plans before capturing.  A graph refers to the workspaces and outputs it was
+ * captured with; they must stay allocated while it is used.
+ * Errors: PDP_E_INVAL, PDP_E_HIP. */
+typedef struct pdp_graph pdp_graph;
+int32_t pdp_capture_begin(void *stream);
+int32_t pdp_capture_end(void *stream, pdp_graph **out);
+int32_t pdp_graph_launch(pdp_graph *graph, void *stream);
+void pdp_graph_destroy(pdp_graph *graph);
+
+/* Autotuner for tile shapes and work splits: each candidate pdp_params is
+ * planned for the given tasks, run once to warm up and then reps times between
+ * two HIP events; the fastest candidate whose runs end with a clean status is
+ * returned.  candidates NULL: a built-in grid of LDS budgets (24-144 KiB),
+ * join group sizes (256-2048 entries) and persistent on/off.  bh/bbh/status as
+ * for pdp_plan_launch (their rows do not depend on the parameters); ws of
+ * pdp_autotune_ws_size bytes.  Synchronises the stream.
+ * Errors: PDP_E_INVAL, PDP_E_HIP, PDP_E_LIMIT (no candidate ran cleanly). */
+typedef struct pdp_tune_result {
+    pdp_params best;
+    double best_ms;   /* average milliseconds per launch of the best candidate */
+    double first_ms;  /* the same for the first candidate that ran */
+    uint32_t tried;   /* candidates that ran cleanly */
+    uint32_t reserved;
+} pdp_tune_result;
+int32_t pdp_autotune_ws_size(const pdp_task *tasks, uint32_t n_tasks, const pdp_params *candidates,
+                             uint32_t n_candidates, uint64_t *ws_bytes);
+int32_t pdp_autotune(const pdp_task *tasks, uint32_t n_tasks, const pdp_params *candidates, uint32_t n_candidates,
+                     uint32_t reps, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *status, void *ws,
+                     uint64_t ws_bytes, void *stream, pdp_tune_result *result);
+
 /* Convenience form of one task: best hits of every gene of q in t (Eq.
  * best_hit, Alg. 2); out->n_rows must equal q->n_genes.  The workspace size
  * comes from pdp_bh_ws_size.  The plan tables are uploaded and the stream is

@@ -447,3 +447,68 @@ def bbh(ab: BHOut, ba: BHOut, capacity: Optional[int] = None, stream=None) -> BB
             raise B.PdpError(code, f"pdp_bbh: {lib().pdp_strerror(code).decode()}")
         return out
     raise B.PdpError(B.PDP_E_CAPACITY, "pdp_bbh: capacity still too small")
+
+
+class Graph:
+    """A HIP graph of library launches: ``with Graph.capture(stream) as g: ...`` then ``g.launch()``."""
+
+    def __init__(self, stream: torch.cuda.Stream):
+        self.stream = stream
+        self.h = B.vp()
+
+    @classmethod
+    def capture(cls, stream: torch.cuda.Stream) -> "Graph":
+        return cls(stream)
+
+    def __enter__(self) -> "Graph":
+        check(lib().pdp_capture_begin(_stream_handle(self.stream)), "pdp_capture_begin")
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        rc = lib().pdp_capture_end(_stream_handle(self.stream), C.byref(self.h))
+        if exc_type is None:
+            check(rc, "pdp_capture_end")
+        return False
+
+    def launch(self, stream: Optional[torch.cuda.Stream] = None) -> None:
+        check(lib().pdp_graph_launch(self.h, _stream_handle(stream or self.stream)), "pdp_graph_launch")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                lib().pdp_graph_destroy(h)
+            except Exception:  # pragma: no cover - interpreter shutdown
+                pass
+            self.h = B.vp()
+
+
+def _task_array(tasks):
+    arr = (B.pdp_task * len(tasks))()
+    for i, (a, b, f) in enumerate(tasks):
+        arr[i].a = C.pointer(a.d)
+        arr[i].b = C.pointer(b.d)
+        arr[i].flags = int(f)
+    return arr
+
+
+def autotune(tasks, candidates: Optional[Sequence[B.pdp_params]] = None, reps: int = 3, stream=None):
+    """pdp_autotune over a list of (dict a, dict b, flags); returns (best params, result)."""
+    arr = _task_array(tasks)
+    cand = (B.pdp_params * len(candidates))(*candidates) if candidates else None
+    nc = len(candidates) if candidates else 0
+    need = B.u64(0)
+    check(lib().pdp_autotune_ws_size(arr, len(tasks), cand, nc, C.byref(need)), "pdp_autotune_ws_size")
+    plan = Plan(tasks)
+    ws = Workspace(need.value)
+    bh_out = BHOut(plan.info.bh_rows, 4 * plan.info.bh_rows + 1024)
+    bbh_out = BBHOut(plan.info.bbh_rows, 2 * plan.info.bbh_rows + 1024) if plan.info.bbh_rows else None
+    st = new_status()
+    res = B.pdp_tune_result()
+    bs = bh_out.struct()
+    bb = bbh_out.struct() if bbh_out is not None else None
+    check(lib().pdp_autotune(arr, len(tasks), cand, nc, int(reps), C.byref(bs), C.byref(bb) if bb is not None else None,
+                             st.data_ptr(), ws.ptr, ws.nbytes, _stream_handle(stream), C.byref(res)), "pdp_autotune")
+    best = B.pdp_params(res.best.inc_capacity, res.best.tile_rows, res.best.join_entries, res.best.lds_budget,
+                        res.best.flags)
+    return best, res

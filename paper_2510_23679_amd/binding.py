@@ -75,6 +75,11 @@ class pdp_plan_info(C.Structure):
                 ("join_groups", u32), ("tiles", u32), ("tile_lds", u32)]
 
 
+class pdp_tune_result(C.Structure):
+    _fields_ = [("best", pdp_params), ("best_ms", C.c_double), ("first_ms", C.c_double), ("tried", u32),
+                ("reserved", u32)]
+
+
 # name -> (restype, argtypes); the same names as include/pdp.h
 SIGNATURES = {
     "pdp_abi_version": (u32, []),
@@ -96,7 +101,14 @@ SIGNATURES = {
     "pdp_plan_timer_start": (i32, [vp, i32, u32]),
     "pdp_plan_timer_read": (i32, [vp, C.POINTER(C.c_double), C.POINTER(u32)]),
     "pdp_plan_timer_stop": (i32, [vp]),
-    "pdp_bh_ws_size":(i32, [C.POINTER(pdp_dict), C.POINTER(pdp_dict), C.POINTER(pdp_params), C.POINTER(u64)]),
+    "pdp_capture_begin": (i32, [vp]),
+    "pdp_capture_end": (i32, [vp, C.POINTER(vp)]),
+    "pdp_graph_launch": (i32, [vp, vp]),
+    "pdp_graph_destroy": (None, [vp]),
+    "pdp_autotune_ws_size": (i32, [C.POINTER(pdp_task), u32, C.POINTER(pdp_params), u32, C.POINTER(u64)]),
+    "pdp_autotune": (i32, [C.POINTER(pdp_task), u32, C.POINTER(pdp_params), u32, u32, C.POINTER(pdp_bh_out),
+                           C.POINTER(pdp_bbh_out), vp, vp, u64, vp, C.POINTER(pdp_tune_result)]),
+    "pdp_bh_ws_size": (i32,[C.POINTER(pdp_dict), C.POINTER(pdp_dict), C.POINTER(pdp_params), C.POINTER(u64)]),
     "pdp_bh": (i32, [C.POINTER(pdp_dict), C.POINTER(pdp_dict), C.POINTER(pdp_params), C.POINTER(pdp_bh_out), vp, vp,
                      u64, vp]),
     "pdp_bbh_ws_size": (i32, [u32, C.POINTER(u64)]),

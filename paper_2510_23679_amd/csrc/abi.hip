@@ -35,6 +35,14 @@ int32_t ok() {
 
 }  // namespace
 
+int32_t pdp::api_fail(int32_t code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
 struct pdp_plan {
     std::vector<DevTask> tasks;
     std::vector<DevTile> tiles;

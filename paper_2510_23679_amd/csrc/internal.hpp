@@ -124,6 +124,9 @@ struct PlanShape {
     uint64_t inc_cap;
     uint32_t join_grid, tile_grid;  // persistent grids (0: one work-group per item)
 };
+// Records the message that pdp_last_error() returns on this thread; returns code.
+int32_t api_fail(int32_t code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
 // Work-groups of the persistent kernels that fit the current device at once.
 uint32_t persistent_join_grid();
 uint32_t persistent_tile_grid(uint32_t tile_lds);
