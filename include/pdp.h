@@ -314,6 +314,75 @@ int32_t pdp_autotune(const pdp_task *tasks, uint32_t n_tasks, const pdp_params *
                      uint32_t reps, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *status, void *ws,
                      uint64_t ws_bytes, void *stream, pdp_tune_result *result);
 
+/* ----------------------------------------------------------------- serving */
+
+/* A request loop: genomes arrive one at a time and each is compared (best
+ * hits both ways and BBH, Eqs. best_hit and bidirectional_best_hit) with every
+ * resident genome, whose dictionaries stay on the device.  A worker thread
+ * admits waiting requests in arrival order whenever a slot (one HIP stream) is
+ * free and the request's device footprint (its genome, dictionary, scratch and
+ * outputs) fits the budget, carved from the caller's arena; admitted requests
+ * run concurrently on their slots, and a finished request's slot and memory
+ * pass at once to the next waiting one.  Results are copied to host memory
+ * owned by the server.  A request's results do not depend on which other
+ * requests share the device. */
+typedef struct pdp_server pdp_server;
+
+typedef struct pdp_server_config {
+    uint64_t budget_bytes;  /* device bytes for requests in flight (at most arena_bytes) */
+    uint32_t slots;         /* requests in flight at most, 1..64 */
+    uint32_t k;             /* k of every resident and request */
+    pdp_params params;      /* pair-path parameters (inc_capacity is managed per request) */
+} pdp_server_config;
+
+/* A finished request.  Times are microseconds since pdp_server_create. */
+typedef struct pdp_request_done {
+    uint64_t tag;
+    int32_t code;        /* PDP_OK, or the request's error (PDP_E_BUDGET: never fits the budget) */
+    uint32_t n_genes;
+    uint32_t attempts;   /* runs, more than 1 after a capacity error grew its buffers */
+    uint32_t reserved;
+    double submit_us, admit_us, done_us;
+    uint64_t bh_entries, bbh_pairs;
+} pdp_request_done;
+
+/* A finished request's results (host memory owned by the server, valid until
+ * pdp_server_release).  Task r is (request, resident r): its rows start at
+ * ab_row[r] (request genes in resident r) and ba_row[r] (resident r's genes
+ * in the request) of the best-hit CSR, and at bbh_row[r] of the BBH CSR. */
+typedef struct pdp_request_result {
+    int32_t code;
+    uint32_t n_residents;
+    pdp_status status;
+    uint32_t bh_rows, bbh_rows;
+    const uint32_t *ab_row, *ba_row, *bbh_row;                 /* [n_residents] */
+    const uint32_t *bh_ptr, *bh_col, *bh_num, *bh_den;         /* CSR */
+    const uint32_t *bbh_ptr, *bbh_a, *bbh_b, *bbh_num, *bbh_den;
+} pdp_request_result;
+
+typedef struct pdp_server_stats {
+    uint64_t admitted, completed, retries, pending;
+    uint64_t budget_bytes, used_bytes, peak_used_bytes;
+    uint32_t inflight, peak_inflight;
+} pdp_server_stats;
+
+/* residents: dictionaries built with cfg->k, borrowed until pdp_server_destroy.
+ * arena: caller device memory (256-byte aligned) of which budget_bytes are used.
+ * Errors: PDP_E_INVAL, PDP_E_WORKSPACE, PDP_E_HIP. */
+int32_t pdp_server_create(const pdp_server_config *cfg, const pdp_dict *const *residents, uint32_t n_residents,
+                          void *arena, uint64_t arena_bytes, pdp_server **out);
+/* Queues one genome (host arrays, copied before return); tag must be unused. */
+int32_t pdp_server_submit(pdp_server *server, const uint8_t *residues, const uint64_t *gene_off, uint32_t n_genes,
+                          uint64_t tag);
+/* Up to max finished requests not yet reported, oldest first; waits up to
+ * wait_us for one if none is ready.  Returns PDP_E_HIP after a device error. */
+int32_t pdp_server_poll(pdp_server *server, pdp_request_done *done, uint32_t max, uint32_t *n_done, uint32_t wait_us);
+int32_t pdp_server_fetch(pdp_server *server, uint64_t tag, pdp_request_result *out);
+int32_t pdp_server_release(pdp_server *server, uint64_t tag);
+int32_t pdp_server_stats_get(pdp_server *server, pdp_server_stats *out);
+/* Waits for requests in flight, then frees the server (not the arena). */
+void pdp_server_destroy(pdp_server *server);
+
 /* Convenience form of one task: best hits of every gene of q in t (Eq.
  * best_hit, Alg. 2); out->n_rows must equal q->n_genes.  The workspace size
  * comes from pdp_bh_ws_size.  The plan tables are uploaded and the stream is

@@ -10,5 +10,6 @@ from .binding import (  # noqa: F401
 )
 from .api import (  # noqa: F401
     BBHOut, BHOut, DeviceGenome, Dictionary, DictionaryBatch, PairResults, PairRunner, Plan, Workspace, abi_version,
-    Graph, all_pairs_tasks, autotune, bbh, bh, dict_size, k_rule, new_status, params, read_status,
+    Graph, RequestResult, Server, all_pairs_tasks, autotune, bbh, bh, dict_size, k_rule, new_status, params,
+    read_status,
 )

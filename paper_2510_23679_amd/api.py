@@ -483,6 +483,102 @@ class Graph:
             self.h = B.vp()
 
 
+@dataclass
+class RequestResult:
+    """Host copy of one served request: per resident r, best hits both ways and BBH."""
+
+    tag: int
+    code: int
+    ab_row: np.ndarray
+    ba_row: np.ndarray
+    bbh_row: np.ndarray
+    bh: tuple  # (ptr, col, num, den)
+    bbh: tuple  # (ptr, a, b, num, den)
+    n_genes: int
+    resident_genes: List[int]
+
+    def best_hits(self, r: int, direction: int = 0):
+        base = int((self.ab_row if direction == 0 else self.ba_row)[r])
+        n = self.n_genes if direction == 0 else self.resident_genes[r]
+        ptr, col, num, den = self.bh
+        p = ptr[base:base + n + 1].astype(np.int64)
+        lo, hi = int(p[0]), int(p[-1])
+        return (p - lo).astype(np.uint32), col[lo:hi], num[lo:hi], den[lo:hi]
+
+    def bbh_pairs(self, r: int):
+        base = int(self.bbh_row[r])
+        ptr, a, b, num, den = self.bbh
+        lo, hi = int(ptr[base]), int(ptr[base + self.n_genes])
+        return a[lo:hi], b[lo:hi], num[lo:hi], den[lo:hi]
+
+
+class Server:
+    """pdp_server: resident dictionaries on device, requests admitted under an HBM budget."""
+
+    def __init__(self, residents: Sequence[Dictionary], budget_bytes: int, slots: int = 8,
+                 prm: Optional[B.pdp_params] = None):
+        self.residents = list(residents)
+        self.k = self.residents[0].k
+        self.arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device=_device())
+        cfg = B.pdp_server_config(int(budget_bytes), int(slots), self.k, prm or params())
+        arr = (C.POINTER(B.pdp_dict) * len(self.residents))(*[C.pointer(d.d) for d in self.residents])
+        self.h = B.vp()
+        torch.cuda.synchronize()  # residents built on torch streams must be complete before other streams read them
+        check(lib().pdp_server_create(C.byref(cfg), arr, len(self.residents), self.arena.data_ptr(), int(budget_bytes),
+                                      C.byref(self.h)), "pdp_server_create")
+        self._keep = []
+
+    def submit(self, genome, tag: int) -> None:
+        res = np.ascontiguousarray(genome.residues, dtype=np.uint8)
+        off = np.ascontiguousarray(genome.offsets, dtype=np.uint64)
+        check(lib().pdp_server_submit(self.h, res.ctypes.data, off.ctypes.data, int(off.shape[0] - 1), int(tag)),
+              "pdp_server_submit")
+
+    def poll(self, max_n: int = 64, wait_us: int = 0) -> List[B.pdp_request_done]:
+        arr = (B.pdp_request_done * max_n)()
+        n = B.u32(0)
+        check(lib().pdp_server_poll(self.h, arr, max_n, C.byref(n), int(wait_us)), "pdp_server_poll")
+        return [arr[i] for i in range(n.value)]
+
+    def fetch(self, tag: int) -> RequestResult:
+        r = B.pdp_request_result()
+        check(lib().pdp_server_fetch(self.h, int(tag), C.byref(r)), "pdp_server_fetch")
+        nr = r.n_residents
+
+        def arr(p, n):
+            return np.ctypeslib.as_array(p, shape=(n,)).copy() if n else np.zeros(0, np.uint32)
+
+        if r.code != 0:
+            return RequestResult(int(tag), int(r.code), None, None, None, None, None, 0, [])
+        bh_ptr = arr(r.bh_ptr, r.bh_rows + 1)
+        bbh_ptr = arr(r.bbh_ptr, r.bbh_rows + 1)
+        nbh, nbb = int(bh_ptr[-1]), int(bbh_ptr[-1])
+        n_genes = r.bbh_rows // max(nr, 1)
+        return RequestResult(int(tag), 0, arr(r.ab_row, nr), arr(r.ba_row, nr), arr(r.bbh_row, nr),
+                             (bh_ptr, arr(r.bh_col, nbh), arr(r.bh_num, nbh), arr(r.bh_den, nbh)),
+                             (bbh_ptr, arr(r.bbh_a, nbb), arr(r.bbh_b, nbb), arr(r.bbh_num, nbb), arr(r.bbh_den, nbb)),
+                             n_genes, [d.n_genes for d in self.residents])
+
+    def release(self, tag: int) -> None:
+        check(lib().pdp_server_release(self.h, int(tag)), "pdp_server_release")
+
+    def stats(self) -> B.pdp_server_stats:
+        s = B.pdp_server_stats()
+        check(lib().pdp_server_stats_get(self.h, C.byref(s)), "pdp_server_stats_get")
+        return s
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().pdp_server_destroy(self.h)
+            self.h = B.vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover - interpreter shutdown
+            pass
+
+
 def _task_array(tasks):
     arr = (B.pdp_task * len(tasks))()
     for i, (a, b, f) in enumerate(tasks):

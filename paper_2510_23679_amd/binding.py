@@ -80,6 +80,31 @@ class pdp_tune_result(C.Structure):
                 ("reserved", u32)]
 
 
+class pdp_server_config(C.Structure):
+    _fields_ = [("budget_bytes", u64), ("slots", u32), ("k", u32), ("params", pdp_params)]
+
+
+class pdp_request_done(C.Structure):
+    _fields_ = [("tag", u64), ("code", i32), ("n_genes", u32), ("attempts", u32), ("reserved", u32),
+                ("submit_us", C.c_double), ("admit_us", C.c_double), ("done_us", C.c_double),
+                ("bh_entries", u64), ("bbh_pairs", u64)]
+
+
+_P32 = C.POINTER(u32)
+
+
+class pdp_request_result(C.Structure):
+    _fields_ = [("code", i32), ("n_residents", u32), ("status", pdp_status), ("bh_rows", u32), ("bbh_rows", u32),
+                ("ab_row", _P32), ("ba_row", _P32), ("bbh_row", _P32),
+                ("bh_ptr", _P32), ("bh_col", _P32), ("bh_num", _P32), ("bh_den", _P32),
+                ("bbh_ptr", _P32), ("bbh_a", _P32), ("bbh_b", _P32), ("bbh_num", _P32), ("bbh_den", _P32)]
+
+
+class pdp_server_stats(C.Structure):
+    _fields_ = [("admitted", u64), ("completed", u64), ("retries", u64), ("pending", u64), ("budget_bytes", u64),
+                ("used_bytes", u64), ("peak_used_bytes", u64), ("inflight", u32), ("peak_inflight", u32)]
+
+
 # name -> (restype, argtypes); the same names as include/pdp.h
 SIGNATURES = {
     "pdp_abi_version": (u32, []),
@@ -108,6 +133,14 @@ SIGNATURES = {
     "pdp_autotune_ws_size": (i32, [C.POINTER(pdp_task), u32, C.POINTER(pdp_params), u32, C.POINTER(u64)]),
     "pdp_autotune": (i32, [C.POINTER(pdp_task), u32, C.POINTER(pdp_params), u32, u32, C.POINTER(pdp_bh_out),
                            C.POINTER(pdp_bbh_out), vp, vp, u64, vp, C.POINTER(pdp_tune_result)]),
+    "pdp_server_create": (i32, [C.POINTER(pdp_server_config), C.POINTER(C.POINTER(pdp_dict)), u32, vp, u64,
+                                C.POINTER(vp)]),
+    "pdp_server_submit": (i32, [vp, vp, vp, u32, u64]),
+    "pdp_server_poll": (i32, [vp, C.POINTER(pdp_request_done), u32, C.POINTER(u32), u32]),
+    "pdp_server_fetch": (i32, [vp, u64, C.POINTER(pdp_request_result)]),
+    "pdp_server_release": (i32, [vp, u64]),
+    "pdp_server_stats_get": (i32, [vp, C.POINTER(pdp_server_stats)]),
+    "pdp_server_destroy": (None, [vp]),
     "pdp_bh_ws_size": (i32,[C.POINTER(pdp_dict), C.POINTER(pdp_dict), C.POINTER(pdp_params), C.POINTER(u64)]),
     "pdp_bh": (i32, [C.POINTER(pdp_dict), C.POINTER(pdp_dict), C.POINTER(pdp_params), C.POINTER(pdp_bh_out), vp, vp,
                      u64, vp]),

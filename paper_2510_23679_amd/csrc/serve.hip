@@ -1,0 +1,572 @@
+// Serving runtime: genomes arrive one by one and each is compared against a
+// set of resident genomes whose dictionaries stay on the device.
+//
+// A worker thread owns the device side.  Requests wait in arrival order; the
+// head request is admitted when a slot (one HIP stream) is free and its whole
+// device footprint fits the budget, carved first-fit from a caller-provided
+// arena.  An admitted request runs, on its own stream: copy of its residues to
+// the device, dictionary build, one plan of |residents| tasks (best hits both
+// ways + BBH against every resident), and the copy of every result and the
+// status back to pinned host memory, closed by an event.  Requests admitted
+// while others run overlap with them on the device (continuous batching); a
+// finished slot and its memory go to the next waiting request at once.  Every
+// request's arithmetic depends only on its own inputs and the residents, so
+// its results are the same alone or in any mix.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace pdp;
+
+namespace {
+
+// First-fit allocator over [0, size) in 256-byte granules, with coalescing.
+class Arena {
+public:
+    explicit Arena(uint64_t size) : size_(size) {
+        if (size) free_[0] = size;
+    }
+    bool alloc(uint64_t bytes, uint64_t *off) {
+        bytes = align_up(std::max<uint64_t>(bytes, 1), 256);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const uint64_t rest = it->second - bytes;
+                const uint64_t at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t bytes) {
+        bytes = align_up(std::max<uint64_t>(bytes, 1), 256);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t size() const { return size_; }
+    uint64_t used() const { return used_; }
+
+private:
+    uint64_t size_, used_ = 0;
+    std::map<uint64_t, uint64_t> free_;
+};
+
+double now_us(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+}
+
+struct Pinned {
+    void *p = nullptr;
+    uint64_t bytes = 0;
+    bool ensure(uint64_t n) {
+        if (n <= bytes) return true;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (hipHostMalloc(&p, n, hipHostMallocDefault) != hipSuccess) return false;
+        bytes = n;
+        return true;
+    }
+    ~Pinned() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
+}  // namespace
+
+struct ServeRequest {
+    uint64_t tag;
+    std::vector<uint8_t> res;
+    std::vector<uint64_t> off;
+    uint32_t n_genes = 0;
+    uint64_t n_res = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int32_t code = PDP_OK;
+    uint32_t attempts = 0;
+    uint64_t inc_cap = 0, bh_cap = 0, bbh_cap = 0;
+    // device side while in flight
+    uint64_t dev_off = 0, dev_bytes = 0;
+    pdp_dict dict{};
+    pdp_plan *plan = nullptr;
+    pdp_bh_out bh{};
+    pdp_bbh_out bbh{};
+    pdp_status *status = nullptr;
+    // results, host
+    pdp_status hstatus{};
+    std::vector<uint32_t> ab_row, ba_row, bbh_row;
+    std::vector<uint32_t> bh_ptr, bh_col, bh_num, bh_den, bbh_ptr, bbh_a, bbh_b, bbh_num, bbh_den;
+};
+
+struct ServeSlot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    ServeRequest *req = nullptr;
+    Pinned pin;
+};
+
+struct pdp_server {
+    pdp_server_config cfg{};
+    int device = 0;
+    std::vector<pdp_dict> residents;
+    char *arena_base = nullptr;
+    std::unique_ptr<Arena> arena;
+    std::vector<ServeSlot> slots;
+    std::deque<ServeRequest *> pending;
+    std::unordered_map<uint64_t, std::unique_ptr<ServeRequest>> all;
+    std::deque<uint64_t> finished;  // tags, completion order, not yet polled
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread worker;
+    bool stop = false;
+    int32_t fatal = PDP_OK;
+    std::chrono::steady_clock::time_point t0;
+    uint64_t admitted = 0, completed = 0, retries = 0, peak_used = 0;
+    uint32_t peak_inflight = 0;
+};
+
+namespace {
+
+uint64_t footprint(pdp_server *S, ServeRequest *r, uint64_t *plan_ws) {
+    uint64_t arena = 0, bws = 0;
+    if (pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, &arena, &bws) != PDP_OK) return 0;
+    pdp_plan_info info;
+    pdp_plan_info_get(r->plan, &info);
+    *plan_ws = info.ws_bytes;
+    const uint64_t A = 256;
+    uint64_t b = 0;
+    b += align_up(r->n_res + 1, A) + align_up(8 * (uint64_t(r->n_genes) + 1), A);  // genome
+    b += align_up(arena, A);                                                         // dictionary
+    b += align_up(std::max(bws, info.ws_bytes), A);                                  // build, then plan scratch
+    b += align_up(4 * (uint64_t(info.bh_rows) + 1), A) + 3 * align_up(4 * std::max<uint64_t>(r->bh_cap, 1), A);
+    b += align_up(4 * (uint64_t(info.bbh_rows) + 1), A) + 4 * align_up(4 * std::max<uint64_t>(r->bbh_cap, 1), A);
+    b += A;  // status
+    return b;
+}
+
+// Creates the request's plan from its (not yet built) dictionary descriptor.
+int32_t make_plan(pdp_server *S, ServeRequest *r) {
+    if (r->plan) pdp_plan_destroy(r->plan);
+    r->plan = nullptr;
+    std::vector<pdp_task> tasks(S->residents.size());
+    for (size_t i = 0; i < tasks.size(); ++i) tasks[i] = {&r->dict, &S->residents[i], PDP_TASK_BBH, 0};
+    pdp_params p = S->cfg.params;
+    p.inc_capacity = r->inc_cap;
+    return pdp_plan_create(tasks.data(), static_cast<uint32_t>(tasks.size()), &p, &r->plan);
+}
+
+// Everything a request enqueues on its slot's stream.
+int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t plan_ws) {
+    hipStream_t s = slot.stream;
+    char *base = S->arena_base + r->dev_off;
+    const uint64_t A = 256;
+    auto take = [&](uint64_t bytes) {
+        char *q = base;
+        base += align_up(bytes, A);
+        return q;
+    };
+    uint8_t *res = reinterpret_cast<uint8_t *>(take(r->n_res + 1));
+    uint64_t *off = reinterpret_cast<uint64_t *>(take(8 * (uint64_t(r->n_genes) + 1)));
+    uint64_t arena = 0, bws = 0;
+    pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, &arena, &bws);
+    void *dict_mem = take(arena);
+    void *scratch = take(std::max(bws, plan_ws));
+    const uint64_t scratch_bytes = std::max(bws, plan_ws);
+    pdp_plan_info info;
+    pdp_plan_info_get(r->plan, &info);
+    r->bh.n_rows = info.bh_rows;
+    r->bh.capacity = r->bh_cap;
+    r->bh.ptr = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(info.bh_rows) + 1)));
+    r->bh.col = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(r->bh_cap, 1)));
+    r->bh.num = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(r->bh_cap, 1)));
+    r->bh.den = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(r->bh_cap, 1)));
+    r->bbh.n_rows = info.bbh_rows;
+    r->bbh.capacity = r->bbh_cap;
+    r->bbh.ptr = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(info.bbh_rows) + 1)));
+    r->bbh.a = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(r->bbh_cap, 1)));
+    r->bbh.b = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(r->bbh_cap, 1)));
+    r->bbh.num = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(r->bbh_cap, 1)));
+    r->bbh.den = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(r->bbh_cap, 1)));
+    r->status = reinterpret_cast<pdp_status *>(take(sizeof(pdp_status)));
+    // The dictionary descriptor must point at this allocation before the plan copies it.
+    int32_t rc = pdp_dict_bind(dict_mem, arena, r->n_genes, r->n_res, S->cfg.k, &r->dict);
+    if (rc) return rc;
+    rc = make_plan(S, r);
+    if (rc) return rc;
+    // host input -> pinned staging -> device; pinned output staging sized for the results
+    const uint64_t in_bytes = r->n_res + 8 * (uint64_t(r->n_genes) + 1);
+    const uint64_t out_bytes = sizeof(pdp_status) + 4 * (uint64_t(info.bh_rows) + 1 + 3 * r->bh_cap) +
+                               4 * (uint64_t(info.bbh_rows) + 1 + 4 * r->bbh_cap);
+    if (!slot.pin.ensure(std::max(in_bytes, out_bytes) + 64)) return PDP_E_HIP;
+    std::memcpy(slot.pin.p, r->res.data(), r->n_res);
+    std::memcpy(static_cast<char *>(slot.pin.p) + r->n_res, r->off.data(), 8 * (uint64_t(r->n_genes) + 1));
+    if (hipMemcpyAsync(res, slot.pin.p, r->n_res, hipMemcpyHostToDevice, s) != hipSuccess) return PDP_E_HIP;
+    if (hipMemcpyAsync(off, static_cast<char *>(slot.pin.p) + r->n_res, 8 * (uint64_t(r->n_genes) + 1),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+        return PDP_E_HIP;
+    pdp_genome g{res, off, r->n_genes, 0, r->n_res};
+    rc = pdp_dict_build(&g, &r->dict, scratch, scratch_bytes, s);
+    if (rc) return rc;
+    rc = pdp_plan_upload(r->plan, scratch, scratch_bytes, s);
+    if (rc) return rc;
+    rc = pdp_plan_launch(r->plan, &r->bh, &r->bbh, r->status, scratch, scratch_bytes, s);
+    if (rc) return rc;
+    // results back; the pinned buffer is reused for output once the input copies are ordered before
+    char *h = static_cast<char *>(slot.pin.p);
+    auto d2h = [&](const void *src, uint64_t bytes) {
+        if (hipMemcpyAsync(h, src, bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+        h += bytes;
+        return true;
+    };
+    bool ok = d2h(r->status, sizeof(pdp_status)) && d2h(r->dict.status, sizeof(pdp_status)) &&
+              d2h(r->bh.ptr, 4 * (uint64_t(info.bh_rows) + 1)) && d2h(r->bh.col, 4 * r->bh_cap) &&
+              d2h(r->bh.num, 4 * r->bh_cap) && d2h(r->bh.den, 4 * r->bh_cap) &&
+              d2h(r->bbh.ptr, 4 * (uint64_t(info.bbh_rows) + 1)) && d2h(r->bbh.a, 4 * r->bbh_cap) &&
+              d2h(r->bbh.b, 4 * r->bbh_cap) && d2h(r->bbh.num, 4 * r->bbh_cap) && d2h(r->bbh.den, 4 * r->bbh_cap);
+    if (!ok) return PDP_E_HIP;
+    if (hipEventRecord(slot.done, s) != hipSuccess) return PDP_E_HIP;
+    return PDP_OK;
+}
+
+// Unpacks the pinned results of a finished slot; true if the request is done (else it is retried).
+bool collect(pdp_server *S, ServeSlot &slot, ServeRequest *r) {
+    pdp_plan_info info;
+    pdp_plan_info_get(r->plan, &info);
+    const char *h = static_cast<const char *>(slot.pin.p);
+    pdp_status st, dst;
+    std::memcpy(&st, h, sizeof(st));
+    h += sizeof(st);
+    std::memcpy(&dst, h, sizeof(dst));
+    h += sizeof(dst);
+    if (dst.code != PDP_OK) {
+        r->hstatus = dst;
+        r->code = dst.code;
+        return true;
+    }
+    if (st.code == PDP_E_CAPACITY && r->attempts < 4) {
+        // grow the array that overflowed and run the request again
+        const uint64_t grow = st.needed + st.needed / 4 + 1024;
+        if (st.where == 0) r->inc_cap = grow;
+        else if (st.where == 1) r->bh_cap = grow;
+        else r->bbh_cap = grow;
+        S->retries++;
+        return false;
+    }
+    r->hstatus = st;
+    r->code = st.code;
+    if (st.code != PDP_OK) return true;
+    auto take = [&](std::vector<uint32_t> &v, uint64_t n, uint64_t stride) {
+        v.assign(reinterpret_cast<const uint32_t *>(h), reinterpret_cast<const uint32_t *>(h) + n);
+        h += 4 * stride;
+    };
+    take(r->bh_ptr, uint64_t(info.bh_rows) + 1, uint64_t(info.bh_rows) + 1);
+    const uint64_t nbh = r->bh_ptr.back();
+    take(r->bh_col, nbh, r->bh_cap);
+    take(r->bh_num, nbh, r->bh_cap);
+    take(r->bh_den, nbh, r->bh_cap);
+    take(r->bbh_ptr, uint64_t(info.bbh_rows) + 1, uint64_t(info.bbh_rows) + 1);
+    const uint64_t nbb = r->bbh_ptr.back();
+    take(r->bbh_a, nbb, r->bbh_cap);
+    take(r->bbh_b, nbb, r->bbh_cap);
+    take(r->bbh_num, nbb, r->bbh_cap);
+    take(r->bbh_den, nbb, r->bbh_cap);
+    const uint32_t nt = static_cast<uint32_t>(S->residents.size());
+    r->ab_row.resize(nt);
+    r->ba_row.resize(nt);
+    r->bbh_row.resize(nt);
+    for (uint32_t t = 0; t < nt; ++t) pdp_plan_rows(r->plan, t, &r->ab_row[t], &r->ba_row[t], &r->bbh_row[t]);
+    return true;
+}
+
+void finish(pdp_server *S, ServeRequest *r) {
+    r->t_done = now_us(S->t0);
+    r->res.clear();
+    r->res.shrink_to_fit();
+    r->off.clear();
+    r->off.shrink_to_fit();
+    if (r->plan) pdp_plan_destroy(r->plan);
+    r->plan = nullptr;
+    S->finished.push_back(r->tag);
+    S->completed++;
+}
+
+void worker_loop(pdp_server *S) {
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (!S->stop) {
+        bool progress = false;
+        // retire finished slots
+        for (ServeSlot &slot : S->slots) {
+            if (!slot.req) continue;
+            const hipError_t q = hipEventQuery(slot.done);
+            if (q == hipErrorNotReady) continue;
+            ServeRequest *r = slot.req;
+            progress = true;
+            bool done = true;
+            if (q != hipSuccess) {
+                r->code = PDP_E_HIP;
+                S->fatal = PDP_E_HIP;
+            } else {
+                done = collect(S, slot, r);
+            }
+            S->arena->release(r->dev_off, r->dev_bytes);
+            slot.req = nullptr;
+            if (done) finish(S, r);
+            else S->pending.push_front(r);  // retried ahead of newer requests
+        }
+        // admit waiting requests in arrival order
+        while (!S->pending.empty()) {
+            ServeSlot *free_slot = nullptr;
+            for (ServeSlot &slot : S->slots)
+                if (!slot.req) {
+                    free_slot = &slot;
+                    break;
+                }
+            if (!free_slot) break;
+            ServeRequest *r = S->pending.front();
+            r->attempts++;
+            // A provisional plan gives the footprint: the descriptor is bound to a placeholder
+            // address (planning reads only its sizes); the final plan is made once the memory is placed.
+            uint64_t plan_ws = 0, bytes = 0, dict_bytes = 0, build_ws = 0;
+            int32_t rc = pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, &dict_bytes, &build_ws);
+            if (rc == PDP_OK)
+                rc = pdp_dict_bind(reinterpret_cast<void *>(uintptr_t(256)), dict_bytes, r->n_genes, r->n_res, S->cfg.k,
+                                   &r->dict);
+            if (rc == PDP_OK) rc = make_plan(S, r);
+            if (rc == PDP_OK) bytes = footprint(S, r, &plan_ws);
+            if (rc != PDP_OK || bytes == 0 || bytes > S->arena->size()) {
+                S->pending.pop_front();
+                r->code = rc != PDP_OK ? rc : PDP_E_BUDGET;
+                finish(S, r);
+                progress = true;
+                continue;
+            }
+            uint64_t off = 0;
+            if (!S->arena->alloc(bytes, &off)) break;  // wait for memory to free up
+            S->pending.pop_front();
+            r->dev_off = off;
+            r->dev_bytes = bytes;
+            if (r->attempts == 1) r->t_admit = now_us(S->t0);
+            rc = launch_request(S, *free_slot, r, plan_ws);
+            if (rc != PDP_OK) {
+                (void)hipStreamSynchronize(free_slot->stream);
+                S->arena->release(off, bytes);
+                r->code = rc;
+                finish(S, r);
+            } else {
+                free_slot->req = r;
+                S->admitted++;
+            }
+            progress = true;
+            S->peak_used = std::max(S->peak_used, S->arena->used());
+            uint32_t inflight = 0;
+            for (ServeSlot &slot : S->slots) inflight += slot.req != nullptr;
+            S->peak_inflight = std::max(S->peak_inflight, inflight);
+        }
+        if (progress) {
+            S->cv.notify_all();
+            continue;
+        }
+        bool busy = false;
+        for (ServeSlot &slot : S->slots) busy = busy || slot.req != nullptr;
+        // poll completions quickly while work is in flight; sleep until a submit otherwise
+        if (busy) {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        } else {
+            S->cv.wait_for(lk, std::chrono::milliseconds(5));
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pdp_server_create(const pdp_server_config *cfg, const pdp_dict *const *residents, uint32_t n_residents,
+                          void *arena, uint64_t arena_bytes, pdp_server **out) {
+    if (!cfg || !out || !arena || (n_residents && !residents)) return api_fail(PDP_E_INVAL, "pdp_server_create: null argument");
+    *out = nullptr;
+    if (n_residents == 0) return api_fail(PDP_E_INVAL, "pdp_server_create: no resident genomes");
+    if (cfg->slots == 0 || cfg->slots > 64) return api_fail(PDP_E_INVAL, "pdp_server_create: slots must be 1..64");
+    if (cfg->budget_bytes > arena_bytes) return api_fail(PDP_E_WORKSPACE, "budget larger than the arena");
+    if (reinterpret_cast<uintptr_t>(arena) % 256) return api_fail(PDP_E_INVAL, "arena not 256-byte aligned");
+    for (uint32_t i = 0; i < n_residents; ++i) {
+        if (!residents[i] || residents[i]->k != cfg->k)
+            return api_fail(PDP_E_INVAL, "resident %u: missing or built with another k", i);
+    }
+    auto S = std::make_unique<pdp_server>();
+    S->cfg = *cfg;
+    if (hipGetDevice(&S->device) != hipSuccess) return api_fail(PDP_E_HIP, "hipGetDevice");
+    for (uint32_t i = 0; i < n_residents; ++i) S->residents.push_back(*residents[i]);
+    S->arena_base = static_cast<char *>(arena);
+    S->arena = std::make_unique<Arena>(cfg->budget_bytes);
+    S->slots.resize(cfg->slots);
+    for (ServeSlot &slot : S->slots) {
+        if (hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) != hipSuccess)
+            return api_fail(PDP_E_HIP, "pdp_server_create: stream or event creation failed");
+    }
+    S->t0 = std::chrono::steady_clock::now();
+    pdp_server *raw = S.release();
+    raw->worker = std::thread(worker_loop, raw);
+    *out = raw;
+    return PDP_OK;
+}
+
+int32_t pdp_server_submit(pdp_server *S, const uint8_t *residues, const uint64_t *gene_off, uint32_t n_genes,
+                          uint64_t tag) {
+    if (!S || !gene_off || (!residues && gene_off[n_genes])) return api_fail(PDP_E_INVAL, "pdp_server_submit: null argument");
+    if (gene_off[0] != 0) return api_fail(PDP_E_INVAL, "pdp_server_submit: gene_off[0] must be 0");
+    for (uint32_t i = 0; i < n_genes; ++i)
+        if (gene_off[i + 1] < gene_off[i]) return api_fail(PDP_E_INVAL, "pdp_server_submit: offsets decrease at gene %u", i);
+    auto r = std::make_unique<ServeRequest>();
+    r->tag = tag;
+    r->n_genes = n_genes;
+    r->n_res = gene_off[n_genes];
+    if (r->n_res >= (1ull << 32) || n_genes > PDP_MAX_GENES) return api_fail(PDP_E_LIMIT, "pdp_server_submit: genome too large");
+    r->res.assign(residues, residues + r->n_res);
+    r->off.assign(gene_off, gene_off + n_genes + 1);
+    // starting capacities; a capacity error grows them and runs the request again
+    uint64_t resident_entries = 0, resident_genes = 0;
+    for (const pdp_dict &d : S->residents) {
+        resident_entries += d.capacity;
+        resident_genes += d.n_genes;
+    }
+    r->inc_cap = (resident_entries + S->residents.size() * (r->n_res + 1)) / 20 + 65536;
+    const uint64_t rows = uint64_t(n_genes) * S->residents.size() + resident_genes;
+    r->bh_cap = rows + rows / 4 + 4096;
+    r->bbh_cap = uint64_t(n_genes) * S->residents.size() * 3 / 4 + 4096;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->all.count(tag)) return api_fail(PDP_E_INVAL, "pdp_server_submit: tag already in use");
+    r->t_submit = now_us(S->t0);
+    S->pending.push_back(r.get());
+    S->all[tag] = std::move(r);
+    S->cv.notify_all();
+    return PDP_OK;
+}
+
+int32_t pdp_server_poll(pdp_server *S, pdp_request_done *done, uint32_t max, uint32_t *n_done, uint32_t wait_us) {
+    if (!S || !n_done || (max && !done)) return api_fail(PDP_E_INVAL, "pdp_server_poll: null argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (S->finished.empty() && wait_us)
+        S->cv.wait_for(lk, std::chrono::microseconds(wait_us), [&] { return !S->finished.empty(); });
+    uint32_t n = 0;
+    while (n < max && !S->finished.empty()) {
+        const uint64_t tag = S->finished.front();
+        S->finished.pop_front();
+        ServeRequest *r = S->all[tag].get();
+        pdp_request_done &d = done[n++];
+        std::memset(&d, 0, sizeof(d));
+        d.tag = tag;
+        d.code = r->code;
+        d.n_genes = r->n_genes;
+        d.attempts = r->attempts;
+        d.submit_us = r->t_submit;
+        d.admit_us = r->t_admit;
+        d.done_us = r->t_done;
+        d.bh_entries = r->bh_ptr.empty() ? 0 : r->bh_ptr.back();
+        d.bbh_pairs = r->bbh_ptr.empty() ? 0 : r->bbh_ptr.back();
+    }
+    *n_done = n;
+    return S->fatal;
+}
+
+int32_t pdp_server_fetch(pdp_server *S, uint64_t tag, pdp_request_result *out) {
+    if (!S || !out) return api_fail(PDP_E_INVAL, "pdp_server_fetch: null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->all.find(tag);
+    if (it == S->all.end() || it->second->t_done == 0) return api_fail(PDP_E_INVAL, "pdp_server_fetch: unknown or unfinished tag");
+    ServeRequest *r = it->second.get();
+    std::memset(out, 0, sizeof(*out));
+    out->code = r->code;
+    out->status = r->hstatus;
+    out->n_residents = static_cast<uint32_t>(S->residents.size());
+    if (r->code != PDP_OK) return PDP_OK;
+    out->bh_rows = static_cast<uint32_t>(r->bh_ptr.size() - 1);
+    out->bbh_rows = static_cast<uint32_t>(r->bbh_ptr.size() - 1);
+    out->ab_row = r->ab_row.data();
+    out->ba_row = r->ba_row.data();
+    out->bbh_row = r->bbh_row.data();
+    out->bh_ptr = r->bh_ptr.data();
+    out->bh_col = r->bh_col.data();
+    out->bh_num = r->bh_num.data();
+    out->bh_den = r->bh_den.data();
+    out->bbh_ptr = r->bbh_ptr.data();
+    out->bbh_a = r->bbh_a.data();
+    out->bbh_b = r->bbh_b.data();
+    out->bbh_num = r->bbh_num.data();
+    out->bbh_den = r->bbh_den.data();
+    return PDP_OK;
+}
+
+int32_t pdp_server_release(pdp_server *S, uint64_t tag) {
+    if (!S) return api_fail(PDP_E_INVAL, "pdp_server_release: null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->all.find(tag);
+    if (it == S->all.end() || it->second->t_done == 0) return api_fail(PDP_E_INVAL, "pdp_server_release: unknown or unfinished tag");
+    S->all.erase(it);
+    return PDP_OK;
+}
+
+int32_t pdp_server_stats_get(pdp_server *S, pdp_server_stats *out) {
+    if (!S || !out) return api_fail(PDP_E_INVAL, "pdp_server_stats_get: null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->admitted = S->admitted;
+    out->completed = S->completed;
+    out->retries = S->retries;
+    out->pending = S->pending.size();
+    out->budget_bytes = S->arena->size();
+    out->used_bytes = S->arena->used();
+    out->peak_used_bytes = S->peak_used;
+    out->peak_inflight = S->peak_inflight;
+    for (const ServeSlot &slot : S->slots) out->inflight += slot.req != nullptr;
+    return PDP_OK;
+}
+
+void pdp_server_destroy(pdp_server *S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    for (ServeSlot &slot : S->slots) {
+        if (slot.stream) (void)hipStreamSynchronize(slot.stream);
+        if (slot.req && slot.req->plan) pdp_plan_destroy(slot.req->plan);
+        if (slot.done) (void)hipEventDestroy(slot.done);
+        if (slot.stream) (void)hipStreamDestroy(slot.stream);
+    }
+    for (auto &kv : S->all)
+        if (kv.second->plan) pdp_plan_destroy(kv.second->plan);
+    delete S;
+}
+
+}  // extern "C"

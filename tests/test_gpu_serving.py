@@ -1,0 +1,101 @@
+"""GPU tests of the serving runtime: results equal the oracle, each request's results are
+identical alone and in a concurrent mix, and the HBM budget is enforced."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import check_bbh, check_bh
+from synth import serving_workload
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU collection
+    pytest.skip("needs the GPU", allow_module_level=True)
+
+import paper_2510_23679_amd as pdp  # noqa: E402
+
+K = 5
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def workload():
+    wl = serving_workload(n_residents=4, resident_genes=200, n_arrivals=6, arrive_lo=80, arrive_hi=300)
+    residents = [pdp.Dictionary.build_from(g, K) for g in wl.residents.genomes]
+    for d in residents:
+        d.check_status()
+    arrivals = [wl.arrival(j) for j in range(6)]
+    return wl, residents, arrivals
+
+
+def run_server(residents, arrivals, slots, budget=1 << 30, one_at_a_time=False):
+    srv = pdp.Server(residents, budget, slots=slots)
+    out = {}
+    try:
+        if one_at_a_time:
+            for j, g in enumerate(arrivals):
+                srv.submit(g, j)
+                done = []
+                while not done:
+                    done = srv.poll(8, wait_us=200000)
+                for d in done:
+                    out[d.tag] = (d, srv.fetch(d.tag))
+                    srv.release(d.tag)
+        else:
+            for j, g in enumerate(arrivals):
+                srv.submit(g, j)
+            while len(out) < len(arrivals):
+                for d in srv.poll(8, wait_us=200000):
+                    out[d.tag] = (d, srv.fetch(d.tag))
+                    srv.release(d.tag)
+        stats = srv.stats()
+    finally:
+        srv.close()
+    return out, stats
+
+
+def test_served_results_match_oracle(workload):
+    wl, residents, arrivals = workload
+    say("serving: 6 requests x 4 residents, 3 slots")
+    out, stats = run_server(residents, arrivals, slots=3)
+    assert stats.completed == 6 and stats.peak_inflight >= 2
+    og_res = [oracle.OracleGenome(g, K) for g in wl.residents.genomes]
+    for j, g in enumerate(arrivals):
+        d, res = out[j]
+        assert d.code == 0 and res.code == 0
+        q = oracle.OracleGenome(g, K)
+        for r, og in enumerate(og_res):
+            ab, ba = oracle.bh(q, og), oracle.bh(og, q)
+            check_bh(res.best_hits(r, 0), ab)
+            check_bh(res.best_hits(r, 1), ba)
+            check_bbh(res.bbh_pairs(r), oracle.bbh(ab, ba))
+
+
+def test_alone_equals_mix(workload):
+    _, residents, arrivals = workload
+    say("serving: each request alone vs all in a mix")
+    alone, _ = run_server(residents, arrivals, slots=1, one_at_a_time=True)
+    mixed, stats = run_server(residents, arrivals, slots=4)
+    assert stats.peak_inflight >= 2
+    for j in range(len(arrivals)):
+        a, m = alone[j][1], mixed[j][1]
+        for x, y in zip(a.bh + a.bbh, m.bh + m.bbh):
+            assert np.array_equal(x, y), f"request {j}"
+
+
+def test_budget_rejects_oversized_request(workload):
+    _, residents, arrivals = workload
+    say("serving: budget too small for any request")
+    srv = pdp.Server(residents, 1 << 20, slots=2)
+    try:
+        srv.submit(arrivals[0], 7)
+        done = []
+        while not done:
+            done = srv.poll(4, wait_us=200000)
+        assert done[0].tag == 7 and done[0].code == pdp.PDP_E_BUDGET
+    finally:
+        srv.close()
