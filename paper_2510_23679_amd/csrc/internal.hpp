@@ -115,6 +115,8 @@ struct PairWs {
     uint32_t *overflow_count;     // counters word 2
     uint32_t *next_join;          // counters word 3: next item of the persistent join
     uint32_t *next_tile;          // counters word 4: next tile of the persistent tile pass
+    uint32_t *next_join_write;    // counters word 5: next item of the persistent join's write pass
+    uint32_t *chunk_cnt;          // join items + 1: incidences per item, scanned into offsets
     uint32_t *order;              // task table indices in the caller's order
     uint32_t *partials;
 };

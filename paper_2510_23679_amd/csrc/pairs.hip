@@ -41,11 +41,26 @@ __device__ __forceinline__ uint32_t find_task(const DevTask *tasks, uint32_t n_t
     return lo;
 }
 
-template <bool STAGED>
-__device__ __forceinline__ void join_range(const DevTask &T, uint32_t task, uint32_t a0, uint32_t a1, const uint64_t *bc,
-                                           const uint32_t *bg, const uint32_t *bn, uint32_t nbe, uint4 *inc, uint64_t inc_cap,
-                                           unsigned long long *inc_count) {
+struct JoinLds {
+    uint64_t code[kJoinLdsCap];
+    uint32_t gene[kJoinLdsCap];
+    uint32_t cnt[kJoinLdsCap];
+    uint32_t scan[kJoinThreads / kWave + 1];
+    uint32_t task;
+    uint32_t next;
+};
+
+// Query entries [a0, a1) of genome a against the target entries of the same bucket
+// range (bc/bg/bn, nbe entries sorted by code): a binary search per query entry.
+// WRITE = false returns the number of incidences; WRITE = true writes them from
+// out_base on in a fixed order (blocks of kJoinThreads query entries, thread order
+// within a block), so positions need no atomics.  Contains barriers.
+template <bool WRITE>
+__device__ __forceinline__ uint32_t join_range(const DevTask &T, uint32_t task, uint32_t a0, uint32_t a1,
+                                               const uint64_t *bc, const uint32_t *bg, const uint32_t *bn, uint32_t nbe,
+                                               uint4 *inc, uint64_t out_base, uint64_t inc_cap, uint32_t *scan_tmp) {
     const uint64_t *ac = T.a.ix_code;
+    uint32_t done = 0;
     for (uint32_t base = a0; base < a1; base += kJoinThreads) {
         const uint32_t i = base + threadIdx.x;
         const bool valid = i < a1;
@@ -59,32 +74,27 @@ __device__ __forceinline__ void join_range(const DevTask &T, uint32_t task, uint
         uint32_t m = 0;
         if (valid)
             while (lo + m < nbe && bc[lo + m] == code) ++m;
-        const unsigned long long slot = wave_reserve(m, inc_count);
-        if (m) {
+        uint32_t total;
+        const uint32_t before = block_exclusive_scan<kJoinThreads>(m, scan_tmp, &total);
+        if (WRITE && m) {
             const uint32_t ag = T.a.ix_gene[i], an = T.a.ix_cnt[i];
+            const uint64_t slot = out_base + done + before;
             for (uint32_t t = 0; t < m; ++t) {
-                if (slot + t < inc_cap) {
-                    const uint32_t v = min(an, bn[lo + t]);
-                    inc[slot + t] = make_uint4(task, ag, bg[lo + t], v);
-                }
+                if (slot + t < inc_cap) inc[slot + t] = make_uint4(task, ag, bg[lo + t], min(an, bn[lo + t]));
             }
         }
+        done += total;
     }
+    return done;
 }
 
-struct JoinLds {
-    uint64_t code[kJoinLdsCap];
-    uint32_t gene[kJoinLdsCap];
-    uint32_t cnt[kJoinLdsCap];
-    uint32_t task;
-    uint32_t next;
-};
-
-// One join work item: a range of leading-residue buckets of one task.  Ends with a
-// barrier so the LDS can take the next item.
+// One join item: a range of leading-residue buckets of one task.  Pass WRITE = false
+// stores the item's incidence count in cnt[chunk]; WRITE = true writes the incidences
+// at the scanned offset off[chunk].  Ends with a barrier so the LDS can take the next item.
+template <bool WRITE>
 __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__restrict__ tasks, uint32_t n_tasks,
-                                           uint4 *__restrict__ inc, uint64_t inc_cap,
-                                           unsigned long long *__restrict__ inc_count, JoinLds &L) {
+                                           uint32_t *__restrict__ chunk_cnt, uint4 *__restrict__ inc, uint64_t inc_cap,
+                                           JoinLds &L) {
     if (threadIdx.x == 0) L.task = find_task(tasks, n_tasks, chunk);
     __syncthreads();
     const uint32_t task = L.task;
@@ -95,6 +105,8 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
     const uint32_t bh = min(nb, bl + T.bpw);
     const uint32_t a0 = T.a.ix_dir[bl], a1 = T.a.ix_dir[bh];
     const uint32_t b0 = T.b.ix_dir[bl], b1 = T.b.ix_dir[bh];
+    uint32_t n = 0;
+    const uint64_t out_base = WRITE ? chunk_cnt[chunk] : 0;
     if (a0 != a1 && b0 != b1) {
         const uint32_t nbe = b1 - b0;
         if (nbe <= kJoinLdsCap) {
@@ -104,46 +116,53 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
                 L.cnt[i] = T.b.ix_cnt[b0 + i];
             }
             __syncthreads();
-            join_range<true>(T, task, a0, a1, L.code, L.gene, L.cnt, nbe, inc, inc_cap, inc_count);
+            n = join_range<WRITE>(T, task, a0, a1, L.code, L.gene, L.cnt, nbe, inc, out_base, inc_cap, L.scan);
         } else {
-            join_range<false>(T, task, a0, a1, T.b.ix_code + b0, T.b.ix_gene + b0, T.b.ix_cnt + b0, nbe, inc, inc_cap,
-                              inc_count);
+            n = join_range<WRITE>(T, task, a0, a1, T.b.ix_code + b0, T.b.ix_gene + b0, T.b.ix_cnt + b0, nbe, inc,
+                                  out_base, inc_cap, L.scan);
         }
     }
+    if (!WRITE && threadIdx.x == 0) chunk_cnt[chunk] = n;
     __syncthreads();
 }
 
+template <bool WRITE>
 __global__ __launch_bounds__(kJoinThreads) void k_join(const DevTask *__restrict__ tasks, uint32_t n_tasks,
-                                                       uint4 *__restrict__ inc, uint64_t inc_cap,
-                                                       unsigned long long *__restrict__ inc_count) {
+                                                       uint32_t *__restrict__ chunk_cnt, uint4 *__restrict__ inc,
+                                                       uint64_t inc_cap) {
     __shared__ JoinLds L;
-    join_chunk(blockIdx.x, tasks, n_tasks, inc, inc_cap, inc_count, L);
+    join_chunk<WRITE>(blockIdx.x, tasks, n_tasks, chunk_cnt, inc, inc_cap, L);
 }
 
-// Persistent form: a fixed grid pulls join items from a counter until none are left.
+// Persistent form: a fixed grid claims join items kClaim at a time from a counter
+// (one atomic per claim, not per item) until none are left.
+constexpr uint32_t kClaim = 8;
+
+template <bool WRITE>
 __global__ __launch_bounds__(kJoinThreads) void k_join_persistent(const DevTask *__restrict__ tasks, uint32_t n_tasks,
-                                                                  uint32_t total_chunks, uint4 *__restrict__ inc,
-                                                                  uint64_t inc_cap,
-                                                                  unsigned long long *__restrict__ inc_count,
+                                                                  uint32_t total_chunks, uint32_t *__restrict__ chunk_cnt,
+                                                                  uint4 *__restrict__ inc, uint64_t inc_cap,
                                                                   uint32_t *__restrict__ next) {
     __shared__ JoinLds L;
     for (;;) {
-        if (threadIdx.x == 0) L.next = atomicAdd(next, 1u);
+        if (threadIdx.x == 0) L.next = atomicAdd(next, kClaim);
         __syncthreads();
-        const uint32_t chunk = L.next;
+        const uint32_t first = L.next;
         __syncthreads();
-        if (chunk >= total_chunks) break;
-        join_chunk(chunk, tasks, n_tasks, inc, inc_cap, inc_count, L);
+        if (first >= total_chunks) break;
+        const uint32_t last = min(total_chunks, first + kClaim);
+        for (uint32_t chunk = first; chunk < last; ++chunk)
+            join_chunk<WRITE>(chunk, tasks, n_tasks, chunk_cnt, inc, inc_cap, L);
     }
 }
 
 template <bool SCATTER>
 __global__ __launch_bounds__(256) void k_inc_bucket(const DevTask *__restrict__ tasks, const uint4 *__restrict__ inc,
-                                                    const unsigned long long *__restrict__ inc_count, uint64_t inc_cap,
+                                                    const uint32_t *__restrict__ inc_total, uint64_t inc_cap,
                                                     uint32_t *__restrict__ tile_cnt, const uint32_t *__restrict__ tile_off,
                                                     uint32_t *__restrict__ tile_fill, uint2 *__restrict__ recs,
                                                     pdp_status *st) {
-    const unsigned long long total = *inc_count;
+    const uint64_t total = *inc_total;
     if (!SCATTER && blockIdx.x == 0 && threadIdx.x == 0 && total > inc_cap) raise_status(st, PDP_E_CAPACITY, total, 0);
     const uint64_t n = total < inc_cap ? total : inc_cap;
     for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
@@ -320,13 +339,15 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count_persistent(
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_flag, s_next;
     for (;;) {
-        if (threadIdx.x == 0) s_next = atomicAdd(next, 1u);
+        if (threadIdx.x == 0) s_next = atomicAdd(next, kClaim);
         __syncthreads();
-        const uint32_t t = s_next;
+        const uint32_t first = s_next;
         __syncthreads();
-        if (t >= total_tiles) break;
-        tile_process<false>(t, tasks, tiles, tile_off, recs, bh_ptr, slab, nullptr, nullptr, nullptr, 0, overflow_tiles,
-                            overflow_count, lds, &s_flag);
+        if (first >= total_tiles) break;
+        const uint32_t last = min(total_tiles, first + kClaim);
+        for (uint32_t t = first; t < last; ++t)
+            tile_process<false>(t, tasks, tiles, tile_off, recs, bh_ptr, slab, nullptr, nullptr, nullptr, 0,
+                                overflow_tiles, overflow_count, lds, &s_flag);
     }
 }
 
@@ -460,7 +481,7 @@ static uint32_t device_cus() {
 
 uint32_t persistent_join_grid() {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_join_persistent, kJoinThreads, 0) != hipSuccess || per < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_join_persistent<true>, kJoinThreads, 0) != hipSuccess || per < 1)
         per = 1;
     return device_cus() * static_cast<uint32_t>(per);
 }
@@ -491,13 +512,15 @@ uint64_t pair_ws_bytes(const PlanShape &p) {
     s += align_up(sizeof(DevTile) * std::max<uint64_t>(p.total_tiles, 1), A);
     s += align_up(4 * std::max<uint64_t>(p.n_tasks, 1), A);
     s += align_up(16 * std::max<uint64_t>(p.inc_cap, 1), A);
-    s += align_up(16, A);
+    s += align_up(32, A);
+    s += align_up(4 * (uint64_t(p.total_chunks) + 1), A);
     s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
     s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
     s += align_up(8 * 2 * std::max<uint64_t>(p.inc_cap, 1), A);
     s += align_up(16 * kSlab * (uint64_t(p.bh_rows) + 1), A);
     s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
-    const uint64_t np = std::max({scan_partials(p.total_tiles), scan_partials(p.bh_rows), scan_partials(p.bbh_rows)});
+    const uint64_t np = std::max({scan_partials(p.total_tiles), scan_partials(p.bh_rows), scan_partials(p.bbh_rows),
+                                  scan_partials(p.total_chunks)});
     s += align_up(4 * np, A);
     return s;
 }
@@ -519,12 +542,15 @@ PairWs pair_ws_carve(void *ws, const PlanShape &p) {
     w.overflow_count = reinterpret_cast<uint32_t *>(w.counters) + 2;
     w.next_join = reinterpret_cast<uint32_t *>(w.counters) + 3;
     w.next_tile = reinterpret_cast<uint32_t *>(w.counters) + 4;
+    w.next_join_write = reinterpret_cast<uint32_t *>(w.counters) + 5;
+    w.chunk_cnt = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_chunks) + 1)));
     w.tile_cnt = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
     w.tile_fill = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
     w.recs = reinterpret_cast<uint2 *>(take(8 * 2 * std::max<uint64_t>(p.inc_cap, 1)));
     w.slab = reinterpret_cast<uint4 *>(take(16 * kSlab * (uint64_t(p.bh_rows) + 1)));
     w.overflow_tiles = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
-    const uint64_t np = std::max({scan_partials(p.total_tiles), scan_partials(p.bh_rows), scan_partials(p.bbh_rows)});
+    const uint64_t np = std::max({scan_partials(p.total_tiles), scan_partials(p.bh_rows), scan_partials(p.bbh_rows),
+                                  scan_partials(p.total_chunks)});
     w.partials = reinterpret_cast<uint32_t *>(take(4 * np));
     return w;
 }
@@ -537,33 +563,46 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     };
     PDP_TRY(mark(PDP_KERNEL_ALL, true));
     PDP_TRY(launch_status_init(st, s));
-    // counters: incidences (64-bit), overflow tiles, next join item, next tile
+    // counters: (unused), overflow tiles, next join item (count pass), next tile, next join item (write pass)
     PDP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(w.counters), 8, 0u, s));
     PDP_TRY(launch_fill_u32(w.tile_cnt, uint64_t(p.total_tiles) + 1, 0u, s));
     PDP_TRY(launch_fill_u32(w.tile_fill, uint64_t(p.total_tiles) + 1, 0u, s));
+    const uint32_t *inc_total = w.chunk_cnt + p.total_chunks;  // after the scan: all incidences
     PDP_TRY(mark(PDP_KERNEL_JOIN, true));
     if (p.total_chunks && p.join_grid) {
-        hipLaunchKernelGGL(k_join_persistent, dim3(std::min(p.join_grid, p.total_chunks)), dim3(kJoinThreads), 0, s,
-                           w.tasks, p.n_tasks, p.total_chunks, w.inc, p.inc_cap, w.counters, w.next_join);
+        const dim3 g(std::min(p.join_grid, (p.total_chunks + kClaim - 1) / kClaim));
+        hipLaunchKernelGGL(k_join_persistent<false>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
+                           w.chunk_cnt, w.inc, p.inc_cap, w.next_join);
+        PDP_TRY(hipGetLastError());
+        PDP_TRY(launch_scan(w.chunk_cnt, w.chunk_cnt, p.total_chunks, w.partials, s));
+        hipLaunchKernelGGL(k_join_persistent<true>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
+                           w.chunk_cnt, w.inc, p.inc_cap, w.next_join_write);
         PDP_TRY(hipGetLastError());
     } else if (p.total_chunks) {
-        hipLaunchKernelGGL(k_join, dim3(p.total_chunks), dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.inc, p.inc_cap,
-                           w.counters);
+        hipLaunchKernelGGL(k_join<false>, dim3(p.total_chunks), dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.chunk_cnt,
+                           w.inc, p.inc_cap);
         PDP_TRY(hipGetLastError());
+        PDP_TRY(launch_scan(w.chunk_cnt, w.chunk_cnt, p.total_chunks, w.partials, s));
+        hipLaunchKernelGGL(k_join<true>, dim3(p.total_chunks), dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.chunk_cnt,
+                           w.inc, p.inc_cap);
+        PDP_TRY(hipGetLastError());
+    } else {
+        PDP_TRY(launch_fill_u32(w.chunk_cnt, 1, 0u, s));
     }
     PDP_TRY(mark(PDP_KERNEL_JOIN, false));
     PDP_TRY(mark(PDP_KERNEL_BUCKET, true));
-    hipLaunchKernelGGL(k_inc_bucket<false>, dim3(kBucketGroups), dim3(256), 0, s, w.tasks, w.inc, w.counters, p.inc_cap,
+    hipLaunchKernelGGL(k_inc_bucket<false>, dim3(kBucketGroups), dim3(256), 0, s, w.tasks, w.inc, inc_total, p.inc_cap,
                        w.tile_cnt, w.tile_cnt, w.tile_fill, w.recs, st);
     PDP_TRY(hipGetLastError());
     PDP_TRY(launch_scan(w.tile_cnt, w.tile_cnt, p.total_tiles, w.partials, s));
-    hipLaunchKernelGGL(k_inc_bucket<true>, dim3(kBucketGroups), dim3(256), 0, s, w.tasks, w.inc, w.counters, p.inc_cap,
+    hipLaunchKernelGGL(k_inc_bucket<true>, dim3(kBucketGroups), dim3(256), 0, s, w.tasks, w.inc, inc_total, p.inc_cap,
                        w.tile_cnt, w.tile_cnt, w.tile_fill, w.recs, st);
     PDP_TRY(hipGetLastError());
     PDP_TRY(mark(PDP_KERNEL_BUCKET, false));
     PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, true));
     if (p.total_tiles && p.tile_grid) {
-        hipLaunchKernelGGL(k_tile_count_persistent, dim3(std::min(p.tile_grid, p.total_tiles)), dim3(kTileThreads),
+        hipLaunchKernelGGL(k_tile_count_persistent, dim3(std::min(p.tile_grid, (p.total_tiles + kClaim - 1) / kClaim)),
+                           dim3(kTileThreads),
                            p.tile_lds, s, w.tasks, w.tiles, p.total_tiles, w.tile_cnt, w.recs, bh->ptr, w.slab,
                            w.overflow_tiles, w.overflow_count, w.next_tile);
         PDP_TRY(hipGetLastError());
