@@ -141,8 +141,7 @@ int32_t pdp_dict_size(uint32_t n_genes, uint64_t n_residues, uint32_t k, uint64_
     if (rc) return rc;
     if (arena_bytes) *arena_bytes = dict_arena_bytes(n_genes, n_residues, k);
     if (ws_bytes) {
-        BuildShape s{1, n_genes, n_buckets_for(k), n_residues + 1};
-        *ws_bytes = build_ws_bytes(s);
+        *ws_bytes = build_ws_bytes(single_build_shape(n_genes, n_residues, k));
     }
     return ok();
 }

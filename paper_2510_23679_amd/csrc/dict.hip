@@ -7,12 +7,14 @@
 //    Genes with more than kMvSortCap windows are queued for k_mv_long, which
 //    does the same with the codes in global memory.
 // 2. A scan of the distinct-k-mer counts of all genes gives the CSR offsets,
-//    and k_mv_compact packs the vectors while counting index entries per
-//    leading-residue bucket.
-// 3. A scan of the bucket counts gives every index directory; k_ix_scatter
-//    places each (code, gene, count) entry in its bucket and the bucket sorts
-//    order each bucket by (code, gene).  The result is each genome's inverted
-//    index: all entries ordered by k-mer code, ties by gene.
+//    and k_mv_compact packs the vectors (and notes each entry's gene).
+// 3. The inverted index (all entries ordered by k-mer code, ties by gene) is a
+//    two-level partition with no global atomics: the leading-residue buckets
+//    are grouped into coarse bins of 2^s buckets (s per genome, ~1K entries
+//    per bin); k_ix_hist counts bins per block of entries in LDS, a scan gives
+//    every (bin, block) its output range, k_ix_place drops the entries there
+//    (LDS cursors), and k_ix_sort_bin sorts each bin by (code, gene) in LDS
+//    and writes the bin's part of the bucket directory.
 // Genes and buckets of all genomes of a call are numbered consecutively; a
 // work-group finds its genome by binary search over the per-genome bases.
 #include <algorithm>
@@ -49,15 +51,6 @@ __device__ __forceinline__ uint32_t find_genome_by_gene(const DevBuild *t, uint3
     return lo;
 }
 
-__device__ __forceinline__ uint32_t find_genome_by_bucket(const DevBuild *t, uint32_t n, uint32_t b) {
-    uint32_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (t[mid].bucket_base <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
 
 __global__ void k_build_init(const DevBuild *table, uint32_t n) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -211,9 +204,10 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_long(const DevBuild *__restri
     }
 }
 
-// One wave per gene: CSR offset of the gene, its vector moved into place, bucket sizes counted.
+// One wave per gene: CSR offset of the gene, its vector moved into place, and the
+// gene of every entry noted for the index.
 __global__ __launch_bounds__(kWave) void k_mv_compact(const DevBuild *__restrict__ table, uint32_t n_genomes,
-                                                      const uint32_t *__restrict__ gptr, uint32_t *__restrict__ bcount) {
+                                                      const uint32_t *__restrict__ gptr, uint32_t *__restrict__ ent_gene) {
     __shared__ uint32_t s_t;
     const uint32_t G = blockIdx.x;
     if (threadIdx.x == 0) s_t = find_genome_by_gene(table, n_genomes, G);
@@ -228,12 +222,10 @@ __global__ __launch_bounds__(kWave) void k_mv_compact(const DevBuild *__restrict
         B.mv_ptr[g] = p;
         if (g + 1 == B.n_genes) B.mv_ptr[g + 1] = p + d;
     }
-    const uint32_t k = B.k, lead = B.lead;
     for (uint32_t e = threadIdx.x; e < d; e += kWave) {
-        const uint64_t c = B.slot_code[o + e];
-        B.mv_code[p + e] = c;
+        B.mv_code[p + e] = B.slot_code[o + e];
         B.mv_cnt[p + e] = B.slot_cnt[o + e];
-        atomicAdd(&bcount[B.bucket_base + bucket_of(c, k, lead)], 1u);
+        ent_gene[gptr[G] + e] = g;
     }
 }
 
@@ -243,76 +235,81 @@ __global__ void k_mv_empty(const DevBuild *table, uint32_t n) {
     if (t < n && table[t].n_genes == 0) table[t].mv_ptr[0] = 0;
 }
 
-// Every bucket of every genome: its directory entry (offset inside its genome).
-__global__ void k_dir_write(const DevBuild *__restrict__ table, uint32_t n_genomes, uint32_t total_buckets,
-                            const uint32_t *__restrict__ gdir) {
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= total_buckets) return;
-    const DevBuild &B = table[find_genome_by_bucket(table, n_genomes, b)];
-    const uint32_t lb = b - B.bucket_base;
-    const uint32_t base = gdir[B.bucket_base];
-    B.ix_dir[lb] = gdir[b] - base;
-    if (lb + 1 == B.nb) B.ix_dir[lb + 1] = gdir[b + 1] - base;
+__device__ __forceinline__ uint32_t find_genome_by_block(const DevBuild *t, uint32_t n, uint32_t blk) {
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (t[mid].blk_base <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
-// One wave per gene: drop each entry into its bucket (order inside a bucket is fixed later).
-__global__ __launch_bounds__(kWave) void k_ix_scatter(const DevBuild *__restrict__ table, uint32_t n_genomes,
-                                                      uint32_t *__restrict__ bfill) {
+__device__ __forceinline__ uint32_t find_genome_by_bin(const DevBuild *t, uint32_t n, uint32_t bin) {
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (t[mid].bin_base <= bin) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Entries [j*kIxBlock, ...) of genome t: genome-local range, clipped to the genome's entry count.
+__device__ __forceinline__ void block_range(const DevBuild &B, const uint32_t *gptr, uint32_t j, uint32_t *e0,
+                                            uint32_t *e1, uint32_t *gbase) {
+    const uint32_t base = gptr[B.gene_base];
+    const uint32_t E = gptr[B.gene_base + B.n_genes] - base;
+    *gbase = base;
+    *e0 = min(E, j * kIxBlock);
+    *e1 = min(E, (j + 1) * kIxBlock);
+}
+
+// One work-group per block of entries: coarse-bin histogram in LDS, written bin-major.
+__global__ __launch_bounds__(256) void k_ix_hist(const DevBuild *__restrict__ table, uint32_t n_genomes,
+                                                 const uint32_t *__restrict__ gptr, uint32_t *__restrict__ hist) {
+    extern __shared__ uint32_t h[];
     __shared__ uint32_t s_t;
-    const uint32_t G = blockIdx.x;
-    if (threadIdx.x == 0) s_t = find_genome_by_gene(table, n_genomes, G);
+    if (threadIdx.x == 0) s_t = find_genome_by_block(table, n_genomes, blockIdx.x);
     __syncthreads();
     const DevBuild &B = table[s_t];
-    const uint32_t g = G - B.gene_base;
-    const uint32_t p = B.mv_ptr[g];
-    const uint32_t d = B.mv_ptr[g + 1] - p;
-    const uint32_t k = B.k, lead = B.lead;
-    for (uint32_t e = threadIdx.x; e < d; e += kWave) {
-        const uint64_t c = B.mv_code[p + e];
-        const uint32_t b = bucket_of(c, k, lead);
-        const uint32_t pos = B.ix_dir[b] + atomicAdd(&bfill[B.bucket_base + b], 1u);
+    const uint32_t j = blockIdx.x - B.blk_base;
+    for (uint32_t i = threadIdx.x; i < B.nh; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    uint32_t e0, e1, gbase;
+    block_range(B, gptr, j, &e0, &e1, &gbase);
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+        atomicAdd(&h[bucket_of(B.mv_code[e], B.k, B.lead) >> B.hshift], 1u);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < B.nh; i += blockDim.x) hist[B.hist_base + i * B.nblk + j] = h[i];
+}
+
+// Same blocks: each entry goes to its bin's range (scanned histogram), position by LDS cursor.
+__global__ __launch_bounds__(256) void k_ix_place(const DevBuild *__restrict__ table, uint32_t n_genomes,
+                                                  const uint32_t *__restrict__ gptr, const uint32_t *__restrict__ off,
+                                                  const uint32_t *__restrict__ ent_gene) {
+    extern __shared__ uint32_t cur[];
+    __shared__ uint32_t s_t;
+    if (threadIdx.x == 0) s_t = find_genome_by_block(table, n_genomes, blockIdx.x);
+    __syncthreads();
+    const DevBuild &B = table[s_t];
+    const uint32_t j = blockIdx.x - B.blk_base;
+    const uint32_t gbase_off = off[B.hist_base];  // the genome's first entry in the scanned order
+    for (uint32_t i = threadIdx.x; i < B.nh; i += blockDim.x) cur[i] = off[B.hist_base + i * B.nblk + j] - gbase_off;
+    __syncthreads();
+    uint32_t e0, e1, gbase;
+    block_range(B, gptr, j, &e0, &e1, &gbase);
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const uint64_t c = B.mv_code[e];
+        const uint32_t pos = atomicAdd(&cur[bucket_of(c, B.k, B.lead) >> B.hshift], 1u);
         B.ix_code[pos] = c;
-        B.ix_gene[pos] = g;
-        B.ix_cnt[pos] = B.mv_cnt[p + e];
+        B.ix_gene[pos] = ent_gene[gbase + e];
+        B.ix_cnt[pos] = B.mv_cnt[e];
     }
 }
 
 __device__ __forceinline__ bool entry_less(uint64_t ca, uint32_t ga, uint64_t cb, uint32_t gb) {
     return ca < cb || (ca == cb && ga < gb);
-}
-
-// One thread per bucket: insertion sort of small buckets; large ones are queued.
-__global__ __launch_bounds__(256) void k_ix_sort_small(const DevBuild *__restrict__ table, uint32_t n_genomes,
-                                                       uint32_t total_buckets, uint64_t *__restrict__ big_list,
-                                                       uint32_t *__restrict__ counters) {
-    const uint32_t gb = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gb >= total_buckets) return;
-    const uint32_t t = find_genome_by_bucket(table, n_genomes, gb);
-    const DevBuild &B = table[t];
-    const uint32_t b = gb - B.bucket_base;
-    const uint32_t lo = B.ix_dir[b], hi = B.ix_dir[b + 1];
-    const uint32_t n = hi - lo;
-    if (n < 2) return;
-    if (n > kBucketSmall) {
-        big_list[atomicAdd(&counters[1], 1u)] = (static_cast<uint64_t>(t) << 32) | b;
-        return;
-    }
-    uint64_t *code = B.ix_code;
-    uint32_t *gene = B.ix_gene, *cnt = B.ix_cnt;
-    for (uint32_t i = lo + 1; i < hi; ++i) {
-        const uint64_t c = code[i];
-        const uint32_t gg = gene[i], m = cnt[i];
-        uint32_t j = i;
-        while (j > lo && entry_less(c, gg, code[j - 1], gene[j - 1])) {
-            code[j] = code[j - 1];
-            gene[j] = gene[j - 1];
-            cnt[j] = cnt[j - 1];
-            --j;
-        }
-        code[j] = c;
-        gene[j] = gg;
-        cnt[j] = m;
-    }
 }
 
 template <typename CP, typename GP>
@@ -332,49 +329,85 @@ __device__ void sort_entries(CP code, GP gene, GP cnt, uint32_t n) {
     });
 }
 
-constexpr uint32_t kBigLds = 2048;
-
-// One work-group per large bucket: sorted in LDS when it fits, else in place in global memory.
-__global__ __launch_bounds__(256) void k_ix_sort_big(const DevBuild *__restrict__ table, const uint64_t *__restrict__ big_list,
-                                                     const uint32_t *__restrict__ counters) {
-    __shared__ uint64_t s_code[kBigLds];
-    __shared__ uint32_t s_gene[kBigLds];
-    __shared__ uint32_t s_cnt[kBigLds];
-    const uint32_t n_big = counters[1];
-    for (uint32_t bi = blockIdx.x; bi < n_big; bi += gridDim.x) {
-        const uint64_t item = big_list[bi];
-        const DevBuild &B = table[item >> 32];
-        const uint32_t b = static_cast<uint32_t>(item);
-        const uint32_t lo = B.ix_dir[b], n = B.ix_dir[b + 1] - lo;
-        if (n <= kBigLds) {
-            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-                s_code[i] = B.ix_code[lo + i];
-                s_gene[i] = B.ix_gene[lo + i];
-                s_cnt[i] = B.ix_cnt[lo + i];
-            }
-            __syncthreads();
-            sort_entries(s_code, s_gene, s_cnt, n);
-            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-                B.ix_code[lo + i] = s_code[i];
-                B.ix_gene[lo + i] = s_gene[i];
-                B.ix_cnt[lo + i] = s_cnt[i];
-            }
-        } else {
-            sort_entries(B.ix_code + lo, B.ix_gene + lo, B.ix_cnt + lo, n);
+// Directory entries of buckets [b0, b1) from a bin sorted by code: the first entry of
+// each bucket, found by binary search on the bucket of the codes.
+template <typename CP>
+__device__ void bin_directory(const DevBuild &B, CP code, uint32_t n, uint32_t lo, uint32_t b0, uint32_t b1) {
+    for (uint32_t b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
+        uint32_t l = 0, r = n;
+        while (l < r) {
+            const uint32_t mid = (l + r) >> 1;
+            if (bucket_of(code[mid], B.k, B.lead) < b) l = mid + 1;
+            else r = mid;
         }
-        __syncthreads();
+        B.ix_dir[b] = lo + l;
     }
 }
 
+// One work-group per coarse bin: its entries sorted by (code, gene), in LDS when they fit
+// (else in place in global memory), then the bin's buckets in the directory.
+__global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict__ table, uint32_t n_genomes,
+                                                     const uint32_t *__restrict__ off) {
+    __shared__ uint64_t s_code[kIxBinLds];
+    __shared__ uint32_t s_gene[kIxBinLds];
+    __shared__ uint32_t s_cnt[kIxBinLds];
+    __shared__ uint32_t s_t;
+    if (threadIdx.x == 0) s_t = find_genome_by_bin(table, n_genomes, blockIdx.x);
+    __syncthreads();
+    const DevBuild &B = table[s_t];
+    const uint32_t h = blockIdx.x - B.bin_base;
+    const uint32_t base = off[B.hist_base];
+    const uint32_t lo = off[B.hist_base + h * B.nblk] - base;
+    const uint32_t hi = off[B.hist_base + (h + 1) * B.nblk] - base;  // for the last bin: the next genome's start
+    const uint32_t n = hi - lo;
+    const uint32_t b0 = h << B.hshift;
+    const uint32_t b1 = min(B.nb, (h + 1) << B.hshift);
+    if (n <= kIxBinLds) {
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            s_code[i] = B.ix_code[lo + i];
+            s_gene[i] = B.ix_gene[lo + i];
+            s_cnt[i] = B.ix_cnt[lo + i];
+        }
+        __syncthreads();
+        sort_entries(s_code, s_gene, s_cnt, n);
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            B.ix_code[lo + i] = s_code[i];
+            B.ix_gene[lo + i] = s_gene[i];
+            B.ix_cnt[lo + i] = s_cnt[i];
+        }
+        bin_directory(B, s_code, n, lo, b0, b1);
+    } else {
+        sort_entries(B.ix_code + lo, B.ix_gene + lo, B.ix_cnt + lo, n);
+        bin_directory(B, B.ix_code + lo, n, lo, b0, b1);
+    }
+    if (h + 1 == B.nh && threadIdx.x == 0) B.ix_dir[B.nb] = hi;
+}
+
 // ------------------------------------------------------------------ host
+
+// Coarse-bin shift: bins of 2^s buckets holding about kIxBinTarget entries on average.
+static uint32_t bin_shift(uint32_t nb, uint64_t cap) {
+    uint32_t s = 0;
+    while ((uint64_t(nb) >> (s + 1)) > 0 && (cap << (s + 1)) <= uint64_t(nb) * kIxBinTarget) ++s;
+    while ((uint64_t(nb) >> s) > kIxMaxBins) ++s;  // keep the LDS histogram bounded
+    return s;
+}
 
 static BuildShape shape_of(const pdp_genome *g, const pdp_dict *const *d, uint32_t n) {
     BuildShape s{};
     s.n_genomes = n;
     for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t cap = g[i].n_residues + 1;
+        const uint32_t nb = d[i]->n_buckets;
+        const uint32_t sh = bin_shift(nb, cap);
+        const uint64_t nh = (uint64_t(nb) + (1ull << sh) - 1) >> sh;
+        const uint64_t nblk = (cap + kIxBlock - 1) / kIxBlock;
         s.total_genes += g[i].n_genes;
-        s.total_buckets += d[i]->n_buckets;
-        s.total_residues += g[i].n_residues + 1;
+        s.total_residues += cap;
+        s.total_blocks += nblk;
+        s.total_bins += nh;
+        s.total_hist += nh * nblk;
+        s.max_nh = std::max<uint64_t>(s.max_nh, nh);
     }
     return s;
 }
@@ -386,17 +419,28 @@ uint64_t build_ws_bytes(const BuildShape &s) {
     b += align_up(8 * s.total_residues, A);             // slot_code
     b += align_up(4 * s.total_residues, A);             // slot_cnt
     b += align_up(8 * s.total_residues, A);             // long_tmp
+    b += align_up(4 * s.total_residues, A);             // ent_gene
     b += align_up(4 * (s.total_genes + 1), A);          // dcnt / gptr
-    b += align_up(4 * (s.total_buckets + 1), A);        // bcount / gdir
+    b += align_up(4 * (s.total_hist + 1), A);           // hist / off
     b += align_up(8 * (s.total_genes + 1), A);          // long_list
-    b += align_up(8 * (s.total_buckets + 1), A);        // big_list
     b += align_up(4 * 4, A);                            // counters
-    const uint64_t np = std::max<uint64_t>(scan_partials(s.total_genes), scan_partials(s.total_buckets));
+    const uint64_t np = std::max<uint64_t>(scan_partials(s.total_genes), scan_partials(s.total_hist));
     b += align_up(4 * np, A);
     return b;
 }
 
 BuildShape build_shape(const pdp_genome *g, const pdp_dict *const *d, uint32_t n) { return shape_of(g, d, n); }
+
+BuildShape single_build_shape(uint32_t n_genes, uint64_t n_residues, uint32_t k) {
+    pdp_genome g{};
+    g.n_genes = n_genes;
+    g.n_residues = n_residues;
+    pdp_dict d{};
+    d.k = k;
+    d.n_buckets = n_buckets_for(k);
+    const pdp_dict *dp = &d;
+    return shape_of(&g, &dp, 1);
+}
 
 hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint32_t n, void *ws, hipStream_t s) {
     const BuildShape sh = shape_of(g, d, n);
@@ -411,16 +455,16 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
     uint64_t *slot_code = reinterpret_cast<uint64_t *>(take(8 * sh.total_residues));
     uint32_t *slot_cnt = reinterpret_cast<uint32_t *>(take(4 * sh.total_residues));
     uint64_t *long_tmp = reinterpret_cast<uint64_t *>(take(8 * sh.total_residues));
+    uint32_t *ent_gene = reinterpret_cast<uint32_t *>(take(4 * sh.total_residues));
     uint32_t *dcnt = reinterpret_cast<uint32_t *>(take(4 * (sh.total_genes + 1)));
-    uint32_t *bcount = reinterpret_cast<uint32_t *>(take(4 * (sh.total_buckets + 1)));
+    uint32_t *hist = reinterpret_cast<uint32_t *>(take(4 * (sh.total_hist + 1)));
     uint64_t *long_list = reinterpret_cast<uint64_t *>(take(8 * (sh.total_genes + 1)));
-    uint64_t *big_list = reinterpret_cast<uint64_t *>(take(8 * (sh.total_buckets + 1)));
     uint32_t *counters = reinterpret_cast<uint32_t *>(take(4 * 4));
-    const uint64_t np = std::max<uint64_t>(scan_partials(sh.total_genes), scan_partials(sh.total_buckets));
+    const uint64_t np = std::max<uint64_t>(scan_partials(sh.total_genes), scan_partials(sh.total_hist));
     uint32_t *partials = reinterpret_cast<uint32_t *>(take(4 * np));
 
     // descriptors, passed by value to a tiny kernel in chunks
-    uint64_t gene_base = 0, bucket_base = 0, res_base = 0;
+    uint64_t gene_base = 0, res_base = 0, blk_base = 0, bin_base = 0, hist_base = 0;
     for (uint32_t c0 = 0; c0 < n; c0 += kDescPerLaunch) {
         DescChunk ch{};
         ch.first = c0;
@@ -429,6 +473,7 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
             const pdp_genome &G = g[c0 + j];
             const pdp_dict &D = *d[c0 + j];
             DevBuild &B = ch.d[j];
+            const uint64_t cap = G.n_residues + 1;
             B.res = G.residues;
             B.off = G.gene_off;
             B.n_residues = G.n_residues;
@@ -436,8 +481,13 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
             B.k = D.k;
             B.nb = D.n_buckets;
             B.lead = lead_residues(D.k);
+            B.hshift = bin_shift(D.n_buckets, cap);
+            B.nh = static_cast<uint32_t>((uint64_t(D.n_buckets) + (1ull << B.hshift) - 1) >> B.hshift);
+            B.nblk = static_cast<uint32_t>((cap + kIxBlock - 1) / kIxBlock);
             B.gene_base = static_cast<uint32_t>(gene_base);
-            B.bucket_base = static_cast<uint32_t>(bucket_base);
+            B.blk_base = static_cast<uint32_t>(blk_base);
+            B.bin_base = static_cast<uint32_t>(bin_base);
+            B.hist_base = static_cast<uint32_t>(hist_base);
             B.nwin = D.nwin;
             B.mv_ptr = D.mv_ptr;
             B.mv_code = D.mv_code;
@@ -451,19 +501,20 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
             B.slot_cnt = slot_cnt + res_base;
             B.long_tmp = long_tmp + res_base;
             gene_base += G.n_genes;
-            bucket_base += D.n_buckets;
-            res_base += G.n_residues + 1;
+            res_base += cap;
+            blk_base += B.nblk;
+            bin_base += B.nh;
+            hist_base += uint64_t(B.nh) * B.nblk;
         }
         hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(kDescPerLaunch), 0, s, table, ch);
         PDP_TRY(hipGetLastError());
     }
     const uint32_t tg = static_cast<uint32_t>(sh.total_genes);
-    const uint32_t tb = static_cast<uint32_t>(sh.total_buckets);
     const uint32_t gblocks = (n + 255) / 256;
+    const uint32_t hist_lds = static_cast<uint32_t>(4 * sh.max_nh);
     hipLaunchKernelGGL(k_build_init, dim3(gblocks), dim3(256), 0, s, table, n);
     PDP_TRY(hipGetLastError());
     PDP_TRY(launch_fill_u32(counters, 4, 0u, s));
-    PDP_TRY(launch_fill_u32(bcount, uint64_t(tb) + 1, 0u, s));
     if (tg > 0) {
         hipLaunchKernelGGL(k_mv_local, dim3(tg), dim3(kMvThreads), 0, s, table, n, dcnt, long_list, counters);
         PDP_TRY(hipGetLastError());
@@ -475,21 +526,18 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
     hipLaunchKernelGGL(k_mv_empty, dim3(gblocks), dim3(256), 0, s, table, n);
     PDP_TRY(hipGetLastError());
     if (tg > 0) {
-        hipLaunchKernelGGL(k_mv_compact, dim3(tg), dim3(kWave), 0, s, table, n, dcnt, bcount);
+        hipLaunchKernelGGL(k_mv_compact, dim3(tg), dim3(kWave), 0, s, table, n, dcnt, ent_gene);
         PDP_TRY(hipGetLastError());
     }
-    PDP_TRY(launch_scan(bcount, bcount, tb, partials, s));  // in place: bcount becomes the directories
-    hipLaunchKernelGGL(k_dir_write, dim3((tb + 255) / 256), dim3(256), 0, s, table, n, tb, bcount);
+    hipLaunchKernelGGL(k_ix_hist, dim3(static_cast<uint32_t>(sh.total_blocks)), dim3(256), hist_lds, s, table, n, dcnt,
+                       hist);
     PDP_TRY(hipGetLastError());
-    PDP_TRY(launch_fill_u32(bcount, tb, 0u, s));
-    if (tg > 0) {
-        hipLaunchKernelGGL(k_ix_scatter, dim3(tg), dim3(kWave), 0, s, table, n, bcount);
-        PDP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_ix_sort_small, dim3((tb + 255) / 256), dim3(256), 0, s, table, n, tb, big_list, counters);
-        PDP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_ix_sort_big, dim3(256), dim3(256), 0, s, table, big_list, counters);
-        PDP_TRY(hipGetLastError());
-    }
+    PDP_TRY(launch_scan(hist, hist, sh.total_hist, partials, s));  // in place: every (bin, block) range
+    hipLaunchKernelGGL(k_ix_place, dim3(static_cast<uint32_t>(sh.total_blocks)), dim3(256), hist_lds, s, table, n, dcnt,
+                       hist, ent_gene);
+    PDP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_ix_sort_bin, dim3(static_cast<uint32_t>(sh.total_bins)), dim3(256), 0, s, table, n, hist);
+    PDP_TRY(hipGetLastError());
     return hipSuccess;
 }
 

@@ -18,8 +18,10 @@ namespace pdp {
 // ---------------------------------------------------------------- sizes
 constexpr uint32_t kScanItems = 4096;        // elements per scan work-group (256 threads x 16)
 constexpr uint32_t kMvSortCap = 2048;        // windows a gene may have to be sorted in LDS
-constexpr uint32_t kBucketSmall = 32;        // buckets up to this size are sorted by one thread
-constexpr uint32_t kBucketLdsCap = 4096;     // larger buckets up to this size are sorted in LDS
+constexpr uint32_t kIxBlock = 4096;          // index entries per histogram block
+constexpr uint32_t kIxBinTarget = 1024;      // average index entries per coarse bin
+constexpr uint32_t kIxBinLds = 2048;         // coarse bins up to this size are sorted in LDS
+constexpr uint32_t kIxMaxBins = 8192;        // coarse bins per genome at most (LDS histogram)
 constexpr uint32_t kJoinLdsCap = 2048;       // target-side index entries staged in LDS per join group
 constexpr uint32_t kTileMaxRows = 64;        // rows per accumulation tile
 constexpr uint32_t kTileThreads = 256;
@@ -84,7 +86,9 @@ struct DevBuild {
     const uint8_t *res;
     const uint64_t *off;
     uint64_t n_residues;
-    uint32_t n_genes, k, nb, lead, gene_base, bucket_base;
+    uint32_t n_genes, k, nb, lead, gene_base;
+    uint32_t hshift, nh, nblk;            // coarse bins of 2^hshift buckets; entry blocks for the histogram
+    uint32_t blk_base, bin_base, hist_base;  // first block, bin and histogram cell of the genome
     uint32_t *nwin, *mv_ptr;
     uint64_t *mv_code;
     uint32_t *mv_cnt, *ix_dir;
@@ -96,9 +100,10 @@ struct DevBuild {
     uint64_t *long_tmp;   // windows of genes too long for LDS
 };
 struct BuildShape {
-    uint64_t n_genomes, total_genes, total_buckets, total_residues;
+    uint64_t n_genomes, total_genes, total_residues, total_blocks, total_bins, total_hist, max_nh;
 };
 BuildShape build_shape(const pdp_genome *g, const pdp_dict *const *d, uint32_t n);
+BuildShape single_build_shape(uint32_t n_genes, uint64_t n_residues, uint32_t k);
 uint64_t build_ws_bytes(const BuildShape &s);
 hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint32_t n, void *ws, hipStream_t s);
 
