@@ -39,6 +39,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--breakdown", action="store_true", help="also time every kernel group (extra launches)")
     p.add_argument("--calibrate-copy", action="store_true", help="only run a copy of known size (counter calibration)")
+    p.add_argument("--tune", action="store_true", help="pick tile shapes and join splits with the autotuner first")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                    help="measured HBM traffic per kernel (from rocprofv3 counters), used when its source hash matches")
     return p.parse_args()
@@ -141,7 +142,16 @@ def main():
     batch = pdp.DictionaryBatch(dev, k)  # all ten dictionaries in one pdp_dict_build_many
     dicts = batch.dicts
     batch.build()
-    runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts))
+    tasks = pdp.all_pairs_tasks(dicts)
+    tuned = None
+    prm = pdp.params()
+    if args.tune:
+        best, tres = pdp.autotune(tasks, reps=3)
+        prm = best
+        tuned = {"lds_budget": int(best.lds_budget), "join_entries": int(best.join_entries),
+                 "persistent": bool(best.flags & B.PDP_PARAM_PERSISTENT), "best_ms": round(tres.best_ms, 4),
+                 "first_ms": round(tres.first_ms, 4), "candidates": int(tres.tried)}
+    runner = pdp.PairRunner(tasks, prm)
     runner.run()  # sizes the scratch and outputs
     for d in dicts:
         d.check_status()
@@ -231,6 +241,7 @@ def main():
                    "genomes": len(genes), "genes_per_genome": genes[0], "k": k, "genome_pairs": len(pairs),
                    "gene_pairs": gene_pairs, "kmer_entries": int(sum(entries)), "best_hits": bh_nnz, "bbh_pairs": bbh_n},
         "roofline": roofline,
+        "params": tuned if tuned is not None else "defaults",
         "breakdown": breakdown,
     }
     if not args.no_cpu_baseline:

@@ -291,9 +291,11 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
             const pdp_dict *R = dir == 0 ? tk.a : tk.b;
             const pdp_dict *C = dir == 0 ? tk.b : tk.a;
             // per row: the packed 16-bit sums plus one bitmap bit per 32-bit word
+            // (plus the column genome's window counts, 16 bits each, once per tile)
             const uint64_t W = (uint64_t(C->n_genes) + 1) / 2;
             const uint64_t row_words = std::max<uint64_t>(W + (W + 31) / 32, 1);
-            uint64_t T = lds_budget / (4 * row_words);
+            const uint64_t fixed_words = W + 4;
+            uint64_t T = lds_budget / 4 > fixed_words ? (lds_budget / 4 - fixed_words) / row_words : 0;
             if (T == 0)
                 return bail(fail(PDP_E_LIMIT, "task %u: %u target genes do not fit an LDS tile of %u bytes", t,
                                  C->n_genes, lds_budget));
@@ -302,7 +304,7 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
             d.tile_rows[dir] = static_cast<uint32_t>(T);
             d.row_base[dir] = static_cast<uint32_t>(bh_rows);
             bh_rows += R->n_genes;
-            tile_lds = std::max<uint32_t>(tile_lds, static_cast<uint32_t>(align_up(T * row_words * 4, 16)));
+            tile_lds = std::max<uint32_t>(tile_lds, static_cast<uint32_t>(4 * (align_up(T * row_words, 4) + W) + 16));
         }
         d.bbh_row_base = static_cast<uint32_t>(bbh_rows);
         if (flags & PDP_TASK_BBH) bbh_rows += tk.a->n_genes;

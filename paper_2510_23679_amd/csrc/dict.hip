@@ -302,9 +302,9 @@ __global__ __launch_bounds__(256) void k_ix_place(const DevBuild *__restrict__ t
     for (uint32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
         const uint64_t c = B.mv_code[e];
         const uint32_t pos = atomicAdd(&cur[bucket_of(c, B.k, B.lead) >> B.hshift], 1u);
-        B.ix_code[pos] = c;
-        B.ix_gene[pos] = ent_gene[gbase + e];
-        B.ix_cnt[pos] = B.mv_cnt[e];
+        // one 16-byte record per entry: a single scattered store instead of three
+        B.ix_tmp[pos] = make_uint4(static_cast<uint32_t>(c), static_cast<uint32_t>(c >> 32), ent_gene[gbase + e],
+                                   B.mv_cnt[e]);
     }
 }
 
@@ -364,9 +364,10 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
     const uint32_t b1 = min(B.nb, (h + 1) << B.hshift);
     if (n <= kIxBinLds) {
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            s_code[i] = B.ix_code[lo + i];
-            s_gene[i] = B.ix_gene[lo + i];
-            s_cnt[i] = B.ix_cnt[lo + i];
+            const uint4 r = B.ix_tmp[lo + i];
+            s_code[i] = (static_cast<uint64_t>(r.y) << 32) | r.x;
+            s_gene[i] = r.z;
+            s_cnt[i] = r.w;
         }
         __syncthreads();
         sort_entries(s_code, s_gene, s_cnt, n);
@@ -377,6 +378,13 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
         }
         bin_directory(B, s_code, n, lo, b0, b1);
     } else {
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint4 r = B.ix_tmp[lo + i];
+            B.ix_code[lo + i] = (static_cast<uint64_t>(r.y) << 32) | r.x;
+            B.ix_gene[lo + i] = r.z;
+            B.ix_cnt[lo + i] = r.w;
+        }
+        __syncthreads();
         sort_entries(B.ix_code + lo, B.ix_gene + lo, B.ix_cnt + lo, n);
         bin_directory(B, B.ix_code + lo, n, lo, b0, b1);
     }
@@ -420,6 +428,7 @@ uint64_t build_ws_bytes(const BuildShape &s) {
     b += align_up(4 * s.total_residues, A);             // slot_cnt
     b += align_up(8 * s.total_residues, A);             // long_tmp
     b += align_up(4 * s.total_residues, A);             // ent_gene
+    b += align_up(16 * s.total_residues, A);            // ix_tmp
     b += align_up(4 * (s.total_genes + 1), A);          // dcnt / gptr
     b += align_up(4 * (s.total_hist + 1), A);           // hist / off
     b += align_up(8 * (s.total_genes + 1), A);          // long_list
@@ -456,6 +465,7 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
     uint32_t *slot_cnt = reinterpret_cast<uint32_t *>(take(4 * sh.total_residues));
     uint64_t *long_tmp = reinterpret_cast<uint64_t *>(take(8 * sh.total_residues));
     uint32_t *ent_gene = reinterpret_cast<uint32_t *>(take(4 * sh.total_residues));
+    uint4 *ix_tmp = reinterpret_cast<uint4 *>(take(16 * sh.total_residues));
     uint32_t *dcnt = reinterpret_cast<uint32_t *>(take(4 * (sh.total_genes + 1)));
     uint32_t *hist = reinterpret_cast<uint32_t *>(take(4 * (sh.total_hist + 1)));
     uint64_t *long_list = reinterpret_cast<uint64_t *>(take(8 * (sh.total_genes + 1)));
@@ -500,6 +510,7 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
             B.slot_code = slot_code + res_base;
             B.slot_cnt = slot_cnt + res_base;
             B.long_tmp = long_tmp + res_base;
+            B.ix_tmp = ix_tmp + res_base;
             gene_base += G.n_genes;
             res_base += cap;
             blk_base += B.nblk;

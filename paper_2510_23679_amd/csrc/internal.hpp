@@ -98,6 +98,7 @@ struct DevBuild {
     uint64_t *slot_code;  // per gene g: sorted distinct codes at offset gene_off[g]
     uint32_t *slot_cnt;
     uint64_t *long_tmp;   // windows of genes too long for LDS
+    uint4 *ix_tmp;        // index entries placed by coarse bin, before the bin sort
 };
 struct BuildShape {
     uint64_t n_genomes, total_genes, total_residues, total_blocks, total_bins, total_hist, max_nh;

@@ -225,6 +225,9 @@ __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__
     const uint32_t words = tl.nrows * (W + WB);
     uint4 *lds4 = reinterpret_cast<uint4 *>(lds);
     for (uint32_t i = threadIdx.x; i < (words + 3) / 4; i += kTileThreads) lds4[i] = make_uint4(0, 0, 0, 0);
+    // window counts of the column genome, 16 bits each (at most PDP_MAX_WINDOWS)
+    uint16_t *cw = reinterpret_cast<uint16_t *>(lds + ((words + 3) & ~3u));
+    for (uint32_t c = threadIdx.x; c < ncols; c += kTileThreads) cw[c] = static_cast<uint16_t>(C.nwin[c]);
     if (threadIdx.x == 0) *s_flag = 0;
     __syncthreads();
     const uint32_t r0 = tile_off[tile_id], r1 = tile_off[tile_id + 1];
@@ -252,11 +255,11 @@ __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__
                 const uint32_t v = arow[w];
                 const uint32_t m0 = v & 0xFFFFu, m1 = v >> 16;
                 if (m0) {
-                    const uint32_t d = nr + C.nwin[2 * w] - m0;
+                    const uint32_t d = nr + cw[2 * w] - m0;
                     if (j_greater(m0, d, bm, bd)) { bm = m0; bd = d; }
                 }
                 if (m1) {
-                    const uint32_t d = nr + C.nwin[2 * w + 1] - m1;
+                    const uint32_t d = nr + cw[2 * w + 1] - m1;
                     if (j_greater(m1, d, bm, bd)) { bm = m1; bd = d; }
                 }
             }
@@ -277,8 +280,8 @@ __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__
                     m &= m - 1;
                     const uint32_t v = arow[w];
                     const uint32_t m0 = v & 0xFFFFu, m1 = v >> 16;
-                    if (m0 && j_equal(m0, nr + C.nwin[2 * w] - m0, bm, bd)) ++cnt;
-                    if (m1 && j_equal(m1, nr + C.nwin[2 * w + 1] - m1, bm, bd)) ++cnt;
+                    if (m0 && j_equal(m0, nr + cw[2 * w] - m0, bm, bd)) ++cnt;
+                    if (m1 && j_equal(m1, nr + cw[2 * w + 1] - m1, bm, bd)) ++cnt;
                 }
                 const uint32_t incl = wave_inclusive_sum(cnt);
                 const uint32_t total = __shfl(incl, kWave - 1, kWave);
@@ -292,7 +295,7 @@ __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__
                         const uint32_t mm = h ? v >> 16 : v & 0xFFFFu;
                         if (!mm) continue;
                         const uint32_t c = 2 * w + h;
-                        const uint32_t d = nr + C.nwin[c] - mm;
+                        const uint32_t d = nr + cw[c] - mm;
                         if (!j_equal(mm, d, bm, bd)) continue;
                         if (WRITE) {
                             if (p < bh_cap) {
