@@ -22,6 +22,7 @@
 // Counts, scans and writes keep every output in a canonical order, so results
 // do not depend on scheduling.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "internal.hpp"
@@ -41,30 +42,42 @@ __device__ __forceinline__ uint32_t find_task(const DevTask *tasks, uint32_t n_t
     return lo;
 }
 
-struct JoinLds {
-    uint64_t code[kJoinLdsCap];
-    uint32_t gene[kJoinLdsCap];
-    uint32_t cnt[kJoinLdsCap];
+// LDS of one join item: both sides' codes (the count pass needs no more); the write
+// pass also stages the target side's genes and counts.
+struct JoinLdsCount {
+    uint64_t bcode[kJoinLdsCap];
+    uint64_t acode[kJoinLdsCap];
     uint32_t scan[kJoinThreads / kWave + 1];
     uint32_t task;
     uint32_t next;
 };
+struct JoinLdsWrite {
+    uint64_t bcode[kJoinLdsCap];
+    uint64_t acode[kJoinLdsCap];
+    uint32_t bgene[kJoinLdsCap];
+    uint32_t bcnt[kJoinLdsCap];
+    uint32_t scan[kJoinThreads / kWave + 1];
+    uint32_t task;
+    uint32_t next;
+};
+template <bool WRITE>
+using JoinLds = typename std::conditional<WRITE, JoinLdsWrite, JoinLdsCount>::type;
 
-// Query entries [a0, a1) of genome a against the target entries of the same bucket
-// range (bc/bg/bn, nbe entries sorted by code): a binary search per query entry.
-// WRITE = false returns the number of incidences; WRITE = true writes them from
-// out_base on in a fixed order (blocks of kJoinThreads query entries, thread order
-// within a block), so positions need no atomics.  Contains barriers.
+// Query entries [a0, a1) of genome a (codes ac, indexed from a0) against the target
+// entries of the same bucket range (bc/bg/bn, nbe entries sorted by code): a binary
+// search per query entry.  WRITE = false returns the number of incidences; WRITE = true
+// writes them from out_base on in a fixed order (blocks of kJoinThreads query entries,
+// thread order within a block), so positions need no atomics.  Contains barriers.
 template <bool WRITE>
 __device__ __forceinline__ uint32_t join_range(const DevTask &T, uint32_t task, uint32_t a0, uint32_t a1,
-                                               const uint64_t *bc, const uint32_t *bg, const uint32_t *bn, uint32_t nbe,
-                                               uint4 *inc, uint64_t out_base, uint64_t inc_cap, uint32_t *scan_tmp) {
-    const uint64_t *ac = T.a.ix_code;
+                                               const uint64_t *ac, const uint64_t *bc, const uint32_t *bg,
+                                               const uint32_t *bn, uint32_t nbe, uint4 *inc, uint64_t out_base,
+                                               uint64_t inc_cap, uint32_t *scan_tmp) {
     uint32_t done = 0;
     for (uint32_t base = a0; base < a1; base += kJoinThreads) {
         const uint32_t i = base + threadIdx.x;
         const bool valid = i < a1;
-        const uint64_t code = valid ? ac[i] : 0;
+        const uint64_t code = valid ? ac[i - a0] : 0;
         uint32_t lo = 0, hi = valid ? nbe : 0;
         while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
@@ -90,11 +103,12 @@ __device__ __forceinline__ uint32_t join_range(const DevTask &T, uint32_t task, 
 
 // One join item: a range of leading-residue buckets of one task.  Pass WRITE = false
 // stores the item's incidence count in cnt[chunk]; WRITE = true writes the incidences
-// at the scanned offset off[chunk].  Ends with a barrier so the LDS can take the next item.
+// at the scanned offset off[chunk].  Both sides are staged in LDS in one go when they
+// fit (one memory latency per item); ends with a barrier so the LDS can take the next item.
 template <bool WRITE>
 __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__restrict__ tasks, uint32_t n_tasks,
                                            uint32_t *__restrict__ chunk_cnt, uint4 *__restrict__ inc, uint64_t inc_cap,
-                                           JoinLds &L) {
+                                           JoinLds<WRITE> &L) {
     if (threadIdx.x == 0) L.task = find_task(tasks, n_tasks, chunk);
     __syncthreads();
     const uint32_t task = L.task;
@@ -108,18 +122,26 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
     uint32_t n = 0;
     const uint64_t out_base = WRITE ? chunk_cnt[chunk] : 0;
     if (a0 != a1 && b0 != b1) {
-        const uint32_t nbe = b1 - b0;
-        if (nbe <= kJoinLdsCap) {
+        const uint32_t nbe = b1 - b0, nae = a1 - a0;
+        if (nbe <= kJoinLdsCap && nae <= kJoinLdsCap) {
             for (uint32_t i = threadIdx.x; i < nbe; i += kJoinThreads) {
-                L.code[i] = T.b.ix_code[b0 + i];
-                L.gene[i] = T.b.ix_gene[b0 + i];
-                L.cnt[i] = T.b.ix_cnt[b0 + i];
+                L.bcode[i] = T.b.ix_code[b0 + i];
+                if constexpr (WRITE) {
+                    L.bgene[i] = T.b.ix_gene[b0 + i];
+                    L.bcnt[i] = T.b.ix_cnt[b0 + i];
+                }
             }
+            for (uint32_t i = threadIdx.x; i < nae; i += kJoinThreads) L.acode[i] = T.a.ix_code[a0 + i];
             __syncthreads();
-            n = join_range<WRITE>(T, task, a0, a1, L.code, L.gene, L.cnt, nbe, inc, out_base, inc_cap, L.scan);
+            if constexpr (WRITE)
+                n = join_range<true>(T, task, a0, a1, L.acode, L.bcode, L.bgene, L.bcnt, nbe, inc, out_base, inc_cap,
+                                     L.scan);
+            else
+                n = join_range<false>(T, task, a0, a1, L.acode, L.bcode, nullptr, nullptr, nbe, inc, out_base, inc_cap,
+                                      L.scan);
         } else {
-            n = join_range<WRITE>(T, task, a0, a1, T.b.ix_code + b0, T.b.ix_gene + b0, T.b.ix_cnt + b0, nbe, inc,
-                                  out_base, inc_cap, L.scan);
+            n = join_range<WRITE>(T, task, a0, a1, T.a.ix_code + a0, T.b.ix_code + b0, T.b.ix_gene + b0,
+                                  T.b.ix_cnt + b0, nbe, inc, out_base, inc_cap, L.scan);
         }
     }
     if (!WRITE && threadIdx.x == 0) chunk_cnt[chunk] = n;
@@ -130,7 +152,7 @@ template <bool WRITE>
 __global__ __launch_bounds__(kJoinThreads) void k_join(const DevTask *__restrict__ tasks, uint32_t n_tasks,
                                                        uint32_t *__restrict__ chunk_cnt, uint4 *__restrict__ inc,
                                                        uint64_t inc_cap) {
-    __shared__ JoinLds L;
+    __shared__ JoinLds<WRITE> L;
     join_chunk<WRITE>(blockIdx.x, tasks, n_tasks, chunk_cnt, inc, inc_cap, L);
 }
 
@@ -143,7 +165,7 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_persistent(const DevTask 
                                                                   uint32_t total_chunks, uint32_t *__restrict__ chunk_cnt,
                                                                   uint4 *__restrict__ inc, uint64_t inc_cap,
                                                                   uint32_t *__restrict__ next) {
-    __shared__ JoinLds L;
+    __shared__ JoinLds<WRITE> L;
     for (;;) {
         if (threadIdx.x == 0) L.next = atomicAdd(next, kClaim);
         __syncthreads();
