@@ -192,7 +192,7 @@ typedef struct pdp_bbh_out {
 typedef struct pdp_params {
     uint64_t inc_capacity;   /* shared-k-mer incidences the scratch can hold (0: from the dictionary sizes) */
     uint32_t tile_rows;      /* query genes per LDS accumulation tile */
-    uint32_t join_entries;   /* target index entries per join work-group */
+    uint32_t join_entries;   /* index entries of the larger genome per join sub-range (1..1024) */
     uint32_t lds_budget;     /* bytes of LDS for one accumulation tile (at most 159 KiB) */
     uint32_t flags;          /* PDP_PARAM_* */
 } pdp_params;
@@ -297,7 +297,7 @@ void pdp_graph_destroy(pdp_graph *graph);
  * planned for the given tasks, run once to warm up and then reps times between
  * two HIP events; the fastest candidate whose runs end with a clean status is
  * returned.  candidates NULL: a built-in grid of LDS budgets (24-144 KiB),
- * join group sizes (256-2048 entries) and persistent on/off.  bh/bbh/status as
+ * join sub-range sizes (256-1024 entries) and persistent on/off.  bh/bbh/status as
  * for pdp_plan_launch (their rows do not depend on the parameters); ws of
  * pdp_autotune_ws_size bytes.  Synchronises the stream.
  * Errors: PDP_E_INVAL, PDP_E_HIP, PDP_E_LIMIT (no candidate ran cleanly). */

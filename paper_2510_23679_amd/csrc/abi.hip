@@ -248,7 +248,7 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     std::memset(&prm, 0, sizeof(prm));
     if (params) prm = *params;
     const uint32_t lds_budget = prm.lds_budget ? prm.lds_budget : kDefaultLdsBudget;
-    const uint32_t join_entries = prm.join_entries ? prm.join_entries : kJoinLdsCap / 2;
+    const uint32_t join_entries = prm.join_entries ? prm.join_entries : kJoinLdsCap / 2;  // ~2x headroom to the stage
     if (lds_budget > kMaxTileLds) return fail(PDP_E_INVAL, "lds_budget above %u bytes", kMaxTileLds);
     if (join_entries > kJoinLdsCap) return fail(PDP_E_INVAL, "join_entries above %u", kJoinLdsCap);
     if (prm.tile_rows > kTileMaxRows) return fail(PDP_E_INVAL, "tile_rows above %u", kTileMaxRows);
@@ -280,10 +280,14 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         d.flags = flags;
         const uint32_t nb = tk.a->n_buckets;
         const uint64_t e_max = std::max<uint64_t>(std::max(tk.a->capacity, tk.b->capacity), 1);
+        // sub-ranges of bpw buckets hold ~join_entries entries of the larger genome; an item
+        // takes as many sub-ranges as its directory slice (kJoinDirCap buckets) allows
         uint64_t bpw = uint64_t(join_entries) * nb / e_max;
-        bpw = std::min<uint64_t>(std::max<uint64_t>(bpw, 1), nb);
+        bpw = std::min<uint64_t>(std::max<uint64_t>(bpw, 1), std::min<uint64_t>(nb, kJoinDirCap));
+        const uint64_t subs = std::max<uint64_t>(1, kJoinDirCap / bpw);
         d.bpw = static_cast<uint32_t>(bpw);
-        d.n_chunks = static_cast<uint32_t>((nb + bpw - 1) / bpw);
+        d.subs = static_cast<uint32_t>(subs);
+        d.n_chunks = static_cast<uint32_t>((nb + bpw * subs - 1) / (bpw * subs));
         for (uint32_t dir = 0; dir < 2; ++dir) {
             d.row_base[dir] = UINT32_MAX;
             d.tile_rows[dir] = 1;

@@ -22,7 +22,8 @@ constexpr uint32_t kIxBlock = 4096;          // index entries per histogram bloc
 constexpr uint32_t kIxBinTarget = 1024;      // average index entries per coarse bin
 constexpr uint32_t kIxBinLds = 2048;         // coarse bins up to this size are sorted in LDS
 constexpr uint32_t kIxMaxBins = 8192;        // coarse bins per genome at most (LDS histogram)
-constexpr uint32_t kJoinLdsCap = 2048;       // target-side index entries staged in LDS per join group
+constexpr uint32_t kJoinLdsCap = 1024;       // index entries per side staged in LDS per join sub-range
+constexpr uint32_t kJoinDirCap = 1024;       // leading-residue buckets per join item (sub-ranges x buckets)
 constexpr uint32_t kTileMaxRows = 64;        // rows per accumulation tile
 constexpr uint32_t kTileThreads = 256;
 constexpr uint32_t kDefaultLdsBudget = 48 * 1024;
@@ -54,14 +55,14 @@ struct DevDict {
 struct DevTask {
     DevDict a, b;
     uint32_t flags;
-    uint32_t bpw;           // buckets per join group
+    uint32_t bpw;           // buckets per join sub-range
+    uint32_t subs;          // sub-ranges per join item
     uint32_t chunk_base;    // first join group of the task
     uint32_t n_chunks;
     uint32_t tile_rows[2];  // rows per tile, direction 0 (a rows) and 1 (b rows)
     uint32_t tile_base[2];  // first tile of each direction
     uint32_t row_base[2];   // first best-hit row of each direction (UINT32_MAX: none)
     uint32_t bbh_row_base;  // first BBH row (UINT32_MAX: none)
-    uint32_t reserved;
 };
 
 struct DevTile {

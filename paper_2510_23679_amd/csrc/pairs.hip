@@ -32,36 +32,49 @@ namespace pdp {
 constexpr uint32_t kJoinThreads = 256;
 constexpr uint32_t kBucketGroups = 1024;
 
-__device__ __forceinline__ uint32_t find_task(const DevTask *tasks, uint32_t n_tasks, uint32_t chunk) {
-    uint32_t lo = 0, hi = n_tasks - 1;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (tasks[mid].chunk_base <= chunk) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-// LDS of one join item: both sides' codes (the count pass needs no more); the write
-// pass also stages the target side's genes and counts.
-struct JoinLdsCount {
-    uint64_t bcode[kJoinLdsCap];
-    uint64_t acode[kJoinLdsCap];
+// LDS of one join item: the task descriptor, the item's slice of both bucket
+// directories, and one sub-range of both sides' codes (the count pass needs no more;
+// the write pass also stages the target side's genes and counts).
+struct JoinLdsBase {
+    DevTask task;
+    uint32_t adir[kJoinDirCap + 1];
+    uint32_t bdir[kJoinDirCap + 1];
     uint32_t scan[kJoinThreads / kWave + 1];
-    uint32_t task;
+    uint32_t found;
     uint32_t next;
 };
-struct JoinLdsWrite {
+struct JoinLdsCount : JoinLdsBase {
+    uint64_t bcode[kJoinLdsCap];
+    uint64_t acode[kJoinLdsCap];
+};
+struct JoinLdsWrite : JoinLdsBase {
     uint64_t bcode[kJoinLdsCap];
     uint64_t acode[kJoinLdsCap];
     uint32_t bgene[kJoinLdsCap];
     uint32_t bcnt[kJoinLdsCap];
-    uint32_t scan[kJoinThreads / kWave + 1];
-    uint32_t task;
-    uint32_t next;
 };
 template <bool WRITE>
 using JoinLds = typename std::conditional<WRITE, JoinLdsWrite, JoinLdsCount>::type;
+
+// Index of the last task whose chunk_base <= chunk, found by the whole work-group with a
+// 256-way search (one memory round trip per level: two levels cover 65536 tasks).
+__device__ __forceinline__ uint32_t find_task_coop(const DevTask *tasks, uint32_t n_tasks, uint32_t chunk,
+                                                   uint32_t *found) {
+    uint32_t lo = 0, hi = n_tasks;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t step = (hi - lo + blockDim.x - 1) / blockDim.x;
+        if (threadIdx.x == 0) *found = 0;
+        __syncthreads();
+        const uint32_t idx = lo + threadIdx.x * step;
+        if (idx < hi && tasks[idx].chunk_base <= chunk) atomicMax(found, threadIdx.x);
+        __syncthreads();
+        const uint32_t t = *found;
+        __syncthreads();
+        lo = lo + t * step;
+        hi = min(hi, lo + step);
+    }
+    return lo;
+}
 
 // Query entries [a0, a1) of genome a (codes ac, indexed from a0) against the target
 // entries of the same bucket range (bc/bg/bn, nbe entries sorted by code): a binary
@@ -101,28 +114,43 @@ __device__ __forceinline__ uint32_t join_range(const DevTask &T, uint32_t task, 
     return done;
 }
 
-// One join item: a range of leading-residue buckets of one task.  Pass WRITE = false
-// stores the item's incidence count in cnt[chunk]; WRITE = true writes the incidences
-// at the scanned offset off[chunk].  Both sides are staged in LDS in one go when they
-// fit (one memory latency per item); ends with a barrier so the LDS can take the next item.
+// One join item: up to T.subs consecutive sub-ranges of T.bpw leading-residue buckets of
+// one task.  Pass WRITE = false stores the item's incidence count in chunk_cnt[chunk];
+// WRITE = true writes the incidences from the scanned offset chunk_cnt[chunk] on.  The
+// task descriptor and the directory slice arrive in one round trip, then each sub-range
+// stages both sides in LDS when they fit.  Ends with a barrier so the LDS can take the
+// next item.
 template <bool WRITE>
 __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__restrict__ tasks, uint32_t n_tasks,
                                            uint32_t *__restrict__ chunk_cnt, uint4 *__restrict__ inc, uint64_t inc_cap,
                                            JoinLds<WRITE> &L) {
-    if (threadIdx.x == 0) L.task = find_task(tasks, n_tasks, chunk);
+    const uint32_t task = find_task_coop(tasks, n_tasks, chunk, &L.found);
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&tasks[task]);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(&L.task);
+        for (uint32_t i = threadIdx.x; i < sizeof(DevTask) / 4; i += blockDim.x) dst[i] = src[i];
+    }
     __syncthreads();
-    const uint32_t task = L.task;
-    const DevTask &T = tasks[task];
+    const DevTask &T = L.task;
     const uint32_t c = chunk - T.chunk_base;
     const uint32_t nb = T.a.n_buckets;
-    const uint32_t bl = c * T.bpw;
-    const uint32_t bh = min(nb, bl + T.bpw);
-    const uint32_t a0 = T.a.ix_dir[bl], a1 = T.a.ix_dir[bh];
-    const uint32_t b0 = T.b.ix_dir[bl], b1 = T.b.ix_dir[bh];
+    const uint32_t span = T.bpw * T.subs;
+    const uint32_t bl = c * span;
+    const uint32_t bh = min(nb, bl + span);
+    for (uint32_t i = threadIdx.x; i <= bh - bl; i += blockDim.x) {
+        L.adir[i] = T.a.ix_dir[bl + i];
+        L.bdir[i] = T.b.ix_dir[bl + i];
+    }
+    uint64_t out = WRITE ? chunk_cnt[chunk] : 0;
+    __syncthreads();
     uint32_t n = 0;
-    const uint64_t out_base = WRITE ? chunk_cnt[chunk] : 0;
-    if (a0 != a1 && b0 != b1) {
+    for (uint32_t s0 = bl; s0 < bh; s0 += T.bpw) {
+        const uint32_t s1 = min(bh, s0 + T.bpw);
+        const uint32_t a0 = L.adir[s0 - bl], a1 = L.adir[s1 - bl];
+        const uint32_t b0 = L.bdir[s0 - bl], b1 = L.bdir[s1 - bl];
+        if (a0 == a1 || b0 == b1) continue;  // uniform across the work-group
         const uint32_t nbe = b1 - b0, nae = a1 - a0;
+        uint32_t got;
         if (nbe <= kJoinLdsCap && nae <= kJoinLdsCap) {
             for (uint32_t i = threadIdx.x; i < nbe; i += kJoinThreads) {
                 L.bcode[i] = T.b.ix_code[b0 + i];
@@ -134,15 +162,18 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
             for (uint32_t i = threadIdx.x; i < nae; i += kJoinThreads) L.acode[i] = T.a.ix_code[a0 + i];
             __syncthreads();
             if constexpr (WRITE)
-                n = join_range<true>(T, task, a0, a1, L.acode, L.bcode, L.bgene, L.bcnt, nbe, inc, out_base, inc_cap,
-                                     L.scan);
+                got = join_range<true>(T, task, a0, a1, L.acode, L.bcode, L.bgene, L.bcnt, nbe, inc, out, inc_cap,
+                                       L.scan);
             else
-                n = join_range<false>(T, task, a0, a1, L.acode, L.bcode, nullptr, nullptr, nbe, inc, out_base, inc_cap,
-                                      L.scan);
+                got = join_range<false>(T, task, a0, a1, L.acode, L.bcode, nullptr, nullptr, nbe, inc, out, inc_cap,
+                                        L.scan);
         } else {
-            n = join_range<WRITE>(T, task, a0, a1, T.a.ix_code + a0, T.b.ix_code + b0, T.b.ix_gene + b0,
-                                  T.b.ix_cnt + b0, nbe, inc, out_base, inc_cap, L.scan);
+            got = join_range<WRITE>(T, task, a0, a1, T.a.ix_code + a0, T.b.ix_code + b0, T.b.ix_gene + b0,
+                                    T.b.ix_cnt + b0, nbe, inc, out, inc_cap, L.scan);
         }
+        n += got;
+        out += got;
+        __syncthreads();  // the staged arrays take the next sub-range
     }
     if (!WRITE && threadIdx.x == 0) chunk_cnt[chunk] = n;
     __syncthreads();
@@ -159,6 +190,7 @@ __global__ __launch_bounds__(kJoinThreads) void k_join(const DevTask *__restrict
 // Persistent form: a fixed grid claims join items kClaim at a time from a counter
 // (one atomic per claim, not per item) until none are left.
 constexpr uint32_t kClaim = 8;
+constexpr uint32_t kClaimJoin = 2;
 
 template <bool WRITE>
 __global__ __launch_bounds__(kJoinThreads) void k_join_persistent(const DevTask *__restrict__ tasks, uint32_t n_tasks,
@@ -167,12 +199,12 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_persistent(const DevTask 
                                                                   uint32_t *__restrict__ next) {
     __shared__ JoinLds<WRITE> L;
     for (;;) {
-        if (threadIdx.x == 0) L.next = atomicAdd(next, kClaim);
+        if (threadIdx.x == 0) L.next = atomicAdd(next, kClaimJoin);
         __syncthreads();
         const uint32_t first = L.next;
         __syncthreads();
         if (first >= total_chunks) break;
-        const uint32_t last = min(total_chunks, first + kClaim);
+        const uint32_t last = min(total_chunks, first + kClaimJoin);
         for (uint32_t chunk = first; chunk < last; ++chunk)
             join_chunk<WRITE>(chunk, tasks, n_tasks, chunk_cnt, inc, inc_cap, L);
     }
@@ -595,7 +627,7 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     const uint32_t *inc_total = w.chunk_cnt + p.total_chunks;  // after the scan: all incidences
     PDP_TRY(mark(PDP_KERNEL_JOIN, true));
     if (p.total_chunks && p.join_grid) {
-        const dim3 g(std::min(p.join_grid, (p.total_chunks + kClaim - 1) / kClaim));
+        const dim3 g(std::min(p.join_grid, (p.total_chunks + kClaimJoin - 1) / kClaimJoin));
         hipLaunchKernelGGL(k_join_persistent<false>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
                            w.chunk_cnt, w.inc, p.inc_cap, w.next_join);
         PDP_TRY(hipGetLastError());

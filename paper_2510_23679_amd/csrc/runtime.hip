@@ -62,7 +62,7 @@ void pdp_graph_destroy(pdp_graph *g) {
 static std::vector<pdp_params> default_candidates() {
     std::vector<pdp_params> c;
     const uint32_t lds[] = {24 * 1024, 48 * 1024, 96 * 1024, 144 * 1024};
-    const uint32_t join[] = {256, 1024, 2048};
+    const uint32_t join[] = {256, 512, 1024};
     for (uint32_t persistent = 0; persistent < 2; ++persistent)
         for (uint32_t l : lds)
             for (uint32_t j : join) {

@@ -185,7 +185,7 @@ def test_genome_without_genes():
 
 
 @pytest.mark.parametrize("prm", [dict(tile_rows=1), dict(tile_rows=7, join_entries=64),
-                                 dict(lds_budget=8192, join_entries=2048), dict(inc_capacity=100),
+                                 dict(lds_budget=8192, join_entries=1024), dict(inc_capacity=100),
                                  dict(persistent=True), dict(persistent=True, lds_budget=128 * 1024, join_entries=256)])
 def test_tuning_knobs_do_not_change_results(prm):
     say("tuning", prm)
