@@ -65,7 +65,7 @@ enum pdp_code {
  * offending size (PDP_E_LIMIT); where is the smallest residue offset
  * (PDP_E_ALPHABET), the gene index (PDP_E_LIMIT, PDP_E_INVAL) or, for
  * PDP_E_CAPACITY, the first array that overflowed in pipeline order
- * (0: shared-k-mer incidences, 1: best-hit entries, 2: BBH pairs); else
+ * (0: shared-k-mer records, 1: best-hit entries, 2: BBH pairs); else
  * UINT64_MAX.  On any error the call's outputs are unspecified. */
 typedef struct pdp_status {
     int32_t code;
@@ -190,10 +190,14 @@ typedef struct pdp_bbh_out {
 
 /* Tuning knobs; zero means "choose automatically". */
 typedef struct pdp_params {
-    uint64_t inc_capacity;   /* shared-k-mer incidences the scratch can hold (0: from the dictionary sizes) */
-    uint32_t tile_rows;      /* query genes per LDS accumulation tile */
+    uint64_t inc_capacity;   /* shared-k-mer records the scratch can hold, below 2^32: one per shared
+                                (k-mer, gene a, gene b) and requested direction (0: from the dictionary sizes) */
+    uint32_t tile_rows;      /* query genes per accumulation tile, 1..256, rounded down to a power of two
+                                (0: 64; raised when a task would have more than 1024 tiles) */
     uint32_t join_entries;   /* index entries of the larger genome per join sub-range (1..1024) */
-    uint32_t lds_budget;     /* bytes of LDS for one accumulation tile (at most 159 KiB) */
+    uint32_t lds_budget;     /* LDS bytes of a tile work-group, at most 156 KiB (0 and anything below
+                                32 KiB: 32 KiB, the sorted path's 4096 records); more lets a tile whose
+                                records overflow the sort sum more rows per dense pass */
     uint32_t flags;          /* PDP_PARAM_* */
 } pdp_params;
 /* The join and the first tile pass run as persistent kernels: a grid sized to
@@ -219,11 +223,11 @@ typedef struct pdp_plan pdp_plan;
 
 typedef struct pdp_plan_info {
     uint64_t ws_bytes;        /* device workspace pdp_plan_run needs */
-    uint64_t inc_capacity;    /* incidences the workspace holds */
+    uint64_t inc_capacity;    /* shared-k-mer records the workspace holds */
     uint32_t bh_rows;         /* rows of the combined best-hit output */
     uint32_t bbh_rows;        /* rows of the combined BBH output */
     uint32_t n_tasks;
-    uint32_t join_groups;     /* join work-groups per run */
+    uint32_t join_groups;     /* join items (bucket ranges) per run */
     uint32_t tiles;           /* accumulation tiles per run */
     uint32_t tile_lds;        /* LDS bytes per accumulation tile */
 } pdp_plan_info;
@@ -250,16 +254,16 @@ int32_t pdp_plan_upload(const pdp_plan *plan, void *ws, uint64_t ws_bytes, void 
  * be captured in a HIP graph.  bh must cover info.bh_rows rows, bbh
  * info.bbh_rows rows (bbh may be NULL if no task asks for BBH).  status is
  * device memory.  Device errors: PDP_E_CAPACITY (needed = required
- * incidences, best-hit entries or BBH pairs; retry with more).
+ * records, best-hit entries or BBH pairs; retry with more).
  * Errors: PDP_E_INVAL, PDP_E_WORKSPACE, PDP_E_HIP. */
 int32_t pdp_plan_launch(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *status,
                         void *ws, uint64_t ws_bytes, void *stream);
 
 /* Kernels of a plan launch, for pdp_plan_timer_start. */
-#define PDP_KERNEL_JOIN 0        /* shared-k-mer join of the two indexes */
-#define PDP_KERNEL_BUCKET 1      /* incidences grouped by tile (count and scatter passes together) */
-#define PDP_KERNEL_TILE_COUNT 2  /* LDS accumulation, row maxima and tie counts */
-#define PDP_KERNEL_TILE_WRITE 3  /* LDS accumulation and best-hit output */
+#define PDP_KERNEL_JOIN 0        /* shared-k-mer join: count pass, scan of the counts, write pass */
+#define PDP_KERNEL_BUCKET 1      /* the scan of the (tile, item) record counts alone */
+#define PDP_KERNEL_TILE_COUNT 2  /* per tile: sort and sum of records, row maxima, tie counts */
+#define PDP_KERNEL_TILE_WRITE 3  /* best-hit output (slab copy, rows with many ties) */
 #define PDP_KERNEL_BBH 4         /* BBH count and write passes together */
 #define PDP_KERNEL_ALL 5         /* the whole launch */
 

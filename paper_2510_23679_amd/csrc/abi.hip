@@ -252,6 +252,11 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     if (lds_budget > kMaxTileLds) return fail(PDP_E_INVAL, "lds_budget above %u bytes", kMaxTileLds);
     if (join_entries > kJoinLdsCap) return fail(PDP_E_INVAL, "join_entries above %u", kJoinLdsCap);
     if (prm.tile_rows > kTileMaxRows) return fail(PDP_E_INVAL, "tile_rows above %u", kTileMaxRows);
+    if (prm.inc_capacity > UINT32_MAX) return fail(PDP_E_LIMIT, "record capacity above 2^32 - 1");
+    uint32_t base_shift = kDefaultTileShift;  // tile rows: the largest power of two <= tile_rows
+    if (prm.tile_rows)
+        for (base_shift = 0; (2u << base_shift) <= prm.tile_rows; ++base_shift) {
+        }
     if (prm.flags & ~PDP_PARAM_PERSISTENT) return fail(PDP_E_INVAL, "unknown parameter flags 0x%x", prm.flags);
 
     pdp_plan *P = new (std::nothrow) pdp_plan();
@@ -261,8 +266,8 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         return rc;
     };
     // Pass 1, in the caller's order: validation, output row layout, tile height per direction.
-    uint64_t bh_rows = 0, bbh_rows = 0, inc_est = 0;
-    uint32_t tile_lds = 16;
+    uint64_t bh_rows = 0, bbh_rows = 0, rec_est = 0;
+    uint32_t tile_lds = std::max<uint32_t>(lds_budget, 8 * kTileCap);
     std::vector<DevTask> caller(n_tasks);
     std::vector<uint64_t> cost(n_tasks);
     for (uint32_t t = 0; t < n_tasks; ++t) {
@@ -288,31 +293,41 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         d.bpw = static_cast<uint32_t>(bpw);
         d.subs = static_cast<uint32_t>(subs);
         d.n_chunks = static_cast<uint32_t>((nb + bpw * subs - 1) / (bpw * subs));
+        uint32_t ndirs = 0;
         for (uint32_t dir = 0; dir < 2; ++dir) {
             d.row_base[dir] = UINT32_MAX;
-            d.tile_rows[dir] = 1;
+            d.tile_shift[dir] = base_shift;
+            d.tiles_n[dir] = 0;
             if (!(flags & (1u << dir))) continue;
+            ++ndirs;
             const pdp_dict *R = dir == 0 ? tk.a : tk.b;
             const pdp_dict *C = dir == 0 ? tk.b : tk.a;
-            // per row: the packed 16-bit sums plus one bitmap bit per 32-bit word
-            // (plus the column genome's window counts, 16 bits each, once per tile)
+            // a tile whose records overflow the LDS sort is summed densely: the column genome's
+            // window counts (16 bits each) and at least one row of packed 16-bit sums plus its
+            // touched-word bitmap must fit
             const uint64_t W = (uint64_t(C->n_genes) + 1) / 2;
-            const uint64_t row_words = std::max<uint64_t>(W + (W + 31) / 32, 1);
-            const uint64_t fixed_words = W + 4;
-            uint64_t T = lds_budget / 4 > fixed_words ? (lds_budget / 4 - fixed_words) / row_words : 0;
-            if (T == 0)
-                return bail(fail(PDP_E_LIMIT, "task %u: %u target genes do not fit an LDS tile of %u bytes", t,
-                                 C->n_genes, lds_budget));
-            T = std::min<uint64_t>(T, prm.tile_rows ? prm.tile_rows : kTileMaxRows);
-            T = std::max<uint64_t>(std::min<uint64_t>(T, std::max<uint32_t>(R->n_genes, 1)), 1);
-            d.tile_rows[dir] = static_cast<uint32_t>(T);
+            const uint64_t dense = 4 * (((W + 3) & ~3ull) + W + (W + 31) / 32);
+            if (dense > kMaxTileLds)
+                return bail(fail(PDP_E_LIMIT, "task %u: %u target genes do not fit an LDS tile", t, C->n_genes));
+            tile_lds = std::max<uint32_t>(tile_lds, static_cast<uint32_t>(dense));
+            d.tiles_n[dir] = static_cast<uint32_t>((uint64_t(R->n_genes) + (1u << base_shift) - 1) >> base_shift);
             d.row_base[dir] = static_cast<uint32_t>(bh_rows);
             bh_rows += R->n_genes;
-            tile_lds = std::max<uint32_t>(tile_lds, static_cast<uint32_t>(4 * (align_up(T * row_words, 4) + W) + 16));
+        }
+        // the join keeps one LDS counter per tile of the task: taller tiles when there are too many
+        while (d.tiles_n[0] + d.tiles_n[1] > kJoinTileCap) {
+            const bool can0 = d.tiles_n[0] && d.tile_shift[0] < 8, can1 = d.tiles_n[1] && d.tile_shift[1] < 8;
+            if (!can0 && !can1)
+                return bail(fail(PDP_E_LIMIT, "task %u: too many genes for %u tiles of %u rows", t, kJoinTileCap,
+                                 kTileMaxRows));
+            const uint32_t dir = can0 && (!can1 || d.tiles_n[0] >= d.tiles_n[1]) ? 0 : 1;
+            ++d.tile_shift[dir];
+            const uint32_t nrows = dir == 0 ? tk.a->n_genes : tk.b->n_genes;
+            d.tiles_n[dir] = static_cast<uint32_t>((uint64_t(nrows) + (1u << d.tile_shift[dir]) - 1) >> d.tile_shift[dir]);
         }
         d.bbh_row_base = static_cast<uint32_t>(bbh_rows);
         if (flags & PDP_TASK_BBH) bbh_rows += tk.a->n_genes;
-        inc_est += (tk.a->capacity + tk.b->capacity) / 2 + 4096;
+        rec_est += ndirs * ((tk.a->capacity + tk.b->capacity) / 2 + 4096);
         cost[t] = tk.a->capacity + tk.b->capacity;
         P->ab_row.push_back(d.row_base[0]);
         P->ba_row.push_back(d.row_base[1]);
@@ -325,27 +340,33 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     for (uint32_t t = 0; t < n_tasks; ++t) by_cost[t] = t;
     std::stable_sort(by_cost.begin(), by_cost.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
     P->order.assign(n_tasks, 0);
-    uint64_t chunks = 0;
+    uint64_t chunks = 0, cells = 0;
     for (uint32_t i = 0; i < n_tasks; ++i) {
         const uint32_t t = by_cost[i];
         P->order[t] = i;
         DevTask d = caller[t];
         d.chunk_base = static_cast<uint32_t>(chunks);
         chunks += d.n_chunks;
+        d.cell_base = static_cast<uint32_t>(cells);
+        uint32_t tile_local = 0;
         for (uint32_t dir = 0; dir < 2; ++dir) {
             d.tile_base[dir] = static_cast<uint32_t>(P->tiles.size());
             if (!(d.flags & (1u << dir))) continue;
             const uint32_t nrows = dir == 0 ? d.a.n_genes : d.b.n_genes;
-            const uint32_t T = d.tile_rows[dir];
-            for (uint32_t r0 = 0; r0 < nrows; r0 += T) {
+            const uint32_t T = 1u << d.tile_shift[dir];
+            for (uint32_t r0 = 0; r0 < nrows; r0 += T, ++tile_local) {
                 DevTile tl;
                 tl.task = i;
                 tl.dir = dir;
                 tl.row0 = r0;
                 tl.nrows = std::min<uint32_t>(T, nrows - r0);
+                tl.cell0 = static_cast<uint32_t>(cells + uint64_t(tile_local) * d.n_chunks);
+                tl.cell1 = static_cast<uint32_t>(tl.cell0 + d.n_chunks);
                 P->tiles.push_back(tl);
             }
         }
+        cells += uint64_t(tile_local) * d.n_chunks;
+        if (cells >= UINT32_MAX) return bail(fail(PDP_E_LIMIT, "plan too large for 32-bit record counts"));
         P->tasks.push_back(d);
         if (chunks > UINT32_MAX || P->tiles.size() >= UINT32_MAX)
             return bail(fail(PDP_E_LIMIT, "plan too large for 32-bit indices"));
@@ -353,10 +374,11 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     P->shape.n_tasks = n_tasks;
     P->shape.total_chunks = static_cast<uint32_t>(chunks);
     P->shape.total_tiles = static_cast<uint32_t>(P->tiles.size());
+    P->shape.total_cells = static_cast<uint32_t>(cells);
     P->shape.bh_rows = static_cast<uint32_t>(bh_rows);
     P->shape.bbh_rows = static_cast<uint32_t>(bbh_rows);
-    P->shape.tile_lds = tile_lds;
-    P->shape.inc_cap = prm.inc_capacity ? prm.inc_capacity : inc_est;
+    P->shape.tile_lds = static_cast<uint32_t>(align_up(tile_lds, 16));
+    P->shape.rec_cap = prm.inc_capacity ? prm.inc_capacity : std::min<uint64_t>(rec_est, UINT32_MAX);
     P->shape.join_grid = 0;
     P->shape.tile_grid = 0;
     P->persistent = (prm.flags & PDP_PARAM_PERSISTENT) != 0;
@@ -368,7 +390,7 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
 int32_t pdp_plan_info_get(const pdp_plan *plan, pdp_plan_info *info) {
     if (!plan || !info) return fail(PDP_E_INVAL, "pdp_plan_info_get: null pointer");
     info->ws_bytes = plan->ws_bytes;
-    info->inc_capacity = plan->shape.inc_cap;
+    info->inc_capacity = plan->shape.rec_cap;
     info->bh_rows = plan->shape.bh_rows;
     info->bbh_rows = plan->shape.bbh_rows;
     info->n_tasks = plan->shape.n_tasks;

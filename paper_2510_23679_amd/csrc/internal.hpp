@@ -22,12 +22,19 @@ constexpr uint32_t kIxBlock = 4096;          // index entries per histogram bloc
 constexpr uint32_t kIxBinTarget = 1024;      // average index entries per coarse bin
 constexpr uint32_t kIxBinLds = 2048;         // coarse bins up to this size are sorted in LDS
 constexpr uint32_t kIxMaxBins = 8192;        // coarse bins per genome at most (LDS histogram)
-constexpr uint32_t kJoinLdsCap = 1024;       // index entries per side staged in LDS per join sub-range
+constexpr uint32_t kJoinLdsCap = 1024;       // target index entries staged in LDS per join sub-range
 constexpr uint32_t kJoinDirCap = 1024;       // leading-residue buckets per join item (sub-ranges x buckets)
-constexpr uint32_t kTileMaxRows = 64;        // rows per accumulation tile
+constexpr uint32_t kJoinTileCap = 1024;      // accumulation tiles per task (one LDS counter each in the join)
+constexpr uint32_t kTileMaxRows = 256;       // rows per accumulation tile (8-bit row field of a record)
+constexpr uint32_t kDefaultTileShift = 6;    // 64 rows per tile unless tuned
 constexpr uint32_t kTileThreads = 256;
-constexpr uint32_t kDefaultLdsBudget = 48 * 1024;
-constexpr uint32_t kMaxTileLds = 160 * 1024 - 1024;  // gfx950 LDS per work-group, less the static part
+constexpr uint32_t kTileCap = 4096;          // records a tile sorts in LDS (8 bytes each)
+constexpr uint32_t kTilePer = kTileCap / kTileThreads;
+constexpr uint32_t kHashBits = 12;           // LDS hash table of a tile: 2^12 slots, 8 bytes each
+constexpr uint32_t kHashSlots = 1u << kHashBits;
+constexpr uint32_t kHashMax = kHashSlots * 3 / 4;  // records one table pass takes (load factor <= 3/4)
+constexpr uint32_t kDefaultLdsBudget = 8 * kTileCap;
+constexpr uint32_t kMaxTileLds = 160 * 1024 - 4096;  // gfx950 LDS per work-group, less the static part
 constexpr uint32_t kSlab = 4;                // best hits per row kept by the first tile pass
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
@@ -57,12 +64,14 @@ struct DevTask {
     uint32_t flags;
     uint32_t bpw;           // buckets per join sub-range
     uint32_t subs;          // sub-ranges per join item
-    uint32_t chunk_base;    // first join group of the task
-    uint32_t n_chunks;
-    uint32_t tile_rows[2];  // rows per tile, direction 0 (a rows) and 1 (b rows)
+    uint32_t chunk_base;    // first join item of the task
+    uint32_t n_chunks;      // join items of the task
+    uint32_t tile_shift[2]; // rows per tile = 2^tile_shift, direction 0 (a rows) and 1 (b rows)
+    uint32_t tiles_n[2];    // tiles per direction (0 when the direction is not requested)
     uint32_t tile_base[2];  // first tile of each direction
     uint32_t row_base[2];   // first best-hit row of each direction (UINT32_MAX: none)
     uint32_t bbh_row_base;  // first BBH row (UINT32_MAX: none)
+    uint32_t cell_base;     // first cell of the task's (tile, item) record-count matrix
 };
 
 struct DevTile {
@@ -70,6 +79,7 @@ struct DevTile {
     uint32_t dir;
     uint32_t row0;
     uint32_t nrows;
+    uint32_t cell0, cell1;  // its records: scanned cells[cell0] .. cells[cell1]
 };
 
 // ------------------------------------------------------------- launchers
@@ -112,25 +122,22 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
 struct PairWs {
     DevTask *tasks;
     DevTile *tiles;
-    uint4 *inc;                   // incidences (task, row gene of a, gene of b, min count)
-    unsigned long long *counters; // [0] incidences
-    uint32_t *tile_cnt;           // tiles + 1 (scanned in place into offsets)
-    uint32_t *tile_fill;          // tiles
-    uint2 *recs;                  // incidences bucketed by tile: ((row<<24)|col, v); 2x capacity
+    uint2 *recs;                  // records grouped by tile: ((row in tile << 24) | column, min count)
+    unsigned long long *counters; // [0] records counted by the join
+    uint32_t *cells;              // (tile, item) record counts, scanned in place into slots; + 1
     uint4 *slab;                  // kSlab (column, m, d, -) per best-hit row
     uint32_t *overflow_tiles;     // tiles holding a row with more than kSlab ties
     uint32_t *overflow_count;     // counters word 2
     uint32_t *next_join;          // counters word 3: next item of the persistent join
     uint32_t *next_tile;          // counters word 4: next tile of the persistent tile pass
     uint32_t *next_join_write;    // counters word 5: next item of the persistent join's write pass
-    uint32_t *chunk_cnt;          // join items + 1: incidences per item, scanned into offsets
     uint32_t *order;              // task table indices in the caller's order
     uint32_t *partials;
 };
 
 struct PlanShape {
-    uint32_t n_tasks, total_chunks, total_tiles, bh_rows, bbh_rows, tile_lds;
-    uint64_t inc_cap;
+    uint32_t n_tasks, total_chunks, total_tiles, total_cells, bh_rows, bbh_rows, tile_lds;
+    uint64_t rec_cap;               // records the scratch holds
     uint32_t join_grid, tile_grid;  // persistent grids (0: one work-group per item)
 };
 // Records the message that pdp_last_error() returns on this thread; returns code.

@@ -3,21 +3,27 @@
 // For a genome pair (A, B) the similarity of Eq. jaccard_k needs, for every
 // gene pair, m = sum over shared k-mers of min(mult_a, mult_b); the sum of
 // maxima over the union is then n_a + n_b - m (max + min = x + y per k-mer).
-// The path never forms the |A| x |B| matrix in HBM:
-//  1. k_join: both genomes' inverted indexes are sorted by code and split into
-//     the same leading-residue bucket ranges; one work-group joins one range
-//     (target side staged in LDS) and emits an incidence (a, b, min count) per
-//     shared (k-mer, gene a, gene b).  Reads are sequential in both indexes.
-//  2. k_inc_bucket: incidences are grouped by accumulation tile (T rows of the
-//     query genome) with a counting sort; each pair contributes to the tiles
-//     of both directions.
-//  3. k_tile: one work-group per tile accumulates m for its T rows against all
-//     columns in LDS (two 16-bit sums per 32-bit word), then one wave per row
-//     finds the row maximum of J = m/d by exact cross-multiplication and
-//     counts or writes every column that reaches it (ties kept, ascending
-//     column order; an all-zero row has no best hit), following Eq. best_hit
-//     and the per-row work of Alg. 2.
-//  4. k_bbh: each best hit (a, b) is kept when a is among b's best hits
+// The path never forms the |A| x |B| matrix, in HBM or in LDS:
+//  1. k_join (count pass): both genomes' inverted indexes are sorted by code
+//     and split into the same leading-residue bucket ranges.  A work-group
+//     takes one range ("item"), stages the target side in LDS, finds the
+//     partners of every query entry through the bucket directory, and counts
+//     the records each accumulation tile (2^s rows of one direction) will get
+//     from this item.  Counts form a (tile, item) matrix per task.
+//  2. An exclusive scan of that matrix (tile-major) gives every (tile, item)
+//     cell its slot range, so each tile's records end up contiguous.
+//  3. k_join (write pass) repeats the join and writes, per shared (k-mer,
+//     gene a, gene b), a record (row in tile, column, min count) for each
+//     requested direction into its tile's range; positions come from LDS
+//     cursors seeded by the scan, so no global atomics are involved.
+//  4. k_tile: one work-group per tile sorts the tile's records by (row,
+//     column) in LDS, sums each run into m, and one wave per row finds the row
+//     maximum of J = m/d by exact cross-multiplication and counts or writes
+//     every column that reaches it (ties kept, ascending column order; a row
+//     without shared k-mers has no best hit), following Eq. best_hit and the
+//     per-row work of Alg. 2.  A tile with more records than LDS holds is
+//     summed densely instead, a few rows per pass.
+//  5. k_bbh: each best hit (a, b) is kept when a is among b's best hits
 //     (Eq. bidirectional_best_hit, the cross-check of Alg. 3).
 // Counts, scans and writes keep every output in a canonical order, so results
 // do not depend on scheduling.
@@ -30,27 +36,25 @@
 namespace pdp {
 
 constexpr uint32_t kJoinThreads = 256;
-constexpr uint32_t kBucketGroups = 1024;
+static_assert(kTilePer * (kTileThreads / kWave) <= kWave, "tile head counts are scanned by one wave");
 
 // LDS of one join item: the task descriptor, the item's slice of both bucket
-// directories, and one sub-range of both sides' codes (the count pass needs no more;
-// the write pass also stages the target side's genes and counts).
+// directories, one counter per tile of the task, and one sub-range of the
+// target side (codes and genes; the write pass also stages the counts).
 struct JoinLdsBase {
     DevTask task;
     uint32_t adir[kJoinDirCap + 1];
     uint32_t bdir[kJoinDirCap + 1];
+    uint32_t tcount[kJoinTileCap];  // count pass: records per tile; write pass: next slot per tile
     uint32_t scan[kJoinThreads / kWave + 1];
     uint32_t found;
     uint32_t next;
 };
 struct JoinLdsCount : JoinLdsBase {
     uint64_t bcode[kJoinLdsCap];
-    uint64_t acode[kJoinLdsCap];
-};
-struct JoinLdsWrite : JoinLdsBase {
-    uint64_t bcode[kJoinLdsCap];
-    uint64_t acode[kJoinLdsCap];
     uint32_t bgene[kJoinLdsCap];
+};
+struct JoinLdsWrite : JoinLdsCount {
     uint32_t bcnt[kJoinLdsCap];
 };
 template <bool WRITE>
@@ -76,54 +80,67 @@ __device__ __forceinline__ uint32_t find_task_coop(const DevTask *tasks, uint32_
     return lo;
 }
 
-// Query entries [a0, a1) of genome a (codes ac, indexed from a0) against the target
-// entries of the same bucket range (bc/bg/bn, nbe entries sorted by code): a binary
-// search per query entry.  WRITE = false returns the number of incidences; WRITE = true
-// writes them from out_base on in a fixed order (blocks of kJoinThreads query entries,
-// thread order within a block), so positions need no atomics.  Contains barriers.
+// Query entries [a0, a1) of genome a against the target entries staged from b0 on
+// (bc/bg/bn, indexed relative to b0).  The partners of a query code lie in its
+// leading-residue bucket, whose target range the directory slice bdir gives (index
+// bucket - bl); a binary search inside that bucket finds the first equal code.
+// WRITE = false adds the records each tile will receive to tcount; WRITE = true
+// takes slots from the tcount cursors and writes the records.  No barriers.
 template <bool WRITE>
-__device__ __forceinline__ uint32_t join_range(const DevTask &T, uint32_t task, uint32_t a0, uint32_t a1,
-                                               const uint64_t *ac, const uint64_t *bc, const uint32_t *bg,
-                                               const uint32_t *bn, uint32_t nbe, uint4 *inc, uint64_t out_base,
-                                               uint64_t inc_cap, uint32_t *scan_tmp) {
-    uint32_t done = 0;
-    for (uint32_t base = a0; base < a1; base += kJoinThreads) {
-        const uint32_t i = base + threadIdx.x;
-        const bool valid = i < a1;
-        const uint64_t code = valid ? ac[i - a0] : 0;
-        uint32_t lo = 0, hi = valid ? nbe : 0;
+__device__ __forceinline__ void join_range(const DevTask &T, uint32_t a0, uint32_t a1, uint32_t b0, uint32_t nbe,
+                                           const uint64_t *bc, const uint32_t *bg, const uint32_t *bn,
+                                           const uint32_t *bdir, uint32_t bl, uint32_t *tcount, uint2 *recs,
+                                           uint64_t rec_cap) {
+    const uint32_t k = T.a.k, lead = k < 4 ? k : 4;
+    const bool ab = T.flags & 1u, ba = T.flags & 2u;
+    const uint32_t s0 = T.tile_shift[0], s1 = T.tile_shift[1], t1 = T.tiles_n[0];
+    for (uint32_t i = a0 + threadIdx.x; i < a1; i += kJoinThreads) {
+        const uint64_t code = T.a.ix_code[i];
+        const uint32_t u = bucket_of(code, k, lead) - bl;
+        const uint32_t end = min(bdir[u + 1] - b0, nbe);  // the bucket lies inside the staged range
+        uint32_t lo = min(bdir[u] - b0, end);
+        uint32_t hi = end;
         while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
             if (bc[mid] < code) lo = mid + 1;
             else hi = mid;
         }
         uint32_t m = 0;
-        if (valid)
-            while (lo + m < nbe && bc[lo + m] == code) ++m;
-        uint32_t total;
-        const uint32_t before = block_exclusive_scan<kJoinThreads>(m, scan_tmp, &total);
-        if (WRITE && m) {
-            const uint32_t ag = T.a.ix_gene[i], an = T.a.ix_cnt[i];
-            const uint64_t slot = out_base + done + before;
-            for (uint32_t t = 0; t < m; ++t) {
-                if (slot + t < inc_cap) inc[slot + t] = make_uint4(task, ag, bg[lo + t], min(an, bn[lo + t]));
+        while (lo + m < end && bc[lo + m] == code) ++m;
+        if (!m) continue;
+        const uint32_t ag = T.a.ix_gene[i];
+        if (!WRITE) {
+            if (ab) atomicAdd(&tcount[ag >> s0], m);
+            if (ba)
+                for (uint32_t t = 0; t < m; ++t) atomicAdd(&tcount[t1 + (bg[lo + t] >> s1)], 1u);
+        } else {
+            const uint32_t an = T.a.ix_cnt[i];
+            if (ab) {
+                const uint32_t p = atomicAdd(&tcount[ag >> s0], m);
+                const uint32_t rl = (ag & ((1u << s0) - 1u)) << 24;
+                for (uint32_t t = 0; t < m; ++t)
+                    if (p + t < rec_cap) recs[p + t] = make_uint2(rl | bg[lo + t], min(an, bn[lo + t]));
+            }
+            if (ba) {
+                for (uint32_t t = 0; t < m; ++t) {
+                    const uint32_t g = bg[lo + t];
+                    const uint32_t p = atomicAdd(&tcount[t1 + (g >> s1)], 1u);
+                    if (p < rec_cap) recs[p] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | ag, min(an, bn[lo + t]));
+                }
             }
         }
-        done += total;
     }
-    return done;
 }
 
 // One join item: up to T.subs consecutive sub-ranges of T.bpw leading-residue buckets of
-// one task.  Pass WRITE = false stores the item's incidence count in chunk_cnt[chunk];
-// WRITE = true writes the incidences from the scanned offset chunk_cnt[chunk] on.  The
-// task descriptor and the directory slice arrive in one round trip, then each sub-range
-// stages both sides in LDS when they fit.  Ends with a barrier so the LDS can take the
+// one task.  The count pass stores the item's column of the task's (tile, item) count
+// matrix and adds its total to *total; the write pass seeds its tile cursors from the
+// scanned matrix and writes the records.  Ends with a barrier so the LDS can take the
 // next item.
 template <bool WRITE>
 __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__restrict__ tasks, uint32_t n_tasks,
-                                           uint32_t *__restrict__ chunk_cnt, uint4 *__restrict__ inc, uint64_t inc_cap,
-                                           JoinLds<WRITE> &L) {
+                                           uint32_t *__restrict__ cells, unsigned long long *__restrict__ total,
+                                           uint2 *__restrict__ recs, uint64_t rec_cap, JoinLds<WRITE> &L) {
     const uint32_t task = find_task_coop(tasks, n_tasks, chunk, &L.found);
     {
         const uint32_t *src = reinterpret_cast<const uint32_t *>(&tasks[task]);
@@ -137,67 +154,83 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
     const uint32_t span = T.bpw * T.subs;
     const uint32_t bl = c * span;
     const uint32_t bh = min(nb, bl + span);
+    const uint32_t ntiles = T.tiles_n[0] + T.tiles_n[1];
     for (uint32_t i = threadIdx.x; i <= bh - bl; i += blockDim.x) {
         L.adir[i] = T.a.ix_dir[bl + i];
         L.bdir[i] = T.b.ix_dir[bl + i];
     }
-    uint64_t out = WRITE ? chunk_cnt[chunk] : 0;
+    for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x)
+        L.tcount[t] = WRITE ? cells[T.cell_base + static_cast<uint64_t>(t) * T.n_chunks + c] : 0u;
     __syncthreads();
-    uint32_t n = 0;
     for (uint32_t s0 = bl; s0 < bh; s0 += T.bpw) {
         const uint32_t s1 = min(bh, s0 + T.bpw);
         const uint32_t a0 = L.adir[s0 - bl], a1 = L.adir[s1 - bl];
         const uint32_t b0 = L.bdir[s0 - bl], b1 = L.bdir[s1 - bl];
         if (a0 == a1 || b0 == b1) continue;  // uniform across the work-group
-        const uint32_t nbe = b1 - b0, nae = a1 - a0;
-        uint32_t got;
-        if (nbe <= kJoinLdsCap && nae <= kJoinLdsCap) {
+        const uint32_t nbe = b1 - b0;
+        if (nbe <= kJoinLdsCap) {
             for (uint32_t i = threadIdx.x; i < nbe; i += kJoinThreads) {
                 L.bcode[i] = T.b.ix_code[b0 + i];
-                if constexpr (WRITE) {
-                    L.bgene[i] = T.b.ix_gene[b0 + i];
-                    L.bcnt[i] = T.b.ix_cnt[b0 + i];
-                }
+                L.bgene[i] = T.b.ix_gene[b0 + i];
+                if constexpr (WRITE) L.bcnt[i] = T.b.ix_cnt[b0 + i];
             }
-            for (uint32_t i = threadIdx.x; i < nae; i += kJoinThreads) L.acode[i] = T.a.ix_code[a0 + i];
             __syncthreads();
             if constexpr (WRITE)
-                got = join_range<true>(T, task, a0, a1, L.acode, L.bcode, L.bgene, L.bcnt, nbe, inc, out, inc_cap,
-                                       L.scan);
+                join_range<true>(T, a0, a1, b0, nbe, L.bcode, L.bgene, L.bcnt, L.bdir, bl, L.tcount, recs, rec_cap);
             else
-                got = join_range<false>(T, task, a0, a1, L.acode, L.bcode, nullptr, nullptr, nbe, inc, out, inc_cap,
-                                        L.scan);
+                join_range<false>(T, a0, a1, b0, nbe, L.bcode, L.bgene, nullptr, L.bdir, bl, L.tcount, recs, rec_cap);
+            __syncthreads();  // the staged arrays take the next sub-range
         } else {
-            got = join_range<WRITE>(T, task, a0, a1, T.a.ix_code + a0, T.b.ix_code + b0, T.b.ix_gene + b0,
-                                    T.b.ix_cnt + b0, nbe, inc, out, inc_cap, L.scan);
+            join_range<WRITE>(T, a0, a1, b0, nbe, T.b.ix_code + b0, T.b.ix_gene + b0, T.b.ix_cnt + b0, L.bdir, bl,
+                              L.tcount, recs, rec_cap);
         }
-        n += got;
-        out += got;
-        __syncthreads();  // the staged arrays take the next sub-range
     }
-    if (!WRITE && threadIdx.x == 0) chunk_cnt[chunk] = n;
+    if (!WRITE) {
+        __syncthreads();
+        uint32_t mine = 0;
+        for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
+            const uint32_t v = L.tcount[t];
+            cells[T.cell_base + static_cast<uint64_t>(t) * T.n_chunks + c] = v;
+            mine += v;
+        }
+        uint32_t sum;
+        (void)block_exclusive_scan<kJoinThreads>(mine, L.scan, &sum);
+        if (threadIdx.x == 0 && sum) atomicAdd(total, static_cast<unsigned long long>(sum));
+    }
     __syncthreads();
+}
+
+// The write pass stops when the records do not fit; the count pass's total is then the
+// capacity needed.
+__device__ __forceinline__ bool join_overflow(const unsigned long long *total, uint64_t rec_cap, pdp_status *st) {
+    const unsigned long long n = *total;
+    if (n <= rec_cap) return false;
+    if (blockIdx.x == 0 && threadIdx.x == 0) raise_status(st, PDP_E_CAPACITY, n, 0);
+    return true;
 }
 
 template <bool WRITE>
 __global__ __launch_bounds__(kJoinThreads) void k_join(const DevTask *__restrict__ tasks, uint32_t n_tasks,
-                                                       uint32_t *__restrict__ chunk_cnt, uint4 *__restrict__ inc,
-                                                       uint64_t inc_cap) {
+                                                       uint32_t *__restrict__ cells, unsigned long long *__restrict__ total,
+                                                       uint2 *__restrict__ recs, uint64_t rec_cap, pdp_status *st) {
     __shared__ JoinLds<WRITE> L;
-    join_chunk<WRITE>(blockIdx.x, tasks, n_tasks, chunk_cnt, inc, inc_cap, L);
+    if (WRITE && join_overflow(total, rec_cap, st)) return;
+    join_chunk<WRITE>(blockIdx.x, tasks, n_tasks, cells, total, recs, rec_cap, L);
 }
 
-// Persistent form: a fixed grid claims join items kClaim at a time from a counter
+// Persistent form: a fixed grid claims join items kClaimJoin at a time from a counter
 // (one atomic per claim, not per item) until none are left.
 constexpr uint32_t kClaim = 8;
 constexpr uint32_t kClaimJoin = 2;
 
 template <bool WRITE>
 __global__ __launch_bounds__(kJoinThreads) void k_join_persistent(const DevTask *__restrict__ tasks, uint32_t n_tasks,
-                                                                  uint32_t total_chunks, uint32_t *__restrict__ chunk_cnt,
-                                                                  uint4 *__restrict__ inc, uint64_t inc_cap,
-                                                                  uint32_t *__restrict__ next) {
+                                                                  uint32_t total_chunks, uint32_t *__restrict__ cells,
+                                                                  unsigned long long *__restrict__ total,
+                                                                  uint2 *__restrict__ recs, uint64_t rec_cap,
+                                                                  pdp_status *st, uint32_t *__restrict__ next) {
     __shared__ JoinLds<WRITE> L;
+    if (WRITE && join_overflow(total, rec_cap, st)) return;
     for (;;) {
         if (threadIdx.x == 0) L.next = atomicAdd(next, kClaimJoin);
         __syncthreads();
@@ -206,38 +239,7 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_persistent(const DevTask 
         if (first >= total_chunks) break;
         const uint32_t last = min(total_chunks, first + kClaimJoin);
         for (uint32_t chunk = first; chunk < last; ++chunk)
-            join_chunk<WRITE>(chunk, tasks, n_tasks, chunk_cnt, inc, inc_cap, L);
-    }
-}
-
-template <bool SCATTER>
-__global__ __launch_bounds__(256) void k_inc_bucket(const DevTask *__restrict__ tasks, const uint4 *__restrict__ inc,
-                                                    const uint32_t *__restrict__ inc_total, uint64_t inc_cap,
-                                                    uint32_t *__restrict__ tile_cnt, const uint32_t *__restrict__ tile_off,
-                                                    uint32_t *__restrict__ tile_fill, uint2 *__restrict__ recs,
-                                                    pdp_status *st) {
-    const uint64_t total = *inc_total;
-    if (!SCATTER && blockIdx.x == 0 && threadIdx.x == 0 && total > inc_cap) raise_status(st, PDP_E_CAPACITY, total, 0);
-    const uint64_t n = total < inc_cap ? total : inc_cap;
-    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        const uint4 r = inc[i];
-        const DevTask &T = tasks[r.x];
-#pragma unroll
-        for (uint32_t d = 0; d < 2; ++d) {
-            if (!(T.flags & (1u << d))) continue;
-            const uint32_t row = d == 0 ? r.y : r.z;
-            const uint32_t col = d == 0 ? r.z : r.y;
-            const uint32_t tr = T.tile_rows[d];
-            const uint32_t q = row / tr;
-            const uint32_t tile = T.tile_base[d] + q;
-            if (!SCATTER) {
-                atomicAdd(&tile_cnt[tile], 1u);
-            } else {
-                const uint32_t pos = tile_off[tile] + atomicAdd(&tile_fill[tile], 1u);
-                recs[pos] = make_uint2(((row - q * tr) << 24) | col, r.w);
-            }
-        }
+            join_chunk<WRITE>(chunk, tasks, n_tasks, cells, total, recs, rec_cap, L);
     }
 }
 
@@ -248,181 +250,479 @@ __device__ __forceinline__ bool j_equal(uint32_t m1, uint32_t d1, uint32_t m2, u
     return static_cast<uint64_t>(m1) * d2 == static_cast<uint64_t>(m2) * d1;
 }
 
-// One accumulation tile: T rows of one direction of one task against every
-// column of the other genome.  LDS holds the sums of minima (two 16-bit sums
-// per 32-bit word) and a bitmap with one bit per word that has been touched,
-// so a row's maximum and ties cost time in proportion to its touched columns.
-// One wave per row: pass 1 finds the exact maximum of m/d (64-bit
-// cross-multiplication); pass 2 emits every column at the maximum in
-// ascending order (lanes own ascending, disjoint column ranges; a wave prefix
-// sum gives positions).  In the first launch (WRITE = false) the ties go to a
-// per-row slab of kSlab entries and the row's count to cnt[row]; a row with
-// more ties marks its tile, and the second launch (WRITE = true) recomputes
-// only the marked tiles and writes their rows straight into the CSR output.
+// Static LDS of a tile work-group.
+struct TileLds {
+    uint32_t rowlen[kTileMaxRows];    // distinct columns per row (sorted path)
+    uint32_t rowfirst[kTileMaxRows];  // first distinct (row, column) of the row
+    uint32_t nr[kTileMaxRows];        // window counts of the tile's rows
+    uint32_t rowcnt[kTileMaxRows];    // records per row (hashed path, when the tile overflows the table)
+    uint32_t ties[kTileMaxRows];      // columns at the row maximum (hashed path)
+    unsigned long long best[kTileMaxRows];  // row maximum as (m << 32) | d (hashed path)
+    uint32_t rank[kTilePer * (kTileThreads / kWave) + 1];
+    uint32_t flag;
+    uint32_t next;
+};
+
+// Best hits of one row, given its candidates one lane-chunk at a time in ascending
+// column order: cand(e, &c, &m, &d) yields the column, the sum of minima and the sum of
+// maxima of candidate e < n.  Pass 1 finds the exact maximum of m/d, pass 2 emits every column at the
+// maximum (ballot + prefix for positions).  WRITE = false puts the first kSlab ties in
+// the row's slab and the count in bh_ptr; WRITE = true writes all ties from the row's
+// scanned offset.  Every lane of the wave calls it.
+template <bool WRITE, typename Cand>
+__device__ __forceinline__ void emit_row(uint32_t grow, uint32_t n, Cand cand,
+                                         uint32_t *bh_ptr, uint4 *slab, uint32_t *bh_col, uint32_t *bh_num,
+                                         uint32_t *bh_den, uint64_t bh_cap, uint32_t *flag) {
+    const uint32_t lane = lane_id();
+    uint32_t bm = 0, bd = 1;
+    for (uint32_t e = lane; e < n; e += kWave) {
+        uint32_t c, m, d;
+        cand(e, &c, &m, &d);
+        if (m && j_greater(m, d, bm, bd)) {
+            bm = m;
+            bd = d;
+        }
+    }
+#pragma unroll
+    for (uint32_t o = kWave / 2; o > 0; o >>= 1) {
+        const uint32_t om = __shfl_xor(bm, o, kWave), od = __shfl_xor(bd, o, kWave);
+        if (j_greater(om, od, bm, bd)) {
+            bm = om;
+            bd = od;
+        }
+    }
+    uint32_t pos = WRITE ? bh_ptr[grow] : 0u;
+    if (bm) {
+        for (uint32_t e0 = 0; e0 < n; e0 += kWave) {
+            const uint32_t e = e0 + lane;
+            uint32_t c = 0, m = 0, d = 0;
+            bool tie = false;
+            if (e < n) {
+                cand(e, &c, &m, &d);
+                tie = m && j_equal(m, d, bm, bd);
+            }
+            const uint64_t mask = __ballot(tie);
+            const uint32_t p = pos + mask_below(mask);
+            if (tie) {
+                if (WRITE) {
+                    if (p < bh_cap) {
+                        bh_col[p] = c;
+                        bh_num[p] = m;
+                        bh_den[p] = d;
+                    }
+                } else if (p < kSlab) {
+                    slab[static_cast<uint64_t>(grow) * kSlab + p] = make_uint4(c, m, d, 0);
+                }
+            }
+            pos += static_cast<uint32_t>(__popcll(mask));
+        }
+    }
+    if (!WRITE && lane == 0) {
+        bh_ptr[grow] = pos;
+        if (pos > kSlab) *flag = 1;
+    }
+}
+
+// Sorted path: the tile's n <= kTileCap records sit in LDS as 48-bit keys (row 8 bits,
+// column 24 bits, min count 16 bits); after the sort every (row, column) is one run.
+// Each thread keeps its kTilePer keys (strided by the work-group size) in registers,
+// ranks the run heads with one ballot scan, then the key array is reused for the
+// distinct columns and their sums.
 template <bool WRITE>
-__device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__restrict__ tasks,
-                                             const DevTile *__restrict__ tiles, const uint32_t *__restrict__ tile_off,
-                                             const uint2 *__restrict__ recs, uint32_t *__restrict__ bh_ptr,
-                                             uint4 *__restrict__ slab, uint32_t *__restrict__ bh_col,
-                                             uint32_t *__restrict__ bh_num, uint32_t *__restrict__ bh_den,
-                                             uint64_t bh_cap, uint32_t *overflow_tiles, uint32_t *overflow_count,
-                                             uint32_t *lds, uint32_t *s_flag) {
-    const DevTile tl = tiles[tile_id];
-    const DevTask &T = tasks[tl.task];
+__device__ __forceinline__ void tile_sorted(const DevTile &tl, const DevTask &T, const uint2 *recs, uint64_t rb,
+                                            uint32_t n, uint32_t *bh_ptr, uint4 *slab, uint32_t *bh_col,
+                                            uint32_t *bh_num, uint32_t *bh_den, uint64_t bh_cap, uint32_t *lds,
+                                            TileLds &S) {
+    const DevDict &R = tl.dir == 0 ? T.a : T.b;
+    const DevDict &C = tl.dir == 0 ? T.b : T.a;
+    uint64_t *keys = reinterpret_cast<uint64_t *>(lds);
+    for (uint32_t r = threadIdx.x; r < tl.nrows; r += kTileThreads) S.rowlen[r] = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += kTileThreads) {
+        const uint2 r = recs[rb + i];
+        keys[i] = (static_cast<uint64_t>(r.x) << 16) | (r.y & 0xFFFFu);
+    }
+    __syncthreads();
+    wg_network_sort(n, [&](uint32_t lo, uint32_t hi) {
+        const uint64_t x = keys[lo], y = keys[hi];
+        if (x > y) {
+            keys[lo] = y;
+            keys[hi] = x;
+        }
+    });
+    const uint32_t w = threadIdx.x / kWave;
+    constexpr uint32_t NW = kTileThreads / kWave;
+    uint64_t kr[kTilePer];
+    uint32_t below[kTilePer];
+    uint32_t head = 0, rstart = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kTilePer; ++j) {
+        const uint32_t i = j * kTileThreads + threadIdx.x;
+        const bool valid = i < n;
+        const uint64_t x = valid ? keys[i] : 0;
+        const uint64_t xp = valid && i ? keys[i - 1] : 0;
+        const bool h = valid && (i == 0 || (x >> 16) != (xp >> 16));
+        const bool rs = valid && (i == 0 || (x >> 40) != (xp >> 40));
+        const uint64_t mask = __ballot(h);
+        kr[j] = x;
+        below[j] = mask_below(mask);
+        head |= static_cast<uint32_t>(h) << j;
+        rstart |= static_cast<uint32_t>(rs) << j;
+        if (lane_id() == 0) S.rank[j * NW + w] = static_cast<uint32_t>(__popcll(mask));
+    }
+    __syncthreads();
+    if (threadIdx.x < kWave) {  // exclusive scan of the kTilePer x NW head counts, chunk-major
+        const uint32_t x = threadIdx.x < kTilePer * NW ? S.rank[threadIdx.x] : 0u;
+        const uint32_t incl = wave_inclusive_sum(x);
+        if (threadIdx.x < kTilePer * NW) S.rank[threadIdx.x] = incl - x;
+        if (threadIdx.x == kWave - 1) S.rank[kTilePer * NW] = incl;
+    }
+    __syncthreads();
+    const uint32_t u = S.rank[kTilePer * NW];  // distinct (row, column)
+    uint32_t *ucol = lds;                      // (row << 24) | column, per distinct pair
+    uint32_t *msum = lds + kTileCap;           // sum of minima, per distinct pair
+    for (uint32_t r = threadIdx.x; r < u; r += kTileThreads) msum[r] = 0;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < kTilePer; ++j) {
+        const uint32_t i = j * kTileThreads + threadIdx.x;
+        if (i >= n) continue;
+        const bool h = (head >> j) & 1u;
+        const uint32_t r = S.rank[j * NW + w] + below[j] + (h ? 0u : ~0u);  // rank of the run head
+        const uint32_t row = static_cast<uint32_t>(kr[j] >> 40);
+        if (h) {
+            ucol[r] = static_cast<uint32_t>(kr[j] >> 16);
+            atomicAdd(&S.rowlen[row], 1u);
+            if ((rstart >> j) & 1u) S.rowfirst[row] = r;
+        }
+        atomicAdd(&msum[r], static_cast<uint32_t>(kr[j] & 0xFFFFu));
+    }
+    __syncthreads();
+    // window counts in one round trip for the whole tile: the column's joins its sum
+    // (both at most 16 bits), the rows' go to S.nr
+    for (uint32_t r = threadIdx.x; r < u; r += kTileThreads) msum[r] |= C.nwin[ucol[r] & 0xFFFFFFu] << 16;
+    for (uint32_t rl = threadIdx.x; rl < tl.nrows; rl += kTileThreads) S.nr[rl] = R.nwin[tl.row0 + rl];
+    __syncthreads();
+    for (uint32_t rl = w; rl < tl.nrows; rl += NW) {
+        const uint32_t len = S.rowlen[rl];
+        const uint32_t beg = len ? S.rowfirst[rl] : 0u;
+        const uint32_t nr = S.nr[rl];
+        emit_row<WRITE>(T.row_base[tl.dir] + tl.row0 + rl, len,
+                        [&](uint32_t e, uint32_t *c, uint32_t *m, uint32_t *d) {
+                            const uint32_t v = msum[beg + e];
+                            *c = ucol[beg + e] & 0xFFFFFFu;
+                            *m = v & 0xFFFFu;
+                            *d = nr + (v >> 16) - *m;
+                        },
+                        bh_ptr, slab, bh_col, bh_num, bh_den, bh_cap, &S.flag);
+    }
+}
+
+// Dense path for rows [rlo, rhi) of a tile whose records overflow LDS otherwise: the
+// column genome's window counts (16 bits each) stay in LDS, and groups of rows are
+// summed into 16-bit LDS accumulators (two per word) with a touched-word bitmap; each
+// group rescans the tile's records.  Rows visit only their touched words.
+template <bool WRITE>
+__device__ __forceinline__ void tile_dense(const DevTile &tl, const DevTask &T, const uint2 *recs, uint64_t rb,
+                                           uint32_t n, uint32_t rlo, uint32_t rhi, uint32_t lds_words,
+                                           uint32_t *bh_ptr, uint4 *slab,
+                                           uint32_t *bh_col, uint32_t *bh_num, uint32_t *bh_den, uint64_t bh_cap,
+                                           uint32_t *lds, TileLds &S) {
     const DevDict &R = tl.dir == 0 ? T.a : T.b;
     const DevDict &C = tl.dir == 0 ? T.b : T.a;
     const uint32_t ncols = C.n_genes;
-    const uint32_t W = (ncols + 1) >> 1;   // accumulator words per row
-    const uint32_t WB = (W + 31) >> 5;     // bitmap words per row
-    uint32_t *acc = lds;
-    uint32_t *bits = lds + tl.nrows * W;
-    const uint32_t words = tl.nrows * (W + WB);
-    uint4 *lds4 = reinterpret_cast<uint4 *>(lds);
-    for (uint32_t i = threadIdx.x; i < (words + 3) / 4; i += kTileThreads) lds4[i] = make_uint4(0, 0, 0, 0);
-    // window counts of the column genome, 16 bits each (at most PDP_MAX_WINDOWS)
-    uint16_t *cw = reinterpret_cast<uint16_t *>(lds + ((words + 3) & ~3u));
+    const uint32_t W = (ncols + 1) >> 1;  // accumulator words per row
+    const uint32_t WB = (W + 31) >> 5;    // bitmap words per row
+    const uint32_t cw_words = (W + 3) & ~3u;
+    uint16_t *cw = reinterpret_cast<uint16_t *>(lds);
     for (uint32_t c = threadIdx.x; c < ncols; c += kTileThreads) cw[c] = static_cast<uint16_t>(C.nwin[c]);
-    if (threadIdx.x == 0) *s_flag = 0;
-    __syncthreads();
-    const uint32_t r0 = tile_off[tile_id], r1 = tile_off[tile_id + 1];
-    for (uint32_t i = r0 + threadIdx.x; i < r1; i += kTileThreads) {
-        const uint2 r = recs[i];
-        const uint32_t rl = r.x >> 24, c = r.x & 0xFFFFFFu, w = c >> 1;
-        const uint32_t old = atomicAdd(&acc[rl * W + w], r.y << ((c & 1u) << 4));
-        if (old == 0) atomicOr(&bits[rl * WB + (w >> 5)], 1u << (w & 31u));
-    }
-    __syncthreads();
+    uint32_t *acc_base = lds + cw_words;
+    const uint32_t G = (lds_words - cw_words) / (W + WB);  // rows per pass, at least 1 by plan
     const uint32_t wave = threadIdx.x / kWave;
-    const uint32_t lane = lane_id();
-    for (uint32_t rl = wave; rl < tl.nrows; rl += kTileThreads / kWave) {
-        const uint32_t row = tl.row0 + rl;
-        const uint32_t grow = T.row_base[tl.dir] + row;
-        const uint32_t nr = R.nwin[row];
-        const uint32_t *arow = acc + rl * W;
-        const uint32_t *brow = bits + rl * WB;
-        uint32_t bm = 0, bd = 1;
-        for (uint32_t bw = lane; bw < WB; bw += kWave) {
-            uint32_t m = brow[bw];
-            while (m) {
-                const uint32_t w = (bw << 5) + (__ffs(m) - 1);
-                m &= m - 1;
-                const uint32_t v = arow[w];
-                const uint32_t m0 = v & 0xFFFFu, m1 = v >> 16;
-                if (m0) {
-                    const uint32_t d = nr + cw[2 * w] - m0;
-                    if (j_greater(m0, d, bm, bd)) { bm = m0; bd = d; }
-                }
-                if (m1) {
-                    const uint32_t d = nr + cw[2 * w + 1] - m1;
-                    if (j_greater(m1, d, bm, bd)) { bm = m1; bd = d; }
-                }
-            }
+    for (uint32_t g0 = rlo; g0 < rhi; g0 += G) {
+        const uint32_t gn = min(G, rhi - g0);
+        uint32_t *acc = acc_base;
+        uint32_t *bits = acc_base + gn * W;
+        const uint32_t words = gn * (W + WB);
+        for (uint32_t i = threadIdx.x; i < words; i += kTileThreads) acc[i] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n; i += kTileThreads) {
+            const uint2 r = recs[rb + i];
+            const uint32_t rr = (r.x >> 24) - g0;
+            if (rr >= gn) continue;
+            const uint32_t c = r.x & 0xFFFFFFu, wd = c >> 1;
+            const uint32_t old = atomicAdd(&acc[rr * W + wd], r.y << ((c & 1u) << 4));
+            if (old == 0) atomicOr(&bits[rr * WB + (wd >> 5)], 1u << (wd & 31u));
         }
-#pragma unroll
-        for (uint32_t o = kWave / 2; o > 0; o >>= 1) {
-            const uint32_t om = __shfl_xor(bm, o, kWave), od = __shfl_xor(bd, o, kWave);
-            if (j_greater(om, od, bm, bd)) { bm = om; bd = od; }
-        }
-        uint32_t pos = WRITE ? bh_ptr[grow] : 0u;
-        if (bm) {
-            for (uint32_t b0 = 0; b0 < WB; b0 += kWave) {
-                const uint32_t bw = b0 + lane;
-                const uint32_t mask = bw < WB ? brow[bw] : 0u;
-                uint32_t cnt = 0;
-                for (uint32_t m = mask; m;) {
-                    const uint32_t w = (bw << 5) + (__ffs(m) - 1);
-                    m &= m - 1;
-                    const uint32_t v = arow[w];
-                    const uint32_t m0 = v & 0xFFFFu, m1 = v >> 16;
-                    if (m0 && j_equal(m0, nr + cw[2 * w] - m0, bm, bd)) ++cnt;
-                    if (m1 && j_equal(m1, nr + cw[2 * w + 1] - m1, bm, bd)) ++cnt;
-                }
-                const uint32_t incl = wave_inclusive_sum(cnt);
-                const uint32_t total = __shfl(incl, kWave - 1, kWave);
-                uint32_t p = pos + incl - cnt;
-                for (uint32_t m = cnt ? mask : 0u; m;) {
-                    const uint32_t w = (bw << 5) + (__ffs(m) - 1);
-                    m &= m - 1;
-                    const uint32_t v = arow[w];
+        __syncthreads();
+        for (uint32_t rr = wave; rr < gn; rr += kTileThreads / kWave) {
+            const uint32_t row = tl.row0 + g0 + rr;
+            const uint32_t *arow = acc + rr * W;
+            const uint32_t *brow = bits + rr * WB;
+            // candidates: the touched words of the row, two columns each, in ascending order;
+            // a lane walks one bitmap word, so lane chunks of 64 words stay in column order
+            const uint32_t lane = lane_id();
+            const uint32_t grow = T.row_base[tl.dir] + row;
+            const uint32_t nr = R.nwin[row];
+            uint32_t bm = 0, bd = 1;
+            for (uint32_t bw = lane; bw < WB; bw += kWave) {
+                for (uint32_t msk = brow[bw]; msk;) {
+                    const uint32_t wd = (bw << 5) + (__ffs(msk) - 1);
+                    msk &= msk - 1;
+                    const uint32_t v = arow[wd];
 #pragma unroll
                     for (uint32_t h = 0; h < 2; ++h) {
-                        const uint32_t mm = h ? v >> 16 : v & 0xFFFFu;
-                        if (!mm) continue;
-                        const uint32_t c = 2 * w + h;
-                        const uint32_t d = nr + cw[c] - mm;
-                        if (!j_equal(mm, d, bm, bd)) continue;
-                        if (WRITE) {
-                            if (p < bh_cap) {
-                                bh_col[p] = c;
-                                bh_num[p] = mm;
-                                bh_den[p] = d;
-                            }
-                        } else if (p < kSlab) {
-                            slab[static_cast<uint64_t>(grow) * kSlab + p] = make_uint4(c, mm, d, 0);
+                        const uint32_t m = h ? v >> 16 : v & 0xFFFFu;
+                        if (!m) continue;
+                        const uint32_t d = nr + cw[2 * wd + h] - m;
+                        if (j_greater(m, d, bm, bd)) {
+                            bm = m;
+                            bd = d;
                         }
-                        ++p;
                     }
                 }
-                pos += total;
+            }
+#pragma unroll
+            for (uint32_t o = kWave / 2; o > 0; o >>= 1) {
+                const uint32_t om = __shfl_xor(bm, o, kWave), od = __shfl_xor(bd, o, kWave);
+                if (j_greater(om, od, bm, bd)) {
+                    bm = om;
+                    bd = od;
+                }
+            }
+            uint32_t pos = WRITE ? bh_ptr[grow] : 0u;
+            if (bm) {
+                for (uint32_t b0 = 0; b0 < WB; b0 += kWave) {
+                    const uint32_t bw = b0 + lane;
+                    const uint32_t mask = bw < WB ? brow[bw] : 0u;
+                    uint32_t cnt = 0;
+                    for (uint32_t msk = mask; msk;) {
+                        const uint32_t wd = (bw << 5) + (__ffs(msk) - 1);
+                        msk &= msk - 1;
+                        const uint32_t v = arow[wd];
+                        const uint32_t m0 = v & 0xFFFFu, m1 = v >> 16;
+                        if (m0 && j_equal(m0, nr + cw[2 * wd] - m0, bm, bd)) ++cnt;
+                        if (m1 && j_equal(m1, nr + cw[2 * wd + 1] - m1, bm, bd)) ++cnt;
+                    }
+                    const uint32_t incl = wave_inclusive_sum(cnt);
+                    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+                    uint32_t p = pos + incl - cnt;
+                    for (uint32_t msk = cnt ? mask : 0u; msk;) {
+                        const uint32_t wd = (bw << 5) + (__ffs(msk) - 1);
+                        msk &= msk - 1;
+                        const uint32_t v = arow[wd];
+#pragma unroll
+                        for (uint32_t h = 0; h < 2; ++h) {
+                            const uint32_t mm = h ? v >> 16 : v & 0xFFFFu;
+                            if (!mm) continue;
+                            const uint32_t c = 2 * wd + h;
+                            const uint32_t d = nr + cw[c] - mm;
+                            if (!j_equal(mm, d, bm, bd)) continue;
+                            if (WRITE) {
+                                if (p < bh_cap) {
+                                    bh_col[p] = c;
+                                    bh_num[p] = mm;
+                                    bh_den[p] = d;
+                                }
+                            } else if (p < kSlab) {
+                                slab[static_cast<uint64_t>(grow) * kSlab + p] = make_uint4(c, mm, d, 0);
+                            }
+                            ++p;
+                        }
+                    }
+                    pos += total;
+                }
+            }
+            if (!WRITE && lane == 0) {
+                bh_ptr[grow] = pos;
+                if (pos > kSlab) S.flag = 1;
             }
         }
-        if (!WRITE && lane == 0) {
-            bh_ptr[grow] = pos;
-            if (pos > kSlab) *s_flag = 1;
+        __syncthreads();
+    }
+}
+
+// Hashed path of the first tile launch, for rows [g0, g1) of a tile (filter: skip the
+// tile's records of other rows): the sums of minima per (row, column) collect in an LDS
+// open-addressing table of kHashSlots (key = record field + 1, so 0 marks a free slot)
+// holding at most kHashMax distinct pairs.  Then one thread per slot: the column's
+// window count is gathered (one round trip for the whole table), d = n_row + n_col - m,
+// and the row maximum of m/d is kept as (m, d) by an exact compare-and-swap loop
+// (64-bit cross-multiplication).  A second sweep counts the columns at the maximum
+// (ties) and puts the first kSlab of them, unordered, in the row's slab; the slab copy
+// orders them by column.
+__device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T, const uint2 *recs, uint64_t rb,
+                                            uint32_t n, uint32_t g0, uint32_t g1, bool filter, uint32_t *bh_ptr,
+                                            uint4 *slab, uint32_t *lds, TileLds &S) {
+    const DevDict &R = tl.dir == 0 ? T.a : T.b;
+    const DevDict &C = tl.dir == 0 ? T.b : T.a;
+    uint32_t *hk = lds;
+    uint32_t *hv = lds + kHashSlots;
+    uint4 *z = reinterpret_cast<uint4 *>(lds);
+    for (uint32_t i = threadIdx.x; i < kHashSlots / 2; i += kTileThreads) z[i] = make_uint4(0, 0, 0, 0);
+    for (uint32_t rl = g0 + threadIdx.x; rl < g1; rl += kTileThreads) {
+        S.best[rl] = 0;
+        S.ties[rl] = 0;
+        S.nr[rl] = R.nwin[tl.row0 + rl];
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += kTileThreads) {
+        const uint2 r = recs[rb + i];
+        if (filter && (r.x >> 24) - g0 >= g1 - g0) continue;
+        const uint32_t key = r.x + 1;  // columns stay below 2^24 - 1, so no wrap to 0
+        uint32_t h = (key * 2654435761u) >> (32 - kHashBits);
+        for (;;) {  // ends: at most kHashMax < kHashSlots keys are distinct
+            const uint32_t prev = atomicCAS(&hk[h], 0u, key);
+            if (prev == 0u || prev == key) break;
+            h = (h + 1) & (kHashSlots - 1);
+        }
+        atomicAdd(&hv[h], r.y);
+    }
+    __syncthreads();
+    for (uint32_t sl = threadIdx.x; sl < kHashSlots; sl += kTileThreads) {
+        const uint32_t key = hk[sl];
+        if (!key) continue;
+        const uint32_t rl = (key - 1) >> 24, c = (key - 1) & 0xFFFFFFu;
+        const uint32_t m = hv[sl];  // at most PDP_MAX_WINDOWS
+        const uint32_t nc = C.nwin[c];
+        hv[sl] = m | (nc << 16);
+        const uint32_t d = S.nr[rl] + nc - m;
+        const unsigned long long want = (static_cast<unsigned long long>(m) << 32) | d;
+        unsigned long long cur = S.best[rl];
+        for (;;) {
+            const uint32_t om = static_cast<uint32_t>(cur >> 32), od = static_cast<uint32_t>(cur);
+            if (om && !j_greater(m, d, om, od)) break;
+            const unsigned long long prev = atomicCAS(&S.best[rl], cur, want);
+            if (prev == cur) break;
+            cur = prev;
         }
     }
     __syncthreads();
-    if (!WRITE && threadIdx.x == 0 && *s_flag) overflow_tiles[atomicAdd(overflow_count, 1u)] = tile_id;
+    const uint32_t rbase = T.row_base[tl.dir] + tl.row0;
+    for (uint32_t sl = threadIdx.x; sl < kHashSlots; sl += kTileThreads) {
+        const uint32_t key = hk[sl];
+        if (!key) continue;
+        const uint32_t rl = (key - 1) >> 24, c = (key - 1) & 0xFFFFFFu;
+        const uint32_t v = hv[sl];
+        const uint32_t m = v & 0xFFFFu, d = S.nr[rl] + (v >> 16) - m;
+        const unsigned long long b = S.best[rl];
+        if (!j_equal(m, d, static_cast<uint32_t>(b >> 32), static_cast<uint32_t>(b))) continue;
+        const uint32_t t = atomicAdd(&S.ties[rl], 1u);
+        if (t < kSlab) slab[static_cast<uint64_t>(rbase + rl) * kSlab + t] = make_uint4(c, m, d, 0);
+    }
+    __syncthreads();
+    for (uint32_t rl = g0 + threadIdx.x; rl < g1; rl += kTileThreads) {
+        const uint32_t cnt = S.ties[rl];
+        bh_ptr[rbase + rl] = cnt;
+        if (cnt > kSlab) S.flag = 1;
+    }
+    __syncthreads();  // the table takes the next row group
+}
+
+// One tile: its records are cells[cell0] .. cells[cell1] of the scanned count matrix
+// (clamped to the record capacity, so a capacity overflow reads no further).  The first
+// launch (WRITE = false) hashes the tile, or, past kHashMax records, groups of whole rows
+// that fit the table (a row alone beyond it is summed densely); ties go to per-row slabs
+// and counts to bh_ptr, and a tile with a row of more than kSlab ties is listed for the
+// second launch (WRITE = true), which recomputes it by sorting (or densely) and writes
+// its rows straight into the CSR output in column order.
+template <bool WRITE>
+__device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__restrict__ tasks,
+                                             const DevTile *__restrict__ tiles, const uint32_t *__restrict__ cells,
+                                             const uint2 *__restrict__ recs, uint64_t rec_cap, uint32_t lds_words,
+                                             uint32_t *__restrict__ bh_ptr, uint4 *__restrict__ slab,
+                                             uint32_t *__restrict__ bh_col, uint32_t *__restrict__ bh_num,
+                                             uint32_t *__restrict__ bh_den, uint64_t bh_cap, uint32_t *overflow_tiles,
+                                             uint32_t *overflow_count, uint32_t *lds, TileLds &S) {
+    const DevTile tl = tiles[tile_id];
+    const DevTask &T = tasks[tl.task];
+    const uint64_t c0 = cells[tl.cell0], c1 = cells[tl.cell1];
+    const uint64_t rb = min(c0, rec_cap);
+    const uint64_t re = max(rb, min(c1, rec_cap));
+    const uint32_t n = static_cast<uint32_t>(re - rb);
+    if (threadIdx.x == 0) S.flag = 0;
+    __syncthreads();
+    if (WRITE) {
+        if (n <= kTileCap)
+            tile_sorted<true>(tl, T, recs, rb, n, bh_ptr, slab, bh_col, bh_num, bh_den, bh_cap, lds, S);
+        else
+            tile_dense<true>(tl, T, recs, rb, n, 0, tl.nrows, lds_words, bh_ptr, slab, bh_col, bh_num, bh_den, bh_cap,
+                             lds, S);
+    } else if (n <= kHashMax) {
+        tile_hashed(tl, T, recs, rb, n, 0, tl.nrows, false, bh_ptr, slab, lds, S);
+    } else {
+        for (uint32_t rl = threadIdx.x; rl < tl.nrows; rl += kTileThreads) S.rowcnt[rl] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n; i += kTileThreads) atomicAdd(&S.rowcnt[recs[rb + i].x >> 24], 1u);
+        __syncthreads();
+        // every thread walks the same counts, so the group loop is uniform
+        for (uint32_t g0 = 0; g0 < tl.nrows;) {
+            if (S.rowcnt[g0] > kHashMax) {
+                tile_dense<false>(tl, T, recs, rb, n, g0, g0 + 1, lds_words, bh_ptr, slab, nullptr, nullptr, nullptr, 0,
+                                  lds, S);
+                ++g0;
+                continue;
+            }
+            uint32_t g1 = g0, sum = 0;
+            while (g1 < tl.nrows && sum + S.rowcnt[g1] <= kHashMax) sum += S.rowcnt[g1++];
+            tile_hashed(tl, T, recs, rb, n, g0, g1, true, bh_ptr, slab, lds, S);
+            g0 = g1;
+        }
+    }
+    __syncthreads();
+    if (!WRITE && threadIdx.x == 0 && S.flag) overflow_tiles[atomicAdd(overflow_count, 1u)] = tile_id;
     __syncthreads();
 }
 
 __global__ __launch_bounds__(kTileThreads) void k_tile_count(const DevTask *__restrict__ tasks,
                                                              const DevTile *__restrict__ tiles,
-                                                             const uint32_t *__restrict__ tile_off,
-                                                             const uint2 *__restrict__ recs, uint32_t *__restrict__ bh_ptr,
+                                                             const uint32_t *__restrict__ cells,
+                                                             const uint2 *__restrict__ recs, uint64_t rec_cap,
+                                                             uint32_t lds_words, uint32_t *__restrict__ bh_ptr,
                                                              uint4 *__restrict__ slab, uint32_t *overflow_tiles,
                                                              uint32_t *overflow_count) {
     extern __shared__ uint32_t lds[];
-    __shared__ uint32_t s_flag;
-    tile_process<false>(blockIdx.x, tasks, tiles, tile_off, recs, bh_ptr, slab, nullptr, nullptr, nullptr, 0,
-                        overflow_tiles, overflow_count, lds, &s_flag);
+    __shared__ TileLds S;
+    tile_process<false>(blockIdx.x, tasks, tiles, cells, recs, rec_cap, lds_words, bh_ptr, slab, nullptr, nullptr,
+                        nullptr, 0, overflow_tiles, overflow_count, lds, S);
 }
 
 // Persistent form: a fixed grid pulls tiles from a counter until none are left.
 __global__ __launch_bounds__(kTileThreads) void k_tile_count_persistent(
     const DevTask *__restrict__ tasks, const DevTile *__restrict__ tiles, uint32_t total_tiles,
-    const uint32_t *__restrict__ tile_off, const uint2 *__restrict__ recs, uint32_t *__restrict__ bh_ptr,
-    uint4 *__restrict__ slab, uint32_t *overflow_tiles, uint32_t *overflow_count, uint32_t *__restrict__ next) {
+    const uint32_t *__restrict__ cells, const uint2 *__restrict__ recs, uint64_t rec_cap, uint32_t lds_words,
+    uint32_t *__restrict__ bh_ptr, uint4 *__restrict__ slab, uint32_t *overflow_tiles, uint32_t *overflow_count,
+    uint32_t *__restrict__ next) {
     extern __shared__ uint32_t lds[];
-    __shared__ uint32_t s_flag, s_next;
+    __shared__ TileLds S;
     for (;;) {
-        if (threadIdx.x == 0) s_next = atomicAdd(next, kClaim);
+        if (threadIdx.x == 0) S.next = atomicAdd(next, kClaim);
         __syncthreads();
-        const uint32_t first = s_next;
+        const uint32_t first = S.next;
         __syncthreads();
         if (first >= total_tiles) break;
         const uint32_t last = min(total_tiles, first + kClaim);
         for (uint32_t t = first; t < last; ++t)
-            tile_process<false>(t, tasks, tiles, tile_off, recs, bh_ptr, slab, nullptr, nullptr, nullptr, 0,
-                                overflow_tiles, overflow_count, lds, &s_flag);
+            tile_process<false>(t, tasks, tiles, cells, recs, rec_cap, lds_words, bh_ptr, slab, nullptr, nullptr,
+                                nullptr, 0, overflow_tiles, overflow_count, lds, S);
     }
 }
 
 // Rows with more ties than the slab holds: their tiles again, written to the CSR output.
 __global__ __launch_bounds__(kTileThreads) void k_tile_write(const DevTask *__restrict__ tasks,
                                                              const DevTile *__restrict__ tiles,
-                                                             const uint32_t *__restrict__ tile_off,
-                                                             const uint2 *__restrict__ recs, uint32_t *__restrict__ bh_ptr,
+                                                             const uint32_t *__restrict__ cells,
+                                                             const uint2 *__restrict__ recs, uint64_t rec_cap,
+                                                             uint32_t lds_words, uint32_t *__restrict__ bh_ptr,
                                                              uint32_t *__restrict__ bh_col, uint32_t *__restrict__ bh_num,
                                                              uint32_t *__restrict__ bh_den, uint64_t bh_cap,
                                                              const uint32_t *__restrict__ overflow_tiles,
                                                              const uint32_t *__restrict__ overflow_count) {
     extern __shared__ uint32_t lds[];
-    __shared__ uint32_t s_flag;
+    __shared__ TileLds S;
     const uint32_t n = *overflow_count;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
-        tile_process<true>(overflow_tiles[i], tasks, tiles, tile_off, recs, bh_ptr, nullptr, bh_col, bh_num, bh_den,
-                           bh_cap, nullptr, nullptr, lds, &s_flag);
+        tile_process<true>(overflow_tiles[i], tasks, tiles, cells, recs, rec_cap, lds_words, bh_ptr, nullptr, bh_col,
+                           bh_num, bh_den, bh_cap, nullptr, nullptr, lds, S);
 }
 
 // One thread per best-hit row: the slab entries of a row with at most kSlab ties go to the CSR output.
@@ -435,12 +735,25 @@ __global__ __launch_bounds__(256) void k_slab_copy(uint32_t bh_rows, const uint3
     if (r >= bh_rows) return;
     const uint32_t p = bh_ptr[r], n = bh_ptr[r + 1] - p;
     if (n > kSlab) return;
-    for (uint32_t i = 0; i < n; ++i) {
-        if (p + i >= bh_cap) break;
-        const uint4 e = slab[static_cast<uint64_t>(r) * kSlab + i];
-        bh_col[p + i] = e.x;
-        bh_num[p + i] = e.y;
-        bh_den[p + i] = e.z;
+    uint4 e[kSlab];
+#pragma unroll
+    for (uint32_t i = 0; i < kSlab; ++i) e[i] = i < n ? slab[static_cast<uint64_t>(r) * kSlab + i] : make_uint4(~0u, 0, 0, 0);
+    // the first tile launch leaves a row's ties in any order: insertion sort by column
+#pragma unroll
+    for (uint32_t i = 1; i < kSlab; ++i)
+#pragma unroll
+        for (uint32_t j = i; j > 0; --j)
+            if (e[j - 1].x > e[j].x) {
+                const uint4 t = e[j - 1];
+                e[j - 1] = e[j];
+                e[j] = t;
+            }
+#pragma unroll
+    for (uint32_t i = 0; i < kSlab; ++i) {
+        if (i >= n || p + i >= bh_cap) continue;
+        bh_col[p + i] = e[i].x;
+        bh_num[p + i] = e[i].y;
+        bh_den[p + i] = e[i].z;
     }
 }
 
@@ -562,23 +875,22 @@ hipError_t allow_tile_lds(uint32_t tile_lds) {
     return hipSuccess;
 }
 
+static uint64_t pair_partials(const PlanShape &p) {
+    return std::max({scan_partials(p.total_cells), scan_partials(p.bh_rows), scan_partials(p.bbh_rows)});
+}
+
 uint64_t pair_ws_bytes(const PlanShape &p) {
     const uint64_t A = 256;
     uint64_t s = 0;
     s += align_up(sizeof(DevTask) * std::max<uint64_t>(p.n_tasks, 1), A);
     s += align_up(sizeof(DevTile) * std::max<uint64_t>(p.total_tiles, 1), A);
     s += align_up(4 * std::max<uint64_t>(p.n_tasks, 1), A);
-    s += align_up(16 * std::max<uint64_t>(p.inc_cap, 1), A);
+    s += align_up(8 * std::max<uint64_t>(p.rec_cap, 1), A);
     s += align_up(32, A);
-    s += align_up(4 * (uint64_t(p.total_chunks) + 1), A);
-    s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
-    s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
-    s += align_up(8 * 2 * std::max<uint64_t>(p.inc_cap, 1), A);
+    s += align_up(4 * (uint64_t(p.total_cells) + 1), A);
     s += align_up(16 * kSlab * (uint64_t(p.bh_rows) + 1), A);
     s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
-    const uint64_t np = std::max({scan_partials(p.total_tiles), scan_partials(p.bh_rows), scan_partials(p.bbh_rows),
-                                  scan_partials(p.total_chunks)});
-    s += align_up(4 * np, A);
+    s += align_up(4 * pair_partials(p), A);
     return s;
 }
 
@@ -594,21 +906,16 @@ PairWs pair_ws_carve(void *ws, const PlanShape &p) {
     w.tasks = reinterpret_cast<DevTask *>(take(sizeof(DevTask) * std::max<uint64_t>(p.n_tasks, 1)));
     w.tiles = reinterpret_cast<DevTile *>(take(sizeof(DevTile) * std::max<uint64_t>(p.total_tiles, 1)));
     w.order = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(p.n_tasks, 1)));
-    w.inc = reinterpret_cast<uint4 *>(take(16 * std::max<uint64_t>(p.inc_cap, 1)));
+    w.recs = reinterpret_cast<uint2 *>(take(8 * std::max<uint64_t>(p.rec_cap, 1)));
     w.counters = reinterpret_cast<unsigned long long *>(take(32));
     w.overflow_count = reinterpret_cast<uint32_t *>(w.counters) + 2;
     w.next_join = reinterpret_cast<uint32_t *>(w.counters) + 3;
     w.next_tile = reinterpret_cast<uint32_t *>(w.counters) + 4;
     w.next_join_write = reinterpret_cast<uint32_t *>(w.counters) + 5;
-    w.chunk_cnt = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_chunks) + 1)));
-    w.tile_cnt = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
-    w.tile_fill = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
-    w.recs = reinterpret_cast<uint2 *>(take(8 * 2 * std::max<uint64_t>(p.inc_cap, 1)));
+    w.cells = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_cells) + 1)));
     w.slab = reinterpret_cast<uint4 *>(take(16 * kSlab * (uint64_t(p.bh_rows) + 1)));
     w.overflow_tiles = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
-    const uint64_t np = std::max({scan_partials(p.total_tiles), scan_partials(p.bh_rows), scan_partials(p.bbh_rows),
-                                  scan_partials(p.total_chunks)});
-    w.partials = reinterpret_cast<uint32_t *>(take(4 * np));
+    w.partials = reinterpret_cast<uint32_t *>(take(4 * pair_partials(p)));
     return w;
 }
 
@@ -618,54 +925,47 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
         if (!timer || timer->kernel != kernel) return hipSuccess;
         return hipEventRecord(begin ? timer->start : timer->stop, s);
     };
+    const uint32_t lds_words = p.tile_lds / 4;
     PDP_TRY(mark(PDP_KERNEL_ALL, true));
     PDP_TRY(launch_status_init(st, s));
-    // counters: (unused), overflow tiles, next join item (count pass), next tile, next join item (write pass)
+    // counters: record total (64 bits), overflow tiles, next join item (count pass), next tile,
+    // next join item (write pass)
     PDP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(w.counters), 8, 0u, s));
-    PDP_TRY(launch_fill_u32(w.tile_cnt, uint64_t(p.total_tiles) + 1, 0u, s));
-    PDP_TRY(launch_fill_u32(w.tile_fill, uint64_t(p.total_tiles) + 1, 0u, s));
-    const uint32_t *inc_total = w.chunk_cnt + p.total_chunks;  // after the scan: all incidences
     PDP_TRY(mark(PDP_KERNEL_JOIN, true));
-    if (p.total_chunks && p.join_grid) {
-        const dim3 g(std::min(p.join_grid, (p.total_chunks + kClaimJoin - 1) / kClaimJoin));
-        hipLaunchKernelGGL(k_join_persistent<false>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
-                           w.chunk_cnt, w.inc, p.inc_cap, w.next_join);
+    if (p.total_chunks) {
+        const bool pers = p.join_grid != 0;
+        const dim3 g = pers ? dim3(std::min(p.join_grid, (p.total_chunks + kClaimJoin - 1) / kClaimJoin))
+                            : dim3(p.total_chunks);
+        if (pers)
+            hipLaunchKernelGGL(k_join_persistent<false>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
+                               w.cells, w.counters, w.recs, p.rec_cap, st, w.next_join);
+        else
+            hipLaunchKernelGGL(k_join<false>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.cells, w.counters,
+                               w.recs, p.rec_cap, st);
         PDP_TRY(hipGetLastError());
-        PDP_TRY(launch_scan(w.chunk_cnt, w.chunk_cnt, p.total_chunks, w.partials, s));
-        hipLaunchKernelGGL(k_join_persistent<true>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
-                           w.chunk_cnt, w.inc, p.inc_cap, w.next_join_write);
-        PDP_TRY(hipGetLastError());
-    } else if (p.total_chunks) {
-        hipLaunchKernelGGL(k_join<false>, dim3(p.total_chunks), dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.chunk_cnt,
-                           w.inc, p.inc_cap);
-        PDP_TRY(hipGetLastError());
-        PDP_TRY(launch_scan(w.chunk_cnt, w.chunk_cnt, p.total_chunks, w.partials, s));
-        hipLaunchKernelGGL(k_join<true>, dim3(p.total_chunks), dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.chunk_cnt,
-                           w.inc, p.inc_cap);
+        PDP_TRY(mark(PDP_KERNEL_BUCKET, true));
+        PDP_TRY(launch_scan(w.cells, w.cells, p.total_cells, w.partials, s));
+        PDP_TRY(mark(PDP_KERNEL_BUCKET, false));
+        if (pers)
+            hipLaunchKernelGGL(k_join_persistent<true>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
+                               w.cells, w.counters, w.recs, p.rec_cap, st, w.next_join_write);
+        else
+            hipLaunchKernelGGL(k_join<true>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.cells, w.counters,
+                               w.recs, p.rec_cap, st);
         PDP_TRY(hipGetLastError());
     } else {
-        PDP_TRY(launch_fill_u32(w.chunk_cnt, 1, 0u, s));
+        PDP_TRY(launch_fill_u32(w.cells, uint64_t(p.total_cells) + 1, 0u, s));
     }
     PDP_TRY(mark(PDP_KERNEL_JOIN, false));
-    PDP_TRY(mark(PDP_KERNEL_BUCKET, true));
-    hipLaunchKernelGGL(k_inc_bucket<false>, dim3(kBucketGroups), dim3(256), 0, s, w.tasks, w.inc, inc_total, p.inc_cap,
-                       w.tile_cnt, w.tile_cnt, w.tile_fill, w.recs, st);
-    PDP_TRY(hipGetLastError());
-    PDP_TRY(launch_scan(w.tile_cnt, w.tile_cnt, p.total_tiles, w.partials, s));
-    hipLaunchKernelGGL(k_inc_bucket<true>, dim3(kBucketGroups), dim3(256), 0, s, w.tasks, w.inc, inc_total, p.inc_cap,
-                       w.tile_cnt, w.tile_cnt, w.tile_fill, w.recs, st);
-    PDP_TRY(hipGetLastError());
-    PDP_TRY(mark(PDP_KERNEL_BUCKET, false));
     PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, true));
     if (p.total_tiles && p.tile_grid) {
         hipLaunchKernelGGL(k_tile_count_persistent, dim3(std::min(p.tile_grid, (p.total_tiles + kClaim - 1) / kClaim)),
-                           dim3(kTileThreads),
-                           p.tile_lds, s, w.tasks, w.tiles, p.total_tiles, w.tile_cnt, w.recs, bh->ptr, w.slab,
-                           w.overflow_tiles, w.overflow_count, w.next_tile);
+                           dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles, p.total_tiles, w.cells, w.recs,
+                           p.rec_cap, lds_words, bh->ptr, w.slab, w.overflow_tiles, w.overflow_count, w.next_tile);
         PDP_TRY(hipGetLastError());
     } else if (p.total_tiles) {
         hipLaunchKernelGGL(k_tile_count, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
-                           w.tile_cnt, w.recs, bh->ptr, w.slab, w.overflow_tiles, w.overflow_count);
+                           w.cells, w.recs, p.rec_cap, lds_words, bh->ptr, w.slab, w.overflow_tiles, w.overflow_count);
         PDP_TRY(hipGetLastError());
     }
     PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, false));
@@ -678,8 +978,8 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     }
     if (p.total_tiles) {
         const uint32_t g = p.total_tiles < 256 ? p.total_tiles : 256;
-        hipLaunchKernelGGL(k_tile_write, dim3(g), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles, w.tile_cnt,
-                           w.recs, bh->ptr, bh->col, bh->num, bh->den, bh->capacity, w.overflow_tiles,
+        hipLaunchKernelGGL(k_tile_write, dim3(g), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles, w.cells, w.recs,
+                           p.rec_cap, lds_words, bh->ptr, bh->col, bh->num, bh->den, bh->capacity, w.overflow_tiles,
                            w.overflow_count);
         PDP_TRY(hipGetLastError());
     }
@@ -699,6 +999,7 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     PDP_TRY(mark(PDP_KERNEL_ALL, false));
     return hipSuccess;
 }
+
 
 hipError_t launch_bbh_standalone(const pdp_bh_out *ab, const pdp_bh_out *ba, pdp_bbh_out *out, pdp_status *st,
                                  uint32_t *partials, hipStream_t s) {

@@ -61,14 +61,14 @@ void pdp_graph_destroy(pdp_graph *g) {
 
 static std::vector<pdp_params> default_candidates() {
     std::vector<pdp_params> c;
-    const uint32_t lds[] = {24 * 1024, 48 * 1024, 96 * 1024, 144 * 1024};
+    const uint32_t rows[] = {32, 64, 128};
     const uint32_t join[] = {256, 512, 1024};
     for (uint32_t persistent = 0; persistent < 2; ++persistent)
-        for (uint32_t l : lds)
+        for (uint32_t r : rows)
             for (uint32_t j : join) {
                 pdp_params p;
                 std::memset(&p, 0, sizeof(p));
-                p.lds_budget = l;
+                p.tile_rows = r;
                 p.join_entries = j;
                 p.flags = persistent ? PDP_PARAM_PERSISTENT : 0;
                 c.push_back(p);

@@ -115,15 +115,25 @@ def test_plan_layout():
     assert rows == [(0, 300, 0), (500, none, none), (none, 800, none)]
     assert L.pdp_plan_rows(h, 3, None, None, None) == pdp.PDP_E_INVAL
     L.pdp_plan_destroy(h)
+    # tile heights are powers of two: 20 rows round down to 16
+    rc, h = _plan([(a, b, pdp.PDP_TASK_BBH)], pdp.params(tile_rows=20))
+    assert rc == 0 and L.pdp_plan_info_get(h, C.byref(info)) == 0 and info.tiles == 19 + 13
+    L.pdp_plan_destroy(h)
 
 
 def test_plan_rejects_bad_tasks():
     a5, b6 = _fake_dict(10, 900, 5), _fake_dict(10, 900, 6)
     assert _plan([(a5, b6, pdp.PDP_TASK_AB)])[0] == pdp.PDP_E_INVAL
     assert _plan([(a5, a5, 0)])[0] == pdp.PDP_E_INVAL
-    big = _fake_dict(30000, 9 * 10 ** 6, 5)
+    # a column genome must leave room for one dense row (its window counts + sums + bitmap) in LDS
+    big = _fake_dict(50000, 9 * 10 ** 6, 5)
     assert _plan([(a5, big, pdp.PDP_TASK_AB)])[0] == pdp.PDP_E_LIMIT
     assert _plan([(a5, big, pdp.PDP_TASK_BA)])[0] == 0  # the big genome as rows fits
+    assert _plan([(a5, _fake_dict(30000, 9 * 10 ** 6, 5), pdp.PDP_TASK_AB)])[0] == 0
+    # rows beyond 1024 tiles of 256 genes cannot be counted per tile in the join
+    huge = _fake_dict(300000, 9 * 10 ** 7, 5)
+    assert _plan([(huge, a5, pdp.PDP_TASK_AB)])[0] == pdp.PDP_E_LIMIT
+    assert _plan([(a5, a5, 1)], pdp.params(inc_capacity=1 << 32))[0] == pdp.PDP_E_LIMIT
     assert _plan([(a5, a5, 1)], pdp.params(lds_budget=1 << 20))[0] == pdp.PDP_E_INVAL
 
 

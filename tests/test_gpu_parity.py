@@ -195,6 +195,59 @@ def test_tuning_knobs_do_not_change_results(prm):
     compare_all(ds.genomes, k, res)
 
 
+def _mutate(rng, s, rate):
+    return "".join(rng.choice(ALPHA) if rng.random() < rate else ch for ch in s)
+
+
+@pytest.mark.parametrize("tile_rows", [1, 64])
+def test_tiles_past_the_lds_sort(tile_rows):
+    # a row whose records overflow the LDS table and sort: 13 copies of one 600-residue
+    # gene (6 exact, so the row has 6 tied best hits and is rewritten by the second tile
+    # launch) give its tile ~7800 records and the copies' tiles ~1200 each, so hashed,
+    # grouped and dense tiles mix in one launch
+    rng = random.Random(5)
+    base = "".join(rng.choice(ALPHA) for _ in range(600))
+    a = [base, _mutate(rng, base, 0.02)] + ["".join(rng.choice(ALPHA) for _ in range(200)) for _ in range(40)]
+    b = [_mutate(rng, base, 0.03) for _ in range(7)] + [base] * 6
+    b += ["".join(rng.choice(ALPHA) for _ in range(200)) for _ in range(40)]
+    rng.shuffle(b)
+    ga, gb = genome_from_strings(a), genome_from_strings(b)
+    say("tiles past the LDS sort, tile_rows", tile_rows)
+    _, res = run_all([ga, gb], 5, pdp.params(tile_rows=tile_rows))
+    compare_all([ga, gb], 5, res)
+
+
+def test_rows_with_many_ties():
+    # rows tied with more best hits than the slab keeps: their tiles are recomputed and
+    # written in column order by the second tile launch
+    rng = random.Random(21)
+    genes = ["".join(rng.choice(ALPHA) for _ in range(rng.randint(30, 120))) for _ in range(60)]
+    a = genes[:30] + [genes[0]] * 3
+    b = [genes[0]] * 7 + genes[30:] + [genes[1]] * 5 + [genes[2]] * 4
+    rng.shuffle(b)
+    ga, gb = genome_from_strings(a), genome_from_strings(b)
+    say("rows with many ties")
+    _, res = run_all([ga, gb], 4)
+    compare_all([ga, gb], 4, res)
+    ptr = res.best_hits(0, 0)[0].astype(np.int64)
+    assert np.diff(ptr).max() >= 7
+
+
+def test_dense_tile_in_several_passes():
+    # 20000 target genes leave LDS room for one dense row at a time, so the overflowing
+    # tile is summed in one pass per row
+    rng = random.Random(9)
+    base = "".join(rng.choice(ALPHA) for _ in range(500))
+    a = [base] + ["".join(rng.choice(ALPHA) for _ in range(60)) for _ in range(69)]
+    b = [_mutate(rng, base, 0.02) for _ in range(12)]
+    b += ["".join(rng.choice(ALPHA) for _ in range(rng.randint(8, 30))) for _ in range(20000)]
+    rng.shuffle(b)
+    ga, gb = genome_from_strings(a), genome_from_strings(b)
+    say("dense tile in several passes, 70 x 20012 genes")
+    _, res = run_all([ga, gb], 4)
+    compare_all([ga, gb], 4, res)
+
+
 def test_join_global_search_path():
     # one leading-residue bucket holding more target entries than the join stages in LDS
     rng = random.Random(11)
