@@ -1,11 +1,13 @@
 // k-mer dictionary build for one or many genomes on gfx950, in one set of launches.
 //
-// 1. k_mv_local: one work-group per gene encodes every window g[p..p+k-1]
-//    into a 5-bit-per-residue code, sorts the codes in LDS and run-length
-//    encodes them into the gene's multiplicity vector (Multiplicity vector
-//    building phase, Alg. 1: group equal identifiers, count, ascending order).
-//    Genes with more than kMvSortCap windows are queued for k_mv_long, which
-//    does the same with the codes in global memory.
+// 1. k_mv_wave: one wave per gene encodes every window g[p..p+k-1] into a
+//    5-bit-per-residue code, sorts the codes in registers (a bitonic network of
+//    kMvWaveCap keys, eight per lane, lanes exchanging by shuffles) and
+//    run-length encodes them into the gene's multiplicity vector (Multiplicity
+//    vector building phase, Alg. 1: group equal identifiers, count, ascending
+//    order).  Longer genes are queued for k_mv_mid (one work-group per gene,
+//    codes sorted in LDS) and, past kMvSortCap windows, for k_mv_long (codes
+//    sorted in global memory).
 // 2. A scan of the distinct-k-mer counts of all genes gives the CSR offsets,
 //    and k_mv_compact packs the vectors (and notes each entry's gene).
 // 3. The inverted index (all entries ordered by k-mer code, ties by gene) is a
@@ -62,95 +64,231 @@ __global__ void k_build_init(const DevBuild *table, uint32_t n) {
     st->where = ~0ull;
 }
 
-__global__ __launch_bounds__(kMvThreads) void k_mv_local(const DevBuild *__restrict__ table, uint32_t n_genomes,
-                                                         uint32_t *__restrict__ dcnt, uint64_t *__restrict__ long_list,
-                                                         uint32_t *__restrict__ counters) {
-    __shared__ uint64_t keys[kMvSortCap];
-    __shared__ uint8_t sym[kMvSortCap + PDP_K_MAX];
-    __shared__ uint32_t tmp[kMvThreads / kWave + 1];
-    __shared__ uint32_t s_t;
-    const uint32_t G = blockIdx.x;  // global gene
-    const uint32_t tid = threadIdx.x;
-    if (tid == 0) s_t = find_genome_by_gene(table, n_genomes, G);
-    __syncthreads();
-    const DevBuild &B = table[s_t];
-    const uint32_t g = G - B.gene_base;
-    const uint32_t k = B.k;
-    const uint64_t o = B.off[g];
+// Orders LDS writes of a wave before its later LDS reads (a wave runs in lock step,
+// so no work-group barrier is needed).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Ascending bitonic sort of kWave * E keys, E per lane in blocked order (lane l holds
+// elements l*E .. l*E+E-1): comparators inside a lane swap registers, the others pair
+// lanes by a shuffle and keep the minimum or maximum.
+template <uint32_t E>
+__device__ __forceinline__ void wave_bitonic_sort(uint64_t (&key)[E]) {
+    constexpr uint32_t N = kWave * E;
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (uint32_t size = 2; size <= N; size <<= 1) {
+#pragma unroll
+        for (uint32_t j = size >> 1; j > 0; j >>= 1) {
+            if (j < E) {
+#pragma unroll
+                for (uint32_t e = 0; e < E; ++e) {
+                    if (e & j) continue;
+                    const bool asc = ((l * E + e) & size) == 0;
+                    const uint64_t a = key[e], b = key[e | j];
+                    const bool sw = asc ? a > b : a < b;
+                    key[e] = sw ? b : a;
+                    key[e | j] = sw ? a : b;
+                }
+            } else {
+                const uint32_t lj = j / E;
+                const bool lower = (l & lj) == 0;
+#pragma unroll
+                for (uint32_t e = 0; e < E; ++e) {
+                    const uint64_t o = __shfl_xor(key[e], lj, kWave);
+                    const bool keep_min = lower == (((l * E + e) & size) == 0);
+                    const uint64_t mn = o < key[e] ? o : key[e], mx = o < key[e] ? key[e] : o;
+                    key[e] = keep_min ? mn : mx;
+                }
+            }
+        }
+    }
+}
+
+// Checks a gene's offsets and window count; on failure records the status and an empty
+// vector and returns false.
+__device__ __forceinline__ bool gene_ok(const DevBuild &B, uint32_t g, uint32_t G, uint32_t *dcnt, uint64_t *o,
+                                        uint64_t *len, uint32_t *nw) {
+    *o = B.off[g];
     const uint64_t e = B.off[g + 1];
-    if (e < o || e > B.n_residues) {
-        if (tid == 0) {
+    if (e < *o || e > B.n_residues) {
+        if (lane_id() == 0) {
             raise_status(B.status, PDP_E_INVAL, 0, g);
             B.nwin[g] = 0;
             dcnt[G] = 0;
         }
-        return;
+        return false;
     }
-    const uint64_t len = e - o;
-    const uint64_t nw64 = len >= k ? len - k + 1 : 0;
+    *len = e - *o;
+    const uint64_t nw64 = *len >= B.k ? *len - B.k + 1 : 0;
     if (nw64 > PDP_MAX_WINDOWS) {
-        if (tid == 0) {
+        if (lane_id() == 0) {
             raise_status(B.status, PDP_E_LIMIT, nw64, g);
             B.nwin[g] = 0;
             dcnt[G] = 0;
         }
+        return false;
+    }
+    *nw = static_cast<uint32_t>(nw64);
+    return true;
+}
+
+constexpr uint32_t kMvWaveE = 8;
+constexpr uint32_t kMvWaveCap = kWave * kMvWaveE;  // windows a wave sorts in registers
+constexpr uint32_t kMvWaves = kMvThreads / kWave;
+
+__global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restrict__ table, uint32_t n_genomes,
+                                                        uint32_t total_genes, uint32_t *__restrict__ dcnt,
+                                                        uint64_t *__restrict__ mid_list, uint32_t *__restrict__ counters) {
+    __shared__ uint8_t sym_all[kMvWaves][kMvWaveCap + PDP_K_MAX];
+    __shared__ uint16_t hp_all[kMvWaves][kMvWaveCap + 1];
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t G = blockIdx.x * kMvWaves + w;
+    if (G >= total_genes) return;
+    const uint32_t t = find_genome_by_gene(table, n_genomes, G);
+    const DevBuild &B = table[t];
+    const uint32_t g = G - B.gene_base;
+    uint64_t o, len;
+    uint32_t nw;
+    if (!gene_ok(B, g, G, dcnt, &o, &len, &nw)) return;
+    if (lane == 0) B.nwin[g] = nw;
+    if (nw > kMvWaveCap) {
+        if (lane == 0) mid_list[atomicAdd(&counters[1], 1u)] = (static_cast<uint64_t>(t) << 32) | g;
         return;
     }
-    const uint32_t nw = static_cast<uint32_t>(nw64);
-    const bool in_lds = nw <= kMvSortCap;
-    const uint8_t *res = B.res;
-    for (uint64_t p = tid; p < len; p += kMvThreads) {
-        uint32_t s = kSym.v[res[o + p]];
-        if (s == kInvalidSym) {
+    uint8_t *sym = sym_all[w];
+    for (uint32_t p = lane; p < len; p += kWave) {
+        uint32_t x = kSym.v[B.res[o + p]];
+        if (x == kInvalidSym) {
             raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
-            s = 0;
+            x = 0;
         }
-        if (in_lds) sym[p] = static_cast<uint8_t>(s);
+        sym[p] = static_cast<uint8_t>(x);
     }
-    if (tid == 0) B.nwin[g] = nw;
-    if (!in_lds) {
-        if (tid == 0) long_list[atomicAdd(&counters[0], 1u)] = (static_cast<uint64_t>(s_t) << 32) | g;
-        return;
-    }
-    __syncthreads();
-    for (uint32_t p = tid; p < nw; p += kMvThreads) {
-        uint64_t c = 0;
-        for (uint32_t j = 0; j < k; ++j) c = (c << 5) | sym[p + j];
-        keys[p] = c;
-    }
-    __syncthreads();
-    wg_network_sort(nw, [&](uint32_t lo, uint32_t hi) {
-        const uint64_t a = keys[lo], b = keys[hi];
-        if (b < a) {
-            keys[lo] = b;
-            keys[hi] = a;
-        }
-    });
-    // run-length encoding; each thread owns kMvPer consecutive sorted codes
-    const uint32_t i0 = tid * kMvPer;
-    uint32_t heads = 0;
+    wave_lds_sync();
+    const uint32_t k = B.k;
+    uint64_t key[kMvWaveE];
 #pragma unroll
-    for (uint32_t j = 0; j < kMvPer; ++j) {
-        const uint32_t i = i0 + j;
-        if (i < nw && (i == 0 || keys[i] != keys[i - 1])) ++heads;
+    for (uint32_t e = 0; e < kMvWaveE; ++e) {
+        const uint32_t p = lane * kMvWaveE + e;
+        uint64_t c = ~0ull;  // past the windows: sorts last
+        if (p < nw) {
+            c = 0;
+            for (uint32_t j = 0; j < k; ++j) c = (c << 5) | sym[p + j];
+        }
+        key[e] = c;
     }
-    uint32_t total;
-    uint32_t rank = block_exclusive_scan<kMvThreads>(heads, tmp, &total);
+    wave_bitonic_sort<kMvWaveE>(key);
+    // run heads: positions go to LDS so each head finds where the next run starts
+    const uint64_t before = __shfl_up(key[kMvWaveE - 1], 1, kWave);
+    uint32_t hmask = 0, nh = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < kMvWaveE; ++e) {
+        const uint32_t i = lane * kMvWaveE + e;
+        const uint64_t prev = e ? key[e - 1] : before;
+        const bool h = i < nw && (i == 0 || key[e] != prev);
+        hmask |= static_cast<uint32_t>(h) << e;
+        nh += h;
+    }
+    const uint32_t incl = wave_inclusive_sum(nh);
+    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+    uint16_t *hp = hp_all[w];
+    uint32_t r = incl - nh;
+#pragma unroll
+    for (uint32_t e = 0; e < kMvWaveE; ++e)
+        if ((hmask >> e) & 1u) hp[r++] = static_cast<uint16_t>(lane * kMvWaveE + e);
+    if (lane == 0) hp[total] = static_cast<uint16_t>(nw);
+    wave_lds_sync();
     uint64_t *slot_code = B.slot_code + o;
     uint32_t *slot_cnt = B.slot_cnt + o;
+    r = incl - nh;
 #pragma unroll
-    for (uint32_t j = 0; j < kMvPer; ++j) {
-        const uint32_t i = i0 + j;
-        if (i < nw && (i == 0 || keys[i] != keys[i - 1])) {
-            const uint64_t c = keys[i];
-            uint32_t end = i + 1;
-            while (end < nw && keys[end] == c) ++end;
-            slot_code[rank] = c;
-            slot_cnt[rank] = end - i;
-            ++rank;
-        }
+    for (uint32_t e = 0; e < kMvWaveE; ++e) {
+        if (!((hmask >> e) & 1u)) continue;
+        slot_code[r] = key[e];
+        slot_cnt[r] = static_cast<uint32_t>(hp[r + 1]) - hp[r];
+        ++r;
     }
-    if (tid == 0) dcnt[G] = total;
+    if (lane == 0) dcnt[G] = total;
+}
+
+// Genes queued by k_mv_wave (more windows than a wave sorts): one work-group per gene,
+// codes sorted in LDS; genes past kMvSortCap windows are queued again for k_mv_long.
+__global__ __launch_bounds__(kMvThreads) void k_mv_mid(const DevBuild *__restrict__ table, uint32_t *__restrict__ dcnt,
+                                                       const uint64_t *__restrict__ mid_list,
+                                                       uint64_t *__restrict__ long_list, uint32_t *__restrict__ counters) {
+    __shared__ uint64_t keys[kMvSortCap];
+    __shared__ uint8_t sym[kMvSortCap + PDP_K_MAX];
+    __shared__ uint32_t tmp[kMvThreads / kWave + 1];
+    const uint32_t n_mid = counters[1];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t li = blockIdx.x; li < n_mid; li += gridDim.x) {
+        const uint64_t item = mid_list[li];
+        const DevBuild &B = table[item >> 32];
+        const uint32_t g = static_cast<uint32_t>(item);
+        const uint32_t G = B.gene_base + g;
+        const uint32_t k = B.k;
+        const uint64_t o = B.off[g];
+        const uint64_t len = B.off[g + 1] - o;
+        const uint32_t nw = static_cast<uint32_t>(len - k + 1);  // checked by k_mv_wave
+        const bool in_lds = nw <= kMvSortCap;
+        const uint8_t *res = B.res;
+        for (uint64_t p = tid; p < len; p += kMvThreads) {
+            uint32_t x = kSym.v[res[o + p]];
+            if (x == kInvalidSym) {
+                raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
+                x = 0;
+            }
+            if (in_lds) sym[p] = static_cast<uint8_t>(x);
+        }
+        if (!in_lds) {
+            if (tid == 0) long_list[atomicAdd(&counters[0], 1u)] = item;
+            continue;  // uniform: the same item for the whole work-group
+        }
+        __syncthreads();
+        for (uint32_t p = tid; p < nw; p += kMvThreads) {
+            uint64_t c = 0;
+            for (uint32_t j = 0; j < k; ++j) c = (c << 5) | sym[p + j];
+            keys[p] = c;
+        }
+        __syncthreads();
+        wg_network_sort(nw, [&](uint32_t lo, uint32_t hi) {
+            const uint64_t a = keys[lo], b = keys[hi];
+            if (b < a) {
+                keys[lo] = b;
+                keys[hi] = a;
+            }
+        });
+        // run-length encoding; each thread owns kMvPer consecutive sorted codes
+        const uint32_t i0 = tid * kMvPer;
+        uint32_t heads = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kMvPer; ++j) {
+            const uint32_t i = i0 + j;
+            if (i < nw && (i == 0 || keys[i] != keys[i - 1])) ++heads;
+        }
+        uint32_t total;
+        uint32_t rank = block_exclusive_scan<kMvThreads>(heads, tmp, &total);
+        uint64_t *slot_code = B.slot_code + o;
+        uint32_t *slot_cnt = B.slot_cnt + o;
+#pragma unroll
+        for (uint32_t j = 0; j < kMvPer; ++j) {
+            const uint32_t i = i0 + j;
+            if (i < nw && (i == 0 || keys[i] != keys[i - 1])) {
+                const uint64_t c = keys[i];
+                uint32_t end = i + 1;
+                while (end < nw && keys[end] == c) ++end;
+                slot_code[rank] = c;
+                slot_cnt[rank] = end - i;
+                ++rank;
+            }
+        }
+        if (tid == 0) dcnt[G] = total;
+        __syncthreads();  // LDS takes the next gene
+    }
 }
 
 // Genes with more windows than fit in LDS: same steps, codes sorted in global memory.
@@ -344,15 +482,45 @@ __device__ void bin_directory(const DevBuild &B, CP code, uint32_t n, uint32_t l
     }
 }
 
-// One work-group per coarse bin: its entries sorted by (code, gene), in LDS when they fit
-// (else in place in global memory), then the bin's buckets in the directory.
+__device__ __forceinline__ uint64_t rec_code(const uint4 &r) { return (static_cast<uint64_t>(r.y) << 32) | r.x; }
+__device__ __forceinline__ bool rec_less(const uint4 &a, const uint4 &b) {
+    return entry_less(rec_code(a), a.z, rec_code(b), b.z);
+}
+
+// Work-group sort of index records (code, gene, count) in LDS by (code, gene).
+__device__ __forceinline__ void sort_recs(uint4 *r, uint32_t n) {
+    wg_network_sort(n, [&](uint32_t lo, uint32_t hi) {
+        const uint4 a = r[lo], b = r[hi];
+        if (rec_less(b, a)) {
+            r[lo] = b;
+            r[hi] = a;
+        }
+    });
+}
+
+constexpr uint32_t kIxBinBuckets = 2048;  // buckets a bin may span for the counting path
+constexpr uint32_t kIxSmallBucket = 16;   // buckets up to this size are sorted by one thread
+constexpr uint32_t kIxBigList = 64;       // larger buckets a bin sorts one by one with the work-group
+constexpr uint32_t kIxPer = kIxBinLds / 256;
+static_assert(kIxBinBuckets == 256 * kIxPer, "each thread scans kIxPer bucket sizes");
+
+// One work-group per coarse bin: its entries ordered by (code, gene) and the bin's part of
+// the bucket directory.  Usual case (the bin fits LDS and spans at most kIxBinBuckets
+// buckets): a counting sort by bucket (LDS histogram, scan, scatter), whose offsets are the
+// directory, then every bucket sorted on its own, by one thread (insertion sort) or, if
+// large, by the work-group.  Otherwise the whole bin is sorted in LDS, or in place in
+// global memory when it does not fit.
 __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict__ table, uint32_t n_genomes,
                                                      const uint32_t *__restrict__ off) {
-    __shared__ uint64_t s_code[kIxBinLds];
-    __shared__ uint32_t s_gene[kIxBinLds];
-    __shared__ uint32_t s_cnt[kIxBinLds];
-    __shared__ uint32_t s_t;
-    if (threadIdx.x == 0) s_t = find_genome_by_bin(table, n_genomes, blockIdx.x);
+    __shared__ uint4 s_rec[kIxBinLds];
+    __shared__ uint32_t s_bstart[kIxBinBuckets + 1];
+    __shared__ uint32_t s_big[kIxBigList];
+    __shared__ uint32_t s_tmp[256 / kWave + 1];
+    __shared__ uint32_t s_t, s_nbig;
+    if (threadIdx.x == 0) {
+        s_t = find_genome_by_bin(table, n_genomes, blockIdx.x);
+        s_nbig = 0;
+    }
     __syncthreads();
     const DevBuild &B = table[s_t];
     const uint32_t h = blockIdx.x - B.bin_base;
@@ -362,27 +530,99 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
     const uint32_t n = hi - lo;
     const uint32_t b0 = h << B.hshift;
     const uint32_t b1 = min(B.nb, (h + 1) << B.hshift);
-    if (n <= kIxBinLds) {
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint4 r = B.ix_tmp[lo + i];
-            s_code[i] = (static_cast<uint64_t>(r.y) << 32) | r.x;
-            s_gene[i] = r.z;
-            s_cnt[i] = r.w;
+    const uint32_t nbb = b1 - b0;
+    if (n <= kIxBinLds && nbb <= kIxBinBuckets) {
+        for (uint32_t i = threadIdx.x; i <= nbb; i += 256) s_bstart[i] = 0;
+        __syncthreads();
+        uint4 r[kIxPer];
+        uint32_t slot[kIxPer], bk[kIxPer];
+#pragma unroll
+        for (uint32_t q = 0; q < kIxPer; ++q) {
+            const uint32_t i = q * 256 + threadIdx.x;
+            if (i < n) {
+                r[q] = B.ix_tmp[lo + i];
+                bk[q] = bucket_of(rec_code(r[q]), B.k, B.lead) - b0;
+                slot[q] = atomicAdd(&s_bstart[bk[q]], 1u);
+            }
         }
         __syncthreads();
-        sort_entries(s_code, s_gene, s_cnt, n);
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            B.ix_code[lo + i] = s_code[i];
-            B.ix_gene[lo + i] = s_gene[i];
-            B.ix_cnt[lo + i] = s_cnt[i];
+        // exclusive scan of the bucket sizes; thread t owns buckets [kIxPer*t, kIxPer*t + kIxPer)
+        uint32_t c[kIxPer], sum = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kIxPer; ++q) {
+            const uint32_t b = threadIdx.x * kIxPer + q;
+            c[q] = b < nbb ? s_bstart[b] : 0u;
+            sum += c[q];
         }
-        bin_directory(B, s_code, n, lo, b0, b1);
+        uint32_t total;
+        uint32_t run = block_exclusive_scan<256>(sum, s_tmp, &total);
+#pragma unroll
+        for (uint32_t q = 0; q < kIxPer; ++q) {
+            const uint32_t b = threadIdx.x * kIxPer + q;
+            if (b < nbb) s_bstart[b] = run;
+            run += c[q];
+        }
+        if (threadIdx.x == 0) s_bstart[nbb] = n;
+        __syncthreads();
+#pragma unroll
+        for (uint32_t q = 0; q < kIxPer; ++q) {
+            const uint32_t i = q * 256 + threadIdx.x;
+            if (i < n) s_rec[s_bstart[bk[q]] + slot[q]] = r[q];
+        }
+        __syncthreads();
+        for (uint32_t b = threadIdx.x; b < nbb; b += 256) {
+            const uint32_t st = s_bstart[b], size = s_bstart[b + 1] - st;
+            B.ix_dir[b0 + b] = lo + st;
+            if (size <= kIxSmallBucket) {
+                for (uint32_t x = st + 1; x < st + size; ++x) {
+                    const uint4 v = s_rec[x];
+                    uint32_t y = x;
+                    while (y > st && rec_less(v, s_rec[y - 1])) {
+                        s_rec[y] = s_rec[y - 1];
+                        --y;
+                    }
+                    s_rec[y] = v;
+                }
+            } else {
+                const uint32_t idx = atomicAdd(&s_nbig, 1u);
+                if (idx < kIxBigList) s_big[idx] = b;
+            }
+        }
+        __syncthreads();
+        const uint32_t nbig = s_nbig;
+        if (nbig > kIxBigList) {
+            sort_recs(s_rec, n);
+        } else {
+            for (uint32_t j = 0; j < nbig; ++j) {  // uniform loop
+                const uint32_t b = s_big[j];
+                sort_recs(s_rec + s_bstart[b], s_bstart[b + 1] - s_bstart[b]);
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n; i += 256) {
+            const uint4 v = s_rec[i];
+            B.ix_code[lo + i] = rec_code(v);
+            B.ix_gene[lo + i] = v.z;
+            B.ix_cnt[lo + i] = v.w;
+        }
+    } else if (n <= kIxBinLds) {
+        for (uint32_t i = threadIdx.x; i < n; i += 256) s_rec[i] = B.ix_tmp[lo + i];
+        __syncthreads();
+        sort_recs(s_rec, n);
+        for (uint32_t i = threadIdx.x; i < n; i += 256) {
+            const uint4 v = s_rec[i];
+            B.ix_code[lo + i] = rec_code(v);
+            B.ix_gene[lo + i] = v.z;
+            B.ix_cnt[lo + i] = v.w;
+        }
+        __syncthreads();
+        bin_directory(B, B.ix_code + lo, n, lo, b0, b1);
     } else {
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint4 r = B.ix_tmp[lo + i];
-            B.ix_code[lo + i] = (static_cast<uint64_t>(r.y) << 32) | r.x;
-            B.ix_gene[lo + i] = r.z;
-            B.ix_cnt[lo + i] = r.w;
+        for (uint32_t i = threadIdx.x; i < n; i += 256) {
+            const uint4 v = B.ix_tmp[lo + i];
+            B.ix_code[lo + i] = rec_code(v);
+            B.ix_gene[lo + i] = v.z;
+            B.ix_cnt[lo + i] = v.w;
         }
         __syncthreads();
         sort_entries(B.ix_code + lo, B.ix_gene + lo, B.ix_cnt + lo, n);
@@ -432,6 +672,7 @@ uint64_t build_ws_bytes(const BuildShape &s) {
     b += align_up(4 * (s.total_genes + 1), A);          // dcnt / gptr
     b += align_up(4 * (s.total_hist + 1), A);           // hist / off
     b += align_up(8 * (s.total_genes + 1), A);          // long_list
+    b += align_up(8 * (s.total_genes + 1), A);          // mid_list
     b += align_up(4 * 4, A);                            // counters
     const uint64_t np = std::max<uint64_t>(scan_partials(s.total_genes), scan_partials(s.total_hist));
     b += align_up(4 * np, A);
@@ -469,6 +710,7 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
     uint32_t *dcnt = reinterpret_cast<uint32_t *>(take(4 * (sh.total_genes + 1)));
     uint32_t *hist = reinterpret_cast<uint32_t *>(take(4 * (sh.total_hist + 1)));
     uint64_t *long_list = reinterpret_cast<uint64_t *>(take(8 * (sh.total_genes + 1)));
+    uint64_t *mid_list = reinterpret_cast<uint64_t *>(take(8 * (sh.total_genes + 1)));
     uint32_t *counters = reinterpret_cast<uint32_t *>(take(4 * 4));
     const uint64_t np = std::max<uint64_t>(scan_partials(sh.total_genes), scan_partials(sh.total_hist));
     uint32_t *partials = reinterpret_cast<uint32_t *>(take(4 * np));
@@ -527,7 +769,11 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
     PDP_TRY(hipGetLastError());
     PDP_TRY(launch_fill_u32(counters, 4, 0u, s));
     if (tg > 0) {
-        hipLaunchKernelGGL(k_mv_local, dim3(tg), dim3(kMvThreads), 0, s, table, n, dcnt, long_list, counters);
+        hipLaunchKernelGGL(k_mv_wave, dim3((tg + kMvWaves - 1) / kMvWaves), dim3(kMvThreads), 0, s, table, n, tg, dcnt,
+                           mid_list, counters);
+        PDP_TRY(hipGetLastError());
+        const uint32_t mid_groups = tg < 2048 ? tg : 2048;
+        hipLaunchKernelGGL(k_mv_mid, dim3(mid_groups), dim3(kMvThreads), 0, s, table, dcnt, mid_list, long_list, counters);
         PDP_TRY(hipGetLastError());
         const uint32_t long_groups = tg < 64 ? tg : 64;
         hipLaunchKernelGGL(k_mv_long, dim3(long_groups), dim3(kMvThreads), 0, s, table, dcnt, long_list, counters);

@@ -36,6 +36,7 @@
 namespace pdp {
 
 constexpr uint32_t kJoinThreads = 256;
+constexpr uint32_t kJoinUnroll = 4;  // query entries a join thread loads at once
 static_assert(kTilePer * (kTileThreads / kWave) <= kWave, "tile head counts are scanned by one wave");
 
 // LDS of one join item: the task descriptor, the item's slice of both bucket
@@ -94,38 +95,56 @@ __device__ __forceinline__ void join_range(const DevTask &T, uint32_t a0, uint32
     const uint32_t k = T.a.k, lead = k < 4 ? k : 4;
     const bool ab = T.flags & 1u, ba = T.flags & 2u;
     const uint32_t s0 = T.tile_shift[0], s1 = T.tile_shift[1], t1 = T.tiles_n[0];
-    for (uint32_t i = a0 + threadIdx.x; i < a1; i += kJoinThreads) {
-        const uint64_t code = T.a.ix_code[i];
-        const uint32_t u = bucket_of(code, k, lead) - bl;
-        const uint32_t end = min(bdir[u + 1] - b0, nbe);  // the bucket lies inside the staged range
-        uint32_t lo = min(bdir[u] - b0, end);
-        uint32_t hi = end;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (bc[mid] < code) lo = mid + 1;
-            else hi = mid;
+    constexpr uint32_t U = kJoinUnroll;
+    // each thread takes U query entries per round, strided by the work-group size; their
+    // code, gene and count are loaded together up front so the global latencies overlap
+    for (uint32_t base = a0; base < a1; base += U * kJoinThreads) {
+        uint64_t code[U];
+        uint32_t gene[U], cnt[U];
+#pragma unroll
+        for (uint32_t q = 0; q < U; ++q) {
+            const uint32_t i = base + q * kJoinThreads + threadIdx.x;
+            const bool v = i < a1;
+            code[q] = v ? T.a.ix_code[i] : ~0ull;
+            gene[q] = v ? T.a.ix_gene[i] : 0u;
+            cnt[q] = v && WRITE ? T.a.ix_cnt[i] : 0u;
         }
-        uint32_t m = 0;
-        while (lo + m < end && bc[lo + m] == code) ++m;
-        if (!m) continue;
-        const uint32_t ag = T.a.ix_gene[i];
-        if (!WRITE) {
-            if (ab) atomicAdd(&tcount[ag >> s0], m);
-            if (ba)
-                for (uint32_t t = 0; t < m; ++t) atomicAdd(&tcount[t1 + (bg[lo + t] >> s1)], 1u);
-        } else {
-            const uint32_t an = T.a.ix_cnt[i];
-            if (ab) {
-                const uint32_t p = atomicAdd(&tcount[ag >> s0], m);
-                const uint32_t rl = (ag & ((1u << s0) - 1u)) << 24;
-                for (uint32_t t = 0; t < m; ++t)
-                    if (p + t < rec_cap) recs[p + t] = make_uint2(rl | bg[lo + t], min(an, bn[lo + t]));
+#pragma unroll
+        for (uint32_t q = 0; q < U; ++q) {
+            if (base + q * kJoinThreads + threadIdx.x >= a1) continue;
+            const uint64_t c = code[q];
+            const uint32_t u = bucket_of(c, k, lead) - bl;
+            const uint32_t end = min(bdir[u + 1] - b0, nbe);  // the bucket lies inside the staged range
+            uint32_t lo = min(bdir[u] - b0, end);
+            uint32_t hi = end;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (bc[mid] < c) lo = mid + 1;
+                else hi = mid;
             }
-            if (ba) {
-                for (uint32_t t = 0; t < m; ++t) {
-                    const uint32_t g = bg[lo + t];
-                    const uint32_t p = atomicAdd(&tcount[t1 + (g >> s1)], 1u);
-                    if (p < rec_cap) recs[p] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | ag, min(an, bn[lo + t]));
+            uint32_t m = 0;
+            while (lo + m < end && bc[lo + m] == c) ++m;
+            if (!m) continue;
+            const uint32_t ag = gene[q];
+            if (!WRITE) {
+                if (ab) atomicAdd(&tcount[ag >> s0], m);
+                if (ba)
+                    for (uint32_t t = 0; t < m; ++t) atomicAdd(&tcount[t1 + (bg[lo + t] >> s1)], 1u);
+            } else {
+                const uint32_t an = cnt[q];
+                if (ab) {
+                    const uint32_t p = atomicAdd(&tcount[ag >> s0], m);
+                    const uint32_t rl = (ag & ((1u << s0) - 1u)) << 24;
+                    for (uint32_t t = 0; t < m; ++t)
+                        if (p + t < rec_cap) recs[p + t] = make_uint2(rl | bg[lo + t], min(an, bn[lo + t]));
+                }
+                if (ba) {
+                    for (uint32_t t = 0; t < m; ++t) {
+                        const uint32_t g = bg[lo + t];
+                        const uint32_t p = atomicAdd(&tcount[t1 + (g >> s1)], 1u);
+                        if (p < rec_cap)
+                            recs[p] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | ag, min(an, bn[lo + t]));
+                    }
                 }
             }
         }
