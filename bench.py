@@ -148,7 +148,7 @@ def main():
     if args.tune:
         best, tres = pdp.autotune(tasks, reps=3)
         prm = best
-        tuned = {"lds_budget": int(best.lds_budget), "join_entries": int(best.join_entries),
+        tuned = {"tile_rows": int(best.tile_rows), "lds_budget": int(best.lds_budget), "join_entries": int(best.join_entries),
                  "persistent": bool(best.flags & B.PDP_PARAM_PERSISTENT), "best_ms": round(tres.best_ms, 4),
                  "first_ms": round(tres.first_ms, 4), "candidates": int(tres.tried)}
     runner = pdp.PairRunner(tasks, prm)

@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define PDP_ABI_VERSION 1u
+#define PDP_ABI_VERSION 2u
 
 /* Largest k: 5-bit residue codes of k <= 12 residues fit in 60 bits. */
 #define PDP_K_MAX 12u
@@ -113,7 +113,7 @@ typedef struct pdp_dict {
     uint32_t k;
     uint64_t capacity;    /* entries every per-entry array can hold (>= total windows) */
     uint32_t n_buckets;   /* index directory size: 20^min(k,4) leading-residue buckets */
-    uint32_t reserved;
+    uint32_t key_shift;   /* gene bits of ix_key; 0: this dictionary has no packed keys */
     uint32_t *nwin;       /* [n_genes] windows per gene, max(0, |g|-k+1) */
     uint32_t *mv_ptr;     /* [n_genes+1] CSR offsets; mv_ptr[n_genes] = entries E */
     uint64_t *mv_code;    /* [capacity] codes, strictly ascending inside a gene */
@@ -122,6 +122,11 @@ typedef struct pdp_dict {
     uint64_t *ix_code;    /* [capacity] all entries ordered by (code, gene) */
     uint32_t *ix_gene;    /* [capacity] gene of each index entry */
     uint32_t *ix_cnt;     /* [capacity] multiplicity of the code in that gene */
+    uint32_t *ix_key;     /* [capacity] when key_shift > 0: (tail << key_shift) | gene per index
+                             entry, where tail is the code without its leading min(k,4) residues
+                             (those are the entry's bucket) and key_shift is the bit length of
+                             n_genes - 1 (at least 1); packed when 5*(k - min(k,4)) + key_shift
+                             <= 32.  Within a bucket the keys ascend like (code, gene). */
     pdp_status *status;   /* device status of the last pdp_dict_build */
 } pdp_dict;
 

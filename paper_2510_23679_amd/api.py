@@ -159,6 +159,8 @@ class Dictionary:
         out["ix_code"] = _view(self.arena, self.d.ix_code, e, torch.int64).cpu().numpy().view(np.uint64)
         out["ix_gene"] = _view(self.arena, self.d.ix_gene, e, torch.int32).cpu().numpy().view(np.uint32)
         out["ix_cnt"] = _view(self.arena, self.d.ix_cnt, e, torch.int32).cpu().numpy().view(np.uint32)
+        if self.d.key_shift:
+            out["ix_key"] = _view(self.arena, self.d.ix_key, e, torch.int32).cpu().numpy().view(np.uint32)
         return out
 
 

@@ -46,9 +46,9 @@ class pdp_genome(C.Structure):
 
 
 class pdp_dict(C.Structure):
-    _fields_ = [("n_genes", u32), ("k", u32), ("capacity", u64), ("n_buckets", u32), ("reserved", u32),
+    _fields_ = [("n_genes", u32), ("k", u32), ("capacity", u64), ("n_buckets", u32), ("key_shift", u32),
                 ("nwin", vp), ("mv_ptr", vp), ("mv_code", vp), ("mv_cnt", vp), ("ix_dir", vp),
-                ("ix_code", vp), ("ix_gene", vp), ("ix_cnt", vp), ("status", vp)]
+                ("ix_code", vp), ("ix_gene", vp), ("ix_cnt", vp), ("ix_key", vp), ("status", vp)]
 
 
 class pdp_bh_out(C.Structure):
@@ -157,6 +157,9 @@ class PdpError(RuntimeError):
         self.code = code
 
 
+ABI_VERSION = 2  # the layout of the structures above; include/pdp.h defines the same number
+
+
 def lib():
     """The loaded libpdp.so; raises if it has not been built."""
     global _lib
@@ -169,6 +172,9 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        if L.pdp_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI {L.pdp_abi_version()}, this binding expects {ABI_VERSION}: "
+                               "rebuild it with __graft_entry__.build()")
         _lib = L
     return _lib
 

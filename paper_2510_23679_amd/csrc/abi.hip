@@ -132,6 +132,7 @@ static uint64_t dict_arena_bytes(uint32_t n_genes, uint64_t n_residues, uint32_t
     s += align_up(8 * cap, A);                      // ix_code
     s += align_up(4 * cap, A);                      // ix_gene
     s += align_up(4 * cap, A);                      // ix_cnt
+    s += align_up(4 * cap, A);                      // ix_key
     s += align_up(sizeof(pdp_status), A);           // status
     return s;
 }
@@ -174,6 +175,8 @@ int32_t pdp_dict_bind(void *arena, uint64_t arena_bytes, uint32_t n_genes, uint6
     d.ix_code = reinterpret_cast<uint64_t *>(take(8 * cap));
     d.ix_gene = reinterpret_cast<uint32_t *>(take(4 * cap));
     d.ix_cnt = reinterpret_cast<uint32_t *>(take(4 * cap));
+    d.ix_key = reinterpret_cast<uint32_t *>(take(4 * cap));
+    d.key_shift = key_shift_for(n_genes, k);
     d.status = reinterpret_cast<pdp_status *>(take(sizeof(pdp_status)));
     *out = d;
     return ok();
@@ -233,10 +236,11 @@ static DevDict dev_dict(const pdp_dict *d) {
     x.ix_cnt = d->ix_cnt;
     x.ix_dir = d->ix_dir;
     x.nwin = d->nwin;
+    x.ix_key = d->ix_key;
     x.n_genes = d->n_genes;
     x.n_buckets = d->n_buckets;
     x.k = d->k;
-    x.reserved = 0;
+    x.key_shift = d->key_shift;
     return x;
 }
 
@@ -287,7 +291,9 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         const uint64_t e_max = std::max<uint64_t>(std::max(tk.a->capacity, tk.b->capacity), 1);
         // sub-ranges of bpw buckets hold ~join_entries entries of the larger genome; an item
         // takes as many sub-ranges as its directory slice (kJoinDirCap buckets) allows
-        uint64_t bpw = uint64_t(join_entries) * nb / e_max;
+        // packed keys take half the LDS per staged entry: twice the entries per sub-range
+        const bool packed = tk.a->key_shift && tk.b->key_shift;
+        uint64_t bpw = uint64_t(join_entries) * (packed ? kJoinLdsCapP / kJoinLdsCap : 1) * nb / e_max;
         bpw = std::min<uint64_t>(std::max<uint64_t>(bpw, 1), std::min<uint64_t>(nb, kJoinDirCap));
         const uint64_t subs = std::max<uint64_t>(1, kJoinDirCap / bpw);
         d.bpw = static_cast<uint32_t>(bpw);

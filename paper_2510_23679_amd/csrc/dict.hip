@@ -483,6 +483,22 @@ __device__ void bin_directory(const DevBuild &B, CP code, uint32_t n, uint32_t l
 }
 
 __device__ __forceinline__ uint64_t rec_code(const uint4 &r) { return (static_cast<uint64_t>(r.y) << 32) | r.x; }
+
+// Packed join key of an index entry: the code's trailing residues (the leading ones are
+// the bucket) above the gene.
+__device__ __forceinline__ uint32_t entry_key(const DevBuild &B, uint64_t code, uint32_t gene) {
+    const uint32_t tb = 5 * (B.k - B.lead);
+    const uint64_t tail = tb ? code & ((1ull << tb) - 1) : 0ull;
+    return static_cast<uint32_t>(tail << B.key_shift) | gene;
+}
+
+__device__ __forceinline__ void put_entry(const DevBuild &B, uint32_t pos, const uint4 &v) {
+    const uint64_t c = rec_code(v);
+    B.ix_code[pos] = c;
+    B.ix_gene[pos] = v.z;
+    B.ix_cnt[pos] = v.w;
+    if (B.key_shift) B.ix_key[pos] = entry_key(B, c, v.z);
+}
 __device__ __forceinline__ bool rec_less(const uint4 &a, const uint4 &b) {
     return entry_less(rec_code(a), a.z, rec_code(b), b.z);
 }
@@ -599,22 +615,12 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
             }
         }
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < n; i += 256) {
-            const uint4 v = s_rec[i];
-            B.ix_code[lo + i] = rec_code(v);
-            B.ix_gene[lo + i] = v.z;
-            B.ix_cnt[lo + i] = v.w;
-        }
+        for (uint32_t i = threadIdx.x; i < n; i += 256) put_entry(B, lo + i, s_rec[i]);
     } else if (n <= kIxBinLds) {
         for (uint32_t i = threadIdx.x; i < n; i += 256) s_rec[i] = B.ix_tmp[lo + i];
         __syncthreads();
         sort_recs(s_rec, n);
-        for (uint32_t i = threadIdx.x; i < n; i += 256) {
-            const uint4 v = s_rec[i];
-            B.ix_code[lo + i] = rec_code(v);
-            B.ix_gene[lo + i] = v.z;
-            B.ix_cnt[lo + i] = v.w;
-        }
+        for (uint32_t i = threadIdx.x; i < n; i += 256) put_entry(B, lo + i, s_rec[i]);
         __syncthreads();
         bin_directory(B, B.ix_code + lo, n, lo, b0, b1);
     } else {
@@ -626,6 +632,8 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
         }
         __syncthreads();
         sort_entries(B.ix_code + lo, B.ix_gene + lo, B.ix_cnt + lo, n);
+        if (B.key_shift)
+            for (uint32_t i = threadIdx.x; i < n; i += 256) B.ix_key[lo + i] = entry_key(B, B.ix_code[lo + i], B.ix_gene[lo + i]);
         bin_directory(B, B.ix_code + lo, n, lo, b0, b1);
     }
     if (h + 1 == B.nh && threadIdx.x == 0) B.ix_dir[B.nb] = hi;
@@ -748,6 +756,8 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
             B.ix_code = D.ix_code;
             B.ix_gene = D.ix_gene;
             B.ix_cnt = D.ix_cnt;
+            B.ix_key = D.ix_key;
+            B.key_shift = D.key_shift;
             B.status = D.status;
             B.slot_code = slot_code + res_base;
             B.slot_cnt = slot_cnt + res_base;

@@ -23,6 +23,7 @@ constexpr uint32_t kIxBinTarget = 1024;      // average index entries per coarse
 constexpr uint32_t kIxBinLds = 2048;         // coarse bins up to this size are sorted in LDS
 constexpr uint32_t kIxMaxBins = 8192;        // coarse bins per genome at most (LDS histogram)
 constexpr uint32_t kJoinLdsCap = 1024;       // target index entries staged in LDS per join sub-range
+constexpr uint32_t kJoinLdsCapP = 2048;      // the same for dictionaries with packed 32-bit keys
 constexpr uint32_t kJoinDirCap = 1024;       // leading-residue buckets per join item (sub-ranges x buckets)
 constexpr uint32_t kJoinTileCap = 1024;      // accumulation tiles per task (one LDS counter each in the join)
 constexpr uint32_t kTileMaxRows = 256;       // rows per accumulation tile (8-bit row field of a record)
@@ -44,6 +45,12 @@ inline uint32_t n_buckets_for(uint32_t k) {
     for (uint32_t i = 0; i < lead_residues(k); ++i) nb *= 20;
     return nb;
 }
+// Gene bits of a dictionary's packed index keys, 0 when tail and gene do not fit 32 bits.
+inline uint32_t key_shift_for(uint32_t n_genes, uint32_t k) {
+    uint32_t gb = 1;
+    while (gb < 32 && (1ull << gb) < n_genes) ++gb;
+    return 5 * (k - lead_residues(k)) + gb <= 32 ? gb : 0;
+}
 inline uint32_t scan_partials(uint64_t n) { return static_cast<uint32_t>((n + kScanItems - 1) / kScanItems) + 1; }
 
 // --------------------------------------------------------- device tables
@@ -53,10 +60,11 @@ struct DevDict {
     const uint32_t *ix_cnt;
     const uint32_t *ix_dir;
     const uint32_t *nwin;
+    const uint32_t *ix_key;  // packed (tail, gene) keys when key_shift > 0
     uint32_t n_genes;
     uint32_t n_buckets;
     uint32_t k;
-    uint32_t reserved;
+    uint32_t key_shift;
 };
 
 struct DevTask {
@@ -105,6 +113,8 @@ struct DevBuild {
     uint32_t *mv_cnt, *ix_dir;
     uint64_t *ix_code;
     uint32_t *ix_gene, *ix_cnt;
+    uint32_t *ix_key;     // packed keys, written when key_shift > 0
+    uint32_t key_shift;
     pdp_status *status;
     uint64_t *slot_code;  // per gene g: sorted distinct codes at offset gene_off[g]
     uint32_t *slot_cnt;

@@ -36,7 +36,8 @@
 namespace pdp {
 
 constexpr uint32_t kJoinThreads = 256;
-constexpr uint32_t kJoinUnroll = 4;  // query entries a join thread loads at once
+constexpr uint32_t kJoinUnroll = 4;   // query entries a join thread loads at once (64-bit codes)
+constexpr uint32_t kJoinUnrollP = 8;  // the same with packed keys
 static_assert(kTilePer * (kTileThreads / kWave) <= kWave, "tile head counts are scanned by one wave");
 
 // LDS of one join item: the task descriptor, the item's slice of both bucket
@@ -56,10 +57,14 @@ struct JoinLdsCount : JoinLdsBase {
     uint32_t bgene[kJoinLdsCap];
 };
 struct JoinLdsWrite : JoinLdsCount {
-    uint32_t bcnt[kJoinLdsCap];
+    uint16_t bcnt[kJoinLdsCapP];  // multiplicities are at most PDP_MAX_WINDOWS
 };
+static_assert(sizeof(uint32_t) * kJoinLdsCap >= sizeof(uint16_t) * kJoinLdsCapP, "bucket table fits the gene stage");
+static_assert(sizeof(uint64_t) * kJoinLdsCap >= sizeof(uint32_t) * kJoinLdsCapP, "packed keys reuse the code stage");
 template <bool WRITE>
 using JoinLds = typename std::conditional<WRITE, JoinLdsWrite, JoinLdsCount>::type;
+__device__ __forceinline__ uint16_t *bcnt_of(JoinLdsWrite &L) { return L.bcnt; }
+__device__ __forceinline__ uint16_t *bcnt_of(JoinLdsCount &) { return nullptr; }
 
 // Index of the last task whose chunk_base <= chunk, found by the whole work-group with a
 // 256-way search (one memory round trip per level: two levels cover 65536 tasks).
@@ -87,9 +92,9 @@ __device__ __forceinline__ uint32_t find_task_coop(const DevTask *tasks, uint32_
 // bucket - bl); a binary search inside that bucket finds the first equal code.
 // WRITE = false adds the records each tile will receive to tcount; WRITE = true
 // takes slots from the tcount cursors and writes the records.  No barriers.
-template <bool WRITE>
+template <bool WRITE, typename CN>
 __device__ __forceinline__ void join_range(const DevTask &T, uint32_t a0, uint32_t a1, uint32_t b0, uint32_t nbe,
-                                           const uint64_t *bc, const uint32_t *bg, const uint32_t *bn,
+                                           const uint64_t *bc, const uint32_t *bg, const CN *bn,
                                            const uint32_t *bdir, uint32_t bl, uint32_t *tcount, uint2 *recs,
                                            uint64_t rec_cap) {
     const uint32_t k = T.a.k, lead = k < 4 ? k : 4;
@@ -136,18 +141,114 @@ __device__ __forceinline__ void join_range(const DevTask &T, uint32_t a0, uint32
                     const uint32_t p = atomicAdd(&tcount[ag >> s0], m);
                     const uint32_t rl = (ag & ((1u << s0) - 1u)) << 24;
                     for (uint32_t t = 0; t < m; ++t)
-                        if (p + t < rec_cap) recs[p + t] = make_uint2(rl | bg[lo + t], min(an, bn[lo + t]));
+                        if (p + t < rec_cap)
+                            recs[p + t] = make_uint2(rl | bg[lo + t], min(an, static_cast<uint32_t>(bn[lo + t])));
                 }
                 if (ba) {
                     for (uint32_t t = 0; t < m; ++t) {
                         const uint32_t g = bg[lo + t];
                         const uint32_t p = atomicAdd(&tcount[t1 + (g >> s1)], 1u);
                         if (p < rec_cap)
-                            recs[p] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | ag, min(an, bn[lo + t]));
+                            recs[p] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | ag,
+                                                 min(an, static_cast<uint32_t>(bn[lo + t])));
                     }
                 }
             }
         }
+    }
+}
+
+// Packed form of the join, used when both dictionaries carry 32-bit (tail, gene) keys:
+// entries are compared by the tail (the code without its leading residues, which the
+// bucket fixes), so an entry moves 4 bytes (8 in the write pass, with its count) instead
+// of 16, and twice as many target entries fit the LDS stage.  A query entry's bucket
+// comes from the staged query directory (the last bucket starting at or before it).
+struct JoinRoundP {
+    uint32_t key[kJoinUnrollP], cnt[kJoinUnrollP];
+};
+
+template <bool WRITE>
+__device__ __forceinline__ void join_load_p(const DevDict &A, uint32_t base, uint32_t a1, JoinRoundP &r) {
+#pragma unroll
+    for (uint32_t q = 0; q < kJoinUnrollP; ++q) {
+        const uint32_t i = base + q * kJoinThreads + threadIdx.x;
+        const bool v = i < a1;
+        r.key[q] = v ? A.ix_key[i] : 0u;
+        r.cnt[q] = v && WRITE ? A.ix_cnt[i] : 0u;
+    }
+}
+
+template <bool WRITE, typename CN>
+__device__ __forceinline__ void join_round_p(const DevTask &T, const JoinRoundP &r, uint32_t base, uint32_t a0,
+                                             uint32_t a1, const uint16_t *abk, uint32_t jlo, uint32_t jhi,
+                                             const uint32_t *adir, uint32_t b0,
+                                             uint32_t nbe, const uint32_t *bk, const CN *bn,
+                                             const uint32_t *bdir, uint32_t *tcount, uint2 *recs, uint64_t rec_cap) {
+    const bool ab = T.flags & 1u, ba = T.flags & 2u;
+    const uint32_t s0 = T.tile_shift[0], s1 = T.tile_shift[1], t1 = T.tiles_n[0];
+    const uint32_t sha = T.a.key_shift, shb = T.b.key_shift;
+    const uint32_t mska = (1u << sha) - 1u, mskb = (1u << shb) - 1u;
+#pragma unroll
+    for (uint32_t q = 0; q < kJoinUnrollP; ++q) {
+        const uint32_t i = base + q * kJoinThreads + threadIdx.x;
+        if (i >= a1) continue;
+        const uint32_t ag = r.key[q] & mska, tail = r.key[q] >> sha;
+        // bucket of entry i: from the sub-range's table, else the last directory slot in
+        // [jlo, jhi) with adir <= i
+        uint32_t lo = jlo, hi = jhi;
+        if (abk) {
+            lo = abk[i - a0];
+        } else {
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (adir[mid] <= i) lo = mid;
+                else hi = mid;
+            }
+        }
+        const uint32_t end = min(bdir[lo + 1] - b0, nbe);
+        uint32_t p = min(bdir[lo] - b0, end), h = end;
+        while (p < h) {
+            const uint32_t mid = (p + h) >> 1;
+            if ((bk[mid] >> shb) < tail) p = mid + 1;
+            else h = mid;
+        }
+        uint32_t m = 0;
+        while (p + m < end && (bk[p + m] >> shb) == tail) ++m;
+        if (!m) continue;
+        if (!WRITE) {
+            if (ab) atomicAdd(&tcount[ag >> s0], m);
+            if (ba)
+                for (uint32_t t = 0; t < m; ++t) atomicAdd(&tcount[t1 + ((bk[p + t] & mskb) >> s1)], 1u);
+        } else {
+            const uint32_t an = r.cnt[q];
+            if (ab) {
+                const uint32_t o = atomicAdd(&tcount[ag >> s0], m);
+                const uint32_t rl = (ag & ((1u << s0) - 1u)) << 24;
+                for (uint32_t t = 0; t < m; ++t)
+                    if (o + t < rec_cap)
+                        recs[o + t] = make_uint2(rl | (bk[p + t] & mskb), min(an, static_cast<uint32_t>(bn[p + t])));
+            }
+            if (ba) {
+                for (uint32_t t = 0; t < m; ++t) {
+                    const uint32_t g = bk[p + t] & mskb;
+                    const uint32_t o = atomicAdd(&tcount[t1 + (g >> s1)], 1u);
+                    if (o < rec_cap)
+                        recs[o] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | ag, min(an, static_cast<uint32_t>(bn[p + t])));
+                }
+            }
+        }
+    }
+}
+
+template <bool WRITE, typename CN>
+__device__ __forceinline__ void join_range_p(const DevTask &T, JoinRoundP &r, bool loaded, uint32_t a0, uint32_t a1,
+                                             const uint16_t *abk, uint32_t jlo, uint32_t jhi, const uint32_t *adir,
+                                             uint32_t b0,
+                                             uint32_t nbe, const uint32_t *bk, const CN *bn,
+                                             const uint32_t *bdir, uint32_t *tcount, uint2 *recs, uint64_t rec_cap) {
+    for (uint32_t base = a0; base < a1; base += kJoinUnrollP * kJoinThreads) {
+        if (!loaded || base != a0) join_load_p<WRITE>(T.a, base, a1, r);
+        join_round_p<WRITE>(T, r, base, a0, a1, abk, jlo, jhi, adir, b0, nbe, bk, bn, bdir, tcount, recs, rec_cap);
     }
 }
 
@@ -174,6 +275,7 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
     const uint32_t bl = c * span;
     const uint32_t bh = min(nb, bl + span);
     const uint32_t ntiles = T.tiles_n[0] + T.tiles_n[1];
+    const bool packed = T.a.key_shift && T.b.key_shift;
     for (uint32_t i = threadIdx.x; i <= bh - bl; i += blockDim.x) {
         L.adir[i] = T.a.ix_dir[bl + i];
         L.bdir[i] = T.b.ix_dir[bl + i];
@@ -187,6 +289,30 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
         const uint32_t b0 = L.bdir[s0 - bl], b1 = L.bdir[s1 - bl];
         if (a0 == a1 || b0 == b1) continue;  // uniform across the work-group
         const uint32_t nbe = b1 - b0;
+        if (packed) {
+            JoinRoundP r;
+            uint32_t *bkey = reinterpret_cast<uint32_t *>(L.bcode);  // packed keys take the code stage
+            // the query entries' buckets, when they fit, in a table over the unused gene stage
+            uint16_t *abk = a1 - a0 <= kJoinLdsCapP ? reinterpret_cast<uint16_t *>(L.bgene) : nullptr;
+            if (nbe <= kJoinLdsCapP) {
+                join_load_p<WRITE>(T.a, a0, a1, r);  // in flight while the target side is staged
+                for (uint32_t i = threadIdx.x; i < nbe; i += kJoinThreads) {
+                    bkey[i] = T.b.ix_key[b0 + i];
+                    if constexpr (WRITE) L.bcnt[i] = T.b.ix_cnt[b0 + i];
+                }
+                if (abk)
+                    for (uint32_t u = s0 - bl + threadIdx.x; u < s1 - bl; u += kJoinThreads)
+                        for (uint32_t i = L.adir[u]; i < L.adir[u + 1]; ++i) abk[i - a0] = static_cast<uint16_t>(u);
+                __syncthreads();
+                join_range_p<WRITE>(T, r, true, a0, a1, abk, s0 - bl, s1 - bl, L.adir, b0, nbe, bkey,
+                                    WRITE ? bcnt_of(L) : nullptr, L.bdir, L.tcount, recs, rec_cap);
+                __syncthreads();
+            } else {
+                join_range_p<WRITE>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, b0, nbe, T.b.ix_key + b0,
+                                    T.b.ix_cnt + b0, L.bdir, L.tcount, recs, rec_cap);
+            }
+            continue;
+        }
         if (nbe <= kJoinLdsCap) {
             for (uint32_t i = threadIdx.x; i < nbe; i += kJoinThreads) {
                 L.bcode[i] = T.b.ix_code[b0 + i];
@@ -197,7 +323,8 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
             if constexpr (WRITE)
                 join_range<true>(T, a0, a1, b0, nbe, L.bcode, L.bgene, L.bcnt, L.bdir, bl, L.tcount, recs, rec_cap);
             else
-                join_range<false>(T, a0, a1, b0, nbe, L.bcode, L.bgene, nullptr, L.bdir, bl, L.tcount, recs, rec_cap);
+                join_range<false>(T, a0, a1, b0, nbe, L.bcode, L.bgene, static_cast<const uint16_t *>(nullptr), L.bdir,
+                                  bl, L.tcount, recs, rec_cap);
             __syncthreads();  // the staged arrays take the next sub-range
         } else {
             join_range<WRITE>(T, a0, a1, b0, nbe, T.b.ix_code + b0, T.b.ix_gene + b0, T.b.ix_cnt + b0, L.bdir, bl,

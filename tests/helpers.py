@@ -38,6 +38,18 @@ def check_dictionary(host: dict, og: oracle.OracleGenome) -> None:
     dir_ = np.zeros(20 ** lead + 1, dtype=np.int64)
     np.add.at(dir_, bucket + 1, 1)
     assert np.array_equal(host["ix_dir"].astype(np.int64), np.cumsum(dir_)), "index directory"
+    # packed join keys: the trailing k - lead residues, 5 bits each, above the gene's bits
+    shift = max(1, (og.n - 1).bit_length()) if og.n > 1 else 1
+    tail_bits = 5 * (k - lead)
+    assert ("ix_key" in host) == (tail_bits + shift <= 32), "packed keys present exactly when they fit"
+    if "ix_key" in host:
+        rest = og.ids[order] % np.uint64(20 ** (k - lead))
+        tail = np.zeros(len(rest), dtype=np.uint64)
+        for j in range(k - lead):  # base 20 -> 5 bits per residue, most significant first
+            digit = (rest // np.uint64(20 ** (k - lead - 1 - j))) % np.uint64(20)
+            tail = (tail << np.uint64(5)) | digit
+        want = (tail << np.uint64(shift)) | genes[order].astype(np.uint64)
+        assert np.array_equal(host["ix_key"].astype(np.uint64), want), "packed index keys"
 
 
 def check_bh(got, want: oracle.BH, rows=None) -> None:
