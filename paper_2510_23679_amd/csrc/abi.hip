@@ -333,7 +333,9 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         }
         d.bbh_row_base = static_cast<uint32_t>(bbh_rows);
         if (flags & PDP_TASK_BBH) bbh_rows += tk.a->n_genes;
-        rec_est += ndirs * ((tk.a->capacity + tk.b->capacity) / 2 + 4096);
+        // divergent homologs share a fraction of their k-mers: an eighth of the entries per
+        // direction covers the family workloads with room; more needs a capacity retry
+        rec_est += ndirs * ((tk.a->capacity + tk.b->capacity) / 8 + 4096);
         cost[t] = tk.a->capacity + tk.b->capacity;
         P->ab_row.push_back(d.row_base[0]);
         P->ba_row.push_back(d.row_base[1]);

@@ -545,7 +545,10 @@ __device__ __forceinline__ void tile_sorted(const DevTile &tl, const DevTask &T,
     __syncthreads();
     // window counts in one round trip for the whole tile: the column's joins its sum
     // (both at most 16 bits), the rows' go to S.nr
-    for (uint32_t r = threadIdx.x; r < u; r += kTileThreads) msum[r] |= C.nwin[ucol[r] & 0xFFFFFFu] << 16;
+    for (uint32_t r = threadIdx.x; r < u; r += kTileThreads) {
+        const uint32_t c = ucol[r] & 0xFFFFFFu;
+        msum[r] |= (c < C.n_genes ? C.nwin[c] : 0u) << 16;  // a column past the genome is never a row's
+    }
     for (uint32_t rl = threadIdx.x; rl < tl.nrows; rl += kTileThreads) S.nr[rl] = R.nwin[tl.row0 + rl];
     __syncthreads();
     for (uint32_t rl = w; rl < tl.nrows; rl += NW) {
@@ -594,8 +597,8 @@ __device__ __forceinline__ void tile_dense(const DevTile &tl, const DevTask &T, 
         for (uint32_t i = threadIdx.x; i < n; i += kTileThreads) {
             const uint2 r = recs[rb + i];
             const uint32_t rr = (r.x >> 24) - g0;
-            if (rr >= gn) continue;
             const uint32_t c = r.x & 0xFFFFFFu, wd = c >> 1;
+            if (rr >= gn || c >= ncols) continue;
             const uint32_t old = atomicAdd(&acc[rr * W + wd], r.y << ((c & 1u) << 4));
             if (old == 0) atomicOr(&bits[rr * WB + (wd >> 5)], 1u << (wd & 31u));
         }
@@ -711,9 +714,12 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
         S.nr[rl] = R.nwin[tl.row0 + rl];
     }
     __syncthreads();
+    const uint32_t ncols = C.n_genes;
     for (uint32_t i = threadIdx.x; i < n; i += kTileThreads) {
         const uint2 r = recs[rb + i];
-        if (filter && (r.x >> 24) - g0 >= g1 - g0) continue;
+        // rows and columns are checked, so no record can address past the tile's rows or the
+        // column genome's window counts
+        if ((r.x >> 24) - g0 >= g1 - g0 || (r.x & 0xFFFFFFu) >= ncols) continue;
         const uint32_t key = r.x + 1;  // columns stay below 2^24 - 1, so no wrap to 0
         uint32_t h = (key * 2654435761u) >> (32 - kHashBits);
         for (;;) {  // ends: at most kHashMax < kHashSlots keys are distinct
@@ -774,16 +780,19 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
 template <bool WRITE>
 __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__restrict__ tasks,
                                              const DevTile *__restrict__ tiles, const uint32_t *__restrict__ cells,
-                                             const uint2 *__restrict__ recs, uint64_t rec_cap, uint32_t lds_words,
+                                             const uint2 *__restrict__ recs, uint64_t rec_cap,
+                                             const unsigned long long *__restrict__ total, uint32_t lds_words,
                                              uint32_t *__restrict__ bh_ptr, uint4 *__restrict__ slab,
                                              uint32_t *__restrict__ bh_col, uint32_t *__restrict__ bh_num,
                                              uint32_t *__restrict__ bh_den, uint64_t bh_cap, uint32_t *overflow_tiles,
                                              uint32_t *overflow_count, uint32_t *lds, TileLds &S) {
     const DevTile tl = tiles[tile_id];
     const DevTask &T = tasks[tl.task];
+    // when the join's records overflowed the scratch its write pass wrote none: every tile is
+    // empty then (the status already asks for a larger capacity)
     const uint64_t c0 = cells[tl.cell0], c1 = cells[tl.cell1];
     const uint64_t rb = min(c0, rec_cap);
-    const uint64_t re = max(rb, min(c1, rec_cap));
+    const uint64_t re = *total > rec_cap ? rb : max(rb, min(c1, rec_cap));
     const uint32_t n = static_cast<uint32_t>(re - rb);
     if (threadIdx.x == 0) S.flag = 0;
     __syncthreads();
@@ -823,21 +832,22 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count(const DevTask *__re
                                                              const DevTile *__restrict__ tiles,
                                                              const uint32_t *__restrict__ cells,
                                                              const uint2 *__restrict__ recs, uint64_t rec_cap,
+                                                             const unsigned long long *__restrict__ total,
                                                              uint32_t lds_words, uint32_t *__restrict__ bh_ptr,
                                                              uint4 *__restrict__ slab, uint32_t *overflow_tiles,
                                                              uint32_t *overflow_count) {
     extern __shared__ uint32_t lds[];
     __shared__ TileLds S;
-    tile_process<false>(blockIdx.x, tasks, tiles, cells, recs, rec_cap, lds_words, bh_ptr, slab, nullptr, nullptr,
+    tile_process<false>(blockIdx.x, tasks, tiles, cells, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr, nullptr,
                         nullptr, 0, overflow_tiles, overflow_count, lds, S);
 }
 
 // Persistent form: a fixed grid pulls tiles from a counter until none are left.
 __global__ __launch_bounds__(kTileThreads) void k_tile_count_persistent(
     const DevTask *__restrict__ tasks, const DevTile *__restrict__ tiles, uint32_t total_tiles,
-    const uint32_t *__restrict__ cells, const uint2 *__restrict__ recs, uint64_t rec_cap, uint32_t lds_words,
-    uint32_t *__restrict__ bh_ptr, uint4 *__restrict__ slab, uint32_t *overflow_tiles, uint32_t *overflow_count,
-    uint32_t *__restrict__ next) {
+    const uint32_t *__restrict__ cells, const uint2 *__restrict__ recs, uint64_t rec_cap,
+    const unsigned long long *__restrict__ total, uint32_t lds_words, uint32_t *__restrict__ bh_ptr,
+    uint4 *__restrict__ slab, uint32_t *overflow_tiles, uint32_t *overflow_count, uint32_t *__restrict__ next) {
     extern __shared__ uint32_t lds[];
     __shared__ TileLds S;
     for (;;) {
@@ -848,7 +858,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count_persistent(
         if (first >= total_tiles) break;
         const uint32_t last = min(total_tiles, first + kClaim);
         for (uint32_t t = first; t < last; ++t)
-            tile_process<false>(t, tasks, tiles, cells, recs, rec_cap, lds_words, bh_ptr, slab, nullptr, nullptr,
+            tile_process<false>(t, tasks, tiles, cells, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr, nullptr,
                                 nullptr, 0, overflow_tiles, overflow_count, lds, S);
     }
 }
@@ -858,6 +868,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_write(const DevTask *__re
                                                              const DevTile *__restrict__ tiles,
                                                              const uint32_t *__restrict__ cells,
                                                              const uint2 *__restrict__ recs, uint64_t rec_cap,
+                                                             const unsigned long long *__restrict__ total,
                                                              uint32_t lds_words, uint32_t *__restrict__ bh_ptr,
                                                              uint32_t *__restrict__ bh_col, uint32_t *__restrict__ bh_num,
                                                              uint32_t *__restrict__ bh_den, uint64_t bh_cap,
@@ -867,7 +878,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_write(const DevTask *__re
     __shared__ TileLds S;
     const uint32_t n = *overflow_count;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
-        tile_process<true>(overflow_tiles[i], tasks, tiles, cells, recs, rec_cap, lds_words, bh_ptr, nullptr, bh_col,
+        tile_process<true>(overflow_tiles[i], tasks, tiles, cells, recs, rec_cap, total, lds_words, bh_ptr, nullptr, bh_col,
                            bh_num, bh_den, bh_cap, nullptr, nullptr, lds, S);
 }
 
@@ -1107,11 +1118,13 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     if (p.total_tiles && p.tile_grid) {
         hipLaunchKernelGGL(k_tile_count_persistent, dim3(std::min(p.tile_grid, (p.total_tiles + kClaim - 1) / kClaim)),
                            dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles, p.total_tiles, w.cells, w.recs,
-                           p.rec_cap, lds_words, bh->ptr, w.slab, w.overflow_tiles, w.overflow_count, w.next_tile);
+                           p.rec_cap, w.counters, lds_words, bh->ptr, w.slab, w.overflow_tiles, w.overflow_count,
+                           w.next_tile);
         PDP_TRY(hipGetLastError());
     } else if (p.total_tiles) {
         hipLaunchKernelGGL(k_tile_count, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
-                           w.cells, w.recs, p.rec_cap, lds_words, bh->ptr, w.slab, w.overflow_tiles, w.overflow_count);
+                           w.cells, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab, w.overflow_tiles,
+                           w.overflow_count);
         PDP_TRY(hipGetLastError());
     }
     PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, false));
@@ -1125,7 +1138,7 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     if (p.total_tiles) {
         const uint32_t g = p.total_tiles < 256 ? p.total_tiles : 256;
         hipLaunchKernelGGL(k_tile_write, dim3(g), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles, w.cells, w.recs,
-                           p.rec_cap, lds_words, bh->ptr, bh->col, bh->num, bh->den, bh->capacity, w.overflow_tiles,
+                           p.rec_cap, w.counters, lds_words, bh->ptr, bh->col, bh->num, bh->den, bh->capacity, w.overflow_tiles,
                            w.overflow_count);
         PDP_TRY(hipGetLastError());
     }

@@ -248,6 +248,25 @@ def test_dense_tile_in_several_passes():
     compare_all([ga, gb], 4, res)
 
 
+def test_capacity_overflow_reads_no_unwritten_records():
+    # a record capacity far below what the join counts: the first launch must stop at the
+    # count, report PDP_E_CAPACITY with the count, and touch none of the (poisoned) record
+    # scratch; the retry with the reported size gives the oracle's results
+    ds = make_config(1)
+    k = 4
+    dicts = [pdp.Dictionary.build_from(g, k) for g in ds.genomes]
+    say("capacity overflow with a poisoned workspace")
+    runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts), pdp.params(inc_capacity=64))
+    runner.ws.buf.fill_(255)  # every unwritten record would name row 255, column 2^24 - 1
+    runner.launch()
+    code, needed, where = pdp.read_status(runner.status)
+    assert code == pdp.PDP_E_CAPACITY and where == 0 and needed > 64
+    ptr = runner.bh.host()[0]
+    assert int(ptr[-1]) == 0  # every row empty in the overflowed launch
+    runner.run()
+    compare_all(ds.genomes, k, runner.results())
+
+
 def test_join_global_search_path():
     # one leading-residue bucket holding more target entries than the join stages in LDS
     rng = random.Random(11)
