@@ -136,9 +136,61 @@ __device__ __forceinline__ bool gene_ok(const DevBuild &B, uint32_t g, uint32_t 
     return true;
 }
 
-constexpr uint32_t kMvWaveE = 8;
-constexpr uint32_t kMvWaveCap = kWave * kMvWaveE;  // windows a wave sorts in registers
+constexpr uint32_t kMvWaveEMax = 16;
+constexpr uint32_t kMvWaveCap = kWave * kMvWaveEMax;  // windows a wave sorts in registers
 constexpr uint32_t kMvWaves = kMvThreads / kWave;
+
+// One gene's multiplicity vector by one wave: codes E per lane in registers, sorted by the
+// wave's bitonic network (E = 4, 8 or 16: the smallest that holds the gene), then run
+// heads ranked by a wave scan; head positions in LDS give the run lengths.  sym holds the
+// gene's residue symbols, hp kWave*E+1 slots.
+template <uint32_t E>
+__device__ __forceinline__ void mv_wave_gene(const DevBuild &B, const uint8_t *sym, uint16_t *hp, uint64_t o,
+                                             uint32_t nw, uint32_t *cnt_out) {
+    const uint32_t lane = lane_id();
+    const uint32_t k = B.k;
+    uint64_t key[E];
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+        const uint32_t p = lane * E + e;
+        uint64_t c = ~0ull;  // past the windows: sorts last
+        if (p < nw) {
+            c = 0;
+            for (uint32_t j = 0; j < k; ++j) c = (c << 5) | sym[p + j];
+        }
+        key[e] = c;
+    }
+    wave_bitonic_sort<E>(key);
+    const uint64_t before = __shfl_up(key[E - 1], 1, kWave);
+    uint32_t hmask = 0, nh = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+        const uint32_t i = lane * E + e;
+        const uint64_t prev = e ? key[e - 1] : before;
+        const bool h = i < nw && (i == 0 || key[e] != prev);
+        hmask |= static_cast<uint32_t>(h) << e;
+        nh += h;
+    }
+    const uint32_t incl = wave_inclusive_sum(nh);
+    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+    uint32_t r = incl - nh;
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e)
+        if ((hmask >> e) & 1u) hp[r++] = static_cast<uint16_t>(lane * E + e);
+    if (lane == 0) hp[total] = static_cast<uint16_t>(nw);
+    wave_lds_sync();
+    uint64_t *slot_code = B.slot_code + o;
+    uint32_t *slot_cnt = B.slot_cnt + o;
+    r = incl - nh;
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+        if (!((hmask >> e) & 1u)) continue;
+        slot_code[r] = key[e];
+        slot_cnt[r] = static_cast<uint32_t>(hp[r + 1]) - hp[r];
+        ++r;
+    }
+    *cnt_out = total;
+}
 
 __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restrict__ table, uint32_t n_genomes,
                                                         uint32_t total_genes, uint32_t *__restrict__ dcnt,
@@ -169,49 +221,10 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restri
         sym[p] = static_cast<uint8_t>(x);
     }
     wave_lds_sync();
-    const uint32_t k = B.k;
-    uint64_t key[kMvWaveE];
-#pragma unroll
-    for (uint32_t e = 0; e < kMvWaveE; ++e) {
-        const uint32_t p = lane * kMvWaveE + e;
-        uint64_t c = ~0ull;  // past the windows: sorts last
-        if (p < nw) {
-            c = 0;
-            for (uint32_t j = 0; j < k; ++j) c = (c << 5) | sym[p + j];
-        }
-        key[e] = c;
-    }
-    wave_bitonic_sort<kMvWaveE>(key);
-    // run heads: positions go to LDS so each head finds where the next run starts
-    const uint64_t before = __shfl_up(key[kMvWaveE - 1], 1, kWave);
-    uint32_t hmask = 0, nh = 0;
-#pragma unroll
-    for (uint32_t e = 0; e < kMvWaveE; ++e) {
-        const uint32_t i = lane * kMvWaveE + e;
-        const uint64_t prev = e ? key[e - 1] : before;
-        const bool h = i < nw && (i == 0 || key[e] != prev);
-        hmask |= static_cast<uint32_t>(h) << e;
-        nh += h;
-    }
-    const uint32_t incl = wave_inclusive_sum(nh);
-    const uint32_t total = __shfl(incl, kWave - 1, kWave);
-    uint16_t *hp = hp_all[w];
-    uint32_t r = incl - nh;
-#pragma unroll
-    for (uint32_t e = 0; e < kMvWaveE; ++e)
-        if ((hmask >> e) & 1u) hp[r++] = static_cast<uint16_t>(lane * kMvWaveE + e);
-    if (lane == 0) hp[total] = static_cast<uint16_t>(nw);
-    wave_lds_sync();
-    uint64_t *slot_code = B.slot_code + o;
-    uint32_t *slot_cnt = B.slot_cnt + o;
-    r = incl - nh;
-#pragma unroll
-    for (uint32_t e = 0; e < kMvWaveE; ++e) {
-        if (!((hmask >> e) & 1u)) continue;
-        slot_code[r] = key[e];
-        slot_cnt[r] = static_cast<uint32_t>(hp[r + 1]) - hp[r];
-        ++r;
-    }
+    uint32_t total;
+    if (nw <= kWave * 4) mv_wave_gene<4>(B, sym, hp_all[w], o, nw, &total);
+    else if (nw <= kWave * 8) mv_wave_gene<8>(B, sym, hp_all[w], o, nw, &total);
+    else mv_wave_gene<16>(B, sym, hp_all[w], o, nw, &total);
     if (lane == 0) dcnt[G] = total;
 }
 

@@ -18,7 +18,7 @@ namespace pdp {
 // ---------------------------------------------------------------- sizes
 constexpr uint32_t kScanItems = 4096;        // elements per scan work-group (256 threads x 16)
 constexpr uint32_t kMvSortCap = 2048;        // windows a gene may have to be sorted in LDS
-constexpr uint32_t kIxBlock = 4096;          // index entries per histogram block
+constexpr uint32_t kIxBlock = 8192;          // index entries per histogram block
 constexpr uint32_t kIxBinTarget = 1024;      // average index entries per coarse bin
 constexpr uint32_t kIxBinLds = 2048;         // coarse bins up to this size are sorted in LDS
 constexpr uint32_t kIxMaxBins = 8192;        // coarse bins per genome at most (LDS histogram)
