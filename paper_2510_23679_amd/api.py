@@ -457,6 +457,7 @@ class Graph:
     def __init__(self, stream: torch.cuda.Stream):
         self.stream = stream
         self.h = B.vp()
+        self._destroy = lib().pdp_graph_destroy  # bound now: module globals may be gone at interpreter exit
 
     @classmethod
     def capture(cls, stream: torch.cuda.Stream) -> "Graph":
@@ -477,11 +478,9 @@ class Graph:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
-            try:
-                lib().pdp_graph_destroy(h)
-            except Exception:  # pragma: no cover - interpreter shutdown
-                pass
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self.h = B.vp()
 
 

@@ -11,18 +11,34 @@ namespace pdp {
 constexpr uint32_t kWave = 64;
 constexpr uint32_t kInvalidSym = 0xFFu;
 
-// Residue letter -> 5-bit symbol (A=0 ... Y=19 in the order ACDEFGHIKLMNPQRSTVWY), 0xFF otherwise.
-struct SymTable {
-    uint8_t v[256];
-};
-constexpr SymTable make_sym_table() {
-    SymTable t{};
-    for (int i = 0; i < 256; ++i) t.v[i] = 0xFF;
+// Residue letter -> 5-bit symbol (A=0 ... Y=19 in the order ACDEFGHIKLMNPQRSTVWY), kInvalidSym
+// otherwise.  The 26 upper-case letters' symbols sit 5 bits each in three 64-bit constants
+// (12 letters per word, 31 = not an amino acid), so the mapping is register arithmetic and
+// no memory load.
+constexpr uint64_t sym_word(int w) {
     const char letters[] = "ACDEFGHIKLMNPQRSTVWY";
-    for (int i = 0; i < 20; ++i) t.v[static_cast<uint8_t>(letters[i])] = static_cast<uint8_t>(i);
-    return t;
+    uint64_t word = 0;
+    for (int j = 0; j < 12; ++j) {
+        const int letter = 12 * w + j;  // 0 = 'A'
+        uint64_t s = 31;
+        for (int i = 0; i < 20; ++i)
+            if (letters[i] - 'A' == letter) s = static_cast<uint64_t>(i);
+        word |= s << (5 * j);
+    }
+    return word;
 }
-static __constant__ constexpr SymTable kSym = make_sym_table();
+constexpr uint64_t kSymWord0 = sym_word(0), kSymWord1 = sym_word(1), kSymWord2 = sym_word(2);
+static_assert((kSymWord0 & 31) == 0 && ((kSymWord0 >> 5) & 31) == 31 && ((kSymWord0 >> 10) & 31) == 1,
+              "A -> 0, B -> none, C -> 1");
+static_assert((kSymWord2 & 31) == 19 && ((kSymWord2 >> 5) & 31) == 31, "Y -> 19, Z -> none");
+
+__device__ __forceinline__ uint32_t sym_of(uint32_t byte) {
+    const uint32_t i = byte - 'A';
+    if (i >= 26u) return kInvalidSym;
+    const uint64_t word = i < 12u ? kSymWord0 : (i < 24u ? kSymWord1 : kSymWord2);
+    const uint32_t s = static_cast<uint32_t>(word >> (5u * (i % 12u))) & 31u;
+    return s == 31u ? kInvalidSym : s;
+}
 
 // Leading-residue bucket of a k-mer code: the first min(k,4) residues read as a base-20 number.
 __device__ __forceinline__ uint32_t bucket_of(uint64_t code, uint32_t k, uint32_t lead) {

@@ -28,6 +28,7 @@ namespace pdp {
 
 constexpr uint32_t kMvThreads = 256;
 constexpr uint32_t kMvPer = kMvSortCap / kMvThreads;
+constexpr uint32_t kIxBatch = 8;  // index entries a thread loads per round in the histogram and placement
 constexpr uint32_t kDescPerLaunch = 8;
 
 struct DescChunk {
@@ -212,13 +213,25 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restri
         return;
     }
     uint8_t *sym = sym_all[w];
-    for (uint32_t p = lane; p < len; p += kWave) {
-        uint32_t x = kSym.v[B.res[o + p]];
-        if (x == kInvalidSym) {
-            raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
-            x = 0;
+    // rounds of 4 residues per lane, the 4 loads issued before any is used
+    for (uint32_t base = 0; base < len; base += 4 * kWave) {
+        uint32_t res[4];
+#pragma unroll
+        for (uint32_t it = 0; it < 4; ++it) {
+            const uint32_t p = base + lane + it * kWave;
+            res[it] = p < len ? B.res[o + p] : 'A';
         }
-        sym[p] = static_cast<uint8_t>(x);
+#pragma unroll
+        for (uint32_t it = 0; it < 4; ++it) {
+            const uint32_t p = base + lane + it * kWave;
+            if (p >= len) continue;
+            uint32_t x = sym_of(res[it]);
+            if (x == kInvalidSym) {
+                raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
+                x = 0;
+            }
+            sym[p] = static_cast<uint8_t>(x);
+        }
     }
     wave_lds_sync();
     uint32_t total;
@@ -249,13 +262,28 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_mid(const DevBuild *__restric
         const uint32_t nw = static_cast<uint32_t>(len - k + 1);  // checked by k_mv_wave
         const bool in_lds = nw <= kMvSortCap;
         const uint8_t *res = B.res;
-        for (uint64_t p = tid; p < len; p += kMvThreads) {
-            uint32_t x = kSym.v[res[o + p]];
-            if (x == kInvalidSym) {
-                raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
-                x = 0;
+        if (in_lds) {  // uniform: loads of a thread issued together, then mapped
+            constexpr uint32_t kIters = (kMvSortCap + PDP_K_MAX + kMvThreads - 1) / kMvThreads;
+            uint32_t rv[kIters];
+#pragma unroll
+            for (uint32_t it = 0; it < kIters; ++it) {
+                const uint32_t p = tid + it * kMvThreads;
+                rv[it] = p < len ? res[o + p] : 'A';
             }
-            if (in_lds) sym[p] = static_cast<uint8_t>(x);
+#pragma unroll
+            for (uint32_t it = 0; it < kIters; ++it) {
+                const uint32_t p = tid + it * kMvThreads;
+                if (p >= len) continue;
+                uint32_t x = sym_of(rv[it]);
+                if (x == kInvalidSym) {
+                    raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
+                    x = 0;
+                }
+                sym[p] = static_cast<uint8_t>(x);
+            }
+        } else {
+            for (uint64_t p = tid; p < len; p += kMvThreads)
+                if (sym_of(res[o + p]) == kInvalidSym) raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
         }
         if (!in_lds) {
             if (tid == 0) long_list[atomicAdd(&counters[0], 1u)] = item;
@@ -322,7 +350,7 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_long(const DevBuild *__restri
         for (uint32_t p = tid; p < nw; p += kMvThreads) {
             uint64_t c = 0;
             for (uint32_t j = 0; j < k; ++j) {
-                uint32_t s = kSym.v[B.res[o + p + j]];
+                uint32_t s = sym_of(B.res[o + p + j]);
                 c = (c << 5) | (s == kInvalidSym ? 0u : s);
             }
             w[p] = c;
@@ -429,8 +457,18 @@ __global__ __launch_bounds__(256) void k_ix_hist(const DevBuild *__restrict__ ta
     __syncthreads();
     uint32_t e0, e1, gbase;
     block_range(B, gptr, j, &e0, &e1, &gbase);
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-        atomicAdd(&h[bucket_of(B.mv_code[e], B.k, B.lead) >> B.hshift], 1u);
+    // rounds of kIxBatch entries per thread: the loads of a round are issued before its atomics
+    for (uint32_t base = e0; base < e1; base += kIxBatch * 256) {
+        uint64_t c[kIxBatch];
+#pragma unroll
+        for (uint32_t q = 0; q < kIxBatch; ++q) {
+            const uint32_t e = base + q * 256 + threadIdx.x;
+            c[q] = e < e1 ? B.mv_code[e] : 0ull;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kIxBatch; ++q)
+            if (base + q * 256 + threadIdx.x < e1) atomicAdd(&h[bucket_of(c[q], B.k, B.lead) >> B.hshift], 1u);
+    }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < B.nh; i += blockDim.x) hist[B.hist_base + i * B.nblk + j] = h[i];
 }
@@ -450,12 +488,24 @@ __global__ __launch_bounds__(256) void k_ix_place(const DevBuild *__restrict__ t
     __syncthreads();
     uint32_t e0, e1, gbase;
     block_range(B, gptr, j, &e0, &e1, &gbase);
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        const uint64_t c = B.mv_code[e];
-        const uint32_t pos = atomicAdd(&cur[bucket_of(c, B.k, B.lead) >> B.hshift], 1u);
-        // one 16-byte record per entry: a single scattered store instead of three
-        B.ix_tmp[pos] = make_uint4(static_cast<uint32_t>(c), static_cast<uint32_t>(c >> 32), ent_gene[gbase + e],
-                                   B.mv_cnt[e]);
+    for (uint32_t base = e0; base < e1; base += kIxBatch * 256) {
+        uint64_t c[kIxBatch];
+        uint32_t gn[kIxBatch], ct[kIxBatch];
+#pragma unroll
+        for (uint32_t q = 0; q < kIxBatch; ++q) {
+            const uint32_t e = base + q * 256 + threadIdx.x;
+            const bool v = e < e1;
+            c[q] = v ? B.mv_code[e] : 0ull;
+            gn[q] = v ? ent_gene[gbase + e] : 0u;
+            ct[q] = v ? B.mv_cnt[e] : 0u;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kIxBatch; ++q) {
+            if (base + q * 256 + threadIdx.x >= e1) continue;
+            const uint32_t pos = atomicAdd(&cur[bucket_of(c[q], B.k, B.lead) >> B.hshift], 1u);
+            // one 16-byte record per entry: a single scattered store instead of three
+            B.ix_tmp[pos] = make_uint4(static_cast<uint32_t>(c[q]), static_cast<uint32_t>(c[q] >> 32), gn[q], ct[q]);
+        }
     }
 }
 
@@ -527,11 +577,10 @@ __device__ __forceinline__ void sort_recs(uint4 *r, uint32_t n) {
     });
 }
 
-constexpr uint32_t kIxBinBuckets = 2048;  // buckets a bin may span for the counting path
 constexpr uint32_t kIxSmallBucket = 16;   // buckets up to this size are sorted by one thread
 constexpr uint32_t kIxBigList = 64;       // larger buckets a bin sorts one by one with the work-group
 constexpr uint32_t kIxPer = kIxBinLds / 256;
-static_assert(kIxBinBuckets == 256 * kIxPer, "each thread scans kIxPer bucket sizes");
+constexpr uint32_t kIxBinBuckets = 256 * kIxPer;  // buckets a bin may span for the counting path (kIxPer per thread)
 
 // One work-group per coarse bin: its entries ordered by (code, gene) and the bin's part of
 // the bucket directory.  Usual case (the bin fits LDS and spans at most kIxBinBuckets
@@ -566,10 +615,14 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
         uint4 r[kIxPer];
         uint32_t slot[kIxPer], bk[kIxPer];
 #pragma unroll
+        for (uint32_t q = 0; q < kIxPer; ++q) {  // every load issued before the first atomic
+            const uint32_t i = q * 256 + threadIdx.x;
+            r[q] = i < n ? B.ix_tmp[lo + i] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
         for (uint32_t q = 0; q < kIxPer; ++q) {
             const uint32_t i = q * 256 + threadIdx.x;
             if (i < n) {
-                r[q] = B.ix_tmp[lo + i];
                 bk[q] = bucket_of(rec_code(r[q]), B.k, B.lead) - b0;
                 slot[q] = atomicAdd(&s_bstart[bk[q]], 1u);
             }

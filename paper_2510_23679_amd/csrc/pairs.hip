@@ -276,9 +276,23 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
     const uint32_t bh = min(nb, bl + span);
     const uint32_t ntiles = T.tiles_n[0] + T.tiles_n[1];
     const bool packed = T.a.key_shift && T.b.key_shift;
-    for (uint32_t i = threadIdx.x; i <= bh - bl; i += blockDim.x) {
-        L.adir[i] = T.a.ix_dir[bl + i];
-        L.bdir[i] = T.b.ix_dir[bl + i];
+    {  // directory slices: all loads of a thread issued before the LDS stores
+        constexpr uint32_t kIters = (kJoinDirCap + 1 + kJoinThreads - 1) / kJoinThreads;
+        uint32_t da[kIters], db[kIters];
+#pragma unroll
+        for (uint32_t it = 0; it < kIters; ++it) {
+            const uint32_t i = threadIdx.x + it * kJoinThreads;
+            da[it] = i <= bh - bl ? T.a.ix_dir[bl + i] : 0u;
+            db[it] = i <= bh - bl ? T.b.ix_dir[bl + i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t it = 0; it < kIters; ++it) {
+            const uint32_t i = threadIdx.x + it * kJoinThreads;
+            if (i <= bh - bl) {
+                L.adir[i] = da[it];
+                L.bdir[i] = db[it];
+            }
+        }
     }
     for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x)
         L.tcount[t] = WRITE ? cells[T.cell_base + static_cast<uint64_t>(t) * T.n_chunks + c] : 0u;
@@ -296,9 +310,23 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
             uint16_t *abk = a1 - a0 <= kJoinLdsCapP ? reinterpret_cast<uint16_t *>(L.bgene) : nullptr;
             if (nbe <= kJoinLdsCapP) {
                 join_load_p<WRITE>(T.a, a0, a1, r);  // in flight while the target side is staged
-                for (uint32_t i = threadIdx.x; i < nbe; i += kJoinThreads) {
-                    bkey[i] = T.b.ix_key[b0 + i];
-                    if constexpr (WRITE) L.bcnt[i] = T.b.ix_cnt[b0 + i];
+                {
+                    constexpr uint32_t kIters = kJoinLdsCapP / kJoinThreads;
+                    uint32_t kv[kIters], cv[kIters];
+#pragma unroll
+                    for (uint32_t it = 0; it < kIters; ++it) {
+                        const uint32_t i = threadIdx.x + it * kJoinThreads;
+                        kv[it] = i < nbe ? T.b.ix_key[b0 + i] : 0u;
+                        cv[it] = WRITE && i < nbe ? T.b.ix_cnt[b0 + i] : 0u;
+                    }
+#pragma unroll
+                    for (uint32_t it = 0; it < kIters; ++it) {
+                        const uint32_t i = threadIdx.x + it * kJoinThreads;
+                        if (i < nbe) {
+                            bkey[i] = kv[it];
+                            if constexpr (WRITE) L.bcnt[i] = static_cast<uint16_t>(cv[it]);
+                        }
+                    }
                 }
                 if (abk)
                     for (uint32_t u = s0 - bl + threadIdx.x; u < s1 - bl; u += kJoinThreads)
@@ -715,27 +743,47 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
     }
     __syncthreads();
     const uint32_t ncols = C.n_genes;
-    for (uint32_t i = threadIdx.x; i < n; i += kTileThreads) {
-        const uint2 r = recs[rb + i];
-        // rows and columns are checked, so no record can address past the tile's rows or the
-        // column genome's window counts
-        if ((r.x >> 24) - g0 >= g1 - g0 || (r.x & 0xFFFFFFu) >= ncols) continue;
-        const uint32_t key = r.x + 1;  // columns stay below 2^24 - 1, so no wrap to 0
-        uint32_t h = (key * 2654435761u) >> (32 - kHashBits);
-        for (;;) {  // ends: at most kHashMax < kHashSlots keys are distinct
-            const uint32_t prev = atomicCAS(&hk[h], 0u, key);
-            if (prev == 0u || prev == key) break;
-            h = (h + 1) & (kHashSlots - 1);
+    constexpr uint32_t kRB = 4;  // records a thread loads per round, all before its inserts
+    for (uint32_t base = 0; base < n; base += kRB * kTileThreads) {
+        uint2 rr[kRB];
+#pragma unroll
+        for (uint32_t q = 0; q < kRB; ++q) {
+            const uint32_t i = base + q * kTileThreads + threadIdx.x;
+            rr[q] = i < n ? recs[rb + i] : make_uint2(0xFFFFFFFFu, 0u);
         }
-        atomicAdd(&hv[h], r.y);
+#pragma unroll
+        for (uint32_t q = 0; q < kRB; ++q) {
+            const uint2 r = rr[q];
+            if (base + q * kTileThreads + threadIdx.x >= n) continue;
+            // rows and columns are checked, so no record can address past the tile's rows or
+            // the column genome's window counts
+            if ((r.x >> 24) - g0 >= g1 - g0 || (r.x & 0xFFFFFFu) >= ncols) continue;
+            const uint32_t key = r.x + 1;  // columns stay below 2^24 - 1, so no wrap to 0
+            uint32_t h = (key * 2654435761u) >> (32 - kHashBits);
+            for (;;) {  // ends: at most kHashMax < kHashSlots keys are distinct
+                const uint32_t prev = atomicCAS(&hk[h], 0u, key);
+                if (prev == 0u || prev == key) break;
+                h = (h + 1) & (kHashSlots - 1);
+            }
+            atomicAdd(&hv[h], r.y);
+        }
     }
     __syncthreads();
-    for (uint32_t sl = threadIdx.x; sl < kHashSlots; sl += kTileThreads) {
+    constexpr uint32_t kSlotsPer = kHashSlots / kTileThreads;
+    uint32_t ncw[kSlotsPer];  // the column window counts of a thread's slots, gathered together
+#pragma unroll
+    for (uint32_t q = 0; q < kSlotsPer; ++q) {
+        const uint32_t key = hk[q * kTileThreads + threadIdx.x];
+        ncw[q] = key ? C.nwin[(key - 1) & 0xFFFFFFu] : 0u;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kSlotsPer; ++q) {
+        const uint32_t sl = q * kTileThreads + threadIdx.x;
         const uint32_t key = hk[sl];
         if (!key) continue;
-        const uint32_t rl = (key - 1) >> 24, c = (key - 1) & 0xFFFFFFu;
+        const uint32_t rl = (key - 1) >> 24;
         const uint32_t m = hv[sl];  // at most PDP_MAX_WINDOWS
-        const uint32_t nc = C.nwin[c];
+        const uint32_t nc = ncw[q];
         hv[sl] = m | (nc << 16);
         const uint32_t d = S.nr[rl] + nc - m;
         const unsigned long long want = (static_cast<unsigned long long>(m) << 32) | d;
