@@ -444,6 +444,18 @@ def main():
             runner.plan.timer_stop()
             breakdown[f"{name}_ms"] = round(ms / max(n, 1), 4)
         torch.cuda.synchronize()
+        # phase (c): gene families from the BBH of the last launch (not part of the step)
+        base = np.concatenate([[0], np.cumsum(genes)]).astype(np.int64)
+        node_a, node_b = [base[i] for i, _ in pairs], [base[j] for _, j in pairs]
+        runner.families(node_a, node_b, int(base[-1]))
+        fe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        fe[0].record(stream)
+        for _ in range(5):
+            labels = runner.families(node_a, node_b, int(base[-1]))
+        fe[1].record(stream)
+        torch.cuda.synchronize()
+        breakdown["families_ms"] = round(fe[0].elapsed_time(fe[1]) / 5, 4)
+        breakdown["families"] = int(torch.unique(labels).numel())
 
     avg_kernel_ms = kern_ms / max(kern_n, 1)
     alg = algorithmic_bytes(args.kernel, pairs, entries, bh_nnz, bbh_n, genes)

@@ -272,6 +272,22 @@ int32_t pdp_plan_launch(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, 
 #define PDP_KERNEL_BBH 4         /* BBH count and write passes together */
 #define PDP_KERNEL_ALL 5         /* the whole launch */
 
+/* Gene families from the BBH of a launched plan (phase (c): families are
+ * extracted from the network the bidirectional best hits form; the paper
+ * specifies no refinement, so a family here is a connected component of that
+ * network, over all genes of all genomes).  Node ids are global gene ids
+ * chosen by the caller: node_a[t] / node_b[t] (device, one per task in the
+ * caller's task order) are the ids of gene 0 of task t's genomes a and b, so
+ * gene g of a is node node_a[t] + g.  labels (device, n_nodes) receives, for
+ * every node, the smallest node id of its family (a node without BBH pairs is
+ * its own family).  bbh must hold the BBH output of the plan's last launch; ws
+ * is that launch's workspace (its task tables are read).  Enqueues kernels only.
+ * Device errors: PDP_E_INVAL (a pair names a node >= n_nodes; where = BBH row).
+ * Errors: PDP_E_INVAL, PDP_E_WORKSPACE, PDP_E_HIP. */
+int32_t pdp_plan_families(const pdp_plan *plan, const pdp_bbh_out *bbh, const uint32_t *node_a,
+                          const uint32_t *node_b, uint32_t n_nodes, uint32_t *labels, pdp_status *status,
+                          void *ws, uint64_t ws_bytes, void *stream);
+
 /* Measurement hook: from now on every pdp_plan_launch of this plan records a
  * pair of HIP events (owned by the plan) on its stream around the given
  * kernel, for at most max_launches launches.  pdp_plan_timer_read waits for

@@ -353,6 +353,7 @@ class PairRunner:
         self.bbh = BBHOut(info.bbh_rows, bbh_capacity if bbh_capacity is not None else info.bbh_rows + 1024) \
             if info.bbh_rows else None
         self.status = new_status()
+        self.fam_status = new_status()
         self.uploaded = False
 
     def _grow(self, where: int, needed: int) -> None:
@@ -392,6 +393,22 @@ class PairRunner:
 
     def results(self) -> PairResults:
         return PairResults(self.plan, self.bh.host(), self.bbh.host() if self.bbh is not None else None)
+
+    def families(self, node_a: Sequence[int], node_b: Sequence[int], n_nodes: int, stream=None) -> torch.Tensor:
+        """pdp_plan_families on the last launch's BBH: node_a[t] / node_b[t] are the global ids of gene 0 of
+        task t's genomes; returns the device labels (smallest node id of each node's family)."""
+        if self.bbh is None:
+            raise ValueError("no task of this plan asks for BBH")
+        dev = _device()
+        na = torch.tensor(np.asarray(node_a, dtype=np.int64), dtype=torch.int32, device=dev)
+        nb = torch.tensor(np.asarray(node_b, dtype=np.int64), dtype=torch.int32, device=dev)
+        labels = torch.empty(max(int(n_nodes), 1), dtype=torch.int32, device=dev)
+        self._fam_keep = (na, nb)  # read asynchronously by the kernels
+        bb = self.bbh.struct()
+        check(lib().pdp_plan_families(self.plan.h, C.byref(bb), na.data_ptr(), nb.data_ptr(), int(n_nodes),
+                                      labels.data_ptr(), self.fam_status.data_ptr(), self.ws.ptr, self.ws.nbytes,
+                                      _stream_handle(stream)), "pdp_plan_families")
+        return labels[: int(n_nodes)]
 
 
 def all_pairs_tasks(dicts: Sequence[Dictionary], pairs: Optional[Sequence[Tuple[int, int]]] = None,

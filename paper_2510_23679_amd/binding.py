@@ -123,6 +123,7 @@ SIGNATURES = {
     "pdp_plan_upload": (i32, [vp, vp, u64, vp]),
     "pdp_plan_launch": (i32, [vp, C.POINTER(pdp_bh_out), C.POINTER(pdp_bbh_out), vp, vp, u64, vp]),
     "pdp_plan_run": (i32, [vp, C.POINTER(pdp_bh_out), C.POINTER(pdp_bbh_out), vp, vp, u64, vp]),
+    "pdp_plan_families": (i32, [vp, C.POINTER(pdp_bbh_out), vp, vp, u32, vp, vp, vp, u64, vp]),
     "pdp_plan_timer_start": (i32, [vp, i32, u32]),
     "pdp_plan_timer_read": (i32, [vp, C.POINTER(C.c_double), C.POINTER(u32)]),
     "pdp_plan_timer_stop": (i32, [vp]),

@@ -479,6 +479,22 @@ int32_t pdp_plan_launch(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, 
     return ok();
 }
 
+int32_t pdp_plan_families(const pdp_plan *plan, const pdp_bbh_out *bbh, const uint32_t *node_a, const uint32_t *node_b,
+                          uint32_t n_nodes, uint32_t *labels, pdp_status *status, void *ws, uint64_t ws_bytes,
+                          void *stream) {
+    if (!plan || !bbh || !ws || !status || (n_nodes && (!labels || !node_a || !node_b)))
+        return fail(PDP_E_INVAL, "pdp_plan_families: null pointer");
+    if (bbh->n_rows != plan->shape.bbh_rows || !bbh->ptr || (bbh->capacity && (!bbh->a || !bbh->b)))
+        return fail(PDP_E_INVAL, "pdp_plan_families: BBH output has %u rows, plan has %u", bbh->n_rows,
+                    plan->shape.bbh_rows);
+    if (ws_bytes < plan->ws_bytes) return fail(PDP_E_WORKSPACE, "workspace %llu < %llu bytes", (unsigned long long)ws_bytes, (unsigned long long)plan->ws_bytes);
+    PairWs w = pair_ws_carve(ws, plan->shape);
+    hipError_t e = launch_families(plan->shape, w, bbh, node_a, node_b, n_nodes, labels, status,
+                                   static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "pdp_plan_families");
+    return ok();
+}
+
 int32_t pdp_plan_timer_start(pdp_plan *plan, int32_t kernel, uint32_t max_launches) {
     if (!plan || kernel < PDP_KERNEL_JOIN || kernel > PDP_KERNEL_ALL || max_launches == 0)
         return fail(PDP_E_INVAL, "pdp_plan_timer_start: bad argument");

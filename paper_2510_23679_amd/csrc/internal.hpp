@@ -166,6 +166,9 @@ struct KernelTimer {
 };
 hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp_bbh_out *bbh,
                         pdp_status *st, hipStream_t s, const KernelTimer *timer);
+// Families (connected components of the BBH network) into labels[n_nodes].
+hipError_t launch_families(const PlanShape &p, const PairWs &w, const pdp_bbh_out *bbh, const uint32_t *node_a,
+                           const uint32_t *node_b, uint32_t n_nodes, uint32_t *labels, pdp_status *st, hipStream_t s);
 hipError_t launch_bbh_standalone(const pdp_bh_out *ab, const pdp_bh_out *ba, pdp_bbh_out *out,
                                  pdp_status *st, uint32_t *partials, hipStream_t s);
 

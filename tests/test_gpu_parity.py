@@ -346,3 +346,56 @@ def test_build_many_mixed_k_and_empty_genomes():
     batch.check_status()
     for d, g, k in zip(batch.dicts, gens, ks):
         check_dictionary(d.host(), oracle.OracleGenome(g, k))
+
+
+# ------------------------------------------------------------ families (phase (c))
+
+def _families_run(genomes, k):
+    dicts = [pdp.Dictionary.build_from(g, k) for g in genomes]
+    pairs = [(i, j) for i in range(len(genomes)) for j in range(i + 1, len(genomes))]
+    runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts, pairs))
+    runner.run()
+    base = np.concatenate([[0], np.cumsum([g.n_genes for g in genomes])]).astype(np.int64)
+    node_a = [base[i] for i, _ in pairs]
+    node_b = [base[j] for _, j in pairs]
+    labels = runner.families(node_a, node_b, int(base[-1]))
+    assert pdp.read_status(runner.fam_status)[0] == 0
+    return runner, pairs, base, node_a, node_b, labels.cpu().numpy().view(np.uint32)
+
+
+def test_families_match_oracle():
+    from oracle.families import bbh_edges, components
+    ds = make_config(2, genomes=4, genes=300)
+    k = 5
+    say("families of 4 x 300 genes")
+    runner, pairs, base, node_a, node_b, got = _families_run(ds.genomes, k)
+    _, want = oracle.all_pairs(ds.genomes, k, pairs=pairs)
+    edges = bbh_edges([want[key][2] for key in want], node_a, node_b)
+    assert len(edges) > 100
+    assert np.array_equal(got, np.asarray(components(int(base[-1]), edges), dtype=np.uint32))
+
+
+def test_families_full_size_properties():
+    """The 10 x 3000 workload: every BBH pair joins one family, each label is its family's smallest
+    gene, and the partition equals the connected components of the GPU's own BBH pairs."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    ds = make_config(2)
+    k = pdp.k_rule(ds.total_residues())
+    say("families of the 10 x 3000 workload")
+    runner, pairs, base, node_a, node_b, got = _families_run(ds.genomes, k)
+    res = runner.results()
+    u, v = [], []
+    for t in range(len(pairs)):
+        a, b, _, _ = res.bbh_pairs(t)
+        u.append(node_a[t] + a.astype(np.int64))
+        v.append(node_b[t] + b.astype(np.int64))
+    u, v = np.concatenate(u), np.concatenate(v)
+    n = int(base[-1])
+    assert np.array_equal(got[u], got[v])
+    assert np.all(got <= np.arange(n)) and np.array_equal(got[got], got)
+    _, comp = connected_components(coo_matrix((np.ones(len(u)), (u, v)), shape=(n, n)), directed=False)
+    smallest = {}
+    for x in range(n):
+        smallest.setdefault(comp[x], x)
+    assert np.array_equal(got, np.array([smallest[c] for c in comp], dtype=np.uint32))

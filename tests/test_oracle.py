@@ -232,3 +232,35 @@ def test_planted_homologs_are_recovered():
     got = set(zip(p.a.tolist(), p.b.tolist()))
     planted = {(int(a), int(b)) for a, b in ds.meta["planted"]}
     assert len(planted & got) >= 140
+
+
+# ------------------------------------------------------------ families (phase (c))
+
+def test_families_hand_cases():
+    from oracle.families import components
+    assert components(5, []) == [0, 1, 2, 3, 4]  # no BBH: every gene its own family
+    assert components(4, [(2, 3), (1, 2)]) == [0, 1, 1, 1]  # a path: one family labelled by its smallest gene
+    assert components(6, [(5, 0), (4, 3), (3, 5)]) == [0, 1, 2, 0, 0, 0]  # edge order and direction do not matter
+    assert components(3, [(1, 1), (2, 1), (1, 2)]) == [0, 1, 1]  # self-loops and repeated edges change nothing
+
+
+def test_families_match_library_components():
+    """The union-find oracle against scipy's connected components on random graphs (labels compared as
+    partitions: same component iff same label; the label is the component's smallest node)."""
+    import numpy as np
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    from oracle.families import components
+    rng = np.random.default_rng(3)
+    for trial in range(20):
+        n = int(rng.integers(1, 300))
+        m = int(rng.integers(0, 2 * n))
+        u = rng.integers(0, n, m)
+        v = rng.integers(0, n, m)
+        lab = np.asarray(components(n, zip(u.tolist(), v.tolist())))
+        _, comp = connected_components(coo_matrix((np.ones(m), (u, v)), shape=(n, n)), directed=False)
+        smallest = {}
+        for x in range(n):
+            smallest.setdefault(comp[x], x)
+        assert np.array_equal(lab, np.array([smallest[c] for c in comp])), trial
