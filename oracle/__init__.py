@@ -56,6 +56,8 @@ def _load():
         "orc_compare_j": (C.c_int, [u64, u64, u64, u64]),
         "orc_pair_terms": (None, [vp, u32, vp, u32, P(u64), P(u64)]),
         "orc_bh_rows": (vp, [vp, vp, vp, u32, C.c_int]),
+        "orc_bh_rows_f": (vp, [vp, vp, vp, u32, C.c_int, u64, u64, u64, u64]),
+        "orc_directional_terms": (None, [P(u64), P(u32), u64, P(u64), P(u32), u64, P(u64), P(u64)]),
         "orc_bh_free": (None, [vp]),
         "orc_bh_nrows": (u32, [vp]),
         "orc_bh_ptr": (P(u64), [vp]),
@@ -196,16 +198,21 @@ class BH:
             self._h = None
 
 
-def bh(q: OracleGenome, t: OracleGenome, rows: Optional[Sequence[int]] = None, threads: Optional[int] = None) -> BH:
-    """Eq. best_hit for the given rows of q (all rows when None) against genome t."""
+def bh(q: OracleGenome, t: OracleGenome, rows: Optional[Sequence[int]] = None, threads: Optional[int] = None,
+       theta=None, tau=None) -> BH:
+    """Eq. best_hit for the given rows of q (all rows when None) against genome t.  theta / tau:
+    (numerator, denominator) of the candidate filters of Eqs. length_threshold and
+    directional_jaccard (None: off); a filtered pair is no best-hit candidate."""
     lib = _load()
     th = default_threads() if threads is None else int(threads)
+    tn, td = theta if theta is not None else (0, 0)
+    un, ud = tau if tau is not None else (0, 0)
     if rows is None:
         rws = np.arange(q.n, dtype=np.uint32)
-        h = lib.orc_bh_rows(q._h, t._h, None, 0, th)
+        h = lib.orc_bh_rows_f(q._h, t._h, None, 0, th, tn, td, un, ud)
     else:
         rws = np.ascontiguousarray(rows, dtype=np.uint32)
-        h = lib.orc_bh_rows(q._h, t._h, rws.ctypes.data, int(rws.shape[0]), th)
+        h = lib.orc_bh_rows_f(q._h, t._h, rws.ctypes.data, int(rws.shape[0]), th, tn, td, un, ud)
     nr = int(lib.orc_bh_nrows(h))
     ptr = _arr(lib.orc_bh_ptr(h), nr + 1, np.uint64)
     nnz = int(ptr[-1])
@@ -240,14 +247,14 @@ def bbh_alg3(gi: OracleGenome, gj: OracleGenome, ab: BH, ba: BH) -> Pairs:
     return _pairs(_load().orc_bbh_alg3(gi._h, gj._h, ab._h, ba._h))
 
 
-def all_pairs(genomes, k: int, threads: Optional[int] = None, pairs=None):
+def all_pairs(genomes, k: int, threads: Optional[int] = None, pairs=None, theta=None, tau=None):
     """BH both ways and BBH for every unordered genome pair i<j (or the given pairs)."""
     og = [OracleGenome(g, k) for g in genomes]
     if pairs is None:
         pairs = [(i, j) for i in range(len(og)) for j in range(i + 1, len(og))]
     out = {}
     for i, j in pairs:
-        ab = bh(og[i], og[j], threads=threads)
-        ba = bh(og[j], og[i], threads=threads)
+        ab = bh(og[i], og[j], threads=threads, theta=theta, tau=tau)
+        ba = bh(og[j], og[i], threads=threads, theta=theta, tau=tau)
         out[(i, j)] = (ab, ba, bbh(ab, ba))
     return og, out

@@ -34,15 +34,35 @@ def jaccard(a: str, b: str, k: int) -> Fraction:
     return Fraction(num, den) if den else Fraction(0)
 
 
-def best_hits(a: str, target: Sequence[str], k: int) -> List[int]:
-    """Eq. best_hit: indices of target genes at the row's maximum J, if that maximum is above zero."""
-    if not target:
+def directional(s: str, t: str, k: int) -> Fraction:
+    """Eq. directional_jaccard: occurrences in s of the k-mers s shares with t, over s's windows
+    (0 for a string without windows)."""
+    ms, mt = multiplicities(s, k), multiplicities(t, k)
+    n = max(0, len(s) - k + 1)
+    return Fraction(sum(ms[w] for w in set(ms) & set(mt)), n) if n else Fraction(0)
+
+
+def candidate(a: str, b: str, k: int, theta=None, tau=None) -> bool:
+    """Eq. length_threshold (|a| >= theta |b| and |b| >= theta |a|) and the directional filter
+    (both directional similarities >= tau); a None threshold is off."""
+    if theta is not None and (len(a) < theta * len(b) or len(b) < theta * len(a)):
+        return False
+    if tau is not None and (directional(a, b, k) < tau or directional(b, a, k) < tau):
+        return False
+    return True
+
+
+def best_hits(a: str, target: Sequence[str], k: int, theta=None, tau=None) -> List[int]:
+    """Eq. best_hit over the candidates: indices of target genes at the maximum J among the pairs
+    that pass the filters, if that maximum is above zero."""
+    cand = [i for i, b in enumerate(target) if candidate(a, b, k, theta, tau)]
+    if not cand:
         return []
-    js = [jaccard(a, b, k) for b in target]
-    top = max(js)
+    js = {i: jaccard(a, target[i], k) for i in cand}
+    top = max(js.values())
     if top <= 0:
         return []
-    return [i for i, j in enumerate(js) if j == top]
+    return [i for i in cand if js[i] == top]
 
 
 def bbh(gi: Sequence[str], gj: Sequence[str], k: int) -> List[Tuple[int, int]]:
@@ -52,9 +72,10 @@ def bbh(gi: Sequence[str], gj: Sequence[str], k: int) -> List[Tuple[int, int]]:
     return sorted((l, m) for l in bh_ij for m in bh_ij[l] if l in bh_ji[m])
 
 
-def all_best_hits(gi: Sequence[str], gj: Sequence[str], k: int) -> Dict[int, List[Tuple[int, int, int]]]:
+def all_best_hits(gi: Sequence[str], gj: Sequence[str], k: int, theta=None,
+                  tau=None) -> Dict[int, List[Tuple[int, int, int]]]:
     """Row -> [(column, num, den)] for every row of gi, columns ascending."""
     out = {}
     for l, a in enumerate(gi):
-        out[l] = [(m, *terms(a, gj[m], k)) for m in best_hits(a, gj, k)]
+        out[l] = [(m, *terms(a, gj[m], k)) for m in best_hits(a, gj, k, theta, tau)]
     return out

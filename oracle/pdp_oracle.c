@@ -121,11 +121,12 @@ typedef struct {
     uint64_t *ids;   /* ptr[n] */
     uint32_t *cnt;   /* ptr[n] */
     uint64_t *nwin;  /* n: windows of each gene */
+    uint64_t *len;   /* n: residues of each gene (Eq. length_threshold compares these) */
 } orc_genome;
 
 void orc_genome_free(orc_genome *g) {
     if (!g) return;
-    free(g->ptr); free(g->ids); free(g->cnt); free(g->nwin); free(g);
+    free(g->ptr); free(g->ids); free(g->cnt); free(g->nwin); free(g->len); free(g);
 }
 
 /* Builds the multiplicity vector of every gene (genes are residues[off[i]..off[i+1])).
@@ -135,8 +136,10 @@ orc_genome *orc_genome_new(const unsigned char *residues, const uint64_t *off, u
     g->n = n; g->k = k;
     g->ptr = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
     g->nwin = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+    g->len = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
     uint64_t cap = 0;
     for (uint32_t i = 0; i < n; ++i) {
+        g->len[i] = off[i + 1] - off[i];
         g->nwin[i] = (uint64_t)orc_n_windows((int64_t)(off[i + 1] - off[i]), k);
         cap += g->nwin[i];
     }
@@ -208,32 +211,83 @@ void orc_pair_terms(const orc_genome *q, uint32_t a, const orc_genome *t, uint32
                       t->ids + t->ptr[b], t->cnt + t->ptr[b], t->ptr[b + 1] - t->ptr[b], smin, smax);
 }
 
+/* ------------------------------------------- Eqs. length_threshold, directional_jaccard */
+
+/* Numerators of the two directional similarities of Eq. directional_jaccard:
+ * *occ_a = sum over k-mers present in both genes of the k-mer's occurrences in a,
+ * *occ_b = the same with b's occurrences.  p(a -> b) = occ_a / (|a| - k + 1). */
+void orc_directional_terms(const uint64_t *ia, const uint32_t *ca, uint64_t na,
+                           const uint64_t *ib, const uint32_t *cb, uint64_t nb,
+                           uint64_t *occ_a, uint64_t *occ_b) {
+    uint64_t i = 0, j = 0, sa = 0, sb = 0;
+    while (i < na && j < nb) {
+        if (ia[i] < ib[j]) ++i;
+        else if (ib[j] < ia[i]) ++j;
+        else { sa += ca[i]; sb += cb[j]; ++i; ++j; }
+    }
+    *occ_a = sa;
+    *occ_b = sb;
+}
+
+/* Candidate filters (theta = theta_n / theta_d, tau = tau_n / tau_d; a zero
+ * denominator switches that filter off).  Eq. length_threshold: both lengths at
+ * least theta times the other.  Eq. directional_jaccard: both directional
+ * similarities at least tau (p = 0 for a gene without windows). */
+static int orc_candidate(const orc_genome *q, uint32_t a, const orc_genome *t, uint32_t b,
+                         uint64_t theta_n, uint64_t theta_d, uint64_t tau_n, uint64_t tau_d) {
+    if (theta_d) {
+        const unsigned __int128 la = q->len[a], lb = t->len[b];
+        if (la * theta_d < (unsigned __int128)theta_n * lb || lb * theta_d < (unsigned __int128)theta_n * la) return 0;
+    }
+    if (tau_d) {
+        uint64_t oa, ob;
+        orc_directional_terms(q->ids + q->ptr[a], q->cnt + q->ptr[a], q->ptr[a + 1] - q->ptr[a],
+                              t->ids + t->ptr[b], t->cnt + t->ptr[b], t->ptr[b + 1] - t->ptr[b], &oa, &ob);
+        const uint64_t wa = q->nwin[a], wb = t->nwin[b];
+        /* p >= tau  <=>  occ * tau_d >= tau_n * windows (both sides non-negative) */
+        if (wa == 0 ? tau_n > 0 : (unsigned __int128)oa * tau_d < (unsigned __int128)tau_n * wa) return 0;
+        if (wb == 0 ? tau_n > 0 : (unsigned __int128)ob * tau_d < (unsigned __int128)tau_n * wb) return 0;
+    }
+    return 1;
+}
+
 /* ------------------------------------------------------------ Eq. best_hit */
 
 /* BH(a, T): the genes b of T whose J(a,b) equals the maximum of row a,
  * provided that maximum is above zero; ascending b.  col/num/den must hold
  * t->n entries.  Returns the number of best hits. */
-int64_t orc_bh_row(const orc_genome *q, uint32_t a, const orc_genome *t, uint32_t *col, uint64_t *num, uint64_t *den) {
+int64_t orc_bh_row_f(const orc_genome *q, uint32_t a, const orc_genome *t, uint32_t *col, uint64_t *num, uint64_t *den,
+                     uint64_t theta_n, uint64_t theta_d, uint64_t tau_n, uint64_t tau_d) {
     uint32_t n = t->n;
     if (n == 0) return 0;
     uint64_t *m = (uint64_t *)malloc(sizeof(uint64_t) * n);
     uint64_t *d = (uint64_t *)malloc(sizeof(uint64_t) * n);
+    char *cand = (char *)malloc(n);
+    int have = 0;
     uint32_t best = 0;
     for (uint32_t b = 0; b < n; ++b) {
         orc_pair_terms(q, a, t, b, &m[b], &d[b]);
-        if (orc_cmp_j(m[b], d[b], m[best], d[best]) > 0) best = b;
+        cand[b] = (char)orc_candidate(q, a, t, b, theta_n, theta_d, tau_n, tau_d);
+        if (!cand[b]) continue;  /* a filtered pair is no best-hit candidate */
+        if (!have || orc_cmp_j(m[b], d[b], m[best], d[best]) > 0) best = b;
+        have = 1;
     }
     int64_t c = 0;
-    if (orc_cmp_j(m[best], d[best], 0, 1) > 0) {
+    if (have && orc_cmp_j(m[best], d[best], 0, 1) > 0) {
         for (uint32_t b = 0; b < n; ++b) {
-            if (orc_cmp_j(m[b], d[b], m[best], d[best]) == 0) {
+            if (cand[b] && orc_cmp_j(m[b], d[b], m[best], d[best]) == 0) {
                 col[c] = b; num[c] = m[b]; den[c] = d[b]; ++c;
             }
         }
     }
     free(m);
     free(d);
+    free(cand);
     return c;
+}
+
+int64_t orc_bh_row(const orc_genome *q, uint32_t a, const orc_genome *t, uint32_t *col, uint64_t *num, uint64_t *den) {
+    return orc_bh_row_f(q, a, t, col, num, den, 0, 0, 0, 0);
 }
 
 /* Best hits of many rows of q against t, rows handed to a pool of threads
@@ -247,6 +301,7 @@ typedef struct {
 
 typedef struct {
     const orc_genome *q, *t;
+    uint64_t theta_n, theta_d, tau_n, tau_d;
     const uint32_t *rows;
     uint32_t nrows;
     uint32_t next;          /* shared row counter */
@@ -265,7 +320,7 @@ static void *orc_bh_worker(void *arg) {
         uint32_t r = __atomic_fetch_add(&J->next, 1u, __ATOMIC_RELAXED);
         if (r >= J->nrows) break;
         uint32_t a = J->rows ? J->rows[r] : r;
-        int64_t c = orc_bh_row(J->q, a, J->t, col, num, den);
+        int64_t c = orc_bh_row_f(J->q, a, J->t, col, num, den, J->theta_n, J->theta_d, J->tau_n, J->tau_d);
         J->rcount[r] = c;
         J->rc[r] = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(c + 1));
         J->rn[r] = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(c + 1));
@@ -278,13 +333,15 @@ static void *orc_bh_worker(void *arg) {
     return NULL;
 }
 
-/* rows == NULL means every row of q, in order. */
-orc_bh *orc_bh_rows(const orc_genome *q, const orc_genome *t, const uint32_t *rows, uint32_t nrows, int nthreads) {
+/* rows == NULL means every row of q, in order.  The filters as in orc_candidate. */
+orc_bh *orc_bh_rows_f(const orc_genome *q, const orc_genome *t, const uint32_t *rows, uint32_t nrows, int nthreads,
+                      uint64_t theta_n, uint64_t theta_d, uint64_t tau_n, uint64_t tau_d) {
     if (!rows) nrows = q->n;
     if (nthreads < 1) nthreads = 1;
     orc_bh_job J;
     memset(&J, 0, sizeof(J));
     J.q = q; J.t = t; J.rows = rows; J.nrows = nrows; J.next = 0;
+    J.theta_n = theta_n; J.theta_d = theta_d; J.tau_n = tau_n; J.tau_d = tau_d;
     J.rc = (uint32_t **)calloc((size_t)nrows + 1, sizeof(void *));
     J.rn = (uint64_t **)calloc((size_t)nrows + 1, sizeof(void *));
     J.rd = (uint64_t **)calloc((size_t)nrows + 1, sizeof(void *));
@@ -310,6 +367,10 @@ orc_bh *orc_bh_rows(const orc_genome *q, const orc_genome *t, const uint32_t *ro
     }
     free(J.rc); free(J.rn); free(J.rd); free(J.rcount);
     return o;
+}
+
+orc_bh *orc_bh_rows(const orc_genome *q, const orc_genome *t, const uint32_t *rows, uint32_t nrows, int nthreads) {
+    return orc_bh_rows_f(q, t, rows, nrows, nthreads, 0, 0, 0, 0);
 }
 
 void orc_bh_free(orc_bh *o) {

@@ -264,3 +264,75 @@ def test_families_match_library_components():
         for x in range(n):
             smallest.setdefault(comp[x], x)
         assert np.array_equal(lab, np.array([smallest[c] for c in comp])), trial
+
+
+# ------------------------------------------------ candidate filters (theta, tau)
+
+def _rows(bh_, n):
+    return [[(int(c), int(x), int(y)) for c, x, y in zip(*bh_.row(r))] for r in range(n)]
+
+
+def test_filter_fixtures(golden):
+    from synth import genome_from_strings
+    for e in golden["filters"]:
+        th = tuple(e["theta"]) if e["theta"] else None
+        ta = tuple(e["tau"]) if e["tau"] else None
+        gi = oracle.OracleGenome(genome_from_strings(e["gi"]), e["k"])
+        gj = oracle.OracleGenome(genome_from_strings(e["gj"]), e["k"])
+        ab = oracle.bh(gi, gj, threads=1, theta=th, tau=ta)
+        ba = oracle.bh(gj, gi, threads=1, theta=th, tau=ta)
+        assert _rows(ab, len(e["gi"])) == [[tuple(x) for x in row] for row in e["bh_ij"]], e["id"]
+        assert _rows(ba, len(e["gj"])) == [[tuple(x) for x in row] for row in e["bh_ji"]], e["id"]
+        p = oracle.bbh(ab, ba)
+        assert [[int(x), int(y)] for x, y in zip(p.a, p.b)] == e["bbh"], e["id"]
+        if "bh_ij_unfiltered" in e:
+            assert _rows(oracle.bh(gi, gj, threads=1), len(e["gi"])) == \
+                [[tuple(x) for x in row] for row in e["bh_ij_unfiltered"]], e["id"]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_filters_match_brute(seed):
+    from fractions import Fraction
+
+    from synth import genome_from_strings
+    rng = random.Random(100 + seed)
+    alpha = "ACDEFGHIKLMNPQRSTVWY"[: rng.choice([2, 3, 4, 20])]
+    k = rng.choice([1, 2, 3])
+    gi = ["".join(rng.choice(alpha) for _ in range(rng.randint(0, 30))) for _ in range(rng.randint(1, 7))]
+    gj = ["".join(rng.choice(alpha) for _ in range(rng.randint(0, 30))) for _ in range(rng.randint(1, 7))]
+    gi += gi[:1]  # duplicates give ties
+    th = rng.choice([None, (1, 2), (3, 4), (9, 10), (0, 1)])
+    ta = rng.choice([None, (1, k), (1, 2), (2, 5), (0, 1)])
+    oi = oracle.OracleGenome(genome_from_strings(gi), k)
+    oj = oracle.OracleGenome(genome_from_strings(gj), k)
+    ab = oracle.bh(oi, oj, threads=2, theta=th, tau=ta)
+    want = brute.all_best_hits(gi, gj, k, Fraction(*th) if th else None, Fraction(*ta) if ta else None)
+    assert _rows(ab, len(gi)) == [want[r] for r in range(len(gi))]
+
+
+def test_zero_thresholds_filter_nothing():
+    ds = make_config(2, genomes=2, genes=120)
+    a, b = (oracle.OracleGenome(g, 4) for g in ds.genomes)
+    plain = oracle.bh(a, b, threads=2)
+    for th, ta in (((0, 1), None), (None, (0, 1)), ((0, 1), (0, 1))):
+        f = oracle.bh(a, b, threads=2, theta=th, tau=ta)
+        assert np.array_equal(f.ptr, plain.ptr) and np.array_equal(f.col, plain.col)
+
+
+def test_filters_only_remove_candidates():
+    """A row's filtered maximum never exceeds its unfiltered one, and a row whose unfiltered best hits
+    all pass the filters keeps exactly them."""
+    from fractions import Fraction
+    ds = make_config(2, genomes=2, genes=150)
+    a, b = (oracle.OracleGenome(g, 4) for g in ds.genomes)
+    plain = oracle.bh(a, b, threads=2)
+    filt = oracle.bh(a, b, threads=2, theta=(4, 5), tau=(1, 4))
+    strs_a = [ds.genomes[0].gene(i).decode() for i in range(ds.genomes[0].n_genes)]
+    strs_b = [ds.genomes[1].gene(i).decode() for i in range(ds.genomes[1].n_genes)]
+    for r in range(a.n):
+        pc, pn, pd = plain.row(r)
+        fc, fn, fd = filt.row(r)
+        if len(fc):
+            assert Fraction(int(fn[0]), int(fd[0])) <= Fraction(int(pn[0]), int(pd[0]))
+        if len(pc) and all(brute.candidate(strs_a[r], strs_b[int(c)], 4, Fraction(4, 5), Fraction(1, 4)) for c in pc):
+            assert list(fc) == list(pc)

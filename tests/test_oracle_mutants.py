@@ -4,6 +4,7 @@ at least one pin (hand values, brute force, invariants) now fails."""
 import ctypes as C
 import os
 import random
+from fractions import Fraction
 import shutil
 import subprocess
 import tempfile
@@ -22,12 +23,18 @@ MUTANTS = [
     ("min and max swapped", "mn += ca[i] < cb[j] ? ca[i] : cb[j];", "mn += ca[i] > cb[j] ? ca[i] : cb[j];"),
     ("union term dropped", "mx += ca[i];               /* only in a */", "/* dropped */"),
     ("set instead of multiset", "cnt[d - 1] += 1;", "cnt[d - 1] += 0;"),
-    ("first maximum only", "if (orc_cmp_j(m[b], d[b], m[best], d[best]) == 0) {",
-     "if (b == best) {"),
-    ("zero maximum kept", "if (orc_cmp_j(m[best], d[best], 0, 1) > 0) {", "if (1) {"),
+    ("first maximum only", "if (cand[b] && orc_cmp_j(m[b], d[b], m[best], d[best]) == 0) {",
+     "if (cand[b] && b == best) {"),
+    ("zero maximum kept", "if (have && orc_cmp_j(m[best], d[best], 0, 1) > 0) {", "if (have) {"),
     ("BBH direction typo", "if (b < ba->nrows && orc_row_has(ba, b, a)) {", "if (b < ba->nrows && orc_row_has(ab, a, b)) {"),
-    ("strict comparison flipped", "if (orc_cmp_j(m[b], d[b], m[best], d[best]) > 0) best = b;",
-     "if (orc_cmp_j(m[b], d[b], m[best], d[best]) < 0) best = b;"),
+    ("strict comparison flipped", "if (!have || orc_cmp_j(m[b], d[b], m[best], d[best]) > 0) best = b;",
+     "if (!have || orc_cmp_j(m[b], d[b], m[best], d[best]) < 0) best = b;"),
+    ("length filter one-sided",
+     "if (la * theta_d < (unsigned __int128)theta_n * lb || lb * theta_d < (unsigned __int128)theta_n * la) return 0;",
+     "if (la * theta_d < (unsigned __int128)theta_n * lb) return 0;"),
+    ("directional filter over the other gene's windows",
+     "if (wa == 0 ? tau_n > 0 : (unsigned __int128)oa * tau_d < (unsigned __int128)tau_n * wa) return 0;",
+     "if (wa == 0 ? tau_n > 0 : (unsigned __int128)oa * tau_d < (unsigned __int128)tau_n * wb) return 0;"),
 ]
 
 
@@ -77,8 +84,21 @@ def _pins_hold(libpath, golden) -> bool:
             p = oracle.bbh(ab, ba)
             if [[int(x), int(y)] for x, y in zip(p.a, p.b)] != e["bbh"]:
                 return False
+        for e in golden["filters"]:
+            th = tuple(e["theta"]) if e["theta"] else None
+            ta = tuple(e["tau"]) if e["tau"] else None
+            gi, gj = og(e["gi"], e["k"]), og(e["gj"], e["k"])
+            ab = oracle.bh(gi, gj, threads=1, theta=th, tau=ta)
+            ba = oracle.bh(gj, gi, threads=1, theta=th, tau=ta)
+            rows = [[(int(c), int(n), int(d)) for c, n, d in zip(*ab.row(r))] for r in range(len(e["gi"]))]
+            rows_ji = [[(int(c), int(n), int(d)) for c, n, d in zip(*ba.row(r))] for r in range(len(e["gj"]))]
+            if rows != [[tuple(x) for x in row] for row in e["bh_ij"]] or \
+                    rows_ji != [[tuple(x) for x in row] for row in e["bh_ji"]]:
+                return False
         rng = random.Random(5)
-        for _ in range(15):
+        for trial in range(15):
+            th = [None, (1, 2), (3, 4)][trial % 3]
+            ta = [None, (1, 2), (1, 3), (2, 5)][trial % 4]
             alpha = "ACDEFGHIKLMNPQRSTVWY"[: rng.choice([2, 3, 20])]
             k = rng.choice([1, 2, 3])
             gi = ["".join(rng.choice(alpha) for _ in range(rng.randint(0, 30))) for _ in range(rng.randint(1, 6))]
@@ -86,6 +106,11 @@ def _pins_hold(libpath, golden) -> bool:
             oi, oj = og(gi, k), og(gj, k)
             ab, ba = oracle.bh(oi, oj, threads=1), oracle.bh(oj, oi, threads=1)
             want = brute.all_best_hits(gi, gj, k)
+            fab = oracle.bh(oi, oj, threads=1, theta=th, tau=ta)
+            fwant = brute.all_best_hits(gi, gj, k, Fraction(*th) if th else None, Fraction(*ta) if ta else None)
+            if [[(int(c), int(n), int(d)) for c, n, d in zip(*fab.row(r))] for r in range(len(gi))] != \
+                    [fwant[r] for r in range(len(gi))]:
+                return False
             got = [[(int(c), int(n), int(d)) for c, n, d in zip(*ab.row(r))] for r in range(len(gi))]
             if got != [want[r] for r in range(len(gi))]:
                 return False
