@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--tune", action="store_true", help="pick tile shapes and join splits with the autotuner first")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                    help="measured HBM traffic per kernel (from rocprofv3 counters), used when its source hash matches")
+    p.add_argument("--theta", default=None, help="length filter as NUM/DEN (Eq. length_threshold); off by default")
+    p.add_argument("--tau", default=None, help="directional filter as NUM/DEN (Eq. directional_jaccard); off by default")
     p.add_argument("--workload", choices=("allpairs", "batched", "serving"), default="allpairs",
                    help="allpairs: the 10 x 3000 metric (default); batched: independent instances in waves, one "
                         "graph-captured persistent launch per wave, against one plan per genome pair; serving: "
@@ -381,9 +383,13 @@ def main():
     batch.build()
     tasks = pdp.all_pairs_tasks(dicts)
     tuned = None
-    prm = pdp.params()
+
+    def frac(x):
+        return tuple(int(v) for v in x.split("/")) if x else None
+
+    prm = pdp.params(theta=frac(args.theta), tau=frac(args.tau))
     if args.tune:
-        best, tres = pdp.autotune(tasks, reps=3)
+        best, tres = pdp.autotune(tasks, reps=3, base=prm)
         prm = best
         tuned = {"tile_rows": int(best.tile_rows), "lds_budget": int(best.lds_budget), "join_entries": int(best.join_entries),
                  "persistent": bool(best.flags & B.PDP_PARAM_PERSISTENT), "best_ms": round(tres.best_ms, 4),
@@ -488,7 +494,8 @@ def main():
         "config": {"workload": "all-pairs BH+BBH: 10 genomes x 3000 genes (family model), 45 genome pairs, "
                                "dictionary build included",
                    "genomes": len(genes), "genes_per_genome": genes[0], "k": k, "genome_pairs": len(pairs),
-                   "gene_pairs": gene_pairs, "kmer_entries": int(sum(entries)), "best_hits": bh_nnz, "bbh_pairs": bbh_n},
+                   "gene_pairs": gene_pairs, "kmer_entries": int(sum(entries)), "best_hits": bh_nnz, "bbh_pairs": bbh_n,
+                   "filters": {"theta": args.theta, "tau": args.tau}},
         "roofline": roofline,
         "params": tuned if tuned is not None else "defaults",
         "breakdown": breakdown,

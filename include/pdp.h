@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define PDP_ABI_VERSION 2u
+#define PDP_ABI_VERSION 3u
 
 /* Largest k: 5-bit residue codes of k <= 12 residues fit in 60 bits. */
 #define PDP_K_MAX 12u
@@ -204,6 +204,15 @@ typedef struct pdp_params {
                                 32 KiB: 32 KiB, the sorted path's 4096 records); more lets a tile whose
                                 records overflow the sort sum more rows per dense pass */
     uint32_t flags;          /* PDP_PARAM_* */
+    /* Candidate filters; a zero denominator switches a filter off (the default).
+     * Eq. length_threshold: genes a, b are compared only if |a| >= theta |b| and
+     * |b| >= theta |a| (theta = theta_num / theta_den <= 1; lengths in residues).
+     * Eq. directional_jaccard: only if p(a -> b) >= tau and p(b -> a) >= tau,
+     * where p(a -> b) = occurrences in a of the k-mers a shares with b, over
+     * |a| - k + 1.  A pair that fails is no best-hit candidate; a row without
+     * candidates has no best hit.  Both tests are exact integer comparisons. */
+    uint32_t theta_num, theta_den;
+    uint32_t tau_num, tau_den;
 } pdp_params;
 /* The join and the first tile pass run as persistent kernels: a grid sized to
  * the device pulls work items from a counter (largest tasks first) instead of

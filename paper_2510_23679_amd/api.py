@@ -239,9 +239,18 @@ class BBHOut:
 
 
 def params(inc_capacity: int = 0, tile_rows: int = 0, join_entries: int = 0, lds_budget: int = 0,
-           persistent: bool = False) -> B.pdp_params:
+           persistent: bool = False, theta=None, tau=None) -> B.pdp_params:
+    """Tuning knobs and the candidate filters: theta / tau as (numerator, denominator) or None (off)."""
+    tn, td = theta if theta is not None else (0, 0)
+    un, ud = tau if tau is not None else (0, 0)
     return B.pdp_params(int(inc_capacity), int(tile_rows), int(join_entries), int(lds_budget),
-                        B.PDP_PARAM_PERSISTENT if persistent else 0)
+                        B.PDP_PARAM_PERSISTENT if persistent else 0, int(tn), int(td), int(un), int(ud))
+
+
+def _with_capacity(prm: B.pdp_params, capacity: int) -> B.pdp_params:
+    """The same parameters with another record capacity."""
+    return B.pdp_params(int(capacity), prm.tile_rows, prm.join_entries, prm.lds_budget, prm.flags, prm.theta_num,
+                        prm.theta_den, prm.tau_num, prm.tau_den)
 
 
 class Plan:
@@ -358,8 +367,7 @@ class PairRunner:
 
     def _grow(self, where: int, needed: int) -> None:
         if where == 0:
-            self.prm = params(int(needed * 1.25) + 1024, self.prm.tile_rows, self.prm.join_entries, self.prm.lds_budget,
-                              bool(self.prm.flags & B.PDP_PARAM_PERSISTENT))
+            self.prm = _with_capacity(self.prm, int(needed * 1.25) + 1024)
             self.plan = Plan(self.tasks, self.prm)
             self.ws = Workspace(self.plan.info.ws_bytes)
             self.uploaded = False
@@ -433,8 +441,7 @@ def bh(q: Dictionary, t: Dictionary, prm: Optional[B.pdp_params] = None, capacit
                            _stream_handle(stream)), "pdp_bh")
         code, needed, where = read_status(st)
         if code == B.PDP_E_CAPACITY and where == 0:
-            prm = params(int(needed * 1.25) + 1024, prm.tile_rows, prm.join_entries, prm.lds_budget,
-                         bool(prm.flags & B.PDP_PARAM_PERSISTENT))
+            prm = _with_capacity(prm, int(needed * 1.25) + 1024)
             check(lib().pdp_bh_ws_size(C.byref(q.d), C.byref(t.d), C.byref(prm), C.byref(ws_bytes)), "pdp_bh_ws_size")
             ws = Workspace(ws_bytes.value)
             continue
@@ -606,8 +613,10 @@ def _task_array(tasks):
     return arr
 
 
-def autotune(tasks, candidates: Optional[Sequence[B.pdp_params]] = None, reps: int = 3, stream=None):
-    """pdp_autotune over a list of (dict a, dict b, flags); returns (best params, result)."""
+def autotune(tasks, candidates: Optional[Sequence[B.pdp_params]] = None, reps: int = 3, stream=None,
+             base: Optional[B.pdp_params] = None):
+    """pdp_autotune over a list of (dict a, dict b, flags); returns (best params, result).  The tuner
+    times the launch shapes only; the candidate filters of ``base`` are carried into the result."""
     arr = _task_array(tasks)
     cand = (B.pdp_params * len(candidates))(*candidates) if candidates else None
     nc = len(candidates) if candidates else 0
@@ -623,6 +632,7 @@ def autotune(tasks, candidates: Optional[Sequence[B.pdp_params]] = None, reps: i
     bb = bbh_out.struct() if bbh_out is not None else None
     check(lib().pdp_autotune(arr, len(tasks), cand, nc, int(reps), C.byref(bs), C.byref(bb) if bb is not None else None,
                              st.data_ptr(), ws.ptr, ws.nbytes, _stream_handle(stream), C.byref(res)), "pdp_autotune")
+    f = base or params()
     best = B.pdp_params(res.best.inc_capacity, res.best.tile_rows, res.best.join_entries, res.best.lds_budget,
-                        res.best.flags)
+                        res.best.flags, f.theta_num, f.theta_den, f.tau_num, f.tau_den)
     return best, res

@@ -63,7 +63,7 @@ class pdp_bbh_out(C.Structure):
 
 class pdp_params(C.Structure):
     _fields_ = [("inc_capacity", u64), ("tile_rows", u32), ("join_entries", u32), ("lds_budget", u32),
-                ("flags", u32)]
+                ("flags", u32), ("theta_num", u32), ("theta_den", u32), ("tau_num", u32), ("tau_den", u32)]
 
 
 class pdp_task(C.Structure):
@@ -158,7 +158,7 @@ class PdpError(RuntimeError):
         self.code = code
 
 
-ABI_VERSION = 2  # the layout of the structures above; include/pdp.h defines the same number
+ABI_VERSION = 3  # the layout of the structures above; include/pdp.h defines the same number
 
 
 def lib():

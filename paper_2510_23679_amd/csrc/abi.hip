@@ -262,6 +262,8 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         for (base_shift = 0; (2u << base_shift) <= prm.tile_rows; ++base_shift) {
         }
     if (prm.flags & ~PDP_PARAM_PERSISTENT) return fail(PDP_E_INVAL, "unknown parameter flags 0x%x", prm.flags);
+    if (prm.theta_den && prm.theta_num > prm.theta_den) return fail(PDP_E_INVAL, "theta above 1");
+    const bool filt = prm.theta_den || prm.tau_den;
 
     pdp_plan *P = new (std::nothrow) pdp_plan();
     if (!P) return fail(PDP_E_INVAL, "out of host memory");
@@ -271,7 +273,8 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     };
     // Pass 1, in the caller's order: validation, output row layout, tile height per direction.
     uint64_t bh_rows = 0, bbh_rows = 0, rec_est = 0;
-    uint32_t tile_lds = std::max<uint32_t>(lds_budget, 8 * kTileCap);
+    // the sorted and hashed tile paths keep 8 bytes per record (12 with the filters' sums)
+    uint32_t tile_lds = std::max<uint32_t>(lds_budget, (filt ? 12 : 8) * kTileCap);
     std::vector<DevTask> caller(n_tasks);
     std::vector<uint64_t> cost(n_tasks);
     for (uint32_t t = 0; t < n_tasks; ++t) {
@@ -287,6 +290,10 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         d.a = dev_dict(tk.a);
         d.b = dev_dict(tk.b);
         d.flags = flags;
+        d.theta_n = prm.theta_num;
+        d.theta_d = prm.theta_den;
+        d.tau_n = prm.tau_num;
+        d.tau_d = prm.tau_den;
         const uint32_t nb = tk.a->n_buckets;
         const uint64_t e_max = std::max<uint64_t>(std::max(tk.a->capacity, tk.b->capacity), 1);
         // sub-ranges of bpw buckets hold ~join_entries entries of the larger genome; an item
@@ -312,7 +319,7 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
             // window counts (16 bits each) and at least one row of packed 16-bit sums plus its
             // touched-word bitmap must fit
             const uint64_t W = (uint64_t(C->n_genes) + 1) / 2;
-            const uint64_t dense = 4 * (((W + 3) & ~3ull) + W + (W + 31) / 32);
+            const uint64_t dense = 4 * (((W + 3) & ~3ull) + (filt ? 3 : 1) * W + (W + 31) / 32);
             if (dense > kMaxTileLds)
                 return bail(fail(PDP_E_LIMIT, "task %u: %u target genes do not fit an LDS tile", t, C->n_genes));
             tile_lds = std::max<uint32_t>(tile_lds, static_cast<uint32_t>(dense));

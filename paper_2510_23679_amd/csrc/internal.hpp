@@ -80,6 +80,7 @@ struct DevTask {
     uint32_t row_base[2];   // first best-hit row of each direction (UINT32_MAX: none)
     uint32_t bbh_row_base;  // first BBH row (UINT32_MAX: none)
     uint32_t cell_base;     // first cell of the task's (tile, item) record-count matrix
+    uint32_t theta_n, theta_d, tau_n, tau_d;  // candidate filters (zero denominator: off)
 };
 
 struct DevTile {

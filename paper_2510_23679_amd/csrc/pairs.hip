@@ -142,7 +142,7 @@ __device__ __forceinline__ void join_range(const DevTask &T, uint32_t a0, uint32
                     const uint32_t rl = (ag & ((1u << s0) - 1u)) << 24;
                     for (uint32_t t = 0; t < m; ++t)
                         if (p + t < rec_cap)
-                            recs[p + t] = make_uint2(rl | bg[lo + t], min(an, static_cast<uint32_t>(bn[lo + t])));
+                            recs[p + t] = make_uint2(rl | bg[lo + t], an | (static_cast<uint32_t>(bn[lo + t]) << 16));
                 }
                 if (ba) {
                     for (uint32_t t = 0; t < m; ++t) {
@@ -150,7 +150,7 @@ __device__ __forceinline__ void join_range(const DevTask &T, uint32_t a0, uint32
                         const uint32_t p = atomicAdd(&tcount[t1 + (g >> s1)], 1u);
                         if (p < rec_cap)
                             recs[p] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | ag,
-                                                 min(an, static_cast<uint32_t>(bn[lo + t])));
+                                                 static_cast<uint32_t>(bn[lo + t]) | (an << 16));
                     }
                 }
             }
@@ -226,14 +226,14 @@ __device__ __forceinline__ void join_round_p(const DevTask &T, const JoinRoundP 
                 const uint32_t rl = (ag & ((1u << s0) - 1u)) << 24;
                 for (uint32_t t = 0; t < m; ++t)
                     if (o + t < rec_cap)
-                        recs[o + t] = make_uint2(rl | (bk[p + t] & mskb), min(an, static_cast<uint32_t>(bn[p + t])));
+                        recs[o + t] = make_uint2(rl | (bk[p + t] & mskb), an | (static_cast<uint32_t>(bn[p + t]) << 16));
             }
             if (ba) {
                 for (uint32_t t = 0; t < m; ++t) {
                     const uint32_t g = bk[p + t] & mskb;
                     const uint32_t o = atomicAdd(&tcount[t1 + (g >> s1)], 1u);
                     if (o < rec_cap)
-                        recs[o] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | ag, min(an, static_cast<uint32_t>(bn[p + t])));
+                        recs[o] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | ag, static_cast<uint32_t>(bn[p + t]) | (an << 16));
                 }
             }
         }
@@ -424,6 +424,25 @@ __device__ __forceinline__ bool j_equal(uint32_t m1, uint32_t d1, uint32_t m2, u
     return static_cast<uint64_t>(m1) * d2 == static_cast<uint64_t>(m2) * d1;
 }
 
+__device__ __forceinline__ uint32_t rec_min(uint32_t y) { return min(y & 0xFFFFu, y >> 16); }
+
+// Candidate filters on one (row, column) pair: nr / nc windows of the two genes (their
+// lengths are windows + k - 1: a pair with a shared k-mer has windows on both sides),
+// sr / sc the occurrences of the shared k-mers in the row / column gene.  Eq.
+// length_threshold: each length at least theta times the other; Eq. directional_jaccard:
+// sr / nr and sc / nc at least tau.  Exact 64-bit products; a zero denominator is "off".
+__device__ __forceinline__ bool candidate(const DevTask &T, uint32_t nr, uint32_t nc, uint32_t sr, uint32_t sc) {
+    if (T.theta_d) {
+        const uint64_t lr = nr + T.a.k - 1, lc = nc + T.a.k - 1;
+        if (lr * T.theta_d < uint64_t(T.theta_n) * lc || lc * T.theta_d < uint64_t(T.theta_n) * lr) return false;
+    }
+    if (T.tau_d) {
+        if (uint64_t(sr) * T.tau_d < uint64_t(T.tau_n) * nr || uint64_t(sc) * T.tau_d < uint64_t(T.tau_n) * nc)
+            return false;
+    }
+    return true;
+}
+
 // Static LDS of a tile work-group.
 struct TileLds {
     uint32_t rowlen[kTileMaxRows];    // distinct columns per row (sorted path)
@@ -497,8 +516,8 @@ __device__ __forceinline__ void emit_row(uint32_t grow, uint32_t n, Cand cand,
     }
 }
 
-// Sorted path: the tile's n <= kTileCap records sit in LDS as 48-bit keys (row 8 bits,
-// column 24 bits, min count 16 bits); after the sort every (row, column) is one run.
+// Sorted path: the tile's n <= kTileCap records sit in LDS as 64-bit keys (row 8 bits,
+// column 24 bits, the two counts 32 bits); after the sort every (row, column) is one run.
 // Each thread keeps its kTilePer keys (strided by the work-group size) in registers,
 // ranks the run heads with one ballot scan, then the key array is reused for the
 // distinct columns and their sums.
@@ -513,7 +532,7 @@ __device__ __forceinline__ void tile_sorted(const DevTile &tl, const DevTask &T,
     for (uint32_t r = threadIdx.x; r < tl.nrows; r += kTileThreads) S.rowlen[r] = 0;
     for (uint32_t i = threadIdx.x; i < n; i += kTileThreads) {
         const uint2 r = recs[rb + i];
-        keys[i] = (static_cast<uint64_t>(r.x) << 16) | (r.y & 0xFFFFu);
+        keys[i] = (static_cast<uint64_t>(r.x) << 32) | r.y;
     }
     __syncthreads();
     wg_network_sort(n, [&](uint32_t lo, uint32_t hi) {
@@ -534,8 +553,8 @@ __device__ __forceinline__ void tile_sorted(const DevTile &tl, const DevTask &T,
         const bool valid = i < n;
         const uint64_t x = valid ? keys[i] : 0;
         const uint64_t xp = valid && i ? keys[i - 1] : 0;
-        const bool h = valid && (i == 0 || (x >> 16) != (xp >> 16));
-        const bool rs = valid && (i == 0 || (x >> 40) != (xp >> 40));
+        const bool h = valid && (i == 0 || (x >> 32) != (xp >> 32));
+        const bool rs = valid && (i == 0 || (x >> 56) != (xp >> 56));
         const uint64_t mask = __ballot(h);
         kr[j] = x;
         below[j] = mask_below(mask);
@@ -554,7 +573,12 @@ __device__ __forceinline__ void tile_sorted(const DevTile &tl, const DevTask &T,
     const uint32_t u = S.rank[kTilePer * NW];  // distinct (row, column)
     uint32_t *ucol = lds;                      // (row << 24) | column, per distinct pair
     uint32_t *msum = lds + kTileCap;           // sum of minima, per distinct pair
-    for (uint32_t r = threadIdx.x; r < u; r += kTileThreads) msum[r] = 0;
+    uint32_t *ssum = lds + 2 * kTileCap;       // with filters: both sums of counts (16 bits each)
+    const bool filt = T.theta_d || T.tau_d;
+    for (uint32_t r = threadIdx.x; r < u; r += kTileThreads) {
+        msum[r] = 0;
+        if (filt) ssum[r] = 0;
+    }
     __syncthreads();
 #pragma unroll
     for (uint32_t j = 0; j < kTilePer; ++j) {
@@ -562,13 +586,15 @@ __device__ __forceinline__ void tile_sorted(const DevTile &tl, const DevTask &T,
         if (i >= n) continue;
         const bool h = (head >> j) & 1u;
         const uint32_t r = S.rank[j * NW + w] + below[j] + (h ? 0u : ~0u);  // rank of the run head
-        const uint32_t row = static_cast<uint32_t>(kr[j] >> 40);
+        const uint32_t row = static_cast<uint32_t>(kr[j] >> 56);
         if (h) {
-            ucol[r] = static_cast<uint32_t>(kr[j] >> 16);
+            ucol[r] = static_cast<uint32_t>(kr[j] >> 32);
             atomicAdd(&S.rowlen[row], 1u);
             if ((rstart >> j) & 1u) S.rowfirst[row] = r;
         }
-        atomicAdd(&msum[r], static_cast<uint32_t>(kr[j] & 0xFFFFu));
+        const uint32_t y = static_cast<uint32_t>(kr[j]);
+        atomicAdd(&msum[r], rec_min(y));
+        if (filt) atomicAdd(&ssum[r], y);  // each half stays below 2^16: no carry
     }
     __syncthreads();
     // window counts in one round trip for the whole tile: the column's joins its sum
@@ -589,6 +615,10 @@ __device__ __forceinline__ void tile_sorted(const DevTile &tl, const DevTask &T,
                             *c = ucol[beg + e] & 0xFFFFFFu;
                             *m = v & 0xFFFFu;
                             *d = nr + (v >> 16) - *m;
+                            if (filt) {
+                                const uint32_t sv = ssum[beg + e];
+                                if (!candidate(T, nr, v >> 16, sv & 0xFFFFu, sv >> 16)) *m = 0;  // not a candidate
+                            }
                         },
                         bh_ptr, slab, bh_col, bh_num, bh_den, bh_cap, &S.flag);
     }
@@ -597,7 +627,8 @@ __device__ __forceinline__ void tile_sorted(const DevTile &tl, const DevTask &T,
 // Dense path for rows [rlo, rhi) of a tile whose records overflow LDS otherwise: the
 // column genome's window counts (16 bits each) stay in LDS, and groups of rows are
 // summed into 16-bit LDS accumulators (two per word) with a touched-word bitmap; each
-// group rescans the tile's records.  Rows visit only their touched words.
+// group rescans the tile's records.  With candidate filters two more accumulators per
+// row hold the occurrence sums of each gene.  Rows visit only their touched words.
 template <bool WRITE>
 __device__ __forceinline__ void tile_dense(const DevTile &tl, const DevTask &T, const uint2 *recs, uint64_t rb,
                                            uint32_t n, uint32_t rlo, uint32_t rhi, uint32_t lds_words,
@@ -606,20 +637,24 @@ __device__ __forceinline__ void tile_dense(const DevTile &tl, const DevTask &T, 
                                            uint32_t *lds, TileLds &S) {
     const DevDict &R = tl.dir == 0 ? T.a : T.b;
     const DevDict &C = tl.dir == 0 ? T.b : T.a;
+    const bool filt = T.theta_d || T.tau_d;
     const uint32_t ncols = C.n_genes;
-    const uint32_t W = (ncols + 1) >> 1;  // accumulator words per row
+    const uint32_t W = (ncols + 1) >> 1;  // accumulator words per row and sum
     const uint32_t WB = (W + 31) >> 5;    // bitmap words per row
+    const uint32_t NA = filt ? 3 : 1;     // sums per column: minima (+ row and column occurrences)
     const uint32_t cw_words = (W + 3) & ~3u;
     uint16_t *cw = reinterpret_cast<uint16_t *>(lds);
     for (uint32_t c = threadIdx.x; c < ncols; c += kTileThreads) cw[c] = static_cast<uint16_t>(C.nwin[c]);
     uint32_t *acc_base = lds + cw_words;
-    const uint32_t G = (lds_words - cw_words) / (W + WB);  // rows per pass, at least 1 by plan
+    const uint32_t G = (lds_words - cw_words) / (NA * W + WB);  // rows per pass, at least 1 by plan
     const uint32_t wave = threadIdx.x / kWave;
     for (uint32_t g0 = rlo; g0 < rhi; g0 += G) {
         const uint32_t gn = min(G, rhi - g0);
-        uint32_t *acc = acc_base;
-        uint32_t *bits = acc_base + gn * W;
-        const uint32_t words = gn * (W + WB);
+        uint32_t *acc = acc_base;              // [gn][W] minima
+        uint32_t *asr = acc_base + gn * W;     // [gn][W] row occurrences (filters)
+        uint32_t *asc = asr + gn * W;          // [gn][W] column occurrences (filters)
+        uint32_t *bits = acc_base + NA * gn * W;
+        const uint32_t words = gn * (NA * W + WB);
         for (uint32_t i = threadIdx.x; i < words; i += kTileThreads) acc[i] = 0;
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < n; i += kTileThreads) {
@@ -627,28 +662,42 @@ __device__ __forceinline__ void tile_dense(const DevTile &tl, const DevTask &T, 
             const uint32_t rr = (r.x >> 24) - g0;
             const uint32_t c = r.x & 0xFFFFFFu, wd = c >> 1;
             if (rr >= gn || c >= ncols) continue;
-            const uint32_t old = atomicAdd(&acc[rr * W + wd], r.y << ((c & 1u) << 4));
+            const uint32_t sh = (c & 1u) << 4;
+            const uint32_t old = atomicAdd(&acc[rr * W + wd], rec_min(r.y) << sh);
+            if (filt) {
+                atomicAdd(&asr[rr * W + wd], (r.y & 0xFFFFu) << sh);
+                atomicAdd(&asc[rr * W + wd], (r.y >> 16) << sh);
+            }
             if (old == 0) atomicOr(&bits[rr * WB + (wd >> 5)], 1u << (wd & 31u));
         }
         __syncthreads();
         for (uint32_t rr = wave; rr < gn; rr += kTileThreads / kWave) {
             const uint32_t row = tl.row0 + g0 + rr;
             const uint32_t *arow = acc + rr * W;
+            const uint32_t *srow = asr + rr * W;
+            const uint32_t *crow = asc + rr * W;
             const uint32_t *brow = bits + rr * WB;
             // candidates: the touched words of the row, two columns each, in ascending order;
             // a lane walks one bitmap word, so lane chunks of 64 words stay in column order
             const uint32_t lane = lane_id();
             const uint32_t grow = T.row_base[tl.dir] + row;
             const uint32_t nr = R.nwin[row];
+            // sum of minima of column 2*wd + h, or 0 when the pair is filtered out
+            auto mval = [&](uint32_t wd, uint32_t h) -> uint32_t {
+                const uint32_t sh = h << 4;
+                const uint32_t m = (arow[wd] >> sh) & 0xFFFFu;
+                if (!m || !filt) return m;
+                return candidate(T, nr, cw[2 * wd + h], (srow[wd] >> sh) & 0xFFFFu, (crow[wd] >> sh) & 0xFFFFu) ? m
+                                                                                                                : 0u;
+            };
             uint32_t bm = 0, bd = 1;
             for (uint32_t bw = lane; bw < WB; bw += kWave) {
                 for (uint32_t msk = brow[bw]; msk;) {
                     const uint32_t wd = (bw << 5) + (__ffs(msk) - 1);
                     msk &= msk - 1;
-                    const uint32_t v = arow[wd];
 #pragma unroll
                     for (uint32_t h = 0; h < 2; ++h) {
-                        const uint32_t m = h ? v >> 16 : v & 0xFFFFu;
+                        const uint32_t m = mval(wd, h);
                         if (!m) continue;
                         const uint32_t d = nr + cw[2 * wd + h] - m;
                         if (j_greater(m, d, bm, bd)) {
@@ -675,10 +724,11 @@ __device__ __forceinline__ void tile_dense(const DevTile &tl, const DevTask &T, 
                     for (uint32_t msk = mask; msk;) {
                         const uint32_t wd = (bw << 5) + (__ffs(msk) - 1);
                         msk &= msk - 1;
-                        const uint32_t v = arow[wd];
-                        const uint32_t m0 = v & 0xFFFFu, m1 = v >> 16;
-                        if (m0 && j_equal(m0, nr + cw[2 * wd] - m0, bm, bd)) ++cnt;
-                        if (m1 && j_equal(m1, nr + cw[2 * wd + 1] - m1, bm, bd)) ++cnt;
+#pragma unroll
+                        for (uint32_t h = 0; h < 2; ++h) {
+                            const uint32_t m = mval(wd, h);
+                            if (m && j_equal(m, nr + cw[2 * wd + h] - m, bm, bd)) ++cnt;
+                        }
                     }
                     const uint32_t incl = wave_inclusive_sum(cnt);
                     const uint32_t total = __shfl(incl, kWave - 1, kWave);
@@ -686,10 +736,9 @@ __device__ __forceinline__ void tile_dense(const DevTile &tl, const DevTask &T, 
                     for (uint32_t msk = cnt ? mask : 0u; msk;) {
                         const uint32_t wd = (bw << 5) + (__ffs(msk) - 1);
                         msk &= msk - 1;
-                        const uint32_t v = arow[wd];
 #pragma unroll
                         for (uint32_t h = 0; h < 2; ++h) {
-                            const uint32_t mm = h ? v >> 16 : v & 0xFFFFu;
+                            const uint32_t mm = mval(wd, h);
                             if (!mm) continue;
                             const uint32_t c = 2 * wd + h;
                             const uint32_t d = nr + cw[c] - mm;
@@ -732,10 +781,12 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
                                             uint4 *slab, uint32_t *lds, TileLds &S) {
     const DevDict &R = tl.dir == 0 ? T.a : T.b;
     const DevDict &C = tl.dir == 0 ? T.b : T.a;
+    const bool filt = T.theta_d || T.tau_d;
     uint32_t *hk = lds;
     uint32_t *hv = lds + kHashSlots;
+    uint32_t *hs = lds + 2 * kHashSlots;  // with filters: occurrences of the row and column genes (16 bits each)
     uint4 *z = reinterpret_cast<uint4 *>(lds);
-    for (uint32_t i = threadIdx.x; i < kHashSlots / 2; i += kTileThreads) z[i] = make_uint4(0, 0, 0, 0);
+    for (uint32_t i = threadIdx.x; i < (filt ? 3 : 2) * kHashSlots / 4; i += kTileThreads) z[i] = make_uint4(0, 0, 0, 0);
     for (uint32_t rl = g0 + threadIdx.x; rl < g1; rl += kTileThreads) {
         S.best[rl] = 0;
         S.ties[rl] = 0;
@@ -765,7 +816,8 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
                 if (prev == 0u || prev == key) break;
                 h = (h + 1) & (kHashSlots - 1);
             }
-            atomicAdd(&hv[h], r.y);
+            atomicAdd(&hv[h], rec_min(r.y));
+            if (filt) atomicAdd(&hs[h], r.y);  // each half stays below 2^16: no carry
         }
     }
     __syncthreads();
@@ -782,9 +834,11 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
         const uint32_t key = hk[sl];
         if (!key) continue;
         const uint32_t rl = (key - 1) >> 24;
-        const uint32_t m = hv[sl];  // at most PDP_MAX_WINDOWS
+        uint32_t m = hv[sl];  // at most PDP_MAX_WINDOWS
         const uint32_t nc = ncw[q];
+        if (filt && !candidate(T, S.nr[rl], nc, hs[sl] & 0xFFFFu, hs[sl] >> 16)) m = 0;  // not a candidate
         hv[sl] = m | (nc << 16);
+        if (!m) continue;
         const uint32_t d = S.nr[rl] + nc - m;
         const unsigned long long want = (static_cast<unsigned long long>(m) << 32) | d;
         unsigned long long cur = S.best[rl];
@@ -804,6 +858,7 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
         const uint32_t rl = (key - 1) >> 24, c = (key - 1) & 0xFFFFFFu;
         const uint32_t v = hv[sl];
         const uint32_t m = v & 0xFFFFu, d = S.nr[rl] + (v >> 16) - m;
+        if (!m) continue;  // filtered out
         const unsigned long long b = S.best[rl];
         if (!j_equal(m, d, static_cast<uint32_t>(b >> 32), static_cast<uint32_t>(b))) continue;
         const uint32_t t = atomicAdd(&S.ties[rl], 1u);

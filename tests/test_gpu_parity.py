@@ -399,3 +399,54 @@ def test_families_full_size_properties():
     for x in range(n):
         smallest.setdefault(comp[x], x)
     assert np.array_equal(got, np.array([smallest[c] for c in comp], dtype=np.uint32))
+
+
+# ------------------------------------------------ candidate filters (theta, tau)
+
+def test_filter_fixtures_on_gpu(golden):
+    for e in golden["filters"]:
+        say("filter fixture", e["id"])
+        gi, gj = genome_from_strings(e["gi"]), genome_from_strings(e["gj"])
+        prm = pdp.params(theta=tuple(e["theta"]) if e["theta"] else None, tau=tuple(e["tau"]) if e["tau"] else None)
+        _, res = run_all([gi, gj], e["k"], prm)
+        for direction, key, n in ((0, "bh_ij", len(e["gi"])), (1, "bh_ji", len(e["gj"]))):
+            ptr, col, num, den = res.best_hits(0, direction)
+            got = [[[int(col[p]), int(num[p]), int(den[p])] for p in range(ptr[r], ptr[r + 1])] for r in range(n)]
+            assert got == e[key], (e["id"], key)
+        a, b, _, _ = res.bbh_pairs(0)
+        assert [[int(x), int(y)] for x, y in zip(a, b)] == e["bbh"], e["id"]
+
+
+def _compare_filtered(genomes, k, res, theta, tau):
+    _, want = oracle.all_pairs(genomes, k, theta=theta, tau=tau)
+    for t, key in enumerate(want):
+        ab, ba, bb = want[key]
+        check_bh(res.best_hits(t, 0), ab)
+        check_bh(res.best_hits(t, 1), ba)
+        check_bbh(res.bbh_pairs(t), bb)
+
+
+@pytest.mark.parametrize("theta,tau", [((3, 4), None), (None, (1, 5)), ((1, 2), (1, 3)), ((9, 10), (2, 5))])
+def test_filters_family_workload(theta, tau):
+    say("filters theta", theta, "tau", tau)
+    ds = make_config(2, genomes=3, genes=300)
+    k = 5
+    _, res = run_all(ds.genomes, k, pdp.params(theta=theta, tau=tau))
+    _compare_filtered(ds.genomes, k, res, theta, tau)
+
+
+@pytest.mark.parametrize("tile_rows", [1, 64])
+def test_filters_on_dense_and_rewritten_tiles(tile_rows):
+    # the overflowing tile of test_tiles_past_the_lds_sort (dense passes, a row with 6 ties rewritten
+    # by the second tile launch), with both filters on
+    rng = random.Random(5)
+    base = "".join(rng.choice(ALPHA) for _ in range(600))
+    a = [base, _mutate(rng, base, 0.02), base[:420]] + ["".join(rng.choice(ALPHA) for _ in range(200)) for _ in range(40)]
+    b = [_mutate(rng, base, 0.03) for _ in range(7)] + [base] * 6 + [base[:300]]
+    b += ["".join(rng.choice(ALPHA) for _ in range(200)) for _ in range(40)]
+    rng.shuffle(b)
+    ga, gb = genome_from_strings(a), genome_from_strings(b)
+    say("filters on dense and rewritten tiles, tile_rows", tile_rows)
+    theta, tau = (3, 4), (1, 5)
+    _, res = run_all([ga, gb], 5, pdp.params(tile_rows=tile_rows, theta=theta, tau=tau))
+    _compare_filtered([ga, gb], 5, res, theta, tau)
