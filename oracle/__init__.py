@@ -1,9 +1,10 @@
 """CPU oracle for the best-hit path -- TEST INFRASTRUCTURE ONLY.
 
 Thin ctypes wrapper around ``pdp_oracle.c`` (a plain C rendering of the
-paper's definitions: k rule, Alg. 1 multiplicity vectors, Eq. jaccard_k,
-Eq. best_hit with ties, Eq. bidirectional_best_hit and Alg. 3), plus
-``brute`` (the same definitions on Python strings, for tiny inputs).
+paper's definitions over the amino-acid or the nucleotide alphabet: k rule,
+Alg. 1 multiplicity vectors, Eq. jaccard_k, Eq. best_hit with ties,
+Eq. bidirectional_best_hit and Alg. 3), plus ``brute`` (the same definitions
+on Python strings, for tiny inputs).
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg import
 this package.  It shares no code with the GPU library and never loads it.
@@ -43,8 +44,9 @@ def _load():
     sig = {
         "orc_k_rule": (C.c_int, [u64, u32, C.c_int, P(u32)]),
         "orc_n_windows": (i64, [i64, u32]),
-        "orc_mv": (i64, [C.c_char_p, i64, u32, P(u64), P(u32), P(i64)]),
-        "orc_genome_new": (vp, [vp, vp, u32, u32, P(i64)]),
+        "orc_k_max": (u32, [u32]),
+        "orc_mv": (i64, [C.c_char_p, i64, u32, u32, P(u64), P(u32), P(i64)]),
+        "orc_genome_new": (vp, [vp, vp, u32, u32, u32, P(i64)]),
         "orc_genome_free": (None, [vp]),
         "orc_genome_n": (u32, [vp]),
         "orc_genome_entries": (u64, [vp]),
@@ -106,40 +108,63 @@ def n_windows(length: int, k: int) -> int:
     return int(_load().orc_n_windows(int(length), int(k)))
 
 
-def mv(gene: bytes, k: int):
-    """Alg. 1 for one gene: (ids ascending, multiplicities); ids are base-20 values of the windows."""
+# The two alphabets of the paper's genes: amino acids and nucleotides.
+ALPHABETS = {"aa": "ACDEFGHIKLMNPQRSTVWY", "nt": "ACGT"}
+_ALPHA_ID = {"aa": 0, "nt": 1}
+
+
+def _alpha(alphabet) -> int:
+    if alphabet not in _ALPHA_ID:
+        raise ValueError(f"unknown alphabet {alphabet!r} (expected 'aa' or 'nt')")
+    return _ALPHA_ID[alphabet]
+
+
+def k_max(alphabet: str = "aa") -> int:
+    """Largest k whose identifiers fit 64 bits for this alphabet."""
+    return int(_load().orc_k_max(_alpha(alphabet)))
+
+
+def mv(gene: bytes, k: int, alphabet: str = "aa"):
+    """Alg. 1 for one gene: (ids ascending, multiplicities); ids are base-|alphabet| values of the windows."""
     lib = _load()
     nw = max(1, n_windows(len(gene), k))
     ids = (C.c_uint64 * nw)()
     cnt = (C.c_uint32 * nw)()
     bad = C.c_int64(-1)
-    d = lib.orc_mv(gene, len(gene), int(k), ids, cnt, C.byref(bad))
+    d = lib.orc_mv(gene, len(gene), int(k), _alpha(alphabet), ids, cnt, C.byref(bad))
+    if d == -2:
+        raise ValueError(f"k = {k} outside 1..{k_max(alphabet)} for alphabet {alphabet!r}")
     if d < 0:
         raise ValueError(f"byte outside the alphabet at offset {bad.value}")
     return np.array(ids[:d], dtype=np.uint64), np.array(cnt[:d], dtype=np.uint32)
 
 
-def decode_id(i: int, k: int) -> str:
-    """k-mer string of a base-20 identifier (for comparing dictionaries by content)."""
-    alpha = "ACDEFGHIKLMNPQRSTVWY"
+def decode_id(i: int, k: int, alphabet: str = "aa") -> str:
+    """k-mer string of a base-|alphabet| identifier (for comparing dictionaries by content)."""
+    alpha = ALPHABETS[alphabet]
     s = []
     for _ in range(k):
-        s.append(alpha[i % 20])
-        i //= 20
+        s.append(alpha[i % len(alpha)])
+        i //= len(alpha)
     return "".join(reversed(s))
 
 
 class OracleGenome:
-    """Multiplicity vectors of every gene of one genome (residues + offsets)."""
+    """Multiplicity vectors of every gene of one genome (residues + offsets).  The alphabet
+    is the genome's own (``genome.alphabet``, amino acids when it has none) unless given."""
 
-    def __init__(self, genome, k: int):
+    def __init__(self, genome, k: int, alphabet: Optional[str] = None):
         lib = _load()
         self.k = int(k)
+        self.alphabet = alphabet or getattr(genome, "alphabet", "aa")
         self._res = np.ascontiguousarray(genome.residues, dtype=np.uint8)
         self._off = np.ascontiguousarray(genome.offsets, dtype=np.uint64)
         n = int(self._off.shape[0] - 1)
         bad = C.c_int64(-1)
-        h = lib.orc_genome_new(self._res.ctypes.data, self._off.ctypes.data, n, self.k, C.byref(bad))
+        h = lib.orc_genome_new(self._res.ctypes.data, self._off.ctypes.data, n, self.k, _alpha(self.alphabet),
+                               C.byref(bad))
+        if not h and bad.value == -2:
+            raise ValueError(f"k = {k} outside 1..{k_max(self.alphabet)} for alphabet {self.alphabet!r}")
         if not h:
             raise ValueError(f"byte outside the alphabet at residue offset {bad.value}")
         self._h = h
@@ -247,9 +272,10 @@ def bbh_alg3(gi: OracleGenome, gj: OracleGenome, ab: BH, ba: BH) -> Pairs:
     return _pairs(_load().orc_bbh_alg3(gi._h, gj._h, ab._h, ba._h))
 
 
-def all_pairs(genomes, k: int, threads: Optional[int] = None, pairs=None, theta=None, tau=None):
+def all_pairs(genomes, k: int, threads: Optional[int] = None, pairs=None, theta=None, tau=None,
+              alphabet: Optional[str] = None):
     """BH both ways and BBH for every unordered genome pair i<j (or the given pairs)."""
-    og = [OracleGenome(g, k) for g in genomes]
+    og = [OracleGenome(g, k, alphabet) for g in genomes]
     if pairs is None:
         pairs = [(i, j) for i in range(len(og)) for j in range(i + 1, len(og))]
     out = {}

@@ -29,9 +29,13 @@
  *   - the k rule sums residues over the dataset and rounds up, computed in
  *     integers (smallest k with |alphabet|^k >= total); rounding down is mode 1.
  *
- * The k-mer identifier f used here is the base-20 value of the window over the
- * alphabet string below.  Best hits do not depend on the choice of f; only the
- * order inside a multiplicity vector does.
+ * The paper's genes are strings over a nucleotide or an amino-acid alphabet
+ * (Basic notions); both are supported: the 20 standard amino acids
+ * ACDEFGHIKLMNPQRSTVWY (alphabet 0) and the four nucleotides ACGT (alphabet 1).
+ * The k-mer identifier f used here is the base-|alphabet| value of the window,
+ * each letter taking its index in the alphabet string below, first letter most
+ * significant.  Best hits do not depend on the choice of f; only the order
+ * inside a multiplicity vector does.
  *
  * Only the tests, the smoke check and the CPU-baseline leg of the benchmark
  * use this file.  It shares nothing with the GPU library.
@@ -41,14 +45,25 @@
 #include <stdlib.h>
 #include <string.h>
 
-static const char ORC_ALPHABET[] = "ACDEFGHIKLMNPQRSTVWY";
-#define ORC_SIGMA 20u
+static const char *const ORC_ALPHABETS[2] = {"ACDEFGHIKLMNPQRSTVWY", "ACGT"};
+static const uint32_t ORC_SIGMA[2] = {20u, 4u};
 
-/* Index of residue c in the alphabet, or -1 for any other byte. */
-static int orc_residue(unsigned char c) {
-    for (int i = 0; i < (int)ORC_SIGMA; ++i)
-        if ((unsigned char)ORC_ALPHABET[i] == c) return i;
+/* Index of byte c in alphabet a (0: amino acids, 1: nucleotides), or -1 for any
+ * other byte. */
+static int orc_residue(unsigned char c, uint32_t a) {
+    for (int i = 0; i < (int)ORC_SIGMA[a]; ++i)
+        if ((unsigned char)ORC_ALPHABETS[a][i] == c) return i;
     return -1;
+}
+
+/* Largest k whose identifiers all fit 64 bits (|alphabet|^k <= 2^64), 0 for an
+ * unknown alphabet. */
+uint32_t orc_k_max(uint32_t a) {
+    if (a > 1) return 0;
+    uint32_t k = 0;
+    unsigned __int128 p = 1;
+    while (p * ORC_SIGMA[a] <= ((unsigned __int128)1 << 64)) { p *= ORC_SIGMA[a]; ++k; }
+    return k;
 }
 
 /* ---------------------------------------------------------------- phase (a) */
@@ -82,21 +97,23 @@ int64_t orc_n_windows(int64_t len, uint32_t k) {
     return len >= (int64_t)k ? len - (int64_t)k + 1 : 0;
 }
 
-/* Alg. 1 for one gene: every window g[p..p+k-1] gets the identifier f(alpha)
- * (its base-20 value); the identifiers are grouped by sorting, and each group
- * becomes one (id, multiplicity) pair, ascending by id.  ids/cnt must hold
- * orc_n_windows(len, k) entries.  Returns the number of distinct k-mers, or -1
- * if a byte outside the alphabet occurs (its offset goes to *bad). */
-int64_t orc_mv(const unsigned char *s, int64_t len, uint32_t k, uint64_t *ids, uint32_t *cnt, int64_t *bad) {
+/* Alg. 1 for one gene over alphabet a: every window g[p..p+k-1] gets the
+ * identifier f(alpha) (its base-|alphabet| value); the identifiers are grouped
+ * by sorting, and each group becomes one (id, multiplicity) pair, ascending by
+ * id.  ids/cnt must hold orc_n_windows(len, k) entries.  Returns the number of
+ * distinct k-mers, -1 if a byte outside the alphabet occurs (its offset goes to
+ * *bad), or -2 for an unknown alphabet or k outside 1..orc_k_max(a). */
+int64_t orc_mv(const unsigned char *s, int64_t len, uint32_t k, uint32_t a, uint64_t *ids, uint32_t *cnt, int64_t *bad) {
+    if (a > 1 || k < 1 || k > orc_k_max(a)) return -2;
     for (int64_t p = 0; p < len; ++p) {
-        if (orc_residue(s[p]) < 0) { if (bad) *bad = p; return -1; }
+        if (orc_residue(s[p], a) < 0) { if (bad) *bad = p; return -1; }
     }
     int64_t nw = orc_n_windows(len, k);
     if (nw == 0) return 0;
     uint64_t *w = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)nw);
     for (int64_t p = 0; p < nw; ++p) {
         uint64_t id = 0;
-        for (uint32_t i = 0; i < k; ++i) id = id * ORC_SIGMA + (uint64_t)orc_residue(s[p + i]);
+        for (uint32_t i = 0; i < k; ++i) id = id * ORC_SIGMA[a] + (uint64_t)orc_residue(s[p + i], a);
         w[p] = id;
     }
     qsort(w, (size_t)nw, sizeof(uint64_t), cmp_u64);
@@ -129,9 +146,15 @@ void orc_genome_free(orc_genome *g) {
     free(g->ptr); free(g->ids); free(g->cnt); free(g->nwin); free(g->len); free(g);
 }
 
-/* Builds the multiplicity vector of every gene (genes are residues[off[i]..off[i+1])).
- * Returns NULL on a byte outside the alphabet (*bad = its offset in residues). */
-orc_genome *orc_genome_new(const unsigned char *residues, const uint64_t *off, uint32_t n, uint32_t k, int64_t *bad) {
+/* Builds the multiplicity vector of every gene (genes are residues[off[i]..off[i+1])) over
+ * alphabet a.  Returns NULL on a byte outside the alphabet (*bad = its offset in residues)
+ * or on an unknown alphabet or k outside 1..orc_k_max(a) (*bad = -2). */
+orc_genome *orc_genome_new(const unsigned char *residues, const uint64_t *off, uint32_t n, uint32_t k, uint32_t a,
+                           int64_t *bad) {
+    if (a > 1 || k < 1 || k > orc_k_max(a)) {
+        if (bad) *bad = -2;
+        return NULL;
+    }
     orc_genome *g = (orc_genome *)calloc(1, sizeof(orc_genome));
     g->n = n; g->k = k;
     g->ptr = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
@@ -149,7 +172,7 @@ orc_genome *orc_genome_new(const unsigned char *residues, const uint64_t *off, u
     for (uint32_t i = 0; i < n; ++i) {
         g->ptr[i] = pos;
         int64_t b = -1;
-        int64_t d = orc_mv(residues + off[i], (int64_t)(off[i + 1] - off[i]), k, g->ids + pos, g->cnt + pos, &b);
+        int64_t d = orc_mv(residues + off[i], (int64_t)(off[i + 1] - off[i]), k, a, g->ids + pos, g->cnt + pos, &b);
         if (d < 0) {
             if (bad) *bad = (int64_t)off[i] + b;
             orc_genome_free(g);

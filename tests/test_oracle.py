@@ -20,8 +20,8 @@ from synth import genome_from_strings, make_config
 ALPHA = "ACDEFGHIKLMNPQRSTVWY"
 
 
-def _og(genes, k):
-    return oracle.OracleGenome(genome_from_strings(genes), k)
+def _og(genes, k, alphabet="aa"):
+    return oracle.OracleGenome(genome_from_strings(genes, alphabet=alphabet), k)
 
 
 def _bh_rows(bh):
@@ -32,17 +32,22 @@ def _bh_rows(bh):
 
 def test_windows_and_mv(golden):
     for w in golden["windows"]:
-        k = w["k"]
+        k, al = w["k"], w.get("alphabet", "aa")
         assert oracle.n_windows(len(w["gene"]), k) == w["n"], w["id"]
-        ids, cnt = oracle.mv(w["gene"].encode(), k)
-        got = [[oracle.decode_id(int(i), k), int(c)] for i, c in zip(ids, cnt)]
+        ids, cnt = oracle.mv(w["gene"].encode(), k, al)
+        got = [[oracle.decode_id(int(i), k, al), int(c)] for i, c in zip(ids, cnt)]
         assert got == w["mv"], w["id"]
         assert int(cnt.sum()) == w["n"]
+        if "ids" in w:
+            assert [int(i) for i in ids] == w["ids"], w["id"]
+        og = _og([w["gene"]], k, al)
+        assert [int(i) for i in og.ids] == [int(i) for i in ids], w["id"]
 
 
 def test_jaccard_hand_values(golden):
     for e in golden["jaccard"]:
-        a, b = _og([e["a"]], e["k"]), _og([e["b"]], e["k"])
+        al = e.get("alphabet", "aa")
+        a, b = _og([e["a"]], e["k"], al), _og([e["b"]], e["k"], al)
         assert a.terms(0, b, 0) == (e["num"], e["den"]), e["id"]
         assert brute.terms(e["a"], e["b"], e["k"]) == (e["num"], e["den"]), e["id"]
 
@@ -85,6 +90,27 @@ def test_invalid_residue_is_reported():
         oracle.mv(b"MKXLA", 2)
     with pytest.raises(ValueError):
         _og(["MKVLA", "ACDBQ"], 2)
+    # nucleotides: N and amino-acid letters are outside ACGT; T is valid in both alphabets
+    with pytest.raises(ValueError):
+        oracle.mv(b"ACGNT", 2, "nt")
+    with pytest.raises(ValueError):
+        _og(["ACGT", "ACDE"], 2, "nt")
+    assert oracle.mv(b"ACGT", 2, "nt")[1].sum() == 3
+    with pytest.raises(ValueError):
+        oracle.mv(b"ACGT", 2, "rna")
+
+
+def test_k_range_per_alphabet():
+    # identifiers are exact 64-bit integers: |alphabet|^k <= 2^64
+    assert oracle.k_max("aa") == 14 and 20 ** 14 <= 2 ** 64 < 20 ** 15
+    assert oracle.k_max("nt") == 32 and 4 ** 32 == 2 ** 64
+    oracle.mv(b"A" * 40, 14)
+    oracle.mv(b"A" * 40, 32, "nt")
+    for k, al in ((15, "aa"), (33, "nt"), (0, "aa"), (0, "nt")):
+        with pytest.raises(ValueError):
+            oracle.mv(b"A" * 40, k, al)
+        with pytest.raises(ValueError):
+            _og(["A" * 40], k, al)
 
 
 # ------------------------------------------------------------- brute force
@@ -116,6 +142,32 @@ def test_brute_force_tiny(seed):
     for a in range(len(gi)):
         for b in range(len(gj)):
             assert oi.terms(a, oj, b) == brute.terms(gi[a], gj[b], k)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_brute_force_nucleotide(seed):
+    """Nucleotide genes (|alphabet| = 4) with k up to 9: windows repeat often at small k and
+    rarely at large k, so both dense and sparse dictionaries are covered."""
+    rng = random.Random(5000 + seed)
+    k = rng.choice([1, 2, 3, 5, 7, 9])
+    gi = _random_genes(rng, rng.randint(1, 7), "ACGT", 0, 70)
+    gj = _random_genes(rng, rng.randint(1, 7), "ACGT", 0, 70)
+    if gi and gj and rng.random() < 0.5:  # a mutated copy keeps shared k-mers at large k
+        s = list(gi[0])
+        for p in range(0, len(s), 9):
+            s[p] = rng.choice("ACGT")
+        gj.append("".join(s))
+    oi, oj = _og(gi, k, "nt"), _og(gj, k, "nt")
+    ab, ba = oracle.bh(oi, oj, threads=2), oracle.bh(oj, oi, threads=2)
+    want_ab = brute.all_best_hits(gi, gj, k)
+    want_ba = brute.all_best_hits(gj, gi, k)
+    assert _bh_rows(ab) == [want_ab[r] for r in range(len(gi))]
+    assert _bh_rows(ba) == [want_ba[r] for r in range(len(gj))]
+    p = oracle.bbh(ab, ba)
+    assert list(zip(p.a.tolist(), p.b.tolist())) == brute.bbh(gi, gj, k)
+    for a, g in enumerate(gi):
+        ids, cnt = oi.mv(a)
+        assert {oracle.decode_id(int(i), k, "nt"): int(c) for i, c in zip(ids, cnt)} == dict(brute.multiplicities(g, k))
 
 
 # --------------------------------------------------------------- invariants

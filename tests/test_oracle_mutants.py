@@ -35,6 +35,9 @@ MUTANTS = [
     ("directional filter over the other gene's windows",
      "if (wa == 0 ? tau_n > 0 : (unsigned __int128)oa * tau_d < (unsigned __int128)tau_n * wa) return 0;",
      "if (wa == 0 ? tau_n > 0 : (unsigned __int128)oa * tau_d < (unsigned __int128)tau_n * wb) return 0;"),
+    ("nucleotide letters out of order", '"ACDEFGHIKLMNPQRSTVWY", "ACGT"};', '"ACDEFGHIKLMNPQRSTVWY", "ACTG"};'),
+    ("identifier base fixed at 20", "id = id * ORC_SIGMA[a] + (uint64_t)orc_residue(s[p + i], a);",
+     "id = id * ORC_SIGMA[0] + (uint64_t)orc_residue(s[p + i], a);"),
 ]
 
 
@@ -66,14 +69,21 @@ def _pins_hold(libpath, golden) -> bool:
             oracle.build = orig_build
         from synth import genome_from_strings
 
-        def og(genes, k):
-            return oracle.OracleGenome(genome_from_strings(genes), k)
+        def og(genes, k, alphabet="aa"):
+            return oracle.OracleGenome(genome_from_strings(genes, alphabet=alphabet), k)
 
         for w in golden["windows"]:
+            al = w.get("alphabet", "aa")
             if oracle.n_windows(len(w["gene"]), w["k"]) != w["n"]:
                 return False
+            ids, cnt = oracle.mv(w["gene"].encode(), w["k"], al)
+            if [[oracle.decode_id(int(i), w["k"], al), int(c)] for i, c in zip(ids, cnt)] != w["mv"]:
+                return False
+            if "ids" in w and [int(i) for i in ids] != w["ids"]:
+                return False
         for e in golden["jaccard"]:
-            if og([e["a"]], e["k"]).terms(0, og([e["b"]], e["k"]), 0) != (e["num"], e["den"]):
+            al = e.get("alphabet", "aa")
+            if og([e["a"]], e["k"], al).terms(0, og([e["b"]], e["k"], al), 0) != (e["num"], e["den"]):
                 return False
         for e in golden["best_hits"]:
             gi, gj = og(e["gi"], e["k"]), og(e["gj"], e["k"])
