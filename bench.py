@@ -44,6 +44,9 @@ def parse():
                    help="measured HBM traffic per kernel (from rocprofv3 counters), used when its source hash matches")
     p.add_argument("--theta", default=None, help="length filter as NUM/DEN (Eq. length_threshold); off by default")
     p.add_argument("--tau", default=None, help="directional filter as NUM/DEN (Eq. directional_jaccard); off by default")
+    p.add_argument("--alphabet", choices=("aa", "nt"), default="aa",
+                   help="allpairs: amino-acid genomes (default) or nucleotide genomes (genes 3x as long, k by the "
+                        "rule with |alphabet| = 4)")
     p.add_argument("--workload", choices=("allpairs", "batched", "serving"), default="allpairs",
                    help="allpairs: the 10 x 3000 metric (default); batched: independent instances in waves, one "
                         "graph-captured persistent launch per wave, against one plan per genome pair; serving: "
@@ -370,8 +373,9 @@ def main():
     from synth import make_config
 
     torch.cuda.set_device(0)
-    ds = make_config(2)
-    k = pdp.k_rule(ds.total_residues())
+    nt = args.alphabet == "nt"
+    ds = make_config(2, alphabet=args.alphabet)
+    k = pdp.k_rule(ds.total_residues(), 4 if nt else 20)
     pairs = ds.pairs()
     gene_pairs = ds.gene_pairs()
     genes = [g.n_genes for g in ds.genomes]
@@ -491,8 +495,9 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "all-pairs BH+BBH: 10 genomes x 3000 genes (family model), 45 genome pairs, "
-                               "dictionary build included",
+        "config": {"workload": "all-pairs BH+BBH: 10 genomes x 3000 genes (family model"
+                               + (", nucleotide genes" if nt else "") + "), 45 genome pairs, dictionary build included",
+                   "alphabet": "nucleotide" if nt else "amino acid",
                    "genomes": len(genes), "genes_per_genome": genes[0], "k": k, "genome_pairs": len(pairs),
                    "gene_pairs": gene_pairs, "kmer_entries": int(sum(entries)), "best_hits": bh_nnz, "bbh_pairs": bbh_n,
                    "filters": {"theta": args.theta, "tau": args.tau}},

@@ -6,8 +6,9 @@
  * other genome with ties kept (Eq. best_hit, the jagged array of Alg. 2) and
  * the bidirectional best hits (Eq. bidirectional_best_hit, Alg. 3).  The
  * problem statement it follows is the paper's Basic notions section: a
- * genome is an ordered list of genes, a gene is a string over the amino-acid
- * alphabet, and k is chosen by phase (a) (Eq. k_length).
+ * genome is an ordered list of genes, a gene is a string over a nucleotide
+ * or an amino-acid alphabet (both are supported), and k is chosen by phase
+ * (a) (Eq. k_length).
  *
  * Conventions shared by every entry point
  *  - Device buffers are allocated and owned by the caller.  The library never
@@ -35,10 +36,19 @@
 extern "C" {
 #endif
 
-#define PDP_ABI_VERSION 3u
+#define PDP_ABI_VERSION 4u
 
-/* Largest k: 5-bit residue codes of k <= 12 residues fit in 60 bits. */
+/* The two alphabets of the Basic notions section.  A dictionary's alphabet
+ * fixes how a letter becomes a symbol, the symbol width of a k-mer code and
+ * the largest k. */
+enum pdp_alphabet {
+    PDP_ALPHA_AMINO = 0,      /* ACDEFGHIKLMNPQRSTVWY -> 0..19, 5 bits per letter */
+    PDP_ALPHA_NUCLEOTIDE = 1  /* ACGT -> 0..3, 2 bits per letter */
+};
+/* Largest k per alphabet: codes of k letters fit in 60 (amino acids) or 62
+ * (nucleotides) bits, below the all-ones value the kernels use as padding. */
 #define PDP_K_MAX 12u
+#define PDP_K_MAX_NT 31u
 /* A gene may have at most this many k-mer windows (|g| - k + 1); longer genes
  * are rejected with PDP_E_LIMIT in the device status.  Every multiplicity and
  * every sum of minima then fits in 16 bits. */
@@ -49,10 +59,11 @@ extern "C" {
 enum pdp_code {
     PDP_OK = 0,
     PDP_E_INVAL = -1,     /* null pointer, inconsistent sizes, k differs inside a pair */
-    PDP_E_KRANGE = -2,    /* k == 0 or k > PDP_K_MAX */
+    PDP_E_KRANGE = -2,    /* k == 0 or k above the alphabet's largest (PDP_K_MAX, PDP_K_MAX_NT) */
     PDP_E_WORKSPACE = -3, /* workspace or arena smaller than the size functions require */
     PDP_E_CAPACITY = -4,  /* device: an output or scratch array was too small; needed holds the size */
-    PDP_E_ALPHABET = -5,  /* device: a residue outside ACDEFGHIKLMNPQRSTVWY; where holds its offset */
+    PDP_E_ALPHABET = -5,  /* device: a letter outside the dictionary's alphabet; where holds its offset.
+                             host: an unknown pdp_alphabet value */
     PDP_E_HIP = -6,       /* a HIP runtime call failed */
     PDP_E_BUDGET = -7,    /* serving: a request cannot fit the admission budget */
     PDP_E_LIMIT = -8,     /* a size beyond PDP_MAX_WINDOWS / PDP_MAX_GENES / 2^32 entries */
@@ -90,7 +101,7 @@ int32_t pdp_k_rule(uint64_t total, uint32_t alphabet, int32_t mode, uint32_t *k_
 /* ------------------------------------------------- k-mer dictionary build */
 
 /* One genome on the device: gene i is residues[gene_off[i] .. gene_off[i+1]),
- * ASCII upper-case letters.  gene_off has n_genes+1 entries, gene_off[0] = 0,
+ * ASCII upper-case letters of the dictionary's alphabet.  gene_off has n_genes+1 entries, gene_off[0] = 0,
  * non-decreasing, gene_off[n_genes] == n_residues (host copy of the last
  * offset, which the library trusts for sizing). */
 typedef struct pdp_genome {
@@ -103,17 +114,24 @@ typedef struct pdp_genome {
 
 /* The k-mer dictionary of one genome: the multiplicity vector of every gene
  * (Multiplicity vector building phase, Alg. 1) and an inverted index from
- * k-mer to (gene, multiplicity).  A k-mer's code packs its residues 5 bits
- * each, first residue most significant, with A=0, C=1, ..., Y=19 in the order
- * ACDEFGHIKLMNPQRSTVWY, so codes sort like the k-mer strings.
+ * k-mer to (gene, multiplicity).  A k-mer's code packs its letters, first
+ * letter most significant: amino acids 5 bits each with A=0, C=1, ..., Y=19
+ * in the order ACDEFGHIKLMNPQRSTVWY; nucleotides 2 bits each with A=0, C=1,
+ * G=2, T=3 (the code is then the base-4 value of the k-mer).  Either way codes
+ * sort like the k-mer strings.  The index is split into buckets by the
+ * leading `lead` letters: min(k, 4) amino acids (20^lead buckets, the leading
+ * letters read as a base-20 number) or min(k, 9) nucleotides (4^lead buckets,
+ * the leading 2*lead bits of the code).
  * All arrays are device memory carved by pdp_dict_bind from one arena.
  * The host fields are set by pdp_dict_bind and must not be changed. */
 typedef struct pdp_dict {
     uint32_t n_genes;
     uint32_t k;
     uint64_t capacity;    /* entries every per-entry array can hold (>= total windows) */
-    uint32_t n_buckets;   /* index directory size: 20^min(k,4) leading-residue buckets */
+    uint32_t n_buckets;   /* index directory size: 20^lead or 4^lead leading-letter buckets */
     uint32_t key_shift;   /* gene bits of ix_key; 0: this dictionary has no packed keys */
+    uint32_t alphabet;    /* pdp_alphabet */
+    uint32_t lead;        /* leading letters that name a k-mer's bucket */
     uint32_t *nwin;       /* [n_genes] windows per gene, max(0, |g|-k+1) */
     uint32_t *mv_ptr;     /* [n_genes+1] CSR offsets; mv_ptr[n_genes] = entries E */
     uint64_t *mv_code;    /* [capacity] codes, strictly ascending inside a gene */
@@ -123,28 +141,30 @@ typedef struct pdp_dict {
     uint32_t *ix_gene;    /* [capacity] gene of each index entry */
     uint32_t *ix_cnt;     /* [capacity] multiplicity of the code in that gene */
     uint32_t *ix_key;     /* [capacity] when key_shift > 0: (tail << key_shift) | gene per index
-                             entry, where tail is the code without its leading min(k,4) residues
+                             entry, where tail is the code without its leading `lead` letters
                              (those are the entry's bucket) and key_shift is the bit length of
-                             n_genes - 1 (at least 1); packed when 5*(k - min(k,4)) + key_shift
-                             <= 32.  Within a bucket the keys ascend like (code, gene). */
+                             n_genes - 1 (at least 1); packed when bits*(k - lead) + key_shift
+                             <= 32 (bits = 5 or 2 per letter).  Within a bucket the keys ascend
+                             like (code, gene). */
     pdp_status *status;   /* device status of the last pdp_dict_build */
 } pdp_dict;
 
 /* Bytes of the device arena that pdp_dict_bind carves, and of the scratch
  * workspace that pdp_dict_build needs, for a genome of n_genes genes and
- * n_residues residues.  Host only.  Errors: PDP_E_KRANGE, PDP_E_LIMIT
+ * n_residues letters over the given pdp_alphabet.  Host only.  Errors:
+ * PDP_E_ALPHABET (unknown alphabet), PDP_E_KRANGE, PDP_E_LIMIT
  * (n_genes > PDP_MAX_GENES or n_residues >= 2^32), PDP_E_INVAL. */
-int32_t pdp_dict_size(uint32_t n_genes, uint64_t n_residues, uint32_t k,
+int32_t pdp_dict_size(uint32_t n_genes, uint64_t n_residues, uint32_t k, uint32_t alphabet,
                       uint64_t *arena_bytes, uint64_t *ws_bytes);
 
 /* Points the arrays of *out into a caller-allocated device arena (256-byte
  * aligned, at least pdp_dict_size's arena_bytes).  Enqueues nothing.
  * Errors: PDP_E_INVAL, PDP_E_WORKSPACE (arena too small), as pdp_dict_size. */
 int32_t pdp_dict_bind(void *arena, uint64_t arena_bytes, uint32_t n_genes, uint64_t n_residues,
-                      uint32_t k, pdp_dict *out);
+                      uint32_t k, uint32_t alphabet, pdp_dict *out);
 
 /* Builds the dictionary of genome g into d (bound with the same n_genes,
- * n_residues and k).  ws is device scratch of pdp_dict_size's ws_bytes.
+ * n_residues, k and alphabet).  ws is device scratch of pdp_dict_size's ws_bytes.
  * Gene i keeps index i.  Device errors (in d->status): PDP_E_ALPHABET,
  * PDP_E_LIMIT (a gene with more than PDP_MAX_WINDOWS windows).
  * Errors: PDP_E_INVAL (sizes differ from the bind), PDP_E_WORKSPACE, PDP_E_HIP. */
@@ -219,7 +239,7 @@ typedef struct pdp_params {
  * one work-group per item. */
 #define PDP_PARAM_PERSISTENT 1u
 
-/* One unit of work: genomes a and b (same k).  flags select the outputs. */
+/* One unit of work: genomes a and b (same k and alphabet).  flags select the outputs. */
 #define PDP_TASK_AB 1u   /* best hits of a's genes in b */
 #define PDP_TASK_BA 2u   /* best hits of b's genes in a */
 #define PDP_TASK_BBH 4u  /* bidirectional best hits of (a, b); needs AB and BA */
@@ -250,7 +270,7 @@ typedef struct pdp_plan_info {
  * laid out task by task: first a's genes (if AB), then b's genes (if BA); BBH
  * rows are a's genes of every task with PDP_TASK_BBH, task by task.
  * pdp_plan_rows gives each task's first row in both outputs.  Host only.
- * Errors: PDP_E_INVAL (null, k mismatch, BBH without AB|BA), PDP_E_LIMIT. */
+ * Errors: PDP_E_INVAL (null, k or alphabet mismatch, BBH without AB|BA), PDP_E_LIMIT. */
 int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_params *params, pdp_plan **out);
 int32_t pdp_plan_info_get(const pdp_plan *plan, pdp_plan_info *info);
 /* For task t: first row of its AB rows, of its BA rows (in bh), and of its BBH
@@ -366,6 +386,8 @@ typedef struct pdp_server_config {
     uint64_t budget_bytes;  /* device bytes for requests in flight (at most arena_bytes) */
     uint32_t slots;         /* requests in flight at most, 1..64 */
     uint32_t k;             /* k of every resident and request */
+    uint32_t alphabet;      /* pdp_alphabet of every resident and request */
+    uint32_t reserved;
     pdp_params params;      /* pair-path parameters (inc_capacity is managed per request) */
 } pdp_server_config;
 
@@ -400,7 +422,7 @@ typedef struct pdp_server_stats {
     uint32_t inflight, peak_inflight;
 } pdp_server_stats;
 
-/* residents: dictionaries built with cfg->k, borrowed until pdp_server_destroy.
+/* residents: dictionaries built with cfg->k and cfg->alphabet, borrowed until pdp_server_destroy.
  * arena: caller device memory (256-byte aligned) of which budget_bytes are used.
  * Errors: PDP_E_INVAL, PDP_E_WORKSPACE, PDP_E_HIP. */
 int32_t pdp_server_create(const pdp_server_config *cfg, const pdp_dict *const *residents, uint32_t n_residents,

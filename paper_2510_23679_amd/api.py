@@ -41,9 +41,10 @@ def k_rule(total: int, alphabet: int = 20, mode: int = 0) -> int:
     return int(k.value)
 
 
-def dict_size(n_genes: int, n_residues: int, k: int) -> Tuple[int, int]:
+def dict_size(n_genes: int, n_residues: int, k: int, alphabet: str = "aa") -> Tuple[int, int]:
     arena, ws = B.u64(0), B.u64(0)
-    check(lib().pdp_dict_size(int(n_genes), int(n_residues), int(k), C.byref(arena), C.byref(ws)), "pdp_dict_size")
+    check(lib().pdp_dict_size(int(n_genes), int(n_residues), int(k), B.alphabet_id(alphabet), C.byref(arena),
+                              C.byref(ws)), "pdp_dict_size")
     return int(arena.value), int(ws.value)
 
 
@@ -76,9 +77,12 @@ def _view(arena: torch.Tensor, ptr: int, count: int, dtype: torch.dtype) -> torc
 
 
 class DeviceGenome:
-    """A genome's residues (ASCII) and gene offsets in device memory."""
+    """A genome's letters (ASCII) and gene offsets in device memory; alphabet "aa" (amino
+    acids) or "nt" (nucleotides)."""
 
-    def __init__(self, residues: np.ndarray, offsets: np.ndarray):
+    def __init__(self, residues: np.ndarray, offsets: np.ndarray, alphabet: str = "aa"):
+        B.alphabet_id(alphabet)
+        self.alphabet = alphabet
         dev = _device()
         res = np.ascontiguousarray(residues, dtype=np.uint8)
         off = np.ascontiguousarray(offsets, dtype=np.uint64)
@@ -89,7 +93,7 @@ class DeviceGenome:
 
     @classmethod
     def of(cls, genome) -> "DeviceGenome":
-        return cls(genome.residues, genome.offsets)
+        return cls(genome.residues, genome.offsets, getattr(genome, "alphabet", "aa"))
 
     def struct(self) -> B.pdp_genome:
         return B.pdp_genome(self.residues.data_ptr(), self.offsets.data_ptr(), self.n_genes, 0, self.n_residues)
@@ -109,14 +113,15 @@ def new_status() -> torch.Tensor:
 class Dictionary:
     """The k-mer dictionary of one genome (multiplicity vectors + inverted index), on device."""
 
-    def __init__(self, n_genes: int, n_residues: int, k: int):
-        arena_bytes, ws_bytes = dict_size(n_genes, n_residues, k)
+    def __init__(self, n_genes: int, n_residues: int, k: int, alphabet: str = "aa"):
+        arena_bytes, ws_bytes = dict_size(n_genes, n_residues, k, alphabet)
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=_device())
         self.d = B.pdp_dict()
         check(lib().pdp_dict_bind(self.arena.data_ptr(), arena_bytes, int(n_genes), int(n_residues), int(k),
-                                  C.byref(self.d)), "pdp_dict_bind")
+                                  B.alphabet_id(alphabet), C.byref(self.d)), "pdp_dict_bind")
         self.ws_bytes = ws_bytes
         self.k = int(k)
+        self.alphabet = alphabet
         self.n_genes = int(n_genes)
         self.n_residues = int(n_residues)
         self.genome: Optional[DeviceGenome] = None
@@ -125,7 +130,7 @@ class Dictionary:
     def build_from(cls, genome, k: int, ws: Optional[Workspace] = None,
                    stream: Optional[torch.cuda.Stream] = None) -> "Dictionary":
         dg = genome if isinstance(genome, DeviceGenome) else DeviceGenome.of(genome)
-        d = cls(dg.n_genes, dg.n_residues, k)
+        d = cls(dg.n_genes, dg.n_residues, k, dg.alphabet)
         d.build(dg, ws, stream)
         return d
 
@@ -170,7 +175,7 @@ class DictionaryBatch:
     def __init__(self, genomes: Sequence[DeviceGenome], k, ws: Optional[Workspace] = None):
         ks = list(k) if isinstance(k, (list, tuple)) else [int(k)] * len(genomes)
         self.genomes = list(genomes)
-        self.dicts = [Dictionary(g.n_genes, g.n_residues, kk) for g, kk in zip(self.genomes, ks)]
+        self.dicts = [Dictionary(g.n_genes, g.n_residues, kk, g.alphabet) for g, kk in zip(self.genomes, ks)]
         n = len(self.genomes)
         self._g = (B.pdp_genome * n)(*[g.struct() for g in self.genomes])
         self._d = (C.POINTER(B.pdp_dict) * n)(*[C.pointer(d.d) for d in self.dicts])
@@ -545,7 +550,9 @@ class Server:
         self.residents = list(residents)
         self.k = self.residents[0].k
         self.arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device=_device())
-        cfg = B.pdp_server_config(int(budget_bytes), int(slots), self.k, prm or params())
+        self.alphabet = getattr(self.residents[0], "alphabet", "aa")
+        cfg = B.pdp_server_config(int(budget_bytes), int(slots), self.k, B.alphabet_id(self.alphabet), 0,
+                                  prm or params())
         arr = (C.POINTER(B.pdp_dict) * len(self.residents))(*[C.pointer(d.d) for d in self.residents])
         self.h = B.vp()
         torch.cuda.synchronize()  # residents built on torch streams must be complete before other streams read them

@@ -31,6 +31,18 @@ PDP_TASK_BA = 2
 PDP_TASK_BBH = 4
 PDP_PARAM_PERSISTENT = 1
 PDP_K_MAX = 12
+PDP_K_MAX_NT = 31
+PDP_ALPHA_AMINO = 0
+PDP_ALPHA_NUCLEOTIDE = 1
+# alphabet names used by the Python side
+ALPHABET_IDS = {"aa": PDP_ALPHA_AMINO, "nt": PDP_ALPHA_NUCLEOTIDE}
+
+
+def alphabet_id(alphabet) -> int:
+    """pdp_alphabet value of "aa" (amino acids) or "nt" (nucleotides)."""
+    if alphabet not in ALPHABET_IDS:
+        raise ValueError(f"unknown alphabet {alphabet!r} (expected 'aa' or 'nt')")
+    return ALPHABET_IDS[alphabet]
 PDP_MAX_WINDOWS = 65535
 
 # kernels that pdp_plan_timer_start can time
@@ -47,7 +59,7 @@ class pdp_genome(C.Structure):
 
 class pdp_dict(C.Structure):
     _fields_ = [("n_genes", u32), ("k", u32), ("capacity", u64), ("n_buckets", u32), ("key_shift", u32),
-                ("nwin", vp), ("mv_ptr", vp), ("mv_code", vp), ("mv_cnt", vp), ("ix_dir", vp),
+                ("alphabet", u32), ("lead", u32), ("nwin", vp), ("mv_ptr", vp), ("mv_code", vp), ("mv_cnt", vp), ("ix_dir", vp),
                 ("ix_code", vp), ("ix_gene", vp), ("ix_cnt", vp), ("ix_key", vp), ("status", vp)]
 
 
@@ -81,7 +93,8 @@ class pdp_tune_result(C.Structure):
 
 
 class pdp_server_config(C.Structure):
-    _fields_ = [("budget_bytes", u64), ("slots", u32), ("k", u32), ("params", pdp_params)]
+    _fields_ = [("budget_bytes", u64), ("slots", u32), ("k", u32), ("alphabet", u32), ("reserved", u32),
+                ("params", pdp_params)]
 
 
 class pdp_request_done(C.Structure):
@@ -111,8 +124,8 @@ SIGNATURES = {
     "pdp_strerror": (C.c_char_p, [i32]),
     "pdp_last_error": (C.c_char_p, []),
     "pdp_k_rule": (i32, [u64, u32, i32, C.POINTER(u32)]),
-    "pdp_dict_size": (i32, [u32, u64, u32, C.POINTER(u64), C.POINTER(u64)]),
-    "pdp_dict_bind": (i32, [vp, u64, u32, u64, u32, C.POINTER(pdp_dict)]),
+    "pdp_dict_size": (i32, [u32, u64, u32, u32, C.POINTER(u64), C.POINTER(u64)]),
+    "pdp_dict_bind": (i32, [vp, u64, u32, u64, u32, u32, C.POINTER(pdp_dict)]),
     "pdp_dict_build": (i32, [C.POINTER(pdp_genome), C.POINTER(pdp_dict), vp, u64, vp]),
     "pdp_dict_build_many_ws_size": (i32, [C.POINTER(pdp_genome), C.POINTER(C.POINTER(pdp_dict)), u32, C.POINTER(u64)]),
     "pdp_dict_build_many": (i32, [C.POINTER(pdp_genome), C.POINTER(C.POINTER(pdp_dict)), u32, vp, u64, vp]),
@@ -158,7 +171,7 @@ class PdpError(RuntimeError):
         self.code = code
 
 
-ABI_VERSION = 3  # the layout of the structures above; include/pdp.h defines the same number
+ABI_VERSION = 4  # the layout of the structures above; include/pdp.h defines the same number
 
 
 def lib():

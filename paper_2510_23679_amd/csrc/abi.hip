@@ -78,10 +78,10 @@ const char *pdp_strerror(int32_t code) {
     switch (code) {
     case PDP_OK: return "ok";
     case PDP_E_INVAL: return "invalid argument";
-    case PDP_E_KRANGE: return "k out of range (1..12)";
+    case PDP_E_KRANGE: return "k out of range for the alphabet (amino acids 1..12, nucleotides 1..31)";
     case PDP_E_WORKSPACE: return "workspace or arena too small";
     case PDP_E_CAPACITY: return "output or scratch capacity too small";
-    case PDP_E_ALPHABET: return "residue outside the 20 amino acids";
+    case PDP_E_ALPHABET: return "letter outside the dictionary's alphabet, or unknown alphabet";
     case PDP_E_HIP: return "HIP runtime error";
     case PDP_E_BUDGET: return "request exceeds the admission budget";
     case PDP_E_LIMIT: return "size beyond a documented limit";
@@ -114,15 +114,17 @@ int32_t pdp_k_rule(uint64_t total, uint32_t alphabet, int32_t mode, uint32_t *k_
 
 // ------------------------------------------------------------ dictionary
 
-static int32_t dict_check(uint32_t n_genes, uint64_t n_residues, uint32_t k) {
-    if (k == 0 || k > PDP_K_MAX) return fail(PDP_E_KRANGE, "k = %u outside 1..%u", k, PDP_K_MAX);
+static int32_t dict_check(uint32_t n_genes, uint64_t n_residues, uint32_t k, uint32_t alphabet) {
+    if (!alpha_known(alphabet)) return fail(PDP_E_ALPHABET, "unknown alphabet %u", alphabet);
+    const uint32_t kmax = alpha_spec(alphabet).k_max;
+    if (k == 0 || k > kmax) return fail(PDP_E_KRANGE, "k = %u outside 1..%u for this alphabet", k, kmax);
     if (n_genes > PDP_MAX_GENES) return fail(PDP_E_LIMIT, "%u genes exceed %u", n_genes, PDP_MAX_GENES);
     if (n_residues >= (1ull << 32)) return fail(PDP_E_LIMIT, "%llu residues exceed 2^32 - 1", (unsigned long long)n_residues);
     return PDP_OK;
 }
 
-static uint64_t dict_arena_bytes(uint32_t n_genes, uint64_t n_residues, uint32_t k) {
-    const uint64_t A = 256, cap = n_residues + 1, nb = n_buckets_for(k);
+static uint64_t dict_arena_bytes(uint32_t n_genes, uint64_t n_residues, uint32_t k, uint32_t alphabet) {
+    const uint64_t A = 256, cap = n_residues + 1, nb = n_buckets_for(k, alphabet);
     uint64_t s = 0;
     s += align_up(4 * (uint64_t(n_genes) + 1), A);  // nwin
     s += align_up(4 * (uint64_t(n_genes) + 1), A);  // mv_ptr
@@ -137,24 +139,26 @@ static uint64_t dict_arena_bytes(uint32_t n_genes, uint64_t n_residues, uint32_t
     return s;
 }
 
-int32_t pdp_dict_size(uint32_t n_genes, uint64_t n_residues, uint32_t k, uint64_t *arena_bytes, uint64_t *ws_bytes) {
-    int32_t rc = dict_check(n_genes, n_residues, k);
+int32_t pdp_dict_size(uint32_t n_genes, uint64_t n_residues, uint32_t k, uint32_t alphabet, uint64_t *arena_bytes,
+                      uint64_t *ws_bytes) {
+    int32_t rc = dict_check(n_genes, n_residues, k, alphabet);
     if (rc) return rc;
-    if (arena_bytes) *arena_bytes = dict_arena_bytes(n_genes, n_residues, k);
+    if (arena_bytes) *arena_bytes = dict_arena_bytes(n_genes, n_residues, k, alphabet);
     if (ws_bytes) {
-        *ws_bytes = build_ws_bytes(single_build_shape(n_genes, n_residues, k));
+        *ws_bytes = build_ws_bytes(single_build_shape(n_genes, n_residues, k, alphabet));
     }
     return ok();
 }
 
-int32_t pdp_dict_bind(void *arena, uint64_t arena_bytes, uint32_t n_genes, uint64_t n_residues, uint32_t k, pdp_dict *out) {
+int32_t pdp_dict_bind(void *arena, uint64_t arena_bytes, uint32_t n_genes, uint64_t n_residues, uint32_t k,
+                      uint32_t alphabet, pdp_dict *out) {
     if (!arena || !out) return fail(PDP_E_INVAL, "pdp_dict_bind: null pointer");
     if (reinterpret_cast<uintptr_t>(arena) % 256) return fail(PDP_E_INVAL, "pdp_dict_bind: arena not 256-byte aligned");
-    int32_t rc = dict_check(n_genes, n_residues, k);
+    int32_t rc = dict_check(n_genes, n_residues, k, alphabet);
     if (rc) return rc;
-    const uint64_t need = dict_arena_bytes(n_genes, n_residues, k);
+    const uint64_t need = dict_arena_bytes(n_genes, n_residues, k, alphabet);
     if (arena_bytes < need) return fail(PDP_E_WORKSPACE, "arena %llu < %llu bytes", (unsigned long long)arena_bytes, (unsigned long long)need);
-    const uint64_t A = 256, cap = n_residues + 1, nb = n_buckets_for(k);
+    const uint64_t A = 256, cap = n_residues + 1, nb = n_buckets_for(k, alphabet);
     char *p = static_cast<char *>(arena);
     auto take = [&](uint64_t bytes) {
         char *q = p;
@@ -176,7 +180,9 @@ int32_t pdp_dict_bind(void *arena, uint64_t arena_bytes, uint32_t n_genes, uint6
     d.ix_gene = reinterpret_cast<uint32_t *>(take(4 * cap));
     d.ix_cnt = reinterpret_cast<uint32_t *>(take(4 * cap));
     d.ix_key = reinterpret_cast<uint32_t *>(take(4 * cap));
-    d.key_shift = key_shift_for(n_genes, k);
+    d.key_shift = key_shift_for(n_genes, k, alphabet);
+    d.alphabet = alphabet;
+    d.lead = lead_letters(k, alphabet);
     d.status = reinterpret_cast<pdp_status *>(take(sizeof(pdp_status)));
     *out = d;
     return ok();
@@ -190,7 +196,9 @@ static int32_t build_check(const pdp_genome *genomes, pdp_dict *const *dicts, ui
         const pdp_dict *d = dicts[i];
         if (!d) return fail(PDP_E_INVAL, "dictionary %u is null", i);
         if (!g->gene_off || (g->n_residues && !g->residues)) return fail(PDP_E_INVAL, "genome %u: null arrays", i);
-        int32_t rc = dict_check(g->n_genes, g->n_residues, d->k);
+        int32_t rc = dict_check(g->n_genes, g->n_residues, d->k, d->alphabet);
+        if (!rc && (d->lead != lead_letters(d->k, d->alphabet) || d->n_buckets != n_buckets_for(d->k, d->alphabet)))
+            rc = fail(PDP_E_INVAL, "dictionary %u: fields changed since pdp_dict_bind", i);
         if (rc) return rc;
         if (g->n_genes != d->n_genes || g->n_residues + 1 > d->capacity)
             return fail(PDP_E_INVAL, "genome %u (%u genes, %llu residues) does not match its dictionary (%u genes, capacity %llu)",
@@ -241,6 +249,8 @@ static DevDict dev_dict(const pdp_dict *d) {
     x.n_buckets = d->n_buckets;
     x.k = d->k;
     x.key_shift = d->key_shift;
+    x.bits = alpha_spec(d->alphabet).bits;
+    x.lead = d->lead;
     return x;
 }
 
@@ -280,8 +290,10 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     for (uint32_t t = 0; t < n_tasks; ++t) {
         const pdp_task &tk = tasks[t];
         if (!tk.a || !tk.b) return bail(fail(PDP_E_INVAL, "task %u: null dictionary", t));
-        if (tk.a->k != tk.b->k || tk.a->n_buckets != tk.b->n_buckets)
-            return bail(fail(PDP_E_INVAL, "task %u: dictionaries built with different k (%u, %u)", t, tk.a->k, tk.b->k));
+        if (tk.a->k != tk.b->k || tk.a->alphabet != tk.b->alphabet || tk.a->lead != tk.b->lead ||
+            tk.a->n_buckets != tk.b->n_buckets)
+            return bail(fail(PDP_E_INVAL, "task %u: dictionaries built with different k or alphabet (k %u/%u, alphabet %u/%u)",
+                             t, tk.a->k, tk.b->k, tk.a->alphabet, tk.b->alphabet));
         uint32_t flags = tk.flags & (PDP_TASK_AB | PDP_TASK_BA | PDP_TASK_BBH);
         if (flags & PDP_TASK_BBH) flags |= PDP_TASK_AB | PDP_TASK_BA;
         if (!flags) return bail(fail(PDP_E_INVAL, "task %u: no output selected", t));

@@ -40,8 +40,25 @@ __device__ __forceinline__ uint32_t sym_of(uint32_t byte) {
     return s == 31u ? kInvalidSym : s;
 }
 
-// Leading-residue bucket of a k-mer code: the first min(k,4) residues read as a base-20 number.
-__device__ __forceinline__ uint32_t bucket_of(uint64_t code, uint32_t k, uint32_t lead) {
+// Nucleotide letter -> 2-bit symbol (A=0, C=1, G=2, T=3), kInvalidSym otherwise: a mask of
+// the four letters among the 26 and their symbols 2 bits each at the letter's index.
+constexpr uint32_t kNtMask = (1u << ('A' - 'A')) | (1u << ('C' - 'A')) | (1u << ('G' - 'A')) | (1u << ('T' - 'A'));
+constexpr uint64_t kNtWord = (1ull << (2 * ('C' - 'A'))) | (2ull << (2 * ('G' - 'A'))) | (3ull << (2 * ('T' - 'A')));
+
+__device__ __forceinline__ uint32_t sym_nt(uint32_t byte) {
+    const uint32_t i = byte - 'A';
+    if (i >= 26u || !((kNtMask >> i) & 1u)) return kInvalidSym;
+    return static_cast<uint32_t>(kNtWord >> (2u * i)) & 3u;
+}
+
+// Symbol of a letter in a dictionary whose symbols are `bits` wide (5: amino acids, 2: nucleotides).
+__device__ __forceinline__ uint32_t sym_in(uint32_t byte, uint32_t bits) { return bits == 2u ? sym_nt(byte) : sym_of(byte); }
+
+// Leading-letter bucket of a k-mer code: for nucleotides the leading 2*lead bits (the code
+// is the k-mer's base-4 value), for amino acids the first `lead` residues read as a base-20
+// number.
+__device__ __forceinline__ uint32_t bucket_of(uint64_t code, uint32_t k, uint32_t lead, uint32_t bits) {
+    if (bits == 2u) return static_cast<uint32_t>(code >> (2u * (k - lead)));
     uint32_t b = 0;
     for (uint32_t i = 0; i < lead; ++i) b = b * 20u + static_cast<uint32_t>((code >> (5u * (k - 1u - i))) & 31u);
     return b;

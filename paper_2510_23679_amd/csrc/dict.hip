@@ -1,7 +1,9 @@
 // k-mer dictionary build for one or many genomes on gfx950, in one set of launches.
 //
 // 1. k_mv_wave: one wave per gene encodes every window g[p..p+k-1] into a
-//    5-bit-per-residue code, sorts the codes in registers (a bitonic network of
+//    code of 5 bits per amino acid or 2 per nucleotide (a lane's windows are
+//    consecutive, so each code is the previous one shifted by one letter),
+//    sorts the codes in registers (a bitonic network of
 //    kMvWaveCap keys, eight per lane, lanes exchanging by shuffles) and
 //    run-length encodes them into the gene's multiplicity vector (Multiplicity
 //    vector building phase, Alg. 1: group equal identifiers, count, ascending
@@ -149,17 +151,20 @@ template <uint32_t E>
 __device__ __forceinline__ void mv_wave_gene(const DevBuild &B, const uint8_t *sym, uint16_t *hp, uint64_t o,
                                              uint32_t nw, uint32_t *cnt_out) {
     const uint32_t lane = lane_id();
-    const uint32_t k = B.k;
+    const uint32_t k = B.k, bits = B.bits;
+    const uint64_t mask = (1ull << (bits * k)) - 1ull;  // bits * k <= 62
     uint64_t key[E];
+    // the lane's windows p0 .. p0+E-1 are consecutive: the first k-1 letters once, then one
+    // letter per window
+    const uint32_t p0 = lane * E;
+    uint64_t c = 0;
+    if (p0 < nw)
+        for (uint32_t j = 0; j + 1 < k; ++j) c = (c << bits) | sym[p0 + j];
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) {
-        const uint32_t p = lane * E + e;
-        uint64_t c = ~0ull;  // past the windows: sorts last
-        if (p < nw) {
-            c = 0;
-            for (uint32_t j = 0; j < k; ++j) c = (c << 5) | sym[p + j];
-        }
-        key[e] = c;
+        const uint32_t p = p0 + e;
+        if (p < nw) c = ((c << bits) | sym[p + k - 1]) & mask;
+        key[e] = p < nw ? c : ~0ull;  // past the windows: sorts last
     }
     wave_bitonic_sort<E>(key);
     const uint64_t before = __shfl_up(key[E - 1], 1, kWave);
@@ -196,7 +201,7 @@ __device__ __forceinline__ void mv_wave_gene(const DevBuild &B, const uint8_t *s
 __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restrict__ table, uint32_t n_genomes,
                                                         uint32_t total_genes, uint32_t *__restrict__ dcnt,
                                                         uint64_t *__restrict__ mid_list, uint32_t *__restrict__ counters) {
-    __shared__ uint8_t sym_all[kMvWaves][kMvWaveCap + PDP_K_MAX];
+    __shared__ uint8_t sym_all[kMvWaves][kMvWaveCap + kKMaxAll];
     __shared__ uint16_t hp_all[kMvWaves][kMvWaveCap + 1];
     const uint32_t w = threadIdx.x / kWave, lane = lane_id();
     const uint32_t G = blockIdx.x * kMvWaves + w;
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restri
         for (uint32_t it = 0; it < 4; ++it) {
             const uint32_t p = base + lane + it * kWave;
             if (p >= len) continue;
-            uint32_t x = sym_of(res[it]);
+            uint32_t x = sym_in(res[it], B.bits);
             if (x == kInvalidSym) {
                 raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
                 x = 0;
@@ -247,7 +252,7 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_mid(const DevBuild *__restric
                                                        const uint64_t *__restrict__ mid_list,
                                                        uint64_t *__restrict__ long_list, uint32_t *__restrict__ counters) {
     __shared__ uint64_t keys[kMvSortCap];
-    __shared__ uint8_t sym[kMvSortCap + PDP_K_MAX];
+    __shared__ uint8_t sym[kMvSortCap + kKMaxAll];
     __shared__ uint32_t tmp[kMvThreads / kWave + 1];
     const uint32_t n_mid = counters[1];
     const uint32_t tid = threadIdx.x;
@@ -256,14 +261,14 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_mid(const DevBuild *__restric
         const DevBuild &B = table[item >> 32];
         const uint32_t g = static_cast<uint32_t>(item);
         const uint32_t G = B.gene_base + g;
-        const uint32_t k = B.k;
+        const uint32_t k = B.k, bits = B.bits;
         const uint64_t o = B.off[g];
         const uint64_t len = B.off[g + 1] - o;
         const uint32_t nw = static_cast<uint32_t>(len - k + 1);  // checked by k_mv_wave
         const bool in_lds = nw <= kMvSortCap;
         const uint8_t *res = B.res;
         if (in_lds) {  // uniform: loads of a thread issued together, then mapped
-            constexpr uint32_t kIters = (kMvSortCap + PDP_K_MAX + kMvThreads - 1) / kMvThreads;
+            constexpr uint32_t kIters = (kMvSortCap + kKMaxAll + kMvThreads - 1) / kMvThreads;
             uint32_t rv[kIters];
 #pragma unroll
             for (uint32_t it = 0; it < kIters; ++it) {
@@ -274,7 +279,7 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_mid(const DevBuild *__restric
             for (uint32_t it = 0; it < kIters; ++it) {
                 const uint32_t p = tid + it * kMvThreads;
                 if (p >= len) continue;
-                uint32_t x = sym_of(rv[it]);
+                uint32_t x = sym_in(rv[it], bits);
                 if (x == kInvalidSym) {
                     raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
                     x = 0;
@@ -283,17 +288,24 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_mid(const DevBuild *__restric
             }
         } else {
             for (uint64_t p = tid; p < len; p += kMvThreads)
-                if (sym_of(res[o + p]) == kInvalidSym) raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
+                if (sym_in(res[o + p], bits) == kInvalidSym) raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
         }
         if (!in_lds) {
             if (tid == 0) long_list[atomicAdd(&counters[0], 1u)] = item;
             continue;  // uniform: the same item for the whole work-group
         }
         __syncthreads();
-        for (uint32_t p = tid; p < nw; p += kMvThreads) {
+        {  // thread tid encodes a run of consecutive windows, one new letter per window
+            const uint64_t mask = (1ull << (bits * k)) - 1ull;
+            const uint32_t per = (nw + kMvThreads - 1) / kMvThreads;
+            const uint32_t p0 = tid * per, p1 = min(nw, p0 + per);
             uint64_t c = 0;
-            for (uint32_t j = 0; j < k; ++j) c = (c << 5) | sym[p + j];
-            keys[p] = c;
+            if (p0 < p1)
+                for (uint32_t j = 0; j + 1 < k; ++j) c = (c << bits) | sym[p0 + j];
+            for (uint32_t p = p0; p < p1; ++p) {
+                c = ((c << bits) | sym[p + k - 1]) & mask;
+                keys[p] = c;
+            }
         }
         __syncthreads();
         wg_network_sort(nw, [&](uint32_t lo, uint32_t hi) {
@@ -350,8 +362,8 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_long(const DevBuild *__restri
         for (uint32_t p = tid; p < nw; p += kMvThreads) {
             uint64_t c = 0;
             for (uint32_t j = 0; j < k; ++j) {
-                uint32_t s = sym_of(B.res[o + p + j]);
-                c = (c << 5) | (s == kInvalidSym ? 0u : s);
+                uint32_t s = sym_in(B.res[o + p + j], B.bits);
+                c = (c << B.bits) | (s == kInvalidSym ? 0u : s);
             }
             w[p] = c;
         }
@@ -467,7 +479,7 @@ __global__ __launch_bounds__(256) void k_ix_hist(const DevBuild *__restrict__ ta
         }
 #pragma unroll
         for (uint32_t q = 0; q < kIxBatch; ++q)
-            if (base + q * 256 + threadIdx.x < e1) atomicAdd(&h[bucket_of(c[q], B.k, B.lead) >> B.hshift], 1u);
+            if (base + q * 256 + threadIdx.x < e1) atomicAdd(&h[bucket_of(c[q], B.k, B.lead, B.bits) >> B.hshift], 1u);
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < B.nh; i += blockDim.x) hist[B.hist_base + i * B.nblk + j] = h[i];
@@ -502,7 +514,7 @@ __global__ __launch_bounds__(256) void k_ix_place(const DevBuild *__restrict__ t
 #pragma unroll
         for (uint32_t q = 0; q < kIxBatch; ++q) {
             if (base + q * 256 + threadIdx.x >= e1) continue;
-            const uint32_t pos = atomicAdd(&cur[bucket_of(c[q], B.k, B.lead) >> B.hshift], 1u);
+            const uint32_t pos = atomicAdd(&cur[bucket_of(c[q], B.k, B.lead, B.bits) >> B.hshift], 1u);
             // one 16-byte record per entry: a single scattered store instead of three
             B.ix_tmp[pos] = make_uint4(static_cast<uint32_t>(c[q]), static_cast<uint32_t>(c[q] >> 32), gn[q], ct[q]);
         }
@@ -538,7 +550,7 @@ __device__ void bin_directory(const DevBuild &B, CP code, uint32_t n, uint32_t l
         uint32_t l = 0, r = n;
         while (l < r) {
             const uint32_t mid = (l + r) >> 1;
-            if (bucket_of(code[mid], B.k, B.lead) < b) l = mid + 1;
+            if (bucket_of(code[mid], B.k, B.lead, B.bits) < b) l = mid + 1;
             else r = mid;
         }
         B.ix_dir[b] = lo + l;
@@ -547,10 +559,10 @@ __device__ void bin_directory(const DevBuild &B, CP code, uint32_t n, uint32_t l
 
 __device__ __forceinline__ uint64_t rec_code(const uint4 &r) { return (static_cast<uint64_t>(r.y) << 32) | r.x; }
 
-// Packed join key of an index entry: the code's trailing residues (the leading ones are
+// Packed join key of an index entry: the code's trailing letters (the leading ones are
 // the bucket) above the gene.
 __device__ __forceinline__ uint32_t entry_key(const DevBuild &B, uint64_t code, uint32_t gene) {
-    const uint32_t tb = 5 * (B.k - B.lead);
+    const uint32_t tb = B.bits * (B.k - B.lead);
     const uint64_t tail = tb ? code & ((1ull << tb) - 1) : 0ull;
     return static_cast<uint32_t>(tail << B.key_shift) | gene;
 }
@@ -623,7 +635,7 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
         for (uint32_t q = 0; q < kIxPer; ++q) {
             const uint32_t i = q * 256 + threadIdx.x;
             if (i < n) {
-                bk[q] = bucket_of(rec_code(r[q]), B.k, B.lead) - b0;
+                bk[q] = bucket_of(rec_code(r[q]), B.k, B.lead, B.bits) - b0;
                 slot[q] = atomicAdd(&s_bstart[bk[q]], 1u);
             }
         }
@@ -755,13 +767,13 @@ uint64_t build_ws_bytes(const BuildShape &s) {
 
 BuildShape build_shape(const pdp_genome *g, const pdp_dict *const *d, uint32_t n) { return shape_of(g, d, n); }
 
-BuildShape single_build_shape(uint32_t n_genes, uint64_t n_residues, uint32_t k) {
+BuildShape single_build_shape(uint32_t n_genes, uint64_t n_residues, uint32_t k, uint32_t alphabet) {
     pdp_genome g{};
     g.n_genes = n_genes;
     g.n_residues = n_residues;
     pdp_dict d{};
     d.k = k;
-    d.n_buckets = n_buckets_for(k);
+    d.n_buckets = n_buckets_for(k, alphabet);
     const pdp_dict *dp = &d;
     return shape_of(&g, &dp, 1);
 }
@@ -806,7 +818,8 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
             B.n_genes = G.n_genes;
             B.k = D.k;
             B.nb = D.n_buckets;
-            B.lead = lead_residues(D.k);
+            B.lead = D.lead;
+            B.bits = alpha_spec(D.alphabet).bits;
             B.hshift = bin_shift(D.n_buckets, cap);
             B.nh = static_cast<uint32_t>((uint64_t(D.n_buckets) + (1ull << B.hshift) - 1) >> B.hshift);
             B.nblk = static_cast<uint32_t>((cap + kIxBlock - 1) / kIxBlock);

@@ -17,7 +17,8 @@ namespace pdp {
 
 // ---------------------------------------------------------------- sizes
 constexpr uint32_t kScanItems = 4096;        // elements per scan work-group (256 threads x 16)
-constexpr uint32_t kMvSortCap = 2048;        // windows a gene may have to be sorted in LDS
+constexpr uint32_t kMvSortCap = 8192;        // windows a gene may have to be sorted in LDS
+constexpr uint32_t kKMaxAll = PDP_K_MAX_NT > PDP_K_MAX ? PDP_K_MAX_NT : PDP_K_MAX;  // k bound over alphabets
 constexpr uint32_t kIxBlock = 8192;          // index entries per histogram block
 constexpr uint32_t kIxBinTarget = 1024;      // average index entries per coarse bin
 constexpr uint32_t kIxBinLds = 2048;         // coarse bins up to this size are sorted in LDS
@@ -39,17 +40,31 @@ constexpr uint32_t kMaxTileLds = 160 * 1024 - 4096;  // gfx950 LDS per work-grou
 constexpr uint32_t kSlab = 4;                // best hits per row kept by the first tile pass
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
-inline uint32_t lead_residues(uint32_t k) { return k < 4 ? k : 4; }
-inline uint32_t n_buckets_for(uint32_t k) {
+
+// Per alphabet: bits of a letter's symbol, letters, leading letters of an index bucket
+// (amino acids: 20^4 = 160000 buckets; nucleotides: 4^9 = 262144, so that a bucket of a
+// genome holds a few entries either way), largest k.
+struct AlphaSpec {
+    uint32_t bits, sigma, lead_max, k_max;
+};
+inline bool alpha_known(uint32_t a) { return a == PDP_ALPHA_AMINO || a == PDP_ALPHA_NUCLEOTIDE; }
+inline AlphaSpec alpha_spec(uint32_t a) {
+    return a == PDP_ALPHA_NUCLEOTIDE ? AlphaSpec{2, 4, 9, PDP_K_MAX_NT} : AlphaSpec{5, 20, 4, PDP_K_MAX};
+}
+inline uint32_t lead_letters(uint32_t k, uint32_t a) {
+    const uint32_t m = alpha_spec(a).lead_max;
+    return k < m ? k : m;
+}
+inline uint32_t n_buckets_for(uint32_t k, uint32_t a) {
     uint32_t nb = 1;
-    for (uint32_t i = 0; i < lead_residues(k); ++i) nb *= 20;
+    for (uint32_t i = 0; i < lead_letters(k, a); ++i) nb *= alpha_spec(a).sigma;
     return nb;
 }
 // Gene bits of a dictionary's packed index keys, 0 when tail and gene do not fit 32 bits.
-inline uint32_t key_shift_for(uint32_t n_genes, uint32_t k) {
+inline uint32_t key_shift_for(uint32_t n_genes, uint32_t k, uint32_t a) {
     uint32_t gb = 1;
     while (gb < 32 && (1ull << gb) < n_genes) ++gb;
-    return 5 * (k - lead_residues(k)) + gb <= 32 ? gb : 0;
+    return alpha_spec(a).bits * (k - lead_letters(k, a)) + gb <= 32 ? gb : 0;
 }
 inline uint32_t scan_partials(uint64_t n) { return static_cast<uint32_t>((n + kScanItems - 1) / kScanItems) + 1; }
 
@@ -65,6 +80,8 @@ struct DevDict {
     uint32_t n_buckets;
     uint32_t k;
     uint32_t key_shift;
+    uint32_t bits;  // symbol bits per letter: 5 (amino acids) or 2 (nucleotides)
+    uint32_t lead;  // leading letters of a bucket
 };
 
 struct DevTask {
@@ -116,6 +133,7 @@ struct DevBuild {
     uint32_t *ix_gene, *ix_cnt;
     uint32_t *ix_key;     // packed keys, written when key_shift > 0
     uint32_t key_shift;
+    uint32_t bits;        // symbol bits per letter: 5 (amino acids) or 2 (nucleotides)
     pdp_status *status;
     uint64_t *slot_code;  // per gene g: sorted distinct codes at offset gene_off[g]
     uint32_t *slot_cnt;
@@ -126,7 +144,7 @@ struct BuildShape {
     uint64_t n_genomes, total_genes, total_residues, total_blocks, total_bins, total_hist, max_nh;
 };
 BuildShape build_shape(const pdp_genome *g, const pdp_dict *const *d, uint32_t n);
-BuildShape single_build_shape(uint32_t n_genes, uint64_t n_residues, uint32_t k);
+BuildShape single_build_shape(uint32_t n_genes, uint64_t n_residues, uint32_t k, uint32_t alphabet);
 uint64_t build_ws_bytes(const BuildShape &s);
 hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint32_t n, void *ws, hipStream_t s);
 

@@ -97,7 +97,7 @@ __device__ __forceinline__ void join_range(const DevTask &T, uint32_t a0, uint32
                                            const uint64_t *bc, const uint32_t *bg, const CN *bn,
                                            const uint32_t *bdir, uint32_t bl, uint32_t *tcount, uint2 *recs,
                                            uint64_t rec_cap) {
-    const uint32_t k = T.a.k, lead = k < 4 ? k : 4;
+    const uint32_t k = T.a.k, lead = T.a.lead, bits = T.a.bits;
     const bool ab = T.flags & 1u, ba = T.flags & 2u;
     const uint32_t s0 = T.tile_shift[0], s1 = T.tile_shift[1], t1 = T.tiles_n[0];
     constexpr uint32_t U = kJoinUnroll;
@@ -118,7 +118,7 @@ __device__ __forceinline__ void join_range(const DevTask &T, uint32_t a0, uint32
         for (uint32_t q = 0; q < U; ++q) {
             if (base + q * kJoinThreads + threadIdx.x >= a1) continue;
             const uint64_t c = code[q];
-            const uint32_t u = bucket_of(c, k, lead) - bl;
+            const uint32_t u = bucket_of(c, k, lead, bits) - bl;
             const uint32_t end = min(bdir[u + 1] - b0, nbe);  // the bucket lies inside the staged range
             uint32_t lo = min(bdir[u] - b0, end);
             uint32_t hi = end;

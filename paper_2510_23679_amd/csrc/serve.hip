@@ -153,7 +153,7 @@ namespace {
 
 uint64_t footprint(pdp_server *S, ServeRequest *r, uint64_t *plan_ws) {
     uint64_t arena = 0, bws = 0;
-    if (pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, &arena, &bws) != PDP_OK) return 0;
+    if (pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, S->cfg.alphabet, &arena, &bws) != PDP_OK) return 0;
     pdp_plan_info info;
     pdp_plan_info_get(r->plan, &info);
     *plan_ws = info.ws_bytes;
@@ -192,7 +192,7 @@ int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t
     uint8_t *res = reinterpret_cast<uint8_t *>(take(r->n_res + 1));
     uint64_t *off = reinterpret_cast<uint64_t *>(take(8 * (uint64_t(r->n_genes) + 1)));
     uint64_t arena = 0, bws = 0;
-    pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, &arena, &bws);
+    pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, S->cfg.alphabet, &arena, &bws);
     void *dict_mem = take(arena);
     void *scratch = take(std::max(bws, plan_ws));
     const uint64_t scratch_bytes = std::max(bws, plan_ws);
@@ -213,7 +213,7 @@ int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t
     r->bbh.den = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(r->bbh_cap, 1)));
     r->status = reinterpret_cast<pdp_status *>(take(sizeof(pdp_status)));
     // The dictionary descriptor must point at this allocation before the plan copies it.
-    int32_t rc = pdp_dict_bind(dict_mem, arena, r->n_genes, r->n_res, S->cfg.k, &r->dict);
+    int32_t rc = pdp_dict_bind(dict_mem, arena, r->n_genes, r->n_res, S->cfg.k, S->cfg.alphabet, &r->dict);
     if (rc) return rc;
     rc = make_plan(S, r);
     if (rc) return rc;
@@ -352,10 +352,10 @@ void worker_loop(pdp_server *S) {
             // A provisional plan gives the footprint: the descriptor is bound to a placeholder
             // address (planning reads only its sizes); the final plan is made once the memory is placed.
             uint64_t plan_ws = 0, bytes = 0, dict_bytes = 0, build_ws = 0;
-            int32_t rc = pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, &dict_bytes, &build_ws);
+            int32_t rc = pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, S->cfg.alphabet, &dict_bytes, &build_ws);
             if (rc == PDP_OK)
                 rc = pdp_dict_bind(reinterpret_cast<void *>(uintptr_t(256)), dict_bytes, r->n_genes, r->n_res, S->cfg.k,
-                                   &r->dict);
+                                   S->cfg.alphabet, &r->dict);
             if (rc == PDP_OK) rc = make_plan(S, r);
             if (rc == PDP_OK) bytes = footprint(S, r, &plan_ws);
             if (rc != PDP_OK || bytes == 0 || bytes > S->arena->size()) {
@@ -417,8 +417,8 @@ int32_t pdp_server_create(const pdp_server_config *cfg, const pdp_dict *const *r
     if (cfg->budget_bytes > arena_bytes) return api_fail(PDP_E_WORKSPACE, "budget larger than the arena");
     if (reinterpret_cast<uintptr_t>(arena) % 256) return api_fail(PDP_E_INVAL, "arena not 256-byte aligned");
     for (uint32_t i = 0; i < n_residents; ++i) {
-        if (!residents[i] || residents[i]->k != cfg->k)
-            return api_fail(PDP_E_INVAL, "resident %u: missing or built with another k", i);
+        if (!residents[i] || residents[i]->k != cfg->k || residents[i]->alphabet != cfg->alphabet)
+            return api_fail(PDP_E_INVAL, "resident %u: missing or built with another k or alphabet", i);
     }
     auto S = std::make_unique<pdp_server>();
     S->cfg = *cfg;

@@ -5,49 +5,57 @@ import numpy as np
 
 import oracle
 
-LEAD = 4
+# Layout of a dictionary per alphabet, as the C-ABI documents it: symbol bits per letter,
+# letters, and leading letters that name an index bucket.
+BITS = {"aa": 5, "nt": 2}
+SIGMA = {"aa": 20, "nt": 4}
+LEAD = {"aa": 4, "nt": 9}
 
 
-def gpu_code_to_base20(codes: np.ndarray, k: int) -> np.ndarray:
-    """The GPU packs residues 5 bits each; the oracle numbers k-mers in base 20.  Both are injective
-    on k-mers, so translating one into the other lets the two dictionaries be compared by content."""
+def gpu_code_to_id(codes: np.ndarray, k: int, alphabet: str = "aa") -> np.ndarray:
+    """The GPU packs letters 5 (amino acids) or 2 (nucleotides) bits each; the oracle numbers
+    k-mers in base 20 or 4.  Both are injective on k-mers, so translating one into the other
+    lets the two dictionaries be compared by content."""
+    bits, sigma = BITS[alphabet], SIGMA[alphabet]
     codes = codes.astype(np.uint64)
+    assert np.all((codes >> np.uint64(bits * k)) == 0), "bits set above the k letters of a code"
     out = np.zeros(codes.shape, dtype=np.uint64)
     for i in range(k):
-        sym = (codes >> np.uint64(5 * (k - 1 - i))) & np.uint64(31)
-        assert np.all(sym < 20), "a 5-bit residue symbol outside 0..19"
-        out = out * np.uint64(20) + sym
+        sym = (codes >> np.uint64(bits * (k - 1 - i))) & np.uint64((1 << bits) - 1)
+        assert np.all(sym < sigma), "a letter symbol outside the alphabet"
+        out = out * np.uint64(sigma) + sym
     return out
 
 
 def check_dictionary(host: dict, og: oracle.OracleGenome) -> None:
     """Every array of a GPU dictionary against the oracle's multiplicity vectors."""
-    k = og.k
+    k, al = og.k, og.alphabet
+    bits, sigma = BITS[al], SIGMA[al]
     assert np.array_equal(host["nwin"].astype(np.uint64), og.nwin), "windows per gene"
     assert np.array_equal(host["mv_ptr"].astype(np.uint64), og.ptr), "distinct k-mers per gene"
-    assert np.array_equal(gpu_code_to_base20(host["mv_code"], k), og.ids), "multiplicity-vector k-mers"
+    assert np.array_equal(gpu_code_to_id(host["mv_code"], k, al), og.ids), "multiplicity-vector k-mers"
     assert np.array_equal(host["mv_cnt"], og.cnt), "multiplicities"
     # inverted index: every (k-mer, gene, count) ordered by k-mer then gene
     genes = np.repeat(np.arange(og.n, dtype=np.uint32), np.diff(og.ptr).astype(np.int64))
     order = np.lexsort((genes, og.ids))
-    assert np.array_equal(gpu_code_to_base20(host["ix_code"], k), og.ids[order]), "index codes"
+    assert np.array_equal(gpu_code_to_id(host["ix_code"], k, al), og.ids[order]), "index codes"
     assert np.array_equal(host["ix_gene"], genes[order]), "index genes"
     assert np.array_equal(host["ix_cnt"], og.cnt[order]), "index counts"
-    lead = min(k, LEAD)
-    bucket = (og.ids // np.uint64(20 ** (k - lead))).astype(np.int64)
-    dir_ = np.zeros(20 ** lead + 1, dtype=np.int64)
+    lead = min(k, LEAD[al])
+    bucket = (og.ids // np.uint64(sigma ** (k - lead))).astype(np.int64)
+    dir_ = np.zeros(sigma ** lead + 1, dtype=np.int64)
     np.add.at(dir_, bucket + 1, 1)
     assert np.array_equal(host["ix_dir"].astype(np.int64), np.cumsum(dir_)), "index directory"
-    # packed join keys: the trailing k - lead residues, 5 bits each, above the gene's bits
+    # packed join keys: the trailing k - lead letters, `bits` each, above the gene's bits
     shift = max(1, (og.n - 1).bit_length()) if og.n > 1 else 1
-    tail_bits = 5 * (k - lead)
+    tail_bits = bits * (k - lead)
     assert ("ix_key" in host) == (tail_bits + shift <= 32), "packed keys present exactly when they fit"
     if "ix_key" in host:
-        rest = og.ids[order] % np.uint64(20 ** (k - lead))
+        rest = og.ids[order] % np.uint64(sigma ** (k - lead))
         tail = np.zeros(len(rest), dtype=np.uint64)
-        for j in range(k - lead):  # base 20 -> 5 bits per residue, most significant first
-            digit = (rest // np.uint64(20 ** (k - lead - 1 - j))) % np.uint64(20)
-            tail = (tail << np.uint64(5)) | digit
+        for j in range(k - lead):  # base sigma -> `bits` per letter, most significant first
+            digit = (rest // np.uint64(sigma ** (k - lead - 1 - j))) % np.uint64(sigma)
+            tail = (tail << np.uint64(bits)) | digit
         want = (tail << np.uint64(shift)) | genes[order].astype(np.uint64)
         assert np.array_equal(host["ix_key"].astype(np.uint64), want), "packed index keys"
 

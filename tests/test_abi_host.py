@@ -63,25 +63,48 @@ def test_dict_size_validation():
     with pytest.raises(pdp.PdpError) as e:
         pdp.dict_size(10, 2 ** 32, 6)
     assert e.value.code == pdp.PDP_E_LIMIT
+    # nucleotides: k up to 31 (62-bit codes)
+    pdp.dict_size(10, 100, 31, "nt")
+    for k in (0, 32):
+        with pytest.raises(pdp.PdpError) as e:
+            pdp.dict_size(10, 100, k, "nt")
+        assert e.value.code == pdp.PDP_E_KRANGE
+    a, w = B.u64(0), B.u64(0)
+    assert pdp.lib().pdp_dict_size(10, 100, 6, 2, C.byref(a), C.byref(w)) == pdp.PDP_E_ALPHABET
+    with pytest.raises(ValueError):
+        pdp.dict_size(10, 100, 6, "rna")
 
 
-def _fake_dict(n_genes, n_residues, k, base=1 << 20):
+def _fake_dict(n_genes, n_residues, k, base=1 << 20, alphabet="aa"):
     """Binds a dictionary to a fake (never dereferenced) aligned address: binding and
     planning only do host arithmetic on the pointers."""
-    arena, _ = pdp.dict_size(n_genes, n_residues, k)
+    arena, _ = pdp.dict_size(n_genes, n_residues, k, alphabet)
     d = B.pdp_dict()
-    B.check(pdp.lib().pdp_dict_bind(base, arena, n_genes, n_residues, k, C.byref(d)), "bind")
+    B.check(pdp.lib().pdp_dict_bind(base, arena, n_genes, n_residues, k, B.alphabet_id(alphabet), C.byref(d)),
+            "bind")
     return d
 
 
 def test_bind_checks_alignment_and_size():
     arena, _ = pdp.dict_size(10, 100, 3)
     d = B.pdp_dict()
-    assert pdp.lib().pdp_dict_bind(4096 + 8, arena, 10, 100, 3, C.byref(d)) == pdp.PDP_E_INVAL
-    assert pdp.lib().pdp_dict_bind(4096, arena - 1, 10, 100, 3, C.byref(d)) == pdp.PDP_E_WORKSPACE
-    assert pdp.lib().pdp_dict_bind(4096, arena, 10, 100, 3, C.byref(d)) == 0
-    assert d.n_buckets == 20 ** 3 and d.capacity == 101
+    assert pdp.lib().pdp_dict_bind(4096 + 8, arena, 10, 100, 3, 0, C.byref(d)) == pdp.PDP_E_INVAL
+    assert pdp.lib().pdp_dict_bind(4096, arena - 1, 10, 100, 3, 0, C.byref(d)) == pdp.PDP_E_WORKSPACE
+    assert pdp.lib().pdp_dict_bind(4096, arena, 10, 100, 3, 0, C.byref(d)) == 0
+    assert d.n_buckets == 20 ** 3 and d.capacity == 101 and d.lead == 3 and d.alphabet == 0
     assert d.nwin % 256 == 0 and d.ix_code > d.mv_code > d.nwin
+
+
+def test_bind_layout_per_alphabet():
+    # amino acids: 20^min(k,4) buckets, 5-bit letters; nucleotides: 4^min(k,9) buckets, 2-bit letters
+    for k, lead in ((2, 2), (4, 4), (6, 4), (12, 4)):
+        d = _fake_dict(100, 10000, k)
+        assert (d.lead, d.n_buckets, d.alphabet) == (lead, 20 ** lead, 0)
+        assert d.key_shift == (7 if 5 * (k - lead) + 7 <= 32 else 0)
+    for k, lead in ((3, 3), (9, 9), (13, 9), (21, 9), (31, 9)):
+        d = _fake_dict(100, 10000, k, alphabet="nt")
+        assert (d.lead, d.n_buckets, d.alphabet) == (lead, 4 ** lead, 1)
+        assert d.key_shift == (7 if 2 * (k - lead) + 7 <= 32 else 0)
 
 
 def _plan(tasks, prm=None):
@@ -124,6 +147,10 @@ def test_plan_layout():
 def test_plan_rejects_bad_tasks():
     a5, b6 = _fake_dict(10, 900, 5), _fake_dict(10, 900, 6)
     assert _plan([(a5, b6, pdp.PDP_TASK_AB)])[0] == pdp.PDP_E_INVAL
+    # same k, other alphabet
+    assert _plan([(a5, _fake_dict(10, 900, 5, alphabet="nt"), pdp.PDP_TASK_AB)])[0] == pdp.PDP_E_INVAL
+    n13 = _fake_dict(10, 900, 13, alphabet="nt")
+    assert _plan([(n13, _fake_dict(20, 2000, 13, alphabet="nt"), pdp.PDP_TASK_BBH)])[0] == 0
     assert _plan([(a5, a5, 0)])[0] == pdp.PDP_E_INVAL
     # a column genome must leave room for one dense row (its window counts + sums + bitmap) in LDS
     big = _fake_dict(50000, 9 * 10 ** 6, 5)

@@ -69,7 +69,9 @@ def test_jaccard_examples(golden):
         if e["num"] == 0:
             continue
         say("jaccard example", e["id"])
-        _, res = run_all([genome_from_strings([e["a"]]), genome_from_strings([e["b"]])], e["k"])
+        al = e.get("alphabet", "aa")
+        _, res = run_all([genome_from_strings([e["a"]], alphabet=al), genome_from_strings([e["b"]], alphabet=al)],
+                         e["k"])
         ptr, col, num, den = res.best_hits(0, 0)
         assert (int(num[0]), int(den[0])) == (e["num"], e["den"]), e["id"]
 
@@ -77,7 +79,7 @@ def test_jaccard_examples(golden):
 def test_windows_examples(golden):
     for w in golden["windows"]:
         say("window example", w["id"])
-        g = genome_from_strings([w["gene"]])
+        g = genome_from_strings([w["gene"]], alphabet=w.get("alphabet", "aa"))
         d = pdp.Dictionary.build_from(g, w["k"])
         d.check_status()
         check_dictionary(d.host(), oracle.OracleGenome(g, w["k"]))
@@ -96,10 +98,12 @@ def test_dictionary_parity(k):
 
 
 def test_dictionary_long_genes_and_big_buckets():
-    # genes longer than the LDS sort (2048 windows) and leading-residue buckets far above
-    # the per-thread insertion sort and the LDS bucket sort (low-complexity prefixes)
+    # genes longer than a wave's register sort (1024 windows) and than the LDS sort (8192
+    # windows), and leading-residue buckets far above the per-thread insertion sort and the
+    # LDS bucket sort (low-complexity prefixes)
     rng = random.Random(3)
     genes = ["A" * 5000 + "".join(rng.choice(ALPHA) for _ in range(300))]
+    genes += ["".join(rng.choice(ALPHA) for _ in range(9500))]
     genes += ["".join(rng.choice("AC") for _ in range(3000))]
     genes += ["AAAA" + "".join(rng.choice(ALPHA) for _ in range(rng.randint(4, 30))) for _ in range(3000)]
     genes += ["", "M", "MK"]
