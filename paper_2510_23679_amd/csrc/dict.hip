@@ -7,9 +7,10 @@
 //    kMvWaveCap keys, eight per lane, lanes exchanging by shuffles) and
 //    run-length encodes them into the gene's multiplicity vector (Multiplicity
 //    vector building phase, Alg. 1: group equal identifiers, count, ascending
-//    order).  Longer genes are queued for k_mv_mid (one work-group per gene,
-//    codes sorted in LDS) and, past kMvSortCap windows, for k_mv_long (codes
-//    sorted in global memory).
+//    order).  Longer genes are queued by size for k_mv_mid (one work-group
+//    per gene, 8, 16 or 32 codes per thread sorted in registers, exchanges
+//    across waves through LDS) and, past kMvSortCap windows, for k_mv_long
+//    (codes sorted in global memory).
 // 2. A scan of the distinct-k-mer counts of all genes gives the CSR offsets,
 //    and k_mv_compact packs the vectors (and notes each entry's gene).
 // 3. The inverted index (all entries ordered by k-mer code, ties by gene) is a
@@ -18,7 +19,9 @@
 //    per bin); k_ix_hist counts bins per block of entries in LDS, a scan gives
 //    every (bin, block) its output range, k_ix_place drops the entries there
 //    (LDS cursors), and k_ix_sort_bin sorts each bin by (code, gene) in LDS
-//    and writes the bin's part of the bucket directory.
+//    (a counting sort by bucket and the next one or two letters, which leaves
+//    about one entry per slot, then a sort inside each slot) and writes the
+//    bin's part of the bucket directory.
 // Genes and buckets of all genomes of a call are numbered consecutively; a
 // work-group finds its genome by binary search over the per-genome bases.
 #include <algorithm>
@@ -29,7 +32,7 @@
 namespace pdp {
 
 constexpr uint32_t kMvThreads = 256;
-constexpr uint32_t kMvPer = kMvSortCap / kMvThreads;
+static_assert(kMvSortCap == kMvThreads * 32, "the largest k_mv_mid class sorts 32 codes per thread");
 constexpr uint32_t kIxBatch = 8;  // index entries a thread loads per round in the histogram and placement
 constexpr uint32_t kDescPerLaunch = 8;
 
@@ -198,9 +201,12 @@ __device__ __forceinline__ void mv_wave_gene(const DevBuild &B, const uint8_t *s
     *cnt_out = total;
 }
 
+// Longer genes go to lists by size: counters[0] / long_list past kMvSortCap windows,
+// counters[c] / mid_list + (c - 1) * stride for k_mv_mid<8 << (c - 1)>, c = 1, 2, 3.
 __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restrict__ table, uint32_t n_genomes,
                                                         uint32_t total_genes, uint32_t *__restrict__ dcnt,
-                                                        uint64_t *__restrict__ mid_list, uint32_t *__restrict__ counters) {
+                                                        uint64_t *__restrict__ mid_list, uint64_t *__restrict__ long_list,
+                                                        uint32_t stride, uint32_t *__restrict__ counters) {
     __shared__ uint8_t sym_all[kMvWaves][kMvWaveCap + kKMaxAll];
     __shared__ uint16_t hp_all[kMvWaves][kMvWaveCap + 1];
     const uint32_t w = threadIdx.x / kWave, lane = lane_id();
@@ -214,7 +220,12 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restri
     if (!gene_ok(B, g, G, dcnt, &o, &len, &nw)) return;
     if (lane == 0) B.nwin[g] = nw;
     if (nw > kMvWaveCap) {
-        if (lane == 0) mid_list[atomicAdd(&counters[1], 1u)] = (static_cast<uint64_t>(t) << 32) | g;
+        if (lane == 0) {
+            const uint64_t item = (static_cast<uint64_t>(t) << 32) | g;
+            const uint32_t c = nw > kMvSortCap ? 0u : (nw <= kMvThreads * 8 ? 1u : (nw <= kMvThreads * 16 ? 2u : 3u));
+            if (c == 0) long_list[atomicAdd(&counters[0], 1u)] = item;
+            else mid_list[(c - 1) * stride + atomicAdd(&counters[c], 1u)] = item;
+        }
         return;
     }
     uint8_t *sym = sym_all[w];
@@ -246,98 +257,151 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restri
     if (lane == 0) dcnt[G] = total;
 }
 
-// Genes queued by k_mv_wave (more windows than a wave sorts): one work-group per gene,
-// codes sorted in LDS; genes past kMvSortCap windows are queued again for k_mv_long.
+// Ascending bitonic sort of kMvThreads * E keys by one work-group, E per thread in blocked
+// order (thread t holds elements t*E .. t*E+E-1): comparators inside a thread swap
+// registers, those inside a wave pair lanes by shuffles, and only those across waves go
+// through LDS (xch: kMvThreads * E keys), so a stage costs a barrier only when its stride
+// spans waves.  Contains barriers; every thread of the work-group must call it.
+template <uint32_t E>
+__device__ __forceinline__ void block_bitonic_sort(uint64_t (&key)[E], uint64_t *xch) {
+    constexpr uint32_t N = kMvThreads * E;
+    const uint32_t t = threadIdx.x;
+    for (uint32_t size = 2; size <= N; size <<= 1) {
+        for (uint32_t j = size >> 1; j >= kWave * E; j >>= 1) {  // partner in another wave
+            const uint32_t lj = j / E;
+#pragma unroll
+            for (uint32_t e = 0; e < E; ++e) xch[e * kMvThreads + t] = key[e];
+            __syncthreads();
+            const bool lower = (t & lj) == 0;
+#pragma unroll
+            for (uint32_t e = 0; e < E; ++e) {
+                const uint64_t o = xch[e * kMvThreads + (t ^ lj)];
+                const bool keep_min = lower == (((t * E + e) & size) == 0);
+                const uint64_t mn = o < key[e] ? o : key[e], mx = o < key[e] ? key[e] : o;
+                key[e] = keep_min ? mn : mx;
+            }
+            __syncthreads();
+        }
+        for (uint32_t j = min(size >> 1, kWave * E / 2); j >= E; j >>= 1) {  // partner lane in this wave
+            const uint32_t lj = j / E;
+            const bool lower = (t & lj) == 0;
+#pragma unroll
+            for (uint32_t e = 0; e < E; ++e) {
+                const uint64_t o = __shfl_xor(key[e], lj, kWave);
+                const bool keep_min = lower == (((t * E + e) & size) == 0);
+                const uint64_t mn = o < key[e] ? o : key[e], mx = o < key[e] ? key[e] : o;
+                key[e] = keep_min ? mn : mx;
+            }
+        }
+#pragma unroll
+        for (uint32_t j = E / 2; j > 0; j >>= 1) {  // partner in this thread's registers
+            if (j >= size) continue;
+#pragma unroll
+            for (uint32_t e = 0; e < E; ++e) {
+                if (e & j) continue;
+                const bool asc = ((t * E + e) & size) == 0;
+                const uint64_t a = key[e], b = key[e | j];
+                const bool sw = asc ? a > b : a < b;
+                key[e] = sw ? b : a;
+                key[e | j] = sw ? a : b;
+            }
+        }
+    }
+}
+
+// Genes queued by k_mv_wave with more windows than a wave sorts, up to kMvThreads * E: one
+// work-group per gene.  The gene's symbols go to LDS, every thread encodes E consecutive
+// windows (one new letter per window), the work-group sorts the codes in registers, and
+// run heads ranked by a work-group scan give the multiplicity vector.  The symbols, the
+// sort's exchange area and the head positions share one LDS array.
+template <uint32_t E>
 __global__ __launch_bounds__(kMvThreads) void k_mv_mid(const DevBuild *__restrict__ table, uint32_t *__restrict__ dcnt,
-                                                       const uint64_t *__restrict__ mid_list,
-                                                       uint64_t *__restrict__ long_list, uint32_t *__restrict__ counters) {
-    __shared__ uint64_t keys[kMvSortCap];
-    __shared__ uint8_t sym[kMvSortCap + kKMaxAll];
-    __shared__ uint32_t tmp[kMvThreads / kWave + 1];
-    const uint32_t n_mid = counters[1];
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t li = blockIdx.x; li < n_mid; li += gridDim.x) {
-        const uint64_t item = mid_list[li];
+                                                       const uint64_t *__restrict__ list,
+                                                       const uint32_t *__restrict__ count) {
+    constexpr uint32_t N = kMvThreads * E;
+    static_assert(N + kKMaxAll <= 8 * N && N + 1 <= 4 * N && N <= 65535, "symbols and u16 head positions fit");
+    __shared__ uint64_t xch[N];
+    __shared__ uint64_t s_last[kMvWaves];
+    __shared__ uint32_t tmp[kMvWaves + 1];
+    uint8_t *sym = reinterpret_cast<uint8_t *>(xch);
+    uint16_t *hp = reinterpret_cast<uint16_t *>(xch);
+    const uint32_t n_items = *count;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    for (uint32_t li = blockIdx.x; li < n_items; li += gridDim.x) {
+        const uint64_t item = list[li];
         const DevBuild &B = table[item >> 32];
         const uint32_t g = static_cast<uint32_t>(item);
         const uint32_t G = B.gene_base + g;
         const uint32_t k = B.k, bits = B.bits;
         const uint64_t o = B.off[g];
-        const uint64_t len = B.off[g + 1] - o;
-        const uint32_t nw = static_cast<uint32_t>(len - k + 1);  // checked by k_mv_wave
-        const bool in_lds = nw <= kMvSortCap;
-        const uint8_t *res = B.res;
-        if (in_lds) {  // uniform: loads of a thread issued together, then mapped
-            constexpr uint32_t kIters = (kMvSortCap + kKMaxAll + kMvThreads - 1) / kMvThreads;
-            uint32_t rv[kIters];
+        const uint32_t len = static_cast<uint32_t>(B.off[g + 1] - o);
+        const uint32_t nw = len - k + 1;  // k_mv_wave queued this gene for nw <= N
+        for (uint32_t base = 0; base < len; base += 4 * kMvThreads) {  // 4 loads in flight per thread
+            uint32_t res[4];
 #pragma unroll
-            for (uint32_t it = 0; it < kIters; ++it) {
-                const uint32_t p = tid + it * kMvThreads;
-                rv[it] = p < len ? res[o + p] : 'A';
+            for (uint32_t it = 0; it < 4; ++it) {
+                const uint32_t p = base + it * kMvThreads + tid;
+                res[it] = p < len ? B.res[o + p] : 'A';
             }
 #pragma unroll
-            for (uint32_t it = 0; it < kIters; ++it) {
-                const uint32_t p = tid + it * kMvThreads;
+            for (uint32_t it = 0; it < 4; ++it) {
+                const uint32_t p = base + it * kMvThreads + tid;
                 if (p >= len) continue;
-                uint32_t x = sym_in(rv[it], bits);
+                uint32_t x = sym_in(res[it], bits);
                 if (x == kInvalidSym) {
                     raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
                     x = 0;
                 }
                 sym[p] = static_cast<uint8_t>(x);
             }
-        } else {
-            for (uint64_t p = tid; p < len; p += kMvThreads)
-                if (sym_in(res[o + p], bits) == kInvalidSym) raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
-        }
-        if (!in_lds) {
-            if (tid == 0) long_list[atomicAdd(&counters[0], 1u)] = item;
-            continue;  // uniform: the same item for the whole work-group
         }
         __syncthreads();
-        {  // thread tid encodes a run of consecutive windows, one new letter per window
+        uint64_t key[E];
+        {
             const uint64_t mask = (1ull << (bits * k)) - 1ull;
-            const uint32_t per = (nw + kMvThreads - 1) / kMvThreads;
-            const uint32_t p0 = tid * per, p1 = min(nw, p0 + per);
+            const uint32_t p0 = tid * E;
             uint64_t c = 0;
-            if (p0 < p1)
+            if (p0 < nw)
                 for (uint32_t j = 0; j + 1 < k; ++j) c = (c << bits) | sym[p0 + j];
-            for (uint32_t p = p0; p < p1; ++p) {
-                c = ((c << bits) | sym[p + k - 1]) & mask;
-                keys[p] = c;
+#pragma unroll
+            for (uint32_t e = 0; e < E; ++e) {
+                const uint32_t p = p0 + e;
+                if (p < nw) c = ((c << bits) | sym[p + k - 1]) & mask;
+                key[e] = p < nw ? c : ~0ull;  // past the windows: sorts last
             }
         }
+        __syncthreads();  // the symbols are read before the sort overwrites them
+        block_bitonic_sort<E>(key, xch);
+        if (lane == kWave - 1) s_last[w] = key[E - 1];
+        uint64_t before = __shfl_up(key[E - 1], 1, kWave);
         __syncthreads();
-        wg_network_sort(nw, [&](uint32_t lo, uint32_t hi) {
-            const uint64_t a = keys[lo], b = keys[hi];
-            if (b < a) {
-                keys[lo] = b;
-                keys[hi] = a;
-            }
-        });
-        // run-length encoding; each thread owns kMvPer consecutive sorted codes
-        const uint32_t i0 = tid * kMvPer;
-        uint32_t heads = 0;
+        if (lane == 0 && w > 0) before = s_last[w - 1];
+        uint32_t hmask = 0, nh = 0;
 #pragma unroll
-        for (uint32_t j = 0; j < kMvPer; ++j) {
-            const uint32_t i = i0 + j;
-            if (i < nw && (i == 0 || keys[i] != keys[i - 1])) ++heads;
+        for (uint32_t e = 0; e < E; ++e) {
+            const uint32_t i = tid * E + e;
+            const uint64_t prev = e ? key[e - 1] : before;
+            const bool h = i < nw && (i == 0 || key[e] != prev);
+            hmask |= static_cast<uint32_t>(h) << e;
+            nh += h;
         }
         uint32_t total;
-        uint32_t rank = block_exclusive_scan<kMvThreads>(heads, tmp, &total);
+        const uint32_t r0 = block_exclusive_scan<kMvThreads>(nh, tmp, &total);
+        uint32_t r = r0;
+#pragma unroll
+        for (uint32_t e = 0; e < E; ++e)
+            if ((hmask >> e) & 1u) hp[r++] = static_cast<uint16_t>(tid * E + e);
+        if (tid == 0) hp[total] = static_cast<uint16_t>(nw);
+        __syncthreads();
         uint64_t *slot_code = B.slot_code + o;
         uint32_t *slot_cnt = B.slot_cnt + o;
+        r = r0;
 #pragma unroll
-        for (uint32_t j = 0; j < kMvPer; ++j) {
-            const uint32_t i = i0 + j;
-            if (i < nw && (i == 0 || keys[i] != keys[i - 1])) {
-                const uint64_t c = keys[i];
-                uint32_t end = i + 1;
-                while (end < nw && keys[end] == c) ++end;
-                slot_code[rank] = c;
-                slot_cnt[rank] = end - i;
-                ++rank;
-            }
+        for (uint32_t e = 0; e < E; ++e) {
+            if (!((hmask >> e) & 1u)) continue;
+            slot_code[r] = key[e];
+            slot_cnt[r] = static_cast<uint32_t>(hp[r + 1]) - hp[r];
+            ++r;
         }
         if (tid == 0) dcnt[G] = total;
         __syncthreads();  // LDS takes the next gene
@@ -359,6 +423,8 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_long(const DevBuild *__restri
         const uint64_t o = B.off[g];
         const uint32_t nw = static_cast<uint32_t>(B.off[g + 1] - o - k + 1);
         uint64_t *w = B.long_tmp + o;
+        for (uint64_t p = tid; p < nw + k - 1; p += kMvThreads)
+            if (sym_in(B.res[o + p], B.bits) == kInvalidSym) raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
         for (uint32_t p = tid; p < nw; p += kMvThreads) {
             uint64_t c = 0;
             for (uint32_t j = 0; j < k; ++j) {
@@ -589,21 +655,29 @@ __device__ __forceinline__ void sort_recs(uint4 *r, uint32_t n) {
     });
 }
 
-constexpr uint32_t kIxSmallBucket = 16;   // buckets up to this size are sorted by one thread
-constexpr uint32_t kIxBigList = 64;       // larger buckets a bin sorts one by one with the work-group
-constexpr uint32_t kIxPer = kIxBinLds / 256;
-constexpr uint32_t kIxBinBuckets = 256 * kIxPer;  // buckets a bin may span for the counting path (kIxPer per thread)
+constexpr uint32_t kIxSmallBucket = 16;   // slots up to this size are sorted by one thread
+constexpr uint32_t kIxBigList = 64;       // larger slots a bin sorts one by one with the work-group
+constexpr uint32_t kIxPer = kIxBinSlots / 256;  // counting-sort slots per thread
+
+// Counting-sort slot of a code inside the bin starting at bucket b0: the bucket, then the
+// next xb bits of the code (whole letters), so slots ascend like codes.
+__device__ __forceinline__ uint32_t bin_slot(const DevBuild &B, uint64_t code, uint32_t b0) {
+    const uint32_t b = bucket_of(code, B.k, B.lead, B.bits) - b0;
+    if (!B.xb) return b;
+    const uint32_t sh = B.bits * (B.k - B.lead) - B.xb;
+    return (b << B.xb) | (static_cast<uint32_t>(code >> sh) & ((1u << B.xb) - 1u));
+}
 
 // One work-group per coarse bin: its entries ordered by (code, gene) and the bin's part of
-// the bucket directory.  Usual case (the bin fits LDS and spans at most kIxBinBuckets
-// buckets): a counting sort by bucket (LDS histogram, scan, scatter), whose offsets are the
-// directory, then every bucket sorted on its own, by one thread (insertion sort) or, if
-// large, by the work-group.  Otherwise the whole bin is sorted in LDS, or in place in
-// global memory when it does not fit.
+// the bucket directory.  Usual case (the bin fits LDS and its slots fit kIxBinSlots): a
+// counting sort by slot (LDS histogram, scan, scatter), whose offsets at the first slot of
+// every bucket are the directory, then every slot sorted on its own, by one thread
+// (insertion sort) or, if large, by the work-group.  Otherwise the whole bin is sorted in
+// LDS, or in place in global memory when it does not fit.
 __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict__ table, uint32_t n_genomes,
                                                      const uint32_t *__restrict__ off) {
     __shared__ uint4 s_rec[kIxBinLds];
-    __shared__ uint32_t s_bstart[kIxBinBuckets + 1];
+    __shared__ uint32_t s_bstart[kIxBinSlots + 1];
     __shared__ uint32_t s_big[kIxBigList];
     __shared__ uint32_t s_tmp[256 / kWave + 1];
     __shared__ uint32_t s_t, s_nbig;
@@ -621,8 +695,9 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
     const uint32_t b0 = h << B.hshift;
     const uint32_t b1 = min(B.nb, (h + 1) << B.hshift);
     const uint32_t nbb = b1 - b0;
-    if (n <= kIxBinLds && nbb <= kIxBinBuckets) {
-        for (uint32_t i = threadIdx.x; i <= nbb; i += 256) s_bstart[i] = 0;
+    const uint32_t nslot = nbb << B.xb;
+    if (n <= kIxBinLds && nslot <= kIxBinSlots) {
+        for (uint32_t i = threadIdx.x; i <= nslot; i += 256) s_bstart[i] = 0;
         __syncthreads();
         uint4 r[kIxPer];
         uint32_t slot[kIxPer], bk[kIxPer];
@@ -635,17 +710,17 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
         for (uint32_t q = 0; q < kIxPer; ++q) {
             const uint32_t i = q * 256 + threadIdx.x;
             if (i < n) {
-                bk[q] = bucket_of(rec_code(r[q]), B.k, B.lead, B.bits) - b0;
+                bk[q] = bin_slot(B, rec_code(r[q]), b0);
                 slot[q] = atomicAdd(&s_bstart[bk[q]], 1u);
             }
         }
         __syncthreads();
-        // exclusive scan of the bucket sizes; thread t owns buckets [kIxPer*t, kIxPer*t + kIxPer)
+        // exclusive scan of the slot sizes; thread t owns slots [kIxPer*t, kIxPer*t + kIxPer)
         uint32_t c[kIxPer], sum = 0;
 #pragma unroll
         for (uint32_t q = 0; q < kIxPer; ++q) {
             const uint32_t b = threadIdx.x * kIxPer + q;
-            c[q] = b < nbb ? s_bstart[b] : 0u;
+            c[q] = b < nslot ? s_bstart[b] : 0u;
             sum += c[q];
         }
         uint32_t total;
@@ -653,10 +728,10 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
 #pragma unroll
         for (uint32_t q = 0; q < kIxPer; ++q) {
             const uint32_t b = threadIdx.x * kIxPer + q;
-            if (b < nbb) s_bstart[b] = run;
+            if (b < nslot) s_bstart[b] = run;
             run += c[q];
         }
-        if (threadIdx.x == 0) s_bstart[nbb] = n;
+        if (threadIdx.x == 0) s_bstart[nslot] = n;
         __syncthreads();
 #pragma unroll
         for (uint32_t q = 0; q < kIxPer; ++q) {
@@ -664,9 +739,9 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
             if (i < n) s_rec[s_bstart[bk[q]] + slot[q]] = r[q];
         }
         __syncthreads();
-        for (uint32_t b = threadIdx.x; b < nbb; b += 256) {
+        for (uint32_t b = threadIdx.x; b < nbb; b += 256) B.ix_dir[b0 + b] = lo + s_bstart[b << B.xb];
+        for (uint32_t b = threadIdx.x; b < nslot; b += 256) {
             const uint32_t st = s_bstart[b], size = s_bstart[b + 1] - st;
-            B.ix_dir[b0 + b] = lo + st;
             if (size <= kIxSmallBucket) {
                 for (uint32_t x = st + 1; x < st + size; ++x) {
                     const uint4 v = s_rec[x];
@@ -727,13 +802,29 @@ static uint32_t bin_shift(uint32_t nb, uint64_t cap) {
     return s;
 }
 
+// Bin shift s and sub-slot bits xb of one genome: a bin's counting sort goes by bucket and,
+// where the slots still fit kIxBinSlots, the next letter (amino acids, 5 bits) or two
+// (nucleotides, 4 bits), so that a slot holds about one entry.  (Smaller bins to make room
+// for the sub-slots cost more in the histogram and placement than they save.)
+struct BinPlan {
+    uint32_t s, xb;
+};
+static BinPlan bin_plan(uint32_t nb, uint64_t cap, uint32_t k, uint32_t alphabet) {
+    const AlphaSpec a = alpha_spec(alphabet);
+    const uint32_t s = bin_shift(nb, cap);
+    const uint32_t rest = k - lead_letters(k, alphabet);
+    uint32_t xb = a.bits * std::min<uint32_t>(rest, a.bits == 2 ? 2u : 1u);
+    while (xb && (1ull << (s + xb)) > kIxBinSlots) xb -= a.bits;
+    return {s, xb};
+}
+
 static BuildShape shape_of(const pdp_genome *g, const pdp_dict *const *d, uint32_t n) {
     BuildShape s{};
     s.n_genomes = n;
     for (uint32_t i = 0; i < n; ++i) {
         const uint64_t cap = g[i].n_residues + 1;
         const uint32_t nb = d[i]->n_buckets;
-        const uint32_t sh = bin_shift(nb, cap);
+        const uint32_t sh = bin_plan(nb, cap, d[i]->k, d[i]->alphabet).s;
         const uint64_t nh = (uint64_t(nb) + (1ull << sh) - 1) >> sh;
         const uint64_t nblk = (cap + kIxBlock - 1) / kIxBlock;
         s.total_genes += g[i].n_genes;
@@ -758,7 +849,7 @@ uint64_t build_ws_bytes(const BuildShape &s) {
     b += align_up(4 * (s.total_genes + 1), A);          // dcnt / gptr
     b += align_up(4 * (s.total_hist + 1), A);           // hist / off
     b += align_up(8 * (s.total_genes + 1), A);          // long_list
-    b += align_up(8 * (s.total_genes + 1), A);          // mid_list
+    b += align_up(3 * 8 * (s.total_genes + 1), A);      // mid_list: three size classes
     b += align_up(4 * 4, A);                            // counters
     const uint64_t np = std::max<uint64_t>(scan_partials(s.total_genes), scan_partials(s.total_hist));
     b += align_up(4 * np, A);
@@ -773,6 +864,7 @@ BuildShape single_build_shape(uint32_t n_genes, uint64_t n_residues, uint32_t k,
     g.n_residues = n_residues;
     pdp_dict d{};
     d.k = k;
+    d.alphabet = alphabet;
     d.n_buckets = n_buckets_for(k, alphabet);
     const pdp_dict *dp = &d;
     return shape_of(&g, &dp, 1);
@@ -796,7 +888,8 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
     uint32_t *dcnt = reinterpret_cast<uint32_t *>(take(4 * (sh.total_genes + 1)));
     uint32_t *hist = reinterpret_cast<uint32_t *>(take(4 * (sh.total_hist + 1)));
     uint64_t *long_list = reinterpret_cast<uint64_t *>(take(8 * (sh.total_genes + 1)));
-    uint64_t *mid_list = reinterpret_cast<uint64_t *>(take(8 * (sh.total_genes + 1)));
+    uint64_t *mid_list = reinterpret_cast<uint64_t *>(take(3 * 8 * (sh.total_genes + 1)));
+    const uint32_t stride = static_cast<uint32_t>(sh.total_genes + 1);
     uint32_t *counters = reinterpret_cast<uint32_t *>(take(4 * 4));
     const uint64_t np = std::max<uint64_t>(scan_partials(sh.total_genes), scan_partials(sh.total_hist));
     uint32_t *partials = reinterpret_cast<uint32_t *>(take(4 * np));
@@ -820,7 +913,9 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
             B.nb = D.n_buckets;
             B.lead = D.lead;
             B.bits = alpha_spec(D.alphabet).bits;
-            B.hshift = bin_shift(D.n_buckets, cap);
+            const BinPlan bp = bin_plan(D.n_buckets, cap, D.k, D.alphabet);
+            B.hshift = bp.s;
+            B.xb = bp.xb;
             B.nh = static_cast<uint32_t>((uint64_t(D.n_buckets) + (1ull << B.hshift) - 1) >> B.hshift);
             B.nblk = static_cast<uint32_t>((cap + kIxBlock - 1) / kIxBlock);
             B.gene_base = static_cast<uint32_t>(gene_base);
@@ -859,10 +954,17 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
     PDP_TRY(launch_fill_u32(counters, 4, 0u, s));
     if (tg > 0) {
         hipLaunchKernelGGL(k_mv_wave, dim3((tg + kMvWaves - 1) / kMvWaves), dim3(kMvThreads), 0, s, table, n, tg, dcnt,
-                           mid_list, counters);
+                           mid_list, long_list, stride, counters);
         PDP_TRY(hipGetLastError());
+        // a fixed grid per size class; work-groups past the class's gene count exit at once
         const uint32_t mid_groups = tg < 2048 ? tg : 2048;
-        hipLaunchKernelGGL(k_mv_mid, dim3(mid_groups), dim3(kMvThreads), 0, s, table, dcnt, mid_list, long_list, counters);
+        hipLaunchKernelGGL(k_mv_mid<8>, dim3(mid_groups), dim3(kMvThreads), 0, s, table, dcnt, mid_list, counters + 1);
+        PDP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_mv_mid<16>, dim3(mid_groups), dim3(kMvThreads), 0, s, table, dcnt, mid_list + stride,
+                           counters + 2);
+        PDP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_mv_mid<32>, dim3(mid_groups), dim3(kMvThreads), 0, s, table, dcnt, mid_list + 2 * stride,
+                           counters + 3);
         PDP_TRY(hipGetLastError());
         const uint32_t long_groups = tg < 64 ? tg : 64;
         hipLaunchKernelGGL(k_mv_long, dim3(long_groups), dim3(kMvThreads), 0, s, table, dcnt, long_list, counters);

@@ -22,6 +22,7 @@ constexpr uint32_t kKMaxAll = PDP_K_MAX_NT > PDP_K_MAX ? PDP_K_MAX_NT : PDP_K_MA
 constexpr uint32_t kIxBlock = 8192;          // index entries per histogram block
 constexpr uint32_t kIxBinTarget = 1024;      // average index entries per coarse bin
 constexpr uint32_t kIxBinLds = 2048;         // coarse bins up to this size are sorted in LDS
+constexpr uint32_t kIxBinSlots = 2048;       // counting-sort slots of a bin (buckets x sub-slots)
 constexpr uint32_t kIxMaxBins = 8192;        // coarse bins per genome at most (LDS histogram)
 constexpr uint32_t kJoinLdsCap = 1024;       // target index entries staged in LDS per join sub-range
 constexpr uint32_t kJoinLdsCapP = 2048;      // the same for dictionaries with packed 32-bit keys
@@ -125,6 +126,7 @@ struct DevBuild {
     uint64_t n_residues;
     uint32_t n_genes, k, nb, lead, gene_base;
     uint32_t hshift, nh, nblk;            // coarse bins of 2^hshift buckets; entry blocks for the histogram
+    uint32_t xb;                          // sub-slot bits per bucket of a bin's counting sort (next letters)
     uint32_t blk_base, bin_base, hist_base;  // first block, bin and histogram cell of the genome
     uint32_t *nwin, *mv_ptr;
     uint64_t *mv_code;
