@@ -16,9 +16,10 @@
 // 3. The inverted index (all entries ordered by k-mer code, ties by gene) is a
 //    two-level partition with no global atomics: the leading-residue buckets
 //    are grouped into coarse bins of 2^s buckets (s per genome, ~1K entries
-//    per bin); k_ix_hist counts bins per block of entries in LDS, a scan gives
-//    every (bin, block) its output range, k_ix_place drops the entries there
-//    (LDS cursors), and k_ix_sort_bin sorts each bin by (code, gene) in LDS
+//    per bin); k_ix_hist counts bins per block of entries in LDS and adds
+//    them to the bin totals, a scan gives every bin its output range,
+//    k_ix_place hands each block a run of every bin's range (one atomic per
+//    block and bin) and drops its entries there by LDS rank, and k_ix_sort_bin sorts each bin by (code, gene) in LDS
 //    (a counting sort by bucket and the next one or two letters, which leaves
 //    about one entry per slot, then a sort inside each slot) and writes the
 //    bin's part of the bucket directory.
@@ -522,9 +523,10 @@ __device__ __forceinline__ void block_range(const DevBuild &B, const uint32_t *g
     *e1 = min(E, (j + 1) * kIxBlock);
 }
 
-// One work-group per block of entries: coarse-bin histogram in LDS, written bin-major.
+// One work-group per block of entries: coarse-bin histogram in LDS, added to the genome's
+// bin totals with one global atomic per non-empty bin.
 __global__ __launch_bounds__(256) void k_ix_hist(const DevBuild *__restrict__ table, uint32_t n_genomes,
-                                                 const uint32_t *__restrict__ gptr, uint32_t *__restrict__ hist) {
+                                                 const uint32_t *__restrict__ gptr, uint32_t *__restrict__ bintot) {
     extern __shared__ uint32_t h[];
     __shared__ uint32_t s_t;
     if (threadIdx.x == 0) s_t = find_genome_by_block(table, n_genomes, blockIdx.x);
@@ -548,41 +550,64 @@ __global__ __launch_bounds__(256) void k_ix_hist(const DevBuild *__restrict__ ta
             if (base + q * 256 + threadIdx.x < e1) atomicAdd(&h[bucket_of(c[q], B.k, B.lead, B.bits) >> B.hshift], 1u);
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < B.nh; i += blockDim.x) hist[B.hist_base + i * B.nblk + j] = h[i];
+    for (uint32_t i = threadIdx.x; i < B.nh; i += blockDim.x)
+        if (h[i]) atomicAdd(&bintot[B.bin_base + i], h[i]);
 }
 
-// Same blocks: each entry goes to its bin's range (scanned histogram), position by LDS cursor.
+constexpr uint32_t kIxPerThread = kIxBlock / 256;  // entries a placement thread keeps in registers
+
+// Same blocks: each entry goes to its bin's range.  The block counts its entries per bin in
+// LDS (every entry's rank among the block's entries of its bin comes back from the LDS
+// atomic), takes a run of each bin's range with one global atomic on the bin's remaining
+// count (binoff holds the scanned totals; the runs of a bin are handed out from its end),
+// and writes each entry at its run start plus its rank.  The order inside a bin depends on
+// scheduling; k_ix_sort_bin sorts every bin completely.
 __global__ __launch_bounds__(256) void k_ix_place(const DevBuild *__restrict__ table, uint32_t n_genomes,
-                                                  const uint32_t *__restrict__ gptr, const uint32_t *__restrict__ off,
-                                                  const uint32_t *__restrict__ ent_gene) {
+                                                  const uint32_t *__restrict__ gptr, const uint32_t *__restrict__ binoff,
+                                                  uint32_t *__restrict__ bintot, const uint32_t *__restrict__ ent_gene) {
     extern __shared__ uint32_t cur[];
     __shared__ uint32_t s_t;
     if (threadIdx.x == 0) s_t = find_genome_by_block(table, n_genomes, blockIdx.x);
     __syncthreads();
     const DevBuild &B = table[s_t];
     const uint32_t j = blockIdx.x - B.blk_base;
-    const uint32_t gbase_off = off[B.hist_base];  // the genome's first entry in the scanned order
-    for (uint32_t i = threadIdx.x; i < B.nh; i += blockDim.x) cur[i] = off[B.hist_base + i * B.nblk + j] - gbase_off;
+    for (uint32_t i = threadIdx.x; i < B.nh; i += blockDim.x) cur[i] = 0;
     __syncthreads();
     uint32_t e0, e1, gbase;
     block_range(B, gptr, j, &e0, &e1, &gbase);
-    for (uint32_t base = e0; base < e1; base += kIxBatch * 256) {
-        uint64_t c[kIxBatch];
+    uint64_t c[kIxPerThread];
+    uint32_t rank[kIxPerThread];
+#pragma unroll
+    for (uint32_t q = 0; q < kIxPerThread; ++q) {
+        const uint32_t e = e0 + q * 256 + threadIdx.x;
+        c[q] = e < e1 ? B.mv_code[e] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kIxPerThread; ++q)
+        if (e0 + q * 256 + threadIdx.x < e1) rank[q] = atomicAdd(&cur[bucket_of(c[q], B.k, B.lead, B.bits) >> B.hshift], 1u);
+    __syncthreads();
+    const uint32_t gstart = binoff[B.bin_base];  // the genome's first entry in the scanned order
+    for (uint32_t i = threadIdx.x; i < B.nh; i += blockDim.x) {
+        const uint32_t n = cur[i];
+        if (n) cur[i] = binoff[B.bin_base + i] - gstart + atomicSub(&bintot[B.bin_base + i], n) - n;
+    }
+    __syncthreads();
+    for (uint32_t q0 = 0; q0 < kIxPerThread; q0 += kIxBatch) {
         uint32_t gn[kIxBatch], ct[kIxBatch];
 #pragma unroll
         for (uint32_t q = 0; q < kIxBatch; ++q) {
-            const uint32_t e = base + q * 256 + threadIdx.x;
+            const uint32_t e = e0 + (q0 + q) * 256 + threadIdx.x;
             const bool v = e < e1;
-            c[q] = v ? B.mv_code[e] : 0ull;
             gn[q] = v ? ent_gene[gbase + e] : 0u;
             ct[q] = v ? B.mv_cnt[e] : 0u;
         }
 #pragma unroll
         for (uint32_t q = 0; q < kIxBatch; ++q) {
-            if (base + q * 256 + threadIdx.x >= e1) continue;
-            const uint32_t pos = atomicAdd(&cur[bucket_of(c[q], B.k, B.lead, B.bits) >> B.hshift], 1u);
+            if (e0 + (q0 + q) * 256 + threadIdx.x >= e1) continue;
+            const uint64_t code = c[q0 + q];
+            const uint32_t pos = cur[bucket_of(code, B.k, B.lead, B.bits) >> B.hshift] + rank[q0 + q];
             // one 16-byte record per entry: a single scattered store instead of three
-            B.ix_tmp[pos] = make_uint4(static_cast<uint32_t>(c[q]), static_cast<uint32_t>(c[q] >> 32), gn[q], ct[q]);
+            B.ix_tmp[pos] = make_uint4(static_cast<uint32_t>(code), static_cast<uint32_t>(code >> 32), gn[q], ct[q]);
         }
     }
 }
@@ -688,9 +713,9 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
     __syncthreads();
     const DevBuild &B = table[s_t];
     const uint32_t h = blockIdx.x - B.bin_base;
-    const uint32_t base = off[B.hist_base];
-    const uint32_t lo = off[B.hist_base + h * B.nblk] - base;
-    const uint32_t hi = off[B.hist_base + (h + 1) * B.nblk] - base;  // for the last bin: the next genome's start
+    const uint32_t base = off[B.bin_base];
+    const uint32_t lo = off[B.bin_base + h] - base;
+    const uint32_t hi = off[B.bin_base + h + 1] - base;  // for the last bin: the next genome's start
     const uint32_t n = hi - lo;
     const uint32_t b0 = h << B.hshift;
     const uint32_t b1 = min(B.nb, (h + 1) << B.hshift);
@@ -831,7 +856,6 @@ static BuildShape shape_of(const pdp_genome *g, const pdp_dict *const *d, uint32
         s.total_residues += cap;
         s.total_blocks += nblk;
         s.total_bins += nh;
-        s.total_hist += nh * nblk;
         s.max_nh = std::max<uint64_t>(s.max_nh, nh);
     }
     return s;
@@ -847,11 +871,12 @@ uint64_t build_ws_bytes(const BuildShape &s) {
     b += align_up(4 * s.total_residues, A);             // ent_gene
     b += align_up(16 * s.total_residues, A);            // ix_tmp
     b += align_up(4 * (s.total_genes + 1), A);          // dcnt / gptr
-    b += align_up(4 * (s.total_hist + 1), A);           // hist / off
+    b += align_up(4 * (s.total_bins + 1), A);           // bin totals
+    b += align_up(4 * (s.total_bins + 1), A);           // scanned bin offsets
     b += align_up(8 * (s.total_genes + 1), A);          // long_list
     b += align_up(3 * 8 * (s.total_genes + 1), A);      // mid_list: three size classes
     b += align_up(4 * 4, A);                            // counters
-    const uint64_t np = std::max<uint64_t>(scan_partials(s.total_genes), scan_partials(s.total_hist));
+    const uint64_t np = std::max<uint64_t>(scan_partials(s.total_genes), scan_partials(s.total_bins));
     b += align_up(4 * np, A);
     return b;
 }
@@ -886,16 +911,17 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
     uint32_t *ent_gene = reinterpret_cast<uint32_t *>(take(4 * sh.total_residues));
     uint4 *ix_tmp = reinterpret_cast<uint4 *>(take(16 * sh.total_residues));
     uint32_t *dcnt = reinterpret_cast<uint32_t *>(take(4 * (sh.total_genes + 1)));
-    uint32_t *hist = reinterpret_cast<uint32_t *>(take(4 * (sh.total_hist + 1)));
+    uint32_t *bintot = reinterpret_cast<uint32_t *>(take(4 * (sh.total_bins + 1)));
+    uint32_t *binoff = reinterpret_cast<uint32_t *>(take(4 * (sh.total_bins + 1)));
     uint64_t *long_list = reinterpret_cast<uint64_t *>(take(8 * (sh.total_genes + 1)));
     uint64_t *mid_list = reinterpret_cast<uint64_t *>(take(3 * 8 * (sh.total_genes + 1)));
     const uint32_t stride = static_cast<uint32_t>(sh.total_genes + 1);
     uint32_t *counters = reinterpret_cast<uint32_t *>(take(4 * 4));
-    const uint64_t np = std::max<uint64_t>(scan_partials(sh.total_genes), scan_partials(sh.total_hist));
+    const uint64_t np = std::max<uint64_t>(scan_partials(sh.total_genes), scan_partials(sh.total_bins));
     uint32_t *partials = reinterpret_cast<uint32_t *>(take(4 * np));
 
     // descriptors, passed by value to a tiny kernel in chunks
-    uint64_t gene_base = 0, res_base = 0, blk_base = 0, bin_base = 0, hist_base = 0;
+    uint64_t gene_base = 0, res_base = 0, blk_base = 0, bin_base = 0;
     for (uint32_t c0 = 0; c0 < n; c0 += kDescPerLaunch) {
         DescChunk ch{};
         ch.first = c0;
@@ -921,7 +947,6 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
             B.gene_base = static_cast<uint32_t>(gene_base);
             B.blk_base = static_cast<uint32_t>(blk_base);
             B.bin_base = static_cast<uint32_t>(bin_base);
-            B.hist_base = static_cast<uint32_t>(hist_base);
             B.nwin = D.nwin;
             B.mv_ptr = D.mv_ptr;
             B.mv_code = D.mv_code;
@@ -941,7 +966,6 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
             res_base += cap;
             blk_base += B.nblk;
             bin_base += B.nh;
-            hist_base += uint64_t(B.nh) * B.nblk;
         }
         hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(kDescPerLaunch), 0, s, table, ch);
         PDP_TRY(hipGetLastError());
@@ -952,6 +976,7 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
     hipLaunchKernelGGL(k_build_init, dim3(gblocks), dim3(256), 0, s, table, n);
     PDP_TRY(hipGetLastError());
     PDP_TRY(launch_fill_u32(counters, 4, 0u, s));
+    PDP_TRY(launch_fill_u32(bintot, sh.total_bins, 0u, s));
     if (tg > 0) {
         hipLaunchKernelGGL(k_mv_wave, dim3((tg + kMvWaves - 1) / kMvWaves), dim3(kMvThreads), 0, s, table, n, tg, dcnt,
                            mid_list, long_list, stride, counters);
@@ -978,13 +1003,13 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
         PDP_TRY(hipGetLastError());
     }
     hipLaunchKernelGGL(k_ix_hist, dim3(static_cast<uint32_t>(sh.total_blocks)), dim3(256), hist_lds, s, table, n, dcnt,
-                       hist);
+                       bintot);
     PDP_TRY(hipGetLastError());
-    PDP_TRY(launch_scan(hist, hist, sh.total_hist, partials, s));  // in place: every (bin, block) range
+    PDP_TRY(launch_scan(bintot, binoff, sh.total_bins, partials, s));  // every bin's range
     hipLaunchKernelGGL(k_ix_place, dim3(static_cast<uint32_t>(sh.total_blocks)), dim3(256), hist_lds, s, table, n, dcnt,
-                       hist, ent_gene);
+                       binoff, bintot, ent_gene);
     PDP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_ix_sort_bin, dim3(static_cast<uint32_t>(sh.total_bins)), dim3(256), 0, s, table, n, hist);
+    hipLaunchKernelGGL(k_ix_sort_bin, dim3(static_cast<uint32_t>(sh.total_bins)), dim3(256), 0, s, table, n, binoff);
     PDP_TRY(hipGetLastError());
     return hipSuccess;
 }

@@ -127,7 +127,7 @@ struct DevBuild {
     uint32_t n_genes, k, nb, lead, gene_base;
     uint32_t hshift, nh, nblk;            // coarse bins of 2^hshift buckets; entry blocks for the histogram
     uint32_t xb;                          // sub-slot bits per bucket of a bin's counting sort (next letters)
-    uint32_t blk_base, bin_base, hist_base;  // first block, bin and histogram cell of the genome
+    uint32_t blk_base, bin_base;          // first block and bin of the genome
     uint32_t *nwin, *mv_ptr;
     uint64_t *mv_code;
     uint32_t *mv_cnt, *ix_dir;
@@ -143,7 +143,7 @@ struct DevBuild {
     uint4 *ix_tmp;        // index entries placed by coarse bin, before the bin sort
 };
 struct BuildShape {
-    uint64_t n_genomes, total_genes, total_residues, total_blocks, total_bins, total_hist, max_nh;
+    uint64_t n_genomes, total_genes, total_residues, total_blocks, total_bins, max_nh;
 };
 BuildShape build_shape(const pdp_genome *g, const pdp_dict *const *d, uint32_t n);
 BuildShape single_build_shape(uint32_t n_genes, uint64_t n_residues, uint32_t k, uint32_t alphabet);
