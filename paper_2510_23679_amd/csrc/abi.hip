@@ -335,7 +335,13 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
             if (dense > kMaxTileLds)
                 return bail(fail(PDP_E_LIMIT, "task %u: %u target genes do not fit an LDS tile", t, C->n_genes));
             tile_lds = std::max<uint32_t>(tile_lds, static_cast<uint32_t>(dense));
-            d.tiles_n[dir] = static_cast<uint32_t>((uint64_t(R->n_genes) + (1u << base_shift) - 1) >> base_shift);
+            // a tile's (row, column) sums share one LDS hash table, and a row meets more
+            // columns by chance the more k-mers it has: unless the caller fixed the height,
+            // rows of long genes (over 512 letters on average, e.g. nucleotide genes) go 32
+            // to a tile instead of 64
+            if (!prm.tile_rows && R->n_genes && R->capacity / R->n_genes > 512) d.tile_shift[dir] = kDefaultTileShift - 1;
+            d.tiles_n[dir] = static_cast<uint32_t>((uint64_t(R->n_genes) + (1u << d.tile_shift[dir]) - 1) >>
+                                                   d.tile_shift[dir]);
             d.row_base[dir] = static_cast<uint32_t>(bh_rows);
             bh_rows += R->n_genes;
         }
