@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--tune", action="store_true", help="pick tile shapes and join splits with the autotuner first")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                    help="measured HBM traffic per kernel (from rocprofv3 counters), used when its source hash matches")
+    p.add_argument("--colmax", action="store_true",
+                   help="second genome's best hits from column maxima (Alg. 3): join records for one direction only")
     p.add_argument("--theta", default=None, help="length filter as NUM/DEN (Eq. length_threshold); off by default")
     p.add_argument("--tau", default=None, help="directional filter as NUM/DEN (Eq. directional_jaccard); off by default")
     p.add_argument("--alphabet", choices=("aa", "nt"), default="aa",
@@ -391,7 +393,7 @@ def main():
     def frac(x):
         return tuple(int(v) for v in x.split("/")) if x else None
 
-    prm = pdp.params(theta=frac(args.theta), tau=frac(args.tau))
+    prm = pdp.params(theta=frac(args.theta), tau=frac(args.tau), colmax=args.colmax)
     if args.tune:
         best, tres = pdp.autotune(tasks, reps=3, base=prm)
         prm = best
@@ -474,7 +476,8 @@ def main():
     try:
         with open(args.traffic) as f:
             tr = json.load(f)
-        if tr.get("source_hash") == source_hash() and args.kernel in tr.get("kernels", {}):
+        if (tr.get("source_hash") == source_hash() and tr.get("alphabet", "aa") == args.alphabet
+                and args.kernel in tr.get("kernels", {})):
             traffic = tr["kernels"][args.kernel]["hbm_bytes_per_launch"]
     except (OSError, ValueError):
         pass
@@ -500,7 +503,7 @@ def main():
                    "alphabet": "nucleotide" if nt else "amino acid",
                    "genomes": len(genes), "genes_per_genome": genes[0], "k": k, "genome_pairs": len(pairs),
                    "gene_pairs": gene_pairs, "kmer_entries": int(sum(entries)), "best_hits": bh_nnz, "bbh_pairs": bbh_n,
-                   "filters": {"theta": args.theta, "tau": args.tau}},
+                   "filters": {"theta": args.theta, "tau": args.tau}, "column_maxima": bool(args.colmax)},
         "roofline": roofline,
         "params": tuned if tuned is not None else "defaults",
         "breakdown": breakdown,

@@ -238,6 +238,13 @@ typedef struct pdp_params {
  * the device pulls work items from a counter (largest tasks first) instead of
  * one work-group per item. */
 #define PDP_PARAM_PERSISTENT 1u
+/* Column maxima (Alg. 3: a gene of the second genome takes as best hits the
+ * rows at the maximum of its column of S): for a task that asks for both
+ * directions, the best hits of b's genes come from the column maxima of the
+ * similarities computed for a's genes, so the join emits shared-k-mer records
+ * for one direction only.  Results are identical to the default.  The column
+ * candidates share the record capacity (PDP_E_CAPACITY with where = 0). */
+#define PDP_PARAM_COLMAX 2u
 
 /* One unit of work: genomes a and b (same k and alphabet).  flags select the outputs. */
 #define PDP_TASK_AB 1u   /* best hits of a's genes in b */

@@ -244,12 +244,14 @@ class BBHOut:
 
 
 def params(inc_capacity: int = 0, tile_rows: int = 0, join_entries: int = 0, lds_budget: int = 0,
-           persistent: bool = False, theta=None, tau=None) -> B.pdp_params:
-    """Tuning knobs and the candidate filters: theta / tau as (numerator, denominator) or None (off)."""
+           persistent: bool = False, theta=None, tau=None, colmax: bool = False) -> B.pdp_params:
+    """Tuning knobs and the candidate filters: theta / tau as (numerator, denominator) or None (off).
+    colmax: the second genome's best hits from the column maxima of the first genome's rows."""
     tn, td = theta if theta is not None else (0, 0)
     un, ud = tau if tau is not None else (0, 0)
-    return B.pdp_params(int(inc_capacity), int(tile_rows), int(join_entries), int(lds_budget),
-                        B.PDP_PARAM_PERSISTENT if persistent else 0, int(tn), int(td), int(un), int(ud))
+    flags = (B.PDP_PARAM_PERSISTENT if persistent else 0) | (B.PDP_PARAM_COLMAX if colmax else 0)
+    return B.pdp_params(int(inc_capacity), int(tile_rows), int(join_entries), int(lds_budget), flags,
+                        int(tn), int(td), int(un), int(ud))
 
 
 def _with_capacity(prm: B.pdp_params, capacity: int) -> B.pdp_params:

@@ -30,6 +30,7 @@ PDP_TASK_AB = 1
 PDP_TASK_BA = 2
 PDP_TASK_BBH = 4
 PDP_PARAM_PERSISTENT = 1
+PDP_PARAM_COLMAX = 2
 PDP_K_MAX = 12
 PDP_K_MAX_NT = 31
 PDP_ALPHA_AMINO = 0

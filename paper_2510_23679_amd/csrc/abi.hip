@@ -271,7 +271,9 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     if (prm.tile_rows)
         for (base_shift = 0; (2u << base_shift) <= prm.tile_rows; ++base_shift) {
         }
-    if (prm.flags & ~PDP_PARAM_PERSISTENT) return fail(PDP_E_INVAL, "unknown parameter flags 0x%x", prm.flags);
+    if (prm.flags & ~(PDP_PARAM_PERSISTENT | PDP_PARAM_COLMAX))
+        return fail(PDP_E_INVAL, "unknown parameter flags 0x%x", prm.flags);
+    bool any_colmax = false;
     if (prm.theta_den && prm.theta_num > prm.theta_den) return fail(PDP_E_INVAL, "theta above 1");
     const bool filt = prm.theta_den || prm.tau_den;
 
@@ -301,7 +303,10 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         std::memset(&d, 0, sizeof(d));
         d.a = dev_dict(tk.a);
         d.b = dev_dict(tk.b);
-        d.flags = flags;
+        // column maxima: b's best hits from the AB tiles' columns, records for one direction
+        const bool colmax = (prm.flags & PDP_PARAM_COLMAX) && (flags & PDP_TASK_AB) && (flags & PDP_TASK_BA);
+        any_colmax |= colmax;
+        d.flags = colmax ? (flags & ~PDP_TASK_BA) | kTaskColmax : flags;
         d.theta_n = prm.theta_num;
         d.theta_d = prm.theta_den;
         d.tau_n = prm.tau_num;
@@ -324,6 +329,11 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
             d.tile_shift[dir] = base_shift;
             d.tiles_n[dir] = 0;
             if (!(flags & (1u << dir))) continue;
+            if (dir == 1 && colmax) {  // rows in the output, no tiles and no records of their own
+                d.row_base[dir] = static_cast<uint32_t>(bh_rows);
+                bh_rows += tk.b->n_genes;
+                continue;
+            }
             ++ndirs;
             const pdp_dict *R = dir == 0 ? tk.a : tk.b;
             const pdp_dict *C = dir == 0 ? tk.b : tk.a;
@@ -414,6 +424,8 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     P->shape.rec_cap = prm.inc_capacity ? prm.inc_capacity : std::min<uint64_t>(rec_est, UINT32_MAX);
     P->shape.join_grid = 0;
     P->shape.tile_grid = 0;
+    P->shape.colmax = any_colmax ? 1u : 0u;
+    P->shape.cand_cap = any_colmax ? P->shape.rec_cap : 0;
     P->persistent = (prm.flags & PDP_PARAM_PERSISTENT) != 0;
     P->ws_bytes = pair_ws_bytes(P->shape);
     *out = P;

@@ -85,6 +85,10 @@ struct DevDict {
     uint32_t lead;  // leading letters of a bucket
 };
 
+// DevTask.flags: PDP_TASK_AB / PDP_TASK_BA select the join's record directions; a task whose
+// BA best hits come from the column maxima of its AB tiles has kTaskColmax instead of BA.
+constexpr uint32_t kTaskColmax = 8u;
+
 struct DevTask {
     DevDict a, b;
     uint32_t flags;
@@ -164,12 +168,20 @@ struct PairWs {
     uint32_t *next_join_write;    // counters word 5: next item of the persistent join's write pass
     uint32_t *order;              // task table indices in the caller's order
     uint32_t *partials;
+    // column maxima (kTaskColmax): per best-hit row the running maximum key of its column,
+    // a cursor for rows with more than kSlab ties, and the candidate list with its count
+    unsigned long long *colkey;
+    uint32_t *colcursor;
+    uint4 *cands;
+    uint32_t *cand_count;         // counters word 6
 };
 
 struct PlanShape {
     uint32_t n_tasks, total_chunks, total_tiles, total_cells, bh_rows, bbh_rows, tile_lds;
     uint64_t rec_cap;               // records the scratch holds
     uint32_t join_grid, tile_grid;  // persistent grids (0: one work-group per item)
+    uint32_t colmax;                // some task takes its BA best hits from column maxima
+    uint64_t cand_cap;              // column candidates the scratch holds (colmax: rec_cap)
 };
 // Records the message that pdp_last_error() returns on this thread; returns code.
 int32_t api_fail(int32_t code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));

@@ -25,6 +25,11 @@
 //     summed densely instead, a few rows per pass.
 //  5. k_bbh: each best hit (a, b) is kept when a is among b's best hits
 //     (Eq. bidirectional_best_hit, the cross-check of Alg. 3).
+// With PDP_PARAM_COLMAX a task asking for both directions writes records for its
+// a-rows only; b's best hits are the rows at each column's maximum (Alg. 3): the AB
+// tiles raise a 64-bit key per column that orders the values of m/d exactly, list every
+// pair that reaches its column's running maximum, and the pairs still at the final
+// maximum become b's best hits.
 // Counts, scans and writes keep every output in a canonical order, so results
 // do not depend on scheduling.
 #include <algorithm>
@@ -454,7 +459,29 @@ struct TileLds {
     uint32_t rank[kTilePer * (kTileThreads / kWave) + 1];
     uint32_t flag;
     uint32_t next;
+    uint32_t cand_n, cand_base;  // column candidates of a row group (column maxima)
 };
+
+// Column maxima: the scratch of the tasks with kTaskColmax.
+struct ColWs {
+    unsigned long long *key;  // per best-hit row (a BA row): the running maximum key of its column
+    uint4 *cands;             // pairs that reached their column's running maximum: (BA row, a, m, d)
+    uint32_t *count;
+    uint64_t cap;
+};
+
+// Key of J = m/d that orders values exactly: floor(m * 2^42 / d).  Distinct values differ by
+// at least 1/(d1 d2) > 2^-42 (d < 2^17), so their keys differ; equal values share a key.
+__device__ __forceinline__ unsigned long long colmax_key(uint32_t m, uint32_t d) {
+    return (static_cast<unsigned long long>(m) << 42) / d;
+}
+
+// Raises the column's running maximum by the pair's key; true when the pair is at or above
+// the maximum so far (the final maximum is never below it, so no final best hit is missed).
+__device__ __forceinline__ bool colmax_raise(const ColWs &cw, uint32_t ba_row, uint32_t m, uint32_t d) {
+    const unsigned long long k = colmax_key(m, d);
+    return k >= atomicMax(&cw.key[ba_row], k);
+}
 
 // Best hits of one row, given its candidates one lane-chunk at a time in ascending
 // column order: cand(e, &c, &m, &d) yields the column, the sum of minima and the sum of
@@ -629,12 +656,13 @@ __device__ __forceinline__ void tile_sorted(const DevTile &tl, const DevTask &T,
 // summed into 16-bit LDS accumulators (two per word) with a touched-word bitmap; each
 // group rescans the tile's records.  With candidate filters two more accumulators per
 // row hold the occurrence sums of each gene.  Rows visit only their touched words.
-template <bool WRITE>
+template <bool WRITE, bool CM = false>
 __device__ __forceinline__ void tile_dense(const DevTile &tl, const DevTask &T, const uint2 *recs, uint64_t rb,
                                            uint32_t n, uint32_t rlo, uint32_t rhi, uint32_t lds_words,
                                            uint32_t *bh_ptr, uint4 *slab,
                                            uint32_t *bh_col, uint32_t *bh_num, uint32_t *bh_den, uint64_t bh_cap,
-                                           uint32_t *lds, TileLds &S) {
+                                           uint32_t *lds, TileLds &S, const ColWs *cmx) {
+    const bool colmax = CM && !WRITE && cmx && (T.flags & kTaskColmax) && tl.dir == 0;
     const DevDict &R = tl.dir == 0 ? T.a : T.b;
     const DevDict &C = tl.dir == 0 ? T.b : T.a;
     const bool filt = T.theta_d || T.tau_d;
@@ -703,6 +731,11 @@ __device__ __forceinline__ void tile_dense(const DevTile &tl, const DevTask &T, 
                         if (j_greater(m, d, bm, bd)) {
                             bm = m;
                             bd = d;
+                        }
+                        // column maxima (rows past the hash table are rare: one global slot each)
+                        if (colmax && colmax_raise(*cmx, T.row_base[1] + 2 * wd + h, m, d)) {
+                            const uint32_t idx = atomicAdd(cmx->count, 1u);
+                            if (idx < cmx->cap) cmx->cands[idx] = make_uint4(T.row_base[1] + 2 * wd + h, row, m, d);
                         }
                     }
                 }
@@ -776,9 +809,11 @@ __device__ __forceinline__ void tile_dense(const DevTile &tl, const DevTask &T, 
 // (64-bit cross-multiplication).  A second sweep counts the columns at the maximum
 // (ties) and puts the first kSlab of them, unordered, in the row's slab; the slab copy
 // orders them by column.
+template <bool CM>
 __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T, const uint2 *recs, uint64_t rb,
                                             uint32_t n, uint32_t g0, uint32_t g1, bool filter, uint32_t *bh_ptr,
-                                            uint4 *slab, uint32_t *lds, TileLds &S) {
+                                            uint4 *slab, uint32_t *lds, TileLds &S, const ColWs &cmx) {
+    const bool colmax = CM && (T.flags & kTaskColmax) && tl.dir == 0;
     const DevDict &R = tl.dir == 0 ? T.a : T.b;
     const DevDict &C = tl.dir == 0 ? T.b : T.a;
     const bool filt = T.theta_d || T.tau_d;
@@ -822,7 +857,9 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
     }
     __syncthreads();
     constexpr uint32_t kSlotsPer = kHashSlots / kTileThreads;
+    static_assert(kSlotsPer <= 32, "a thread's column candidates fit one mask word");
     uint32_t ncw[kSlotsPer];  // the column window counts of a thread's slots, gathered together
+    uint32_t app = 0;         // column maxima: this thread's slots at their column's running maximum
 #pragma unroll
     for (uint32_t q = 0; q < kSlotsPer; ++q) {
         const uint32_t key = hk[q * kTileThreads + threadIdx.x];
@@ -840,6 +877,7 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
         hv[sl] = m | (nc << 16);
         if (!m) continue;
         const uint32_t d = S.nr[rl] + nc - m;
+        if (colmax && colmax_raise(cmx, T.row_base[1] + ((key - 1) & 0xFFFFFFu), m, d)) app |= 1u << q;
         const unsigned long long want = (static_cast<unsigned long long>(m) << 32) | d;
         unsigned long long cur = S.best[rl];
         for (;;) {
@@ -851,6 +889,25 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
         }
     }
     __syncthreads();
+    if (colmax) {  // uniform per tile: the row group's candidates go out with one global atomic
+        if (threadIdx.x == 0) S.cand_n = 0;
+        __syncthreads();
+        const uint32_t mine = __popc(app);
+        uint32_t off = mine ? atomicAdd(&S.cand_n, mine) : 0u;
+        __syncthreads();
+        if (threadIdx.x == 0 && S.cand_n) S.cand_base = atomicAdd(cmx.count, S.cand_n);
+        __syncthreads();
+#pragma unroll
+        for (uint32_t q = 0; q < kSlotsPer; ++q) {
+            if (!((app >> q) & 1u)) continue;
+            const uint32_t sl = q * kTileThreads + threadIdx.x;
+            const uint32_t key = hk[sl], v = hv[sl];
+            const uint32_t rl = (key - 1) >> 24, m = v & 0xFFFFu;
+            const uint64_t idx = uint64_t(S.cand_base) + off++;
+            if (idx < cmx.cap)
+                cmx.cands[idx] = make_uint4(T.row_base[1] + ((key - 1) & 0xFFFFFFu), tl.row0 + rl, m, S.nr[rl] + (v >> 16) - m);
+        }
+    }
     const uint32_t rbase = T.row_base[tl.dir] + tl.row0;
     for (uint32_t sl = threadIdx.x; sl < kHashSlots; sl += kTileThreads) {
         const uint32_t key = hk[sl];
@@ -880,7 +937,7 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
 // and counts to bh_ptr, and a tile with a row of more than kSlab ties is listed for the
 // second launch (WRITE = true), which recomputes it by sorting (or densely) and writes
 // its rows straight into the CSR output in column order.
-template <bool WRITE>
+template <bool WRITE, bool CM = false>
 __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__restrict__ tasks,
                                              const DevTile *__restrict__ tiles, const uint32_t *__restrict__ cells,
                                              const uint2 *__restrict__ recs, uint64_t rec_cap,
@@ -888,7 +945,7 @@ __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__
                                              uint32_t *__restrict__ bh_ptr, uint4 *__restrict__ slab,
                                              uint32_t *__restrict__ bh_col, uint32_t *__restrict__ bh_num,
                                              uint32_t *__restrict__ bh_den, uint64_t bh_cap, uint32_t *overflow_tiles,
-                                             uint32_t *overflow_count, uint32_t *lds, TileLds &S) {
+                                             uint32_t *overflow_count, uint32_t *lds, TileLds &S, const ColWs &cmx) {
     const DevTile tl = tiles[tile_id];
     const DevTask &T = tasks[tl.task];
     // when the join's records overflowed the scratch its write pass wrote none: every tile is
@@ -904,9 +961,9 @@ __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__
             tile_sorted<true>(tl, T, recs, rb, n, bh_ptr, slab, bh_col, bh_num, bh_den, bh_cap, lds, S);
         else
             tile_dense<true>(tl, T, recs, rb, n, 0, tl.nrows, lds_words, bh_ptr, slab, bh_col, bh_num, bh_den, bh_cap,
-                             lds, S);
+                             lds, S, nullptr);
     } else if (n <= kHashMax) {
-        tile_hashed(tl, T, recs, rb, n, 0, tl.nrows, false, bh_ptr, slab, lds, S);
+        tile_hashed<CM>(tl, T, recs, rb, n, 0, tl.nrows, false, bh_ptr, slab, lds, S, cmx);
     } else {
         for (uint32_t rl = threadIdx.x; rl < tl.nrows; rl += kTileThreads) S.rowcnt[rl] = 0;
         __syncthreads();
@@ -915,14 +972,14 @@ __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__
         // every thread walks the same counts, so the group loop is uniform
         for (uint32_t g0 = 0; g0 < tl.nrows;) {
             if (S.rowcnt[g0] > kHashMax) {
-                tile_dense<false>(tl, T, recs, rb, n, g0, g0 + 1, lds_words, bh_ptr, slab, nullptr, nullptr, nullptr, 0,
-                                  lds, S);
+                tile_dense<false, CM>(tl, T, recs, rb, n, g0, g0 + 1, lds_words, bh_ptr, slab, nullptr, nullptr, nullptr,
+                                      0, lds, S, &cmx);
                 ++g0;
                 continue;
             }
             uint32_t g1 = g0, sum = 0;
             while (g1 < tl.nrows && sum + S.rowcnt[g1] <= kHashMax) sum += S.rowcnt[g1++];
-            tile_hashed(tl, T, recs, rb, n, g0, g1, true, bh_ptr, slab, lds, S);
+            tile_hashed<CM>(tl, T, recs, rb, n, g0, g1, true, bh_ptr, slab, lds, S, cmx);
             g0 = g1;
         }
     }
@@ -931,6 +988,8 @@ __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__
     __syncthreads();
 }
 
+// CM: the plan has column-maximum tasks (a separate instance, so the default carries none of it).
+template <bool CM>
 __global__ __launch_bounds__(kTileThreads) void k_tile_count(const DevTask *__restrict__ tasks,
                                                              const DevTile *__restrict__ tiles,
                                                              const uint32_t *__restrict__ cells,
@@ -938,19 +997,20 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count(const DevTask *__re
                                                              const unsigned long long *__restrict__ total,
                                                              uint32_t lds_words, uint32_t *__restrict__ bh_ptr,
                                                              uint4 *__restrict__ slab, uint32_t *overflow_tiles,
-                                                             uint32_t *overflow_count) {
+                                                             uint32_t *overflow_count, ColWs cmx) {
     extern __shared__ uint32_t lds[];
     __shared__ TileLds S;
-    tile_process<false>(blockIdx.x, tasks, tiles, cells, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr, nullptr,
-                        nullptr, 0, overflow_tiles, overflow_count, lds, S);
+    tile_process<false, CM>(blockIdx.x, tasks, tiles, cells, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr,
+                            nullptr, nullptr, 0, overflow_tiles, overflow_count, lds, S, cmx);
 }
 
 // Persistent form: a fixed grid pulls tiles from a counter until none are left.
+template <bool CM>
 __global__ __launch_bounds__(kTileThreads) void k_tile_count_persistent(
     const DevTask *__restrict__ tasks, const DevTile *__restrict__ tiles, uint32_t total_tiles,
     const uint32_t *__restrict__ cells, const uint2 *__restrict__ recs, uint64_t rec_cap,
     const unsigned long long *__restrict__ total, uint32_t lds_words, uint32_t *__restrict__ bh_ptr,
-    uint4 *__restrict__ slab, uint32_t *overflow_tiles, uint32_t *overflow_count, uint32_t *__restrict__ next) {
+    uint4 *__restrict__ slab, uint32_t *overflow_tiles, uint32_t *overflow_count, uint32_t *__restrict__ next, ColWs cmx) {
     extern __shared__ uint32_t lds[];
     __shared__ TileLds S;
     for (;;) {
@@ -961,8 +1021,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count_persistent(
         if (first >= total_tiles) break;
         const uint32_t last = min(total_tiles, first + kClaim);
         for (uint32_t t = first; t < last; ++t)
-            tile_process<false>(t, tasks, tiles, cells, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr, nullptr,
-                                nullptr, 0, overflow_tiles, overflow_count, lds, S);
+            tile_process<false, CM>(t, tasks, tiles, cells, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr,
+                                    nullptr, nullptr, 0, overflow_tiles, overflow_count, lds, S, cmx);
     }
 }
 
@@ -982,7 +1042,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_write(const DevTask *__re
     const uint32_t n = *overflow_count;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
         tile_process<true>(overflow_tiles[i], tasks, tiles, cells, recs, rec_cap, total, lds_words, bh_ptr, nullptr, bh_col,
-                           bh_num, bh_den, bh_cap, nullptr, nullptr, lds, S);
+                           bh_num, bh_den, bh_cap, nullptr, nullptr, lds, S, ColWs{});
 }
 
 // One thread per best-hit row: the slab entries of a row with at most kSlab ties go to the CSR output.
@@ -1014,6 +1074,66 @@ __global__ __launch_bounds__(256) void k_slab_copy(uint32_t bh_rows, const uint3
         bh_col[p + i] = e[i].x;
         bh_num[p + i] = e[i].y;
         bh_den[p + i] = e[i].z;
+    }
+}
+
+// Column maxima, after the AB tiles: every listed pair still at its column's final maximum
+// is a best hit of the column's gene (Alg. 3's test S[l,k] = max_r S[r,k]).  The count goes
+// to the BA row's bh_ptr and the first kSlab hits to its slab, as the tiles do for AB rows.
+__global__ __launch_bounds__(256) void k_colmax_rows(ColWs cmx, uint32_t *__restrict__ bh_ptr, uint4 *__restrict__ slab,
+                                                     pdp_status *st) {
+    const uint32_t n = *cmx.count;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n > cmx.cap) raise_status(st, PDP_E_CAPACITY, n, 0);
+    const uint64_t lim = min(static_cast<uint64_t>(n), cmx.cap);
+    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < lim; i += gridDim.x * 256ull) {
+        const uint4 c = cmx.cands[i];
+        if (colmax_key(c.z, c.w) != cmx.key[c.x]) continue;
+        const uint32_t t = atomicAdd(&bh_ptr[c.x], 1u);
+        if (t < kSlab) slab[static_cast<uint64_t>(c.x) * kSlab + t] = make_uint4(c.y, c.z, c.w, 0);
+    }
+}
+
+// After the scan: hits of BA rows with more than kSlab of them go straight to the CSR (in
+// any order; k_colmax_sort orders those rows), slots taken from a per-row cursor.
+__global__ __launch_bounds__(256) void k_colmax_big(ColWs cmx, uint32_t *__restrict__ cursor,
+                                                    const uint32_t *__restrict__ bh_ptr, uint32_t *__restrict__ bh_col,
+                                                    uint32_t *__restrict__ bh_num, uint32_t *__restrict__ bh_den,
+                                                    uint64_t bh_cap) {
+    const uint64_t lim = min(static_cast<uint64_t>(*cmx.count), cmx.cap);
+    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < lim; i += gridDim.x * 256ull) {
+        const uint4 c = cmx.cands[i];
+        if (colmax_key(c.z, c.w) != cmx.key[c.x]) continue;
+        const uint32_t p = bh_ptr[c.x];
+        if (bh_ptr[c.x + 1] - p <= kSlab) continue;
+        const uint64_t pos = uint64_t(p) + atomicAdd(&cursor[c.x], 1u);
+        if (pos < bh_cap) {
+            bh_col[pos] = c.y;
+            bh_num[pos] = c.z;
+            bh_den[pos] = c.w;
+        }
+    }
+}
+
+// One thread per row that k_colmax_big filled: insertion sort of its hits by column.
+__global__ __launch_bounds__(256) void k_colmax_sort(uint32_t bh_rows, const uint32_t *__restrict__ cursor,
+                                                     const uint32_t *__restrict__ bh_ptr, uint32_t *__restrict__ bh_col,
+                                                     uint32_t *__restrict__ bh_num, uint32_t *__restrict__ bh_den,
+                                                     uint64_t bh_cap) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= bh_rows || !cursor[r]) return;
+    const uint64_t p0 = bh_ptr[r], p1 = min(static_cast<uint64_t>(bh_ptr[r + 1]), bh_cap);
+    for (uint64_t x = p0 + 1; x < p1; ++x) {
+        const uint32_t c = bh_col[x], m = bh_num[x], d = bh_den[x];
+        uint64_t y = x;
+        while (y > p0 && bh_col[y - 1] > c) {
+            bh_col[y] = bh_col[y - 1];
+            bh_num[y] = bh_num[y - 1];
+            bh_den[y] = bh_den[y - 1];
+            --y;
+        }
+        bh_col[y] = c;
+        bh_num[y] = m;
+        bh_den[y] = d;
     }
 }
 
@@ -1118,9 +1238,14 @@ uint32_t persistent_join_grid() {
 
 uint32_t persistent_tile_grid(uint32_t tile_lds) {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tile_count_persistent, kTileThreads, tile_lds) != hipSuccess ||
-        per < 1)
+    int per_cm = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tile_count_persistent<false>, kTileThreads, tile_lds) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cm, k_tile_count_persistent<true>, kTileThreads, tile_lds) !=
+            hipSuccess)
         per = 1;
+    per = std::min(per, per_cm);  // one grid size for both instances
+    if (per < 1) per = 1;
     return device_cus() * static_cast<uint32_t>(per);
 }
 
@@ -1128,8 +1253,13 @@ uint32_t persistent_tile_grid(uint32_t tile_lds) {
 hipError_t allow_tile_lds(uint32_t tile_lds) {
     if (tile_lds <= 64 * 1024) return hipSuccess;
     const int v = static_cast<int>(tile_lds);
-    PDP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_count), hipFuncAttributeMaxDynamicSharedMemorySize, v));
-    PDP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_count_persistent),
+    PDP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_count<false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, v));
+    PDP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_count<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, v));
+    PDP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_count_persistent<false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, v));
+    PDP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_count_persistent<true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, v));
     PDP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_write), hipFuncAttributeMaxDynamicSharedMemorySize, v));
     return hipSuccess;
@@ -1151,6 +1281,10 @@ uint64_t pair_ws_bytes(const PlanShape &p) {
     s += align_up(16 * kSlab * (uint64_t(p.bh_rows) + 1), A);
     s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
     s += align_up(4 * pair_partials(p), A);
+    const uint64_t colrows = p.colmax ? uint64_t(p.bh_rows) + 1 : 1;
+    s += align_up(8 * colrows, A);                                  // column keys
+    s += align_up(4 * colrows, A);                                  // big-row cursors
+    s += align_up(16 * std::max<uint64_t>(p.colmax ? p.cand_cap : 0, 1), A);  // candidates
     return s;
 }
 
@@ -1176,6 +1310,11 @@ PairWs pair_ws_carve(void *ws, const PlanShape &p) {
     w.slab = reinterpret_cast<uint4 *>(take(16 * kSlab * (uint64_t(p.bh_rows) + 1)));
     w.overflow_tiles = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
     w.partials = reinterpret_cast<uint32_t *>(take(4 * pair_partials(p)));
+    const uint64_t colrows = p.colmax ? uint64_t(p.bh_rows) + 1 : 1;
+    w.colkey = reinterpret_cast<unsigned long long *>(take(8 * colrows));
+    w.colcursor = reinterpret_cast<uint32_t *>(take(4 * colrows));
+    w.cands = reinterpret_cast<uint4 *>(take(16 * std::max<uint64_t>(p.colmax ? p.cand_cap : 0, 1)));
+    w.cand_count = reinterpret_cast<uint32_t *>(w.counters) + 6;
     return w;
 }
 
@@ -1191,6 +1330,12 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     // counters: record total (64 bits), overflow tiles, next join item (count pass), next tile,
     // next join item (write pass)
     PDP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(w.counters), 8, 0u, s));
+    const ColWs cmx{w.colkey, w.cands, w.cand_count, p.colmax ? p.cand_cap : 0};
+    if (p.colmax) {  // BA rows are counted by atomics; column keys and cursors start at zero
+        PDP_TRY(launch_fill_u32(bh->ptr, uint64_t(p.bh_rows) + 1, 0u, s));
+        PDP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(w.colkey), 2 * (uint64_t(p.bh_rows) + 1), 0u, s));
+        PDP_TRY(launch_fill_u32(w.colcursor, uint64_t(p.bh_rows) + 1, 0u, s));
+    }
     PDP_TRY(mark(PDP_KERNEL_JOIN, true));
     if (p.total_chunks) {
         const bool pers = p.join_grid != 0;
@@ -1219,15 +1364,30 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     PDP_TRY(mark(PDP_KERNEL_JOIN, false));
     PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, true));
     if (p.total_tiles && p.tile_grid) {
-        hipLaunchKernelGGL(k_tile_count_persistent, dim3(std::min(p.tile_grid, (p.total_tiles + kClaim - 1) / kClaim)),
-                           dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles, p.total_tiles, w.cells, w.recs,
-                           p.rec_cap, w.counters, lds_words, bh->ptr, w.slab, w.overflow_tiles, w.overflow_count,
-                           w.next_tile);
+        const dim3 g(std::min(p.tile_grid, (p.total_tiles + kClaim - 1) / kClaim));
+        if (p.colmax)
+            hipLaunchKernelGGL(k_tile_count_persistent<true>, g, dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
+                               p.total_tiles, w.cells, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
+                               w.overflow_tiles, w.overflow_count, w.next_tile, cmx);
+        else
+            hipLaunchKernelGGL(k_tile_count_persistent<false>, g, dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
+                               p.total_tiles, w.cells, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
+                               w.overflow_tiles, w.overflow_count, w.next_tile, cmx);
         PDP_TRY(hipGetLastError());
     } else if (p.total_tiles) {
-        hipLaunchKernelGGL(k_tile_count, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
-                           w.cells, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab, w.overflow_tiles,
-                           w.overflow_count);
+        if (p.colmax)
+            hipLaunchKernelGGL(k_tile_count<true>, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks,
+                               w.tiles, w.cells, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
+                               w.overflow_tiles, w.overflow_count, cmx);
+        else
+            hipLaunchKernelGGL(k_tile_count<false>, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks,
+                               w.tiles, w.cells, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
+                               w.overflow_tiles, w.overflow_count, cmx);
+        PDP_TRY(hipGetLastError());
+    }
+    const uint32_t col_grid = std::max<uint32_t>(1, std::min<uint32_t>(2048, static_cast<uint32_t>((p.cand_cap + 255) / 256)));
+    if (p.colmax) {
+        hipLaunchKernelGGL(k_colmax_rows, dim3(col_grid), dim3(256), 0, s, cmx, bh->ptr, w.slab, st);
         PDP_TRY(hipGetLastError());
     }
     PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, false));
@@ -1243,6 +1403,14 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
         hipLaunchKernelGGL(k_tile_write, dim3(g), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles, w.cells, w.recs,
                            p.rec_cap, w.counters, lds_words, bh->ptr, bh->col, bh->num, bh->den, bh->capacity, w.overflow_tiles,
                            w.overflow_count);
+        PDP_TRY(hipGetLastError());
+    }
+    if (p.colmax && p.bh_rows) {
+        hipLaunchKernelGGL(k_colmax_big, dim3(col_grid), dim3(256), 0, s, cmx, w.colcursor, bh->ptr, bh->col, bh->num,
+                           bh->den, bh->capacity);
+        PDP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_colmax_sort, dim3((p.bh_rows + 255) / 256), dim3(256), 0, s, p.bh_rows, w.colcursor, bh->ptr,
+                           bh->col, bh->num, bh->den, bh->capacity);
         PDP_TRY(hipGetLastError());
     }
     PDP_TRY(mark(PDP_KERNEL_TILE_WRITE, false));

@@ -144,6 +144,22 @@ def test_plan_layout():
     L.pdp_plan_destroy(h)
 
 
+def test_colmax_plan_has_tiles_for_one_direction():
+    # column maxima: a task asking for both directions gets tiles (and records) for a's rows
+    # only, while b's rows keep their place in the output
+    a, b = _fake_dict(300, 90000, 5), _fake_dict(200, 60000, 5)
+    L = pdp.lib()
+    info = B.pdp_plan_info()
+    rc, h = _plan([(a, b, pdp.PDP_TASK_BBH), (b, a, pdp.PDP_TASK_BA)], pdp.params(tile_rows=16, colmax=True))
+    assert rc == 0 and L.pdp_plan_info_get(h, C.byref(info)) == 0
+    assert info.bh_rows == 300 + 200 + 300 and info.bbh_rows == 300
+    assert info.tiles == 19 + 19  # a's rows of the BBH task, a's rows (as b) of the BA task
+    L.pdp_plan_destroy(h)
+    bad = pdp.params()
+    bad.flags = 4
+    assert _plan([(a, b, pdp.PDP_TASK_AB)], bad)[0] == pdp.PDP_E_INVAL
+
+
 def test_plan_rejects_bad_tasks():
     a5, b6 = _fake_dict(10, 900, 5), _fake_dict(10, 900, 6)
     assert _plan([(a5, b6, pdp.PDP_TASK_AB)])[0] == pdp.PDP_E_INVAL
