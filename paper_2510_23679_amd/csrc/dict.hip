@@ -82,8 +82,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Ascending bitonic sort of kWave * E keys, E per lane in blocked order (lane l holds
 // elements l*E .. l*E+E-1): comparators inside a lane swap registers, the others pair
 // lanes by a shuffle and keep the minimum or maximum.
-template <uint32_t E>
-__device__ __forceinline__ void wave_bitonic_sort(uint64_t (&key)[E]) {
+template <uint32_t E, typename K>
+__device__ __forceinline__ void wave_bitonic_sort(K (&key)[E]) {
     constexpr uint32_t N = kWave * E;
     const uint32_t l = lane_id();
 #pragma unroll
@@ -95,7 +95,7 @@ __device__ __forceinline__ void wave_bitonic_sort(uint64_t (&key)[E]) {
                 for (uint32_t e = 0; e < E; ++e) {
                     if (e & j) continue;
                     const bool asc = ((l * E + e) & size) == 0;
-                    const uint64_t a = key[e], b = key[e | j];
+                    const K a = key[e], b = key[e | j];
                     const bool sw = asc ? a > b : a < b;
                     key[e] = sw ? b : a;
                     key[e | j] = sw ? a : b;
@@ -105,9 +105,9 @@ __device__ __forceinline__ void wave_bitonic_sort(uint64_t (&key)[E]) {
                 const bool lower = (l & lj) == 0;
 #pragma unroll
                 for (uint32_t e = 0; e < E; ++e) {
-                    const uint64_t o = __shfl_xor(key[e], lj, kWave);
+                    const K o = __shfl_xor(key[e], lj, kWave);
                     const bool keep_min = lower == (((l * E + e) & size) == 0);
-                    const uint64_t mn = o < key[e] ? o : key[e], mx = o < key[e] ? key[e] : o;
+                    const K mn = o < key[e] ? o : key[e], mx = o < key[e] ? key[e] : o;
                     key[e] = keep_min ? mn : mx;
                 }
             }
@@ -151,13 +151,14 @@ constexpr uint32_t kMvWaves = kMvThreads / kWave;
 // wave's bitonic network (E = 4, 8 or 16: the smallest that holds the gene), then run
 // heads ranked by a wave scan; head positions in LDS give the run lengths.  sym holds the
 // gene's residue symbols, hp kWave*E+1 slots.
-template <uint32_t E>
+// K: the key type, 32 bits when the codes fit (bits * k <= 32), halving the shuffles.
+template <uint32_t E, typename K>
 __device__ __forceinline__ void mv_wave_gene(const DevBuild &B, const uint8_t *sym, uint16_t *hp, uint64_t o,
                                              uint32_t nw, uint32_t *cnt_out) {
     const uint32_t lane = lane_id();
     const uint32_t k = B.k, bits = B.bits;
     const uint64_t mask = (1ull << (bits * k)) - 1ull;  // bits * k <= 62
-    uint64_t key[E];
+    K key[E];
     // the lane's windows p0 .. p0+E-1 are consecutive: the first k-1 letters once, then one
     // letter per window
     const uint32_t p0 = lane * E;
@@ -168,15 +169,15 @@ __device__ __forceinline__ void mv_wave_gene(const DevBuild &B, const uint8_t *s
     for (uint32_t e = 0; e < E; ++e) {
         const uint32_t p = p0 + e;
         if (p < nw) c = ((c << bits) | sym[p + k - 1]) & mask;
-        key[e] = p < nw ? c : ~0ull;  // past the windows: sorts last
+        key[e] = p < nw ? static_cast<K>(c) : static_cast<K>(~0ull);  // past the windows: sorts last
     }
-    wave_bitonic_sort<E>(key);
-    const uint64_t before = __shfl_up(key[E - 1], 1, kWave);
+    wave_bitonic_sort<E, K>(key);
+    const K before = __shfl_up(key[E - 1], 1, kWave);
     uint32_t hmask = 0, nh = 0;
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) {
         const uint32_t i = lane * E + e;
-        const uint64_t prev = e ? key[e - 1] : before;
+        const K prev = e ? key[e - 1] : before;
         const bool h = i < nw && (i == 0 || key[e] != prev);
         hmask |= static_cast<uint32_t>(h) << e;
         nh += h;
@@ -252,9 +253,15 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restri
     }
     wave_lds_sync();
     uint32_t total;
-    if (nw <= kWave * 4) mv_wave_gene<4>(B, sym, hp_all[w], o, nw, &total);
-    else if (nw <= kWave * 8) mv_wave_gene<8>(B, sym, hp_all[w], o, nw, &total);
-    else mv_wave_gene<16>(B, sym, hp_all[w], o, nw, &total);
+    if (B.bits * B.k <= 32) {  // uniform per wave
+        if (nw <= kWave * 4) mv_wave_gene<4, uint32_t>(B, sym, hp_all[w], o, nw, &total);
+        else if (nw <= kWave * 8) mv_wave_gene<8, uint32_t>(B, sym, hp_all[w], o, nw, &total);
+        else mv_wave_gene<16, uint32_t>(B, sym, hp_all[w], o, nw, &total);
+    } else {
+        if (nw <= kWave * 4) mv_wave_gene<4, uint64_t>(B, sym, hp_all[w], o, nw, &total);
+        else if (nw <= kWave * 8) mv_wave_gene<8, uint64_t>(B, sym, hp_all[w], o, nw, &total);
+        else mv_wave_gene<16, uint64_t>(B, sym, hp_all[w], o, nw, &total);
+    }
     if (lane == 0) dcnt[G] = total;
 }
 
@@ -263,8 +270,8 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restri
 // registers, those inside a wave pair lanes by shuffles, and only those across waves go
 // through LDS (xch: kMvThreads * E keys), so a stage costs a barrier only when its stride
 // spans waves.  Contains barriers; every thread of the work-group must call it.
-template <uint32_t E>
-__device__ __forceinline__ void block_bitonic_sort(uint64_t (&key)[E], uint64_t *xch) {
+template <uint32_t E, typename K>
+__device__ __forceinline__ void block_bitonic_sort(K (&key)[E], K *xch) {
     constexpr uint32_t N = kMvThreads * E;
     const uint32_t t = threadIdx.x;
     for (uint32_t size = 2; size <= N; size <<= 1) {
@@ -276,9 +283,9 @@ __device__ __forceinline__ void block_bitonic_sort(uint64_t (&key)[E], uint64_t 
             const bool lower = (t & lj) == 0;
 #pragma unroll
             for (uint32_t e = 0; e < E; ++e) {
-                const uint64_t o = xch[e * kMvThreads + (t ^ lj)];
+                const K o = xch[e * kMvThreads + (t ^ lj)];
                 const bool keep_min = lower == (((t * E + e) & size) == 0);
-                const uint64_t mn = o < key[e] ? o : key[e], mx = o < key[e] ? key[e] : o;
+                const K mn = o < key[e] ? o : key[e], mx = o < key[e] ? key[e] : o;
                 key[e] = keep_min ? mn : mx;
             }
             __syncthreads();
@@ -288,9 +295,9 @@ __device__ __forceinline__ void block_bitonic_sort(uint64_t (&key)[E], uint64_t 
             const bool lower = (t & lj) == 0;
 #pragma unroll
             for (uint32_t e = 0; e < E; ++e) {
-                const uint64_t o = __shfl_xor(key[e], lj, kWave);
+                const K o = __shfl_xor(key[e], lj, kWave);
                 const bool keep_min = lower == (((t * E + e) & size) == 0);
-                const uint64_t mn = o < key[e] ? o : key[e], mx = o < key[e] ? key[e] : o;
+                const K mn = o < key[e] ? o : key[e], mx = o < key[e] ? key[e] : o;
                 key[e] = keep_min ? mn : mx;
             }
         }
@@ -301,7 +308,7 @@ __device__ __forceinline__ void block_bitonic_sort(uint64_t (&key)[E], uint64_t 
             for (uint32_t e = 0; e < E; ++e) {
                 if (e & j) continue;
                 const bool asc = ((t * E + e) & size) == 0;
-                const uint64_t a = key[e], b = key[e | j];
+                const K a = key[e], b = key[e | j];
                 const bool sw = asc ? a > b : a < b;
                 key[e] = sw ? b : a;
                 key[e | j] = sw ? a : b;
@@ -315,6 +322,86 @@ __device__ __forceinline__ void block_bitonic_sort(uint64_t (&key)[E], uint64_t 
 // windows (one new letter per window), the work-group sorts the codes in registers, and
 // run heads ranked by a work-group scan give the multiplicity vector.  The symbols, the
 // sort's exchange area and the head positions share one LDS array.
+// One gene of k_mv_mid: len letters at offset o, nw <= kMvThreads * E windows; K as in the wave kernel.
+template <uint32_t E, typename K>
+__device__ __forceinline__ void mid_gene(const DevBuild &B, uint32_t G, uint64_t o, uint32_t len, uint32_t nw,
+                                         uint64_t *xch64, K *s_last, uint32_t *tmp, uint32_t *__restrict__ dcnt) {
+    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    const uint32_t k = B.k, bits = B.bits;
+    uint8_t *sym = reinterpret_cast<uint8_t *>(xch64);
+    uint16_t *hp = reinterpret_cast<uint16_t *>(xch64);
+    K *xch = reinterpret_cast<K *>(xch64);
+    for (uint32_t base = 0; base < len; base += 4 * kMvThreads) {  // 4 loads in flight per thread
+        uint32_t res[4];
+#pragma unroll
+        for (uint32_t it = 0; it < 4; ++it) {
+            const uint32_t p = base + it * kMvThreads + tid;
+            res[it] = p < len ? B.res[o + p] : 'A';
+        }
+#pragma unroll
+        for (uint32_t it = 0; it < 4; ++it) {
+            const uint32_t p = base + it * kMvThreads + tid;
+            if (p >= len) continue;
+            uint32_t x = sym_in(res[it], bits);
+            if (x == kInvalidSym) {
+                raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
+                x = 0;
+            }
+            sym[p] = static_cast<uint8_t>(x);
+        }
+    }
+    __syncthreads();
+    K key[E];
+    {
+        const uint64_t mask = (1ull << (bits * k)) - 1ull;
+        const uint32_t p0 = tid * E;
+        uint64_t c = 0;
+        if (p0 < nw)
+            for (uint32_t j = 0; j + 1 < k; ++j) c = (c << bits) | sym[p0 + j];
+#pragma unroll
+        for (uint32_t e = 0; e < E; ++e) {
+            const uint32_t p = p0 + e;
+            if (p < nw) c = ((c << bits) | sym[p + k - 1]) & mask;
+            key[e] = p < nw ? static_cast<K>(c) : static_cast<K>(~0ull);  // past the windows: sorts last
+        }
+    }
+    __syncthreads();  // the symbols are read before the sort overwrites them
+    block_bitonic_sort<E, K>(key, xch);
+    if (lane == kWave - 1) s_last[w] = key[E - 1];
+    K before = __shfl_up(key[E - 1], 1, kWave);
+    __syncthreads();
+    if (lane == 0 && w > 0) before = s_last[w - 1];
+    uint32_t hmask = 0, nh = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+        const uint32_t i = tid * E + e;
+        const K prev = e ? key[e - 1] : before;
+        const bool h = i < nw && (i == 0 || key[e] != prev);
+        hmask |= static_cast<uint32_t>(h) << e;
+        nh += h;
+    }
+    uint32_t total;
+    const uint32_t r0 = block_exclusive_scan<kMvThreads>(nh, tmp, &total);
+    uint32_t r = r0;
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e)
+        if ((hmask >> e) & 1u) hp[r++] = static_cast<uint16_t>(tid * E + e);
+    if (tid == 0) hp[total] = static_cast<uint16_t>(nw);
+    __syncthreads();
+    uint64_t *slot_code = B.slot_code + o;
+    uint32_t *slot_cnt = B.slot_cnt + o;
+    r = r0;
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+        if (!((hmask >> e) & 1u)) continue;
+        slot_code[r] = key[e];
+        slot_cnt[r] = static_cast<uint32_t>(hp[r + 1]) - hp[r];
+        ++r;
+    }
+    if (tid == 0) dcnt[G] = total;
+    __syncthreads();  // LDS takes the next gene
+}
+
 template <uint32_t E>
 __global__ __launch_bounds__(kMvThreads) void k_mv_mid(const DevBuild *__restrict__ table, uint32_t *__restrict__ dcnt,
                                                        const uint64_t *__restrict__ list,
@@ -324,88 +411,18 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_mid(const DevBuild *__restric
     __shared__ uint64_t xch[N];
     __shared__ uint64_t s_last[kMvWaves];
     __shared__ uint32_t tmp[kMvWaves + 1];
-    uint8_t *sym = reinterpret_cast<uint8_t *>(xch);
-    uint16_t *hp = reinterpret_cast<uint16_t *>(xch);
     const uint32_t n_items = *count;
-    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     for (uint32_t li = blockIdx.x; li < n_items; li += gridDim.x) {
         const uint64_t item = list[li];
         const DevBuild &B = table[item >> 32];
         const uint32_t g = static_cast<uint32_t>(item);
-        const uint32_t G = B.gene_base + g;
-        const uint32_t k = B.k, bits = B.bits;
         const uint64_t o = B.off[g];
         const uint32_t len = static_cast<uint32_t>(B.off[g + 1] - o);
-        const uint32_t nw = len - k + 1;  // k_mv_wave queued this gene for nw <= N
-        for (uint32_t base = 0; base < len; base += 4 * kMvThreads) {  // 4 loads in flight per thread
-            uint32_t res[4];
-#pragma unroll
-            for (uint32_t it = 0; it < 4; ++it) {
-                const uint32_t p = base + it * kMvThreads + tid;
-                res[it] = p < len ? B.res[o + p] : 'A';
-            }
-#pragma unroll
-            for (uint32_t it = 0; it < 4; ++it) {
-                const uint32_t p = base + it * kMvThreads + tid;
-                if (p >= len) continue;
-                uint32_t x = sym_in(res[it], bits);
-                if (x == kInvalidSym) {
-                    raise_status(B.status, PDP_E_ALPHABET, 0, o + p);
-                    x = 0;
-                }
-                sym[p] = static_cast<uint8_t>(x);
-            }
-        }
-        __syncthreads();
-        uint64_t key[E];
-        {
-            const uint64_t mask = (1ull << (bits * k)) - 1ull;
-            const uint32_t p0 = tid * E;
-            uint64_t c = 0;
-            if (p0 < nw)
-                for (uint32_t j = 0; j + 1 < k; ++j) c = (c << bits) | sym[p0 + j];
-#pragma unroll
-            for (uint32_t e = 0; e < E; ++e) {
-                const uint32_t p = p0 + e;
-                if (p < nw) c = ((c << bits) | sym[p + k - 1]) & mask;
-                key[e] = p < nw ? c : ~0ull;  // past the windows: sorts last
-            }
-        }
-        __syncthreads();  // the symbols are read before the sort overwrites them
-        block_bitonic_sort<E>(key, xch);
-        if (lane == kWave - 1) s_last[w] = key[E - 1];
-        uint64_t before = __shfl_up(key[E - 1], 1, kWave);
-        __syncthreads();
-        if (lane == 0 && w > 0) before = s_last[w - 1];
-        uint32_t hmask = 0, nh = 0;
-#pragma unroll
-        for (uint32_t e = 0; e < E; ++e) {
-            const uint32_t i = tid * E + e;
-            const uint64_t prev = e ? key[e - 1] : before;
-            const bool h = i < nw && (i == 0 || key[e] != prev);
-            hmask |= static_cast<uint32_t>(h) << e;
-            nh += h;
-        }
-        uint32_t total;
-        const uint32_t r0 = block_exclusive_scan<kMvThreads>(nh, tmp, &total);
-        uint32_t r = r0;
-#pragma unroll
-        for (uint32_t e = 0; e < E; ++e)
-            if ((hmask >> e) & 1u) hp[r++] = static_cast<uint16_t>(tid * E + e);
-        if (tid == 0) hp[total] = static_cast<uint16_t>(nw);
-        __syncthreads();
-        uint64_t *slot_code = B.slot_code + o;
-        uint32_t *slot_cnt = B.slot_cnt + o;
-        r = r0;
-#pragma unroll
-        for (uint32_t e = 0; e < E; ++e) {
-            if (!((hmask >> e) & 1u)) continue;
-            slot_code[r] = key[e];
-            slot_cnt[r] = static_cast<uint32_t>(hp[r + 1]) - hp[r];
-            ++r;
-        }
-        if (tid == 0) dcnt[G] = total;
-        __syncthreads();  // LDS takes the next gene
+        const uint32_t nw = len - B.k + 1;  // k_mv_wave queued this gene for nw <= kMvThreads * E
+        if (B.bits * B.k <= 32)  // uniform per work-group
+            mid_gene<E, uint32_t>(B, B.gene_base + g, o, len, nw, xch, reinterpret_cast<uint32_t *>(s_last), tmp, dcnt);
+        else
+            mid_gene<E, uint64_t>(B, B.gene_base + g, o, len, nw, xch, s_last, tmp, dcnt);
     }
 }
 
