@@ -22,7 +22,7 @@ constexpr uint32_t kKMaxAll = PDP_K_MAX_NT > PDP_K_MAX ? PDP_K_MAX_NT : PDP_K_MA
 constexpr uint32_t kIxBlock = 8192;          // index entries per histogram block
 constexpr uint32_t kIxBinTarget = 512;       // average index entries per coarse bin
 constexpr uint32_t kIxBinLds = 1024;         // coarse bins up to this size are sorted in LDS
-constexpr uint32_t kIxBinSlots = 1024;       // counting-sort slots of a bin (buckets x sub-slots)
+constexpr uint32_t kIxBinSlots = 2048;       // counting-sort slots of a bin (buckets x sub-slots)
 constexpr uint32_t kIxMaxBins = 8192;        // coarse bins per genome at most (LDS histogram)
 constexpr uint32_t kJoinLdsCap = 1024;       // target index entries staged in LDS per join sub-range
 constexpr uint32_t kJoinLdsCapP = 2048;      // the same for dictionaries with packed 32-bit keys
