@@ -32,7 +32,8 @@ hipError_t launch_status_init(pdp_status *st, hipStream_t s) {
 
 // ----------------------------------------------------------------- scan
 // Three phases: per-group sums, a scan of the sums by one group, and a
-// per-group scan that adds the group's offset.  A group covers kScanItems
+// per-group scan that adds the group's offset (up to kScanFuseGroups groups the
+// second phase folds into the third).  A group covers kScanItems
 // consecutive values (16 per thread, blocked).
 constexpr uint32_t kScanThreads = 256;
 constexpr uint32_t kScanPer = kScanItems / kScanThreads;
@@ -62,6 +63,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(uint32_t *partials, u
     }
 }
 
+// FUSED: partials holds the groups' plain sums (no k_scan_top), and every group adds up
+// those of the groups before it itself, so a scan of up to kScanFuseGroups groups takes
+// two launches instead of three.
+template <bool FUSED>
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t *in, uint32_t *out, uint64_t n,
                                                               const uint32_t *partials, uint32_t nb) {
     __shared__ uint32_t tmp[kScanThreads / kWave + 1];
@@ -73,8 +78,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t *in,
         v[j] = base + j < n ? in[base + j] : 0u;
         s += v[j];
     }
+    uint32_t before = 0;
+    if (FUSED) {
+        uint32_t mine = 0;
+        for (uint32_t g = threadIdx.x; g < blockIdx.x; g += kScanThreads) mine += partials[g];
+        uint32_t all;
+        (void)block_exclusive_scan<kScanThreads>(mine, tmp, &all);
+        before = all;
+    } else if (nb > 1) {
+        before = partials[blockIdx.x];
+    }
     uint32_t total;
-    uint32_t run = block_exclusive_scan<kScanThreads>(s, tmp, &total) + (nb > 1 ? partials[blockIdx.x] : 0u);
+    uint32_t run = block_exclusive_scan<kScanThreads>(s, tmp, &total) + before;
 #pragma unroll
     for (uint32_t j = 0; j < kScanPer; ++j) {
         if (base + j < n) out[base + j] = run;
@@ -86,14 +101,21 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t *in,
     }
 }
 
+constexpr uint32_t kScanFuseGroups = 1024;  // up to here each group sums the earlier group totals itself
+
 hipError_t launch_scan(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *partials, hipStream_t s) {
     const uint32_t nb = static_cast<uint32_t>((n + kScanItems - 1) / kScanItems);
     if (nb == 0) return launch_fill_u32(out, 1, 0u, s);
-    if (nb > 1) {
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_apply<false>, dim3(1), dim3(kScanThreads), 0, s, in, out, n, partials, nb);
+    } else if (nb <= kScanFuseGroups) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, in, n, partials);
+        hipLaunchKernelGGL(k_scan_apply<true>, dim3(nb), dim3(kScanThreads), 0, s, in, out, n, partials, nb);
+    } else {
         hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, in, n, partials);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, partials, nb);
+        hipLaunchKernelGGL(k_scan_apply<false>, dim3(nb), dim3(kScanThreads), 0, s, in, out, n, partials, nb);
     }
-    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, s, in, out, n, partials, nb);
     return hipGetLastError();
 }
 
