@@ -35,12 +35,13 @@ namespace pdp {
 constexpr uint32_t kMvThreads = 256;
 static_assert(kMvSortCap == kMvThreads * 32, "the largest k_mv_mid class sorts 32 codes per thread");
 constexpr uint32_t kIxBatch = 8;  // index entries a thread loads per round in the histogram and placement
-constexpr uint32_t kDescPerLaunch = 8;
+constexpr uint32_t kDescPerLaunch = 16;
 
 struct DescChunk {
     uint32_t first, count;
     DevBuild d[kDescPerLaunch];
 };
+static_assert(sizeof(DescChunk) <= 4096, "descriptor chunks travel as kernel arguments");
 
 // Copies descriptors passed by value into the workspace table (kernel
 // arguments are captured at launch, so the host copy may go away at once).
@@ -61,14 +62,22 @@ __device__ __forceinline__ uint32_t find_genome_by_gene(const DevBuild *t, uint3
 }
 
 
-__global__ void k_build_init(const DevBuild *table, uint32_t n) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    pdp_status *st = table[t].status;
-    st->code = 0;
-    st->reserved = 0;
-    st->needed = 0;
-    st->where = ~0ull;
+// Set-up of a build in one launch: every genome's status cleared and the CSR of a genome
+// without genes written (nothing else writes it), the build's counters and the bin totals
+// zeroed.
+__global__ void k_build_init(const DevBuild *table, uint32_t n, uint32_t *counters, uint32_t *bintot,
+                             uint32_t total_bins) {
+    const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    for (uint32_t t = i0; t < n; t += stride) {
+        pdp_status *st = table[t].status;
+        st->code = 0;
+        st->reserved = 0;
+        st->needed = 0;
+        st->where = ~0ull;
+        if (table[t].n_genes == 0) table[t].mv_ptr[0] = 0;
+    }
+    if (i0 < 4) counters[i0] = 0;
+    for (uint32_t b = i0; b < total_bins; b += stride) bintot[b] = 0;
 }
 
 // Orders LDS writes of a wave before its later LDS reads (a wave runs in lock step,
@@ -504,11 +513,6 @@ __global__ __launch_bounds__(kWave) void k_mv_compact(const DevBuild *__restrict
     }
 }
 
-// Per genome: empty CSR of a genome without genes.
-__global__ void k_mv_empty(const DevBuild *table, uint32_t n) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n && table[t].n_genes == 0) table[t].mv_ptr[0] = 0;
-}
 
 __device__ __forceinline__ uint32_t find_genome_by_block(const DevBuild *t, uint32_t n, uint32_t blk) {
     uint32_t lo = 0, hi = n - 1;
@@ -988,12 +992,11 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
         PDP_TRY(hipGetLastError());
     }
     const uint32_t tg = static_cast<uint32_t>(sh.total_genes);
-    const uint32_t gblocks = (n + 255) / 256;
     const uint32_t hist_lds = static_cast<uint32_t>(4 * sh.max_nh);
-    hipLaunchKernelGGL(k_build_init, dim3(gblocks), dim3(256), 0, s, table, n);
+    const uint64_t init_items = std::max<uint64_t>(std::max<uint64_t>(n, sh.total_bins), 4);
+    hipLaunchKernelGGL(k_build_init, dim3(static_cast<uint32_t>(std::min<uint64_t>((init_items + 255) / 256, 1024))),
+                       dim3(256), 0, s, table, n, counters, bintot, static_cast<uint32_t>(sh.total_bins));
     PDP_TRY(hipGetLastError());
-    PDP_TRY(launch_fill_u32(counters, 4, 0u, s));
-    PDP_TRY(launch_fill_u32(bintot, sh.total_bins, 0u, s));
     if (tg > 0) {
         hipLaunchKernelGGL(k_mv_wave, dim3((tg + kMvWaves - 1) / kMvWaves), dim3(kMvThreads), 0, s, table, n, tg, dcnt,
                            mid_list, long_list, stride, counters);
@@ -1002,19 +1005,18 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
         const uint32_t mid_groups = tg < 2048 ? tg : 2048;
         hipLaunchKernelGGL(k_mv_mid<8>, dim3(mid_groups), dim3(kMvThreads), 0, s, table, dcnt, mid_list, counters + 1);
         PDP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_mv_mid<16>, dim3(mid_groups), dim3(kMvThreads), 0, s, table, dcnt, mid_list + stride,
-                           counters + 2);
+        // the larger classes hold fewer genes and fewer work-groups fit a CU: smaller grids
+        hipLaunchKernelGGL(k_mv_mid<16>, dim3(std::min(mid_groups, 1024u)), dim3(kMvThreads), 0, s, table, dcnt,
+                           mid_list + stride, counters + 2);
         PDP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_mv_mid<32>, dim3(mid_groups), dim3(kMvThreads), 0, s, table, dcnt, mid_list + 2 * stride,
-                           counters + 3);
+        hipLaunchKernelGGL(k_mv_mid<32>, dim3(std::min(mid_groups, 512u)), dim3(kMvThreads), 0, s, table, dcnt,
+                           mid_list + 2 * stride, counters + 3);
         PDP_TRY(hipGetLastError());
         const uint32_t long_groups = tg < 64 ? tg : 64;
         hipLaunchKernelGGL(k_mv_long, dim3(long_groups), dim3(kMvThreads), 0, s, table, dcnt, long_list, counters);
         PDP_TRY(hipGetLastError());
     }
     PDP_TRY(launch_scan(dcnt, dcnt, tg, partials, s));  // in place: dcnt becomes the global offsets
-    hipLaunchKernelGGL(k_mv_empty, dim3(gblocks), dim3(256), 0, s, table, n);
-    PDP_TRY(hipGetLastError());
     if (tg > 0) {
         hipLaunchKernelGGL(k_mv_compact, dim3(tg), dim3(kWave), 0, s, table, n, dcnt, ent_gene);
         PDP_TRY(hipGetLastError());

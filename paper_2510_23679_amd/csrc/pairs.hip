@@ -379,6 +379,16 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
     __syncthreads();
 }
 
+__global__ void k_pairs_init(pdp_status *st, uint32_t *counters) {
+    if (threadIdx.x == 0) {
+        st->code = 0;
+        st->reserved = 0;
+        st->needed = 0;
+        st->where = ~0ull;
+    }
+    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+}
+
 // The write pass stops when the records do not fit; the count pass's total is then the
 // capacity needed.
 __device__ __forceinline__ bool join_overflow(const unsigned long long *total, uint64_t rec_cap, pdp_status *st) {
@@ -1326,10 +1336,10 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     };
     const uint32_t lds_words = p.tile_lds / 4;
     PDP_TRY(mark(PDP_KERNEL_ALL, true));
-    PDP_TRY(launch_status_init(st, s));
-    // counters: record total (64 bits), overflow tiles, next join item (count pass), next tile,
-    // next join item (write pass)
-    PDP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(w.counters), 8, 0u, s));
+    // status and counters (record total (64 bits), overflow tiles, next join item (count
+    // pass), next tile, next join item (write pass), column candidates) in one launch
+    hipLaunchKernelGGL(k_pairs_init, dim3(1), dim3(64), 0, s, st, reinterpret_cast<uint32_t *>(w.counters));
+    PDP_TRY(hipGetLastError());
     const ColWs cmx{w.colkey, w.cands, w.cand_count, p.colmax ? p.cand_cap : 0};
     if (p.colmax) {  // BA rows are counted by atomics; column keys and cursors start at zero
         PDP_TRY(launch_fill_u32(bh->ptr, uint64_t(p.bh_rows) + 1, 0u, s));
