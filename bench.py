@@ -35,7 +35,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--kernel", default="join", help="kernel for the roofline entry (join, bucket, tile_count, "
                                                     "tile_write, bbh)")
-    p.add_argument("--cpu-rows", type=int, default=128, help="rows per direction per pair in the CPU-oracle sample")
+    p.add_argument("--cpu-rows", type=int, default=None,
+                   help="rows per direction per pair in the CPU-oracle sample (default: 384 amino-acid, 128 nucleotide "
+                        "rows, about 15 s of oracle work)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--breakdown", action="store_true", help="also time every kernel group (extra launches)")
     p.add_argument("--calibrate-copy", action="store_true", help="only run a copy of known size (counter calibration)")
@@ -509,7 +511,7 @@ def main():
         "breakdown": breakdown,
     }
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(ds, k, args.cpu_rows)
+        cb = cpu_baseline(ds, k, args.cpu_rows or (128 if nt else 384))
         cb["gpu_over_cpu"] = round(value / cb["value"], 1)
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
