@@ -575,7 +575,9 @@ __global__ __launch_bounds__(256) void k_ix_hist(const DevBuild *__restrict__ ta
         if (h[i]) atomicAdd(&bintot[B.bin_base + i], h[i]);
 }
 
-constexpr uint32_t kIxPerThread = kIxBlock / 256;  // entries a placement thread keeps in registers
+constexpr uint32_t kIxPlaceThreads = 512;  // a placement work-group: its block of entries in registers
+constexpr uint32_t kIxPerThread = kIxBlock / kIxPlaceThreads;  // entries a placement thread keeps
+static_assert(kIxPerThread % kIxBatch == 0, "placement rounds divide the entries of a thread");
 
 // Same blocks: each entry goes to its bin's range.  The block counts its entries per bin in
 // LDS (every entry's rank among the block's entries of its bin comes back from the LDS
@@ -583,7 +585,7 @@ constexpr uint32_t kIxPerThread = kIxBlock / 256;  // entries a placement thread
 // count (binoff holds the scanned totals; the runs of a bin are handed out from its end),
 // and writes each entry at its run start plus its rank.  The order inside a bin depends on
 // scheduling; k_ix_sort_bin sorts every bin completely.
-__global__ __launch_bounds__(256) void k_ix_place(const DevBuild *__restrict__ table, uint32_t n_genomes,
+__global__ __launch_bounds__(kIxPlaceThreads) void k_ix_place(const DevBuild *__restrict__ table, uint32_t n_genomes,
                                                   const uint32_t *__restrict__ gptr, const uint32_t *__restrict__ binoff,
                                                   uint32_t *__restrict__ bintot, const uint32_t *__restrict__ ent_gene) {
     extern __shared__ uint32_t cur[];
@@ -600,12 +602,12 @@ __global__ __launch_bounds__(256) void k_ix_place(const DevBuild *__restrict__ t
     uint32_t rank[kIxPerThread];
 #pragma unroll
     for (uint32_t q = 0; q < kIxPerThread; ++q) {
-        const uint32_t e = e0 + q * 256 + threadIdx.x;
+        const uint32_t e = e0 + q * kIxPlaceThreads + threadIdx.x;
         c[q] = e < e1 ? B.mv_code[e] : 0ull;
     }
 #pragma unroll
     for (uint32_t q = 0; q < kIxPerThread; ++q)
-        if (e0 + q * 256 + threadIdx.x < e1) rank[q] = atomicAdd(&cur[bucket_of(c[q], B.k, B.lead, B.bits) >> B.hshift], 1u);
+        if (e0 + q * kIxPlaceThreads + threadIdx.x < e1) rank[q] = atomicAdd(&cur[bucket_of(c[q], B.k, B.lead, B.bits) >> B.hshift], 1u);
     __syncthreads();
     const uint32_t gstart = binoff[B.bin_base];  // the genome's first entry in the scanned order
     for (uint32_t i = threadIdx.x; i < B.nh; i += blockDim.x) {
@@ -617,14 +619,14 @@ __global__ __launch_bounds__(256) void k_ix_place(const DevBuild *__restrict__ t
         uint32_t gn[kIxBatch], ct[kIxBatch];
 #pragma unroll
         for (uint32_t q = 0; q < kIxBatch; ++q) {
-            const uint32_t e = e0 + (q0 + q) * 256 + threadIdx.x;
+            const uint32_t e = e0 + (q0 + q) * kIxPlaceThreads + threadIdx.x;
             const bool v = e < e1;
             gn[q] = v ? ent_gene[gbase + e] : 0u;
             ct[q] = v ? B.mv_cnt[e] : 0u;
         }
 #pragma unroll
         for (uint32_t q = 0; q < kIxBatch; ++q) {
-            if (e0 + (q0 + q) * 256 + threadIdx.x >= e1) continue;
+            if (e0 + (q0 + q) * kIxPlaceThreads + threadIdx.x >= e1) continue;
             const uint64_t code = c[q0 + q];
             const uint32_t pos = cur[bucket_of(code, B.k, B.lead, B.bits) >> B.hshift] + rank[q0 + q];
             // one 16-byte record per entry: a single scattered store instead of three
@@ -1025,7 +1027,8 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
                        bintot);
     PDP_TRY(hipGetLastError());
     PDP_TRY(launch_scan(bintot, binoff, sh.total_bins, partials, s));  // every bin's range
-    hipLaunchKernelGGL(k_ix_place, dim3(static_cast<uint32_t>(sh.total_blocks)), dim3(256), hist_lds, s, table, n, dcnt,
+    hipLaunchKernelGGL(k_ix_place, dim3(static_cast<uint32_t>(sh.total_blocks)), dim3(kIxPlaceThreads), hist_lds, s, table,
+                       n, dcnt,
                        binoff, bintot, ent_gene);
     PDP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_ix_sort_bin, dim3(static_cast<uint32_t>(sh.total_bins)), dim3(256), 0, s, table, n, binoff);

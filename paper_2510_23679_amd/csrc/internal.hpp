@@ -19,7 +19,7 @@ namespace pdp {
 constexpr uint32_t kScanItems = 4096;        // elements per scan work-group (256 threads x 16)
 constexpr uint32_t kMvSortCap = 8192;        // windows a gene may have to be sorted in LDS
 constexpr uint32_t kKMaxAll = PDP_K_MAX_NT > PDP_K_MAX ? PDP_K_MAX_NT : PDP_K_MAX;  // k bound over alphabets
-constexpr uint32_t kIxBlock = 8192;          // index entries per histogram block
+constexpr uint32_t kIxBlock = 16384;         // index entries per histogram block
 constexpr uint32_t kIxBinTarget = 512;       // average index entries per coarse bin
 constexpr uint32_t kIxBinLds = 1024;         // coarse bins up to this size are sorted in LDS
 constexpr uint32_t kIxBinSlots = 2048;       // counting-sort slots of a bin (buckets x sub-slots)
