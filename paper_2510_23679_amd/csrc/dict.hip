@@ -214,6 +214,9 @@ __device__ __forceinline__ void mv_wave_gene(const DevBuild &B, const uint8_t *s
 
 // Longer genes go to lists by size: counters[0] / long_list past kMvSortCap windows,
 // counters[c] / mid_list + (c - 1) * stride for k_mv_mid<8 << (c - 1)>, c = 1, 2, 3.
+// NARROW: every genome of the build has codes of at most 32 bits (a separate instance without
+// the 64-bit path, which needs fewer registers).
+template <bool NARROW>
 __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restrict__ table, uint32_t n_genomes,
                                                         uint32_t total_genes, uint32_t *__restrict__ dcnt,
                                                         uint64_t *__restrict__ mid_list, uint64_t *__restrict__ long_list,
@@ -262,14 +265,16 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restri
     }
     wave_lds_sync();
     uint32_t total;
-    if (B.bits * B.k <= 32) {  // uniform per wave
+    if (NARROW || B.bits * B.k <= 32) {  // uniform per wave
         if (nw <= kWave * 4) mv_wave_gene<4, uint32_t>(B, sym, hp_all[w], o, nw, &total);
         else if (nw <= kWave * 8) mv_wave_gene<8, uint32_t>(B, sym, hp_all[w], o, nw, &total);
         else mv_wave_gene<16, uint32_t>(B, sym, hp_all[w], o, nw, &total);
     } else {
-        if (nw <= kWave * 4) mv_wave_gene<4, uint64_t>(B, sym, hp_all[w], o, nw, &total);
-        else if (nw <= kWave * 8) mv_wave_gene<8, uint64_t>(B, sym, hp_all[w], o, nw, &total);
-        else mv_wave_gene<16, uint64_t>(B, sym, hp_all[w], o, nw, &total);
+        if constexpr (!NARROW) {
+            if (nw <= kWave * 4) mv_wave_gene<4, uint64_t>(B, sym, hp_all[w], o, nw, &total);
+            else if (nw <= kWave * 8) mv_wave_gene<8, uint64_t>(B, sym, hp_all[w], o, nw, &total);
+            else mv_wave_gene<16, uint64_t>(B, sym, hp_all[w], o, nw, &total);
+        }
     }
     if (lane == 0) dcnt[G] = total;
 }
@@ -411,7 +416,7 @@ __device__ __forceinline__ void mid_gene(const DevBuild &B, uint32_t G, uint64_t
     __syncthreads();  // LDS takes the next gene
 }
 
-template <uint32_t E>
+template <uint32_t E, bool NARROW>
 __global__ __launch_bounds__(kMvThreads) void k_mv_mid(const DevBuild *__restrict__ table, uint32_t *__restrict__ dcnt,
                                                        const uint64_t *__restrict__ list,
                                                        const uint32_t *__restrict__ count) {
@@ -428,10 +433,11 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_mid(const DevBuild *__restric
         const uint64_t o = B.off[g];
         const uint32_t len = static_cast<uint32_t>(B.off[g + 1] - o);
         const uint32_t nw = len - B.k + 1;  // k_mv_wave queued this gene for nw <= kMvThreads * E
-        if (B.bits * B.k <= 32)  // uniform per work-group
+        if (NARROW || B.bits * B.k <= 32) {  // uniform per work-group
             mid_gene<E, uint32_t>(B, B.gene_base + g, o, len, nw, xch, reinterpret_cast<uint32_t *>(s_last), tmp, dcnt);
-        else
-            mid_gene<E, uint64_t>(B, B.gene_base + g, o, len, nw, xch, s_last, tmp, dcnt);
+        } else {
+            if constexpr (!NARROW) mid_gene<E, uint64_t>(B, B.gene_base + g, o, len, nw, xch, s_last, tmp, dcnt);
+        }
     }
 }
 
@@ -1000,19 +1006,37 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
                        dim3(256), 0, s, table, n, counters, bintot, static_cast<uint32_t>(sh.total_bins));
     PDP_TRY(hipGetLastError());
     if (tg > 0) {
-        hipLaunchKernelGGL(k_mv_wave, dim3((tg + kMvWaves - 1) / kMvWaves), dim3(kMvThreads), 0, s, table, n, tg, dcnt,
-                           mid_list, long_list, stride, counters);
+        bool narrow = true;
+        for (uint32_t i = 0; i < n; ++i) narrow &= alpha_spec(d[i]->alphabet).bits * d[i]->k <= 32;
+        if (narrow)
+            hipLaunchKernelGGL(k_mv_wave<true>, dim3((tg + kMvWaves - 1) / kMvWaves), dim3(kMvThreads), 0, s, table, n,
+                               tg, dcnt, mid_list, long_list, stride, counters);
+        else
+            hipLaunchKernelGGL(k_mv_wave<false>, dim3((tg + kMvWaves - 1) / kMvWaves), dim3(kMvThreads), 0, s, table, n,
+                               tg, dcnt, mid_list, long_list, stride, counters);
         PDP_TRY(hipGetLastError());
-        // a fixed grid per size class; work-groups past the class's gene count exit at once
+        // a fixed grid per size class; work-groups past the class's gene count exit at once; the
+        // larger classes hold fewer genes and fewer work-groups fit a CU: smaller grids
         const uint32_t mid_groups = tg < 2048 ? tg : 2048;
-        hipLaunchKernelGGL(k_mv_mid<8>, dim3(mid_groups), dim3(kMvThreads), 0, s, table, dcnt, mid_list, counters + 1);
-        PDP_TRY(hipGetLastError());
-        // the larger classes hold fewer genes and fewer work-groups fit a CU: smaller grids
-        hipLaunchKernelGGL(k_mv_mid<16>, dim3(std::min(mid_groups, 1024u)), dim3(kMvThreads), 0, s, table, dcnt,
-                           mid_list + stride, counters + 2);
-        PDP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_mv_mid<32>, dim3(std::min(mid_groups, 512u)), dim3(kMvThreads), 0, s, table, dcnt,
-                           mid_list + 2 * stride, counters + 3);
+        if (narrow) {
+            hipLaunchKernelGGL((k_mv_mid<8, true>), dim3(mid_groups), dim3(kMvThreads), 0, s, table, dcnt, mid_list,
+                               counters + 1);
+            PDP_TRY(hipGetLastError());
+            hipLaunchKernelGGL((k_mv_mid<16, true>), dim3(std::min(mid_groups, 1024u)), dim3(kMvThreads), 0, s, table,
+                               dcnt, mid_list + stride, counters + 2);
+            PDP_TRY(hipGetLastError());
+            hipLaunchKernelGGL((k_mv_mid<32, true>), dim3(std::min(mid_groups, 512u)), dim3(kMvThreads), 0, s, table,
+                               dcnt, mid_list + 2 * stride, counters + 3);
+        } else {
+            hipLaunchKernelGGL((k_mv_mid<8, false>), dim3(mid_groups), dim3(kMvThreads), 0, s, table, dcnt, mid_list,
+                               counters + 1);
+            PDP_TRY(hipGetLastError());
+            hipLaunchKernelGGL((k_mv_mid<16, false>), dim3(std::min(mid_groups, 1024u)), dim3(kMvThreads), 0, s, table,
+                               dcnt, mid_list + stride, counters + 2);
+            PDP_TRY(hipGetLastError());
+            hipLaunchKernelGGL((k_mv_mid<32, false>), dim3(std::min(mid_groups, 512u)), dim3(kMvThreads), 0, s, table,
+                               dcnt, mid_list + 2 * stride, counters + 3);
+        }
         PDP_TRY(hipGetLastError());
         const uint32_t long_groups = tg < 64 ? tg : 64;
         hipLaunchKernelGGL(k_mv_long, dim3(long_groups), dim3(kMvThreads), 0, s, table, dcnt, long_list, counters);
