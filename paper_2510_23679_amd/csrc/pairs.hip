@@ -42,7 +42,7 @@ namespace pdp {
 
 constexpr uint32_t kJoinThreads = 256;
 constexpr uint32_t kJoinUnroll = 4;   // query entries a join thread loads at once (64-bit codes)
-constexpr uint32_t kJoinUnrollP = 8;  // the same with packed keys
+constexpr uint32_t kJoinUnrollP = 4;  // the same with packed keys
 static_assert(kTilePer * (kTileThreads / kWave) <= kWave, "tile head counts are scanned by one wave");
 
 // LDS of one join item: the task descriptor, the item's slice of both bucket
