@@ -14,15 +14,16 @@
 // 2. A scan of the distinct-k-mer counts of all genes gives the CSR offsets,
 //    and k_mv_compact packs the vectors (and notes each entry's gene).
 // 3. The inverted index (all entries ordered by k-mer code, ties by gene) is a
-//    two-level partition with no global atomics: the leading-residue buckets
-//    are grouped into coarse bins of 2^s buckets (s per genome, ~1K entries
-//    per bin); k_ix_hist counts bins per block of entries in LDS and adds
-//    them to the bin totals, a scan gives every bin its output range,
-//    k_ix_place hands each block a run of every bin's range (one atomic per
-//    block and bin) and drops its entries there by LDS rank, and k_ix_sort_bin sorts each bin by (code, gene) in LDS
-//    (a counting sort by bucket and the next one or two letters, which leaves
-//    about one entry per slot, then a sort inside each slot) and writes the
-//    bin's part of the bucket directory.
+//    two-level partition: the leading-letter buckets are grouped into coarse
+//    bins of 2^s buckets (s per genome, ~500 entries per bin); k_ix_hist
+//    counts bins per block of entries in LDS and adds them to the bin totals
+//    (one global atomic per block and bin), a scan gives every bin its output
+//    range, k_ix_place hands each block a run of every bin's range (again one
+//    atomic per block and bin) and drops its entries there by LDS rank, and
+//    k_ix_sort_bin sorts each bin by (code, gene) in LDS (a counting sort by
+//    bucket and the next one or two letters, which leaves about one entry per
+//    slot, then a sort inside each slot) and writes the bin's part of the
+//    bucket directory.
 // Genes and buckets of all genomes of a call are numbered consecutively; a
 // work-group finds its genome by binary search over the per-genome bases.
 #include <algorithm>

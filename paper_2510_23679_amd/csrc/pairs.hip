@@ -5,7 +5,7 @@
 // maxima over the union is then n_a + n_b - m (max + min = x + y per k-mer).
 // The path never forms the |A| x |B| matrix, in HBM or in LDS:
 //  1. k_join (count pass): both genomes' inverted indexes are sorted by code
-//     and split into the same leading-residue bucket ranges.  A work-group
+//     and split into the same leading-letter bucket ranges.  A work-group
 //     takes one range ("item"), stages the target side in LDS, finds the
 //     partners of every query entry through the bucket directory, and counts
 //     the records each accumulation tile (2^s rows of one direction) will get
@@ -93,7 +93,7 @@ __device__ __forceinline__ uint32_t find_task_coop(const DevTask *tasks, uint32_
 
 // Query entries [a0, a1) of genome a against the target entries staged from b0 on
 // (bc/bg/bn, indexed relative to b0).  The partners of a query code lie in its
-// leading-residue bucket, whose target range the directory slice bdir gives (index
+// leading-letter bucket, whose target range the directory slice bdir gives (index
 // bucket - bl); a binary search inside that bucket finds the first equal code.
 // WRITE = false adds the records each tile will receive to tcount; WRITE = true
 // takes slots from the tcount cursors and writes the records.  No barriers.
@@ -164,7 +164,7 @@ __device__ __forceinline__ void join_range(const DevTask &T, uint32_t a0, uint32
 }
 
 // Packed form of the join, used when both dictionaries carry 32-bit (tail, gene) keys:
-// entries are compared by the tail (the code without its leading residues, which the
+// entries are compared by the tail (the code without its leading letters, which the
 // bucket fixes), so an entry moves 4 bytes (8 in the write pass, with its count) instead
 // of 16, and twice as many target entries fit the LDS stage.  A query entry's bucket
 // comes from the staged query directory (the last bucket starting at or before it).
@@ -257,7 +257,7 @@ __device__ __forceinline__ void join_range_p(const DevTask &T, JoinRoundP &r, bo
     }
 }
 
-// One join item: up to T.subs consecutive sub-ranges of T.bpw leading-residue buckets of
+// One join item: up to T.subs consecutive sub-ranges of T.bpw leading-letter buckets of
 // one task.  The count pass stores the item's column of the task's (tile, item) count
 // matrix and adds its total to *total; the write pass seeds its tile cursors from the
 // scanned matrix and writes the records.  Ends with a barrier so the LDS can take the
