@@ -302,7 +302,7 @@ int32_t pdp_plan_launch(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, 
 
 /* Kernels of a plan launch, for pdp_plan_timer_start. */
 #define PDP_KERNEL_JOIN 0        /* shared-k-mer join: count pass, scan of the counts, write pass */
-#define PDP_KERNEL_BUCKET 1      /* the scan of the (tile, item) record counts alone */
+#define PDP_KERNEL_BUCKET 1      /* the scan of the per-tile record totals alone */
 #define PDP_KERNEL_TILE_COUNT 2  /* per tile: sort and sum of records, row maxima, tie counts */
 #define PDP_KERNEL_TILE_WRITE 3  /* best-hit output (slab copy, rows with many ties) */
 #define PDP_KERNEL_BBH 4         /* BBH count and write passes together */

@@ -403,8 +403,6 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
                 tl.dir = dir;
                 tl.row0 = r0;
                 tl.nrows = std::min<uint32_t>(T, nrows - r0);
-                tl.cell0 = static_cast<uint32_t>(cells + uint64_t(tile_local) * d.n_chunks);
-                tl.cell1 = static_cast<uint32_t>(tl.cell0 + d.n_chunks);
                 P->tiles.push_back(tl);
             }
         }

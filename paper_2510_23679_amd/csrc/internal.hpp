@@ -101,7 +101,7 @@ struct DevTask {
     uint32_t tile_base[2];  // first tile of each direction
     uint32_t row_base[2];   // first best-hit row of each direction (UINT32_MAX: none)
     uint32_t bbh_row_base;  // first BBH row (UINT32_MAX: none)
-    uint32_t cell_base;     // first cell of the task's (tile, item) record-count matrix
+    uint32_t cell_base;     // first cell of the task's (item, tile) record counts (item-major)
     uint32_t theta_n, theta_d, tau_n, tau_d;  // candidate filters (zero denominator: off)
 };
 
@@ -110,7 +110,6 @@ struct DevTile {
     uint32_t dir;
     uint32_t row0;
     uint32_t nrows;
-    uint32_t cell0, cell1;  // its records: scanned cells[cell0] .. cells[cell1]
 };
 
 // ------------------------------------------------------------- launchers
@@ -159,7 +158,9 @@ struct PairWs {
     DevTile *tiles;
     uint2 *recs;                  // records grouped by tile: ((row in tile << 24) | column, min count)
     unsigned long long *counters; // [0] records counted by the join
-    uint32_t *cells;              // (tile, item) record counts, scanned in place into slots; + 1
+    uint32_t *cells;              // (item, tile) record counts of the join's count pass, item-major
+    uint32_t *tile_tot;           // records per tile, counted by the join (the write pass consumes them)
+    uint32_t *tile_off;           // scanned tile totals: tile t's records start at tile_off[t]; + 1
     uint4 *slab;                  // kSlab (column, m, d, -) per best-hit row
     uint32_t *overflow_tiles;     // tiles holding a row with more than kSlab ties
     uint32_t *overflow_count;     // counters word 2

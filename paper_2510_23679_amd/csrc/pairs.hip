@@ -9,20 +9,24 @@
 //     takes one range ("item"), stages the target side in LDS, finds the
 //     partners of every query entry through the bucket directory, and counts
 //     the records each accumulation tile (2^s rows of one direction) will get
-//     from this item.  Counts form a (tile, item) matrix per task.
-//  2. An exclusive scan of that matrix (tile-major) gives every (tile, item)
-//     cell its slot range, so each tile's records end up contiguous.
-//  3. k_join (write pass) repeats the join and writes, per shared (k-mer,
-//     gene a, gene b), a record (row in tile, column, min count) for each
-//     requested direction into its tile's range; positions come from LDS
-//     cursors seeded by the scan, so no global atomics are involved.
-//  4. k_tile: one work-group per tile sorts the tile's records by (row,
-//     column) in LDS, sums each run into m, and one wave per row finds the row
-//     maximum of J = m/d by exact cross-multiplication and counts or writes
-//     every column that reaches it (ties kept, ascending column order; a row
-//     without shared k-mers has no best hit), following Eq. best_hit and the
-//     per-row work of Alg. 2.  A tile with more records than LDS holds is
-//     summed densely instead, a few rows per pass.
+//     from this item; it stores the counts (item-major) and adds them to the
+//     tiles' totals, one atomic per tile it feeds.
+//  2. An exclusive scan of the tile totals gives every tile its record range.
+//  3. k_join (write pass) repeats the join: the item takes a run of each
+//     tile's range with one atomic on the tile's remaining count, and writes,
+//     per shared (k-mer, gene a, gene b), a record (row in tile, column, both
+//     counts) for each requested direction into its run, positions from LDS
+//     cursors.  Runs of different items land in a tile in any order; the tile
+//     pass does not depend on the order of its records.
+//  4. k_tile_count: one work-group per tile sums the tile's records into m per
+//     (row, column) in an LDS hash table, finds each row's maximum of
+//     J = m/d by exact cross-multiplication, and counts the columns that reach
+//     it, keeping the first few per row (ties kept; a row without shared
+//     k-mers has no best hit), following Eq. best_hit and the per-row work of
+//     Alg. 2.  A tile with more records than the table holds goes in groups of
+//     rows, and a row alone past it is summed densely.  The slab copy orders
+//     each row's hits by column; k_tile_write recomputes tiles with a row of
+//     more ties (sorted in LDS, or densely) and writes them in column order.
 //  5. k_bbh: each best hit (a, b) is kept when a is among b's best hits
 //     (Eq. bidirectional_best_hit, the cross-check of Alg. 3).
 // With PDP_PARAM_COLMAX a task asking for both directions writes records for its
@@ -30,8 +34,8 @@
 // tiles raise a 64-bit key per column that orders the values of m/d exactly, list every
 // pair that reaches its column's running maximum, and the pairs still at the final
 // maximum become b's best hits.
-// Counts, scans and writes keep every output in a canonical order, so results
-// do not depend on scheduling.
+// Every output is written in a canonical order, so results do not depend on
+// scheduling.
 #include <algorithm>
 #include <type_traits>
 
@@ -264,7 +268,8 @@ __device__ __forceinline__ void join_range_p(const DevTask &T, JoinRoundP &r, bo
 // next item.
 template <bool WRITE>
 __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__restrict__ tasks, uint32_t n_tasks,
-                                           uint32_t *__restrict__ cells, unsigned long long *__restrict__ total,
+                                           uint32_t *__restrict__ cells, uint32_t *__restrict__ tile_tot,
+                                           const uint32_t *__restrict__ tile_off, unsigned long long *__restrict__ total,
                                            uint2 *__restrict__ recs, uint64_t rec_cap, JoinLds<WRITE> &L) {
     const uint32_t task = find_task_coop(tasks, n_tasks, chunk, &L.found);
     {
@@ -299,8 +304,17 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
             }
         }
     }
-    for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x)
-        L.tcount[t] = WRITE ? cells[T.cell_base + static_cast<uint64_t>(t) * T.n_chunks + c] : 0u;
+    // write pass: the item takes a run of each tile's range for its records, one atomic on the
+    // tile's remaining count per tile it feeds; the cursors start at the runs
+    const uint64_t crow = T.cell_base + static_cast<uint64_t>(c) * ntiles;
+    for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
+        uint32_t cur = 0;
+        if (WRITE) {
+            const uint32_t v = cells[crow + t], gt = T.tile_base[0] + t;
+            if (v) cur = tile_off[gt] + atomicSub(&tile_tot[gt], v) - v;
+        }
+        L.tcount[t] = cur;
+    }
     __syncthreads();
     for (uint32_t s0 = bl; s0 < bh; s0 += T.bpw) {
         const uint32_t s1 = min(bh, s0 + T.bpw);
@@ -369,7 +383,8 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
         uint32_t mine = 0;
         for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
             const uint32_t v = L.tcount[t];
-            cells[T.cell_base + static_cast<uint64_t>(t) * T.n_chunks + c] = v;
+            cells[crow + t] = v;
+            if (v) atomicAdd(&tile_tot[T.tile_base[0] + t], v);
             mine += v;
         }
         uint32_t sum;
@@ -379,14 +394,16 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
     __syncthreads();
 }
 
-__global__ void k_pairs_init(pdp_status *st, uint32_t *counters) {
-    if (threadIdx.x == 0) {
+__global__ void k_pairs_init(pdp_status *st, uint32_t *counters, uint32_t *tile_tot, uint32_t n_tiles) {
+    const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0) {
         st->code = 0;
         st->reserved = 0;
         st->needed = 0;
         st->where = ~0ull;
     }
-    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+    if (i0 < 8) counters[i0] = 0;
+    for (uint32_t t = i0; t < n_tiles; t += gridDim.x * blockDim.x) tile_tot[t] = 0;
 }
 
 // The write pass stops when the records do not fit; the count pass's total is then the
@@ -400,11 +417,13 @@ __device__ __forceinline__ bool join_overflow(const unsigned long long *total, u
 
 template <bool WRITE>
 __global__ __launch_bounds__(kJoinThreads) void k_join(const DevTask *__restrict__ tasks, uint32_t n_tasks,
-                                                       uint32_t *__restrict__ cells, unsigned long long *__restrict__ total,
+                                                       uint32_t *__restrict__ cells, uint32_t *__restrict__ tile_tot,
+                                                       const uint32_t *__restrict__ tile_off,
+                                                       unsigned long long *__restrict__ total,
                                                        uint2 *__restrict__ recs, uint64_t rec_cap, pdp_status *st) {
     __shared__ JoinLds<WRITE> L;
     if (WRITE && join_overflow(total, rec_cap, st)) return;
-    join_chunk<WRITE>(blockIdx.x, tasks, n_tasks, cells, total, recs, rec_cap, L);
+    join_chunk<WRITE>(blockIdx.x, tasks, n_tasks, cells, tile_tot, tile_off, total, recs, rec_cap, L);
 }
 
 // Persistent form: a fixed grid claims join items kClaimJoin at a time from a counter
@@ -415,6 +434,8 @@ constexpr uint32_t kClaimJoin = 2;
 template <bool WRITE>
 __global__ __launch_bounds__(kJoinThreads) void k_join_persistent(const DevTask *__restrict__ tasks, uint32_t n_tasks,
                                                                   uint32_t total_chunks, uint32_t *__restrict__ cells,
+                                                                  uint32_t *__restrict__ tile_tot,
+                                                                  const uint32_t *__restrict__ tile_off,
                                                                   unsigned long long *__restrict__ total,
                                                                   uint2 *__restrict__ recs, uint64_t rec_cap,
                                                                   pdp_status *st, uint32_t *__restrict__ next) {
@@ -428,7 +449,7 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_persistent(const DevTask 
         if (first >= total_chunks) break;
         const uint32_t last = min(total_chunks, first + kClaimJoin);
         for (uint32_t chunk = first; chunk < last; ++chunk)
-            join_chunk<WRITE>(chunk, tasks, n_tasks, cells, total, recs, rec_cap, L);
+            join_chunk<WRITE>(chunk, tasks, n_tasks, cells, tile_tot, tile_off, total, recs, rec_cap, L);
     }
 }
 
@@ -940,7 +961,7 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
     __syncthreads();  // the table takes the next row group
 }
 
-// One tile: its records are cells[cell0] .. cells[cell1] of the scanned count matrix
+// One tile: its records are tile_off[tile] .. tile_off[tile + 1] of the scanned tile totals
 // (clamped to the record capacity, so a capacity overflow reads no further).  The first
 // launch (WRITE = false) hashes the tile, or, past kHashMax records, groups of whole rows
 // that fit the table (a row alone beyond it is summed densely); ties go to per-row slabs
@@ -949,7 +970,7 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
 // its rows straight into the CSR output in column order.
 template <bool WRITE, bool CM = false>
 __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__restrict__ tasks,
-                                             const DevTile *__restrict__ tiles, const uint32_t *__restrict__ cells,
+                                             const DevTile *__restrict__ tiles, const uint32_t *__restrict__ tile_off,
                                              const uint2 *__restrict__ recs, uint64_t rec_cap,
                                              const unsigned long long *__restrict__ total, uint32_t lds_words,
                                              uint32_t *__restrict__ bh_ptr, uint4 *__restrict__ slab,
@@ -960,7 +981,7 @@ __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__
     const DevTask &T = tasks[tl.task];
     // when the join's records overflowed the scratch its write pass wrote none: every tile is
     // empty then (the status already asks for a larger capacity)
-    const uint64_t c0 = cells[tl.cell0], c1 = cells[tl.cell1];
+    const uint64_t c0 = tile_off[tile_id], c1 = tile_off[tile_id + 1];
     const uint64_t rb = min(c0, rec_cap);
     const uint64_t re = *total > rec_cap ? rb : max(rb, min(c1, rec_cap));
     const uint32_t n = static_cast<uint32_t>(re - rb);
@@ -1002,7 +1023,7 @@ __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__
 template <bool CM>
 __global__ __launch_bounds__(kTileThreads) void k_tile_count(const DevTask *__restrict__ tasks,
                                                              const DevTile *__restrict__ tiles,
-                                                             const uint32_t *__restrict__ cells,
+                                                             const uint32_t *__restrict__ tile_off,
                                                              const uint2 *__restrict__ recs, uint64_t rec_cap,
                                                              const unsigned long long *__restrict__ total,
                                                              uint32_t lds_words, uint32_t *__restrict__ bh_ptr,
@@ -1010,7 +1031,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count(const DevTask *__re
                                                              uint32_t *overflow_count, ColWs cmx) {
     extern __shared__ uint32_t lds[];
     __shared__ TileLds S;
-    tile_process<false, CM>(blockIdx.x, tasks, tiles, cells, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr,
+    tile_process<false, CM>(blockIdx.x, tasks, tiles, tile_off, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr,
                             nullptr, nullptr, 0, overflow_tiles, overflow_count, lds, S, cmx);
 }
 
@@ -1018,7 +1039,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count(const DevTask *__re
 template <bool CM>
 __global__ __launch_bounds__(kTileThreads) void k_tile_count_persistent(
     const DevTask *__restrict__ tasks, const DevTile *__restrict__ tiles, uint32_t total_tiles,
-    const uint32_t *__restrict__ cells, const uint2 *__restrict__ recs, uint64_t rec_cap,
+    const uint32_t *__restrict__ tile_off, const uint2 *__restrict__ recs, uint64_t rec_cap,
     const unsigned long long *__restrict__ total, uint32_t lds_words, uint32_t *__restrict__ bh_ptr,
     uint4 *__restrict__ slab, uint32_t *overflow_tiles, uint32_t *overflow_count, uint32_t *__restrict__ next, ColWs cmx) {
     extern __shared__ uint32_t lds[];
@@ -1031,7 +1052,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count_persistent(
         if (first >= total_tiles) break;
         const uint32_t last = min(total_tiles, first + kClaim);
         for (uint32_t t = first; t < last; ++t)
-            tile_process<false, CM>(t, tasks, tiles, cells, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr,
+            tile_process<false, CM>(t, tasks, tiles, tile_off, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr,
                                     nullptr, nullptr, 0, overflow_tiles, overflow_count, lds, S, cmx);
     }
 }
@@ -1039,7 +1060,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count_persistent(
 // Rows with more ties than the slab holds: their tiles again, written to the CSR output.
 __global__ __launch_bounds__(kTileThreads) void k_tile_write(const DevTask *__restrict__ tasks,
                                                              const DevTile *__restrict__ tiles,
-                                                             const uint32_t *__restrict__ cells,
+                                                             const uint32_t *__restrict__ tile_off,
                                                              const uint2 *__restrict__ recs, uint64_t rec_cap,
                                                              const unsigned long long *__restrict__ total,
                                                              uint32_t lds_words, uint32_t *__restrict__ bh_ptr,
@@ -1051,7 +1072,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_write(const DevTask *__re
     __shared__ TileLds S;
     const uint32_t n = *overflow_count;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
-        tile_process<true>(overflow_tiles[i], tasks, tiles, cells, recs, rec_cap, total, lds_words, bh_ptr, nullptr, bh_col,
+        tile_process<true>(overflow_tiles[i], tasks, tiles, tile_off, recs, rec_cap, total, lds_words, bh_ptr, nullptr, bh_col,
                            bh_num, bh_den, bh_cap, nullptr, nullptr, lds, S, ColWs{});
 }
 
@@ -1276,7 +1297,7 @@ hipError_t allow_tile_lds(uint32_t tile_lds) {
 }
 
 static uint64_t pair_partials(const PlanShape &p) {
-    return std::max({scan_partials(p.total_cells), scan_partials(p.bh_rows), scan_partials(p.bbh_rows)});
+    return std::max({scan_partials(p.total_tiles), scan_partials(p.bh_rows), scan_partials(p.bbh_rows)});
 }
 
 uint64_t pair_ws_bytes(const PlanShape &p) {
@@ -1288,6 +1309,8 @@ uint64_t pair_ws_bytes(const PlanShape &p) {
     s += align_up(8 * std::max<uint64_t>(p.rec_cap, 1), A);
     s += align_up(32, A);
     s += align_up(4 * (uint64_t(p.total_cells) + 1), A);
+    s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);  // records per tile (join), consumed by the write pass
+    s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);  // scanned: each tile's first record
     s += align_up(16 * kSlab * (uint64_t(p.bh_rows) + 1), A);
     s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
     s += align_up(4 * pair_partials(p), A);
@@ -1317,6 +1340,8 @@ PairWs pair_ws_carve(void *ws, const PlanShape &p) {
     w.next_tile = reinterpret_cast<uint32_t *>(w.counters) + 4;
     w.next_join_write = reinterpret_cast<uint32_t *>(w.counters) + 5;
     w.cells = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_cells) + 1)));
+    w.tile_tot = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
+    w.tile_off = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
     w.slab = reinterpret_cast<uint4 *>(take(16 * kSlab * (uint64_t(p.bh_rows) + 1)));
     w.overflow_tiles = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
     w.partials = reinterpret_cast<uint32_t *>(take(4 * pair_partials(p)));
@@ -1338,7 +1363,8 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     PDP_TRY(mark(PDP_KERNEL_ALL, true));
     // status and counters (record total (64 bits), overflow tiles, next join item (count
     // pass), next tile, next join item (write pass), column candidates) in one launch
-    hipLaunchKernelGGL(k_pairs_init, dim3(1), dim3(64), 0, s, st, reinterpret_cast<uint32_t *>(w.counters));
+    hipLaunchKernelGGL(k_pairs_init, dim3(std::max<uint32_t>(1, std::min<uint32_t>(1024, (p.total_tiles + 255) / 256))),
+                       dim3(256), 0, s, st, reinterpret_cast<uint32_t *>(w.counters), w.tile_tot, p.total_tiles);
     PDP_TRY(hipGetLastError());
     const ColWs cmx{w.colkey, w.cands, w.cand_count, p.colmax ? p.cand_cap : 0};
     if (p.colmax) {  // BA rows are counted by atomics; column keys and cursors start at zero
@@ -1353,23 +1379,25 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
                             : dim3(p.total_chunks);
         if (pers)
             hipLaunchKernelGGL(k_join_persistent<false>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
-                               w.cells, w.counters, w.recs, p.rec_cap, st, w.next_join);
+                               w.cells, w.tile_tot, w.tile_off, w.counters, w.recs, p.rec_cap, st, w.next_join);
         else
-            hipLaunchKernelGGL(k_join<false>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.cells, w.counters,
+            hipLaunchKernelGGL(k_join<false>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.cells, w.tile_tot,
+                               w.tile_off, w.counters,
                                w.recs, p.rec_cap, st);
         PDP_TRY(hipGetLastError());
         PDP_TRY(mark(PDP_KERNEL_BUCKET, true));
-        PDP_TRY(launch_scan(w.cells, w.cells, p.total_cells, w.partials, s));
+        PDP_TRY(launch_scan(w.tile_tot, w.tile_off, p.total_tiles, w.partials, s));
         PDP_TRY(mark(PDP_KERNEL_BUCKET, false));
         if (pers)
             hipLaunchKernelGGL(k_join_persistent<true>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
-                               w.cells, w.counters, w.recs, p.rec_cap, st, w.next_join_write);
+                               w.cells, w.tile_tot, w.tile_off, w.counters, w.recs, p.rec_cap, st, w.next_join_write);
         else
-            hipLaunchKernelGGL(k_join<true>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.cells, w.counters,
+            hipLaunchKernelGGL(k_join<true>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.cells, w.tile_tot,
+                               w.tile_off, w.counters,
                                w.recs, p.rec_cap, st);
         PDP_TRY(hipGetLastError());
     } else {
-        PDP_TRY(launch_fill_u32(w.cells, uint64_t(p.total_cells) + 1, 0u, s));
+        PDP_TRY(launch_fill_u32(w.tile_off, uint64_t(p.total_tiles) + 1, 0u, s));
     }
     PDP_TRY(mark(PDP_KERNEL_JOIN, false));
     PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, true));
@@ -1377,21 +1405,21 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
         const dim3 g(std::min(p.tile_grid, (p.total_tiles + kClaim - 1) / kClaim));
         if (p.colmax)
             hipLaunchKernelGGL(k_tile_count_persistent<true>, g, dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
-                               p.total_tiles, w.cells, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
+                               p.total_tiles, w.tile_off, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
                                w.overflow_tiles, w.overflow_count, w.next_tile, cmx);
         else
             hipLaunchKernelGGL(k_tile_count_persistent<false>, g, dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
-                               p.total_tiles, w.cells, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
+                               p.total_tiles, w.tile_off, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
                                w.overflow_tiles, w.overflow_count, w.next_tile, cmx);
         PDP_TRY(hipGetLastError());
     } else if (p.total_tiles) {
         if (p.colmax)
             hipLaunchKernelGGL(k_tile_count<true>, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks,
-                               w.tiles, w.cells, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
+                               w.tiles, w.tile_off, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
                                w.overflow_tiles, w.overflow_count, cmx);
         else
             hipLaunchKernelGGL(k_tile_count<false>, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks,
-                               w.tiles, w.cells, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
+                               w.tiles, w.tile_off, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
                                w.overflow_tiles, w.overflow_count, cmx);
         PDP_TRY(hipGetLastError());
     }
@@ -1410,7 +1438,7 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     }
     if (p.total_tiles) {
         const uint32_t g = p.total_tiles < 256 ? p.total_tiles : 256;
-        hipLaunchKernelGGL(k_tile_write, dim3(g), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles, w.cells, w.recs,
+        hipLaunchKernelGGL(k_tile_write, dim3(g), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles, w.tile_off, w.recs,
                            p.rec_cap, w.counters, lds_words, bh->ptr, bh->col, bh->num, bh->den, bh->capacity, w.overflow_tiles,
                            w.overflow_count);
         PDP_TRY(hipGetLastError());
