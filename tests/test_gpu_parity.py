@@ -281,6 +281,21 @@ def test_join_global_search_path():
     compare_all([a, b], 6, res)
 
 
+def test_kmer_shared_by_hundreds_of_genes():
+    # a k-mer present in 300 genes of the target genome: one query entry with 300 partners in
+    # the join, and a row with many tied columns
+    rng = random.Random(31)
+    core = "".join(rng.choice(ALPHA) for _ in range(80))
+    a = [core] + ["".join(rng.choice(ALPHA) for _ in range(rng.randint(40, 120))) for _ in range(50)]
+    b = [core[:40] + "".join(rng.choice(ALPHA) for _ in range(20)) for _ in range(300)]
+    b += ["".join(rng.choice(ALPHA) for _ in range(rng.randint(40, 120))) for _ in range(60)]
+    rng.shuffle(b)
+    ga, gb = genome_from_strings(a), genome_from_strings(b)
+    say("k-mer shared by 300 target genes")
+    _, res = run_all([ga, gb], 5)
+    compare_all([ga, gb], 5, res)
+
+
 def test_single_direction_and_standalone_bbh():
     say("pdp_bh both ways + pdp_bbh")
     ds = make_config(2, genomes=2, genes=350)
