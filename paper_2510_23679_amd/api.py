@@ -563,6 +563,9 @@ class Server:
         self._keep = []
 
     def submit(self, genome, tag: int) -> None:
+        al = getattr(genome, "alphabet", self.alphabet)
+        if al != self.alphabet:
+            raise ValueError(f"genome alphabet {al!r} differs from the residents' {self.alphabet!r}")
         res = np.ascontiguousarray(genome.residues, dtype=np.uint8)
         off = np.ascontiguousarray(genome.offsets, dtype=np.uint64)
         check(lib().pdp_server_submit(self.h, res.ctypes.data, off.ctypes.data, int(off.shape[0] - 1), int(tag)),

@@ -99,3 +99,27 @@ def test_budget_rejects_oversized_request(workload):
         assert done[0].tag == 7 and done[0].code == pdp.PDP_E_BUDGET
     finally:
         srv.close()
+
+
+def test_served_nucleotide_genomes():
+    # residents and requests over ACGT: the server builds each request's dictionary with the
+    # residents' alphabet and k
+    from synth import make_config
+
+    k = 11
+    res_ds = make_config(2, genomes=3, genes=120, alphabet="nt")
+    residents = [pdp.Dictionary.build_from(g, k) for g in res_ds.genomes]
+    arrivals = make_config(1, alphabet="nt", n_genes=60, n_planted=40).genomes
+    say("serving nucleotides: 2 requests x 3 residents, k =", k)
+    out, stats = run_server(residents, arrivals, slots=2)
+    assert stats.completed == 2
+    og_res = [oracle.OracleGenome(g, k) for g in res_ds.genomes]
+    for j, g in enumerate(arrivals):
+        d, res = out[j]
+        assert d.code == 0 and res.code == 0
+        q = oracle.OracleGenome(g, k)
+        for r, og in enumerate(og_res):
+            ab, ba = oracle.bh(q, og), oracle.bh(og, q)
+            check_bh(res.best_hits(r, 0), ab)
+            check_bh(res.best_hits(r, 1), ba)
+            check_bbh(res.bbh_pairs(r), oracle.bbh(ab, ba))
