@@ -44,6 +44,7 @@ def parse():
     p.add_argument("--tune", action="store_true", help="pick tile shapes and join splits with the autotuner first")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                    help="measured HBM traffic per kernel (from rocprofv3 counters), used when its source hash matches")
+    p.add_argument("--two-pass", action="store_true", help="join in two passes (count, then write)")
     p.add_argument("--colmax", action="store_true",
                    help="second genome's best hits from column maxima (Alg. 3): join records for one direction only")
     p.add_argument("--theta", default=None, help="length filter as NUM/DEN (Eq. length_threshold); off by default")
@@ -397,7 +398,7 @@ def main():
     def frac(x):
         return tuple(int(v) for v in x.split("/")) if x else None
 
-    prm = pdp.params(theta=frac(args.theta), tau=frac(args.tau), colmax=args.colmax)
+    prm = pdp.params(theta=frac(args.theta), tau=frac(args.tau), colmax=args.colmax, two_pass=args.two_pass)
     if args.tune:
         best, tres = pdp.autotune(tasks, reps=3, base=prm)
         prm = best
@@ -438,6 +439,7 @@ def main():
     code, needed, where = pdp.read_status(runner.status)
     if code != 0:
         raise SystemExit(f"device status {code} in the timed region")
+    two_pass = bool(pdp.status_flags(runner.status) & pdp.PDP_STATUS_TWO_PASS) or bool(prm.flags & B.PDP_PARAM_TWO_PASS)
     for d in dicts:
         d.check_status()
 
@@ -487,7 +489,8 @@ def main():
         pass
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": args.kernel,
-                "kernel_ms": round(avg_kernel_ms, 5), "algorithmic_bytes": alg, "launches_timed": kern_n}
+                "kernel_ms": round(avg_kernel_ms, 5), "algorithmic_bytes": alg, "launches_timed": kern_n,
+                "join_layout": "two passes" if two_pass else "one pass"}
 
     out = {
         "metric": METRIC,

@@ -77,13 +77,18 @@ enum pdp_code {
  * (PDP_E_ALPHABET), the gene index (PDP_E_LIMIT, PDP_E_INVAL) or, for
  * PDP_E_CAPACITY, the first array that overflowed in pipeline order
  * (0: shared-k-mer records, 1: best-hit entries, 2: BBH pairs); else
- * UINT64_MAX.  On any error the call's outputs are unspecified. */
+ * UINT64_MAX.  On any error the call's outputs are unspecified.  flags
+ * reports how a call ran, not an error: PDP_STATUS_TWO_PASS. */
 typedef struct pdp_status {
     int32_t code;
-    uint32_t reserved;
+    uint32_t flags;
     uint64_t needed;
     uint64_t where;
 } pdp_status;
+
+/* pdp_status.flags: a tile's record region of the one-pass join overflowed, and
+ * the two-pass join laid out the records instead (see PDP_PARAM_TWO_PASS). */
+#define PDP_STATUS_TWO_PASS 1u
 
 uint32_t pdp_abi_version(void);
 const char *pdp_strerror(int32_t code);
@@ -245,6 +250,12 @@ typedef struct pdp_params {
  * for one direction only.  Results are identical to the default.  The column
  * candidates share the record capacity (PDP_E_CAPACITY with where = 0). */
 #define PDP_PARAM_COLMAX 2u
+/* The shared-k-mer join in two passes (count, then write) instead of one.  By
+ * default one pass searches every query entry once and writes each record into
+ * its tile's region, whose size the plan derives from the record capacity; when
+ * a region overflows, the two passes run after it and lay the records out
+ * exactly.  Results are identical either way. */
+#define PDP_PARAM_TWO_PASS 4u
 
 /* One unit of work: genomes a and b (same k and alphabet).  flags select the outputs. */
 #define PDP_TASK_AB 1u   /* best hits of a's genes in b */

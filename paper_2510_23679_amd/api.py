@@ -106,6 +106,12 @@ def read_status(t: torch.Tensor) -> Tuple[int, int, int]:
     return int(st.code), int(st.needed), int(st.where)
 
 
+def status_flags(t: torch.Tensor) -> int:
+    """pdp_status.flags of a status tensor (PDP_STATUS_*; synchronises)."""
+    raw = t.detach().cpu().numpy().view(np.uint8)[:24].tobytes()
+    return int(B.pdp_status.from_buffer_copy(raw).flags)
+
+
 def new_status() -> torch.Tensor:
     return torch.zeros(32, dtype=torch.uint8, device=_device())
 
@@ -244,12 +250,15 @@ class BBHOut:
 
 
 def params(inc_capacity: int = 0, tile_rows: int = 0, join_entries: int = 0, lds_budget: int = 0,
-           persistent: bool = False, theta=None, tau=None, colmax: bool = False) -> B.pdp_params:
+           persistent: bool = False, theta=None, tau=None, colmax: bool = False,
+           two_pass: bool = False) -> B.pdp_params:
     """Tuning knobs and the candidate filters: theta / tau as (numerator, denominator) or None (off).
-    colmax: the second genome's best hits from the column maxima of the first genome's rows."""
+    colmax: the second genome's best hits from the column maxima of the first genome's rows.
+    two_pass: the join counts its records in a pass of its own before writing them."""
     tn, td = theta if theta is not None else (0, 0)
     un, ud = tau if tau is not None else (0, 0)
-    flags = (B.PDP_PARAM_PERSISTENT if persistent else 0) | (B.PDP_PARAM_COLMAX if colmax else 0)
+    flags = (B.PDP_PARAM_PERSISTENT if persistent else 0) | (B.PDP_PARAM_COLMAX if colmax else 0) \
+        | (B.PDP_PARAM_TWO_PASS if two_pass else 0)
     return B.pdp_params(int(inc_capacity), int(tile_rows), int(join_entries), int(lds_budget), flags,
                         int(tn), int(td), int(un), int(ud))
 

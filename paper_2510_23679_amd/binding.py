@@ -31,6 +31,8 @@ PDP_TASK_BA = 2
 PDP_TASK_BBH = 4
 PDP_PARAM_PERSISTENT = 1
 PDP_PARAM_COLMAX = 2
+PDP_PARAM_TWO_PASS = 4
+PDP_STATUS_TWO_PASS = 1
 PDP_K_MAX = 12
 PDP_K_MAX_NT = 31
 PDP_ALPHA_AMINO = 0
@@ -51,7 +53,7 @@ KERNELS = {"join": 0, "bucket": 1, "tile_count": 2, "tile_write": 3, "bbh": 4, "
 
 
 class pdp_status(C.Structure):
-    _fields_ = [("code", i32), ("reserved", u32), ("needed", u64), ("where", u64)]
+    _fields_ = [("code", i32), ("flags", u32), ("needed", u64), ("where", u64)]
 
 
 class pdp_genome(C.Structure):

@@ -52,7 +52,7 @@ struct pdp_plan {
     uint64_t ws_bytes;
     bool persistent = false;
     mutable bool device_ready = false;  // persistent grids and LDS limit set up on the device
-    mutable uint32_t join_grid = 0, tile_grid = 0;
+    mutable uint32_t join_grid = 0, tile_grid = 0, fallback_grid = 0;
     // measurement hook: event pairs owned by the plan, one per timed launch
     mutable int32_t timer_kernel = -1;
     mutable uint32_t timer_used = 0;
@@ -271,7 +271,7 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     if (prm.tile_rows)
         for (base_shift = 0; (2u << base_shift) <= prm.tile_rows; ++base_shift) {
         }
-    if (prm.flags & ~(PDP_PARAM_PERSISTENT | PDP_PARAM_COLMAX))
+    if (prm.flags & ~(PDP_PARAM_PERSISTENT | PDP_PARAM_COLMAX | PDP_PARAM_TWO_PASS))
         return fail(PDP_E_INVAL, "unknown parameter flags 0x%x", prm.flags);
     bool any_colmax = false;
     if (prm.theta_den && prm.theta_num > prm.theta_den) return fail(PDP_E_INVAL, "theta above 1");
@@ -379,6 +379,9 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     }
     // Pass 2, largest tasks first: join items and tiles are numbered in this order, so work-groups
     // (and the persistent kernels' counters) take the long items early.
+    // each tile's expected records, the estimate rec_est sums: a region of the one-pass join each
+    std::vector<uint64_t> tile_est;
+    uint32_t join_tiles = 1;
     std::vector<uint32_t> by_cost(n_tasks);
     for (uint32_t t = 0; t < n_tasks; ++t) by_cost[t] = t;
     std::stable_sort(by_cost.begin(), by_cost.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
@@ -392,6 +395,7 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         chunks += d.n_chunks;
         d.cell_base = static_cast<uint32_t>(cells);
         uint32_t tile_local = 0;
+        const uint64_t dir_est = (tasks[t].a->capacity + tasks[t].b->capacity) / 8 + 4096;
         for (uint32_t dir = 0; dir < 2; ++dir) {
             d.tile_base[dir] = static_cast<uint32_t>(P->tiles.size());
             if (!(d.flags & (1u << dir))) continue;
@@ -403,9 +407,14 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
                 tl.dir = dir;
                 tl.row0 = r0;
                 tl.nrows = std::min<uint32_t>(T, nrows - r0);
+                tl.rbase = 0;
+                tl.rcap = 0;
                 P->tiles.push_back(tl);
+                // the direction's estimate split by rows (a direction without genes expects none)
+                tile_est.push_back(nrows ? dir_est * tl.nrows / nrows : 0);
             }
         }
+        join_tiles = std::max(join_tiles, tile_local);
         cells += uint64_t(tile_local) * d.n_chunks;
         if (cells >= UINT32_MAX) return bail(fail(PDP_E_LIMIT, "plan too large for 32-bit record counts"));
         P->tasks.push_back(d);
@@ -420,6 +429,22 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     P->shape.bbh_rows = static_cast<uint32_t>(bbh_rows);
     P->shape.tile_lds = static_cast<uint32_t>(align_up(tile_lds, 16));
     P->shape.rec_cap = prm.inc_capacity ? prm.inc_capacity : std::min<uint64_t>(rec_est, UINT32_MAX);
+    P->shape.fused = (prm.flags & PDP_PARAM_TWO_PASS) ? 0u : 1u;
+    P->shape.join_tiles = join_tiles;
+    P->shape.fallback_grid = 0;
+    {  // regions of the one-pass join: the record capacity split in proportion to the estimates
+        unsigned __int128 est_sum = 0;
+        for (uint64_t e : tile_est) est_sum += e;
+        uint64_t at = 0;
+        for (size_t ti = 0; ti < P->tiles.size(); ++ti) {
+            const uint64_t cap = est_sum ? static_cast<uint64_t>(
+                                               static_cast<unsigned __int128>(P->shape.rec_cap) * tile_est[ti] / est_sum)
+                                         : 0;
+            P->tiles[ti].rbase = static_cast<uint32_t>(at);
+            P->tiles[ti].rcap = static_cast<uint32_t>(cap);
+            at += cap;
+        }
+    }
     P->shape.join_grid = 0;
     P->shape.tile_grid = 0;
     P->shape.colmax = any_colmax ? 1u : 0u;
@@ -494,13 +519,15 @@ int32_t pdp_plan_launch(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, 
         hipError_t e = allow_tile_lds(plan->shape.tile_lds);
         if (e != hipSuccess) return hip_fail(e, "pdp_plan_launch");
         if (plan->persistent) {
-            plan->join_grid = persistent_join_grid();
+            plan->join_grid = plan->shape.fused ? persistent_fused_grid(plan->shape.join_tiles) : persistent_join_grid();
             plan->tile_grid = persistent_tile_grid(plan->shape.tile_lds);
         }
+        if (plan->shape.fused) plan->fallback_grid = persistent_join_grid();
         plan->device_ready = true;
     }
     shape.join_grid = plan->join_grid;
     shape.tile_grid = plan->tile_grid;
+    shape.fallback_grid = plan->fallback_grid;
     KernelTimer timer{-1, nullptr, nullptr};
     if (plan->timer_kernel >= 0 && plan->timer_used < plan->timer_events.size()) {
         timer.kernel = plan->timer_kernel;

@@ -72,7 +72,7 @@ __global__ void k_build_init(const DevBuild *table, uint32_t n, uint32_t *counte
     for (uint32_t t = i0; t < n; t += stride) {
         pdp_status *st = table[t].status;
         st->code = 0;
-        st->reserved = 0;
+        st->flags = 0;
         st->needed = 0;
         st->where = ~0ull;
         if (table[t].n_genes == 0) table[t].mv_ptr[0] = 0;

@@ -110,6 +110,8 @@ struct DevTile {
     uint32_t dir;
     uint32_t row0;
     uint32_t nrows;
+    uint32_t rbase;  // the tile's record region in the one-pass join: records rbase .. rbase + rcap
+    uint32_t rcap;
 };
 
 // ------------------------------------------------------------- launchers
@@ -161,6 +163,10 @@ struct PairWs {
     uint32_t *cells;              // (item, tile) record counts of the join's count pass, item-major
     uint32_t *tile_tot;           // records per tile, counted by the join (the write pass consumes them)
     uint32_t *tile_off;           // scanned tile totals: tile t's records start at tile_off[t]; + 1
+    uint32_t *fill;               // one-pass join: records reserved in each tile's region
+    uint2 *tile_rng;              // records of each tile, [x, y), for the tile kernels
+    uint32_t *fallback;           // counters word 7: a region overflowed, the two-pass join redoes the records
+    uint32_t *next_fused;         // counters word 8: next item of the persistent one-pass join
     uint4 *slab;                  // kSlab (column, m, d, -) per best-hit row
     uint32_t *overflow_tiles;     // tiles holding a row with more than kSlab ties
     uint32_t *overflow_count;     // counters word 2
@@ -182,6 +188,9 @@ struct PlanShape {
     uint64_t rec_cap;               // records the scratch holds
     uint32_t join_grid, tile_grid;  // persistent grids (0: one work-group per item)
     uint32_t colmax;                // some task takes its BA best hits from column maxima
+    uint32_t fused;                 // one-pass join into per-tile regions (else count pass + write pass)
+    uint32_t join_tiles;            // most tiles of one task: LDS counters of the one-pass join
+    uint32_t fallback_grid;         // work-groups of the two-pass join when it backs up the one-pass join
     uint64_t cand_cap;              // column candidates the scratch holds (colmax: rec_cap)
 };
 // Records the message that pdp_last_error() returns on this thread; returns code.
@@ -189,6 +198,7 @@ int32_t api_fail(int32_t code, const char *fmt, ...) __attribute__((format(print
 
 // Work-groups of the persistent kernels that fit the current device at once.
 uint32_t persistent_join_grid();
+uint32_t persistent_fused_grid(uint32_t join_tiles);
 uint32_t persistent_tile_grid(uint32_t tile_lds);
 hipError_t allow_tile_lds(uint32_t tile_lds);
 uint64_t pair_ws_bytes(const PlanShape &p);

@@ -394,16 +394,19 @@ __device__ __forceinline__ void join_chunk(uint32_t chunk, const DevTask *__rest
     __syncthreads();
 }
 
-__global__ void k_pairs_init(pdp_status *st, uint32_t *counters, uint32_t *tile_tot, uint32_t n_tiles) {
+__global__ void k_pairs_init(pdp_status *st, uint32_t *counters, uint32_t *tile_tot, uint32_t *fill, uint32_t n_tiles) {
     const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
     if (i0 == 0) {
         st->code = 0;
-        st->reserved = 0;
+        st->flags = 0;
         st->needed = 0;
         st->where = ~0ull;
     }
-    if (i0 < 8) counters[i0] = 0;
-    for (uint32_t t = i0; t < n_tiles; t += gridDim.x * blockDim.x) tile_tot[t] = 0;
+    if (i0 < 16) counters[i0] = 0;
+    for (uint32_t t = i0; t < n_tiles; t += gridDim.x * blockDim.x) {
+        tile_tot[t] = 0;
+        fill[t] = 0;
+    }
 }
 
 // The write pass stops when the records do not fit; the count pass's total is then the
@@ -420,8 +423,11 @@ __global__ __launch_bounds__(kJoinThreads) void k_join(const DevTask *__restrict
                                                        uint32_t *__restrict__ cells, uint32_t *__restrict__ tile_tot,
                                                        const uint32_t *__restrict__ tile_off,
                                                        unsigned long long *__restrict__ total,
-                                                       uint2 *__restrict__ recs, uint64_t rec_cap, pdp_status *st) {
+                                                       uint2 *__restrict__ recs, uint64_t rec_cap, pdp_status *st,
+                                                       const uint32_t *__restrict__ gate) {
     __shared__ JoinLds<WRITE> L;
+    if (gate && *gate == 0u) return;  // backing up the one-pass join, which did not overflow
+    if (!WRITE && gate && blockIdx.x == 0 && threadIdx.x == 0) st->flags |= PDP_STATUS_TWO_PASS;
     if (WRITE && join_overflow(total, rec_cap, st)) return;
     join_chunk<WRITE>(blockIdx.x, tasks, n_tasks, cells, tile_tot, tile_off, total, recs, rec_cap, L);
 }
@@ -438,8 +444,11 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_persistent(const DevTask 
                                                                   const uint32_t *__restrict__ tile_off,
                                                                   unsigned long long *__restrict__ total,
                                                                   uint2 *__restrict__ recs, uint64_t rec_cap,
-                                                                  pdp_status *st, uint32_t *__restrict__ next) {
+                                                                  pdp_status *st, uint32_t *__restrict__ next,
+                                                                  const uint32_t *__restrict__ gate) {
     __shared__ JoinLds<WRITE> L;
+    if (gate && *gate == 0u) return;  // backing up the one-pass join, which did not overflow
+    if (!WRITE && gate && blockIdx.x == 0 && threadIdx.x == 0) st->flags |= PDP_STATUS_TWO_PASS;
     if (WRITE && join_overflow(total, rec_cap, st)) return;
     for (;;) {
         if (threadIdx.x == 0) L.next = atomicAdd(next, kClaimJoin);
@@ -450,6 +459,323 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_persistent(const DevTask 
         const uint32_t last = min(total_chunks, first + kClaimJoin);
         for (uint32_t chunk = first; chunk < last; ++chunk)
             join_chunk<WRITE>(chunk, tasks, n_tasks, cells, tile_tot, tile_off, total, recs, rec_cap, L);
+    }
+}
+
+// ------------------------------------------------------------------ one-pass join
+// The one-pass join searches every query entry once.  Each batch of query entries
+// (kFuseUnroll per thread) is searched against the staged target side.  The records the
+// batch produces are counted per tile in LDS.  Every tile the batch feeds then reserves a
+// run of its record region, with one atomic on the tile's fill count.  Finally the
+// records are written into those runs from LDS cursors.  The plan sizes every tile's
+// region from the dictionary sizes.  A reservation that passes its region's end sets the
+// fallback flag and stops the item; the count pass, the scan and the write pass then
+// lay out every record again (when the flag is clear they exit at once).
+constexpr uint32_t kFuseUnroll = 4;
+
+struct JoinLdsFused {
+    DevTask task;
+    uint32_t adir[kJoinDirCap + 1];
+    uint32_t bdir[kJoinDirCap + 1];
+    uint64_t bcode[kJoinLdsCap];  // staged target codes, or kJoinLdsCapP packed keys
+    uint32_t bgene[kJoinLdsCap];  // staged target genes, or the query entries' buckets (16 bits each)
+    uint16_t bcnt[kJoinLdsCapP];
+    uint32_t found, next, drop;
+};
+// followed in dynamic LDS by two words per tile of the task: the batch's record count and
+// the write cursor
+
+// A batch of query entries: packed key (or 64-bit code), gene and multiplicity.
+struct FusedBatch {
+    uint64_t code[kFuseUnroll];
+    uint32_t ag[kFuseUnroll], an[kFuseUnroll];
+};
+
+template <bool PACKED>
+__device__ __forceinline__ void fused_load(const DevDict &A, uint32_t base, uint32_t a1, FusedBatch &r) {
+#pragma unroll
+    for (uint32_t q = 0; q < kFuseUnroll; ++q) {
+        const uint32_t i = base + q * kJoinThreads + threadIdx.x;
+        const bool v = i < a1;
+        if constexpr (PACKED) {
+            r.code[q] = v ? A.ix_key[i] : 0u;
+            r.ag[q] = 0u;
+        } else {
+            r.code[q] = v ? A.ix_code[i] : ~0ull;
+            r.ag[q] = v ? A.ix_gene[i] : 0u;
+        }
+        r.an[q] = v ? A.ix_cnt[i] : 0u;
+    }
+}
+
+// Query entries [a0, a1) against the target entries from b0 on (nbe of them): packed keys bk
+// or codes bc with genes bg, counts bn, all indexed relative to b0; bdir is the item's slice
+// of the target directory (index bucket - bl), adir the query's.  abk (packed, optional) holds
+// each query entry's bucket.  Returns false, uniformly, when a region overflowed.
+template <bool PACKED, typename CN>
+__device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, bool loaded, uint32_t a0, uint32_t a1,
+                                            const uint16_t *abk, uint32_t jlo, uint32_t jhi, const uint32_t *adir,
+                                            uint32_t bl, uint32_t b0, uint32_t nbe, const uint64_t *bc,
+                                            const uint32_t *bk, const uint32_t *bg, const CN *bn, const uint32_t *bdir,
+                                            uint32_t *tcount, uint32_t *tcur, uint32_t *drop,
+                                            uint32_t *__restrict__ fill, const DevTile *__restrict__ tiles,
+                                            uint32_t *__restrict__ fallback, uint2 *__restrict__ recs, uint64_t rec_cap) {
+    constexpr uint32_t U = kFuseUnroll;
+    const bool ab = T.flags & 1u, ba = T.flags & 2u;
+    const uint32_t s0 = T.tile_shift[0], s1 = T.tile_shift[1], t1 = T.tiles_n[0];
+    const uint32_t ntiles = T.tiles_n[0] + T.tiles_n[1];
+    const uint32_t sha = T.a.key_shift, shb = T.b.key_shift;
+    const uint32_t mska = (1u << sha) - 1u, mskb = (1u << shb) - 1u;
+    auto gene_at = [&](uint32_t j) -> uint32_t {
+        if constexpr (PACKED) return bk[j] & mskb;
+        else return bg[j];
+    };
+    for (uint32_t base = a0; base < a1; base += U * kJoinThreads) {
+        if (!loaded || base != a0) fused_load<PACKED>(T.a, base, a1, r);
+        uint32_t p[U], m[U];
+        // search: the first target entry of the query's k-mer inside its bucket, and the run length
+#pragma unroll
+        for (uint32_t q = 0; q < U; ++q) {
+            const uint32_t i = base + q * kJoinThreads + threadIdx.x;
+            p[q] = 0;
+            m[q] = 0;
+            if (i >= a1) continue;
+            uint32_t u;
+            uint64_t want;
+            if constexpr (PACKED) {
+                const uint32_t key = static_cast<uint32_t>(r.code[q]);
+                r.ag[q] = key & mska;
+                want = key >> sha;
+                if (abk) {
+                    u = abk[i - a0];
+                } else {  // the last directory slot in [jlo, jhi) with adir <= i
+                    uint32_t lo = jlo, hi = jhi;
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (adir[mid] <= i) lo = mid;
+                        else hi = mid;
+                    }
+                    u = lo;
+                }
+            } else {
+                want = r.code[q];
+                u = bucket_of(want, T.a.k, T.a.lead, T.a.bits) - bl;
+            }
+            const uint32_t end = min(bdir[u + 1] - b0, nbe);
+            uint32_t lo = min(bdir[u] - b0, end), hi = end;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                const uint64_t v = PACKED ? static_cast<uint64_t>(bk[mid] >> shb) : bc[mid];
+                if (v < want) lo = mid + 1;
+                else hi = mid;
+            }
+            uint32_t n = 0;
+            while (lo + n < end && (PACKED ? static_cast<uint64_t>(bk[lo + n] >> shb) : bc[lo + n]) == want) ++n;
+            p[q] = lo;
+            m[q] = n;
+        }
+        // count the batch's records per tile
+#pragma unroll
+        for (uint32_t q = 0; q < U; ++q) {
+            if (!m[q]) continue;
+            if (ab) atomicAdd(&tcount[r.ag[q] >> s0], m[q]);
+            if (ba)
+                for (uint32_t t = 0; t < m[q]; ++t) atomicAdd(&tcount[t1 + (gene_at(p[q] + t) >> s1)], 1u);
+        }
+        __syncthreads();
+        // reserve a run of each fed tile's region; a run past the region's end stops the item
+        for (uint32_t t = threadIdx.x; t < ntiles; t += kJoinThreads) {
+            const uint32_t c = tcount[t];
+            if (!c) continue;
+            const uint32_t gt = T.tile_base[0] + t;
+            const uint32_t at = atomicAdd(&fill[gt], c);
+            const uint32_t rbase = tiles[gt].rbase, rcap = tiles[gt].rcap;
+            if (static_cast<uint64_t>(at) + c > rcap) *drop = 1u;
+            tcur[t] = rbase + at;
+            tcount[t] = 0;
+        }
+        __syncthreads();
+        if (*drop) {
+            if (threadIdx.x == 0) atomicOr(fallback, 1u);
+            return false;
+        }
+        // write the records into the runs
+#pragma unroll
+        for (uint32_t q = 0; q < U; ++q) {
+            if (!m[q]) continue;
+            const uint32_t a = r.ag[q], na = r.an[q];
+            if (ab) {
+                const uint32_t o = atomicAdd(&tcur[a >> s0], m[q]);
+                const uint32_t rl = (a & ((1u << s0) - 1u)) << 24;
+                for (uint32_t t = 0; t < m[q]; ++t)
+                    if (o + t < rec_cap)
+                        recs[o + t] = make_uint2(rl | gene_at(p[q] + t), na | (static_cast<uint32_t>(bn[p[q] + t]) << 16));
+            }
+            if (ba) {
+                for (uint32_t t = 0; t < m[q]; ++t) {
+                    const uint32_t g = gene_at(p[q] + t);
+                    const uint32_t o = atomicAdd(&tcur[t1 + (g >> s1)], 1u);
+                    if (o < rec_cap)
+                        recs[o] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | a, static_cast<uint32_t>(bn[p[q] + t]) | (na << 16));
+                }
+            }
+        }
+    }
+    return true;
+}
+
+// One item of the one-pass join (the same bucket ranges and sub-ranges as the two-pass
+// join).  Ends with a barrier so the LDS can take the next item.
+__device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__restrict__ tasks, uint32_t n_tasks,
+                                            uint32_t *__restrict__ fill, const DevTile *__restrict__ tiles,
+                                            uint32_t *__restrict__ fallback, uint2 *__restrict__ recs,
+                                            uint64_t rec_cap, JoinLdsFused &L, uint32_t *tcount, uint32_t *tcur) {
+    const uint32_t task = find_task_coop(tasks, n_tasks, chunk, &L.found);
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&tasks[task]);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(&L.task);
+        for (uint32_t i = threadIdx.x; i < sizeof(DevTask) / 4; i += blockDim.x) dst[i] = src[i];
+    }
+    // an item that starts after another one overflowed has nothing left to do
+    if (threadIdx.x == 0) L.drop = __hip_atomic_load(fallback, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+    __syncthreads();
+    const DevTask &T = L.task;
+    const uint32_t c = chunk - T.chunk_base;
+    const uint32_t nb = T.a.n_buckets;
+    const uint32_t span = T.bpw * T.subs;
+    const uint32_t bl = c * span;
+    const uint32_t bh = min(nb, bl + span);
+    const uint32_t ntiles = T.tiles_n[0] + T.tiles_n[1];
+    const bool packed = T.a.key_shift && T.b.key_shift;
+    {  // directory slices: all loads of a thread issued before the LDS stores
+        constexpr uint32_t kIters = (kJoinDirCap + 1 + kJoinThreads - 1) / kJoinThreads;
+        uint32_t da[kIters], db[kIters];
+#pragma unroll
+        for (uint32_t it = 0; it < kIters; ++it) {
+            const uint32_t i = threadIdx.x + it * kJoinThreads;
+            da[it] = i <= bh - bl ? T.a.ix_dir[bl + i] : 0u;
+            db[it] = i <= bh - bl ? T.b.ix_dir[bl + i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t it = 0; it < kIters; ++it) {
+            const uint32_t i = threadIdx.x + it * kJoinThreads;
+            if (i <= bh - bl) {
+                L.adir[i] = da[it];
+                L.bdir[i] = db[it];
+            }
+        }
+    }
+    for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) tcount[t] = 0;
+    __syncthreads();
+    const bool skip = L.drop != 0;
+    for (uint32_t s0 = bl; s0 < bh && !skip; s0 += T.bpw) {
+        const uint32_t s1 = min(bh, s0 + T.bpw);
+        const uint32_t a0 = L.adir[s0 - bl], a1 = L.adir[s1 - bl];
+        const uint32_t b0 = L.bdir[s0 - bl], b1 = L.bdir[s1 - bl];
+        if (a0 == a1 || b0 == b1) continue;  // uniform across the work-group
+        const uint32_t nbe = b1 - b0;
+        FusedBatch r;
+        bool ok;
+        if (packed) {
+            uint32_t *bkey = reinterpret_cast<uint32_t *>(L.bcode);  // packed keys take the code stage
+            if (nbe <= kJoinLdsCapP) {
+                uint16_t *abk = a1 - a0 <= kJoinLdsCapP ? reinterpret_cast<uint16_t *>(L.bgene) : nullptr;
+                fused_load<true>(T.a, a0, a1, r);  // in flight while the target side is staged
+                {
+                    constexpr uint32_t kIters = kJoinLdsCapP / kJoinThreads;
+                    uint32_t kv[kIters], cv[kIters];
+#pragma unroll
+                    for (uint32_t it = 0; it < kIters; ++it) {
+                        const uint32_t i = threadIdx.x + it * kJoinThreads;
+                        kv[it] = i < nbe ? T.b.ix_key[b0 + i] : 0u;
+                        cv[it] = i < nbe ? T.b.ix_cnt[b0 + i] : 0u;
+                    }
+#pragma unroll
+                    for (uint32_t it = 0; it < kIters; ++it) {
+                        const uint32_t i = threadIdx.x + it * kJoinThreads;
+                        if (i < nbe) {
+                            bkey[i] = kv[it];
+                            L.bcnt[i] = static_cast<uint16_t>(cv[it]);
+                        }
+                    }
+                }
+                if (abk)
+                    for (uint32_t u = s0 - bl + threadIdx.x; u < s1 - bl; u += kJoinThreads)
+                        for (uint32_t i = L.adir[u]; i < L.adir[u + 1]; ++i) abk[i - a0] = static_cast<uint16_t>(u);
+                __syncthreads();
+                ok = fused_range<true>(T, r, true, a0, a1, abk, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, nullptr, bkey,
+                                       nullptr, L.bcnt, L.bdir, tcount, tcur, &L.drop, fill, tiles, fallback, recs,
+                                       rec_cap);
+                __syncthreads();  // the staged arrays take the next sub-range
+            } else {
+                ok = fused_range<true>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, nullptr,
+                                       T.b.ix_key + b0, nullptr, T.b.ix_cnt + b0, L.bdir, tcount, tcur, &L.drop, fill,
+                                       tiles, fallback, recs, rec_cap);
+            }
+        } else if (nbe <= kJoinLdsCap) {
+            for (uint32_t i = threadIdx.x; i < nbe; i += kJoinThreads) {
+                L.bcode[i] = T.b.ix_code[b0 + i];
+                L.bgene[i] = T.b.ix_gene[b0 + i];
+                L.bcnt[i] = static_cast<uint16_t>(T.b.ix_cnt[b0 + i]);
+            }
+            __syncthreads();
+            ok = fused_range<false>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, L.bcode,
+                                    nullptr, L.bgene, L.bcnt, L.bdir, tcount, tcur, &L.drop, fill, tiles, fallback,
+                                    recs, rec_cap);
+            __syncthreads();
+        } else {
+            ok = fused_range<false>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe,
+                                    T.b.ix_code + b0, nullptr, T.b.ix_gene + b0, T.b.ix_cnt + b0, L.bdir, tcount, tcur,
+                                    &L.drop, fill, tiles, fallback, recs, rec_cap);
+        }
+        if (!ok) break;  // uniform: every thread read the same drop flag after a barrier
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kJoinThreads) void k_join_fused(const DevTask *__restrict__ tasks, uint32_t n_tasks,
+                                                             uint32_t *__restrict__ fill,
+                                                             const DevTile *__restrict__ tiles,
+                                                             uint32_t *__restrict__ fallback,
+                                                             uint2 *__restrict__ recs, uint64_t rec_cap,
+                                                             uint32_t join_tiles) {
+    __shared__ JoinLdsFused L;
+    extern __shared__ uint32_t join_dyn[];
+    fused_chunk(blockIdx.x, tasks, n_tasks, fill, tiles, fallback, recs, rec_cap, L, join_dyn, join_dyn + join_tiles);
+}
+
+__global__ __launch_bounds__(kJoinThreads) void k_join_fused_persistent(
+    const DevTask *__restrict__ tasks, uint32_t n_tasks, uint32_t total_chunks, uint32_t *__restrict__ fill,
+    const DevTile *__restrict__ tiles, uint32_t *__restrict__ fallback, uint2 *__restrict__ recs, uint64_t rec_cap,
+    uint32_t join_tiles, uint32_t *__restrict__ next) {
+    __shared__ JoinLdsFused L;
+    extern __shared__ uint32_t join_dyn[];
+    for (;;) {
+        if (threadIdx.x == 0) L.next = atomicAdd(next, kClaimJoin);
+        __syncthreads();
+        const uint32_t first = L.next;
+        __syncthreads();
+        if (first >= total_chunks) break;
+        const uint32_t last = min(total_chunks, first + kClaimJoin);
+        for (uint32_t chunk = first; chunk < last; ++chunk)
+            fused_chunk(chunk, tasks, n_tasks, fill, tiles, fallback, recs, rec_cap, L, join_dyn,
+                        join_dyn + join_tiles);
+    }
+}
+
+// Each tile's record range for the tile kernels: its region's filled part after the
+// one-pass join, its scanned range after the two-pass join.
+__global__ void k_tile_ranges(const DevTile *__restrict__ tiles, uint32_t n_tiles, const uint32_t *__restrict__ tile_off,
+                              const uint32_t *__restrict__ fill, const uint32_t *__restrict__ fallback,
+                              uint2 *__restrict__ rng) {
+    const bool two = fill == nullptr || *fallback != 0u;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += gridDim.x * blockDim.x) {
+        if (two) {
+            rng[t] = make_uint2(tile_off[t], tile_off[t + 1]);
+        } else {
+            const uint32_t b = tiles[t].rbase;
+            rng[t] = make_uint2(b, b + min(fill[t], tiles[t].rcap));
+        }
     }
 }
 
@@ -961,8 +1287,8 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
     __syncthreads();  // the table takes the next row group
 }
 
-// One tile: its records are tile_off[tile] .. tile_off[tile + 1] of the scanned tile totals
-// (clamped to the record capacity, so a capacity overflow reads no further).  The first
+// One tile: its records are tile_rng[tile] (its region's filled part, or its range of the
+// scanned tile totals, clamped to the record capacity, so a capacity overflow reads no further).  The first
 // launch (WRITE = false) hashes the tile, or, past kHashMax records, groups of whole rows
 // that fit the table (a row alone beyond it is summed densely); ties go to per-row slabs
 // and counts to bh_ptr, and a tile with a row of more than kSlab ties is listed for the
@@ -970,7 +1296,7 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
 // its rows straight into the CSR output in column order.
 template <bool WRITE, bool CM = false>
 __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__restrict__ tasks,
-                                             const DevTile *__restrict__ tiles, const uint32_t *__restrict__ tile_off,
+                                             const DevTile *__restrict__ tiles, const uint2 *__restrict__ tile_rng,
                                              const uint2 *__restrict__ recs, uint64_t rec_cap,
                                              const unsigned long long *__restrict__ total, uint32_t lds_words,
                                              uint32_t *__restrict__ bh_ptr, uint4 *__restrict__ slab,
@@ -981,7 +1307,8 @@ __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__
     const DevTask &T = tasks[tl.task];
     // when the join's records overflowed the scratch its write pass wrote none: every tile is
     // empty then (the status already asks for a larger capacity)
-    const uint64_t c0 = tile_off[tile_id], c1 = tile_off[tile_id + 1];
+    const uint2 rg = tile_rng[tile_id];
+    const uint64_t c0 = rg.x, c1 = rg.y;
     const uint64_t rb = min(c0, rec_cap);
     const uint64_t re = *total > rec_cap ? rb : max(rb, min(c1, rec_cap));
     const uint32_t n = static_cast<uint32_t>(re - rb);
@@ -1023,7 +1350,7 @@ __device__ __forceinline__ void tile_process(uint32_t tile_id, const DevTask *__
 template <bool CM>
 __global__ __launch_bounds__(kTileThreads) void k_tile_count(const DevTask *__restrict__ tasks,
                                                              const DevTile *__restrict__ tiles,
-                                                             const uint32_t *__restrict__ tile_off,
+                                                             const uint2 *__restrict__ tile_rng,
                                                              const uint2 *__restrict__ recs, uint64_t rec_cap,
                                                              const unsigned long long *__restrict__ total,
                                                              uint32_t lds_words, uint32_t *__restrict__ bh_ptr,
@@ -1031,7 +1358,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count(const DevTask *__re
                                                              uint32_t *overflow_count, ColWs cmx) {
     extern __shared__ uint32_t lds[];
     __shared__ TileLds S;
-    tile_process<false, CM>(blockIdx.x, tasks, tiles, tile_off, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr,
+    tile_process<false, CM>(blockIdx.x, tasks, tiles, tile_rng, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr,
                             nullptr, nullptr, 0, overflow_tiles, overflow_count, lds, S, cmx);
 }
 
@@ -1039,7 +1366,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count(const DevTask *__re
 template <bool CM>
 __global__ __launch_bounds__(kTileThreads) void k_tile_count_persistent(
     const DevTask *__restrict__ tasks, const DevTile *__restrict__ tiles, uint32_t total_tiles,
-    const uint32_t *__restrict__ tile_off, const uint2 *__restrict__ recs, uint64_t rec_cap,
+    const uint2 *__restrict__ tile_rng, const uint2 *__restrict__ recs, uint64_t rec_cap,
     const unsigned long long *__restrict__ total, uint32_t lds_words, uint32_t *__restrict__ bh_ptr,
     uint4 *__restrict__ slab, uint32_t *overflow_tiles, uint32_t *overflow_count, uint32_t *__restrict__ next, ColWs cmx) {
     extern __shared__ uint32_t lds[];
@@ -1052,7 +1379,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count_persistent(
         if (first >= total_tiles) break;
         const uint32_t last = min(total_tiles, first + kClaim);
         for (uint32_t t = first; t < last; ++t)
-            tile_process<false, CM>(t, tasks, tiles, tile_off, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr,
+            tile_process<false, CM>(t, tasks, tiles, tile_rng, recs, rec_cap, total, lds_words, bh_ptr, slab, nullptr,
                                     nullptr, nullptr, 0, overflow_tiles, overflow_count, lds, S, cmx);
     }
 }
@@ -1060,7 +1387,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_count_persistent(
 // Rows with more ties than the slab holds: their tiles again, written to the CSR output.
 __global__ __launch_bounds__(kTileThreads) void k_tile_write(const DevTask *__restrict__ tasks,
                                                              const DevTile *__restrict__ tiles,
-                                                             const uint32_t *__restrict__ tile_off,
+                                                             const uint2 *__restrict__ tile_rng,
                                                              const uint2 *__restrict__ recs, uint64_t rec_cap,
                                                              const unsigned long long *__restrict__ total,
                                                              uint32_t lds_words, uint32_t *__restrict__ bh_ptr,
@@ -1072,7 +1399,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_write(const DevTask *__re
     __shared__ TileLds S;
     const uint32_t n = *overflow_count;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
-        tile_process<true>(overflow_tiles[i], tasks, tiles, tile_off, recs, rec_cap, total, lds_words, bh_ptr, nullptr, bh_col,
+        tile_process<true>(overflow_tiles[i], tasks, tiles, tile_rng, recs, rec_cap, total, lds_words, bh_ptr, nullptr, bh_col,
                            bh_num, bh_den, bh_cap, nullptr, nullptr, lds, S, ColWs{});
 }
 
@@ -1267,6 +1594,15 @@ uint32_t persistent_join_grid() {
     return device_cus() * static_cast<uint32_t>(per);
 }
 
+uint32_t persistent_fused_grid(uint32_t join_tiles) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_join_fused_persistent, kJoinThreads, 8 * join_tiles) !=
+            hipSuccess ||
+        per < 1)
+        per = 1;
+    return device_cus() * static_cast<uint32_t>(per);
+}
+
 uint32_t persistent_tile_grid(uint32_t tile_lds) {
     int per = 0;
     int per_cm = 0;
@@ -1307,10 +1643,12 @@ uint64_t pair_ws_bytes(const PlanShape &p) {
     s += align_up(sizeof(DevTile) * std::max<uint64_t>(p.total_tiles, 1), A);
     s += align_up(4 * std::max<uint64_t>(p.n_tasks, 1), A);
     s += align_up(8 * std::max<uint64_t>(p.rec_cap, 1), A);
-    s += align_up(32, A);
+    s += align_up(64, A);
     s += align_up(4 * (uint64_t(p.total_cells) + 1), A);
     s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);  // records per tile (join), consumed by the write pass
     s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);  // scanned: each tile's first record
+    s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);  // one-pass join: records reserved per region
+    s += align_up(8 * (uint64_t(p.total_tiles) + 1), A);  // record range of each tile
     s += align_up(16 * kSlab * (uint64_t(p.bh_rows) + 1), A);
     s += align_up(4 * (uint64_t(p.total_tiles) + 1), A);
     s += align_up(4 * pair_partials(p), A);
@@ -1334,7 +1672,7 @@ PairWs pair_ws_carve(void *ws, const PlanShape &p) {
     w.tiles = reinterpret_cast<DevTile *>(take(sizeof(DevTile) * std::max<uint64_t>(p.total_tiles, 1)));
     w.order = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(p.n_tasks, 1)));
     w.recs = reinterpret_cast<uint2 *>(take(8 * std::max<uint64_t>(p.rec_cap, 1)));
-    w.counters = reinterpret_cast<unsigned long long *>(take(32));
+    w.counters = reinterpret_cast<unsigned long long *>(take(64));
     w.overflow_count = reinterpret_cast<uint32_t *>(w.counters) + 2;
     w.next_join = reinterpret_cast<uint32_t *>(w.counters) + 3;
     w.next_tile = reinterpret_cast<uint32_t *>(w.counters) + 4;
@@ -1342,6 +1680,10 @@ PairWs pair_ws_carve(void *ws, const PlanShape &p) {
     w.cells = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_cells) + 1)));
     w.tile_tot = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
     w.tile_off = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
+    w.fill = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
+    w.tile_rng = reinterpret_cast<uint2 *>(take(8 * (uint64_t(p.total_tiles) + 1)));
+    w.fallback = reinterpret_cast<uint32_t *>(w.counters) + 7;
+    w.next_fused = reinterpret_cast<uint32_t *>(w.counters) + 8;
     w.slab = reinterpret_cast<uint4 *>(take(16 * kSlab * (uint64_t(p.bh_rows) + 1)));
     w.overflow_tiles = reinterpret_cast<uint32_t *>(take(4 * (uint64_t(p.total_tiles) + 1)));
     w.partials = reinterpret_cast<uint32_t *>(take(4 * pair_partials(p)));
@@ -1364,7 +1706,7 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     // status and counters (record total (64 bits), overflow tiles, next join item (count
     // pass), next tile, next join item (write pass), column candidates) in one launch
     hipLaunchKernelGGL(k_pairs_init, dim3(std::max<uint32_t>(1, std::min<uint32_t>(1024, (p.total_tiles + 255) / 256))),
-                       dim3(256), 0, s, st, reinterpret_cast<uint32_t *>(w.counters), w.tile_tot, p.total_tiles);
+                       dim3(256), 0, s, st, reinterpret_cast<uint32_t *>(w.counters), w.tile_tot, w.fill, p.total_tiles);
     PDP_TRY(hipGetLastError());
     const ColWs cmx{w.colkey, w.cands, w.cand_count, p.colmax ? p.cand_cap : 0};
     if (p.colmax) {  // BA rows are counted by atomics; column keys and cursors start at zero
@@ -1375,29 +1717,51 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     PDP_TRY(mark(PDP_KERNEL_JOIN, true));
     if (p.total_chunks) {
         const bool pers = p.join_grid != 0;
-        const dim3 g = pers ? dim3(std::min(p.join_grid, (p.total_chunks + kClaimJoin - 1) / kClaimJoin))
-                            : dim3(p.total_chunks);
-        if (pers)
-            hipLaunchKernelGGL(k_join_persistent<false>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
-                               w.cells, w.tile_tot, w.tile_off, w.counters, w.recs, p.rec_cap, st, w.next_join);
+        // the two-pass join: the main path, or the back-up of the one-pass join (then persistent
+        // and gated on the fallback flag, so it costs a few empty work-groups when not needed)
+        const uint32_t *gate = nullptr;
+        bool two_pers = pers;
+        dim3 g2 = pers ? dim3(std::min(p.join_grid, (p.total_chunks + kClaimJoin - 1) / kClaimJoin)) : dim3(p.total_chunks);
+        if (p.fused) {
+            const uint32_t dyn = 8 * p.join_tiles;
+            if (pers)
+                hipLaunchKernelGGL(k_join_fused_persistent,
+                                   dim3(std::min(p.join_grid, (p.total_chunks + kClaimJoin - 1) / kClaimJoin)),
+                                   dim3(kJoinThreads), dyn, s, w.tasks, p.n_tasks, p.total_chunks, w.fill, w.tiles,
+                                   w.fallback, w.recs, p.rec_cap, p.join_tiles, w.next_fused);
+            else
+                hipLaunchKernelGGL(k_join_fused, dim3(p.total_chunks), dim3(kJoinThreads), dyn, s, w.tasks, p.n_tasks,
+                                   w.fill, w.tiles, w.fallback, w.recs, p.rec_cap, p.join_tiles);
+            PDP_TRY(hipGetLastError());
+            gate = w.fallback;
+            two_pers = true;
+            g2 = dim3(std::max<uint32_t>(1, std::min(p.fallback_grid, (p.total_chunks + kClaimJoin - 1) / kClaimJoin)));
+        }
+        if (two_pers)
+            hipLaunchKernelGGL(k_join_persistent<false>, g2, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
+                               w.cells, w.tile_tot, w.tile_off, w.counters, w.recs, p.rec_cap, st, w.next_join, gate);
         else
-            hipLaunchKernelGGL(k_join<false>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.cells, w.tile_tot,
-                               w.tile_off, w.counters,
-                               w.recs, p.rec_cap, st);
+            hipLaunchKernelGGL(k_join<false>, g2, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.cells, w.tile_tot,
+                               w.tile_off, w.counters, w.recs, p.rec_cap, st, gate);
         PDP_TRY(hipGetLastError());
         PDP_TRY(mark(PDP_KERNEL_BUCKET, true));
         PDP_TRY(launch_scan(w.tile_tot, w.tile_off, p.total_tiles, w.partials, s));
         PDP_TRY(mark(PDP_KERNEL_BUCKET, false));
-        if (pers)
-            hipLaunchKernelGGL(k_join_persistent<true>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
-                               w.cells, w.tile_tot, w.tile_off, w.counters, w.recs, p.rec_cap, st, w.next_join_write);
+        if (two_pers)
+            hipLaunchKernelGGL(k_join_persistent<true>, g2, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
+                               w.cells, w.tile_tot, w.tile_off, w.counters, w.recs, p.rec_cap, st, w.next_join_write, gate);
         else
-            hipLaunchKernelGGL(k_join<true>, g, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.cells, w.tile_tot,
-                               w.tile_off, w.counters,
-                               w.recs, p.rec_cap, st);
+            hipLaunchKernelGGL(k_join<true>, g2, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.cells, w.tile_tot,
+                               w.tile_off, w.counters, w.recs, p.rec_cap, st, gate);
         PDP_TRY(hipGetLastError());
     } else {
         PDP_TRY(launch_fill_u32(w.tile_off, uint64_t(p.total_tiles) + 1, 0u, s));
+    }
+    if (p.total_tiles) {
+        hipLaunchKernelGGL(k_tile_ranges, dim3(std::min<uint32_t>(1024, (p.total_tiles + 255) / 256)), dim3(256), 0, s,
+                           w.tiles, p.total_tiles, w.tile_off, p.fused && p.total_chunks ? w.fill : nullptr, w.fallback,
+                           w.tile_rng);
+        PDP_TRY(hipGetLastError());
     }
     PDP_TRY(mark(PDP_KERNEL_JOIN, false));
     PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, true));
@@ -1405,21 +1769,21 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
         const dim3 g(std::min(p.tile_grid, (p.total_tiles + kClaim - 1) / kClaim));
         if (p.colmax)
             hipLaunchKernelGGL(k_tile_count_persistent<true>, g, dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
-                               p.total_tiles, w.tile_off, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
+                               p.total_tiles, w.tile_rng, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
                                w.overflow_tiles, w.overflow_count, w.next_tile, cmx);
         else
             hipLaunchKernelGGL(k_tile_count_persistent<false>, g, dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles,
-                               p.total_tiles, w.tile_off, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
+                               p.total_tiles, w.tile_rng, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
                                w.overflow_tiles, w.overflow_count, w.next_tile, cmx);
         PDP_TRY(hipGetLastError());
     } else if (p.total_tiles) {
         if (p.colmax)
             hipLaunchKernelGGL(k_tile_count<true>, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks,
-                               w.tiles, w.tile_off, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
+                               w.tiles, w.tile_rng, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
                                w.overflow_tiles, w.overflow_count, cmx);
         else
             hipLaunchKernelGGL(k_tile_count<false>, dim3(p.total_tiles), dim3(kTileThreads), p.tile_lds, s, w.tasks,
-                               w.tiles, w.tile_off, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
+                               w.tiles, w.tile_rng, w.recs, p.rec_cap, w.counters, lds_words, bh->ptr, w.slab,
                                w.overflow_tiles, w.overflow_count, cmx);
         PDP_TRY(hipGetLastError());
     }
@@ -1438,7 +1802,7 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     }
     if (p.total_tiles) {
         const uint32_t g = p.total_tiles < 256 ? p.total_tiles : 256;
-        hipLaunchKernelGGL(k_tile_write, dim3(g), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles, w.tile_off, w.recs,
+        hipLaunchKernelGGL(k_tile_write, dim3(g), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles, w.tile_rng, w.recs,
                            p.rec_cap, w.counters, lds_words, bh->ptr, bh->col, bh->num, bh->den, bh->capacity, w.overflow_tiles,
                            w.overflow_count);
         PDP_TRY(hipGetLastError());

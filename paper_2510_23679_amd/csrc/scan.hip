@@ -12,7 +12,7 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
 
 __global__ void k_status_init(pdp_status *st) {
     st->code = 0;
-    st->reserved = 0;
+    st->flags = 0;
     st->needed = 0;
     st->where = ~0ull;
 }

@@ -156,8 +156,12 @@ def test_colmax_plan_has_tiles_for_one_direction():
     assert info.tiles == 19 + 19  # a's rows of the BBH task, a's rows (as b) of the BA task
     L.pdp_plan_destroy(h)
     bad = pdp.params()
-    bad.flags = 4
+    bad.flags = 8
     assert _plan([(a, b, pdp.PDP_TASK_AB)], bad)[0] == pdp.PDP_E_INVAL
+    # the two-pass join is a known flag
+    rc, h = _plan([(a, b, pdp.PDP_TASK_BBH)], pdp.params(two_pass=True))
+    assert rc == 0
+    L.pdp_plan_destroy(h)
 
 
 def test_plan_rejects_bad_tasks():
