@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                    help="measured HBM traffic per kernel (from rocprofv3 counters), used when its source hash matches")
     p.add_argument("--two-pass", action="store_true", help="join in two passes (count, then write)")
+    p.add_argument("--join-entries", type=int, default=0, help="index entries per join sub-range (0: default)")
+    p.add_argument("--persistent", action="store_true", help="persistent join and tile kernels")
     p.add_argument("--colmax", action="store_true",
                    help="second genome's best hits from column maxima (Alg. 3): join records for one direction only")
     p.add_argument("--theta", default=None, help="length filter as NUM/DEN (Eq. length_threshold); off by default")
@@ -398,7 +400,8 @@ def main():
     def frac(x):
         return tuple(int(v) for v in x.split("/")) if x else None
 
-    prm = pdp.params(theta=frac(args.theta), tau=frac(args.tau), colmax=args.colmax, two_pass=args.two_pass)
+    prm = pdp.params(theta=frac(args.theta), tau=frac(args.tau), colmax=args.colmax, two_pass=args.two_pass,
+                     join_entries=args.join_entries, persistent=args.persistent)
     if args.tune:
         best, tres = pdp.autotune(tasks, reps=3, base=prm)
         prm = best
@@ -512,7 +515,8 @@ def main():
                    "gene_pairs": gene_pairs, "kmer_entries": int(sum(entries)), "best_hits": bh_nnz, "bbh_pairs": bbh_n,
                    "filters": {"theta": args.theta, "tau": args.tau}, "column_maxima": bool(args.colmax)},
         "roofline": roofline,
-        "params": tuned if tuned is not None else "defaults",
+        "params": tuned if tuned is not None else ("defaults" if not (args.join_entries or args.persistent) else
+                                                   {"join_entries": args.join_entries, "persistent": args.persistent}),
         "breakdown": breakdown,
     }
     if not args.no_cpu_baseline:

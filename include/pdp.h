@@ -312,12 +312,15 @@ int32_t pdp_plan_launch(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, 
                         void *ws, uint64_t ws_bytes, void *stream);
 
 /* Kernels of a plan launch, for pdp_plan_timer_start. */
-#define PDP_KERNEL_JOIN 0        /* shared-k-mer join: count pass, scan of the counts, write pass */
+#define PDP_KERNEL_JOIN 0        /* shared-k-mer join: the one-pass kernel (with PDP_PARAM_TWO_PASS: count
+                                    pass, scan of the counts, write pass) */
 #define PDP_KERNEL_BUCKET 1      /* the scan of the per-tile record totals alone */
 #define PDP_KERNEL_TILE_COUNT 2  /* per tile: sort and sum of records, row maxima, tie counts */
 #define PDP_KERNEL_TILE_WRITE 3  /* best-hit output (slab copy, rows with many ties) */
 #define PDP_KERNEL_BBH 4         /* BBH count and write passes together */
 #define PDP_KERNEL_ALL 5         /* the whole launch */
+#define PDP_KERNEL_JOIN_BACKUP 6 /* the two-pass join gated behind the one-pass join (empty unless a
+                                    region overflowed) and the tiles' record ranges */
 
 /* Gene families from the BBH of a launched plan (phase (c): families are
  * extracted from the network the bidirectional best hits form; the paper

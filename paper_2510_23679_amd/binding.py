@@ -49,7 +49,7 @@ def alphabet_id(alphabet) -> int:
 PDP_MAX_WINDOWS = 65535
 
 # kernels that pdp_plan_timer_start can time
-KERNELS = {"join": 0, "bucket": 1, "tile_count": 2, "tile_write": 3, "bbh": 4, "all": 5}
+KERNELS = {"join": 0, "bucket": 1, "tile_count": 2, "tile_write": 3, "bbh": 4, "all": 5, "join_backup": 6}
 
 
 class pdp_status(C.Structure):

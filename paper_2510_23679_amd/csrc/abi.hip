@@ -558,7 +558,7 @@ int32_t pdp_plan_families(const pdp_plan *plan, const pdp_bbh_out *bbh, const ui
 }
 
 int32_t pdp_plan_timer_start(pdp_plan *plan, int32_t kernel, uint32_t max_launches) {
-    if (!plan || kernel < PDP_KERNEL_JOIN || kernel > PDP_KERNEL_ALL || max_launches == 0)
+    if (!plan || kernel < PDP_KERNEL_JOIN || kernel > PDP_KERNEL_JOIN_BACKUP || max_launches == 0)
         return fail(PDP_E_INVAL, "pdp_plan_timer_start: bad argument");
     plan->timer_release();
     for (uint32_t i = 0; i < max_launches; ++i) {

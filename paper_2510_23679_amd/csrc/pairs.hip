@@ -472,7 +472,6 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_persistent(const DevTask 
 // fallback flag and stops the item; the count pass, the scan and the write pass then
 // lay out every record again (when the flag is clear they exit at once).
 constexpr uint32_t kFuseUnroll = 4;
-
 struct JoinLdsFused {
     DevTask task;
     uint32_t adir[kJoinDirCap + 1];
@@ -1714,16 +1713,16 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
         PDP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(w.colkey), 2 * (uint64_t(p.bh_rows) + 1), 0u, s));
         PDP_TRY(launch_fill_u32(w.colcursor, uint64_t(p.bh_rows) + 1, 0u, s));
     }
-    PDP_TRY(mark(PDP_KERNEL_JOIN, true));
+    // the join: the one-pass kernel (PDP_KERNEL_JOIN), then its back-up, the two-pass join gated on
+    // the fallback flag (PDP_KERNEL_JOIN_BACKUP); with PDP_PARAM_TWO_PASS the two passes are the join
     if (p.total_chunks) {
         const bool pers = p.join_grid != 0;
-        // the two-pass join: the main path, or the back-up of the one-pass join (then persistent
-        // and gated on the fallback flag, so it costs a few empty work-groups when not needed)
         const uint32_t *gate = nullptr;
         bool two_pers = pers;
         dim3 g2 = pers ? dim3(std::min(p.join_grid, (p.total_chunks + kClaimJoin - 1) / kClaimJoin)) : dim3(p.total_chunks);
         if (p.fused) {
             const uint32_t dyn = 8 * p.join_tiles;
+            PDP_TRY(mark(PDP_KERNEL_JOIN, true));
             if (pers)
                 hipLaunchKernelGGL(k_join_fused_persistent,
                                    dim3(std::min(p.join_grid, (p.total_chunks + kClaimJoin - 1) / kClaimJoin)),
@@ -1733,9 +1732,14 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
                 hipLaunchKernelGGL(k_join_fused, dim3(p.total_chunks), dim3(kJoinThreads), dyn, s, w.tasks, p.n_tasks,
                                    w.fill, w.tiles, w.fallback, w.recs, p.rec_cap, p.join_tiles);
             PDP_TRY(hipGetLastError());
+            PDP_TRY(mark(PDP_KERNEL_JOIN, false));
+            PDP_TRY(mark(PDP_KERNEL_JOIN_BACKUP, true));
+            // the back-up is persistent and gated: a few empty work-groups when no region overflowed
             gate = w.fallback;
             two_pers = true;
             g2 = dim3(std::max<uint32_t>(1, std::min(p.fallback_grid, (p.total_chunks + kClaimJoin - 1) / kClaimJoin)));
+        } else {
+            PDP_TRY(mark(PDP_KERNEL_JOIN, true));
         }
         if (two_pers)
             hipLaunchKernelGGL(k_join_persistent<false>, g2, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, p.total_chunks,
@@ -1754,7 +1758,14 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
             hipLaunchKernelGGL(k_join<true>, g2, dim3(kJoinThreads), 0, s, w.tasks, p.n_tasks, w.cells, w.tile_tot,
                                w.tile_off, w.counters, w.recs, p.rec_cap, st, gate);
         PDP_TRY(hipGetLastError());
+        if (!p.fused) {
+            PDP_TRY(mark(PDP_KERNEL_JOIN, false));
+            PDP_TRY(mark(PDP_KERNEL_JOIN_BACKUP, true));
+        }
     } else {
+        PDP_TRY(mark(PDP_KERNEL_JOIN, true));
+        PDP_TRY(mark(PDP_KERNEL_JOIN, false));
+        PDP_TRY(mark(PDP_KERNEL_JOIN_BACKUP, true));
         PDP_TRY(launch_fill_u32(w.tile_off, uint64_t(p.total_tiles) + 1, 0u, s));
     }
     if (p.total_tiles) {
@@ -1763,7 +1774,7 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
                            w.tile_rng);
         PDP_TRY(hipGetLastError());
     }
-    PDP_TRY(mark(PDP_KERNEL_JOIN, false));
+    PDP_TRY(mark(PDP_KERNEL_JOIN_BACKUP, false));
     PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, true));
     if (p.total_tiles && p.tile_grid) {
         const dim3 g(std::min(p.tile_grid, (p.total_tiles + kClaim - 1) / kClaim));
