@@ -485,9 +485,9 @@ def main():
     try:
         with open(args.traffic) as f:
             tr = json.load(f)
-        if (tr.get("source_hash") == source_hash() and tr.get("alphabet", "aa") == args.alphabet
-                and args.kernel in tr.get("kernels", {})):
-            traffic = tr["kernels"][args.kernel]["hbm_bytes_per_launch"]
+        kernels = tr.get("workloads", {}).get(args.alphabet, {}).get("kernels", {})
+        if tr.get("source_hash") == source_hash() and args.kernel in kernels and not (args.two_pass or args.colmax):
+            traffic = kernels[args.kernel]["hbm_bytes_per_launch"]
     except (OSError, ValueError):
         pass
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
