@@ -46,6 +46,7 @@ int32_t pdp::api_fail(int32_t code, const char *fmt, ...) {
 struct pdp_plan {
     std::vector<DevTask> tasks;
     std::vector<DevTile> tiles;
+    std::vector<DevItem> items;
     std::vector<uint32_t> ab_row, ba_row, bbh_row;
     std::vector<uint32_t> order;  // order[t]: position of caller task t in the task table
     PlanShape shape;
@@ -393,6 +394,18 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         DevTask d = caller[t];
         d.chunk_base = static_cast<uint32_t>(chunks);
         chunks += d.n_chunks;
+        {  // the task's join items: bucket ranges of bpw * subs buckets
+            const uint64_t span = uint64_t(d.bpw) * d.subs;
+            for (uint32_t c = 0; c < d.n_chunks; ++c) {
+                DevItem it;
+                const uint64_t bl = c * span;
+                it.adir = d.a.ix_dir + bl;
+                it.bdir = d.b.ix_dir + bl;
+                it.task = i;
+                it.n_buckets = static_cast<uint32_t>(std::min<uint64_t>(d.a.n_buckets - bl, span));
+                P->items.push_back(it);
+            }
+        }
         d.cell_base = static_cast<uint32_t>(cells);
         uint32_t tile_local = 0;
         const uint64_t dir_est = (tasks[t].a->capacity + tasks[t].b->capacity) / 8 + 4096;
@@ -488,6 +501,10 @@ int32_t pdp_plan_upload(const pdp_plan *plan, void *ws, uint64_t ws_bytes, void 
     if (e != hipSuccess) return hip_fail(e, "pdp_plan_upload");
     e = hipMemcpyAsync(w.order, plan->order.data(), sizeof(uint32_t) * plan->order.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "pdp_plan_upload");
+    if (!plan->items.empty()) {
+        e = hipMemcpyAsync(w.items, plan->items.data(), sizeof(DevItem) * plan->items.size(), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "pdp_plan_upload");
+    }
     if (!plan->tiles.empty()) {
         e = hipMemcpyAsync(w.tiles, plan->tiles.data(), sizeof(DevTile) * plan->tiles.size(), hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "pdp_plan_upload");

@@ -105,6 +105,15 @@ struct DevTask {
     uint32_t theta_n, theta_d, tau_n, tau_d;  // candidate filters (zero denominator: off)
 };
 
+// A join item of the one-pass join, laid out by the plan: its task, its buckets' slices of
+// both genomes' directories (from its first bucket), and how many buckets it covers.
+struct DevItem {
+    const uint32_t *adir;
+    const uint32_t *bdir;
+    uint32_t task;
+    uint32_t n_buckets;
+};
+
 struct DevTile {
     uint32_t task;
     uint32_t dir;
@@ -158,6 +167,7 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
 struct PairWs {
     DevTask *tasks;
     DevTile *tiles;
+    DevItem *items;               // one per join item (the one-pass join)
     uint2 *recs;                  // records grouped by tile: ((row in tile << 24) | column, min count)
     unsigned long long *counters; // [0] records counted by the join
     uint32_t *cells;              // (item, tile) record counts of the join's count pass, item-major

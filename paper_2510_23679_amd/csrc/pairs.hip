@@ -625,47 +625,47 @@ __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, boo
 
 // One item of the one-pass join (the same bucket ranges and sub-ranges as the two-pass
 // join).  Ends with a barrier so the LDS can take the next item.
-__device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__restrict__ tasks, uint32_t n_tasks,
-                                            uint32_t *__restrict__ fill, const DevTile *__restrict__ tiles,
-                                            uint32_t *__restrict__ fallback, uint2 *__restrict__ recs,
-                                            uint64_t rec_cap, JoinLdsFused &L, uint32_t *tcount, uint32_t *tcur) {
-    const uint32_t task = find_task_coop(tasks, n_tasks, chunk, &L.found);
+__device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__restrict__ tasks,
+                                            const DevItem *__restrict__ items, uint32_t *__restrict__ fill,
+                                            const DevTile *__restrict__ tiles, uint32_t *__restrict__ fallback,
+                                            uint2 *__restrict__ recs, uint64_t rec_cap, JoinLdsFused &L,
+                                            uint32_t *tcount, uint32_t *tcur, uint32_t join_tiles) {
+    // set-up in one round of loads: the item (same address for every thread), then the task's
+    // words and both directory slices together
+    const DevItem it = items[chunk];
     {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(&tasks[task]);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(&L.task);
-        for (uint32_t i = threadIdx.x; i < sizeof(DevTask) / 4; i += blockDim.x) dst[i] = src[i];
-    }
-    // an item that starts after another one overflowed has nothing left to do
-    if (threadIdx.x == 0) L.drop = __hip_atomic_load(fallback, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
-    __syncthreads();
-    const DevTask &T = L.task;
-    const uint32_t c = chunk - T.chunk_base;
-    const uint32_t nb = T.a.n_buckets;
-    const uint32_t span = T.bpw * T.subs;
-    const uint32_t bl = c * span;
-    const uint32_t bh = min(nb, bl + span);
-    const uint32_t ntiles = T.tiles_n[0] + T.tiles_n[1];
-    const bool packed = T.a.key_shift && T.b.key_shift;
-    {  // directory slices: all loads of a thread issued before the LDS stores
+        constexpr uint32_t kTaskWords = sizeof(DevTask) / 4;
         constexpr uint32_t kIters = (kJoinDirCap + 1 + kJoinThreads - 1) / kJoinThreads;
+        static_assert(kTaskWords <= kJoinThreads, "one task word per thread");
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&tasks[it.task]);
+        const uint32_t tw = threadIdx.x < kTaskWords ? src[threadIdx.x] : 0u;
         uint32_t da[kIters], db[kIters];
 #pragma unroll
-        for (uint32_t it = 0; it < kIters; ++it) {
-            const uint32_t i = threadIdx.x + it * kJoinThreads;
-            da[it] = i <= bh - bl ? T.a.ix_dir[bl + i] : 0u;
-            db[it] = i <= bh - bl ? T.b.ix_dir[bl + i] : 0u;
+        for (uint32_t k = 0; k < kIters; ++k) {
+            const uint32_t i = threadIdx.x + k * kJoinThreads;
+            da[k] = i <= it.n_buckets ? it.adir[i] : 0u;
+            db[k] = i <= it.n_buckets ? it.bdir[i] : 0u;
         }
+        for (uint32_t t = threadIdx.x; t < join_tiles; t += kJoinThreads) tcount[t] = 0;
+        // an item that starts after another one overflowed has nothing left to do
+        if (threadIdx.x == 0) L.drop = __hip_atomic_load(fallback, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+        if (threadIdx.x < kTaskWords) reinterpret_cast<uint32_t *>(&L.task)[threadIdx.x] = tw;
 #pragma unroll
-        for (uint32_t it = 0; it < kIters; ++it) {
-            const uint32_t i = threadIdx.x + it * kJoinThreads;
-            if (i <= bh - bl) {
-                L.adir[i] = da[it];
-                L.bdir[i] = db[it];
+        for (uint32_t k = 0; k < kIters; ++k) {
+            const uint32_t i = threadIdx.x + k * kJoinThreads;
+            if (i <= it.n_buckets) {
+                L.adir[i] = da[k];
+                L.bdir[i] = db[k];
             }
         }
     }
-    for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) tcount[t] = 0;
     __syncthreads();
+    const DevTask &T = L.task;
+    const uint32_t c = chunk - T.chunk_base;
+    const uint32_t span = T.bpw * T.subs;
+    const uint32_t bl = c * span;
+    const uint32_t bh = bl + it.n_buckets;
+    const bool packed = T.a.key_shift && T.b.key_shift;
     const bool skip = L.drop != 0;
     for (uint32_t s0 = bl; s0 < bh && !skip; s0 += T.bpw) {
         const uint32_t s1 = min(bh, s0 + T.bpw);
@@ -732,7 +732,8 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kJoinThreads) void k_join_fused(const DevTask *__restrict__ tasks, uint32_t n_tasks,
+__global__ __launch_bounds__(kJoinThreads) void k_join_fused(const DevTask *__restrict__ tasks,
+                                                             const DevItem *__restrict__ items,
                                                              uint32_t *__restrict__ fill,
                                                              const DevTile *__restrict__ tiles,
                                                              uint32_t *__restrict__ fallback,
@@ -740,13 +741,14 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_fused(const DevTask *__re
                                                              uint32_t join_tiles) {
     __shared__ JoinLdsFused L;
     extern __shared__ uint32_t join_dyn[];
-    fused_chunk(blockIdx.x, tasks, n_tasks, fill, tiles, fallback, recs, rec_cap, L, join_dyn, join_dyn + join_tiles);
+    fused_chunk(blockIdx.x, tasks, items, fill, tiles, fallback, recs, rec_cap, L, join_dyn, join_dyn + join_tiles,
+                join_tiles);
 }
 
 __global__ __launch_bounds__(kJoinThreads) void k_join_fused_persistent(
-    const DevTask *__restrict__ tasks, uint32_t n_tasks, uint32_t total_chunks, uint32_t *__restrict__ fill,
-    const DevTile *__restrict__ tiles, uint32_t *__restrict__ fallback, uint2 *__restrict__ recs, uint64_t rec_cap,
-    uint32_t join_tiles, uint32_t *__restrict__ next) {
+    const DevTask *__restrict__ tasks, const DevItem *__restrict__ items, uint32_t total_chunks,
+    uint32_t *__restrict__ fill, const DevTile *__restrict__ tiles, uint32_t *__restrict__ fallback,
+    uint2 *__restrict__ recs, uint64_t rec_cap, uint32_t join_tiles, uint32_t *__restrict__ next) {
     __shared__ JoinLdsFused L;
     extern __shared__ uint32_t join_dyn[];
     for (;;) {
@@ -757,8 +759,8 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_fused_persistent(
         if (first >= total_chunks) break;
         const uint32_t last = min(total_chunks, first + kClaimJoin);
         for (uint32_t chunk = first; chunk < last; ++chunk)
-            fused_chunk(chunk, tasks, n_tasks, fill, tiles, fallback, recs, rec_cap, L, join_dyn,
-                        join_dyn + join_tiles);
+            fused_chunk(chunk, tasks, items, fill, tiles, fallback, recs, rec_cap, L, join_dyn, join_dyn + join_tiles,
+                        join_tiles);
     }
 }
 
@@ -1640,6 +1642,7 @@ uint64_t pair_ws_bytes(const PlanShape &p) {
     uint64_t s = 0;
     s += align_up(sizeof(DevTask) * std::max<uint64_t>(p.n_tasks, 1), A);
     s += align_up(sizeof(DevTile) * std::max<uint64_t>(p.total_tiles, 1), A);
+    s += align_up(sizeof(DevItem) * std::max<uint64_t>(p.total_chunks, 1), A);
     s += align_up(4 * std::max<uint64_t>(p.n_tasks, 1), A);
     s += align_up(8 * std::max<uint64_t>(p.rec_cap, 1), A);
     s += align_up(64, A);
@@ -1669,6 +1672,7 @@ PairWs pair_ws_carve(void *ws, const PlanShape &p) {
     PairWs w;
     w.tasks = reinterpret_cast<DevTask *>(take(sizeof(DevTask) * std::max<uint64_t>(p.n_tasks, 1)));
     w.tiles = reinterpret_cast<DevTile *>(take(sizeof(DevTile) * std::max<uint64_t>(p.total_tiles, 1)));
+    w.items = reinterpret_cast<DevItem *>(take(sizeof(DevItem) * std::max<uint64_t>(p.total_chunks, 1)));
     w.order = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(p.n_tasks, 1)));
     w.recs = reinterpret_cast<uint2 *>(take(8 * std::max<uint64_t>(p.rec_cap, 1)));
     w.counters = reinterpret_cast<unsigned long long *>(take(64));
@@ -1726,10 +1730,10 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
             if (pers)
                 hipLaunchKernelGGL(k_join_fused_persistent,
                                    dim3(std::min(p.join_grid, (p.total_chunks + kClaimJoin - 1) / kClaimJoin)),
-                                   dim3(kJoinThreads), dyn, s, w.tasks, p.n_tasks, p.total_chunks, w.fill, w.tiles,
+                                   dim3(kJoinThreads), dyn, s, w.tasks, w.items, p.total_chunks, w.fill, w.tiles,
                                    w.fallback, w.recs, p.rec_cap, p.join_tiles, w.next_fused);
             else
-                hipLaunchKernelGGL(k_join_fused, dim3(p.total_chunks), dim3(kJoinThreads), dyn, s, w.tasks, p.n_tasks,
+                hipLaunchKernelGGL(k_join_fused, dim3(p.total_chunks), dim3(kJoinThreads), dyn, s, w.tasks, w.items,
                                    w.fill, w.tiles, w.fallback, w.recs, p.rec_cap, p.join_tiles);
             PDP_TRY(hipGetLastError());
             PDP_TRY(mark(PDP_KERNEL_JOIN, false));
