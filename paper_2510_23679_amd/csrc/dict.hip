@@ -679,6 +679,16 @@ __device__ void bin_directory(const DevBuild &B, CP code, uint32_t n, uint32_t l
 }
 
 __device__ __forceinline__ uint64_t rec_code(const uint4 &r) { return (static_cast<uint64_t>(r.y) << 32) | r.x; }
+__device__ __forceinline__ uint32_t rec_gene(const uint4 &r) { return r.z; }
+__device__ __forceinline__ uint32_t rec_cnt(const uint4 &r) { return r.w; }
+__device__ __forceinline__ uint64_t rec_code(const uint2 &r) { return r.x; }
+__device__ __forceinline__ uint32_t rec_gene(const uint2 &r) { return r.y & 0xFFFFu; }
+__device__ __forceinline__ uint32_t rec_cnt(const uint2 &r) { return r.y >> 16; }
+// An index record in the form a bin sort keeps in LDS: uint4 = (code low, code high, gene,
+// count), or, when every genome of the build has codes of at most 32 bits and at most 65536
+// genes, uint2 = (code, gene | count << 16): half the LDS, more work-groups per CU.
+__device__ __forceinline__ void to_rec(const uint4 &v, uint4 *r) { *r = v; }
+__device__ __forceinline__ void to_rec(const uint4 &v, uint2 *r) { *r = make_uint2(v.x, v.z | (v.w << 16)); }
 
 // Packed join key of an index entry: the code's trailing letters (the leading ones are
 // the bucket) above the gene.
@@ -688,21 +698,25 @@ __device__ __forceinline__ uint32_t entry_key(const DevBuild &B, uint64_t code, 
     return static_cast<uint32_t>(tail << B.key_shift) | gene;
 }
 
-__device__ __forceinline__ void put_entry(const DevBuild &B, uint32_t pos, const uint4 &v) {
+template <typename R>
+__device__ __forceinline__ void put_entry(const DevBuild &B, uint32_t pos, const R &v) {
     const uint64_t c = rec_code(v);
+    const uint32_t g = rec_gene(v);
     B.ix_code[pos] = c;
-    B.ix_gene[pos] = v.z;
-    B.ix_cnt[pos] = v.w;
-    if (B.key_shift) B.ix_key[pos] = entry_key(B, c, v.z);
+    B.ix_gene[pos] = g;
+    B.ix_cnt[pos] = rec_cnt(v);
+    if (B.key_shift) B.ix_key[pos] = entry_key(B, c, g);
 }
-__device__ __forceinline__ bool rec_less(const uint4 &a, const uint4 &b) {
-    return entry_less(rec_code(a), a.z, rec_code(b), b.z);
+template <typename R>
+__device__ __forceinline__ bool rec_less(const R &a, const R &b) {
+    return entry_less(rec_code(a), rec_gene(a), rec_code(b), rec_gene(b));
 }
 
 // Work-group sort of index records (code, gene, count) in LDS by (code, gene).
-__device__ __forceinline__ void sort_recs(uint4 *r, uint32_t n) {
+template <typename R>
+__device__ __forceinline__ void sort_recs(R *r, uint32_t n) {
     wg_network_sort(n, [&](uint32_t lo, uint32_t hi) {
-        const uint4 a = r[lo], b = r[hi];
+        const R a = r[lo], b = r[hi];
         if (rec_less(b, a)) {
             r[lo] = b;
             r[hi] = a;
@@ -729,9 +743,10 @@ __device__ __forceinline__ uint32_t bin_slot(const DevBuild &B, uint64_t code, u
 // every bucket are the directory, then every slot sorted on its own, by one thread
 // (insertion sort) or, if large, by the work-group.  Otherwise the whole bin is sorted in
 // LDS, or in place in global memory when it does not fit.
+template <typename R>
 __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict__ table, uint32_t n_genomes,
                                                      const uint32_t *__restrict__ off) {
-    __shared__ uint4 s_rec[kIxBinLds];
+    __shared__ R s_rec[kIxBinLds];
     __shared__ uint32_t s_bstart[kIxBinSlots + 1];
     __shared__ uint32_t s_big[kIxBigList];
     __shared__ uint32_t s_tmp[256 / kWave + 1];
@@ -751,16 +766,20 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
     const uint32_t b1 = min(B.nb, (h + 1) << B.hshift);
     const uint32_t nbb = b1 - b0;
     const uint32_t nslot = nbb << B.xb;
+    const uint4 *tmp = B.ix_tmp;
     if (n <= kIxBinLds && nslot <= kIxBinSlots) {
         for (uint32_t i = threadIdx.x; i <= nslot; i += 256) s_bstart[i] = 0;
         __syncthreads();
-        uint4 r[kIxPer];
+        R r[kIxPer];
+        uint4 w[kIxPer];
         uint32_t slot[kIxPer], bk[kIxPer];
 #pragma unroll
         for (uint32_t q = 0; q < kIxPer; ++q) {  // every load issued before the first atomic
             const uint32_t i = q * 256 + threadIdx.x;
-            r[q] = i < n ? B.ix_tmp[lo + i] : make_uint4(0, 0, 0, 0);
+            w[q] = i < n ? tmp[lo + i] : make_uint4(0, 0, 0, 0);
         }
+#pragma unroll
+        for (uint32_t q = 0; q < kIxPer; ++q) to_rec(w[q], &r[q]);
 #pragma unroll
         for (uint32_t q = 0; q < kIxPer; ++q) {
             const uint32_t i = q * 256 + threadIdx.x;
@@ -799,7 +818,7 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
             const uint32_t st = s_bstart[b], size = s_bstart[b + 1] - st;
             if (size <= kIxSmallBucket) {
                 for (uint32_t x = st + 1; x < st + size; ++x) {
-                    const uint4 v = s_rec[x];
+                    const R v = s_rec[x];
                     uint32_t y = x;
                     while (y > st && rec_less(v, s_rec[y - 1])) {
                         s_rec[y] = s_rec[y - 1];
@@ -825,7 +844,7 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < n; i += 256) put_entry(B, lo + i, s_rec[i]);
     } else if (n <= kIxBinLds) {
-        for (uint32_t i = threadIdx.x; i < n; i += 256) s_rec[i] = B.ix_tmp[lo + i];
+        for (uint32_t i = threadIdx.x; i < n; i += 256) to_rec(tmp[lo + i], &s_rec[i]);
         __syncthreads();
         sort_recs(s_rec, n);
         for (uint32_t i = threadIdx.x; i < n; i += 256) put_entry(B, lo + i, s_rec[i]);
@@ -833,10 +852,10 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
         bin_directory(B, B.ix_code + lo, n, lo, b0, b1);
     } else {
         for (uint32_t i = threadIdx.x; i < n; i += 256) {
-            const uint4 v = B.ix_tmp[lo + i];
+            const uint4 v = tmp[lo + i];
             B.ix_code[lo + i] = rec_code(v);
-            B.ix_gene[lo + i] = v.z;
-            B.ix_cnt[lo + i] = v.w;
+            B.ix_gene[lo + i] = rec_gene(v);
+            B.ix_cnt[lo + i] = rec_cnt(v);
         }
         __syncthreads();
         sort_entries(B.ix_code + lo, B.ix_gene + lo, B.ix_cnt + lo, n);
@@ -1053,10 +1072,18 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
     PDP_TRY(hipGetLastError());
     PDP_TRY(launch_scan(bintot, binoff, sh.total_bins, partials, s));  // every bin's range
     hipLaunchKernelGGL(k_ix_place, dim3(static_cast<uint32_t>(sh.total_blocks)), dim3(kIxPlaceThreads), hist_lds, s, table,
-                       n, dcnt,
-                       binoff, bintot, ent_gene);
+                       n, dcnt, binoff, bintot, ent_gene);
     PDP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_ix_sort_bin, dim3(static_cast<uint32_t>(sh.total_bins)), dim3(256), 0, s, table, n, binoff);
+    // bins sorted in LDS as 8-byte records when every code fits 32 bits and every gene index 16 bits
+    bool narrow_rec = true;
+    for (uint32_t i = 0; i < n; ++i)
+        narrow_rec &= alpha_spec(d[i]->alphabet).bits * d[i]->k <= 32 && g[i].n_genes <= 65536;
+    if (narrow_rec)
+        hipLaunchKernelGGL(k_ix_sort_bin<uint2>, dim3(static_cast<uint32_t>(sh.total_bins)), dim3(256), 0, s, table, n,
+                           binoff);
+    else
+        hipLaunchKernelGGL(k_ix_sort_bin<uint4>, dim3(static_cast<uint32_t>(sh.total_bins)), dim3(256), 0, s, table, n,
+                           binoff);
     PDP_TRY(hipGetLastError());
     return hipSuccess;
 }
