@@ -56,7 +56,7 @@ def parse():
                         "rule with |alphabet| = 4)")
     p.add_argument("--workload", choices=("allpairs", "batched", "serving"), default="allpairs",
                    help="allpairs: the 10 x 3000 metric (default); batched: independent instances in waves, one "
-                        "graph-captured persistent launch per wave, against one plan per genome pair; serving: "
+                        "graph-captured launch per wave, against one plan per genome pair; serving: "
                         "resident dictionaries and a Poisson stream of arriving genomes")
     p.add_argument("--instances", type=int, default=64, help="batched: instances (of the 400-instance workload)")
     p.add_argument("--wave-genomes", type=int, default=256, help="batched: genomes per wave")
@@ -160,7 +160,7 @@ def _pctl(xs, q):
 
 def run_batched(args):
     """Workload 4 sample: independent instances, all pairs of each, in waves.  A wave is one
-    dictionary build of all its genomes (k per instance) plus one persistent plan launch,
+    dictionary build of all its genomes (k per instance) plus one plan launch,
     captured in a HIP graph; its replay is timed with events.  Instance latency = its wave's
     time (every instance of a wave finishes in the same launch).  The same pairs are also
     timed with one plan per genome pair (a sample), the launch pattern batching replaces."""
@@ -206,7 +206,7 @@ def run_batched(args):
                         tasks.append((batch.dicts[first + i], batch.dicts[first + j],
                                       pdp.PDP_TASK_AB | pdp.PDP_TASK_BA | pdp.PDP_TASK_BBH))
                         gp += devs[first + i].n_genes * devs[first + j].n_genes
-            runner = pdp.PairRunner(tasks, pdp.params(persistent=True))
+            runner = pdp.PairRunner(tasks, pdp.params(persistent=args.persistent))
             runner.run(stream)
             batch.check_status()
             graph = pdp.Graph.capture(stream)
@@ -226,11 +226,12 @@ def run_batched(args):
             code = pdp.read_status(runner.status)[0]
             if code != 0:
                 raise SystemExit(f"wave {w}: device status {code}")
+            two_pass = bool(pdp.status_flags(runner.status) & pdp.PDP_STATUS_TWO_PASS)
             total_gp += gp
             total_ms += ms
             lat += [ms] * len(wave)
             wave_rows.append({"instances": len(wave), "genomes": len(devs), "pairs": len(tasks), "gene_pairs": gp,
-                              "ms": round(ms, 3)})
+                              "ms": round(ms, 3), "join_two_passes": two_pass})
             # one plan per genome pair, launched back to back (sampled)
             pick = rng.choice(len(tasks), min(args.per_pair_sample, len(tasks)), replace=False)
             singles = [pdp.PairRunner([tasks[t]]) for t in pick]

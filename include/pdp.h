@@ -254,7 +254,10 @@ typedef struct pdp_params {
  * default one pass searches every query entry once and writes each record into
  * its tile's region, whose size the plan derives from the record capacity; when
  * a region overflows, the two passes run after it and lay the records out
- * exactly.  Results are identical either way. */
+ * exactly, and the regions in the workspace are refitted to that launch's
+ * record counts (with the spare capacity spread in proportion), so the next
+ * launch on the same dictionaries fits in one pass.  pdp_plan_upload restores
+ * the estimated regions.  Results are identical either way. */
 #define PDP_PARAM_TWO_PASS 4u
 
 /* One unit of work: genomes a and b (same k and alphabet).  flags select the outputs. */

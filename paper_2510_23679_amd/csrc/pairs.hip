@@ -765,14 +765,28 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_fused_persistent(
 }
 
 // Each tile's record range for the tile kernels: its region's filled part after the
-// one-pass join, its scanned range after the two-pass join.
-__global__ void k_tile_ranges(const DevTile *__restrict__ tiles, uint32_t n_tiles, const uint32_t *__restrict__ tile_off,
+// one-pass join, its scanned range after the two-pass join.  When the two passes backed up
+// the one-pass join (and the records fitted the capacity), the regions are refitted to this
+// launch's exact counts: tile t's region starts at off_t + floor(slack * off_t / total), with
+// off_t its scanned offset and slack the capacity left over, so every region holds its count
+// and the regions still fill the capacity.  The next launch of the plan on the same
+// dictionaries then fits in one pass.
+__global__ void k_tile_ranges(DevTile *__restrict__ tiles, uint32_t n_tiles, const uint32_t *__restrict__ tile_off,
                               const uint32_t *__restrict__ fill, const uint32_t *__restrict__ fallback,
-                              uint2 *__restrict__ rng) {
+                              uint64_t rec_cap, uint2 *__restrict__ rng) {
     const bool two = fill == nullptr || *fallback != 0u;
+    const uint64_t total = tile_off[n_tiles];
+    const bool refit = fill != nullptr && two && total <= rec_cap && total > 0;
+    const uint64_t slack = refit ? rec_cap - total : 0;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += gridDim.x * blockDim.x) {
         if (two) {
-            rng[t] = make_uint2(tile_off[t], tile_off[t + 1]);
+            const uint32_t o0 = tile_off[t], o1 = tile_off[t + 1];
+            rng[t] = make_uint2(o0, o1);
+            if (refit) {
+                const uint64_t r0 = o0 + slack * o0 / total, r1 = o1 + slack * o1 / total;
+                tiles[t].rbase = static_cast<uint32_t>(r0);
+                tiles[t].rcap = static_cast<uint32_t>(r1 - r0);
+            }
         } else {
             const uint32_t b = tiles[t].rbase;
             rng[t] = make_uint2(b, b + min(fill[t], tiles[t].rcap));
@@ -1775,7 +1789,7 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     if (p.total_tiles) {
         hipLaunchKernelGGL(k_tile_ranges, dim3(std::min<uint32_t>(1024, (p.total_tiles + 255) / 256)), dim3(256), 0, s,
                            w.tiles, p.total_tiles, w.tile_off, p.fused && p.total_chunks ? w.fill : nullptr, w.fallback,
-                           w.tile_rng);
+                           p.rec_cap, w.tile_rng);
         PDP_TRY(hipGetLastError());
     }
     PDP_TRY(mark(PDP_KERNEL_JOIN_BACKUP, false));

@@ -3,7 +3,8 @@
 By default one pass searches each query entry once and writes its records into
 per-tile regions that the plan sizes from the record capacity.  When a region
 overflows, the count pass, the scan and the write pass run after it and lay the
-records out exactly (pdp_status.flags reports PDP_STATUS_TWO_PASS).  PDP_PARAM_TWO_PASS
+records out exactly (pdp_status.flags reports PDP_STATUS_TWO_PASS), and the
+regions are refitted to that launch's counts for the next launch.  PDP_PARAM_TWO_PASS
 asks for the two passes from the start.  Each layout must give the oracle's best
 hits and BBH, element by element.
 """
@@ -90,7 +91,13 @@ def test_region_overflow_falls_back_to_two_passes(persistent):
     assert code == 0
     assert pdp.status_flags(r.status) & pdp.PDP_STATUS_TWO_PASS
     _compare(ds.genomes, k, r.results())
-    # the next launch of the same plan starts from a clear flag and overflows again
+    # the fallback refitted the regions to the exact counts (no slack is left here): the next
+    # launch of the same plan on the same dictionaries fits in one pass
+    r.launch()
+    assert pdp.read_status(r.status)[0] == 0 and pdp.status_flags(r.status) == 0
+    _compare(ds.genomes, k, r.results())
+    # a fresh upload of the plan tables restores the estimated regions, and the fallback again
+    r.plan.upload(r.ws)
     r.launch()
     assert pdp.read_status(r.status)[0] == 0 and pdp.status_flags(r.status) & pdp.PDP_STATUS_TWO_PASS
     _compare(ds.genomes, k, r.results())
