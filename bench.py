@@ -355,6 +355,7 @@ def run_serving(args):
            "service_ms": {"p50": round(_pctl(svc, 50), 3), "p99": round(_pctl(svc, 99), 3)},
            "closed_loop_genomes_per_s": round(capacity, 2), "offered_rate_per_s": round(lam, 2),
            "gene_pairs_per_s": round(gp / wall, 1), "retries": int(stats.retries),
+           "join_two_passes": sum(1 for d in done.values() if d.flags & pdp.PDP_STATUS_TWO_PASS),
            "peak_inflight": int(stats.peak_inflight), "peak_used_gb": round(stats.peak_used_bytes / 2 ** 30, 2),
            "host_generation_s": round(gen_s, 1),
            "note": "latency includes the host-to-device copy of each arriving genome"}

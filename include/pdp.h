@@ -421,7 +421,7 @@ typedef struct pdp_request_done {
     int32_t code;        /* PDP_OK, or the request's error (PDP_E_BUDGET: never fits the budget) */
     uint32_t n_genes;
     uint32_t attempts;   /* runs, more than 1 after a capacity error grew its buffers */
-    uint32_t reserved;
+    uint32_t flags;      /* pdp_status.flags of its last run (PDP_STATUS_TWO_PASS) */
     double submit_us, admit_us, done_us;
     uint64_t bh_entries, bbh_pairs;
 } pdp_request_done;

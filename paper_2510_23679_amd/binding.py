@@ -101,7 +101,7 @@ class pdp_server_config(C.Structure):
 
 
 class pdp_request_done(C.Structure):
-    _fields_ = [("tag", u64), ("code", i32), ("n_genes", u32), ("attempts", u32), ("reserved", u32),
+    _fields_ = [("tag", u64), ("code", i32), ("n_genes", u32), ("attempts", u32), ("flags", u32),
                 ("submit_us", C.c_double), ("admit_us", C.c_double), ("done_us", C.c_double),
                 ("bh_entries", u64), ("bbh_pairs", u64)]
 

@@ -487,6 +487,7 @@ int32_t pdp_server_poll(pdp_server *S, pdp_request_done *done, uint32_t max, uin
         d.code = r->code;
         d.n_genes = r->n_genes;
         d.attempts = r->attempts;
+        d.flags = r->hstatus.flags;
         d.submit_us = r->t_submit;
         d.admit_us = r->t_admit;
         d.done_us = r->t_done;
