@@ -147,3 +147,37 @@ def test_one_pass_unpacked_codes():
     r.run()
     assert pdp.status_flags(r.status) == 0
     _compare(gens, k, r.results())
+
+
+def test_graph_replays_refit_after_fallback():
+    # a plan whose regions overflow, captured in a HIP graph after a fresh upload of its tables:
+    # the first replay falls back to two passes and refits the regions, the later replays fit in
+    # one pass; eager work between the replays, every replay equal to the eager result
+    ds = make_config(2, genomes=3, genes=300)
+    k = 5
+    needed = _needed_records(ds.genomes, k, False)
+    say("graph replays around a region refit, capacity", needed)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        dicts, r = _runner(ds.genomes, k, pdp.params(inc_capacity=needed))
+        r.run(stream)
+        eager = r.results()
+        r.plan.upload(r.ws, stream)  # back to the estimated regions
+        graph = pdp.Graph.capture(stream)
+        with graph:
+            r.launch(stream)
+        for rep in range(4):
+            r.bh.col.fill_(-1)
+            r.bbh.a.fill_(-1)
+            scratch = torch.randn(1 << 20, device="cuda", dtype=torch.float32).sum()
+            stream.synchronize()
+            graph.launch(stream)
+            stream.synchronize()
+            assert pdp.read_status(r.status)[0] == 0
+            flags = pdp.status_flags(r.status)
+            assert bool(flags & pdp.PDP_STATUS_TWO_PASS) == (rep == 0), f"replay {rep}: flags {flags}"
+            again = r.results()
+            for x, y in zip(eager.bh + eager.bbh, again.bh + again.bbh):
+                assert np.array_equal(x, y), f"replay {rep}"
+            del scratch
+    _compare(ds.genomes, k, eager)
