@@ -484,9 +484,11 @@ struct JoinLdsFused {
 // followed in dynamic LDS by two words per tile of the task: the batch's record count and
 // the write cursor
 
-// A batch of query entries: packed key (or 64-bit code), gene and multiplicity.
+// A batch of query entries: packed key or 64-bit code (one of the two arrays is used), gene
+// and multiplicity.
 struct FusedBatch {
     uint64_t code[kFuseUnroll];
+    uint32_t key[kFuseUnroll];
     uint32_t ag[kFuseUnroll], an[kFuseUnroll];
 };
 
@@ -497,7 +499,7 @@ __device__ __forceinline__ void fused_load(const DevDict &A, uint32_t base, uint
         const uint32_t i = base + q * kJoinThreads + threadIdx.x;
         const bool v = i < a1;
         if constexpr (PACKED) {
-            r.code[q] = v ? A.ix_key[i] : 0u;
+            r.key[q] = v ? A.ix_key[i] : 0u;
             r.ag[q] = 0u;
         } else {
             r.code[q] = v ? A.ix_code[i] : ~0ull;
@@ -533,18 +535,18 @@ __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, boo
         if (!loaded || base != a0) fused_load<PACKED>(T.a, base, a1, r);
         uint32_t p[U], m[U];
         // search: the first target entry of the query's k-mer inside its bucket, and the run length
+        // (packed keys compare their 32-bit tails, codes their 64 bits)
 #pragma unroll
         for (uint32_t q = 0; q < U; ++q) {
             const uint32_t i = base + q * kJoinThreads + threadIdx.x;
             p[q] = 0;
             m[q] = 0;
             if (i >= a1) continue;
-            uint32_t u;
-            uint64_t want;
             if constexpr (PACKED) {
-                const uint32_t key = static_cast<uint32_t>(r.code[q]);
+                const uint32_t key = r.key[q];
                 r.ag[q] = key & mska;
-                want = key >> sha;
+                const uint32_t want = key >> sha;
+                uint32_t u;
                 if (abk) {
                     u = abk[i - a0];
                 } else {  // the last directory slot in [jlo, jhi) with adir <= i
@@ -556,22 +558,32 @@ __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, boo
                     }
                     u = lo;
                 }
+                const uint32_t end = min(bdir[u + 1] - b0, nbe);
+                uint32_t lo = min(bdir[u] - b0, end), hi = end;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if ((bk[mid] >> shb) < want) lo = mid + 1;
+                    else hi = mid;
+                }
+                uint32_t n = 0;
+                while (lo + n < end && (bk[lo + n] >> shb) == want) ++n;
+                p[q] = lo;
+                m[q] = n;
             } else {
-                want = r.code[q];
-                u = bucket_of(want, T.a.k, T.a.lead, T.a.bits) - bl;
+                const uint64_t want = r.code[q];
+                const uint32_t u = bucket_of(want, T.a.k, T.a.lead, T.a.bits) - bl;
+                const uint32_t end = min(bdir[u + 1] - b0, nbe);
+                uint32_t lo = min(bdir[u] - b0, end), hi = end;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (bc[mid] < want) lo = mid + 1;
+                    else hi = mid;
+                }
+                uint32_t n = 0;
+                while (lo + n < end && bc[lo + n] == want) ++n;
+                p[q] = lo;
+                m[q] = n;
             }
-            const uint32_t end = min(bdir[u + 1] - b0, nbe);
-            uint32_t lo = min(bdir[u] - b0, end), hi = end;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                const uint64_t v = PACKED ? static_cast<uint64_t>(bk[mid] >> shb) : bc[mid];
-                if (v < want) lo = mid + 1;
-                else hi = mid;
-            }
-            uint32_t n = 0;
-            while (lo + n < end && (PACKED ? static_cast<uint64_t>(bk[lo + n] >> shb) : bc[lo + n]) == want) ++n;
-            p[q] = lo;
-            m[q] = n;
         }
         // count the batch's records per tile
 #pragma unroll
@@ -598,7 +610,8 @@ __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, boo
             if (threadIdx.x == 0) atomicOr(fallback, 1u);
             return false;
         }
-        // write the records into the runs
+        // write the records into the runs: every reservation of the batch fitted its region, so
+        // each record lands inside its tile's region, and the regions lie inside the capacity
 #pragma unroll
         for (uint32_t q = 0; q < U; ++q) {
             if (!m[q]) continue;
@@ -607,15 +620,13 @@ __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, boo
                 const uint32_t o = atomicAdd(&tcur[a >> s0], m[q]);
                 const uint32_t rl = (a & ((1u << s0) - 1u)) << 24;
                 for (uint32_t t = 0; t < m[q]; ++t)
-                    if (o + t < rec_cap)
-                        recs[o + t] = make_uint2(rl | gene_at(p[q] + t), na | (static_cast<uint32_t>(bn[p[q] + t]) << 16));
+                    recs[o + t] = make_uint2(rl | gene_at(p[q] + t), na | (static_cast<uint32_t>(bn[p[q] + t]) << 16));
             }
             if (ba) {
                 for (uint32_t t = 0; t < m[q]; ++t) {
                     const uint32_t g = gene_at(p[q] + t);
                     const uint32_t o = atomicAdd(&tcur[t1 + (g >> s1)], 1u);
-                    if (o < rec_cap)
-                        recs[o] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | a, static_cast<uint32_t>(bn[p[q] + t]) | (na << 16));
+                    recs[o] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | a, static_cast<uint32_t>(bn[p[q] + t]) | (na << 16));
                 }
             }
         }
