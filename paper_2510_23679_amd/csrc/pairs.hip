@@ -634,6 +634,28 @@ __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, boo
     return true;
 }
 
+// Target entries [b0, b0 + nbe) of a packed dictionary into LDS (keys, 16-bit counts), in
+// ITERS rounds of the work-group with every load issued before the first store.
+template <uint32_t ITERS>
+__device__ __forceinline__ void stage_packed(const DevDict &B, uint32_t b0, uint32_t nbe, uint32_t *bkey,
+                                             uint16_t *bcnt) {
+    uint32_t kv[ITERS], cv[ITERS];
+#pragma unroll
+    for (uint32_t it = 0; it < ITERS; ++it) {
+        const uint32_t i = threadIdx.x + it * kJoinThreads;
+        kv[it] = i < nbe ? B.ix_key[b0 + i] : 0u;
+        cv[it] = i < nbe ? B.ix_cnt[b0 + i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t it = 0; it < ITERS; ++it) {
+        const uint32_t i = threadIdx.x + it * kJoinThreads;
+        if (i < nbe) {
+            bkey[i] = kv[it];
+            bcnt[i] = static_cast<uint16_t>(cv[it]);
+        }
+    }
+}
+
 // One item of the one-pass join (the same bucket ranges and sub-ranges as the two-pass
 // join).  Ends with a barrier so the LDS can take the next item.
 __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__restrict__ tasks,
@@ -691,24 +713,11 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
             if (nbe <= kJoinLdsCapP) {
                 uint16_t *abk = a1 - a0 <= kJoinLdsCapP ? reinterpret_cast<uint16_t *>(L.bgene) : nullptr;
                 fused_load<true>(T.a, a0, a1, r);  // in flight while the target side is staged
-                {
-                    constexpr uint32_t kIters = kJoinLdsCapP / kJoinThreads;
-                    uint32_t kv[kIters], cv[kIters];
-#pragma unroll
-                    for (uint32_t it = 0; it < kIters; ++it) {
-                        const uint32_t i = threadIdx.x + it * kJoinThreads;
-                        kv[it] = i < nbe ? T.b.ix_key[b0 + i] : 0u;
-                        cv[it] = i < nbe ? T.b.ix_cnt[b0 + i] : 0u;
-                    }
-#pragma unroll
-                    for (uint32_t it = 0; it < kIters; ++it) {
-                        const uint32_t i = threadIdx.x + it * kJoinThreads;
-                        if (i < nbe) {
-                            bkey[i] = kv[it];
-                            L.bcnt[i] = static_cast<uint16_t>(cv[it]);
-                        }
-                    }
-                }
+                // a typical sub-range stages at most half the stage: half the unrolled iterations
+                if (nbe <= kJoinLdsCapP / 2)
+                    stage_packed<kJoinLdsCapP / 2 / kJoinThreads>(T.b, b0, nbe, bkey, L.bcnt);
+                else
+                    stage_packed<kJoinLdsCapP / kJoinThreads>(T.b, b0, nbe, bkey, L.bcnt);
                 if (abk)
                     for (uint32_t u = s0 - bl + threadIdx.x; u < s1 - bl; u += kJoinThreads)
                         for (uint32_t i = L.adir[u]; i < L.adir[u + 1]; ++i) abk[i - a0] = static_cast<uint16_t>(u);
