@@ -309,7 +309,10 @@ int32_t pdp_plan_upload(const pdp_plan *plan, void *ws, uint64_t ws_bytes, void 
  * be captured in a HIP graph.  bh must cover info.bh_rows rows, bbh
  * info.bbh_rows rows (bbh may be NULL if no task asks for BBH).  status is
  * device memory.  Device errors: PDP_E_CAPACITY (needed = required
- * records, best-hit entries or BBH pairs; retry with more).
+ * records, best-hit entries or BBH pairs; retry with more).  status.flags
+ * reports PDP_STATUS_TWO_PASS when the join's record regions overflowed and
+ * the two-pass join ran; the launch then also refits the regions held in ws
+ * (see PDP_PARAM_TWO_PASS), so a launch writes the plan's tile table in ws.
  * Errors: PDP_E_INVAL, PDP_E_WORKSPACE, PDP_E_HIP. */
 int32_t pdp_plan_launch(const pdp_plan *plan, pdp_bh_out *bh, pdp_bbh_out *bbh, pdp_status *status,
                         void *ws, uint64_t ws_bytes, void *stream);

@@ -4,20 +4,20 @@
 // gene pair, m = sum over shared k-mers of min(mult_a, mult_b); the sum of
 // maxima over the union is then n_a + n_b - m (max + min = x + y per k-mer).
 // The path never forms the |A| x |B| matrix, in HBM or in LDS:
-//  1. k_join (count pass): both genomes' inverted indexes are sorted by code
-//     and split into the same leading-letter bucket ranges.  A work-group
-//     takes one range ("item"), stages the target side in LDS, finds the
-//     partners of every query entry through the bucket directory, and counts
-//     the records each accumulation tile (2^s rows of one direction) will get
-//     from this item; it stores the counts (item-major) and adds them to the
-//     tiles' totals, one atomic per tile it feeds.
-//  2. An exclusive scan of the tile totals gives every tile its record range.
-//  3. k_join (write pass) repeats the join: the item takes a run of each
-//     tile's range with one atomic on the tile's remaining count, and writes,
-//     per shared (k-mer, gene a, gene b), a record (row in tile, column, both
-//     counts) for each requested direction into its run, positions from LDS
-//     cursors.  Runs of different items land in a tile in any order; the tile
-//     pass does not depend on the order of its records.
+//  1. k_join_fused: both genomes' inverted indexes are sorted by code and split into the
+//     same leading-letter bucket ranges.  A work-group takes one range ("item"), stages
+//     the target side in LDS and finds the partners of every query entry through the
+//     bucket directory.  Per batch of query entries it counts the records each
+//     accumulation tile (2^s rows of one direction) gets, reserves a run of each tile's
+//     region (sized by the plan) with one atomic, and writes, per shared (k-mer, gene a,
+//     gene b), a record (row in tile, column, both counts) for each requested direction.
+//     Runs land in a tile's region in any order; the tile pass does not depend on it.
+//  2. Back-up, gated on an overflow flag: a reservation past its region's end stops the
+//     one-pass join; then k_join (count pass) counts per (item, tile), a scan of the tile
+//     totals gives every tile its exact range, k_join (write pass) writes the records
+//     there, and the regions are refitted to those counts for the next launch.  With no
+//     overflow these kernels exit at once.  PDP_PARAM_TWO_PASS runs the two passes alone.
+//  3. k_tile_ranges: each tile's record range for the tile pass.
 //  4. k_tile_count: one work-group per tile sums the tile's records into m per
 //     (row, column) in an LDS hash table, finds each row's maximum of
 //     J = m/d by exact cross-multiplication, and counts the columns that reach
