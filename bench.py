@@ -54,8 +54,9 @@ def parse():
     p.add_argument("--alphabet", choices=("aa", "nt"), default="aa",
                    help="allpairs: amino-acid genomes (default) or nucleotide genomes (genes 3x as long, k by the "
                         "rule with |alphabet| = 4)")
-    p.add_argument("--workload", choices=("allpairs", "batched", "serving"), default="allpairs",
-                   help="allpairs: the 10 x 3000 metric (default); batched: independent instances in waves, one "
+    p.add_argument("--workload", choices=("allpairs", "large", "batched", "serving"), default="allpairs",
+                   help="allpairs: the 10 x 3000 metric (default); large: 50 genomes x U{3000..5000} genes with "
+                        "paralog copies, all 1225 pairs in one launch; batched: independent instances in waves, one "
                         "graph-captured launch per wave, against one plan per genome pair; serving: "
                         "resident dictionaries and a Poisson stream of arriving genomes")
     p.add_argument("--instances", type=int, default=64, help="batched: instances (of the 400-instance workload)")
@@ -367,7 +368,7 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
-    if args.workload != "allpairs" and args.gpus == 1:
+    if args.workload not in ("allpairs", "large") and args.gpus == 1:
         (run_batched if args.workload == "batched" else run_serving)(args)
         return
     if args.gpus != 1:
@@ -385,7 +386,8 @@ def main():
 
     torch.cuda.set_device(0)
     nt = args.alphabet == "nt"
-    ds = make_config(2, alphabet=args.alphabet)
+    large = args.workload == "large"
+    ds = make_config(3 if large else 2, alphabet=args.alphabet)
     k = pdp.k_rule(ds.total_residues(), 4 if nt else 20)
     pairs = ds.pairs()
     gene_pairs = ds.gene_pairs()
@@ -510,10 +512,13 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "all-pairs BH+BBH: 10 genomes x 3000 genes (family model"
-                               + (", nucleotide genes" if nt else "") + "), 45 genome pairs, dictionary build included",
+        "config": {"workload": ("all-pairs BH+BBH: 50 genomes x U{3000..5000} genes (family model with 5% paralog "
+                                "copies" if large else "all-pairs BH+BBH: 10 genomes x 3000 genes (family model")
+                               + (", nucleotide genes" if nt else "")
+                               + f"), {len(pairs)} genome pairs, dictionary build included",
                    "alphabet": "nucleotide" if nt else "amino acid",
-                   "genomes": len(genes), "genes_per_genome": genes[0], "k": k, "genome_pairs": len(pairs),
+                   "genomes": len(genes), "genes_per_genome": genes[0] if not large else [min(genes), max(genes)],
+                   "k": k, "genome_pairs": len(pairs),
                    "gene_pairs": gene_pairs, "kmer_entries": int(sum(entries)), "best_hits": bh_nnz, "bbh_pairs": bbh_n,
                    "filters": {"theta": args.theta, "tau": args.tau}, "column_maxima": bool(args.colmax)},
         "roofline": roofline,
@@ -522,7 +527,7 @@ def main():
         "breakdown": breakdown,
     }
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(ds, k, args.cpu_rows or (128 if nt else 384))
+        cb = cpu_baseline(ds, k, args.cpu_rows or (16 if large else (128 if nt else 384)))
         cb["gpu_over_cpu"] = round(value / cb["value"], 1)
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)

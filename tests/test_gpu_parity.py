@@ -350,6 +350,38 @@ def test_full_size_family_model_sampled():
             check_bh(ba, oracle.bh(og[j], og[i], rows=cols), rows=cols)
 
 
+def test_full_size_large_workload_sampled():
+    """All 1225 pairs of the 50 x U{3000..5000}-gene workload with paralog copies (exact and
+    near ties) in one launch, k = 7 by the rule; every 25th pair against the oracle on sampled
+    rows (first and last rows included) and against the any-size properties."""
+    ds = make_config(3)
+    k = pdp.k_rule(ds.total_residues())
+    assert k == 7
+    say("full-size 50-genome workload, k =", k, "pairs", len(ds.pairs()))
+    dicts = pdp.DictionaryBatch([pdp.DeviceGenome.of(g) for g in ds.genomes], k)
+    dicts.build()
+    dicts.check_status()
+    runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts.dicts))
+    runner.run()
+    res = runner.results()
+    picked = list(range(0, len(ds.pairs()), 25))
+    used = sorted({x for t in picked for x in ds.pairs()[t]})
+    og = {i: oracle.OracleGenome(ds.genomes[i], k) for i in used}
+    rng = np.random.default_rng(11)
+    ties = 0
+    for t in picked:
+        i, j = ds.pairs()[t]
+        ab, ba, bb = res.best_hits(t, 0), res.best_hits(t, 1), res.bbh_pairs(t)
+        check_bh_properties(ab, ba, bb, ds.genomes[i].n_genes, ds.genomes[j].n_genes)
+        ties += int(np.sum(np.diff(ab[0].astype(np.int64)) > 1))
+        rows = np.sort(rng.choice(ds.genomes[i].n_genes, 16, replace=False))
+        rows = np.concatenate([[0], rows, [ds.genomes[i].n_genes - 1]])
+        check_bh(ab, oracle.bh(og[i], og[j], rows=rows), rows=rows)
+        cols = np.sort(rng.choice(ds.genomes[j].n_genes, 16, replace=False))
+        check_bh(ba, oracle.bh(og[j], og[i], rows=cols), rows=cols)
+    assert ties > 0, "the paralog copies should give tied best hits"
+
+
 def test_build_many_mixed_k_and_empty_genomes():
     say("pdp_dict_build_many: 5 genomes, mixed k, an empty genome")
     ds = make_config(2, genomes=3, genes=200)
