@@ -582,7 +582,7 @@ __global__ __launch_bounds__(256) void k_ix_hist(const DevBuild *__restrict__ ta
         if (h[i]) atomicAdd(&bintot[B.bin_base + i], h[i]);
 }
 
-constexpr uint32_t kIxPlaceThreads = 512;  // a placement work-group: its block of entries in registers
+constexpr uint32_t kIxPlaceThreads = 1024;  // a placement work-group: its block of entries in registers, 16 per thread
 constexpr uint32_t kIxPerThread = kIxBlock / kIxPlaceThreads;  // entries a placement thread keeps
 static_assert(kIxPerThread % kIxBatch == 0, "placement rounds divide the entries of a thread");
 
