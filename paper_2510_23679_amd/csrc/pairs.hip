@@ -520,7 +520,7 @@ __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, boo
                                             const uint32_t *bk, const uint32_t *bg, const CN *bn, const uint32_t *bdir,
                                             uint32_t *tcount, uint32_t *tcur, uint32_t *drop,
                                             uint32_t *__restrict__ fill, const DevTile *__restrict__ tiles,
-                                            uint32_t *__restrict__ fallback, uint2 *__restrict__ recs, uint64_t rec_cap) {
+                                            uint32_t *__restrict__ fallback, uint2 *__restrict__ recs) {
     constexpr uint32_t U = kFuseUnroll;
     const bool ab = T.flags & 1u, ba = T.flags & 2u;
     const uint32_t s0 = T.tile_shift[0], s1 = T.tile_shift[1], t1 = T.tiles_n[0];
@@ -661,7 +661,7 @@ __device__ __forceinline__ void stage_packed(const DevDict &B, uint32_t b0, uint
 __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__restrict__ tasks,
                                             const DevItem *__restrict__ items, uint32_t *__restrict__ fill,
                                             const DevTile *__restrict__ tiles, uint32_t *__restrict__ fallback,
-                                            uint2 *__restrict__ recs, uint64_t rec_cap, JoinLdsFused &L,
+                                            uint2 *__restrict__ recs, JoinLdsFused &L,
                                             uint32_t *tcount, uint32_t *tcur, uint32_t join_tiles) {
     // set-up in one round of loads: the item (same address for every thread), then the task's
     // words and both directory slices together
@@ -723,13 +723,12 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
                         for (uint32_t i = L.adir[u]; i < L.adir[u + 1]; ++i) abk[i - a0] = static_cast<uint16_t>(u);
                 __syncthreads();
                 ok = fused_range<true>(T, r, true, a0, a1, abk, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, nullptr, bkey,
-                                       nullptr, L.bcnt, L.bdir, tcount, tcur, &L.drop, fill, tiles, fallback, recs,
-                                       rec_cap);
+                                       nullptr, L.bcnt, L.bdir, tcount, tcur, &L.drop, fill, tiles, fallback, recs);
                 __syncthreads();  // the staged arrays take the next sub-range
             } else {
                 ok = fused_range<true>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, nullptr,
                                        T.b.ix_key + b0, nullptr, T.b.ix_cnt + b0, L.bdir, tcount, tcur, &L.drop, fill,
-                                       tiles, fallback, recs, rec_cap);
+                                       tiles, fallback, recs);
             }
         } else if (nbe <= kJoinLdsCap) {
             for (uint32_t i = threadIdx.x; i < nbe; i += kJoinThreads) {
@@ -740,12 +739,12 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
             __syncthreads();
             ok = fused_range<false>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, L.bcode,
                                     nullptr, L.bgene, L.bcnt, L.bdir, tcount, tcur, &L.drop, fill, tiles, fallback,
-                                    recs, rec_cap);
+                                    recs);
             __syncthreads();
         } else {
             ok = fused_range<false>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe,
                                     T.b.ix_code + b0, nullptr, T.b.ix_gene + b0, T.b.ix_cnt + b0, L.bdir, tcount, tcur,
-                                    &L.drop, fill, tiles, fallback, recs, rec_cap);
+                                    &L.drop, fill, tiles, fallback, recs);
         }
         if (!ok) break;  // uniform: every thread read the same drop flag after a barrier
     }
@@ -757,18 +756,18 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_fused(const DevTask *__re
                                                              uint32_t *__restrict__ fill,
                                                              const DevTile *__restrict__ tiles,
                                                              uint32_t *__restrict__ fallback,
-                                                             uint2 *__restrict__ recs, uint64_t rec_cap,
+                                                             uint2 *__restrict__ recs,
                                                              uint32_t join_tiles) {
     __shared__ JoinLdsFused L;
     extern __shared__ uint32_t join_dyn[];
-    fused_chunk(blockIdx.x, tasks, items, fill, tiles, fallback, recs, rec_cap, L, join_dyn, join_dyn + join_tiles,
+    fused_chunk(blockIdx.x, tasks, items, fill, tiles, fallback, recs, L, join_dyn, join_dyn + join_tiles,
                 join_tiles);
 }
 
 __global__ __launch_bounds__(kJoinThreads) void k_join_fused_persistent(
     const DevTask *__restrict__ tasks, const DevItem *__restrict__ items, uint32_t total_chunks,
     uint32_t *__restrict__ fill, const DevTile *__restrict__ tiles, uint32_t *__restrict__ fallback,
-    uint2 *__restrict__ recs, uint64_t rec_cap, uint32_t join_tiles, uint32_t *__restrict__ next) {
+    uint2 *__restrict__ recs, uint32_t join_tiles, uint32_t *__restrict__ next) {
     __shared__ JoinLdsFused L;
     extern __shared__ uint32_t join_dyn[];
     for (;;) {
@@ -779,7 +778,7 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_fused_persistent(
         if (first >= total_chunks) break;
         const uint32_t last = min(total_chunks, first + kClaimJoin);
         for (uint32_t chunk = first; chunk < last; ++chunk)
-            fused_chunk(chunk, tasks, items, fill, tiles, fallback, recs, rec_cap, L, join_dyn, join_dyn + join_tiles,
+            fused_chunk(chunk, tasks, items, fill, tiles, fallback, recs, L, join_dyn, join_dyn + join_tiles,
                         join_tiles);
     }
 }
@@ -1765,10 +1764,10 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
                 hipLaunchKernelGGL(k_join_fused_persistent,
                                    dim3(std::min(p.join_grid, (p.total_chunks + kClaimJoin - 1) / kClaimJoin)),
                                    dim3(kJoinThreads), dyn, s, w.tasks, w.items, p.total_chunks, w.fill, w.tiles,
-                                   w.fallback, w.recs, p.rec_cap, p.join_tiles, w.next_fused);
+                                   w.fallback, w.recs, p.join_tiles, w.next_fused);
             else
                 hipLaunchKernelGGL(k_join_fused, dim3(p.total_chunks), dim3(kJoinThreads), dyn, s, w.tasks, w.items,
-                                   w.fill, w.tiles, w.fallback, w.recs, p.rec_cap, p.join_tiles);
+                                   w.fill, w.tiles, w.fallback, w.recs, p.join_tiles);
             PDP_TRY(hipGetLastError());
             PDP_TRY(mark(PDP_KERNEL_JOIN, false));
             PDP_TRY(mark(PDP_KERNEL_JOIN_BACKUP, true));
