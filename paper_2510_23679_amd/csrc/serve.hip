@@ -116,10 +116,15 @@ struct ServeRequest {
     pdp_bh_out bh{};
     pdp_bbh_out bbh{};
     pdp_status *status = nullptr;
-    // results, host
+    // results, host: the arrays stay in the pinned buffer they were copied to (one of the
+    // server's pool, held until the request is released)
     pdp_status hstatus{};
+    std::unique_ptr<Pinned> out;
     std::vector<uint32_t> ab_row, ba_row, bbh_row;
-    std::vector<uint32_t> bh_ptr, bh_col, bh_num, bh_den, bbh_ptr, bbh_a, bbh_b, bbh_num, bbh_den;
+    uint32_t bh_rows = 0, bbh_rows = 0;
+    uint64_t nbh = 0, nbb = 0;
+    const uint32_t *bh_ptr = nullptr, *bh_col = nullptr, *bh_num = nullptr, *bh_den = nullptr;
+    const uint32_t *bbh_ptr = nullptr, *bbh_a = nullptr, *bbh_b = nullptr, *bbh_num = nullptr, *bbh_den = nullptr;
 };
 
 struct ServeSlot {
@@ -139,6 +144,7 @@ struct pdp_server {
     std::deque<ServeRequest *> pending;
     std::unordered_map<uint64_t, std::unique_ptr<ServeRequest>> all;
     std::deque<uint64_t> finished;  // tags, completion order, not yet polled
+    std::vector<std::unique_ptr<Pinned>> pins;  // pinned result buffers not held by a request
     std::mutex mu;
     std::condition_variable cv;
     std::thread worker;
@@ -150,6 +156,27 @@ struct pdp_server {
 };
 
 namespace {
+
+// A pinned buffer of at least n bytes from the pool (the smallest that fits, else one grown).
+std::unique_ptr<Pinned> take_pin(pdp_server *S, uint64_t n) {
+    size_t best = S->pins.size();
+    for (size_t i = 0; i < S->pins.size(); ++i)
+        if (S->pins[i]->bytes >= n && (best == S->pins.size() || S->pins[i]->bytes < S->pins[best]->bytes)) best = i;
+    if (best == S->pins.size() && !S->pins.empty()) best = 0;  // grow one
+    std::unique_ptr<Pinned> p;
+    if (best < S->pins.size()) {
+        p = std::move(S->pins[best]);
+        S->pins.erase(S->pins.begin() + static_cast<std::ptrdiff_t>(best));
+    } else {
+        p = std::make_unique<Pinned>();
+    }
+    if (!p->ensure(n)) return nullptr;
+    return p;
+}
+
+void give_pin(pdp_server *S, std::unique_ptr<Pinned> &p) {
+    if (p) S->pins.push_back(std::move(p));
+}
 
 uint64_t footprint(pdp_server *S, ServeRequest *r, uint64_t *plan_ws) {
     uint64_t arena = 0, bws = 0;
@@ -221,7 +248,10 @@ int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t
     const uint64_t in_bytes = r->n_res + 8 * (uint64_t(r->n_genes) + 1);
     const uint64_t out_bytes = sizeof(pdp_status) + 4 * (uint64_t(info.bh_rows) + 1 + 3 * r->bh_cap) +
                                4 * (uint64_t(info.bbh_rows) + 1 + 4 * r->bbh_cap);
-    if (!slot.pin.ensure(std::max(in_bytes, out_bytes) + 64)) return PDP_E_HIP;
+    if (!slot.pin.ensure(in_bytes + 64)) return PDP_E_HIP;
+    give_pin(S, r->out);  // a retried request gives back its earlier buffer
+    r->out = take_pin(S, out_bytes + 64);
+    if (!r->out) return PDP_E_HIP;
     std::memcpy(slot.pin.p, r->res.data(), r->n_res);
     std::memcpy(static_cast<char *>(slot.pin.p) + r->n_res, r->off.data(), 8 * (uint64_t(r->n_genes) + 1));
     if (hipMemcpyAsync(res, slot.pin.p, r->n_res, hipMemcpyHostToDevice, s) != hipSuccess) return PDP_E_HIP;
@@ -235,8 +265,8 @@ int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t
     if (rc) return rc;
     rc = pdp_plan_launch(r->plan, &r->bh, &r->bbh, r->status, scratch, scratch_bytes, s);
     if (rc) return rc;
-    // results back; the pinned buffer is reused for output once the input copies are ordered before
-    char *h = static_cast<char *>(slot.pin.p);
+    // results back to the request's own pinned buffer
+    char *h = static_cast<char *>(r->out->p);
     auto d2h = [&](const void *src, uint64_t bytes) {
         if (hipMemcpyAsync(h, src, bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
         h += bytes;
@@ -253,10 +283,10 @@ int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t
 }
 
 // Unpacks the pinned results of a finished slot; true if the request is done (else it is retried).
-bool collect(pdp_server *S, ServeSlot &slot, ServeRequest *r) {
+bool collect(pdp_server *S, ServeSlot &, ServeRequest *r) {
     pdp_plan_info info;
     pdp_plan_info_get(r->plan, &info);
-    const char *h = static_cast<const char *>(slot.pin.p);
+    const char *h = static_cast<const char *>(r->out->p);
     pdp_status st, dst;
     std::memcpy(&st, h, sizeof(st));
     h += sizeof(st);
@@ -274,26 +304,31 @@ bool collect(pdp_server *S, ServeSlot &slot, ServeRequest *r) {
         else if (st.where == 1) r->bh_cap = grow;
         else r->bbh_cap = grow;
         S->retries++;
+        give_pin(S, r->out);
         return false;
     }
     r->hstatus = st;
     r->code = st.code;
     if (st.code != PDP_OK) return true;
-    auto take = [&](std::vector<uint32_t> &v, uint64_t n, uint64_t stride) {
-        v.assign(reinterpret_cast<const uint32_t *>(h), reinterpret_cast<const uint32_t *>(h) + n);
+    // views of the arrays in the pinned buffer, laid out as the copies wrote them
+    auto view = [&](uint64_t stride) {
+        const uint32_t *v = reinterpret_cast<const uint32_t *>(h);
         h += 4 * stride;
+        return v;
     };
-    take(r->bh_ptr, uint64_t(info.bh_rows) + 1, uint64_t(info.bh_rows) + 1);
-    const uint64_t nbh = r->bh_ptr.back();
-    take(r->bh_col, nbh, r->bh_cap);
-    take(r->bh_num, nbh, r->bh_cap);
-    take(r->bh_den, nbh, r->bh_cap);
-    take(r->bbh_ptr, uint64_t(info.bbh_rows) + 1, uint64_t(info.bbh_rows) + 1);
-    const uint64_t nbb = r->bbh_ptr.back();
-    take(r->bbh_a, nbb, r->bbh_cap);
-    take(r->bbh_b, nbb, r->bbh_cap);
-    take(r->bbh_num, nbb, r->bbh_cap);
-    take(r->bbh_den, nbb, r->bbh_cap);
+    r->bh_rows = info.bh_rows;
+    r->bbh_rows = info.bbh_rows;
+    r->bh_ptr = view(uint64_t(info.bh_rows) + 1);
+    r->bh_col = view(r->bh_cap);
+    r->bh_num = view(r->bh_cap);
+    r->bh_den = view(r->bh_cap);
+    r->bbh_ptr = view(uint64_t(info.bbh_rows) + 1);
+    r->bbh_a = view(r->bbh_cap);
+    r->bbh_b = view(r->bbh_cap);
+    r->bbh_num = view(r->bbh_cap);
+    r->bbh_den = view(r->bbh_cap);
+    r->nbh = r->bh_ptr[info.bh_rows];
+    r->nbb = r->bbh_ptr[info.bbh_rows];
     const uint32_t nt = static_cast<uint32_t>(S->residents.size());
     r->ab_row.resize(nt);
     r->ba_row.resize(nt);
@@ -493,8 +528,8 @@ int32_t pdp_server_poll(pdp_server *S, pdp_request_done *done, uint32_t max, uin
         d.submit_us = r->t_submit;
         d.admit_us = r->t_admit;
         d.done_us = r->t_done;
-        d.bh_entries = r->bh_ptr.empty() ? 0 : r->bh_ptr.back();
-        d.bbh_pairs = r->bbh_ptr.empty() ? 0 : r->bbh_ptr.back();
+        d.bh_entries = r->code == PDP_OK ? r->nbh : 0;
+        d.bbh_pairs = r->code == PDP_OK ? r->nbb : 0;
     }
     *n_done = n;
     return S->fatal;
@@ -511,20 +546,20 @@ int32_t pdp_server_fetch(pdp_server *S, uint64_t tag, pdp_request_result *out) {
     out->status = r->hstatus;
     out->n_residents = static_cast<uint32_t>(S->residents.size());
     if (r->code != PDP_OK) return PDP_OK;
-    out->bh_rows = static_cast<uint32_t>(r->bh_ptr.size() - 1);
-    out->bbh_rows = static_cast<uint32_t>(r->bbh_ptr.size() - 1);
+    out->bh_rows = r->bh_rows;
+    out->bbh_rows = r->bbh_rows;
     out->ab_row = r->ab_row.data();
     out->ba_row = r->ba_row.data();
     out->bbh_row = r->bbh_row.data();
-    out->bh_ptr = r->bh_ptr.data();
-    out->bh_col = r->bh_col.data();
-    out->bh_num = r->bh_num.data();
-    out->bh_den = r->bh_den.data();
-    out->bbh_ptr = r->bbh_ptr.data();
-    out->bbh_a = r->bbh_a.data();
-    out->bbh_b = r->bbh_b.data();
-    out->bbh_num = r->bbh_num.data();
-    out->bbh_den = r->bbh_den.data();
+    out->bh_ptr = r->bh_ptr;
+    out->bh_col = r->bh_col;
+    out->bh_num = r->bh_num;
+    out->bh_den = r->bh_den;
+    out->bbh_ptr = r->bbh_ptr;
+    out->bbh_a = r->bbh_a;
+    out->bbh_b = r->bbh_b;
+    out->bbh_num = r->bbh_num;
+    out->bbh_den = r->bbh_den;
     return PDP_OK;
 }
 
@@ -533,6 +568,7 @@ int32_t pdp_server_release(pdp_server *S, uint64_t tag) {
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->all.find(tag);
     if (it == S->all.end() || it->second->t_done == 0) return api_fail(PDP_E_INVAL, "pdp_server_release: unknown or unfinished tag");
+    give_pin(S, it->second->out);  // its pinned result buffer goes back to the pool
     S->all.erase(it);
     return PDP_OK;
 }
