@@ -7,7 +7,9 @@
 // arena.  An admitted request runs, on its own stream: copy of its residues to
 // the device, dictionary build, one plan of |residents| tasks (best hits both
 // ways + BBH against every resident), and the copy of every result and the
-// status back to pinned host memory, closed by an event.  Requests admitted
+// status back to a pinned host buffer of the request's own (from a pool; the
+// results stay there, and fetch returns views, until the request is released),
+// closed by an event.  Requests admitted
 // while others run overlap with them on the device (continuous batching); a
 // finished slot and its memory go to the next waiting request at once.  Every
 // request's arithmetic depends only on its own inputs and the residents, so
