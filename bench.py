@@ -161,7 +161,8 @@ def _pctl(xs, q):
 
 def run_batched(args):
     """Workload 4 sample: independent instances, all pairs of each, in waves.  A wave is one
-    dictionary build of all its genomes (k per instance) plus one plan launch,
+    dictionary build of all its genomes (k per instance) plus one plan launch (tile height, join
+    sub-range size and persistence picked by the autotuner on the first wave),
     captured in a HIP graph; its replay is timed with events.  Instance latency = its wave's
     time (every instance of a wave finishes in the same launch).  The same pairs are also
     timed with one plan per genome pair (a sample), the launch pattern batching replaces."""
@@ -174,6 +175,7 @@ def run_batched(args):
     import torch
 
     import paper_2510_23679_amd as pdp
+    from paper_2510_23679_amd import binding as B
 
     torch.cuda.set_device(0)
     waves, cur, cur_g = [], [], 0
@@ -189,6 +191,7 @@ def run_batched(args):
     total_gp, total_ms, lat, wave_rows = 0, 0.0, [], []
     pp_gp, pp_ms = 0, 0.0
     rng = np.random.default_rng(4)
+    tuned = None
     for w, wave in enumerate(waves):
         with torch.cuda.stream(stream):
             devs, ks, spans = [], [], []
@@ -207,7 +210,23 @@ def run_batched(args):
                         tasks.append((batch.dicts[first + i], batch.dicts[first + j],
                                       pdp.PDP_TASK_AB | pdp.PDP_TASK_BA | pdp.PDP_TASK_BBH))
                         gp += devs[first + i].n_genes * devs[first + j].n_genes
-            runner = pdp.PairRunner(tasks, pdp.params(persistent=args.persistent))
+            if tuned is None and not args.persistent:
+                # the first wave picks tile height, join sub-range size and persistence for all waves:
+                # the autotuner times every combination at the capacity a sizing run found
+                sizing = pdp.PairRunner(tasks, pdp.params())
+                sizing.run(stream)
+                cap = int(sizing.plan.info.inc_capacity)
+                del sizing
+                cands = [pdp.params(inc_capacity=cap, tile_rows=tr, join_entries=je, persistent=pe)
+                         for tr in (32, 64, 128) for je in (256, 512, 1024) for pe in (False, True)]
+                best, tres = pdp.autotune(tasks, cands, reps=2, stream=stream)
+                tuned = {"tile_rows": int(best.tile_rows), "join_entries": int(best.join_entries),
+                         "persistent": bool(best.flags & B.PDP_PARAM_PERSISTENT), "candidates": int(tres.tried),
+                         "best_ms": round(tres.best_ms, 3), "first_ms": round(tres.first_ms, 3)}
+            prm = (pdp.params(persistent=True) if args.persistent else
+                   pdp.params(tile_rows=tuned["tile_rows"], join_entries=tuned["join_entries"],
+                              persistent=tuned["persistent"]))
+            runner = pdp.PairRunner(tasks, prm)
             runner.run(stream)
             batch.check_status()
             graph = pdp.Graph.capture(stream)
@@ -257,6 +276,7 @@ def run_batched(args):
                                   f"{args.wave_genomes} genomes", "instances": len(insts), "waves": len(waves),
                       "gene_pairs": total_gp},
            "ms_total": round(total_ms, 3),
+           "params": tuned if tuned is not None else {"persistent": True},
            "instance_latency_ms": {"p50": round(_pctl(lat, 50), 3), "p99": round(_pctl(lat, 99), 3)},
            "per_pair_launches": {"value": round(per_pair, 1), "pairs_timed": int(sum(min(args.per_pair_sample, w["pairs"])
                                                                                      for w in wave_rows)),
