@@ -468,6 +468,32 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     return ok();
 }
 
+}  // extern "C"
+
+namespace pdp {
+int32_t plan_rebind(pdp_plan *P, const pdp_dict *from, const pdp_dict *to) {
+    if (!P || !from || !to) return PDP_E_INVAL;
+    if (from->n_genes != to->n_genes || from->capacity != to->capacity || from->k != to->k ||
+        from->alphabet != to->alphabet || from->n_buckets != to->n_buckets || from->key_shift != to->key_shift ||
+        (from->ix_key == nullptr) != (to->ix_key == nullptr))
+        return PDP_E_INVAL;
+    const DevDict nd = dev_dict(to);
+    const uint32_t *lo = from->ix_dir, *hi = from->ix_dir + from->n_buckets + 1;
+    auto move = [&](const uint32_t *p) { return p >= lo && p < hi ? to->ix_dir + (p - lo) : p; };
+    for (DevTask &t : P->tasks) {
+        if (t.a.ix_dir == from->ix_dir) t.a = nd;
+        if (t.b.ix_dir == from->ix_dir) t.b = nd;
+    }
+    for (DevItem &it : P->items) {
+        it.adir = move(it.adir);
+        it.bdir = move(it.bdir);
+    }
+    return PDP_OK;
+}
+}  // namespace pdp
+
+extern "C" {
+
 int32_t pdp_plan_info_get(const pdp_plan *plan, pdp_plan_info *info) {
     if (!plan || !info) return fail(PDP_E_INVAL, "pdp_plan_info_get: null pointer");
     info->ws_bytes = plan->ws_bytes;

@@ -208,6 +208,10 @@ int32_t api_fail(int32_t code, const char *fmt, ...) __attribute__((format(print
 
 // Work-groups of the persistent kernels that fit the current device at once.
 uint32_t persistent_join_grid();
+// Moves a plan's pointers from dictionary `from` to dictionary `to`, bound with the same sizes
+// elsewhere (so a plan made before a dictionary's memory is placed serves it afterwards).
+// PDP_E_INVAL when the two differ in anything but their addresses.
+int32_t plan_rebind(pdp_plan *plan, const pdp_dict *from, const pdp_dict *to);
 uint32_t persistent_fused_grid(uint32_t join_tiles);
 uint32_t persistent_tile_grid(uint32_t tile_lds);
 hipError_t allow_tile_lds(uint32_t tile_lds);

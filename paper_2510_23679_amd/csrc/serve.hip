@@ -241,10 +241,12 @@ int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t
     r->bbh.num = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(r->bbh_cap, 1)));
     r->bbh.den = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(r->bbh_cap, 1)));
     r->status = reinterpret_cast<pdp_status *>(take(sizeof(pdp_status)));
-    // The dictionary descriptor must point at this allocation before the plan copies it.
+    // The dictionary now lives in this allocation: the admission plan, made with the
+    // descriptor bound to a placeholder address, moves its pointers here.
+    const pdp_dict placeholder = r->dict;
     int32_t rc = pdp_dict_bind(dict_mem, arena, r->n_genes, r->n_res, S->cfg.k, S->cfg.alphabet, &r->dict);
     if (rc) return rc;
-    rc = make_plan(S, r);
+    rc = r->plan ? plan_rebind(r->plan, &placeholder, &r->dict) : make_plan(S, r);
     if (rc) return rc;
     // host input -> pinned staging -> device; pinned output staging sized for the results
     const uint64_t in_bytes = r->n_res + 8 * (uint64_t(r->n_genes) + 1);
