@@ -47,6 +47,7 @@ def parse():
     p.add_argument("--two-pass", action="store_true", help="join in two passes (count, then write)")
     p.add_argument("--join-entries", type=int, default=0, help="index entries per join sub-range (0: default)")
     p.add_argument("--persistent", action="store_true", help="persistent join and tile kernels")
+    p.add_argument("--tile-rows", type=int, default=0, help="rows per accumulation tile (0: default; allpairs, serving)")
     p.add_argument("--colmax", action="store_true",
                    help="second genome's best hits from column maxima (Alg. 3): join records for one direction only")
     p.add_argument("--theta", default=None, help="length filter as NUM/DEN (Eq. length_threshold); off by default")
@@ -324,7 +325,8 @@ def run_serving(args):
     torch.cuda.synchronize()
     batch.check_status()
     res_genes = sum(d.n_genes for d in batch.dicts)
-    srv = pdp.Server(batch.dicts, int(args.budget_gb * (1 << 30)), slots=args.slots)
+    srv = pdp.Server(batch.dicts, int(args.budget_gb * (1 << 30)), slots=args.slots,
+                     prm=pdp.params(tile_rows=args.tile_rows))
 
     def drain(want, done):
         while len(done) < want:
@@ -425,7 +427,7 @@ def main():
         return tuple(int(v) for v in x.split("/")) if x else None
 
     prm = pdp.params(theta=frac(args.theta), tau=frac(args.tau), colmax=args.colmax, two_pass=args.two_pass,
-                     join_entries=args.join_entries, persistent=args.persistent)
+                     join_entries=args.join_entries, persistent=args.persistent, tile_rows=args.tile_rows)
     if args.tune:
         best, tres = pdp.autotune(tasks, reps=3, base=prm)
         prm = best
@@ -542,8 +544,9 @@ def main():
                    "gene_pairs": gene_pairs, "kmer_entries": int(sum(entries)), "best_hits": bh_nnz, "bbh_pairs": bbh_n,
                    "filters": {"theta": args.theta, "tau": args.tau}, "column_maxima": bool(args.colmax)},
         "roofline": roofline,
-        "params": tuned if tuned is not None else ("defaults" if not (args.join_entries or args.persistent) else
-                                                   {"join_entries": args.join_entries, "persistent": args.persistent}),
+        "params": tuned if tuned is not None else ("defaults" if not (args.join_entries or args.persistent or args.tile_rows)
+                                                   else {"join_entries": args.join_entries, "persistent": args.persistent,
+                                                         "tile_rows": args.tile_rows}),
         "breakdown": breakdown,
     }
     if not args.no_cpu_baseline:
