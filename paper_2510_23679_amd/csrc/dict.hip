@@ -89,6 +89,30 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The value of x in lane (this lane ^ lj), lj a power of two below kWave, without an LDS
+// round trip where the lane pattern allows: DPP moves for 1 and 2 (quad permutations) and 8
+// (rotation by 8 inside each row of 16 lanes), ds_swizzle in bit-mask mode (lanes of a half
+// wave, no address operand) for 4 and 16, ds_bpermute for 32.  Every lane of the wave must
+// be active.
+__device__ __forceinline__ uint32_t xor_lanes32(uint32_t x, uint32_t lj) {
+    const int v = static_cast<int>(x);
+    switch (lj) {
+        case 1: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false));
+        case 2: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false));
+        case 8: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false));
+        case 4: return static_cast<uint32_t>(__builtin_amdgcn_ds_swizzle(v, 0x101F));
+        case 16: return static_cast<uint32_t>(__builtin_amdgcn_ds_swizzle(v, 0x401F));
+        default: return __shfl_xor(x, lj, kWave);
+    }
+}
+// 32-bit keys only: with 64-bit keys, and in the work-group sort (whose distance is not a
+// compile-time constant), the variants raised register use enough to cost occupancy.
+template <typename K>
+__device__ __forceinline__ K xor_lanes(K x, uint32_t lj) {
+    if constexpr (sizeof(K) == 4) return xor_lanes32(x, lj);
+    else return __shfl_xor(x, lj, kWave);
+}
+
 // Ascending bitonic sort of kWave * E keys, E per lane in blocked order (lane l holds
 // elements l*E .. l*E+E-1): comparators inside a lane swap registers, the others pair
 // lanes by a shuffle and keep the minimum or maximum.
@@ -115,7 +139,7 @@ __device__ __forceinline__ void wave_bitonic_sort(K (&key)[E]) {
                 const bool lower = (l & lj) == 0;
 #pragma unroll
                 for (uint32_t e = 0; e < E; ++e) {
-                    const K o = __shfl_xor(key[e], lj, kWave);
+                    const K o = xor_lanes(key[e], lj);
                     const bool keep_min = lower == (((l * E + e) & size) == 0);
                     const K mn = o < key[e] ? o : key[e], mx = o < key[e] ? key[e] : o;
                     key[e] = keep_min ? mn : mx;
