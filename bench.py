@@ -394,8 +394,8 @@ def main():
         (run_batched if args.workload == "batched" else run_serving)(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the path shards genome pairs "
-                                   "across GPUs by design but no multi-GPU run is part of this build",
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; genome pairs are independent and "
+                                   "would shard across GPUs, but no multi-GPU path is implemented",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
