@@ -497,9 +497,9 @@ int32_t pdp_server_submit(pdp_server *S, const uint8_t *residues, const uint64_t
         resident_entries += d.capacity;
         resident_genes += d.n_genes;
     }
-    // records, both directions: about a fifth of the entries of every pair, so that the one-pass
+    // records, both directions: about a quarter of the entries of every pair, so that the one-pass
     // join's per-tile regions (the capacity split over the tiles) rarely overflow
-    r->inc_cap = (resident_entries + S->residents.size() * (r->n_res + 1)) / 5 + 65536;
+    r->inc_cap = (resident_entries + S->residents.size() * (r->n_res + 1)) / 4 + 65536;
     const uint64_t rows = uint64_t(n_genes) * S->residents.size() + resident_genes;
     r->bh_cap = rows + rows / 4 + 4096;
     r->bbh_cap = uint64_t(n_genes) * S->residents.size() * 3 / 4 + 4096;
