@@ -497,3 +497,232 @@ const uint32_t *orc_pairs_a(const orc_pairs *P) { return P->a; }
 const uint32_t *orc_pairs_b(const orc_pairs *P) { return P->b; }
 const uint64_t *orc_pairs_num(const orc_pairs *P) { return P->num; }
 const uint64_t *orc_pairs_den(const orc_pairs *P) { return P->den; }
+
+/* ===================================================== sparse exact oracle (O2)
+ *
+ * The same best hits as orc_bh_rows_f, computed without visiting gene pairs that share
+ * nothing, so that whole genome-scale workloads can be checked in full.  It is still
+ * plain: for the target genome a hash map sends each k-mer identifier to its postings
+ * (gene, multiplicity), in gene order; for a query gene a, every k-mer w of MV(a) adds
+ * min(mult_a(w), mult_b(w)) to the accumulator of each gene b posted under w (Eq.
+ * jaccard_k's sum of minima over D(a) and D(b) together).  A gene b never touched shares
+ * no k-mer with a, so J(a,b) = 0 and b is no best hit (the maximum must be above zero).
+ * For a touched b the sum of maxima over the union is n_a + n_b - m: per k-mer,
+ * max(x,y) = x + y - min(x,y), with x or y = 0 for a k-mer in one gene only, and the
+ * multiplicities of a gene sum to its window count.  The dense oracle computes that sum
+ * literally; the tests pin this one to it (and to brute force) on shared inputs.  The
+ * row maximum and its ties follow Eq. best_hit exactly as in orc_bh_row_f, with the same
+ * candidate filters (the directional sums of Eq. directional_jaccard accumulate beside the
+ * minima: occurrences in a and in b of every shared k-mer).
+ */
+
+/* One slot of the map: an identifier and the range of its postings; len 0 marks a free
+ * slot (every identifier present has at least one posting). */
+typedef struct {
+    uint64_t key;
+    uint32_t start, len;
+} orc_slot;
+
+typedef struct {
+    uint64_t mask;       /* slots - 1 (slots a power of two) */
+    orc_slot *slot;
+    uint32_t *gene;      /* postings */
+    uint32_t *cnt;
+} orc_index;
+
+static uint64_t orc_hash(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return x;
+}
+
+/* The slot holding id, or the free slot where it would go (linear probing). */
+static orc_slot *orc_index_slot(const orc_index *ix, uint64_t id) {
+    uint64_t s = orc_hash(id) & ix->mask;
+    while (ix->slot[s].len && ix->slot[s].key != id) s = (s + 1) & ix->mask;
+    return &ix->slot[s];
+}
+
+/* Map from identifier to postings over every gene of t (at most 2^32 - 1 entries). */
+orc_index *orc_index_new(const orc_genome *t) {
+    const uint64_t e = t->ptr[t->n];
+    if (e >= 0xffffffffull) return NULL;
+    uint64_t slots = 16;
+    while (slots < e + e / 2) slots <<= 1;  /* distinct identifiers <= e: load at most 2/3 */
+    orc_index *ix = (orc_index *)calloc(1, sizeof(orc_index));
+    ix->mask = slots - 1;
+    ix->slot = (orc_slot *)calloc((size_t)slots, sizeof(orc_slot));
+    ix->gene = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(e + 1));
+    ix->cnt = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(e + 1));
+    /* pass 1: postings per identifier */
+    for (uint64_t p = 0; p < e; ++p) {
+        orc_slot *s = orc_index_slot(ix, t->ids[p]);
+        s->key = t->ids[p];
+        s->len += 1;
+    }
+    uint32_t run = 0;
+    for (uint64_t s = 0; s < slots; ++s) { ix->slot[s].start = run; run += ix->slot[s].len; }
+    /* pass 2: fill, genes ascending inside each identifier (start advances, then is restored) */
+    for (uint32_t b = 0; b < t->n; ++b)
+        for (uint64_t p = t->ptr[b]; p < t->ptr[b + 1]; ++p) {
+            orc_slot *s = orc_index_slot(ix, t->ids[p]);
+            ix->gene[s->start] = b;
+            ix->cnt[s->start] = t->cnt[p];
+            s->start += 1;
+        }
+    for (uint64_t s = 0; s < slots; ++s) ix->slot[s].start -= ix->slot[s].len;
+    return ix;
+}
+
+void orc_index_free(orc_index *ix) {
+    if (!ix) return;
+    free(ix->slot); free(ix->gene); free(ix->cnt); free(ix);
+}
+
+/* Scratch of one worker: accumulators over the target's genes and the touched list. */
+typedef struct {
+    uint64_t *m, *oa, *ob;
+    uint32_t *touched;
+} orc_acc;
+
+static int cmp_u32(const void *a, const void *b) {
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Best hits of row a of q in t through t's index; same contract as orc_bh_row_f. */
+static int64_t orc_bh_row_sparse(const orc_genome *q, uint32_t a, const orc_genome *t, const orc_index *ix,
+                                 orc_acc *A, uint32_t *col, uint64_t *num, uint64_t *den,
+                                 uint64_t theta_n, uint64_t theta_d, uint64_t tau_n, uint64_t tau_d) {
+    uint32_t nt = 0;
+    for (uint64_t p = q->ptr[a]; p < q->ptr[a + 1]; ++p) {
+        const orc_slot *s = orc_index_slot(ix, q->ids[p]);
+        if (!s->len) continue;  /* a k-mer no gene of t has */
+        const uint32_t ca = q->cnt[p];
+        for (uint64_t x = s->start; x < (uint64_t)s->start + s->len; ++x) {
+            const uint32_t b = ix->gene[x], cb = ix->cnt[x];
+            if (A->m[b] == 0) A->touched[nt++] = b;
+            A->m[b] += ca < cb ? ca : cb;
+            A->oa[b] += ca;
+            A->ob[b] += cb;
+        }
+    }
+    qsort(A->touched, nt, sizeof(uint32_t), cmp_u32);
+    const uint64_t na = q->nwin[a];
+    int have = 0;
+    uint64_t bm = 0, bd = 1;
+    int64_t c = 0;
+    /* the candidates' maximum, then every candidate at it, ascending b */
+    for (int pass = 0; pass < 2; ++pass) {
+        for (uint32_t i = 0; i < nt; ++i) {
+            const uint32_t b = A->touched[i];
+            const uint64_t m = A->m[b], d = na + t->nwin[b] - m;
+            int ok = 1;
+            if (theta_d) {
+                const unsigned __int128 la = q->len[a], lb = t->len[b];
+                if (la * theta_d < (unsigned __int128)theta_n * lb || lb * theta_d < (unsigned __int128)theta_n * la) ok = 0;
+            }
+            if (ok && tau_d) {
+                if ((unsigned __int128)A->oa[b] * tau_d < (unsigned __int128)tau_n * na) ok = 0;
+                if ((unsigned __int128)A->ob[b] * tau_d < (unsigned __int128)tau_n * t->nwin[b]) ok = 0;
+            }
+            if (!ok) continue;
+            if (pass == 0) {
+                if (!have || orc_cmp_j(m, d, bm, bd) > 0) { bm = m; bd = d; }
+                have = 1;
+            } else if (orc_cmp_j(m, d, bm, bd) == 0) {
+                col[c] = b; num[c] = m; den[c] = d; ++c;
+            }
+        }
+        if (pass == 0 && !(have && orc_cmp_j(bm, bd, 0, 1) > 0)) break;
+    }
+    for (uint32_t i = 0; i < nt; ++i) {
+        const uint32_t b = A->touched[i];
+        A->m[b] = 0; A->oa[b] = 0; A->ob[b] = 0;
+    }
+    return c;
+}
+
+typedef struct {
+    const orc_genome *q, *t;
+    const orc_index *ix;
+    uint64_t theta_n, theta_d, tau_n, tau_d;
+    const uint32_t *rows;
+    uint32_t nrows;
+    uint32_t next;
+    uint32_t **rc;
+    uint64_t **rn, **rd;
+    int64_t *rcount;
+} orc_sparse_job;
+
+static void *orc_sparse_worker(void *arg) {
+    orc_sparse_job *J = (orc_sparse_job *)arg;
+    const uint32_t n = J->t->n ? J->t->n : 1;
+    orc_acc A;
+    A.m = (uint64_t *)calloc(n, sizeof(uint64_t));
+    A.oa = (uint64_t *)calloc(n, sizeof(uint64_t));
+    A.ob = (uint64_t *)calloc(n, sizeof(uint64_t));
+    A.touched = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    uint32_t *col = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    uint64_t *num = (uint64_t *)malloc(sizeof(uint64_t) * n);
+    uint64_t *den = (uint64_t *)malloc(sizeof(uint64_t) * n);
+    for (;;) {
+        const uint32_t r = __atomic_fetch_add(&J->next, 1u, __ATOMIC_RELAXED);
+        if (r >= J->nrows) break;
+        const uint32_t a = J->rows ? J->rows[r] : r;
+        const int64_t c = orc_bh_row_sparse(J->q, a, J->t, J->ix, &A, col, num, den, J->theta_n, J->theta_d,
+                                            J->tau_n, J->tau_d);
+        J->rcount[r] = c;
+        J->rc[r] = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(c + 1));
+        J->rn[r] = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(c + 1));
+        J->rd[r] = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(c + 1));
+        memcpy(J->rc[r], col, sizeof(uint32_t) * (size_t)c);
+        memcpy(J->rn[r], num, sizeof(uint64_t) * (size_t)c);
+        memcpy(J->rd[r], den, sizeof(uint64_t) * (size_t)c);
+    }
+    free(A.m); free(A.oa); free(A.ob); free(A.touched);
+    free(col); free(num); free(den);
+    return NULL;
+}
+
+/* Best hits of the given rows of q (every row when rows == NULL) in t, whose index is ix;
+ * rows go to a pool of threads one at a time.  Returns the same structure as
+ * orc_bh_rows_f, so orc_bbh applies to it. */
+orc_bh *orc_bh_sparse(const orc_genome *q, const orc_genome *t, const orc_index *ix, const uint32_t *rows,
+                      uint32_t nrows, int nthreads, uint64_t theta_n, uint64_t theta_d, uint64_t tau_n,
+                      uint64_t tau_d) {
+    if (!rows) nrows = q->n;
+    if (nthreads < 1) nthreads = 1;
+    orc_sparse_job J;
+    memset(&J, 0, sizeof(J));
+    J.q = q; J.t = t; J.ix = ix; J.rows = rows; J.nrows = nrows;
+    J.theta_n = theta_n; J.theta_d = theta_d; J.tau_n = tau_n; J.tau_d = tau_d;
+    J.rc = (uint32_t **)calloc((size_t)nrows + 1, sizeof(void *));
+    J.rn = (uint64_t **)calloc((size_t)nrows + 1, sizeof(void *));
+    J.rd = (uint64_t **)calloc((size_t)nrows + 1, sizeof(void *));
+    J.rcount = (int64_t *)calloc((size_t)nrows + 1, sizeof(int64_t));
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    for (int i = 0; i < nthreads; ++i) pthread_create(&th[i], NULL, orc_sparse_worker, &J);
+    for (int i = 0; i < nthreads; ++i) pthread_join(th[i], NULL);
+    free(th);
+    orc_bh *o = (orc_bh *)calloc(1, sizeof(orc_bh));
+    o->nrows = nrows;
+    o->ptr = (uint64_t *)calloc((size_t)nrows + 1, sizeof(uint64_t));
+    for (uint32_t r = 0; r < nrows; ++r) o->ptr[r + 1] = o->ptr[r] + (uint64_t)J.rcount[r];
+    const uint64_t nnz = o->ptr[nrows];
+    o->col = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nnz + 1));
+    o->num = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nnz + 1));
+    o->den = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nnz + 1));
+    for (uint32_t r = 0; r < nrows; ++r) {
+        const uint64_t p = o->ptr[r], c = (uint64_t)J.rcount[r];
+        memcpy(o->col + p, J.rc[r], sizeof(uint32_t) * (size_t)c);
+        memcpy(o->num + p, J.rn[r], sizeof(uint64_t) * (size_t)c);
+        memcpy(o->den + p, J.rd[r], sizeof(uint64_t) * (size_t)c);
+        free(J.rc[r]); free(J.rn[r]); free(J.rd[r]);
+    }
+    free(J.rc); free(J.rn); free(J.rd); free(J.rcount);
+    return o;
+}

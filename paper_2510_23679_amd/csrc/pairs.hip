@@ -1529,18 +1529,25 @@ __global__ __launch_bounds__(256) void k_colmax_sort(uint32_t bh_rows, const uin
     }
 }
 
-// BBH of one row: keep each best hit (a, b) whose reverse row contains a.
+// BBH of one row: keep each best hit (a, b) whose reverse row contains a.  Every read stays
+// inside the best-hit arrays' capacity (bh_cap) and a column b outside the reverse rows
+// (ncols) is skipped, so a corrupt or overflowed input cannot send the walk out of bounds;
+// the callers stop before this when the best-hit output overflowed.
 template <bool WRITE>
-__device__ __forceinline__ void bbh_row(uint32_t a, uint32_t grow, uint32_t rab, uint32_t ba_base, const uint32_t *ab_ptr,
-                                        const uint32_t *ab_col, const uint32_t *ab_num, const uint32_t *ab_den,
-                                        const uint32_t *ba_ptr, const uint32_t *ba_col, uint32_t *out_ptr, uint32_t *out_a,
+__device__ __forceinline__ void bbh_row(uint32_t a, uint32_t grow, uint32_t rab, uint32_t ba_base, uint32_t ncols,
+                                        const uint32_t *ab_ptr, const uint32_t *ab_col, const uint32_t *ab_num,
+                                        const uint32_t *ab_den, uint64_t ab_cap, const uint32_t *ba_ptr,
+                                        const uint32_t *ba_col, uint64_t ba_cap, uint32_t *out_ptr, uint32_t *out_a,
                                         uint32_t *out_b, uint32_t *out_num, uint32_t *out_den, uint64_t cap) {
     uint32_t pos = WRITE ? out_ptr[grow] : 0u;
-    for (uint32_t p = ab_ptr[rab]; p < ab_ptr[rab + 1]; ++p) {
+    const uint64_t pend = min(static_cast<uint64_t>(ab_ptr[rab + 1]), ab_cap);
+    for (uint64_t p = ab_ptr[rab]; p < pend; ++p) {
         const uint32_t b = ab_col[p];
+        if (b >= ncols) continue;
         const uint32_t rba = ba_base + b;
         bool found = false;
-        for (uint32_t q = ba_ptr[rba]; q < ba_ptr[rba + 1]; ++q) {
+        const uint64_t qend = min(static_cast<uint64_t>(ba_ptr[rba + 1]), ba_cap);
+        for (uint64_t q = ba_ptr[rba]; q < qend; ++q) {
             const uint32_t x = ba_col[q];
             if (x >= a) {
                 found = x == a;
@@ -1573,43 +1580,63 @@ __device__ __forceinline__ uint32_t find_bbh_task(const DevTask *tasks, const ui
     return order[lo];
 }
 
+// BBH of a plan: one thread per BBH row.  When an earlier kernel of the launch raised an
+// error (record or best-hit capacity, the best-hit entries then being incomplete), no row
+// is walked: the count pass writes zeros and the write pass writes nothing.
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_bbh(const DevTask *__restrict__ tasks, const uint32_t *__restrict__ order,
-                                             uint32_t n_tasks, uint32_t bbh_rows,
+                                             uint32_t n_tasks, uint32_t bbh_rows, uint32_t bh_rows,
                                              const uint32_t *__restrict__ bh_ptr, const uint32_t *__restrict__ bh_col,
                                              const uint32_t *__restrict__ bh_num, const uint32_t *__restrict__ bh_den,
-                                             uint32_t *__restrict__ out_ptr, uint32_t *__restrict__ out_a,
+                                             uint64_t bh_cap, uint32_t *__restrict__ out_ptr, uint32_t *__restrict__ out_a,
                                              uint32_t *__restrict__ out_b, uint32_t *__restrict__ out_num,
                                              uint32_t *__restrict__ out_den, uint64_t cap, pdp_status *st) {
     const uint32_t grow = blockIdx.x * blockDim.x + threadIdx.x;
-    if (WRITE && grow == 0 && out_ptr[bbh_rows] > cap) raise_status(st, PDP_E_CAPACITY, out_ptr[bbh_rows], 2);
     if (grow >= bbh_rows) return;
+    if (st->code != 0 || bh_ptr[bh_rows] > bh_cap) {
+        if (!WRITE) out_ptr[grow] = 0;
+        return;
+    }
+    if (WRITE && grow == 0 && out_ptr[bbh_rows] > cap) raise_status(st, PDP_E_CAPACITY, out_ptr[bbh_rows], 2);
     const DevTask &T = tasks[find_bbh_task(tasks, order, n_tasks, grow)];
     const uint32_t a = grow - T.bbh_row_base;
-    bbh_row<WRITE>(a, grow, T.row_base[0] + a, T.row_base[1], bh_ptr, bh_col, bh_num, bh_den, bh_ptr, bh_col, out_ptr,
-                   out_a, out_b, out_num, out_den, cap);
+    bbh_row<WRITE>(a, grow, T.row_base[0] + a, T.row_base[1], T.b.n_genes, bh_ptr, bh_col, bh_num, bh_den, bh_cap, bh_ptr,
+                   bh_col, bh_cap, out_ptr, out_a, out_b, out_num, out_den, cap);
 }
 
+// pdp_bbh: the two best-hit outputs are the caller's.  A total past an output's capacity
+// (an overflowed best-hit call) is PDP_E_CAPACITY (where = 1), a column past the reverse
+// output's rows PDP_E_INVAL (where = the row); either way nothing is walked.
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_bbh_pair(uint32_t rows, const uint32_t *__restrict__ ab_ptr,
                                                   const uint32_t *__restrict__ ab_col, const uint32_t *__restrict__ ab_num,
-                                                  const uint32_t *__restrict__ ab_den, const uint32_t *__restrict__ ba_ptr,
-                                                  const uint32_t *__restrict__ ba_col, uint32_t ba_rows,
-                                                  uint32_t *__restrict__ out_ptr, uint32_t *__restrict__ out_a,
-                                                  uint32_t *__restrict__ out_b, uint32_t *__restrict__ out_num,
-                                                  uint32_t *__restrict__ out_den, uint64_t cap, pdp_status *st) {
+                                                  const uint32_t *__restrict__ ab_den, uint64_t ab_cap,
+                                                  const uint32_t *__restrict__ ba_ptr, const uint32_t *__restrict__ ba_col,
+                                                  uint32_t ba_rows, uint64_t ba_cap, uint32_t *__restrict__ out_ptr,
+                                                  uint32_t *__restrict__ out_a, uint32_t *__restrict__ out_b,
+                                                  uint32_t *__restrict__ out_num, uint32_t *__restrict__ out_den,
+                                                  uint64_t cap, pdp_status *st) {
     const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (WRITE && a == 0 && out_ptr[rows] > cap) raise_status(st, PDP_E_CAPACITY, out_ptr[rows], 2);
     if (a >= rows) return;
+    const uint32_t ab_tot = ab_ptr[rows], ba_tot = ba_ptr[ba_rows];
+    if (ab_tot > ab_cap || ba_tot > ba_cap) {
+        if (a == 0 && !WRITE) raise_status(st, PDP_E_CAPACITY, ab_tot > ab_cap ? ab_tot : ba_tot, 1);
+        if (!WRITE) out_ptr[a] = 0;
+        return;
+    }
+    if (WRITE && a == 0 && out_ptr[rows] > cap) raise_status(st, PDP_E_CAPACITY, out_ptr[rows], 2);
     // a column index past the reverse output's rows cannot name a best hit there
     for (uint32_t p = ab_ptr[a]; p < ab_ptr[a + 1]; ++p) {
         if (ab_col[p] >= ba_rows) {
-            raise_status(st, PDP_E_INVAL, 0, a);
-            if (!WRITE) out_ptr[a] = 0;
+            if (!WRITE) {
+                raise_status(st, PDP_E_INVAL, 0, a);
+                out_ptr[a] = 0;
+            }
             return;
         }
     }
-    bbh_row<WRITE>(a, a, a, 0, ab_ptr, ab_col, ab_num, ab_den, ba_ptr, ba_col, out_ptr, out_a, out_b, out_num, out_den, cap);
+    bbh_row<WRITE>(a, a, a, 0, ba_rows, ab_ptr, ab_col, ab_num, ab_den, ab_cap, ba_ptr, ba_col, ba_cap, out_ptr, out_a,
+                   out_b, out_num, out_den, cap);
 }
 
 // ------------------------------------------------------------------ host
@@ -1867,12 +1894,14 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     PDP_TRY(mark(PDP_KERNEL_BBH, true));
     if (p.bbh_rows && bbh) {
         const uint32_t g = (p.bbh_rows + 255) / 256;
-        hipLaunchKernelGGL(k_bbh<false>, dim3(g), dim3(256), 0, s, w.tasks, w.order, p.n_tasks, p.bbh_rows, bh->ptr, bh->col,
-                           bh->num, bh->den, bbh->ptr, bbh->a, bbh->b, bbh->num, bbh->den, bbh->capacity, st);
+        hipLaunchKernelGGL(k_bbh<false>, dim3(g), dim3(256), 0, s, w.tasks, w.order, p.n_tasks, p.bbh_rows, p.bh_rows,
+                           bh->ptr, bh->col, bh->num, bh->den, bh->capacity, bbh->ptr, bbh->a, bbh->b, bbh->num, bbh->den,
+                           bbh->capacity, st);
         PDP_TRY(hipGetLastError());
         PDP_TRY(launch_scan(bbh->ptr, bbh->ptr, p.bbh_rows, w.partials, s));
-        hipLaunchKernelGGL(k_bbh<true>, dim3(g), dim3(256), 0, s, w.tasks, w.order, p.n_tasks, p.bbh_rows, bh->ptr, bh->col,
-                           bh->num, bh->den, bbh->ptr, bbh->a, bbh->b, bbh->num, bbh->den, bbh->capacity, st);
+        hipLaunchKernelGGL(k_bbh<true>, dim3(g), dim3(256), 0, s, w.tasks, w.order, p.n_tasks, p.bbh_rows, p.bh_rows,
+                           bh->ptr, bh->col, bh->num, bh->den, bh->capacity, bbh->ptr, bbh->a, bbh->b, bbh->num, bbh->den,
+                           bbh->capacity, st);
         PDP_TRY(hipGetLastError());
     }
     PDP_TRY(mark(PDP_KERNEL_BBH, false));
@@ -1887,15 +1916,17 @@ hipError_t launch_bbh_standalone(const pdp_bh_out *ab, const pdp_bh_out *ba, pdp
     const uint32_t rows = ab->n_rows;
     if (rows) {
         const uint32_t g = (rows + 255) / 256;
-        hipLaunchKernelGGL(k_bbh_pair<false>, dim3(g), dim3(256), 0, s, rows, ab->ptr, ab->col, ab->num, ab->den, ba->ptr,
-                           ba->col, ba->n_rows, out->ptr, out->a, out->b, out->num, out->den, out->capacity, st);
+        hipLaunchKernelGGL(k_bbh_pair<false>, dim3(g), dim3(256), 0, s, rows, ab->ptr, ab->col, ab->num, ab->den,
+                           ab->capacity, ba->ptr, ba->col, ba->n_rows, ba->capacity, out->ptr, out->a, out->b, out->num,
+                           out->den, out->capacity, st);
         PDP_TRY(hipGetLastError());
     }
     PDP_TRY(launch_scan(out->ptr, out->ptr, rows, partials, s));
     if (rows) {
         const uint32_t g = (rows + 255) / 256;
-        hipLaunchKernelGGL(k_bbh_pair<true>, dim3(g), dim3(256), 0, s, rows, ab->ptr, ab->col, ab->num, ab->den, ba->ptr,
-                           ba->col, ba->n_rows, out->ptr, out->a, out->b, out->num, out->den, out->capacity, st);
+        hipLaunchKernelGGL(k_bbh_pair<true>, dim3(g), dim3(256), 0, s, rows, ab->ptr, ab->col, ab->num, ab->den,
+                           ab->capacity, ba->ptr, ba->col, ba->n_rows, ba->capacity, out->ptr, out->a, out->b, out->num,
+                           out->den, out->capacity, st);
         PDP_TRY(hipGetLastError());
     }
     return hipSuccess;

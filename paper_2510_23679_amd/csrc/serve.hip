@@ -111,6 +111,10 @@ struct ServeRequest {
     int32_t code = PDP_OK;
     uint32_t attempts = 0;
     uint64_t inc_cap = 0, bh_cap = 0, bbh_cap = 0;
+    // admission: the provisional plan and the footprint it gives are made once per run of the
+    // request and kept while it waits for memory (cleared when a capacity retry grows it)
+    bool planned = false;
+    uint64_t foot_bytes = 0, foot_plan_ws = 0;
     // device side while in flight
     uint64_t dev_off = 0, dev_bytes = 0;
     pdp_dict dict{};
@@ -308,6 +312,7 @@ bool collect(pdp_server *S, ServeSlot &, ServeRequest *r) {
         else if (st.where == 1) r->bh_cap = grow;
         else r->bbh_cap = grow;
         S->retries++;
+        r->planned = false;  // the capacities changed: plan and footprint are made again
         give_pin(S, r->out);
         return false;
     }
@@ -387,16 +392,21 @@ void worker_loop(pdp_server *S) {
                 }
             if (!free_slot) break;
             ServeRequest *r = S->pending.front();
-            r->attempts++;
-            // A provisional plan gives the footprint: the descriptor is bound to a placeholder
-            // address (planning reads only its sizes); the final plan is made once the memory is placed.
-            uint64_t plan_ws = 0, bytes = 0, dict_bytes = 0, build_ws = 0;
-            int32_t rc = pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, S->cfg.alphabet, &dict_bytes, &build_ws);
-            if (rc == PDP_OK)
-                rc = pdp_dict_bind(reinterpret_cast<void *>(uintptr_t(256)), dict_bytes, r->n_genes, r->n_res, S->cfg.k,
-                                   S->cfg.alphabet, &r->dict);
-            if (rc == PDP_OK) rc = make_plan(S, r);
-            if (rc == PDP_OK) bytes = footprint(S, r, &plan_ws);
+            int32_t rc = PDP_OK;
+            if (!r->planned) {
+                // A provisional plan gives the footprint: the descriptor is bound to a placeholder
+                // address (planning reads only its sizes); launch_request moves the plan's pointers
+                // once the memory is placed.  Both are kept while the request waits for memory.
+                uint64_t dict_bytes = 0, build_ws = 0;
+                rc = pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, S->cfg.alphabet, &dict_bytes, &build_ws);
+                if (rc == PDP_OK)
+                    rc = pdp_dict_bind(reinterpret_cast<void *>(uintptr_t(256)), dict_bytes, r->n_genes, r->n_res,
+                                       S->cfg.k, S->cfg.alphabet, &r->dict);
+                if (rc == PDP_OK) rc = make_plan(S, r);
+                if (rc == PDP_OK) r->foot_bytes = footprint(S, r, &r->foot_plan_ws);
+                r->planned = rc == PDP_OK;
+            }
+            const uint64_t bytes = r->foot_bytes, plan_ws = r->foot_plan_ws;
             if (rc != PDP_OK || bytes == 0 || bytes > S->arena->size()) {
                 S->pending.pop_front();
                 r->code = rc != PDP_OK ? rc : PDP_E_BUDGET;
@@ -409,6 +419,8 @@ void worker_loop(pdp_server *S) {
             S->pending.pop_front();
             r->dev_off = off;
             r->dev_bytes = bytes;
+            // a run starts only now that its memory is placed: waiting for memory is no attempt
+            r->attempts++;
             if (r->attempts == 1) r->t_admit = now_us(S->t0);
             rc = launch_request(S, *free_slot, r, plan_ws);
             if (rc != PDP_OK) {

@@ -83,24 +83,47 @@ def check_bbh(got, want: oracle.Pairs) -> None:
     assert np.array_equal(num.astype(np.uint64), want.num) and np.array_equal(den.astype(np.uint64), want.den)
 
 
+def bbh_from_best_hits(bh_ab, bh_ba, n_a: int, n_b: int):
+    """Eq. bidirectional_best_hit applied to two best-hit CSRs: every (a, b) with b in BH(a) and a
+    in BH(b), in (a, b) order, with the (num, den) of the AB entry."""
+    pab, cab = bh_ab[0].astype(np.int64), bh_ab[1].astype(np.int64)
+    pba, cba = bh_ba[0].astype(np.int64), bh_ba[1].astype(np.int64)
+    ra = np.repeat(np.arange(n_a, dtype=np.int64), np.diff(pab))
+    rb = np.repeat(np.arange(n_b, dtype=np.int64), np.diff(pba))
+    key_ab = ra * (n_b + 1) + cab            # (a, b) of every AB best hit
+    key_ba = cba * (n_b + 1) + rb            # (a, b) of every BA best hit, transposed
+    keep = np.isin(key_ab, key_ba)           # AB keys ascend: rows ascend, columns ascend in a row
+    return (ra[keep].astype(np.uint32), cab[keep].astype(np.uint32), bh_ab[2][keep], bh_ab[3][keep])
+
+
 def check_bh_properties(bh_ab, bh_ba, bbh, n_a: int, n_b: int) -> None:
     """Properties that hold at any size: CSR well-formed, columns ascending and in range,
-    0 < num <= den, ties equal in value, BBH inside both best-hit sets and in (a, b) order."""
-    for (ptr, col, num, den), ncols in ((bh_ab, n_b), (bh_ba, n_a)):
+    0 < num <= den, ties equal in value, and the BBH list exactly the mutual pairs of the two
+    best-hit sets (none missing, none extra), in (a, b) order with the AB entry's num/den."""
+    for (ptr, col, num, den), nrows, ncols in ((bh_ab, n_a, n_b), (bh_ba, n_b, n_a)):
         p = ptr.astype(np.int64)
-        assert p[0] == 0 and np.all(np.diff(p) >= 0)
+        assert len(p) == nrows + 1 and p[0] == 0 and np.all(np.diff(p) >= 0)
         assert np.all(col < ncols)
         assert np.all(num > 0) and np.all(num <= den)
-        for r in np.nonzero(np.diff(p) > 1)[0]:
-            lo, hi = p[r], p[r + 1]
-            assert np.all(np.diff(col[lo:hi].astype(np.int64)) > 0), "columns ascending"
-            x = num[lo:hi].astype(np.uint64) * den[lo].astype(np.uint64)
-            y = num[lo].astype(np.uint64) * den[lo:hi].astype(np.uint64)
-            assert np.array_equal(x, y), "ties share one value"
+        rows = np.repeat(np.arange(nrows, dtype=np.int64), np.diff(p))
+        key = rows * (ncols + 1) + col.astype(np.int64)
+        assert np.all(np.diff(key) > 0), "columns ascending inside every row"
+        first = p[:-1][np.diff(p) > 0]
+        lead = np.repeat(first, np.diff(p)[np.diff(p) > 0])  # each entry's row's first entry
+        x = num.astype(np.uint64) * den[lead].astype(np.uint64)
+        y = num[lead].astype(np.uint64) * den.astype(np.uint64)
+        assert np.array_equal(x, y), "ties share one value"
     a, b, num, den = bbh
-    key = a.astype(np.int64) * (n_b + 1) + b
-    assert np.all(np.diff(key) > 0), "BBH in (a, b) order"
-    pab, cab = bh_ab[0].astype(np.int64), bh_ab[1]
-    pba, cba = bh_ba[0].astype(np.int64), bh_ba[1]
-    for x, y in zip(a.tolist(), b.tolist()):
-        assert y in cab[pab[x]:pab[x + 1]] and x in cba[pba[y]:pba[y + 1]]
+    wa, wb, wn, wd = bbh_from_best_hits(bh_ab, bh_ba, n_a, n_b)
+    assert np.array_equal(a, wa) and np.array_equal(b, wb), "BBH = the mutual pairs of the two best-hit sets"
+    assert np.array_equal(num, wn) and np.array_equal(den, wd), "BBH num/den = the AB entries'"
+
+
+def check_pair_complete(ab, ba, bb, want, n_a: int, n_b: int) -> None:
+    """One genome pair in full: every best-hit row both ways and the whole BBH set against the
+    oracle's (ab, ba, bbh), plus the any-size properties."""
+    wab, wba, wbb = want
+    check_bh(ab, wab)
+    check_bh(ba, wba)
+    check_bbh(bb, wbb)
+    check_bh_properties(ab, ba, bb, n_a, n_b)

@@ -2,14 +2,14 @@
 benchmark times: the first wave of the 400-instance batched workload (independent instances of
 U{4..30} genomes x U{500..5000} genes, k per instance by the rule, 128-row tiles and 512-entry
 join sub-ranges, not persistent) and full-size arrivals served against all 200 resident genomes
-of 4000 genes (k = 7 fixed from the residents).  Sampled rows are checked against the oracle one
-by one (first and last rows included), and the outputs (every third pair of the wave, every
-resident of a request) against the properties that hold at any size."""
+of 4000 genes (k = 7 fixed from the residents).  Every genome pair is compared in full -- every
+best-hit row both ways and the whole BBH set -- against the sparse oracle, whose agreement with
+the dense oracle and with brute force the CPU tests pin."""
 import numpy as np
 import pytest
 
 import oracle
-from helpers import check_bbh, check_bh, check_bh_properties
+from helpers import check_bh, check_pair_complete
 from synth import batched_instances, serving_workload
 
 torch = pytest.importorskip("torch")
@@ -27,12 +27,8 @@ def say(*a):
     print("[case]", *a, flush=True)
 
 
-def sampled_rows(rng, n, m=16):
-    rows = rng.choice(n, min(m, n), replace=False)
-    return np.unique(np.concatenate([[0, n - 1], rows]))
-
-
-def test_full_size_batched_first_wave_sampled():
+@pytest.mark.timeout(900)
+def test_full_size_batched_first_wave_complete():
     wave, genomes = [], 0
     for ds in batched_instances(0, 400):
         if wave and genomes + len(ds.genomes) > WAVE_GENOMES:
@@ -60,30 +56,23 @@ def test_full_size_batched_first_wave_sampled():
     runner = pdp.PairRunner(tasks, pdp.params(tile_rows=128, join_entries=512))
     runner.run()
     res = runner.results()
-    rng = np.random.default_rng(41)
-    picked = list(range(0, len(tasks), 97)) + [len(tasks) - 1]
-    cache = {}
-
-    def og(x, i):
-        if (x, i) not in cache:
-            cache[(x, i)] = oracle.OracleGenome(wave[x].genomes[i], spans[x][2])
-        return cache[(x, i)]
-
-    for t in range(0, len(where), 3):  # every third pair: the property checks loop in Python
-        x, i, j = where[t]
-        ab, ba, bb = res.best_hits(t, 0), res.best_hits(t, 1), res.bbh_pairs(t)
-        check_bh_properties(ab, ba, bb, wave[x].genomes[i].n_genes, wave[x].genomes[j].n_genes)
-    say("sampled pairs:", len(picked), "of", len(tasks))
-    for t in picked:
-        x, i, j = where[t]
-        a, b = og(x, i), og(x, j)
-        rows = sampled_rows(rng, wave[x].genomes[i].n_genes)
-        check_bh(res.best_hits(t, 0), oracle.bh(a, b, rows=rows), rows=rows)
-        cols = sampled_rows(rng, wave[x].genomes[j].n_genes)
-        check_bh(res.best_hits(t, 1), oracle.bh(b, a, rows=cols), rows=cols)
+    del runner, batch, devs
+    say("comparing", len(tasks), "pairs against the sparse oracle")
+    t = 0
+    for x, ds in enumerate(wave):
+        og = oracle.genomes(ds.genomes, spans[x][2])
+        want = oracle.all_pairs_sparse(og)
+        for i in range(len(ds.genomes)):
+            for j in range(i + 1, len(ds.genomes)):
+                assert where[t] == (x, i, j)
+                check_pair_complete(res.best_hits(t, 0), res.best_hits(t, 1), res.bbh_pairs(t), want[(i, j)],
+                                    ds.genomes[i].n_genes, ds.genomes[j].n_genes)
+                t += 1
+    assert t == len(tasks)
 
 
-def test_full_size_serving_sampled():
+@pytest.mark.timeout(900)
+def test_full_size_serving_complete():
     wl = serving_workload()
     k = pdp.k_rule(wl.residents.total_residues())
     assert k == 7
@@ -104,22 +93,20 @@ def test_full_size_serving_sampled():
                 srv.release(d.tag)
     finally:
         srv.close()
-    rng = np.random.default_rng(43)
-    residents = [0, 71, 142, 199]
-    og_res = {r: oracle.OracleGenome(wl.residents.genomes[r], k) for r in residents}
+    del batch
+    og_res = oracle.genomes(wl.residents.genomes, k)
+    n_res = len(og_res)
     for j, g in enumerate(arrivals):
         d, res = out[j]
         assert d.code == 0 and res.code == 0
-        say("arrival", j, "genes", g.n_genes)
-        for r in range(len(wl.residents.genomes)):
-            check_bh_properties(res.best_hits(r, 0), res.best_hits(r, 1), res.bbh_pairs(r), g.n_genes,
-                                wl.residents.genomes[r].n_genes)
-        q = oracle.OracleGenome(g, k)
-        for r in residents:
-            rows = sampled_rows(rng, g.n_genes)
-            check_bh(res.best_hits(r, 0), oracle.bh(q, og_res[r], rows=rows), rows=rows)
-            cols = sampled_rows(rng, wl.residents.genomes[r].n_genes)
-            check_bh(res.best_hits(r, 1), oracle.bh(og_res[r], q, rows=cols), rows=cols)
-        # a request's BBH against one resident, in full: both directions computed by the oracle
-        ab, ba = oracle.bh(q, og_res[0]), oracle.bh(og_res[0], q)
-        check_bbh(res.bbh_pairs(0), oracle.bbh(ab, ba))
+        say("arrival", j, "genes", g.n_genes, "against all", n_res, "residents")
+        og = og_res + [oracle.OracleGenome(g, k)]
+        dirs = [(n_res, r) for r in range(n_res)] + [(r, n_res) for r in range(n_res)]
+        hits = oracle.bh_sparse_directions(og, dirs)
+        for r in range(n_res):
+            ab, ba = hits[(n_res, r)], hits[(r, n_res)]
+            check_pair_complete(res.best_hits(r, 0), res.best_hits(r, 1), res.bbh_pairs(r),
+                                (ab, ba, oracle.bbh(ab, ba)), g.n_genes, wl.residents.genomes[r].n_genes)
+        # one resident's rows against the dense oracle as well
+        rows = np.unique(np.linspace(0, g.n_genes - 1, 40).astype(np.uint32))
+        check_bh(res.best_hits(0, 0), oracle.bh(og[n_res], og_res[0], rows=rows), rows=rows)

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import check_bbh, check_bh, check_bh_properties, check_dictionary
+from helpers import check_bbh, check_bh, check_bh_properties, check_dictionary, check_pair_complete
 from synth import genome_from_strings, make_config
 
 torch = pytest.importorskip("torch")
@@ -142,9 +142,10 @@ def test_nucleotide_filters(theta, tau):
     compare_all(ds.genomes, 13, res, theta, tau)
 
 
-def test_full_size_nucleotide_sampled():
-    """All 45 pairs of 10 nucleotide genomes x 3000 genes (k = 13) in one launch; sampled rows
-    against the oracle, every output against the any-size properties."""
+@pytest.mark.timeout(900)
+def test_full_size_nucleotide_complete():
+    """All 45 pairs of 10 nucleotide genomes x 3000 genes (k = 13) in one launch: every best-hit row
+    both ways and every BBH set against the sparse oracle, one dictionary against the oracle's."""
     ds = make_config(2, alphabet="nt")
     k = pdp.k_rule(ds.total_residues(), 4)
     say("full-size nucleotide 10 x 3000 workload, k =", k)
@@ -154,15 +155,9 @@ def test_full_size_nucleotide_sampled():
     for d in dicts:
         d.check_status()
     res = runner.results()
-    og = [oracle.OracleGenome(g, k) for g in ds.genomes]
+    og = oracle.genomes(ds.genomes, k)
     check_dictionary(dicts[3].host(), og[3])
-    rng = np.random.default_rng(17)
+    want = oracle.all_pairs_sparse(og, ds.pairs())
     for t, (i, j) in enumerate(ds.pairs()):
         ab, ba, bb = res.best_hits(t, 0), res.best_hits(t, 1), res.bbh_pairs(t)
-        check_bh_properties(ab, ba, bb, ds.genomes[i].n_genes, ds.genomes[j].n_genes)
-        if t % 7 == 0:
-            rows = np.sort(rng.choice(ds.genomes[i].n_genes, 20, replace=False))
-            rows = np.concatenate([[0], rows, [ds.genomes[i].n_genes - 1]])
-            check_bh(ab, oracle.bh(og[i], og[j], rows=rows), rows=rows)
-            cols = np.sort(rng.choice(ds.genomes[j].n_genes, 20, replace=False))
-            check_bh(ba, oracle.bh(og[j], og[i], rows=cols), rows=cols)
+        check_pair_complete(ab, ba, bb, want[(i, j)], ds.genomes[i].n_genes, ds.genomes[j].n_genes)

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import check_bbh, check_bh, check_bh_properties, check_dictionary
+from helpers import check_bbh, check_bh, check_bh_properties, check_dictionary, check_pair_complete
 from synth import genome_from_strings, make_config
 
 torch = pytest.importorskip("torch")
@@ -271,6 +271,60 @@ def test_capacity_overflow_reads_no_unwritten_records():
     compare_all(ds.genomes, k, runner.results())
 
 
+def test_best_hit_capacity_overflow_with_bbh():
+    # best-hit output far below the tied rows' entries, BBH on, every buffer poisoned: the launch
+    # reports PDP_E_CAPACITY for the best hits (where = 1), the BBH kernels walk nothing (all BBH
+    # rows empty), and the retry with the reported size gives the oracle's results
+    rng = random.Random(21)
+    genes = ["".join(rng.choice(ALPHA) for _ in range(rng.randint(30, 120))) for _ in range(60)]
+    a = genes[:30] + [genes[0]] * 3
+    b = [genes[0]] * 7 + genes[30:] + [genes[1]] * 5 + [genes[2]] * 4
+    rng.shuffle(b)
+    gens = [genome_from_strings(a), genome_from_strings(b)]
+    k = 4
+    dicts = [pdp.Dictionary.build_from(g, k) for g in gens]
+    say("best-hit capacity overflow with BBH, poisoned buffers")
+    runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts), bh_capacity=8)
+    runner.ws.buf.fill_(255)
+    for t in (runner.bh.col, runner.bh.num, runner.bh.den, runner.bbh.a, runner.bbh.b):
+        t.fill_(0x7F7F7F7F)  # a column read from here would index far past every array
+    runner.launch()
+    code, needed, where = pdp.read_status(runner.status)
+    assert code == pdp.PDP_E_CAPACITY and where == 1 and needed > 8
+    assert int(runner.bbh.ptr.cpu().numpy().view(np.uint32)[-1]) == 0
+    runner.run()
+    compare_all(gens, k, runner.results())
+
+
+def test_standalone_bbh_rejects_overflowed_best_hits():
+    # pdp_bbh given a best-hit output whose total exceeds its capacity (the output of an
+    # overflowed call) reports PDP_E_CAPACITY (where = 1) and walks none of its entries
+    from paper_2510_23679_amd import binding as B
+    import ctypes as C
+    ds = make_config(2, genomes=2, genes=300)
+    k = 5
+    da, db = (pdp.Dictionary.build_from(g, k) for g in ds.genomes)
+    ab, ba = pdp.bh(da, db), pdp.bh(db, da)
+    n_ab = int(ab.ptr.cpu().numpy().view(np.uint32)[-1])
+    say("pdp_bbh on an overflowed best-hit output")
+    short = pdp.BHOut(ab.n_rows, n_ab // 2)
+    short.ptr.copy_(ab.ptr)
+    short.col.fill_(0x7F7F7F7F)
+    out = pdp.BBHOut(ab.n_rows, ab.n_rows + 1024)
+    st = pdp.new_status()
+    need = B.u64(0)
+    B.check(B.lib().pdp_bbh_ws_size(ab.n_rows, C.byref(need)), "pdp_bbh_ws_size")
+    ws = pdp.Workspace(need.value)
+    x, y, o = short.struct(), ba.struct(), out.struct()
+    B.check(B.lib().pdp_bbh(C.byref(x), C.byref(y), C.byref(o), st.data_ptr(), ws.ptr, ws.nbytes,
+                            int(torch.cuda.current_stream().cuda_stream)), "pdp_bbh")
+    code, needed, where = pdp.read_status(st)
+    assert code == pdp.PDP_E_CAPACITY and where == 1 and needed == n_ab
+    assert int(out.ptr.cpu().numpy().view(np.uint32)[-1]) == 0
+    oa, ob = (oracle.OracleGenome(g, k) for g in ds.genomes)
+    check_bbh(pdp.bbh(ab, ba).host()[1:], oracle.bbh(oracle.bh(oa, ob), oracle.bh(ob, oa)))
+
+
 def test_join_global_search_path():
     # one leading-residue bucket holding more target entries than the join stages in LDS
     rng = random.Random(11)
@@ -326,9 +380,11 @@ def test_repeat_runs_identical():
             assert np.array_equal(x, y)
 
 
-def test_full_size_family_model_sampled():
-    """All 45 pairs of the 10 x 3000-gene workload in one launch (the benchmark's configuration);
-    sampled rows against the oracle, every output against the any-size properties."""
+@pytest.mark.timeout(900)
+def test_full_size_family_model_complete():
+    """All 45 pairs of the 10 x 3000-gene workload in one launch (the benchmark's configuration):
+    every best-hit row both ways and every BBH set against the sparse oracle, plus sampled rows of
+    five pairs against the dense oracle."""
     ds = make_config(2)
     k = pdp.k_rule(ds.total_residues())
     assert k == 6
@@ -337,23 +393,23 @@ def test_full_size_family_model_sampled():
     runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts))
     runner.run()
     res = runner.results()
-    og = [oracle.OracleGenome(g, k) for g in ds.genomes]
+    og = oracle.genomes(ds.genomes, k)
+    want = oracle.all_pairs_sparse(og, ds.pairs())
+    say("sparse oracle done; comparing 45 pairs")
     rng = np.random.default_rng(7)
     for t, (i, j) in enumerate(ds.pairs()):
         ab, ba, bb = res.best_hits(t, 0), res.best_hits(t, 1), res.bbh_pairs(t)
-        check_bh_properties(ab, ba, bb, ds.genomes[i].n_genes, ds.genomes[j].n_genes)
-        if t % 5 == 0:
+        check_pair_complete(ab, ba, bb, want[(i, j)], ds.genomes[i].n_genes, ds.genomes[j].n_genes)
+        if t % 9 == 0:
             rows = np.sort(rng.choice(ds.genomes[i].n_genes, 24, replace=False))
-            rows = np.concatenate([[0], rows, [ds.genomes[i].n_genes - 1]])
             check_bh(ab, oracle.bh(og[i], og[j], rows=rows), rows=rows)
-            cols = np.sort(rng.choice(ds.genomes[j].n_genes, 24, replace=False))
-            check_bh(ba, oracle.bh(og[j], og[i], rows=cols), rows=cols)
 
 
-def test_full_size_large_workload_sampled():
-    """All 1225 pairs of the 50 x U{3000..5000}-gene workload with paralog copies (exact and
-    near ties) in one launch, k = 7 by the rule; every 25th pair against the oracle on sampled
-    rows (first and last rows included) and against the any-size properties."""
+@pytest.mark.timeout(900)
+def test_full_size_large_workload_complete():
+    """All 1225 pairs of the 50 x U{3000..5000}-gene workload with paralog copies (exact and near
+    ties) in one launch, k = 7 by the rule: every best-hit row both ways and every BBH set against
+    the sparse oracle; tied best hits must be present."""
     ds = make_config(3)
     k = pdp.k_rule(ds.total_residues())
     assert k == 7
@@ -364,21 +420,15 @@ def test_full_size_large_workload_sampled():
     runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts.dicts))
     runner.run()
     res = runner.results()
-    picked = list(range(0, len(ds.pairs()), 25))
-    used = sorted({x for t in picked for x in ds.pairs()[t]})
-    og = {i: oracle.OracleGenome(ds.genomes[i], k) for i in used}
-    rng = np.random.default_rng(11)
+    del runner, dicts
+    og = oracle.genomes(ds.genomes, k)
+    want = oracle.all_pairs_sparse(og, ds.pairs())
+    say("sparse oracle done; comparing 1225 pairs")
     ties = 0
-    for t in picked:
-        i, j = ds.pairs()[t]
+    for t, (i, j) in enumerate(ds.pairs()):
         ab, ba, bb = res.best_hits(t, 0), res.best_hits(t, 1), res.bbh_pairs(t)
-        check_bh_properties(ab, ba, bb, ds.genomes[i].n_genes, ds.genomes[j].n_genes)
+        check_pair_complete(ab, ba, bb, want.pop((i, j)), ds.genomes[i].n_genes, ds.genomes[j].n_genes)
         ties += int(np.sum(np.diff(ab[0].astype(np.int64)) > 1))
-        rows = np.sort(rng.choice(ds.genomes[i].n_genes, 16, replace=False))
-        rows = np.concatenate([[0], rows, [ds.genomes[i].n_genes - 1]])
-        check_bh(ab, oracle.bh(og[i], og[j], rows=rows), rows=rows)
-        cols = np.sort(rng.choice(ds.genomes[j].n_genes, 16, replace=False))
-        check_bh(ba, oracle.bh(og[j], og[i], rows=cols), rows=cols)
     assert ties > 0, "the paralog copies should give tied best hits"
 
 
