@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the best-hit path on one MI355X.
 
-Workload (default): 10 synthetic protein genomes x 3000 genes from the family
-model (60% core, 30% accessory, 10% singletons, 5-30% divergence), k = 6 from
-the k rule; a step rebuilds all ten k-mer dictionaries from residues already
-in HBM and computes best hits in both directions plus BBH for all 45 genome
+Headline workload (default): 50 synthetic protein genomes x U{3000..5000} genes
+from the family model with 5% paralog copies (exact and near ties), k = 7 from
+the k rule.  A step rebuilds all fifty k-mer dictionaries from residues already
+in HBM and computes best hits in both directions plus BBH for all 1225 genome
 pairs in one plan launch.  value = gene pairs compared (sum of |A||B| over the
-45 pairs) per second.
+pairs) per second.  The same JSON line carries the latency half of the metric:
+the serving workload (200 resident genomes of 4000 genes, 2000 Poisson arrivals
+at 0.8 of the closed-loop capacity, each compared with every resident), with
+its p50/p99 per-genome latency and genomes/s.
 
 Printed: one JSON line with the metric, a roofline entry for the dominant
-kernel (HIP events recorded by the library around that kernel on its own
-stream) and the CPU oracle timed on a bounded sample of the same workload.
+kernel plus the pair path and the whole step (HIP events recorded by the
+library around the kernels on their own stream), and the CPU oracle timed on
+a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -36,9 +40,10 @@ def parse():
     p.add_argument("--kernel", default="join", help="kernel for the roofline entry (join, bucket, tile_count, "
                                                     "tile_write, bbh)")
     p.add_argument("--cpu-rows", type=int, default=None,
-                   help="rows per direction per pair in the CPU-oracle sample (default: 384 amino-acid, 128 nucleotide "
-                        "rows, about 15 s of oracle work)")
+                   help="rows per direction per sampled pair in the dense CPU-oracle sample (default: 160 on the "
+                        "50-genome workload, 384 amino-acid / 128 nucleotide rows on the 10 x 3000 one)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-latency", action="store_true", help="skip the serving run that gives p50/p99 latency")
     p.add_argument("--breakdown", action="store_true", help="also time every kernel group (extra launches)")
     p.add_argument("--calibrate-copy", action="store_true", help="only run a copy of known size (counter calibration)")
     p.add_argument("--tune", action="store_true", help="pick tile shapes and join splits with the autotuner first")
@@ -53,22 +58,23 @@ def parse():
     p.add_argument("--theta", default=None, help="length filter as NUM/DEN (Eq. length_threshold); off by default")
     p.add_argument("--tau", default=None, help="directional filter as NUM/DEN (Eq. directional_jaccard); off by default")
     p.add_argument("--alphabet", choices=("aa", "nt"), default="aa",
-                   help="allpairs: amino-acid genomes (default) or nucleotide genomes (genes 3x as long, k by the "
-                        "rule with |alphabet| = 4)")
-    p.add_argument("--workload", choices=("allpairs", "large", "batched", "serving"), default="allpairs",
-                   help="allpairs: the 10 x 3000 metric (default); large: 50 genomes x U{3000..5000} genes with "
-                        "paralog copies, all 1225 pairs in one launch; batched: independent instances in waves, one "
-                        "graph-captured launch per wave, against one plan per genome pair; serving: "
-                        "resident dictionaries and a Poisson stream of arriving genomes")
+                   help="amino-acid genomes (default) or nucleotide genomes (genes 3x as long, k by the rule with "
+                        "|alphabet| = 4)")
+    p.add_argument("--workload", choices=("large", "allpairs", "batched", "serving"), default="large",
+                   help="large: 50 genomes x U{3000..5000} genes with paralog copies, all 1225 pairs in one launch, "
+                        "plus the serving run for latency (default); allpairs: 10 genomes x 3000 genes, 45 pairs; "
+                        "batched: independent instances in waves, one graph-captured launch per wave, against one "
+                        "plan per genome pair; serving: resident dictionaries and a Poisson stream of arriving genomes")
     p.add_argument("--instances", type=int, default=64, help="batched: instances (of the 400-instance workload)")
     p.add_argument("--wave-genomes", type=int, default=256, help="batched: genomes per wave")
     p.add_argument("--per-pair-sample", type=int, default=256, help="batched: pairs timed with one plan each")
     p.add_argument("--residents", type=int, default=200, help="serving: resident genomes")
     p.add_argument("--resident-genes", type=int, default=4000, help="serving: genes per resident")
-    p.add_argument("--arrivals", type=int, default=400, help="serving: arriving genomes (of the 2000-arrival stream)")
+    p.add_argument("--arrivals", type=int, default=2000, help="serving: arriving genomes (of the 2000-arrival stream)")
     p.add_argument("--load", type=float, default=0.8, help="serving: offered load as a fraction of closed-loop capacity")
     p.add_argument("--slots", type=int, default=8, help="serving: concurrent request slots")
     p.add_argument("--budget-gb", type=float, default=32.0, help="serving: HBM budget for requests in flight")
+    p.add_argument("--serve-colmax", action="store_true", help="serving: column maxima for the residents' best hits")
     return p.parse_args()
 
 
@@ -84,44 +90,140 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kernel: str, pairs, entries, res_bh_nnz, res_bbh, genes) -> float:
-    """Bytes the method itself needs per launch, for the kernel's share of the path.
+# ------------------------------------------------------------------ algorithmic bytes
 
-    join: each unordered genome pair reads both genomes' k-mer entries once, a u64 code
-    and a u32 multiplicity each (12 bytes per entry).  tile_write: the best-hit output,
-    16 bytes per entry (column, two integers, row bookkeeping) plus 8 bytes per row.
-    bbh: 16 bytes per BBH pair.  Other kernels move only intermediate data."""
+def input_bytes(pairs, entries) -> float:
+    """Per unordered genome pair (A, B), each genome's k-mer entries read once: a u64 code and a
+    u32 multiplicity, 12 bytes per entry (the join's share of the path)."""
+    return float(sum(12 * (entries[i] + entries[j]) for i, j in pairs))
+
+
+def output_bytes(pairs, genes, bh_nnz, bbh_n) -> float:
+    """The outputs of the path: 16 bytes per best hit (row bookkeeping, column, num, den), 16 per
+    BBH pair and 8 per gene of each pair's genomes (row pointers of both directions)."""
+    return float(16 * bh_nnz + 16 * bbh_n + 8 * sum(genes[i] + genes[j] for i, j in pairs))
+
+
+def build_bytes(residues, entries) -> float:
+    """Dictionary build per genome: the residues read, the multiplicity vectors written (12 bytes
+    per entry), read again and written out as the inverted index with its join keys (20 bytes)."""
+    return float(sum(r + 12 * e + 12 * e + 20 * e for r, e in zip(residues, entries)))
+
+
+def kernel_bytes(kernel: str, pairs, entries, genes, bh_nnz, bbh_n) -> float:
     if kernel == "join":
-        return float(sum(12 * (entries[i] + entries[j]) for i, j in pairs))
+        return input_bytes(pairs, entries)
     if kernel == "tile_write":
-        return float(16 * res_bh_nnz + 8 * sum(genes[i] + genes[j] for i, j in pairs))
+        return float(16 * bh_nnz + 8 * sum(genes[i] + genes[j] for i, j in pairs))
     if kernel == "bbh":
-        return float(16 * res_bbh)
+        return float(16 * bbh_n)
     return 0.0
 
 
-def cpu_baseline(ds, k, rows_per_dir):
-    """The oracle as it stands, on a bounded sample: multiplicity vectors of every genome, then
-    best hits of rows_per_dir evenly spaced rows in each direction of every pair."""
+def _frac(nbytes, ms):
+    gbs = nbytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+    return round(gbs, 2), round(gbs / HBM_PEAK_GBS, 5)
+
+
+# ------------------------------------------------------------------ CPU baseline
+
+def cpu_info() -> dict:
+    model, sockets, cores = None, set(), set()
+    try:
+        phys = None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "model name" and model is None:
+                    model = val
+                elif key == "physical id":
+                    phys = val
+                    sockets.add(val)
+                elif key == "core id":
+                    cores.add((phys, val))
+    except OSError:
+        pass
+    import oracle
+
+    return {"model": model, "sockets": len(sockets) or None, "physical_cores": len(cores) or None,
+            "logical_cpus": os.cpu_count(), "threads_used": oracle.default_threads()}
+
+
+def _evenly(n, m):
+    import numpy as np
+
+    return np.unique(np.linspace(0, n - 1, min(m, n)).astype(np.uint32))
+
+
+def cpu_baseline(ds, k, rows_per_dir, full_workload: bool):
+    """The oracle as it stands, on the host cores.
+
+    dense: the oracle that merges the multiplicity vectors of every gene pair (the paper's
+    per-gene-pair similarity, rows handed to a pool of threads as Alg. 2's units of work), on
+    ``rows_per_dir`` evenly spaced rows per direction of a seeded sample of pairs (all pairs of
+    the 10 x 3000 workload, 32 of the 50-genome one); its rate gives a labelled extrapolation to
+    the whole workload.  One whole pair (both directions and BBH) is timed as well, and a
+    single-thread rate for comparison with per-thread CPU figures.  sparse: the oracle that
+    visits only gene pairs sharing a k-mer, on every pair of the workload (BH both ways + BBH)."""
     import numpy as np
 
     import oracle
 
     threads = oracle.default_threads()
     t0 = time.perf_counter()
-    og = [oracle.OracleGenome(g, k) for g in ds.genomes]
+    og = oracle.genomes(ds.genomes, k, threads=threads)
+    mv_s = time.perf_counter() - t0
+    pairs = ds.pairs()
+    if full_workload and len(pairs) > 32:
+        rng = np.random.default_rng(2510236790)
+        pick = sorted(int(x) for x in rng.choice(len(pairs), 32, replace=False))
+    else:
+        pick = list(range(len(pairs)))
     gene_pairs = 0
-    for i, j in ds.pairs():
-        for q, t in ((og[i], og[j]), (og[j], og[i])):
-            rows = np.linspace(0, q.n - 1, min(rows_per_dir, q.n)).astype(np.uint32)
-            oracle.bh(q, t, rows=rows, threads=threads)
-            gene_pairs += len(rows) * t.n
-    dt = time.perf_counter() - t0
-    return {"value": gene_pairs / dt, "unit": "gene-pair similarities/s", "cores": threads, "kind": "oracle",
-            "sample": f"multiplicity vectors of all {len(og)} genomes plus best hits of {rows_per_dir} evenly "
-                      f"spaced rows per direction of each of the {len(ds.pairs())} pairs "
-                      f"({gene_pairs} gene pairs, {dt:.1f} s); BBH on the sampled rows is not included",
-            "seconds": dt}
+    t0 = time.perf_counter()
+    for t in pick:
+        i, j = pairs[t]
+        for q, tt in ((og[i], og[j]), (og[j], og[i])):
+            rows = _evenly(q.n, rows_per_dir)
+            oracle.bh(q, tt, rows=rows, threads=threads)
+            gene_pairs += len(rows) * tt.n
+    dense_s = time.perf_counter() - t0
+    rate = gene_pairs / dense_s
+    # one whole pair, both directions and BBH: the two smallest genomes
+    small = sorted(range(len(og)), key=lambda x: og[x].n)[:2]
+    a, b = og[small[0]], og[small[1]]
+    t0 = time.perf_counter()
+    ab = oracle.bh(a, b, threads=threads)
+    ba = oracle.bh(b, a, threads=threads)
+    nbbh = len(oracle.bbh(ab, ba).a)
+    pair_s = time.perf_counter() - t0
+    # one thread
+    rows = _evenly(og[0].n, 48)
+    t0 = time.perf_counter()
+    oracle.bh(og[0], og[1], rows=rows, threads=1)
+    one_s = time.perf_counter() - t0
+    one_rate = len(rows) * og[1].n / one_s
+    # the sparse oracle on the whole workload
+    t0 = time.perf_counter()
+    oracle.all_pairs_sparse(og, pairs, threads=threads)
+    sparse_s = time.perf_counter() - t0
+    total_gp = ds.gene_pairs()
+    return {"value": round(rate, 1), "unit": "gene-pair similarities/s", "cores": threads, "kind": "oracle",
+            "sample": f"dense oracle (every gene pair's multiplicity vectors merged, rows over a thread pool): "
+                      f"{rows_per_dir} evenly spaced rows per direction of {len(pick)} seeded pairs of the "
+                      f"{len(pairs)} ({gene_pairs} gene pairs, {dense_s:.1f} s); multiplicity vectors of every "
+                      f"genome built first ({mv_s:.1f} s, not in the rate)",
+            "seconds": round(dense_s, 2),
+            "whole_pair_with_bbh": {"genes": [a.n, b.n], "seconds": round(pair_s, 2), "bbh_pairs": nbbh,
+                                    "gene_pairs_per_s": round(2 * a.n * b.n / pair_s, 1)},
+            "single_thread_gene_pairs_per_s": round(one_rate, 1),
+            "extrapolated_whole_workload_s": {"value": round(total_gp * 2 / rate, 1),
+                                              "label": "extrapolation: both directions of every gene pair of the "
+                                                       "workload at the sampled dense rate, BBH excluded"},
+            "sparse_oracle": {"seconds": round(sparse_s, 2), "gene_pairs_per_s": round(total_gp / sparse_s, 1),
+                              "scope": f"all {len(pairs)} pairs, BH both ways + BBH, after the multiplicity vectors"},
+            "host": cpu_info()}
 
 
 def calibrate_copy(mib: int = 1024) -> None:
@@ -287,6 +389,8 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------------ serving
+
 _SERVING = None
 
 
@@ -294,14 +398,10 @@ def _gen_arrival(j):
     return _SERVING.arrival(j)
 
 
-def run_serving(args):
-    """Workload 5 sample: resident dictionaries built once; arriving genomes are submitted to
-    pdp_server at Poisson times at the offered load (a fraction of the closed-loop capacity
-    measured first); latency = completion - submission on the server's clock.  Each request
-    builds its dictionary and computes BH both ways + BBH against every resident."""
+def prepare_serving(args):
+    """Resident genomes and the first args.arrivals arriving genomes of the serving workload,
+    generated on the host (arrivals in forked workers, before anything touches the GPU)."""
     global _SERVING
-    import numpy as np
-
     from synth import serving_workload
 
     t0 = time.perf_counter()
@@ -309,15 +409,21 @@ def run_serving(args):
                           rate_per_s=1.0)
     _SERVING = wl
     n = min(args.arrivals, 2000)
-    warm = min(16, n)
     arrivals = _pool_map(_gen_arrival, list(range(n)))
-    gen_s = time.perf_counter() - t0
+    return wl, arrivals, time.perf_counter() - t0
 
+
+def serve_stream(args, wl, arrivals):
+    """Resident dictionaries built once; the arrivals are submitted to pdp_server at Poisson
+    times at the offered load (a fraction of the closed-loop capacity measured first on the first
+    arrivals); latency = completion - submission on the server's clock.  Each request builds its
+    dictionary and computes BH both ways + BBH against every resident."""
     import torch
 
     import paper_2510_23679_amd as pdp
 
-    torch.cuda.set_device(0)
+    n = len(arrivals)
+    warm = min(16, n)
     k = pdp.k_rule(wl.residents.total_residues())
     devs = [pdp.DeviceGenome.of(g) for g in wl.residents.genomes]
     batch = pdp.DictionaryBatch(devs, k)
@@ -326,7 +432,7 @@ def run_serving(args):
     batch.check_status()
     res_genes = sum(d.n_genes for d in batch.dicts)
     srv = pdp.Server(batch.dicts, int(args.budget_gb * (1 << 30)), slots=args.slots,
-                     prm=pdp.params(tile_rows=args.tile_rows))
+                     prm=pdp.params(tile_rows=args.tile_rows, colmax=args.serve_colmax))
 
     def drain(want, done):
         while len(done) < want:
@@ -361,45 +467,70 @@ def run_serving(args):
         stats = srv.stats()
     finally:
         srv.close()
+        del srv, batch, devs
+        torch.cuda.empty_cache()
     bad = [d.code for d in done.values() if d.code != 0]
     if bad:
         raise SystemExit(f"{len(bad)} requests failed, first code {bad[0]}")
     lat = [(d.done_us - d.submit_us) / 1e3 for d in done.values()]
     svc = [(d.done_us - d.admit_us) / 1e3 for d in done.values()]
-    gp = sum(int(g.n_genes) * res_genes for g in arrivals[:n])
+    wait = [(d.admit_us - d.submit_us) / 1e3 for d in done.values()]
+    gp = sum(int(g.n_genes) * res_genes for g in arrivals)
+    return {"genomes_per_s": round(n / wall, 2), "p50_ms": round(_pctl(lat, 50), 3), "p99_ms": round(_pctl(lat, 99), 3),
+            "max_ms": round(max(lat), 3), "service_p50_ms": round(_pctl(svc, 50), 3),
+            "service_p99_ms": round(_pctl(svc, 99), 3), "admission_wait_p99_ms": round(_pctl(wait, 99), 3),
+            "closed_loop_genomes_per_s": round(capacity, 2), "offered_rate_per_s": round(lam, 2),
+            "gene_pairs_per_s": round(gp / wall, 1), "arrivals": n, "retries": int(stats.retries),
+            "attempts_max": int(max(d.attempts for d in done.values())),
+            "join_two_passes": sum(1 for d in done.values() if d.flags & pdp.PDP_STATUS_TWO_PASS),
+            "peak_inflight": int(stats.peak_inflight), "peak_used_gb": round(stats.peak_used_bytes / 2 ** 30, 2),
+            "workload": f"serving: {len(wl.residents.genomes)} resident genomes x "
+                        f"{wl.residents.genomes[0].n_genes} genes (k = {k}), first {n} of 2000 Poisson arrivals "
+                        f"(U{{1000..6000}} genes drawn from resident families), offered load {args.load} of the "
+                        f"closed-loop capacity, {args.slots} slots, {args.budget_gb} GB budget",
+            "note": "latency = completion - submission, including admission wait, the host-to-device copy of the "
+                    "arriving genome and the copy of its results to host memory"}
+
+
+def run_serving(args):
+    wl, arrivals, gen_s = prepare_serving(args)
+    import torch
+
+    torch.cuda.set_device(0)
+    lat = serve_stream(args, wl, arrivals)
     out = {"metric": "served genomes/sec and p50/p99 per-genome latency (BH+BBH against every resident, 1 GPU)",
-           "value": round(n / wall, 2), "unit": "genomes/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u32",
-           "data": "synthetic",
-           "config": {"workload": f"serving: {args.residents} resident genomes x {args.resident_genes} genes, first "
-                                  f"{n} of 2000 Poisson arrivals (U{{1000..6000}} genes, drawn from resident families)",
-                      "k": k, "slots": args.slots, "budget_gb": args.budget_gb, "offered_load": args.load},
-           "latency_ms": {"p50": round(_pctl(lat, 50), 3), "p99": round(_pctl(lat, 99), 3),
-                          "max": round(max(lat), 3)},
-           "service_ms": {"p50": round(_pctl(svc, 50), 3), "p99": round(_pctl(svc, 99), 3)},
-           "closed_loop_genomes_per_s": round(capacity, 2), "offered_rate_per_s": round(lam, 2),
-           "gene_pairs_per_s": round(gp / wall, 1), "retries": int(stats.retries),
-           "join_two_passes": sum(1 for d in done.values() if d.flags & pdp.PDP_STATUS_TWO_PASS),
-           "peak_inflight": int(stats.peak_inflight), "peak_used_gb": round(stats.peak_used_bytes / 2 ** 30, 2),
-           "host_generation_s": round(gen_s, 1),
-           "note": "latency includes the host-to-device copy of each arriving genome"}
+           "value": lat["genomes_per_s"], "unit": "genomes/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u32",
+           "data": "synthetic", "config": {"workload": lat.pop("workload"), "slots": args.slots,
+                                            "budget_gb": args.budget_gb, "offered_load": args.load,
+                                            "column_maxima": bool(args.serve_colmax)},
+           "latency": lat, "host_generation_s": round(gen_s, 1)}
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------------ all pairs
+
 def main():
     args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: genome pairs are independent and "
+                                   "would shard across GPUs, but no multi-GPU path is built",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
         return
-    if args.workload not in ("allpairs", "large") and args.gpus == 1:
-        (run_batched if args.workload == "batched" else run_serving)(args)
+    if args.workload == "batched":
+        run_batched(args)
         return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; genome pairs are independent and "
-                                   "would shard across GPUs, but no multi-GPU path is implemented",
-                          "n_gpus": args.gpus}), flush=True)
-        sys.exit(2)
+    if args.workload == "serving":
+        run_serving(args)
+        return
 
-    import numpy as np
+    large = args.workload == "large"
+    serving = None
+    if large and not args.no_latency:
+        serving = prepare_serving(args)  # forks workers: before anything touches the GPU
+
     import torch
 
     import paper_2510_23679_amd as pdp
@@ -408,7 +539,6 @@ def main():
 
     torch.cuda.set_device(0)
     nt = args.alphabet == "nt"
-    large = args.workload == "large"
     ds = make_config(3 if large else 2, alphabet=args.alphabet)
     k = pdp.k_rule(ds.total_residues(), 4 if nt else 20)
     pairs = ds.pairs()
@@ -417,7 +547,7 @@ def main():
 
     # residues and offsets resident in HBM before anything is timed
     dev = [pdp.DeviceGenome.of(g) for g in ds.genomes]
-    batch = pdp.DictionaryBatch(dev, k)  # all ten dictionaries in one pdp_dict_build_many
+    batch = pdp.DictionaryBatch(dev, k)  # every dictionary in one pdp_dict_build_many
     dicts = batch.dicts
     batch.build()
     tasks = pdp.all_pairs_tasks(dicts)
@@ -440,12 +570,9 @@ def main():
         d.check_status()
     stream = torch.cuda.current_stream()
 
-    def step():
+    for _ in range(args.warmup):
         batch.build()
         runner.launch()
-
-    for _ in range(args.warmup):
-        step()
     torch.cuda.synchronize()
     code, needed, where = pdp.read_status(runner.status)
     if code != 0:
@@ -478,10 +605,20 @@ def main():
 
     res = runner.results()
     entries = [int(d.host()["mv_ptr"][-1]) for d in dicts]
+    residues = [int(g.n_residues) for g in ds.genomes]
     bh_nnz = int(res.bh[0][-1])
     bbh_n = int(res.bbh[0][-1]) if res.bbh is not None else 0
 
-    breakdown = {"dictionary_build_ms": round(dict_ms, 4)}
+    # the whole plan launch (every kernel of the pair path), timed after the timed steps
+    reps = 5
+    runner.plan.timer_start(B.KERNELS["all"], reps)
+    for _ in range(reps):
+        runner.launch()
+    path_ms, path_n = runner.plan.timer_read()
+    runner.plan.timer_stop()
+    path_ms /= max(path_n, 1)
+
+    breakdown = {"dictionary_build_ms": round(dict_ms, 4), "pair_path_ms": round(path_ms, 4)}
     if args.breakdown:
         for name, kid in B.KERNELS.items():
             runner.plan.timer_start(kid, 5)
@@ -491,35 +628,39 @@ def main():
             runner.plan.timer_stop()
             breakdown[f"{name}_ms"] = round(ms / max(n, 1), 4)
         torch.cuda.synchronize()
-        # phase (c): gene families from the BBH of the last launch (not part of the step)
-        base = np.concatenate([[0], np.cumsum(genes)]).astype(np.int64)
-        node_a, node_b = [base[i] for i, _ in pairs], [base[j] for _, j in pairs]
-        runner.families(node_a, node_b, int(base[-1]))
-        fe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        fe[0].record(stream)
-        for _ in range(5):
-            labels = runner.families(node_a, node_b, int(base[-1]))
-        fe[1].record(stream)
-        torch.cuda.synchronize()
-        breakdown["families_ms"] = round(fe[0].elapsed_time(fe[1]) / 5, 4)
-        breakdown["families"] = int(torch.unique(labels).numel())
 
     avg_kernel_ms = kern_ms / max(kern_n, 1)
-    alg = algorithmic_bytes(args.kernel, pairs, entries, bh_nnz, bbh_n, genes)
-    achieved = alg / (avg_kernel_ms / 1e3) / 1e9 if avg_kernel_ms > 0 else 0.0
-    traffic = None
+    alg = kernel_bytes(args.kernel, pairs, entries, genes, bh_nnz, bbh_n)
+    achieved, kfrac = _frac(alg, avg_kernel_ms)
+    path_bytes = input_bytes(pairs, entries) + output_bytes(pairs, genes, bh_nnz, bbh_n)
+    step_bytes = path_bytes + build_bytes(residues, entries)
+    path_gbs, path_frac = _frac(path_bytes, path_ms)
+    step_gbs, step_frac = _frac(step_bytes, ms_per_step)
+    traffic, measured = None, None
+    wl_key = ("large" if large else "allpairs") + ("_nt" if nt else "")
     try:
         with open(args.traffic) as f:
             tr = json.load(f)
-        kernels = tr.get("workloads", {}).get(args.alphabet, {}).get("kernels", {})
+        kernels = tr.get("workloads", {}).get(wl_key, {}).get("kernels", {})
         if tr.get("source_hash") == source_hash() and args.kernel in kernels and not (args.two_pass or args.colmax):
             traffic = kernels[args.kernel]["hbm_bytes_per_launch"]
+            measured = dict(zip(("achieved", "frac"), _frac(traffic, avg_kernel_ms)))
     except (OSError, ValueError):
         pass
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": args.kernel,
-                "kernel_ms": round(avg_kernel_ms, 5), "algorithmic_bytes": alg, "launches_timed": kern_n,
-                "join_layout": "two passes" if two_pass else "one pass"}
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kfrac,
+                "traffic": traffic, "kernel": args.kernel, "kernel_ms": round(avg_kernel_ms, 5),
+                "algorithmic_bytes": alg,
+                "bytes_scope": "join: 12 bytes per k-mer entry of both genomes of every pair (the input term)",
+                "launches_timed": kern_n, "join_layout": "two passes" if two_pass else "one pass",
+                "measured": measured,
+                "path": {"achieved": path_gbs, "frac": path_frac, "ms": round(path_ms, 4),
+                         "algorithmic_bytes": path_bytes,
+                         "scope": "every kernel of the plan launch; inputs + outputs (16 B per best hit and per BBH "
+                                  "pair, 8 B per gene of each pair)"},
+                "step": {"achieved": step_gbs, "frac": step_frac, "ms": round(ms_per_step, 4),
+                         "algorithmic_bytes": step_bytes,
+                         "scope": "the whole step: the pair path's bytes + the dictionary build's (residues, "
+                                  "multiplicity vectors written and read, index written)"}}
 
     out = {
         "metric": METRIC,
@@ -540,7 +681,7 @@ def main():
                                + f"), {len(pairs)} genome pairs, dictionary build included",
                    "alphabet": "nucleotide" if nt else "amino acid",
                    "genomes": len(genes), "genes_per_genome": genes[0] if not large else [min(genes), max(genes)],
-                   "k": k, "genome_pairs": len(pairs),
+                   "genes": int(sum(genes)), "k": k, "genome_pairs": len(pairs),
                    "gene_pairs": gene_pairs, "kmer_entries": int(sum(entries)), "best_hits": bh_nnz, "bbh_pairs": bbh_n,
                    "filters": {"theta": args.theta, "tau": args.tau}, "column_maxima": bool(args.colmax)},
         "roofline": roofline,
@@ -549,8 +690,15 @@ def main():
                                                          "tile_rows": args.tile_rows}),
         "breakdown": breakdown,
     }
+    del runner, res, batch, dicts, dev
+    torch.cuda.empty_cache()
+    if serving is not None:
+        wl, arrivals, gen_s = serving
+        lat = serve_stream(args, wl, arrivals)
+        lat["host_generation_s"] = round(gen_s, 1)
+        out["latency"] = lat
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(ds, k, args.cpu_rows or (16 if large else (128 if nt else 384)))
+        cb = cpu_baseline(ds, k, args.cpu_rows or (160 if large else (128 if nt else 384)), large)
         cb["gpu_over_cpu"] = round(value / cb["value"], 1)
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)

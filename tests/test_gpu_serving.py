@@ -102,21 +102,25 @@ def test_budget_rejects_oversized_request(workload):
 
 
 def test_budget_admits_one_request_at_a_time(workload):
-    # a budget that fits the largest request but no two requests: six requests submitted at
-    # once on four slots wait for memory over many polls.  Waiting is no attempt: each runs
+    # a budget that fits the largest request but no two of the requests submitted: they are
+    # submitted at once on four slots and wait for memory over many polls.  Waiting is no attempt: each runs
     # once, its admission is stamped when its memory is placed (after its submission and after
     # the previous request's completion), and its results are the oracle's.
     wl, residents, arrivals = workload
-    say("serving: budget for one request at a time, 6 requests on 4 slots")
     foot = []
     for j, g in enumerate(arrivals):  # each request's footprint, alone
         _, st = run_server(residents, [g], slots=1)
         foot.append(int(st.peak_used_bytes))
     budget = max(foot) + 256
-    assert 2 * min(foot) > budget, "two requests must not fit the budget together"
+    # the requests of which no two fit together
+    big = [j for j in range(len(arrivals)) if 2 * foot[j] > budget]
+    assert len(big) >= 3
+    say("serving: budget for one request at a time,", len(big), "requests on 4 slots")
+    arrivals = [arrivals[j] for j in big]
     out, stats = run_server(residents, arrivals, slots=4, budget=budget)
-    assert stats.completed == 6 and stats.peak_inflight == 1 and stats.peak_used_bytes <= budget
-    done = sorted((out[j][0] for j in range(6)), key=lambda d: d.admit_us)
+    n = len(arrivals)
+    assert stats.completed == n and stats.peak_inflight == 1 and stats.peak_used_bytes <= budget
+    done = sorted((out[j][0] for j in range(n)), key=lambda d: d.admit_us)
     for prev, d in zip([None] + done[:-1], done):
         assert d.code == 0 and d.attempts == 1
         assert d.admit_us >= d.submit_us and d.done_us >= d.admit_us
