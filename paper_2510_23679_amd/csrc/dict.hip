@@ -177,6 +177,63 @@ __device__ __forceinline__ bool gene_ok(const DevBuild &B, uint32_t g, uint32_t 
     return true;
 }
 
+// Amino-acid k-mers of 7 letters take 35 bits as 5-bit codes but only 31 as base-20 values
+// (20^7 < 2^31), and both order k-mers alike (letter by letter, first letter most
+// significant).  For such genomes the multiplicity-vector sorts run on 32-bit base-20 keys, and
+// each distinct key is turned back into its 5-bit code when the vector is written.
+__device__ __forceinline__ bool base20_keys(const DevBuild &B) { return B.bits == 5u && B.k == 7u; }
+constexpr uint32_t kPow20_6 = 64000000u;  // 20^(7-1): the weight of a 7-mer's first letter
+
+__device__ __forceinline__ uint64_t base20_to_code(uint32_t v, uint32_t k) {
+    uint64_t c = 0;
+    for (uint32_t i = 0; i < k; ++i) {  // digits from the last letter on
+        const uint32_t q = v / 20u;
+        c |= static_cast<uint64_t>(v - q * 20u) << (5u * i);
+        v = q;
+    }
+    return c;
+}
+
+// The keys of windows p0 .. p0+E-1 (those below nw; the rest sort last) from the gene's symbols:
+// 5-bit codes, or base-20 values when B20; each window's key is the previous one shifted by one
+// letter, so the first k-1 letters are read once.
+template <uint32_t E, typename K, bool B20>
+__device__ __forceinline__ void window_keys(const uint8_t *sym, uint32_t p0, uint32_t nw, uint32_t k, uint32_t bits,
+                                            K (&key)[E]) {
+    if constexpr (B20) {
+        uint32_t c = 0;  // base-20 value of the k-1 letters after the window's first
+        if (p0 < nw)
+            for (uint32_t j = 0; j + 1 < k; ++j) c = c * 20u + sym[p0 + j];
+#pragma unroll
+        for (uint32_t e = 0; e < E; ++e) {
+            const uint32_t p = p0 + e;
+            uint32_t full = ~0u;
+            if (p < nw) {
+                full = c * 20u + sym[p + k - 1];
+                c = full - sym[p] * kPow20_6;
+            }
+            key[e] = static_cast<K>(full);
+        }
+    } else {
+        const uint64_t mask = (1ull << (bits * k)) - 1ull;  // bits * k <= 62
+        uint64_t c = 0;
+        if (p0 < nw)
+            for (uint32_t j = 0; j + 1 < k; ++j) c = (c << bits) | sym[p0 + j];
+#pragma unroll
+        for (uint32_t e = 0; e < E; ++e) {
+            const uint32_t p = p0 + e;
+            if (p < nw) c = ((c << bits) | sym[p + k - 1]) & mask;
+            key[e] = p < nw ? static_cast<K>(c) : static_cast<K>(~0ull);  // past the windows: sorts last
+        }
+    }
+}
+
+template <bool B20, typename K>
+__device__ __forceinline__ uint64_t key_code(K key, uint32_t k) {
+    if constexpr (B20) return base20_to_code(static_cast<uint32_t>(key), k);
+    else return static_cast<uint64_t>(key);
+}
+
 constexpr uint32_t kMvWaveEMax = 16;
 constexpr uint32_t kMvWaveCap = kWave * kMvWaveEMax;  // windows a wave sorts in registers
 constexpr uint32_t kMvWaves = kMvThreads / kWave;
@@ -186,25 +243,15 @@ constexpr uint32_t kMvWaves = kMvThreads / kWave;
 // heads ranked by a wave scan; head positions in LDS give the run lengths.  sym holds the
 // gene's residue symbols, hp kWave*E+1 slots.
 // K: the key type, 32 bits when the codes fit (bits * k <= 32), halving the shuffles.
-template <uint32_t E, typename K>
+// B20: base-20 keys (base20_keys).
+template <uint32_t E, typename K, bool B20 = false>
 __device__ __forceinline__ void mv_wave_gene(const DevBuild &B, const uint8_t *sym, uint16_t *hp, uint64_t o,
                                              uint32_t nw, uint32_t *cnt_out) {
     const uint32_t lane = lane_id();
-    const uint32_t k = B.k, bits = B.bits;
-    const uint64_t mask = (1ull << (bits * k)) - 1ull;  // bits * k <= 62
+    const uint32_t k = B.k;
     K key[E];
-    // the lane's windows p0 .. p0+E-1 are consecutive: the first k-1 letters once, then one
-    // letter per window
-    const uint32_t p0 = lane * E;
-    uint64_t c = 0;
-    if (p0 < nw)
-        for (uint32_t j = 0; j + 1 < k; ++j) c = (c << bits) | sym[p0 + j];
-#pragma unroll
-    for (uint32_t e = 0; e < E; ++e) {
-        const uint32_t p = p0 + e;
-        if (p < nw) c = ((c << bits) | sym[p + k - 1]) & mask;
-        key[e] = p < nw ? static_cast<K>(c) : static_cast<K>(~0ull);  // past the windows: sorts last
-    }
+    // the lane's windows p0 .. p0+E-1 are consecutive
+    window_keys<E, K, B20>(sym, lane * E, nw, k, B.bits, key);
     wave_bitonic_sort<E, K>(key);
     const K before = __shfl_up(key[E - 1], 1, kWave);
     uint32_t hmask = 0, nh = 0;
@@ -230,7 +277,7 @@ __device__ __forceinline__ void mv_wave_gene(const DevBuild &B, const uint8_t *s
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) {
         if (!((hmask >> e) & 1u)) continue;
-        slot_code[r] = key[e];
+        slot_code[r] = key_code<B20>(key[e], k);
         slot_cnt[r] = static_cast<uint32_t>(hp[r + 1]) - hp[r];
         ++r;
     }
@@ -239,8 +286,8 @@ __device__ __forceinline__ void mv_wave_gene(const DevBuild &B, const uint8_t *s
 
 // Longer genes go to lists by size: counters[0] / long_list past kMvSortCap windows,
 // counters[c] / mid_list + (c - 1) * stride for k_mv_mid<8 << (c - 1)>, c = 1, 2, 3.
-// NARROW: every genome of the build has codes of at most 32 bits (a separate instance without
-// the 64-bit path, which needs fewer registers).
+// NARROW: every genome of the build sorts 32-bit keys (5-bit codes of at most 32 bits, or
+// base-20 values): a separate instance without the 64-bit path, which needs fewer registers.
 template <bool NARROW>
 __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restrict__ table, uint32_t n_genomes,
                                                         uint32_t total_genes, uint32_t *__restrict__ dcnt,
@@ -290,10 +337,14 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restri
     }
     wave_lds_sync();
     uint32_t total;
-    if (NARROW || B.bits * B.k <= 32) {  // uniform per wave
+    if (B.bits * B.k <= 32) {  // uniform per wave
         if (nw <= kWave * 4) mv_wave_gene<4, uint32_t>(B, sym, hp_all[w], o, nw, &total);
         else if (nw <= kWave * 8) mv_wave_gene<8, uint32_t>(B, sym, hp_all[w], o, nw, &total);
         else mv_wave_gene<16, uint32_t>(B, sym, hp_all[w], o, nw, &total);
+    } else if (base20_keys(B)) {
+        if (nw <= kWave * 4) mv_wave_gene<4, uint32_t, true>(B, sym, hp_all[w], o, nw, &total);
+        else if (nw <= kWave * 8) mv_wave_gene<8, uint32_t, true>(B, sym, hp_all[w], o, nw, &total);
+        else mv_wave_gene<16, uint32_t, true>(B, sym, hp_all[w], o, nw, &total);
     } else {
         if constexpr (!NARROW) {
             if (nw <= kWave * 4) mv_wave_gene<4, uint64_t>(B, sym, hp_all[w], o, nw, &total);
@@ -362,7 +413,7 @@ __device__ __forceinline__ void block_bitonic_sort(K (&key)[E], K *xch) {
 // run heads ranked by a work-group scan give the multiplicity vector.  The symbols, the
 // sort's exchange area and the head positions share one LDS array.
 // One gene of k_mv_mid: len letters at offset o, nw <= kMvThreads * E windows; K as in the wave kernel.
-template <uint32_t E, typename K>
+template <uint32_t E, typename K, bool B20 = false>
 __device__ __forceinline__ void mid_gene(const DevBuild &B, uint32_t G, uint64_t o, uint32_t len, uint32_t nw,
                                          uint64_t *xch64, K *s_last, uint32_t *tmp, uint32_t *__restrict__ dcnt) {
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
@@ -391,19 +442,7 @@ __device__ __forceinline__ void mid_gene(const DevBuild &B, uint32_t G, uint64_t
     }
     __syncthreads();
     K key[E];
-    {
-        const uint64_t mask = (1ull << (bits * k)) - 1ull;
-        const uint32_t p0 = tid * E;
-        uint64_t c = 0;
-        if (p0 < nw)
-            for (uint32_t j = 0; j + 1 < k; ++j) c = (c << bits) | sym[p0 + j];
-#pragma unroll
-        for (uint32_t e = 0; e < E; ++e) {
-            const uint32_t p = p0 + e;
-            if (p < nw) c = ((c << bits) | sym[p + k - 1]) & mask;
-            key[e] = p < nw ? static_cast<K>(c) : static_cast<K>(~0ull);  // past the windows: sorts last
-        }
-    }
+    window_keys<E, K, B20>(sym, tid * E, nw, k, bits, key);
     __syncthreads();  // the symbols are read before the sort overwrites them
     block_bitonic_sort<E, K>(key, xch);
     if (lane == kWave - 1) s_last[w] = key[E - 1];
@@ -433,7 +472,7 @@ __device__ __forceinline__ void mid_gene(const DevBuild &B, uint32_t G, uint64_t
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) {
         if (!((hmask >> e) & 1u)) continue;
-        slot_code[r] = key[e];
+        slot_code[r] = key_code<B20>(key[e], k);
         slot_cnt[r] = static_cast<uint32_t>(hp[r + 1]) - hp[r];
         ++r;
     }
@@ -458,8 +497,11 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_mid(const DevBuild *__restric
         const uint64_t o = B.off[g];
         const uint32_t len = static_cast<uint32_t>(B.off[g + 1] - o);
         const uint32_t nw = len - B.k + 1;  // k_mv_wave queued this gene for nw <= kMvThreads * E
-        if (NARROW || B.bits * B.k <= 32) {  // uniform per work-group
+        if (B.bits * B.k <= 32) {  // uniform per work-group
             mid_gene<E, uint32_t>(B, B.gene_base + g, o, len, nw, xch, reinterpret_cast<uint32_t *>(s_last), tmp, dcnt);
+        } else if (base20_keys(B)) {
+            mid_gene<E, uint32_t, true>(B, B.gene_base + g, o, len, nw, xch, reinterpret_cast<uint32_t *>(s_last), tmp,
+                                        dcnt);
         } else {
             if constexpr (!NARROW) mid_gene<E, uint64_t>(B, B.gene_base + g, o, len, nw, xch, s_last, tmp, dcnt);
         }
@@ -709,10 +751,24 @@ __device__ __forceinline__ uint64_t rec_code(const uint2 &r) { return r.x; }
 __device__ __forceinline__ uint32_t rec_gene(const uint2 &r) { return r.y & 0xFFFFu; }
 __device__ __forceinline__ uint32_t rec_cnt(const uint2 &r) { return r.y >> 16; }
 // An index record in the form a bin sort keeps in LDS: uint4 = (code low, code high, gene,
-// count), or, when every genome of the build has codes of at most 32 bits and at most 65536
-// genes, uint2 = (code, gene | count << 16): half the LDS, more work-groups per CU.
-__device__ __forceinline__ void to_rec(const uint4 &v, uint4 *r) { *r = v; }
-__device__ __forceinline__ void to_rec(const uint4 &v, uint2 *r) { *r = make_uint2(v.x, v.z | (v.w << 16)); }
+// count), or, when every genome of the build has 32-bit keys (codes of at most 32 bits, or
+// base-20 values: base20_keys) and at most 65536 genes, uint2 = (key, gene | count << 16):
+// half the LDS, more work-groups per CU.  A base-20 key orders records as the code does.
+__device__ __forceinline__ uint32_t code_to_base20(uint64_t c, uint32_t k) {
+    uint32_t v = 0;
+    for (uint32_t i = 0; i < k; ++i) v = v * 20u + static_cast<uint32_t>((c >> (5u * (k - 1u - i))) & 31u);
+    return v;
+}
+__device__ __forceinline__ void to_rec(const DevBuild &, const uint4 &v, uint4 *r) { *r = v; }
+__device__ __forceinline__ void to_rec(const DevBuild &B, const uint4 &v, uint2 *r) {
+    const uint32_t key = base20_keys(B) ? code_to_base20((static_cast<uint64_t>(v.y) << 32) | v.x, B.k) : v.x;
+    *r = make_uint2(key, v.z | (v.w << 16));
+}
+// The 5-bit code of a record.
+__device__ __forceinline__ uint64_t rec_code5(const DevBuild &, const uint4 &r) { return rec_code(r); }
+__device__ __forceinline__ uint64_t rec_code5(const DevBuild &B, const uint2 &r) {
+    return base20_keys(B) ? base20_to_code(r.x, B.k) : static_cast<uint64_t>(r.x);
+}
 
 // Packed join key of an index entry: the code's trailing letters (the leading ones are
 // the bucket) above the gene.
@@ -724,7 +780,7 @@ __device__ __forceinline__ uint32_t entry_key(const DevBuild &B, uint64_t code, 
 
 template <typename R>
 __device__ __forceinline__ void put_entry(const DevBuild &B, uint32_t pos, const R &v) {
-    const uint64_t c = rec_code(v);
+    const uint64_t c = rec_code5(B, v);
     const uint32_t g = rec_gene(v);
     B.ix_code[pos] = c;
     B.ix_gene[pos] = g;
@@ -759,6 +815,16 @@ __device__ __forceinline__ uint32_t bin_slot(const DevBuild &B, uint64_t code, u
     if (!B.xb) return b;
     const uint32_t sh = B.bits * (B.k - B.lead) - B.xb;
     return (b << B.xb) | (static_cast<uint32_t>(code >> sh) & ((1u << B.xb) - 1u));
+}
+// The same from a record: a base-20 key of a 7-mer gives its bucket (first 4 letters) and next
+// letter directly.
+__device__ __forceinline__ uint32_t rec_slot(const DevBuild &B, const uint4 &r, uint32_t b0) {
+    return bin_slot(B, rec_code(r), b0);
+}
+__device__ __forceinline__ uint32_t rec_slot(const DevBuild &B, const uint2 &r, uint32_t b0) {
+    if (!base20_keys(B)) return bin_slot(B, r.x, b0);
+    const uint32_t b = r.x / 8000u - b0;  // 20^3: the last three letters
+    return B.xb ? (b << B.xb) | ((r.x / 400u) % 20u) : b;
 }
 
 // One work-group per coarse bin: its entries ordered by (code, gene) and the bin's part of
@@ -803,12 +869,12 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
             w[q] = i < n ? tmp[lo + i] : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
-        for (uint32_t q = 0; q < kIxPer; ++q) to_rec(w[q], &r[q]);
+        for (uint32_t q = 0; q < kIxPer; ++q) to_rec(B, w[q], &r[q]);
 #pragma unroll
         for (uint32_t q = 0; q < kIxPer; ++q) {
             const uint32_t i = q * 256 + threadIdx.x;
             if (i < n) {
-                bk[q] = bin_slot(B, rec_code(r[q]), b0);
+                bk[q] = rec_slot(B, r[q], b0);
                 slot[q] = atomicAdd(&s_bstart[bk[q]], 1u);
             }
         }
@@ -868,7 +934,7 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < n; i += 256) put_entry(B, lo + i, s_rec[i]);
     } else if (n <= kIxBinLds) {
-        for (uint32_t i = threadIdx.x; i < n; i += 256) to_rec(tmp[lo + i], &s_rec[i]);
+        for (uint32_t i = threadIdx.x; i < n; i += 256) to_rec(B, tmp[lo + i], &s_rec[i]);
         __syncthreads();
         sort_recs(s_rec, n);
         for (uint32_t i = threadIdx.x; i < n; i += 256) put_entry(B, lo + i, s_rec[i]);
@@ -1051,7 +1117,8 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
     PDP_TRY(hipGetLastError());
     if (tg > 0) {
         bool narrow = true;
-        for (uint32_t i = 0; i < n; ++i) narrow &= alpha_spec(d[i]->alphabet).bits * d[i]->k <= 32;
+        for (uint32_t i = 0; i < n; ++i)
+            narrow &= alpha_spec(d[i]->alphabet).bits * d[i]->k <= 32 || (d[i]->alphabet == PDP_ALPHA_AMINO && d[i]->k == 7);
         if (narrow)
             hipLaunchKernelGGL(k_mv_wave<true>, dim3((tg + kMvWaves - 1) / kMvWaves), dim3(kMvThreads), 0, s, table, n,
                                tg, dcnt, mid_list, long_list, stride, counters);
@@ -1098,10 +1165,11 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
     hipLaunchKernelGGL(k_ix_place, dim3(static_cast<uint32_t>(sh.total_blocks)), dim3(kIxPlaceThreads), hist_lds, s, table,
                        n, dcnt, binoff, bintot, ent_gene);
     PDP_TRY(hipGetLastError());
-    // bins sorted in LDS as 8-byte records when every code fits 32 bits and every gene index 16 bits
+    // bins sorted in LDS as 8-byte records when every key fits 32 bits and every gene index 16 bits
     bool narrow_rec = true;
     for (uint32_t i = 0; i < n; ++i)
-        narrow_rec &= alpha_spec(d[i]->alphabet).bits * d[i]->k <= 32 && g[i].n_genes <= 65536;
+        narrow_rec &= (alpha_spec(d[i]->alphabet).bits * d[i]->k <= 32 || (d[i]->alphabet == PDP_ALPHA_AMINO && d[i]->k == 7)) &&
+                      g[i].n_genes <= 65536;
     if (narrow_rec)
         hipLaunchKernelGGL(k_ix_sort_bin<uint2>, dim3(static_cast<uint32_t>(sh.total_bins)), dim3(256), 0, s, table, n,
                            binoff);
