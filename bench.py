@@ -120,6 +120,11 @@ def kernel_bytes(kernel: str, pairs, entries, genes, bh_nnz, bbh_n) -> float:
     return 0.0
 
 
+def say(*a):
+    """Progress of the run on stderr (the result is the one JSON line on stdout)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def _frac(nbytes, ms):
     gbs = nbytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
     return round(gbs, 2), round(gbs / HBM_PEAK_GBS, 5)
@@ -171,6 +176,7 @@ def cpu_baseline(ds, k, rows_per_dir, full_workload: bool):
     import oracle
 
     threads = oracle.default_threads()
+    say(f"CPU baseline on {threads} threads")
     t0 = time.perf_counter()
     og = oracle.genomes(ds.genomes, k, threads=threads)
     mv_s = time.perf_counter() - t0
@@ -190,6 +196,7 @@ def cpu_baseline(ds, k, rows_per_dir, full_workload: bool):
             gene_pairs += len(rows) * tt.n
     dense_s = time.perf_counter() - t0
     rate = gene_pairs / dense_s
+    say(f"dense oracle sample: {gene_pairs} gene pairs in {dense_s:.1f} s")
     # one whole pair, both directions and BBH: the two smallest genomes
     small = sorted(range(len(og)), key=lambda x: og[x].n)[:2]
     a, b = og[small[0]], og[small[1]]
@@ -205,6 +212,7 @@ def cpu_baseline(ds, k, rows_per_dir, full_workload: bool):
     one_s = time.perf_counter() - t0
     one_rate = len(rows) * og[1].n / one_s
     # the sparse oracle on the whole workload
+    say("sparse oracle on every pair")
     t0 = time.perf_counter()
     oracle.all_pairs_sparse(og, pairs, threads=threads)
     sparse_s = time.perf_counter() - t0
@@ -409,7 +417,9 @@ def prepare_serving(args):
                           rate_per_s=1.0)
     _SERVING = wl
     n = min(args.arrivals, 2000)
+    say(f"serving residents generated ({time.perf_counter() - t0:.1f} s); generating {n} arrivals")
     arrivals = _pool_map(_gen_arrival, list(range(n)))
+    say(f"serving inputs ready ({time.perf_counter() - t0:.1f} s)")
     return wl, arrivals, time.perf_counter() - t0
 
 
@@ -451,6 +461,7 @@ def serve_stream(args, wl, arrivals):
         drain(warm, done)
         cap_s = time.perf_counter() - tw
         capacity = warm / cap_s
+        say(f"serving: closed-loop capacity {capacity:.1f} genomes/s; open loop of {n} arrivals")
         # open loop at the offered load
         lam = args.load * capacity
         times = wl.arrival_times[:n] / lam  # unit-rate Poisson times rescaled to rate lam
@@ -540,6 +551,7 @@ def main():
     torch.cuda.set_device(0)
     nt = args.alphabet == "nt"
     ds = make_config(3 if large else 2, alphabet=args.alphabet)
+    say(f"{ds.description}: {len(ds.genomes)} genomes, {ds.total_genes()} genes")
     k = pdp.k_rule(ds.total_residues(), 4 if nt else 20)
     pairs = ds.pairs()
     gene_pairs = ds.gene_pairs()
@@ -601,6 +613,7 @@ def main():
 
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = gene_pairs / (ms_per_step / 1e3)
+    say(f"{args.steps} timed steps: {ms_per_step:.3f} ms per step")
     dict_ms = sum(a.elapsed_time(b) for a, b in dict_ev) / args.steps
 
     res = runner.results()

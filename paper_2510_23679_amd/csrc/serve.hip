@@ -133,9 +133,14 @@ struct ServeRequest {
     const uint32_t *bbh_ptr = nullptr, *bbh_a = nullptr, *bbh_b = nullptr, *bbh_num = nullptr, *bbh_den = nullptr;
 };
 
+// A request on a slot ends in two steps: `head` completes when its statuses and both row-pointer
+// arrays are on the host; the worker then reads the totals and enqueues copies of the used
+// entries only (tail_queued), which `done` closes.
 struct ServeSlot {
     hipStream_t stream = nullptr;
+    hipEvent_t head = nullptr;
     hipEvent_t done = nullptr;
+    bool tail_queued = false;
     ServeRequest *req = nullptr;
     Pinned pin;
 };
@@ -254,7 +259,7 @@ int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t
     if (rc) return rc;
     // host input -> pinned staging -> device; pinned output staging sized for the results
     const uint64_t in_bytes = r->n_res + 8 * (uint64_t(r->n_genes) + 1);
-    const uint64_t out_bytes = sizeof(pdp_status) + 4 * (uint64_t(info.bh_rows) + 1 + 3 * r->bh_cap) +
+    const uint64_t out_bytes = 2 * sizeof(pdp_status) + 4 * (uint64_t(info.bh_rows) + 1 + 3 * r->bh_cap) +
                                4 * (uint64_t(info.bbh_rows) + 1 + 4 * r->bbh_cap);
     if (!slot.pin.ensure(in_bytes + 64)) return PDP_E_HIP;
     give_pin(S, r->out);  // a retried request gives back its earlier buffer
@@ -273,7 +278,8 @@ int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t
     if (rc) return rc;
     rc = pdp_plan_launch(r->plan, &r->bh, &r->bbh, r->status, scratch, scratch_bytes, s);
     if (rc) return rc;
-    // results back to the request's own pinned buffer
+    // first step of the results: both statuses and both row-pointer arrays, to the request's own
+    // pinned buffer (the entries follow once their totals are known, copy_tail)
     char *h = static_cast<char *>(r->out->p);
     auto d2h = [&](const void *src, uint64_t bytes) {
         if (hipMemcpyAsync(h, src, bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
@@ -281,29 +287,58 @@ int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t
         return true;
     };
     bool ok = d2h(r->status, sizeof(pdp_status)) && d2h(r->dict.status, sizeof(pdp_status)) &&
-              d2h(r->bh.ptr, 4 * (uint64_t(info.bh_rows) + 1)) && d2h(r->bh.col, 4 * r->bh_cap) &&
-              d2h(r->bh.num, 4 * r->bh_cap) && d2h(r->bh.den, 4 * r->bh_cap) &&
-              d2h(r->bbh.ptr, 4 * (uint64_t(info.bbh_rows) + 1)) && d2h(r->bbh.a, 4 * r->bbh_cap) &&
-              d2h(r->bbh.b, 4 * r->bbh_cap) && d2h(r->bbh.num, 4 * r->bbh_cap) && d2h(r->bbh.den, 4 * r->bbh_cap);
+              d2h(r->bh.ptr, 4 * (uint64_t(info.bh_rows) + 1)) && d2h(r->bbh.ptr, 4 * (uint64_t(info.bbh_rows) + 1));
     if (!ok) return PDP_E_HIP;
-    if (hipEventRecord(slot.done, s) != hipSuccess) return PDP_E_HIP;
+    if (hipEventRecord(slot.head, s) != hipSuccess) return PDP_E_HIP;
+    slot.tail_queued = false;
     return PDP_OK;
 }
 
-// Unpacks the pinned results of a finished slot; true if the request is done (else it is retried).
-bool collect(pdp_server *S, ServeSlot &, ServeRequest *r) {
+// Layout of a request's pinned results: statuses, best-hit row pointers, BBH row pointers, then
+// the used entries of each array (bh col, num, den; BBH a, b, num, den).
+struct HostLayout {
+    const char *base;
+    uint64_t bh_rows, bbh_rows;
+    const pdp_status *status() const { return reinterpret_cast<const pdp_status *>(base); }
+    const pdp_status *dict_status() const { return reinterpret_cast<const pdp_status *>(base) + 1; }
+    const uint32_t *bh_ptr() const { return reinterpret_cast<const uint32_t *>(base + 2 * sizeof(pdp_status)); }
+    const uint32_t *bbh_ptr() const { return bh_ptr() + bh_rows + 1; }
+    const uint32_t *entries() const { return bbh_ptr() + bbh_rows + 1; }
+};
+
+// Second step: the used entries, sized by the totals the first step brought back (a total is
+// at most its capacity once the status is clean), then `done`.
+int32_t copy_tail(ServeSlot &slot, ServeRequest *r) {
     pdp_plan_info info;
     pdp_plan_info_get(r->plan, &info);
-    const char *h = static_cast<const char *>(r->out->p);
-    pdp_status st, dst;
-    std::memcpy(&st, h, sizeof(st));
-    h += sizeof(st);
-    std::memcpy(&dst, h, sizeof(dst));
-    h += sizeof(dst);
+    const HostLayout L{static_cast<const char *>(r->out->p), info.bh_rows, info.bbh_rows};
+    const uint64_t nbh = std::min<uint64_t>(L.bh_ptr()[info.bh_rows], r->bh_cap);
+    const uint64_t nbb = std::min<uint64_t>(L.bbh_ptr()[info.bbh_rows], r->bbh_cap);
+    char *h = const_cast<char *>(reinterpret_cast<const char *>(L.entries()));
+    hipStream_t s = slot.stream;
+    auto d2h = [&](const void *src, uint64_t bytes) {
+        if (bytes && hipMemcpyAsync(h, src, bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+        h += bytes;
+        return true;
+    };
+    const bool ok = d2h(r->bh.col, 4 * nbh) && d2h(r->bh.num, 4 * nbh) && d2h(r->bh.den, 4 * nbh) &&
+                    d2h(r->bbh.a, 4 * nbb) && d2h(r->bbh.b, 4 * nbb) && d2h(r->bbh.num, 4 * nbb) &&
+                    d2h(r->bbh.den, 4 * nbb);
+    if (!ok) return PDP_E_HIP;
+    if (hipEventRecord(slot.done, s) != hipSuccess) return PDP_E_HIP;
+    slot.tail_queued = true;
+    return PDP_OK;
+}
+
+// After the first step: 0 when the run is clean (its entries are to be copied), 1 when the request
+// is done with an error, 2 when a capacity error grew its buffers and it runs again.
+int head_check(pdp_server *S, ServeRequest *r) {
+    const pdp_status st = *reinterpret_cast<const pdp_status *>(r->out->p);
+    const pdp_status dst = *(reinterpret_cast<const pdp_status *>(r->out->p) + 1);
     if (dst.code != PDP_OK) {
         r->hstatus = dst;
         r->code = dst.code;
-        return true;
+        return 1;
     }
     if (st.code == PDP_E_CAPACITY && r->attempts < 4) {
         // grow the array that overflowed and run the request again
@@ -314,36 +349,38 @@ bool collect(pdp_server *S, ServeSlot &, ServeRequest *r) {
         S->retries++;
         r->planned = false;  // the capacities changed: plan and footprint are made again
         give_pin(S, r->out);
-        return false;
+        return 2;
     }
     r->hstatus = st;
     r->code = st.code;
-    if (st.code != PDP_OK) return true;
-    // views of the arrays in the pinned buffer, laid out as the copies wrote them
-    auto view = [&](uint64_t stride) {
-        const uint32_t *v = reinterpret_cast<const uint32_t *>(h);
-        h += 4 * stride;
-        return v;
-    };
+    return st.code != PDP_OK ? 1 : 0;
+}
+
+// After the second step: views of the arrays in the pinned buffer, laid out as the copies wrote them.
+void collect(pdp_server *S, ServeRequest *r) {
+    pdp_plan_info info;
+    pdp_plan_info_get(r->plan, &info);
+    const HostLayout L{static_cast<const char *>(r->out->p), info.bh_rows, info.bbh_rows};
     r->bh_rows = info.bh_rows;
     r->bbh_rows = info.bbh_rows;
-    r->bh_ptr = view(uint64_t(info.bh_rows) + 1);
-    r->bh_col = view(r->bh_cap);
-    r->bh_num = view(r->bh_cap);
-    r->bh_den = view(r->bh_cap);
-    r->bbh_ptr = view(uint64_t(info.bbh_rows) + 1);
-    r->bbh_a = view(r->bbh_cap);
-    r->bbh_b = view(r->bbh_cap);
-    r->bbh_num = view(r->bbh_cap);
-    r->bbh_den = view(r->bbh_cap);
+    r->bh_ptr = L.bh_ptr();
+    r->bbh_ptr = L.bbh_ptr();
     r->nbh = r->bh_ptr[info.bh_rows];
     r->nbb = r->bbh_ptr[info.bbh_rows];
+    const uint32_t *e = L.entries();
+    r->bh_col = e;
+    r->bh_num = e + r->nbh;
+    r->bh_den = e + 2 * r->nbh;
+    e += 3 * r->nbh;
+    r->bbh_a = e;
+    r->bbh_b = e + r->nbb;
+    r->bbh_num = e + 2 * r->nbb;
+    r->bbh_den = e + 3 * r->nbb;
     const uint32_t nt = static_cast<uint32_t>(S->residents.size());
     r->ab_row.resize(nt);
     r->ba_row.resize(nt);
     r->bbh_row.resize(nt);
     for (uint32_t t = 0; t < nt; ++t) pdp_plan_rows(r->plan, t, &r->ab_row[t], &r->ba_row[t], &r->bbh_row[t]);
-    return true;
 }
 
 void finish(pdp_server *S, ServeRequest *r) {
@@ -363,10 +400,11 @@ void worker_loop(pdp_server *S) {
     std::unique_lock<std::mutex> lk(S->mu);
     while (!S->stop) {
         bool progress = false;
-        // retire finished slots
+        // advance and retire slots: a clean first step gets its entries copied; a finished second
+        // step, or a first step with an error, frees the slot and the request's memory
         for (ServeSlot &slot : S->slots) {
             if (!slot.req) continue;
-            const hipError_t q = hipEventQuery(slot.done);
+            const hipError_t q = hipEventQuery(slot.tail_queued ? slot.done : slot.head);
             if (q == hipErrorNotReady) continue;
             ServeRequest *r = slot.req;
             progress = true;
@@ -374,11 +412,21 @@ void worker_loop(pdp_server *S) {
             if (q != hipSuccess) {
                 r->code = PDP_E_HIP;
                 S->fatal = PDP_E_HIP;
+            } else if (!slot.tail_queued) {
+                const int h = head_check(S, r);
+                if (h == 0) {
+                    if (copy_tail(slot, r) == PDP_OK) continue;  // the slot keeps the request until `done`
+                    (void)hipStreamSynchronize(slot.stream);
+                    r->code = PDP_E_HIP;
+                    S->fatal = PDP_E_HIP;
+                }
+                done = h != 2;
             } else {
-                done = collect(S, slot, r);
+                collect(S, r);
             }
             S->arena->release(r->dev_off, r->dev_bytes);
             slot.req = nullptr;
+            slot.tail_queued = false;
             if (done) finish(S, r);
             else S->pending.push_front(r);  // retried ahead of newer requests
         }
@@ -480,6 +528,7 @@ int32_t pdp_server_create(const pdp_server_config *cfg, const pdp_dict *const *r
     S->slots.resize(cfg->slots);
     for (ServeSlot &slot : S->slots) {
         if (hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&slot.head, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) != hipSuccess)
             return api_fail(PDP_E_HIP, "pdp_server_create: stream or event creation failed");
     }
@@ -509,9 +558,10 @@ int32_t pdp_server_submit(pdp_server *S, const uint8_t *residues, const uint64_t
         resident_entries += d.capacity;
         resident_genes += d.n_genes;
     }
-    // records, both directions: about a quarter of the entries of every pair, so that the one-pass
-    // join's per-tile regions (the capacity split over the tiles) rarely overflow
-    r->inc_cap = (resident_entries + S->residents.size() * (r->n_res + 1)) / 4 + 65536;
+    // records, both directions: half the entries of every pair.  Arrivals share many k-mers with
+    // the residents (their genes come from resident families), and the one-pass join falls back to
+    // two passes when one tile's share of the capacity overflows, so the capacity is generous.
+    r->inc_cap = (resident_entries + S->residents.size() * (r->n_res + 1)) / 2 + 65536;
     const uint64_t rows = uint64_t(n_genes) * S->residents.size() + resident_genes;
     r->bh_cap = rows + rows / 4 + 4096;
     r->bbh_cap = uint64_t(n_genes) * S->residents.size() * 3 / 4 + 4096;
@@ -616,6 +666,7 @@ void pdp_server_destroy(pdp_server *S) {
     for (ServeSlot &slot : S->slots) {
         if (slot.stream) (void)hipStreamSynchronize(slot.stream);
         if (slot.req && slot.req->plan) pdp_plan_destroy(slot.req->plan);
+        if (slot.head) (void)hipEventDestroy(slot.head);
         if (slot.done) (void)hipEventDestroy(slot.done);
         if (slot.stream) (void)hipStreamDestroy(slot.stream);
     }
