@@ -475,6 +475,22 @@ int32_t pdp_bh_ws_size(const pdp_dict *q, const pdp_dict *t, const pdp_params *p
 int32_t pdp_bh(const pdp_dict *q, const pdp_dict *t, const pdp_params *params, pdp_bh_out *out,
                pdp_status *status, void *ws, uint64_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, hosts that forbid hipMalloc): pdp_bh with its scratch in a
+ * fixed device array of the library instead of a caller workspace.  Arguments,
+ * results and device errors as pdp_bh.  The array holds PDP_NOALLOC_SCRATCH_BYTES
+ * on every device the library runs on, from the library's load to the end of the
+ * process; a genome pair whose pdp_bh_ws_size exceeds it is rejected with
+ * PDP_E_WORKSPACE before anything is enqueued.  The call allocates no device
+ * memory.  All calls on one device share that device's array: calls that overlap
+ * on one device (concurrent streams or threads) race and give undefined results;
+ * calls one after another are independent of each other.  Synchronises the
+ * stream once, as pdp_bh does.
+ * Errors: PDP_E_INVAL, PDP_E_WORKSPACE, PDP_E_LIMIT, PDP_E_HIP, as pdp_bh. */
+#define PDP_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int32_t pdp_bh_noalloc(const pdp_dict *q, const pdp_dict *t, const pdp_params *params, pdp_bh_out *out,
+                       pdp_status *status, void *stream);
+
 /* BBH from two best-hit outputs (Alg. 3's cross-check of A_ij against A_ji):
  * ab has one row per gene of genome i, ba one row per gene of genome j.
  * out->n_rows must equal ab->n_rows.  Device errors: PDP_E_CAPACITY.

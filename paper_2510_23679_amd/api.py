@@ -470,6 +470,31 @@ def bh(q: Dictionary, t: Dictionary, prm: Optional[B.pdp_params] = None, capacit
     raise B.PdpError(B.PDP_E_CAPACITY, "pdp_bh: capacity still too small")
 
 
+def bh_noalloc(q: Dictionary, t: Dictionary, prm: Optional[B.pdp_params] = None, capacity: Optional[int] = None,
+               stream=None) -> BHOut:
+    """pdp_bh_noalloc: best hits of q's genes in t with the library's fixed device scratch (no
+    workspace).  Grows the output and retries on a best-hit capacity error; a record capacity
+    error retries with more records while the fixed scratch holds them (synchronises)."""
+    prm = prm or params()
+    out = BHOut(q.n_genes, capacity if capacity is not None else 2 * q.n_genes + 1024)
+    st = new_status()
+    for _ in range(4):
+        o = out.struct()
+        check(lib().pdp_bh_noalloc(C.byref(q.d), C.byref(t.d), C.byref(prm), C.byref(o), st.data_ptr(),
+                                   _stream_handle(stream)), "pdp_bh_noalloc")
+        code, needed, where = read_status(st)
+        if code == B.PDP_E_CAPACITY and where == 0:
+            prm = _with_capacity(prm, int(needed * 1.25) + 1024)
+            continue
+        if code == B.PDP_E_CAPACITY and where == 1:
+            out = BHOut(q.n_genes, int(needed * 1.25) + 1024)
+            continue
+        if code != 0:
+            raise B.PdpError(code, f"pdp_bh_noalloc: {lib().pdp_strerror(code).decode()}")
+        return out
+    raise B.PdpError(B.PDP_E_CAPACITY, "pdp_bh_noalloc: capacity still too small")
+
+
 def bbh(ab: BHOut, ba: BHOut, capacity: Optional[int] = None, stream=None) -> BBHOut:
     """pdp_bbh: BBH from two best-hit outputs (synchronises to read the status)."""
     ws_bytes = B.u64(0)

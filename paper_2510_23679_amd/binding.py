@@ -49,6 +49,8 @@ def alphabet_id(alphabet) -> int:
 PDP_MAX_WINDOWS = 65535
 
 # kernels that pdp_plan_timer_start can time
+PDP_NOALLOC_SCRATCH_BYTES = 64 << 20  # include/pdp.h: the fixed scratch of pdp_bh_noalloc
+
 KERNELS = {"join": 0, "bucket": 1, "tile_count": 2, "tile_write": 3, "bbh": 4, "all": 5, "join_backup": 6}
 
 
@@ -161,6 +163,8 @@ SIGNATURES = {
     "pdp_bh_ws_size": (i32,[C.POINTER(pdp_dict), C.POINTER(pdp_dict), C.POINTER(pdp_params), C.POINTER(u64)]),
     "pdp_bh": (i32, [C.POINTER(pdp_dict), C.POINTER(pdp_dict), C.POINTER(pdp_params), C.POINTER(pdp_bh_out), vp, vp,
                      u64, vp]),
+    "pdp_bh_noalloc": (i32, [C.POINTER(pdp_dict), C.POINTER(pdp_dict), C.POINTER(pdp_params), C.POINTER(pdp_bh_out),
+                             vp, vp]),
     "pdp_bbh_ws_size": (i32, [u32, C.POINTER(u64)]),
     "pdp_bbh": (i32, [C.POINTER(pdp_bh_out), C.POINTER(pdp_bh_out), C.POINTER(pdp_bbh_out), vp, vp, u64, vp]),
 }
