@@ -46,7 +46,11 @@ def parse():
     p.add_argument("--no-latency", action="store_true", help="skip the serving run that gives p50/p99 latency")
     p.add_argument("--breakdown", action="store_true", help="also time every kernel group (extra launches)")
     p.add_argument("--calibrate-copy", action="store_true", help="only run a copy of known size (counter calibration)")
-    p.add_argument("--tune", action="store_true", help="pick tile shapes and join splits with the autotuner first")
+    p.add_argument("--no-tune", action="store_true",
+                   help="library defaults instead of the autotuner's pick of tile height and column maxima")
+    p.add_argument("--tune-all", action="store_true",
+                   help="the autotuner's whole built-in grid (tile height x sub-range size x persistence x column "
+                        "maxima) instead of tile height x column maxima")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                    help="measured HBM traffic per kernel (from rocprofv3 counters), used when its source hash matches")
     p.add_argument("--two-pass", action="store_true", help="join in two passes (count, then write)")
@@ -72,9 +76,11 @@ def parse():
     p.add_argument("--resident-genes", type=int, default=4000, help="serving: genes per resident")
     p.add_argument("--arrivals", type=int, default=2000, help="serving: arriving genomes (of the 2000-arrival stream)")
     p.add_argument("--load", type=float, default=0.8, help="serving: offered load as a fraction of closed-loop capacity")
-    p.add_argument("--slots", type=int, default=8, help="serving: concurrent request slots")
+    p.add_argument("--slots", type=int, default=4, help="serving: concurrent request slots")
     p.add_argument("--budget-gb", type=float, default=32.0, help="serving: HBM budget for requests in flight")
-    p.add_argument("--serve-colmax", action="store_true", help="serving: column maxima for the residents' best hits")
+    p.add_argument("--serve-no-colmax", action="store_true",
+                   help="serving: the residents' best hits from their own rows instead of column maxima")
+    p.add_argument("--serve-tile-rows", type=int, default=128, help="serving: rows per accumulation tile")
     return p.parse_args()
 
 
@@ -328,15 +334,16 @@ def run_batched(args):
                 sizing.run(stream)
                 cap = int(sizing.plan.info.inc_capacity)
                 del sizing
-                cands = [pdp.params(inc_capacity=cap, tile_rows=tr, join_entries=je, persistent=pe)
-                         for tr in (32, 64, 128) for je in (256, 512, 1024) for pe in (False, True)]
+                cands = [pdp.params(inc_capacity=cap, tile_rows=tr, join_entries=je, persistent=pe, colmax=cm)
+                         for tr in (64, 128) for je in (256, 512, 1024) for pe in (False, True) for cm in (False, True)]
                 best, tres = pdp.autotune(tasks, cands, reps=2, stream=stream)
                 tuned = {"tile_rows": int(best.tile_rows), "join_entries": int(best.join_entries),
-                         "persistent": bool(best.flags & B.PDP_PARAM_PERSISTENT), "candidates": int(tres.tried),
+                         "persistent": bool(best.flags & B.PDP_PARAM_PERSISTENT),
+                         "column_maxima": bool(best.flags & B.PDP_PARAM_COLMAX), "candidates": int(tres.tried),
                          "best_ms": round(tres.best_ms, 3), "first_ms": round(tres.first_ms, 3)}
             prm = (pdp.params(persistent=True) if args.persistent else
                    pdp.params(tile_rows=tuned["tile_rows"], join_entries=tuned["join_entries"],
-                              persistent=tuned["persistent"]))
+                              persistent=tuned["persistent"], colmax=tuned["column_maxima"]))
             runner = pdp.PairRunner(tasks, prm)
             runner.run(stream)
             batch.check_status()
@@ -442,7 +449,7 @@ def serve_stream(args, wl, arrivals):
     batch.check_status()
     res_genes = sum(d.n_genes for d in batch.dicts)
     srv = pdp.Server(batch.dicts, int(args.budget_gb * (1 << 30)), slots=args.slots,
-                     prm=pdp.params(tile_rows=args.tile_rows, colmax=args.serve_colmax))
+                     prm=pdp.params(tile_rows=args.serve_tile_rows, colmax=not args.serve_no_colmax))
 
     def drain(want, done):
         while len(done) < want:
@@ -486,10 +493,15 @@ def serve_stream(args, wl, arrivals):
     lat = [(d.done_us - d.submit_us) / 1e3 for d in done.values()]
     svc = [(d.done_us - d.admit_us) / 1e3 for d in done.values()]
     wait = [(d.admit_us - d.submit_us) / 1e3 for d in done.values()]
+    phases = {}
+    for name in ("h2d_ms", "build_ms", "pairs_ms", "d2h_ms"):
+        xs = [getattr(d, name) for d in done.values()]
+        phases[name[:-3]] = {"p50_ms": round(_pctl(xs, 50), 3), "p99_ms": round(_pctl(xs, 99), 3)}
     gp = sum(int(g.n_genes) * res_genes for g in arrivals)
     return {"genomes_per_s": round(n / wall, 2), "p50_ms": round(_pctl(lat, 50), 3), "p99_ms": round(_pctl(lat, 99), 3),
             "max_ms": round(max(lat), 3), "service_p50_ms": round(_pctl(svc, 50), 3),
             "service_p99_ms": round(_pctl(svc, 99), 3), "admission_wait_p99_ms": round(_pctl(wait, 99), 3),
+            "device_phases": phases,
             "closed_loop_genomes_per_s": round(capacity, 2), "offered_rate_per_s": round(lam, 2),
             "gene_pairs_per_s": round(gp / wall, 1), "arrivals": n, "retries": int(stats.retries),
             "attempts_max": int(max(d.attempts for d in done.values())),
@@ -498,7 +510,8 @@ def serve_stream(args, wl, arrivals):
             "workload": f"serving: {len(wl.residents.genomes)} resident genomes x "
                         f"{wl.residents.genomes[0].n_genes} genes (k = {k}), first {n} of 2000 Poisson arrivals "
                         f"(U{{1000..6000}} genes drawn from resident families), offered load {args.load} of the "
-                        f"closed-loop capacity, {args.slots} slots, {args.budget_gb} GB budget",
+                        f"closed-loop capacity, {args.slots} slots, {args.budget_gb} GB budget, "
+                        f"{args.serve_tile_rows}-row tiles, column maxima {'off' if args.serve_no_colmax else 'on'}",
             "note": "latency = completion - submission, including admission wait, the host-to-device copy of the "
                     "arriving genome and the copy of its results to host memory"}
 
@@ -513,7 +526,8 @@ def run_serving(args):
            "value": lat["genomes_per_s"], "unit": "genomes/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u32",
            "data": "synthetic", "config": {"workload": lat.pop("workload"), "slots": args.slots,
                                             "budget_gb": args.budget_gb, "offered_load": args.load,
-                                            "column_maxima": bool(args.serve_colmax)},
+                                            "tile_rows": args.serve_tile_rows,
+                                            "column_maxima": not args.serve_no_colmax},
            "latency": lat, "host_generation_s": round(gen_s, 1)}
     print(json.dumps(out), flush=True)
 
@@ -570,12 +584,18 @@ def main():
 
     prm = pdp.params(theta=frac(args.theta), tau=frac(args.tau), colmax=args.colmax, two_pass=args.two_pass,
                      join_entries=args.join_entries, persistent=args.persistent, tile_rows=args.tile_rows)
-    if args.tune:
-        best, tres = pdp.autotune(tasks, reps=3, base=prm)
+    explicit = args.join_entries or args.persistent or args.tile_rows or args.colmax or args.two_pass
+    if not args.no_tune and not explicit:
+        # the launch shape for this workload, picked by the library's autotuner before anything is timed
+        cands = None if args.tune_all else [pdp.params(tile_rows=tr, colmax=cm, theta=frac(args.theta), tau=frac(args.tau))
+                                            for tr in (64, 128) for cm in (False, True)]
+        best, tres = pdp.autotune(tasks, cands, reps=3, base=prm)
         prm = best
-        tuned = {"tile_rows": int(best.tile_rows), "lds_budget": int(best.lds_budget), "join_entries": int(best.join_entries),
-                 "persistent": bool(best.flags & B.PDP_PARAM_PERSISTENT), "best_ms": round(tres.best_ms, 4),
+        tuned = {"autotuned": True, "tile_rows": int(best.tile_rows), "join_entries": int(best.join_entries),
+                 "persistent": bool(best.flags & B.PDP_PARAM_PERSISTENT),
+                 "column_maxima": bool(best.flags & B.PDP_PARAM_COLMAX), "best_ms": round(tres.best_ms, 4),
                  "first_ms": round(tres.first_ms, 4), "candidates": int(tres.tried)}
+        say(f"autotuner: {tuned}")
     runner = pdp.PairRunner(tasks, prm)
     runner.run()  # sizes the scratch and outputs
     for d in dicts:
@@ -696,11 +716,13 @@ def main():
                    "genomes": len(genes), "genes_per_genome": genes[0] if not large else [min(genes), max(genes)],
                    "genes": int(sum(genes)), "k": k, "genome_pairs": len(pairs),
                    "gene_pairs": gene_pairs, "kmer_entries": int(sum(entries)), "best_hits": bh_nnz, "bbh_pairs": bbh_n,
-                   "filters": {"theta": args.theta, "tau": args.tau}, "column_maxima": bool(args.colmax)},
+                   "filters": {"theta": args.theta, "tau": args.tau},
+                   "column_maxima": bool(prm.flags & B.PDP_PARAM_COLMAX)},
         "roofline": roofline,
-        "params": tuned if tuned is not None else ("defaults" if not (args.join_entries or args.persistent or args.tile_rows)
+        "params": tuned if tuned is not None else ("defaults" if not explicit
                                                    else {"join_entries": args.join_entries, "persistent": args.persistent,
-                                                         "tile_rows": args.tile_rows}),
+                                                         "tile_rows": args.tile_rows, "column_maxima": args.colmax,
+                                                         "two_pass": args.two_pass}),
         "breakdown": breakdown,
     }
     del runner, res, batch, dicts, dev

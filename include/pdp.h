@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PDP_ABI_VERSION 4u
+#define PDP_ABI_VERSION 5u
 
 /* The two alphabets of the Basic notions section.  A dictionary's alphabet
  * fixes how a letter becomes a symbol, the symbol width of a k-mer code and
@@ -377,8 +377,9 @@ void pdp_graph_destroy(pdp_graph *graph);
 /* Autotuner for tile shapes and work splits: each candidate pdp_params is
  * planned for the given tasks, run once to warm up and then reps times between
  * two HIP events; the fastest candidate whose runs end with a clean status is
- * returned.  candidates NULL: a built-in grid of LDS budgets (24-144 KiB),
- * join sub-range sizes (256-1024 entries) and persistent on/off.  bh/bbh/status as
+ * returned.  candidates NULL: a built-in grid of tile heights (32, 64, 128
+ * rows), join sub-range sizes (256, 512, 1024 entries), persistent on/off and
+ * column maxima on/off (PDP_PARAM_COLMAX).  bh/bbh/status as
  * for pdp_plan_launch (their rows do not depend on the parameters); ws of
  * pdp_autotune_ws_size bytes.  Synchronises the stream.
  * Errors: PDP_E_INVAL, PDP_E_HIP, PDP_E_LIMIT (no candidate ran cleanly). */
@@ -427,6 +428,12 @@ typedef struct pdp_request_done {
     uint32_t flags;      /* pdp_status.flags of its last run (PDP_STATUS_TWO_PASS) */
     double submit_us, admit_us, done_us;
     uint64_t bh_entries, bbh_pairs;
+    /* Device time of the request's last run, in milliseconds between HIP events on its slot's
+     * stream: the copy of its genome to the device, its dictionary build, the plan launch
+     * against every resident (join, tiles, best hits, BBH), and the copies of its results to
+     * host memory (both steps: statuses and row pointers, then the used entries; the worker's
+     * turnaround between the two is not included). */
+    float h2d_ms, build_ms, pairs_ms, d2h_ms;
 } pdp_request_done;
 
 /* A finished request's results (host memory owned by the server, valid until

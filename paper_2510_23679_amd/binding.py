@@ -105,7 +105,8 @@ class pdp_server_config(C.Structure):
 class pdp_request_done(C.Structure):
     _fields_ = [("tag", u64), ("code", i32), ("n_genes", u32), ("attempts", u32), ("flags", u32),
                 ("submit_us", C.c_double), ("admit_us", C.c_double), ("done_us", C.c_double),
-                ("bh_entries", u64), ("bbh_pairs", u64)]
+                ("bh_entries", u64), ("bbh_pairs", u64), ("h2d_ms", C.c_float), ("build_ms", C.c_float),
+                ("pairs_ms", C.c_float), ("d2h_ms", C.c_float)]
 
 
 _P32 = C.POINTER(u32)
@@ -178,7 +179,7 @@ class PdpError(RuntimeError):
         self.code = code
 
 
-ABI_VERSION = 4  # the layout of the structures above; include/pdp.h defines the same number
+ABI_VERSION = 5  # the layout of the structures above; include/pdp.h defines the same number
 
 
 def lib():

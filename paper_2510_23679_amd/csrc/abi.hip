@@ -403,6 +403,8 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
                 it.bdir = d.b.ix_dir + bl;
                 it.task = i;
                 it.n_buckets = static_cast<uint32_t>(std::min<uint64_t>(d.a.n_buckets - bl, span));
+                it.bl = static_cast<uint32_t>(bl);
+                it.reserved = 0;
                 P->items.push_back(it);
             }
         }
@@ -433,6 +435,21 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         P->tasks.push_back(d);
         if (chunks > UINT32_MAX || P->tiles.size() >= UINT32_MAX)
             return bail(fail(PDP_E_LIMIT, "plan too large for 32-bit indices"));
+    }
+    {  // the one-pass join's items by leading-letter range across tasks (each range as a fraction of
+       // its task's buckets), tasks in processing order within a range: the items in flight read
+       // the same stretch of each genome's index (see the join kernel's XCD mapping)
+        std::vector<uint64_t> key(P->items.size());
+        for (size_t x = 0; x < P->items.size(); ++x) {
+            const DevItem &it = P->items[x];
+            key[x] = (static_cast<uint64_t>(it.bl) << 32) / P->tasks[it.task].a.n_buckets;
+        }
+        std::vector<uint32_t> idx(P->items.size());
+        for (size_t x = 0; x < idx.size(); ++x) idx[x] = static_cast<uint32_t>(x);
+        std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return key[x] < key[y]; });
+        std::vector<DevItem> sorted(P->items.size());
+        for (size_t x = 0; x < idx.size(); ++x) sorted[x] = P->items[idx[x]];
+        P->items.swap(sorted);
     }
     P->shape.n_tasks = n_tasks;
     P->shape.total_chunks = static_cast<uint32_t>(chunks);

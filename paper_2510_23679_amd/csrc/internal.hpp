@@ -112,6 +112,8 @@ struct DevItem {
     const uint32_t *bdir;
     uint32_t task;
     uint32_t n_buckets;
+    uint32_t bl;  // first bucket
+    uint32_t reserved;
 };
 
 struct DevTile {

@@ -694,9 +694,7 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
     }
     __syncthreads();
     const DevTask &T = L.task;
-    const uint32_t c = chunk - T.chunk_base;
-    const uint32_t span = T.bpw * T.subs;
-    const uint32_t bl = c * span;
+    const uint32_t bl = it.bl;
     const uint32_t bh = bl + it.n_buckets;
     const bool packed = T.a.key_shift && T.b.key_shift;
     const bool skip = L.drop != 0;
@@ -751,6 +749,16 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
     __syncthreads();
 }
 
+// Work-groups of a launch go to the XCDs in turn (work-group b to XCD b mod 8); item b' below gives
+// XCD x a contiguous run of items.  The plan orders items by leading-letter bucket range across
+// tasks, so an XCD works on one stretch of every genome's index at a time and its L2 serves
+// the same slices to all the genome pairs that read them.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_item(uint32_t b, uint32_t n) {
+    const uint32_t q = n / kXcds, r = n % kXcds, x = b % kXcds;
+    return x * q + min(x, r) + b / kXcds;  // a bijection of [0, n)
+}
+
 __global__ __launch_bounds__(kJoinThreads) void k_join_fused(const DevTask *__restrict__ tasks,
                                                              const DevItem *__restrict__ items,
                                                              uint32_t *__restrict__ fill,
@@ -760,11 +768,11 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_fused(const DevTask *__re
                                                              uint32_t join_tiles) {
     __shared__ JoinLdsFused L;
     extern __shared__ uint32_t join_dyn[];
-    fused_chunk(blockIdx.x, tasks, items, fill, tiles, fallback, recs, L, join_dyn, join_dyn + join_tiles,
-                join_tiles);
+    fused_chunk(xcd_item(blockIdx.x, gridDim.x), tasks, items, fill, tiles, fallback, recs, L, join_dyn,
+                join_dyn + join_tiles, join_tiles);
 }
 
-__global__ __launch_bounds__(kJoinThreads) void k_join_fused_persistent(
+__global__ __launch_bounds__(kJoinThreads, 6) void k_join_fused_persistent(
     const DevTask *__restrict__ tasks, const DevItem *__restrict__ items, uint32_t total_chunks,
     uint32_t *__restrict__ fill, const DevTile *__restrict__ tiles, uint32_t *__restrict__ fallback,
     uint2 *__restrict__ recs, uint32_t join_tiles, uint32_t *__restrict__ next) {

@@ -59,20 +59,23 @@ void pdp_graph_destroy(pdp_graph *g) {
 
 // ------------------------------------------------------------- autotuner
 
+// Tile height x join sub-range size x persistent kernels x column maxima: the best tile height
+// follows the records per row (denser at small k), column maxima pay off when the join dominates.
 static std::vector<pdp_params> default_candidates() {
     std::vector<pdp_params> c;
     const uint32_t rows[] = {32, 64, 128};
     const uint32_t join[] = {256, 512, 1024};
-    for (uint32_t persistent = 0; persistent < 2; ++persistent)
-        for (uint32_t r : rows)
-            for (uint32_t j : join) {
-                pdp_params p;
-                std::memset(&p, 0, sizeof(p));
-                p.tile_rows = r;
-                p.join_entries = j;
-                p.flags = persistent ? PDP_PARAM_PERSISTENT : 0;
-                c.push_back(p);
-            }
+    for (uint32_t colmax = 0; colmax < 2; ++colmax)
+        for (uint32_t persistent = 0; persistent < 2; ++persistent)
+            for (uint32_t r : rows)
+                for (uint32_t j : join) {
+                    pdp_params p;
+                    std::memset(&p, 0, sizeof(p));
+                    p.tile_rows = r;
+                    p.join_entries = j;
+                    p.flags = (persistent ? PDP_PARAM_PERSISTENT : 0) | (colmax ? PDP_PARAM_COLMAX : 0);
+                    c.push_back(p);
+                }
     return c;
 }
 

@@ -111,6 +111,7 @@ struct ServeRequest {
     int32_t code = PDP_OK;
     uint32_t attempts = 0;
     uint64_t inc_cap = 0, bh_cap = 0, bbh_cap = 0;
+    float h2d_ms = 0, build_ms = 0, pairs_ms = 0, d2h_ms = 0;  // device time of the last run
     // admission: the provisional plan and the footprint it gives are made once per run of the
     // request and kept while it waits for memory (cleared when a capacity retry grows it)
     bool planned = false;
@@ -136,10 +137,15 @@ struct ServeRequest {
 // A request on a slot ends in two steps: `head` completes when its statuses and both row-pointer
 // arrays are on the host; the worker then reads the totals and enqueues copies of the used
 // entries only (tail_queued), which `done` closes.
+// Timing events of a run on a slot's stream: before the genome's copy, after it, after the
+// dictionary build, after the plan launch, after the first result copies; before and after the
+// second.
+enum { kEvStart, kEvH2d, kEvBuild, kEvPairs, kEvHead, kEvTail0, kEvTail1, kEvCount };
 struct ServeSlot {
     hipStream_t stream = nullptr;
     hipEvent_t head = nullptr;
     hipEvent_t done = nullptr;
+    hipEvent_t ev[kEvCount] = {};
     bool tail_queued = false;
     ServeRequest *req = nullptr;
     Pinned pin;
@@ -217,6 +223,23 @@ int32_t make_plan(pdp_server *S, ServeRequest *r) {
     return pdp_plan_create(tasks.data(), static_cast<uint32_t>(tasks.size()), &p, &r->plan);
 }
 
+// The provisional plan of a request and the device footprint it gives: the descriptor is bound
+// to a placeholder address (planning reads only its sizes); launch_request moves the plan's
+// pointers once the memory is placed.  Both are kept while the request waits for memory.  Reads
+// only the request and the server's fixed configuration, so any thread may call it for a request
+// it owns.
+int32_t prepare_plan(pdp_server *S, ServeRequest *r) {
+    uint64_t dict_bytes = 0, build_ws = 0;
+    int32_t rc = pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, S->cfg.alphabet, &dict_bytes, &build_ws);
+    if (rc == PDP_OK)
+        rc = pdp_dict_bind(reinterpret_cast<void *>(uintptr_t(256)), dict_bytes, r->n_genes, r->n_res, S->cfg.k,
+                           S->cfg.alphabet, &r->dict);
+    if (rc == PDP_OK) rc = make_plan(S, r);
+    if (rc == PDP_OK) r->foot_bytes = footprint(S, r, &r->foot_plan_ws);
+    r->planned = rc == PDP_OK;
+    return rc;
+}
+
 // Everything a request enqueues on its slot's stream.
 int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t plan_ws) {
     hipStream_t s = slot.stream;
@@ -265,19 +288,23 @@ int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t
     give_pin(S, r->out);  // a retried request gives back its earlier buffer
     r->out = take_pin(S, out_bytes + 64);
     if (!r->out) return PDP_E_HIP;
+    if (hipEventRecord(slot.ev[kEvStart], s) != hipSuccess) return PDP_E_HIP;
     std::memcpy(slot.pin.p, r->res.data(), r->n_res);
     std::memcpy(static_cast<char *>(slot.pin.p) + r->n_res, r->off.data(), 8 * (uint64_t(r->n_genes) + 1));
     if (hipMemcpyAsync(res, slot.pin.p, r->n_res, hipMemcpyHostToDevice, s) != hipSuccess) return PDP_E_HIP;
     if (hipMemcpyAsync(off, static_cast<char *>(slot.pin.p) + r->n_res, 8 * (uint64_t(r->n_genes) + 1),
                        hipMemcpyHostToDevice, s) != hipSuccess)
         return PDP_E_HIP;
+    if (hipEventRecord(slot.ev[kEvH2d], s) != hipSuccess) return PDP_E_HIP;
     pdp_genome g{res, off, r->n_genes, 0, r->n_res};
     rc = pdp_dict_build(&g, &r->dict, scratch, scratch_bytes, s);
     if (rc) return rc;
+    if (hipEventRecord(slot.ev[kEvBuild], s) != hipSuccess) return PDP_E_HIP;
     rc = pdp_plan_upload(r->plan, scratch, scratch_bytes, s);
     if (rc) return rc;
     rc = pdp_plan_launch(r->plan, &r->bh, &r->bbh, r->status, scratch, scratch_bytes, s);
     if (rc) return rc;
+    if (hipEventRecord(slot.ev[kEvPairs], s) != hipSuccess) return PDP_E_HIP;
     // first step of the results: both statuses and both row-pointer arrays, to the request's own
     // pinned buffer (the entries follow once their totals are known, copy_tail)
     char *h = static_cast<char *>(r->out->p);
@@ -289,7 +316,8 @@ int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t
     bool ok = d2h(r->status, sizeof(pdp_status)) && d2h(r->dict.status, sizeof(pdp_status)) &&
               d2h(r->bh.ptr, 4 * (uint64_t(info.bh_rows) + 1)) && d2h(r->bbh.ptr, 4 * (uint64_t(info.bbh_rows) + 1));
     if (!ok) return PDP_E_HIP;
-    if (hipEventRecord(slot.head, s) != hipSuccess) return PDP_E_HIP;
+    if (hipEventRecord(slot.ev[kEvHead], s) != hipSuccess || hipEventRecord(slot.head, s) != hipSuccess)
+        return PDP_E_HIP;
     slot.tail_queued = false;
     return PDP_OK;
 }
@@ -316,6 +344,7 @@ int32_t copy_tail(ServeSlot &slot, ServeRequest *r) {
     const uint64_t nbb = std::min<uint64_t>(L.bbh_ptr()[info.bbh_rows], r->bbh_cap);
     char *h = const_cast<char *>(reinterpret_cast<const char *>(L.entries()));
     hipStream_t s = slot.stream;
+    if (hipEventRecord(slot.ev[kEvTail0], s) != hipSuccess) return PDP_E_HIP;
     auto d2h = [&](const void *src, uint64_t bytes) {
         if (bytes && hipMemcpyAsync(h, src, bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
         h += bytes;
@@ -325,7 +354,8 @@ int32_t copy_tail(ServeSlot &slot, ServeRequest *r) {
                     d2h(r->bbh.a, 4 * nbb) && d2h(r->bbh.b, 4 * nbb) && d2h(r->bbh.num, 4 * nbb) &&
                     d2h(r->bbh.den, 4 * nbb);
     if (!ok) return PDP_E_HIP;
-    if (hipEventRecord(slot.done, s) != hipSuccess) return PDP_E_HIP;
+    if (hipEventRecord(slot.ev[kEvTail1], s) != hipSuccess || hipEventRecord(slot.done, s) != hipSuccess)
+        return PDP_E_HIP;
     slot.tail_queued = true;
     return PDP_OK;
 }
@@ -356,8 +386,18 @@ int head_check(pdp_server *S, ServeRequest *r) {
     return st.code != PDP_OK ? 1 : 0;
 }
 
-// After the second step: views of the arrays in the pinned buffer, laid out as the copies wrote them.
-void collect(pdp_server *S, ServeRequest *r) {
+float event_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0;
+    return hipEventElapsedTime(&ms, a, b) == hipSuccess ? ms : 0.0f;
+}
+
+// After the second step: the run's device times, and views of the arrays in the pinned buffer,
+// laid out as the copies wrote them.
+void collect(pdp_server *S, const ServeSlot &slot, ServeRequest *r) {
+    r->h2d_ms = event_ms(slot.ev[kEvStart], slot.ev[kEvH2d]);
+    r->build_ms = event_ms(slot.ev[kEvH2d], slot.ev[kEvBuild]);
+    r->pairs_ms = event_ms(slot.ev[kEvBuild], slot.ev[kEvPairs]);
+    r->d2h_ms = event_ms(slot.ev[kEvPairs], slot.ev[kEvHead]) + event_ms(slot.ev[kEvTail0], slot.ev[kEvTail1]);
     pdp_plan_info info;
     pdp_plan_info_get(r->plan, &info);
     const HostLayout L{static_cast<const char *>(r->out->p), info.bh_rows, info.bbh_rows};
@@ -422,7 +462,7 @@ void worker_loop(pdp_server *S) {
                 }
                 done = h != 2;
             } else {
-                collect(S, r);
+                collect(S, slot, r);
             }
             S->arena->release(r->dev_off, r->dev_bytes);
             slot.req = nullptr;
@@ -440,20 +480,8 @@ void worker_loop(pdp_server *S) {
                 }
             if (!free_slot) break;
             ServeRequest *r = S->pending.front();
-            int32_t rc = PDP_OK;
-            if (!r->planned) {
-                // A provisional plan gives the footprint: the descriptor is bound to a placeholder
-                // address (planning reads only its sizes); launch_request moves the plan's pointers
-                // once the memory is placed.  Both are kept while the request waits for memory.
-                uint64_t dict_bytes = 0, build_ws = 0;
-                rc = pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, S->cfg.alphabet, &dict_bytes, &build_ws);
-                if (rc == PDP_OK)
-                    rc = pdp_dict_bind(reinterpret_cast<void *>(uintptr_t(256)), dict_bytes, r->n_genes, r->n_res,
-                                       S->cfg.k, S->cfg.alphabet, &r->dict);
-                if (rc == PDP_OK) rc = make_plan(S, r);
-                if (rc == PDP_OK) r->foot_bytes = footprint(S, r, &r->foot_plan_ws);
-                r->planned = rc == PDP_OK;
-            }
+            // normally planned by pdp_server_submit; again here after a capacity retry
+            int32_t rc = r->planned ? PDP_OK : prepare_plan(S, r);
             const uint64_t bytes = r->foot_bytes, plan_ws = r->foot_plan_ws;
             if (rc != PDP_OK || bytes == 0 || bytes > S->arena->size()) {
                 S->pending.pop_front();
@@ -531,6 +559,8 @@ int32_t pdp_server_create(const pdp_server_config *cfg, const pdp_dict *const *r
             hipEventCreateWithFlags(&slot.head, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) != hipSuccess)
             return api_fail(PDP_E_HIP, "pdp_server_create: stream or event creation failed");
+        for (hipEvent_t &e : slot.ev)
+            if (hipEventCreate(&e) != hipSuccess) return api_fail(PDP_E_HIP, "pdp_server_create: event creation failed");
     }
     S->t0 = std::chrono::steady_clock::now();
     pdp_server *raw = S.release();
@@ -542,6 +572,7 @@ int32_t pdp_server_create(const pdp_server_config *cfg, const pdp_dict *const *r
 int32_t pdp_server_submit(pdp_server *S, const uint8_t *residues, const uint64_t *gene_off, uint32_t n_genes,
                           uint64_t tag) {
     if (!S || !gene_off || (!residues && gene_off[n_genes])) return api_fail(PDP_E_INVAL, "pdp_server_submit: null argument");
+    const double t_in = now_us(S->t0);  // the request's latency counts from here, planning included
     if (gene_off[0] != 0) return api_fail(PDP_E_INVAL, "pdp_server_submit: gene_off[0] must be 0");
     for (uint32_t i = 0; i < n_genes; ++i)
         if (gene_off[i + 1] < gene_off[i]) return api_fail(PDP_E_INVAL, "pdp_server_submit: offsets decrease at gene %u", i);
@@ -558,16 +589,24 @@ int32_t pdp_server_submit(pdp_server *S, const uint8_t *residues, const uint64_t
         resident_entries += d.capacity;
         resident_genes += d.n_genes;
     }
-    // records, both directions: half the entries of every pair.  Arrivals share many k-mers with
-    // the residents (their genes come from resident families), and the one-pass join falls back to
-    // two passes when one tile's share of the capacity overflows, so the capacity is generous.
-    r->inc_cap = (resident_entries + S->residents.size() * (r->n_res + 1)) / 2 + 65536;
+    // records: half the entries of every pair with records for both directions, a quarter with
+    // column maxima (records for the request's rows only).  Arrivals share many k-mers with the
+    // residents (their genes come from resident families), and the one-pass join falls back to two
+    // passes when one tile's share of the capacity overflows, so the capacity is generous.
+    const uint64_t entries = resident_entries + S->residents.size() * (r->n_res + 1);
+    r->inc_cap = (S->cfg.params.flags & PDP_PARAM_COLMAX ? entries / 4 : entries / 2) + 65536;
     const uint64_t rows = uint64_t(n_genes) * S->residents.size() + resident_genes;
     r->bh_cap = rows + rows / 4 + 4096;
     r->bbh_cap = uint64_t(n_genes) * S->residents.size() * 3 / 4 + 4096;
+    // planning here, in the caller's thread, keeps it off the worker's loop (the worker plans
+    // again only when this fails, to report the error, or after a capacity retry)
+    (void)prepare_plan(S, r.get());
     std::lock_guard<std::mutex> lk(S->mu);
-    if (S->all.count(tag)) return api_fail(PDP_E_INVAL, "pdp_server_submit: tag already in use");
-    r->t_submit = now_us(S->t0);
+    if (S->all.count(tag)) {
+        if (r->plan) pdp_plan_destroy(r->plan);
+        return api_fail(PDP_E_INVAL, "pdp_server_submit: tag already in use");
+    }
+    r->t_submit = t_in;
     S->pending.push_back(r.get());
     S->all[tag] = std::move(r);
     S->cv.notify_all();
@@ -596,6 +635,10 @@ int32_t pdp_server_poll(pdp_server *S, pdp_request_done *done, uint32_t max, uin
         d.done_us = r->t_done;
         d.bh_entries = r->code == PDP_OK ? r->nbh : 0;
         d.bbh_pairs = r->code == PDP_OK ? r->nbb : 0;
+        d.h2d_ms = r->h2d_ms;
+        d.build_ms = r->build_ms;
+        d.pairs_ms = r->pairs_ms;
+        d.d2h_ms = r->d2h_ms;
     }
     *n_done = n;
     return S->fatal;
@@ -666,6 +709,8 @@ void pdp_server_destroy(pdp_server *S) {
     for (ServeSlot &slot : S->slots) {
         if (slot.stream) (void)hipStreamSynchronize(slot.stream);
         if (slot.req && slot.req->plan) pdp_plan_destroy(slot.req->plan);
+        for (hipEvent_t e : slot.ev)
+            if (e) (void)hipEventDestroy(e);
         if (slot.head) (void)hipEventDestroy(slot.head);
         if (slot.done) (void)hipEventDestroy(slot.done);
         if (slot.stream) (void)hipStreamDestroy(slot.stream);

@@ -2,7 +2,7 @@
 benchmark times: the first wave of the 400-instance batched workload (independent instances of
 U{4..30} genomes x U{500..5000} genes, k per instance by the rule, 128-row tiles and 512-entry
 join sub-ranges, not persistent) and full-size arrivals served against all 200 resident genomes
-of 4000 genes (k = 7 fixed from the residents).  Every genome pair is compared in full -- every
+of 4000 genes (k = 7 fixed from the residents; 4 slots, column maxima, 128-row tiles).  Every genome pair is compared in full -- every
 best-hit row both ways and the whole BBH set -- against the sparse oracle, whose agreement with
 the dense oracle and with brute force the CPU tests pin."""
 import numpy as np
@@ -82,7 +82,8 @@ def test_full_size_serving_complete():
     torch.cuda.synchronize()
     batch.check_status()
     arrivals = [wl.arrival(j) for j in range(3)]
-    srv = pdp.Server(batch.dicts, 32 << 30, slots=8, prm=pdp.params())
+    # the benchmark's serving configuration: 4 slots, column maxima, 128-row tiles
+    srv = pdp.Server(batch.dicts, 32 << 30, slots=4, prm=pdp.params(colmax=True, tile_rows=128))
     out = {}
     try:
         for j, g in enumerate(arrivals):

@@ -388,21 +388,22 @@ def test_full_size_family_model_complete():
     ds = make_config(2)
     k = pdp.k_rule(ds.total_residues())
     assert k == 6
-    say("full-size 10 x 3000 workload, k =", k)
-    dicts = [pdp.Dictionary.build_from(g, k) for g in ds.genomes]
-    runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts))
-    runner.run()
-    res = runner.results()
     og = oracle.genomes(ds.genomes, k)
     want = oracle.all_pairs_sparse(og, ds.pairs())
-    say("sparse oracle done; comparing 45 pairs")
+    dicts = [pdp.Dictionary.build_from(g, k) for g in ds.genomes]
     rng = np.random.default_rng(7)
-    for t, (i, j) in enumerate(ds.pairs()):
-        ab, ba, bb = res.best_hits(t, 0), res.best_hits(t, 1), res.bbh_pairs(t)
-        check_pair_complete(ab, ba, bb, want[(i, j)], ds.genomes[i].n_genes, ds.genomes[j].n_genes)
-        if t % 9 == 0:
-            rows = np.sort(rng.choice(ds.genomes[i].n_genes, 24, replace=False))
-            check_bh(ab, oracle.bh(og[i], og[j], rows=rows), rows=rows)
+    # the launch shapes the benchmark's autotuner chooses between
+    for prm in (pdp.params(), pdp.params(colmax=True), pdp.params(colmax=True, tile_rows=128)):
+        say("full-size 10 x 3000 workload, k =", k, "column maxima", bool(prm.flags & 2), "tile rows", prm.tile_rows)
+        runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts), prm)
+        runner.run()
+        res = runner.results()
+        for t, (i, j) in enumerate(ds.pairs()):
+            ab, ba, bb = res.best_hits(t, 0), res.best_hits(t, 1), res.bbh_pairs(t)
+            check_pair_complete(ab, ba, bb, want[(i, j)], ds.genomes[i].n_genes, ds.genomes[j].n_genes)
+            if t % 9 == 0:
+                rows = np.sort(rng.choice(ds.genomes[i].n_genes, 24, replace=False))
+                check_bh(ab, oracle.bh(og[i], og[j], rows=rows), rows=rows)
 
 
 @pytest.mark.timeout(900)
@@ -417,17 +418,23 @@ def test_full_size_large_workload_complete():
     dicts = pdp.DictionaryBatch([pdp.DeviceGenome.of(g) for g in ds.genomes], k)
     dicts.build()
     dicts.check_status()
-    runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts.dicts))
-    runner.run()
-    res = runner.results()
-    del runner, dicts
+    # the default launch shape and the one the benchmark's autotuner picks on this workload
+    results = []
+    for prm in (pdp.params(), pdp.params(colmax=True, tile_rows=128)):
+        runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts.dicts), prm)
+        runner.run()
+        results.append(runner.results())
+        del runner
+    del dicts
     og = oracle.genomes(ds.genomes, k)
     want = oracle.all_pairs_sparse(og, ds.pairs())
-    say("sparse oracle done; comparing 1225 pairs")
+    say("sparse oracle done; comparing 1225 pairs in two launch shapes")
     ties = 0
     for t, (i, j) in enumerate(ds.pairs()):
-        ab, ba, bb = res.best_hits(t, 0), res.best_hits(t, 1), res.bbh_pairs(t)
-        check_pair_complete(ab, ba, bb, want.pop((i, j)), ds.genomes[i].n_genes, ds.genomes[j].n_genes)
+        w = want.pop((i, j))
+        for res in results:
+            ab, ba, bb = res.best_hits(t, 0), res.best_hits(t, 1), res.bbh_pairs(t)
+            check_pair_complete(ab, ba, bb, w, ds.genomes[i].n_genes, ds.genomes[j].n_genes)
         ties += int(np.sum(np.diff(ab[0].astype(np.int64)) > 1))
     assert ties > 0, "the paralog copies should give tied best hits"
 

@@ -32,8 +32,8 @@ def workload():
     return wl, residents, arrivals
 
 
-def run_server(residents, arrivals, slots, budget=1 << 30, one_at_a_time=False):
-    srv = pdp.Server(residents, budget, slots=slots)
+def run_server(residents, arrivals, slots, budget=1 << 30, one_at_a_time=False, prm=None):
+    srv = pdp.Server(residents, budget, slots=slots, prm=prm)
     out = {}
     try:
         if one_at_a_time:
@@ -63,6 +63,28 @@ def test_served_results_match_oracle(workload):
     say("serving: 6 requests x 4 residents, 3 slots")
     out, stats = run_server(residents, arrivals, slots=3)
     assert stats.completed == 6 and stats.peak_inflight >= 2
+    og_res = [oracle.OracleGenome(g, K) for g in wl.residents.genomes]
+    for j, g in enumerate(arrivals):
+        d, res = out[j]
+        assert d.code == 0 and res.code == 0
+        # the device times of the request's phases, from events on its slot's stream
+        assert d.h2d_ms > 0 and d.build_ms > 0 and d.pairs_ms > 0 and d.d2h_ms > 0
+        assert d.h2d_ms + d.build_ms + d.pairs_ms + d.d2h_ms <= (d.done_us - d.admit_us) / 1e3 + 0.5
+        q = oracle.OracleGenome(g, K)
+        for r, og in enumerate(og_res):
+            ab, ba = oracle.bh(q, og), oracle.bh(og, q)
+            check_bh(res.best_hits(r, 0), ab)
+            check_bh(res.best_hits(r, 1), ba)
+            check_bbh(res.bbh_pairs(r), oracle.bbh(ab, ba))
+
+
+def test_served_with_column_maxima_and_tall_tiles(workload):
+    # the benchmark's serving parameters: the residents' best hits from the column maxima of the
+    # request's rows, 128-row tiles
+    wl, residents, arrivals = workload
+    say("serving with column maxima and 128-row tiles: 6 requests x 4 residents, 4 slots")
+    out, stats = run_server(residents, arrivals, slots=4, prm=pdp.params(colmax=True, tile_rows=128))
+    assert stats.completed == 6
     og_res = [oracle.OracleGenome(g, K) for g in wl.residents.genomes]
     for j, g in enumerate(arrivals):
         d, res = out[j]
