@@ -46,6 +46,12 @@ def parse():
     p.add_argument("--no-latency", action="store_true", help="skip the serving run that gives p50/p99 latency")
     p.add_argument("--breakdown", action="store_true", help="also time every kernel group (extra launches)")
     p.add_argument("--calibrate-copy", action="store_true", help="only run a copy of known size (counter calibration)")
+    p.add_argument("--counters-to-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                   default=None,
+                   help="no GPU: turn four rocprofv3 --pmc output folders (FETCH_SIZE and WRITE_SIZE of this "
+                        "benchmark, then of --calibrate-copy) into the workload's entry of --traffic for the current "
+                        "sources, in the launch shape given by --workload/--alphabet/--tile-rows/--colmax/--two-pass, "
+                        "and print a markdown table")
     p.add_argument("--no-tune", action="store_true",
                    help="library defaults instead of the autotuner's pick of tile height and column maxima")
     p.add_argument("--tune-all", action="store_true",
@@ -76,7 +82,9 @@ def parse():
     p.add_argument("--resident-genes", type=int, default=4000, help="serving: genes per resident")
     p.add_argument("--arrivals", type=int, default=2000, help="serving: arriving genomes (of the 2000-arrival stream)")
     p.add_argument("--load", type=float, default=0.8, help="serving: offered load as a fraction of closed-loop capacity")
-    p.add_argument("--slots", type=int, default=4, help="serving: concurrent request slots")
+    p.add_argument("--light-load", type=float, default=0.5,
+                   help="serving: a second pass of the arrivals at this load (0: none), where queueing adds little")
+    p.add_argument("--slots", type=int, default=2, help="serving: concurrent request slots")
     p.add_argument("--budget-gb", type=float, default=32.0, help="serving: HBM budget for requests in flight")
     p.add_argument("--serve-no-colmax", action="store_true",
                    help="serving: the residents' best hits from their own rows instead of column maxima")
@@ -253,6 +261,83 @@ def calibrate_copy(mib: int = 1024) -> None:
     torch.cuda.synchronize()
     print(json.dumps({"calibration": "elementwise int32 copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
                       "launches": 3}), flush=True)
+
+
+# kernel groups of the traffic table: the group's kernels by name prefix
+TRAFFIC_GROUPS = {"join": ("pdp::k_join_fused",),
+                  "tile_count": ("void pdp::k_tile_count",),
+                  "join_backup": ("void pdp::k_join_persistent", "void pdp::k_join<", "pdp::k_tile_ranges"),
+                  "dictionary_build": ("pdp::k_mv", "void pdp::k_mv", "pdp::k_ix", "void pdp::k_ix")}
+
+
+def _counter_rows(folder: str, counter: str):
+    """{kernel name: [per-dispatch values]} of one counter from a rocprofv3 --pmc csv folder."""
+    import csv
+    import glob
+
+    out = {}
+    for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def counters_to_traffic(args) -> None:
+    """Calibrated HBM bytes per launch of each kernel group from FETCH_SIZE / WRITE_SIZE runs (KiB per
+    dispatch), scaled by what the same counters read for a copy of 1 GiB read and 1 GiB written."""
+    fetch_dir, write_dir, cf_dir, cw_dir = args.counters_to_traffic
+    gib_kib = float(1 << 20)
+    copy_f = max(_counter_rows(cf_dir, "FETCH_SIZE").items(), key=lambda kv: sum(kv[1]))[1]
+    copy_w = max(_counter_rows(cw_dir, "WRITE_SIZE").items(), key=lambda kv: sum(kv[1]))[1]
+    ff = gib_kib / (sum(copy_f) / len(copy_f))
+    wf = gib_kib / (sum(copy_w) / len(copy_w))
+    fetch, write = _counter_rows(fetch_dir, "FETCH_SIZE"), _counter_rows(write_dir, "WRITE_SIZE")
+    groups, lines = {}, []
+    for name in sorted(set(fetch) | set(write)):
+        grp = next((g for g, pre in TRAFFIC_GROUPS.items() if any(name.startswith(x) for x in pre)), None)
+        if grp is None:
+            continue
+        fk = sum(fetch.get(name, [0.0])) / max(1, len(fetch.get(name, [])))
+        wk = sum(write.get(name, [0.0])) / max(1, len(write.get(name, [])))
+        b = ff * fk * 1024 + wf * wk * 1024
+        g = groups.setdefault(grp, {"hbm_bytes_per_launch": 0.0, "fetch_kib": 0.0, "write_kib": 0.0})
+        g["hbm_bytes_per_launch"] += b
+        g["fetch_kib"] += fk
+        g["write_kib"] += wk
+        lines.append((grp, name.split("(")[0], len(fetch.get(name, [])), fk, wk, b))
+    for g in groups.values():
+        g["hbm_bytes_per_launch"] = int(round(g["hbm_bytes_per_launch"]))
+        g["fetch_kib"] = round(g["fetch_kib"], 1)
+        g["write_kib"] = round(g["write_kib"], 1)
+    large = args.workload == "large"
+    nt = args.alphabet == "nt"
+    wl_key = ("large" if large else "allpairs") + ("_nt" if nt else "")
+    try:
+        with open(args.traffic) as f:
+            tr = json.load(f)
+    except (OSError, ValueError):
+        tr = {}
+    if tr.get("source_hash") != source_hash():
+        tr = {"workloads": {}}  # counters of other sources say nothing about these kernels
+    tr["source_hash"] = source_hash()
+    tr["calibration"] = {"kernel": "elementwise int32 copy (1 GiB read, 1 GiB written)",
+                         "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)}
+    tr.setdefault("workloads", {})[wl_key] = {
+        "shape": {"tile_rows": int(args.tile_rows or 64), "column_maxima": bool(args.colmax),
+                  "two_pass": bool(args.two_pass)},
+        "kernels": groups}
+    with open(args.traffic, "w") as f:
+        json.dump(tr, f, indent=1)
+        f.write("\n")
+    print(f"calibration: FETCH_SIZE x 1024 x {ff:.4f}, WRITE_SIZE x 1024 x {wf:.4f}; source hash {tr['source_hash']}")
+    print("| kernel group | kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes |")
+    print("|---|---|---:|---:|---:|---:|")
+    for grp, name, n, fk, wk, b in sorted(lines, key=lambda x: -x[5]):
+        print(f"| {grp} | `{name}` | {n} | {fk:.0f} | {wk:.0f} | {b / 1e9:.3f} GB |")
+    for grp, g in groups.items():
+        print(f"| **{grp}** | **bytes per launch (calibrated)** | | | | **{g['hbm_bytes_per_launch'] / 1e9:.3f} GB** |")
 
 
 def _pool_map(fn, items):
@@ -457,6 +542,38 @@ def serve_stream(args, wl, arrivals):
                 done[d.tag] = d
                 srv.release(d.tag)
 
+    def open_loop(load, tag0):
+        """Every arrival submitted at its Poisson time rescaled to load x capacity; per-request records."""
+        lam = load * capacity
+        times = wl.arrival_times[:n] / lam  # unit-rate Poisson times rescaled to rate lam
+        done = {}
+        start = time.perf_counter()
+        for j in range(n):
+            while time.perf_counter() - start < times[j]:
+                for d in srv.poll(64, wait_us=0):
+                    done[d.tag] = d
+                    srv.release(d.tag)
+            srv.submit(arrivals[j], tag0 + j)
+        drain(n, done)
+        wall = time.perf_counter() - start
+        bad = [d.code for d in done.values() if d.code != 0]
+        if bad:
+            raise SystemExit(f"{len(bad)} requests failed, first code {bad[0]}")
+        lat = [(d.done_us - d.submit_us) / 1e3 for d in done.values()]
+        svc = [(d.done_us - d.admit_us) / 1e3 for d in done.values()]
+        wait = [(d.admit_us - d.submit_us) / 1e3 for d in done.values()]
+        phases = {}
+        for name in ("h2d_ms", "build_ms", "pairs_ms", "d2h_ms"):
+            xs = [getattr(d, name) for d in done.values()]
+            phases[name[:-3]] = {"p50_ms": round(_pctl(xs, 50), 3), "p99_ms": round(_pctl(xs, 99), 3)}
+        return {"offered_load": load, "offered_rate_per_s": round(lam, 2), "genomes_per_s": round(n / wall, 2),
+                "p50_ms": round(_pctl(lat, 50), 3), "p99_ms": round(_pctl(lat, 99), 3), "max_ms": round(max(lat), 3),
+                "service_p50_ms": round(_pctl(svc, 50), 3), "service_p99_ms": round(_pctl(svc, 99), 3),
+                "admission_wait_p99_ms": round(_pctl(wait, 99), 3), "device_phases": phases,
+                "gene_pairs_per_s": round(gp / wall, 1), "attempts_max": int(max(d.attempts for d in done.values())),
+                "join_two_passes": sum(1 for d in done.values() if d.flags & pdp.PDP_STATUS_TWO_PASS)}
+
+    gp = sum(int(g.n_genes) * res_genes for g in arrivals)
     try:
         # closed loop: the first arrivals submitted at once (admission under the budget), rate =
         # completions/s; the server keeps nothing of a request after its release, so the same
@@ -468,52 +585,30 @@ def serve_stream(args, wl, arrivals):
         drain(warm, done)
         cap_s = time.perf_counter() - tw
         capacity = warm / cap_s
-        say(f"serving: closed-loop capacity {capacity:.1f} genomes/s; open loop of {n} arrivals")
-        # open loop at the offered load
-        lam = args.load * capacity
-        times = wl.arrival_times[:n] / lam  # unit-rate Poisson times rescaled to rate lam
-        done = {}
-        start = time.perf_counter()
-        for j in range(n):
-            while time.perf_counter() - start < times[j]:
-                for d in srv.poll(64, wait_us=0):
-                    done[d.tag] = d
-                    srv.release(d.tag)
-            srv.submit(arrivals[j], j)
-        drain(n, done)
-        wall = time.perf_counter() - start
+        say(f"serving: closed-loop capacity {capacity:.1f} genomes/s; open loop of {n} arrivals at {args.load}")
+        main = open_loop(args.load, 0)
+        light = None
+        if args.light_load:
+            say(f"serving: open loop of {n} arrivals at {args.light_load}")
+            light = open_loop(args.light_load, 2 * 10 ** 6)
         stats = srv.stats()
     finally:
         srv.close()
         del srv, batch, devs
         torch.cuda.empty_cache()
-    bad = [d.code for d in done.values() if d.code != 0]
-    if bad:
-        raise SystemExit(f"{len(bad)} requests failed, first code {bad[0]}")
-    lat = [(d.done_us - d.submit_us) / 1e3 for d in done.values()]
-    svc = [(d.done_us - d.admit_us) / 1e3 for d in done.values()]
-    wait = [(d.admit_us - d.submit_us) / 1e3 for d in done.values()]
-    phases = {}
-    for name in ("h2d_ms", "build_ms", "pairs_ms", "d2h_ms"):
-        xs = [getattr(d, name) for d in done.values()]
-        phases[name[:-3]] = {"p50_ms": round(_pctl(xs, 50), 3), "p99_ms": round(_pctl(xs, 99), 3)}
-    gp = sum(int(g.n_genes) * res_genes for g in arrivals)
-    return {"genomes_per_s": round(n / wall, 2), "p50_ms": round(_pctl(lat, 50), 3), "p99_ms": round(_pctl(lat, 99), 3),
-            "max_ms": round(max(lat), 3), "service_p50_ms": round(_pctl(svc, 50), 3),
-            "service_p99_ms": round(_pctl(svc, 99), 3), "admission_wait_p99_ms": round(_pctl(wait, 99), 3),
-            "device_phases": phases,
-            "closed_loop_genomes_per_s": round(capacity, 2), "offered_rate_per_s": round(lam, 2),
-            "gene_pairs_per_s": round(gp / wall, 1), "arrivals": n, "retries": int(stats.retries),
-            "attempts_max": int(max(d.attempts for d in done.values())),
-            "join_two_passes": sum(1 for d in done.values() if d.flags & pdp.PDP_STATUS_TWO_PASS),
-            "peak_inflight": int(stats.peak_inflight), "peak_used_gb": round(stats.peak_used_bytes / 2 ** 30, 2),
-            "workload": f"serving: {len(wl.residents.genomes)} resident genomes x "
-                        f"{wl.residents.genomes[0].n_genes} genes (k = {k}), first {n} of 2000 Poisson arrivals "
-                        f"(U{{1000..6000}} genes drawn from resident families), offered load {args.load} of the "
-                        f"closed-loop capacity, {args.slots} slots, {args.budget_gb} GB budget, "
-                        f"{args.serve_tile_rows}-row tiles, column maxima {'off' if args.serve_no_colmax else 'on'}",
-            "note": "latency = completion - submission, including admission wait, the host-to-device copy of the "
-                    "arriving genome and the copy of its results to host memory"}
+    out = dict(main)
+    out.update({"arrivals": n, "closed_loop_genomes_per_s": round(capacity, 2), "retries": int(stats.retries),
+                "peak_inflight": int(stats.peak_inflight), "peak_used_gb": round(stats.peak_used_bytes / 2 ** 30, 2),
+                "workload": f"serving: {len(wl.residents.genomes)} resident genomes x "
+                            f"{wl.residents.genomes[0].n_genes} genes (k = {k}), first {n} of 2000 Poisson arrivals "
+                            f"(U{{1000..6000}} genes drawn from resident families), offered load {args.load} of the "
+                            f"closed-loop capacity, {args.slots} slots, {args.budget_gb} GB budget, "
+                            f"{args.serve_tile_rows}-row tiles, column maxima {'off' if args.serve_no_colmax else 'on'}",
+                "note": "latency = completion - submission, including planning, admission wait, the host-to-device "
+                        "copy of the arriving genome and the copy of its results to host memory"})
+    if light is not None:
+        out["light_load"] = light
+    return out
 
 
 def run_serving(args):
@@ -543,6 +638,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.counters_to_traffic:
+        counters_to_traffic(args)
         return
     if args.workload == "batched":
         run_batched(args)
@@ -671,11 +769,15 @@ def main():
     step_gbs, step_frac = _frac(step_bytes, ms_per_step)
     traffic, measured = None, None
     wl_key = ("large" if large else "allpairs") + ("_nt" if nt else "")
+    shape = {"tile_rows": int(prm.tile_rows or 64), "column_maxima": bool(prm.flags & B.PDP_PARAM_COLMAX),
+             "two_pass": two_pass}
     try:
         with open(args.traffic) as f:
             tr = json.load(f)
-        kernels = tr.get("workloads", {}).get(wl_key, {}).get("kernels", {})
-        if tr.get("source_hash") == source_hash() and args.kernel in kernels and not (args.two_pass or args.colmax):
+        wl_tr = tr.get("workloads", {}).get(wl_key, {})
+        kernels = wl_tr.get("kernels", {})
+        # counters hold for these kernels in the launch shape they were taken in
+        if tr.get("source_hash") == source_hash() and args.kernel in kernels and wl_tr.get("shape") == shape:
             traffic = kernels[args.kernel]["hbm_bytes_per_launch"]
             measured = dict(zip(("achieved", "frac"), _frac(traffic, avg_kernel_ms)))
     except (OSError, ValueError):

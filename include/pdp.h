@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PDP_ABI_VERSION 5u
+#define PDP_ABI_VERSION 6u
 
 /* The two alphabets of the Basic notions section.  A dictionary's alphabet
  * fixes how a letter becomes a symbol, the symbol width of a k-mer code and
@@ -49,10 +49,21 @@ enum pdp_alphabet {
  * (nucleotides) bits, below the all-ones value the kernels use as padding. */
 #define PDP_K_MAX 12u
 #define PDP_K_MAX_NT 31u
-/* A gene may have at most this many k-mer windows (|g| - k + 1); longer genes
- * are rejected with PDP_E_LIMIT in the device status.  Every multiplicity and
- * every sum of minima then fits in 16 bits. */
+/* A gene may have at most this many k-mer windows (|g| - k + 1) unless its
+ * dictionary is bound with PDP_DICT_LONG_GENES; longer genes are rejected with
+ * PDP_E_LIMIT in the device status.  Every multiplicity and every sum of
+ * minima then fits in 16 bits, which the default pair path relies on. */
 #define PDP_MAX_WINDOWS 65535u
+/* pdp_dict_bind flags.  PDP_DICT_LONG_GENES: genes may have up to
+ * PDP_MAX_WINDOWS_LONG windows.  Multiplicities and sums of minima (Eq.
+ * kmer_multiplicity, Eq. jaccard_k) are then carried in 32 bits: every task
+ * that names such a dictionary takes the long-gene path, which computes each
+ * best-hit row on its own from the row gene's multiplicity vector and the
+ * other genome's index (no shared-k-mer records, no column maxima).  It gives
+ * the same results as the default path, more slowly; set the flag only for
+ * genomes that hold such a gene. */
+#define PDP_DICT_LONG_GENES 1u
+#define PDP_MAX_WINDOWS_LONG 2147483647u
 /* A genome may hold at most this many genes (column indices are 24-bit). */
 #define PDP_MAX_GENES 16777215u
 
@@ -66,7 +77,7 @@ enum pdp_code {
                              host: an unknown pdp_alphabet value */
     PDP_E_HIP = -6,       /* a HIP runtime call failed */
     PDP_E_BUDGET = -7,    /* serving: a request cannot fit the admission budget */
-    PDP_E_LIMIT = -8,     /* a size beyond PDP_MAX_WINDOWS / PDP_MAX_GENES / 2^32 entries */
+    PDP_E_LIMIT = -8,     /* a size beyond PDP_MAX_WINDOWS(_LONG) / PDP_MAX_GENES / 2^32 entries */
     PDP_E_UNIMPL = -9
 };
 
@@ -137,6 +148,8 @@ typedef struct pdp_dict {
     uint32_t key_shift;   /* gene bits of ix_key; 0: this dictionary has no packed keys */
     uint32_t alphabet;    /* pdp_alphabet */
     uint32_t lead;        /* leading letters that name a k-mer's bucket */
+    uint32_t flags;       /* PDP_DICT_* given to pdp_dict_bind */
+    uint32_t reserved;
     uint32_t *nwin;       /* [n_genes] windows per gene, max(0, |g|-k+1) */
     uint32_t *mv_ptr;     /* [n_genes+1] CSR offsets; mv_ptr[n_genes] = entries E */
     uint64_t *mv_code;    /* [capacity] codes, strictly ascending inside a gene */
@@ -163,15 +176,17 @@ int32_t pdp_dict_size(uint32_t n_genes, uint64_t n_residues, uint32_t k, uint32_
                       uint64_t *arena_bytes, uint64_t *ws_bytes);
 
 /* Points the arrays of *out into a caller-allocated device arena (256-byte
- * aligned, at least pdp_dict_size's arena_bytes).  Enqueues nothing.
- * Errors: PDP_E_INVAL, PDP_E_WORKSPACE (arena too small), as pdp_dict_size. */
+ * aligned, at least pdp_dict_size's arena_bytes).  flags: 0 or
+ * PDP_DICT_LONG_GENES.  Enqueues nothing.  Errors: PDP_E_INVAL (also unknown
+ * flags), PDP_E_WORKSPACE (arena too small), as pdp_dict_size. */
 int32_t pdp_dict_bind(void *arena, uint64_t arena_bytes, uint32_t n_genes, uint64_t n_residues,
-                      uint32_t k, uint32_t alphabet, pdp_dict *out);
+                      uint32_t k, uint32_t alphabet, uint32_t flags, pdp_dict *out);
 
 /* Builds the dictionary of genome g into d (bound with the same n_genes,
  * n_residues, k and alphabet).  ws is device scratch of pdp_dict_size's ws_bytes.
  * Gene i keeps index i.  Device errors (in d->status): PDP_E_ALPHABET,
- * PDP_E_LIMIT (a gene with more than PDP_MAX_WINDOWS windows).
+ * PDP_E_LIMIT (a gene with more than PDP_MAX_WINDOWS windows, or
+ * PDP_MAX_WINDOWS_LONG with PDP_DICT_LONG_GENES; where = the gene).
  * Errors: PDP_E_INVAL (sizes differ from the bind), PDP_E_WORKSPACE, PDP_E_HIP. */
 int32_t pdp_dict_build(const pdp_genome *g, pdp_dict *d, void *ws, uint64_t ws_bytes, void *stream);
 
@@ -285,12 +300,17 @@ typedef struct pdp_plan_info {
     uint32_t join_groups;     /* join items (bucket ranges) per run */
     uint32_t tiles;           /* accumulation tiles per run */
     uint32_t tile_lds;        /* LDS bytes per accumulation tile */
+    uint32_t long_rows;       /* best-hit rows of the tasks that take the long-gene path */
+    uint32_t reserved;
 } pdp_plan_info;
 
 /* Builds a plan for n_tasks tasks.  Best-hit rows of the combined output are
  * laid out task by task: first a's genes (if AB), then b's genes (if BA); BBH
  * rows are a's genes of every task with PDP_TASK_BBH, task by task.
- * pdp_plan_rows gives each task's first row in both outputs.  Host only.
+ * pdp_plan_rows gives each task's first row in both outputs.  A task that
+ * names a dictionary bound with PDP_DICT_LONG_GENES has no join items and no
+ * tiles: its rows take the long-gene path (and PDP_PARAM_COLMAX does not apply
+ * to it), with the same output layout.  Host only.
  * Errors: PDP_E_INVAL (null, k or alphabet mismatch, BBH without AB|BA), PDP_E_LIMIT. */
 int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_params *params, pdp_plan **out);
 int32_t pdp_plan_info_get(const pdp_plan *plan, pdp_plan_info *info);
@@ -461,7 +481,9 @@ typedef struct pdp_server_stats {
  * Errors: PDP_E_INVAL, PDP_E_WORKSPACE, PDP_E_HIP. */
 int32_t pdp_server_create(const pdp_server_config *cfg, const pdp_dict *const *residents, uint32_t n_residents,
                           void *arena, uint64_t arena_bytes, pdp_server **out);
-/* Queues one genome (host arrays, copied before return); tag must be unused. */
+/* Queues one genome (host arrays, copied before return); tag must be unused.
+ * A genome with a gene past PDP_MAX_WINDOWS windows gets a dictionary bound
+ * with PDP_DICT_LONG_GENES, so its pairs take the long-gene path. */
 int32_t pdp_server_submit(pdp_server *server, const uint8_t *residues, const uint64_t *gene_off, uint32_t n_genes,
                           uint64_t tag);
 /* Up to max finished requests not yet reported, oldest first; waits up to

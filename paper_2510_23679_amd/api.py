@@ -90,6 +90,11 @@ class DeviceGenome:
         self.offsets = torch.from_numpy(off.view(np.int64)).to(dev)
         self.n_genes = int(off.shape[0] - 1)
         self.n_residues = int(off[-1]) if off.size else 0
+        self.longest = int(np.diff(off).max()) if self.n_genes else 0  # letters of the longest gene
+
+    def long_genes(self, k: int) -> bool:
+        """True when a gene has more than PDP_MAX_WINDOWS k-mer windows (the long-gene path)."""
+        return self.longest >= k and self.longest - k + 1 > B.PDP_MAX_WINDOWS
 
     @classmethod
     def of(cls, genome) -> "DeviceGenome":
@@ -119,12 +124,14 @@ def new_status() -> torch.Tensor:
 class Dictionary:
     """The k-mer dictionary of one genome (multiplicity vectors + inverted index), on device."""
 
-    def __init__(self, n_genes: int, n_residues: int, k: int, alphabet: str = "aa"):
+    def __init__(self, n_genes: int, n_residues: int, k: int, alphabet: str = "aa", long_genes: bool = False):
         arena_bytes, ws_bytes = dict_size(n_genes, n_residues, k, alphabet)
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=_device())
         self.d = B.pdp_dict()
+        flags = B.PDP_DICT_LONG_GENES if long_genes else 0
         check(lib().pdp_dict_bind(self.arena.data_ptr(), arena_bytes, int(n_genes), int(n_residues), int(k),
-                                  B.alphabet_id(alphabet), C.byref(self.d)), "pdp_dict_bind")
+                                  B.alphabet_id(alphabet), flags, C.byref(self.d)), "pdp_dict_bind")
+        self.long_genes = bool(long_genes)
         self.ws_bytes = ws_bytes
         self.k = int(k)
         self.alphabet = alphabet
@@ -136,7 +143,7 @@ class Dictionary:
     def build_from(cls, genome, k: int, ws: Optional[Workspace] = None,
                    stream: Optional[torch.cuda.Stream] = None) -> "Dictionary":
         dg = genome if isinstance(genome, DeviceGenome) else DeviceGenome.of(genome)
-        d = cls(dg.n_genes, dg.n_residues, k, dg.alphabet)
+        d = cls(dg.n_genes, dg.n_residues, k, dg.alphabet, long_genes=dg.long_genes(k))
         d.build(dg, ws, stream)
         return d
 
@@ -181,7 +188,8 @@ class DictionaryBatch:
     def __init__(self, genomes: Sequence[DeviceGenome], k, ws: Optional[Workspace] = None):
         ks = list(k) if isinstance(k, (list, tuple)) else [int(k)] * len(genomes)
         self.genomes = list(genomes)
-        self.dicts = [Dictionary(g.n_genes, g.n_residues, kk, g.alphabet) for g, kk in zip(self.genomes, ks)]
+        self.dicts = [Dictionary(g.n_genes, g.n_residues, kk, g.alphabet, long_genes=g.long_genes(kk))
+                      for g, kk in zip(self.genomes, ks)]
         n = len(self.genomes)
         self._g = (B.pdp_genome * n)(*[g.struct() for g in self.genomes])
         self._d = (C.POINTER(B.pdp_dict) * n)(*[C.pointer(d.d) for d in self.dicts])

@@ -47,6 +47,8 @@ def alphabet_id(alphabet) -> int:
         raise ValueError(f"unknown alphabet {alphabet!r} (expected 'aa' or 'nt')")
     return ALPHABET_IDS[alphabet]
 PDP_MAX_WINDOWS = 65535
+PDP_MAX_WINDOWS_LONG = 2147483647
+PDP_DICT_LONG_GENES = 1  # pdp_dict_bind flag: genes up to PDP_MAX_WINDOWS_LONG windows (the long-gene path)
 
 # kernels that pdp_plan_timer_start can time
 PDP_NOALLOC_SCRATCH_BYTES = 64 << 20  # include/pdp.h: the fixed scratch of pdp_bh_noalloc
@@ -64,7 +66,7 @@ class pdp_genome(C.Structure):
 
 class pdp_dict(C.Structure):
     _fields_ = [("n_genes", u32), ("k", u32), ("capacity", u64), ("n_buckets", u32), ("key_shift", u32),
-                ("alphabet", u32), ("lead", u32), ("nwin", vp), ("mv_ptr", vp), ("mv_code", vp), ("mv_cnt", vp), ("ix_dir", vp),
+                ("alphabet", u32), ("lead", u32), ("flags", u32), ("reserved", u32), ("nwin", vp), ("mv_ptr", vp), ("mv_code", vp), ("mv_cnt", vp), ("ix_dir", vp),
                 ("ix_code", vp), ("ix_gene", vp), ("ix_cnt", vp), ("ix_key", vp), ("status", vp)]
 
 
@@ -89,7 +91,7 @@ class pdp_task(C.Structure):
 
 class pdp_plan_info(C.Structure):
     _fields_ = [("ws_bytes", u64), ("inc_capacity", u64), ("bh_rows", u32), ("bbh_rows", u32), ("n_tasks", u32),
-                ("join_groups", u32), ("tiles", u32), ("tile_lds", u32)]
+                ("join_groups", u32), ("tiles", u32), ("tile_lds", u32), ("long_rows", u32), ("reserved", u32)]
 
 
 class pdp_tune_result(C.Structure):
@@ -131,7 +133,7 @@ SIGNATURES = {
     "pdp_last_error": (C.c_char_p, []),
     "pdp_k_rule": (i32, [u64, u32, i32, C.POINTER(u32)]),
     "pdp_dict_size": (i32, [u32, u64, u32, u32, C.POINTER(u64), C.POINTER(u64)]),
-    "pdp_dict_bind": (i32, [vp, u64, u32, u64, u32, u32, C.POINTER(pdp_dict)]),
+    "pdp_dict_bind": (i32, [vp, u64, u32, u64, u32, u32, u32, C.POINTER(pdp_dict)]),
     "pdp_dict_build": (i32, [C.POINTER(pdp_genome), C.POINTER(pdp_dict), vp, u64, vp]),
     "pdp_dict_build_many_ws_size": (i32, [C.POINTER(pdp_genome), C.POINTER(C.POINTER(pdp_dict)), u32, C.POINTER(u64)]),
     "pdp_dict_build_many": (i32, [C.POINTER(pdp_genome), C.POINTER(C.POINTER(pdp_dict)), u32, vp, u64, vp]),
@@ -179,7 +181,7 @@ class PdpError(RuntimeError):
         self.code = code
 
 
-ABI_VERSION = 5  # the layout of the structures above; include/pdp.h defines the same number
+ABI_VERSION = 6  # the layout of the structures above; include/pdp.h defines the same number
 
 
 def lib():

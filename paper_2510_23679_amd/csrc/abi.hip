@@ -47,6 +47,7 @@ struct pdp_plan {
     std::vector<DevTask> tasks;
     std::vector<DevTile> tiles;
     std::vector<DevItem> items;
+    std::vector<DevLongSeg> long_segs;  // long-gene path: row segments by first row
     std::vector<uint32_t> ab_row, ba_row, bbh_row;
     std::vector<uint32_t> order;  // order[t]: position of caller task t in the task table
     PlanShape shape;
@@ -152,8 +153,9 @@ int32_t pdp_dict_size(uint32_t n_genes, uint64_t n_residues, uint32_t k, uint32_
 }
 
 int32_t pdp_dict_bind(void *arena, uint64_t arena_bytes, uint32_t n_genes, uint64_t n_residues, uint32_t k,
-                      uint32_t alphabet, pdp_dict *out) {
+                      uint32_t alphabet, uint32_t flags, pdp_dict *out) {
     if (!arena || !out) return fail(PDP_E_INVAL, "pdp_dict_bind: null pointer");
+    if (flags & ~PDP_DICT_LONG_GENES) return fail(PDP_E_INVAL, "pdp_dict_bind: unknown flags 0x%x", flags);
     if (reinterpret_cast<uintptr_t>(arena) % 256) return fail(PDP_E_INVAL, "pdp_dict_bind: arena not 256-byte aligned");
     int32_t rc = dict_check(n_genes, n_residues, k, alphabet);
     if (rc) return rc;
@@ -184,6 +186,7 @@ int32_t pdp_dict_bind(void *arena, uint64_t arena_bytes, uint32_t n_genes, uint6
     d.key_shift = key_shift_for(n_genes, k, alphabet);
     d.alphabet = alphabet;
     d.lead = lead_letters(k, alphabet);
+    d.flags = flags;
     d.status = reinterpret_cast<pdp_status *>(take(sizeof(pdp_status)));
     *out = d;
     return ok();
@@ -198,7 +201,8 @@ static int32_t build_check(const pdp_genome *genomes, pdp_dict *const *dicts, ui
         if (!d) return fail(PDP_E_INVAL, "dictionary %u is null", i);
         if (!g->gene_off || (g->n_residues && !g->residues)) return fail(PDP_E_INVAL, "genome %u: null arrays", i);
         int32_t rc = dict_check(g->n_genes, g->n_residues, d->k, d->alphabet);
-        if (!rc && (d->lead != lead_letters(d->k, d->alphabet) || d->n_buckets != n_buckets_for(d->k, d->alphabet)))
+        if (!rc && (d->lead != lead_letters(d->k, d->alphabet) || d->n_buckets != n_buckets_for(d->k, d->alphabet) ||
+                    (d->flags & ~PDP_DICT_LONG_GENES)))
             rc = fail(PDP_E_INVAL, "dictionary %u: fields changed since pdp_dict_bind", i);
         if (rc) return rc;
         if (g->n_genes != d->n_genes || g->n_residues + 1 > d->capacity)
@@ -246,6 +250,9 @@ static DevDict dev_dict(const pdp_dict *d) {
     x.ix_dir = d->ix_dir;
     x.nwin = d->nwin;
     x.ix_key = d->ix_key;
+    x.mv_ptr = d->mv_ptr;
+    x.mv_code = d->mv_code;
+    x.mv_cnt = d->mv_cnt;
     x.n_genes = d->n_genes;
     x.n_buckets = d->n_buckets;
     x.k = d->k;
@@ -290,6 +297,7 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     uint32_t tile_lds = std::max<uint32_t>(lds_budget, (filt ? 12 : 8) * kTileCap);
     std::vector<DevTask> caller(n_tasks);
     std::vector<uint64_t> cost(n_tasks);
+    std::vector<uint8_t> is_long(n_tasks, 0);  // the task takes the long-gene path
     for (uint32_t t = 0; t < n_tasks; ++t) {
         const pdp_task &tk = tasks[t];
         if (!tk.a || !tk.b) return bail(fail(PDP_E_INVAL, "task %u: null dictionary", t));
@@ -304,8 +312,11 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         std::memset(&d, 0, sizeof(d));
         d.a = dev_dict(tk.a);
         d.b = dev_dict(tk.b);
+        const bool long_task = ((tk.a->flags | tk.b->flags) & PDP_DICT_LONG_GENES) != 0;
+        is_long[t] = long_task ? 1 : 0;
         // column maxima: b's best hits from the AB tiles' columns, records for one direction
-        const bool colmax = (prm.flags & PDP_PARAM_COLMAX) && (flags & PDP_TASK_AB) && (flags & PDP_TASK_BA);
+        const bool colmax =
+            !long_task && (prm.flags & PDP_PARAM_COLMAX) && (flags & PDP_TASK_AB) && (flags & PDP_TASK_BA);
         any_colmax |= colmax;
         d.flags = colmax ? (flags & ~PDP_TASK_BA) | kTaskColmax : flags;
         d.theta_n = prm.theta_num;
@@ -323,16 +334,16 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         const uint64_t subs = std::max<uint64_t>(1, kJoinDirCap / bpw);
         d.bpw = static_cast<uint32_t>(bpw);
         d.subs = static_cast<uint32_t>(subs);
-        d.n_chunks = static_cast<uint32_t>((nb + bpw * subs - 1) / (bpw * subs));
+        d.n_chunks = long_task ? 0u : static_cast<uint32_t>((nb + bpw * subs - 1) / (bpw * subs));
         uint32_t ndirs = 0;
         for (uint32_t dir = 0; dir < 2; ++dir) {
             d.row_base[dir] = UINT32_MAX;
             d.tile_shift[dir] = base_shift;
             d.tiles_n[dir] = 0;
             if (!(flags & (1u << dir))) continue;
-            if (dir == 1 && colmax) {  // rows in the output, no tiles and no records of their own
+            if ((dir == 1 && colmax) || long_task) {  // rows in the output, no tiles and no records of their own
                 d.row_base[dir] = static_cast<uint32_t>(bh_rows);
-                bh_rows += tk.b->n_genes;
+                bh_rows += (dir == 0 ? tk.a : tk.b)->n_genes;
                 continue;
             }
             ++ndirs;
@@ -387,7 +398,7 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     for (uint32_t t = 0; t < n_tasks; ++t) by_cost[t] = t;
     std::stable_sort(by_cost.begin(), by_cost.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
     P->order.assign(n_tasks, 0);
-    uint64_t chunks = 0, cells = 0;
+    uint64_t chunks = 0, cells = 0, long_rows = 0;
     for (uint32_t i = 0; i < n_tasks; ++i) {
         const uint32_t t = by_cost[i];
         P->order[t] = i;
@@ -414,6 +425,12 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         for (uint32_t dir = 0; dir < 2; ++dir) {
             d.tile_base[dir] = static_cast<uint32_t>(P->tiles.size());
             if (!(d.flags & (1u << dir))) continue;
+            if (is_long[t]) {  // the long-gene path: a row segment instead of tiles
+                const uint32_t nrows = dir == 0 ? d.a.n_genes : d.b.n_genes;
+                if (nrows) P->long_segs.push_back(DevLongSeg{i, dir, static_cast<uint32_t>(long_rows), nrows});
+                long_rows += nrows;
+                continue;
+            }
             const uint32_t nrows = dir == 0 ? d.a.n_genes : d.b.n_genes;
             const uint32_t T = 1u << d.tile_shift[dir];
             for (uint32_t r0 = 0; r0 < nrows; r0 += T, ++tile_local) {
@@ -479,6 +496,8 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     P->shape.tile_grid = 0;
     P->shape.colmax = any_colmax ? 1u : 0u;
     P->shape.cand_cap = any_colmax ? P->shape.rec_cap : 0;
+    P->shape.n_long_segs = static_cast<uint32_t>(P->long_segs.size());
+    P->shape.long_rows = static_cast<uint32_t>(long_rows);  // at most the best-hit rows, below 2^32
     P->persistent = (prm.flags & PDP_PARAM_PERSISTENT) != 0;
     P->ws_bytes = pair_ws_bytes(P->shape);
     *out = P;
@@ -492,7 +511,7 @@ int32_t plan_rebind(pdp_plan *P, const pdp_dict *from, const pdp_dict *to) {
     if (!P || !from || !to) return PDP_E_INVAL;
     if (from->n_genes != to->n_genes || from->capacity != to->capacity || from->k != to->k ||
         from->alphabet != to->alphabet || from->n_buckets != to->n_buckets || from->key_shift != to->key_shift ||
-        (from->ix_key == nullptr) != (to->ix_key == nullptr))
+        from->flags != to->flags || (from->ix_key == nullptr) != (to->ix_key == nullptr))
         return PDP_E_INVAL;
     const DevDict nd = dev_dict(to);
     const uint32_t *lo = from->ix_dir, *hi = from->ix_dir + from->n_buckets + 1;
@@ -521,6 +540,8 @@ int32_t pdp_plan_info_get(const pdp_plan *plan, pdp_plan_info *info) {
     info->join_groups = plan->shape.total_chunks;
     info->tiles = plan->shape.total_tiles;
     info->tile_lds = plan->shape.tile_lds;
+    info->long_rows = plan->shape.long_rows;
+    info->reserved = 0;
     return ok();
 }
 
@@ -550,6 +571,11 @@ int32_t pdp_plan_upload(const pdp_plan *plan, void *ws, uint64_t ws_bytes, void 
     }
     if (!plan->tiles.empty()) {
         e = hipMemcpyAsync(w.tiles, plan->tiles.data(), sizeof(DevTile) * plan->tiles.size(), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "pdp_plan_upload");
+    }
+    if (!plan->long_segs.empty()) {
+        e = hipMemcpyAsync(w.long_segs, plan->long_segs.data(), sizeof(DevLongSeg) * plan->long_segs.size(),
+                           hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "pdp_plan_upload");
     }
     return ok();

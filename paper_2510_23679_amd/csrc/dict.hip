@@ -165,7 +165,7 @@ __device__ __forceinline__ bool gene_ok(const DevBuild &B, uint32_t g, uint32_t 
     }
     *len = e - *o;
     const uint64_t nw64 = *len >= B.k ? *len - B.k + 1 : 0;
-    if (nw64 > PDP_MAX_WINDOWS) {
+    if (nw64 > B.max_windows) {
         if (lane_id() == 0) {
             raise_status(B.status, PDP_E_LIMIT, nw64, g);
             B.nwin[g] = 0;
@@ -648,6 +648,32 @@ __global__ __launch_bounds__(256) void k_ix_hist(const DevBuild *__restrict__ ta
         if (h[i]) atomicAdd(&bintot[B.bin_base + i], h[i]);
 }
 
+__device__ __forceinline__ uint64_t rec_code(const uint4 &r) { return (static_cast<uint64_t>(r.y) << 32) | r.x; }
+__device__ __forceinline__ uint32_t rec_gene(const uint4 &r) { return r.z; }
+__device__ __forceinline__ uint32_t rec_cnt(const uint4 &r) { return r.w; }
+__device__ __forceinline__ uint64_t rec_code(const uint2 &r) { return r.x; }
+__device__ __forceinline__ uint32_t rec_gene(const uint2 &r) { return r.y & 0xFFFFu; }
+__device__ __forceinline__ uint32_t rec_cnt(const uint2 &r) { return r.y >> 16; }
+// An index record in the form a bin sort keeps in LDS: uint4 = (code low, code high, gene,
+// count), or, when every genome of the build has 32-bit keys (codes of at most 32 bits, or
+// base-20 values: base20_keys) and at most 65536 genes, uint2 = (key, gene | count << 16):
+// half the LDS, more work-groups per CU.  A base-20 key orders records as the code does.
+__device__ __forceinline__ uint32_t code_to_base20(uint64_t c, uint32_t k) {
+    uint32_t v = 0;
+    for (uint32_t i = 0; i < k; ++i) v = v * 20u + static_cast<uint32_t>((c >> (5u * (k - 1u - i))) & 31u);
+    return v;
+}
+__device__ __forceinline__ void to_rec(const DevBuild &, const uint4 &v, uint4 *r) { *r = v; }
+__device__ __forceinline__ void to_rec(const DevBuild &B, const uint4 &v, uint2 *r) {
+    const uint32_t key = base20_keys(B) ? code_to_base20((static_cast<uint64_t>(v.y) << 32) | v.x, B.k) : v.x;
+    *r = make_uint2(key, v.z | (v.w << 16));
+}
+// The 5-bit code of a record.
+__device__ __forceinline__ uint64_t rec_code5(const DevBuild &, const uint4 &r) { return rec_code(r); }
+__device__ __forceinline__ uint64_t rec_code5(const DevBuild &B, const uint2 &r) {
+    return base20_keys(B) ? base20_to_code(r.x, B.k) : static_cast<uint64_t>(r.x);
+}
+
 constexpr uint32_t kIxPlaceThreads = 1024;  // a placement work-group: its block of entries in registers, 16 per thread
 constexpr uint32_t kIxPerThread = kIxBlock / kIxPlaceThreads;  // entries a placement thread keeps
 static_assert(kIxPerThread % kIxBatch == 0, "placement rounds divide the entries of a thread");
@@ -656,8 +682,11 @@ static_assert(kIxPerThread % kIxBatch == 0, "placement rounds divide the entries
 // LDS (every entry's rank among the block's entries of its bin comes back from the LDS
 // atomic), takes a run of each bin's range with one global atomic on the bin's remaining
 // count (binoff holds the scanned totals; the runs of a bin are handed out from its end),
-// and writes each entry at its run start plus its rank.  The order inside a bin depends on
-// scheduling; k_ix_sort_bin sorts every bin completely.
+// and writes each entry at its run start plus its rank, in the record form R the bin sort
+// keeps (8 bytes when the build allows it, so the scattered stores and the sort's loads move
+// half the bytes).  The order inside a bin depends on scheduling; k_ix_sort_bin sorts every
+// bin completely.
+template <typename R>
 __global__ __launch_bounds__(kIxPlaceThreads) void k_ix_place(const DevBuild *__restrict__ table, uint32_t n_genomes,
                                                   const uint32_t *__restrict__ gptr, const uint32_t *__restrict__ binoff,
                                                   uint32_t *__restrict__ bintot, const uint32_t *__restrict__ ent_gene) {
@@ -702,8 +731,10 @@ __global__ __launch_bounds__(kIxPlaceThreads) void k_ix_place(const DevBuild *__
             if (e0 + (q0 + q) * kIxPlaceThreads + threadIdx.x >= e1) continue;
             const uint64_t code = c[q0 + q];
             const uint32_t pos = cur[bucket_of(code, B.k, B.lead, B.bits) >> B.hshift] + rank[q0 + q];
-            // one 16-byte record per entry: a single scattered store instead of three
-            B.ix_tmp[pos] = make_uint4(static_cast<uint32_t>(code), static_cast<uint32_t>(code >> 32), gn[q], ct[q]);
+            // one record per entry: a single scattered store instead of three
+            R r;
+            to_rec(B, make_uint4(static_cast<uint32_t>(code), static_cast<uint32_t>(code >> 32), gn[q], ct[q]), &r);
+            reinterpret_cast<R *>(B.ix_tmp)[pos] = r;
         }
     }
 }
@@ -742,32 +773,6 @@ __device__ void bin_directory(const DevBuild &B, CP code, uint32_t n, uint32_t l
         }
         B.ix_dir[b] = lo + l;
     }
-}
-
-__device__ __forceinline__ uint64_t rec_code(const uint4 &r) { return (static_cast<uint64_t>(r.y) << 32) | r.x; }
-__device__ __forceinline__ uint32_t rec_gene(const uint4 &r) { return r.z; }
-__device__ __forceinline__ uint32_t rec_cnt(const uint4 &r) { return r.w; }
-__device__ __forceinline__ uint64_t rec_code(const uint2 &r) { return r.x; }
-__device__ __forceinline__ uint32_t rec_gene(const uint2 &r) { return r.y & 0xFFFFu; }
-__device__ __forceinline__ uint32_t rec_cnt(const uint2 &r) { return r.y >> 16; }
-// An index record in the form a bin sort keeps in LDS: uint4 = (code low, code high, gene,
-// count), or, when every genome of the build has 32-bit keys (codes of at most 32 bits, or
-// base-20 values: base20_keys) and at most 65536 genes, uint2 = (key, gene | count << 16):
-// half the LDS, more work-groups per CU.  A base-20 key orders records as the code does.
-__device__ __forceinline__ uint32_t code_to_base20(uint64_t c, uint32_t k) {
-    uint32_t v = 0;
-    for (uint32_t i = 0; i < k; ++i) v = v * 20u + static_cast<uint32_t>((c >> (5u * (k - 1u - i))) & 31u);
-    return v;
-}
-__device__ __forceinline__ void to_rec(const DevBuild &, const uint4 &v, uint4 *r) { *r = v; }
-__device__ __forceinline__ void to_rec(const DevBuild &B, const uint4 &v, uint2 *r) {
-    const uint32_t key = base20_keys(B) ? code_to_base20((static_cast<uint64_t>(v.y) << 32) | v.x, B.k) : v.x;
-    *r = make_uint2(key, v.z | (v.w << 16));
-}
-// The 5-bit code of a record.
-__device__ __forceinline__ uint64_t rec_code5(const DevBuild &, const uint4 &r) { return rec_code(r); }
-__device__ __forceinline__ uint64_t rec_code5(const DevBuild &B, const uint2 &r) {
-    return base20_keys(B) ? base20_to_code(r.x, B.k) : static_cast<uint64_t>(r.x);
 }
 
 // Packed join key of an index entry: the code's trailing letters (the leading ones are
@@ -856,20 +861,17 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
     const uint32_t b1 = min(B.nb, (h + 1) << B.hshift);
     const uint32_t nbb = b1 - b0;
     const uint32_t nslot = nbb << B.xb;
-    const uint4 *tmp = B.ix_tmp;
+    const R *tmp = reinterpret_cast<const R *>(B.ix_tmp);  // the placement wrote R records
     if (n <= kIxBinLds && nslot <= kIxBinSlots) {
         for (uint32_t i = threadIdx.x; i <= nslot; i += 256) s_bstart[i] = 0;
         __syncthreads();
         R r[kIxPer];
-        uint4 w[kIxPer];
         uint32_t slot[kIxPer], bk[kIxPer];
 #pragma unroll
         for (uint32_t q = 0; q < kIxPer; ++q) {  // every load issued before the first atomic
             const uint32_t i = q * 256 + threadIdx.x;
-            w[q] = i < n ? tmp[lo + i] : make_uint4(0, 0, 0, 0);
+            r[q] = i < n ? tmp[lo + i] : R{};
         }
-#pragma unroll
-        for (uint32_t q = 0; q < kIxPer; ++q) to_rec(B, w[q], &r[q]);
 #pragma unroll
         for (uint32_t q = 0; q < kIxPer; ++q) {
             const uint32_t i = q * 256 + threadIdx.x;
@@ -934,7 +936,7 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < n; i += 256) put_entry(B, lo + i, s_rec[i]);
     } else if (n <= kIxBinLds) {
-        for (uint32_t i = threadIdx.x; i < n; i += 256) to_rec(B, tmp[lo + i], &s_rec[i]);
+        for (uint32_t i = threadIdx.x; i < n; i += 256) s_rec[i] = tmp[lo + i];
         __syncthreads();
         sort_recs(s_rec, n);
         for (uint32_t i = threadIdx.x; i < n; i += 256) put_entry(B, lo + i, s_rec[i]);
@@ -942,8 +944,8 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
         bin_directory(B, B.ix_code + lo, n, lo, b0, b1);
     } else {
         for (uint32_t i = threadIdx.x; i < n; i += 256) {
-            const uint4 v = tmp[lo + i];
-            B.ix_code[lo + i] = rec_code(v);
+            const R v = tmp[lo + i];
+            B.ix_code[lo + i] = rec_code5(B, v);
             B.ix_gene[lo + i] = rec_gene(v);
             B.ix_cnt[lo + i] = rec_cnt(v);
         }
@@ -1096,6 +1098,7 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
             B.ix_cnt = D.ix_cnt;
             B.ix_key = D.ix_key;
             B.key_shift = D.key_shift;
+            B.max_windows = (D.flags & PDP_DICT_LONG_GENES) ? PDP_MAX_WINDOWS_LONG : PDP_MAX_WINDOWS;
             B.status = D.status;
             B.slot_code = slot_code + res_base;
             B.slot_cnt = slot_cnt + res_base;
@@ -1162,14 +1165,19 @@ hipError_t launch_dict_build_many(const pdp_genome *g, pdp_dict *const *d, uint3
                        bintot);
     PDP_TRY(hipGetLastError());
     PDP_TRY(launch_scan(bintot, binoff, sh.total_bins, partials, s));  // every bin's range
-    hipLaunchKernelGGL(k_ix_place, dim3(static_cast<uint32_t>(sh.total_blocks)), dim3(kIxPlaceThreads), hist_lds, s, table,
-                       n, dcnt, binoff, bintot, ent_gene);
-    PDP_TRY(hipGetLastError());
-    // bins sorted in LDS as 8-byte records when every key fits 32 bits and every gene index 16 bits
+    // bins placed and sorted as 8-byte records when every key fits 32 bits, every gene index 16
+    // bits and every multiplicity 16 bits (no long-gene dictionary)
     bool narrow_rec = true;
     for (uint32_t i = 0; i < n; ++i)
         narrow_rec &= (alpha_spec(d[i]->alphabet).bits * d[i]->k <= 32 || (d[i]->alphabet == PDP_ALPHA_AMINO && d[i]->k == 7)) &&
-                      g[i].n_genes <= 65536;
+                      g[i].n_genes <= 65536 && !(d[i]->flags & PDP_DICT_LONG_GENES);
+    if (narrow_rec)
+        hipLaunchKernelGGL(k_ix_place<uint2>, dim3(static_cast<uint32_t>(sh.total_blocks)), dim3(kIxPlaceThreads), hist_lds,
+                           s, table, n, dcnt, binoff, bintot, ent_gene);
+    else
+        hipLaunchKernelGGL(k_ix_place<uint4>, dim3(static_cast<uint32_t>(sh.total_blocks)), dim3(kIxPlaceThreads), hist_lds,
+                           s, table, n, dcnt, binoff, bintot, ent_gene);
+    PDP_TRY(hipGetLastError());
     if (narrow_rec)
         hipLaunchKernelGGL(k_ix_sort_bin<uint2>, dim3(static_cast<uint32_t>(sh.total_bins)), dim3(256), 0, s, table, n,
                            binoff);

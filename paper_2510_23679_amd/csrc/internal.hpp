@@ -77,6 +77,9 @@ struct DevDict {
     const uint32_t *ix_dir;
     const uint32_t *nwin;
     const uint32_t *ix_key;  // packed (tail, gene) keys when key_shift > 0
+    const uint32_t *mv_ptr;  // multiplicity vectors (the long-gene path walks a row gene's)
+    const uint64_t *mv_code;
+    const uint32_t *mv_cnt;
     uint32_t n_genes;
     uint32_t n_buckets;
     uint32_t k;
@@ -116,6 +119,15 @@ struct DevItem {
     uint32_t reserved;
 };
 
+// The rows of one direction of a task on the long-gene path: rows first .. first + n_rows of
+// the plan's long-row numbering are the task's row genes 0 .. n_rows - 1 in direction dir.
+struct DevLongSeg {
+    uint32_t task;
+    uint32_t dir;
+    uint32_t first;
+    uint32_t n_rows;
+};
+
 struct DevTile {
     uint32_t task;
     uint32_t dir;
@@ -152,6 +164,7 @@ struct DevBuild {
     uint32_t *ix_key;     // packed keys, written when key_shift > 0
     uint32_t key_shift;
     uint32_t bits;        // symbol bits per letter: 5 (amino acids) or 2 (nucleotides)
+    uint32_t max_windows; // PDP_MAX_WINDOWS, or PDP_MAX_WINDOWS_LONG for a long-gene dictionary
     pdp_status *status;
     uint64_t *slot_code;  // per gene g: sorted distinct codes at offset gene_off[g]
     uint32_t *slot_cnt;
@@ -178,7 +191,7 @@ struct PairWs {
     uint32_t *fill;               // one-pass join: records reserved in each tile's region
     uint2 *tile_rng;              // records of each tile, [x, y), for the tile kernels
     uint32_t *fallback;           // counters word 7: a region overflowed, the two-pass join redoes the records
-    uint32_t *next_fused;         // counters word 8: next item of the persistent one-pass join
+    uint32_t *next_fused;         // counters words 8..15: next item of each XCD in the persistent one-pass join
     uint4 *slab;                  // kSlab (column, m, d, -) per best-hit row
     uint32_t *overflow_tiles;     // tiles holding a row with more than kSlab ties
     uint32_t *overflow_count;     // counters word 2
@@ -193,6 +206,7 @@ struct PairWs {
     uint32_t *colcursor;
     uint4 *cands;
     uint32_t *cand_count;         // counters word 6
+    DevLongSeg *long_segs;        // long-gene path, by first row
 };
 
 struct PlanShape {
@@ -204,6 +218,8 @@ struct PlanShape {
     uint32_t join_tiles;            // most tiles of one task: LDS counters of the one-pass join
     uint32_t fallback_grid;         // work-groups of the two-pass join when it backs up the one-pass join
     uint64_t cand_cap;              // column candidates the scratch holds (colmax: rec_cap)
+    uint32_t n_long_segs;           // long-gene path: segments and rows
+    uint32_t long_rows;
 };
 // Records the message that pdp_last_error() returns on this thread; returns code.
 int32_t api_fail(int32_t code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));

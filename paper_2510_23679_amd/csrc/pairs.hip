@@ -772,22 +772,31 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_fused(const DevTask *__re
                 join_dyn + join_tiles, join_tiles);
 }
 
+// Persistent form: XCD x (work-groups b with b mod 8 = x) claims, from a counter of its own, the
+// items a one-per-item launch would run on it, in the same order, so the L2 reuse of the bucket
+// ranges survives; once its own counter is spent it helps the other XCDs' in turn.  Every
+// work-group ends after all eight counters are spent, whatever the grid size.
 __global__ __launch_bounds__(kJoinThreads, 6) void k_join_fused_persistent(
     const DevTask *__restrict__ tasks, const DevItem *__restrict__ items, uint32_t total_chunks,
     uint32_t *__restrict__ fill, const DevTile *__restrict__ tiles, uint32_t *__restrict__ fallback,
     uint2 *__restrict__ recs, uint32_t join_tiles, uint32_t *__restrict__ next) {
     __shared__ JoinLdsFused L;
     extern __shared__ uint32_t join_dyn[];
-    for (;;) {
-        if (threadIdx.x == 0) L.next = atomicAdd(next, kClaimJoin);
-        __syncthreads();
-        const uint32_t first = L.next;
-        __syncthreads();
-        if (first >= total_chunks) break;
-        const uint32_t last = min(total_chunks, first + kClaimJoin);
-        for (uint32_t chunk = first; chunk < last; ++chunk)
-            fused_chunk(chunk, tasks, items, fill, tiles, fallback, recs, L, join_dyn, join_dyn + join_tiles,
-                        join_tiles);
+    const uint32_t home = blockIdx.x % kXcds;
+    for (uint32_t s = 0; s < kXcds; ++s) {
+        const uint32_t x = (home + s) % kXcds;
+        const uint32_t own = x < total_chunks ? (total_chunks - x + kXcds - 1) / kXcds : 0u;  // v = x + 8 j < total
+        for (;;) {
+            if (threadIdx.x == 0) L.next = atomicAdd(&next[x], kClaimJoin);
+            __syncthreads();
+            const uint32_t first = L.next;
+            __syncthreads();
+            if (first >= own) break;
+            const uint32_t last = min(own, first + kClaimJoin);
+            for (uint32_t j = first; j < last; ++j)
+                fused_chunk(xcd_item(x + kXcds * j, total_chunks), tasks, items, fill, tiles, fallback, recs, L,
+                            join_dyn, join_dyn + join_tiles, join_tiles);
+        }
     }
 }
 
@@ -1647,6 +1656,171 @@ __global__ __launch_bounds__(256) void k_bbh_pair(uint32_t rows, const uint32_t 
                    out_b, out_num, out_den, cap);
 }
 
+// ------------------------------------------------------------------ long genes
+// Rows of the tasks that name a dictionary bound for long genes, whose multiplicities and sums
+// of minima may pass 16 bits.  One work-group computes a row on its own, as Eq. jaccard_k
+// reads: for every k-mer of the row gene's multiplicity vector it finds the k-mer in the column
+// genome's index (its leading-letter bucket, then a binary search on the code) and adds
+// min(count in the row gene, count in the column gene) to that column gene's 32-bit LDS sum;
+// with the filters the occurrence sums of both genes are kept the same way.  The column genes
+// are taken kLongCols at a time in ascending order: a first sweep finds the row's maximum of
+// m/d (Eq. best_hit, exact 64-bit cross-multiplication), a second one emits the columns at the
+// maximum in column order.  WRITE = false puts the first kSlab ties in the row's slab and the
+// count in bh_ptr, as the tiles do; WRITE = true writes the rows with more than kSlab ties
+// straight into the CSR output after the scan.
+constexpr uint32_t kLongThreads = 256;
+constexpr uint32_t kLongCols = 4096;   // column genes per LDS block: three 32-bit sums each, 48 KiB
+constexpr uint32_t kLongGrid = 1024;   // work-groups at most; each takes rows in turn
+
+template <bool WRITE>
+__global__ __launch_bounds__(kLongThreads) void k_long_rows(const DevTask *__restrict__ tasks,
+                                                            const DevLongSeg *__restrict__ segs, uint32_t n_segs,
+                                                            uint32_t n_rows, uint32_t *__restrict__ bh_ptr,
+                                                            uint4 *__restrict__ slab, uint32_t *__restrict__ bh_col,
+                                                            uint32_t *__restrict__ bh_num, uint32_t *__restrict__ bh_den,
+                                                            uint64_t bh_cap) {
+    __shared__ uint32_t acc[kLongCols];  // sum of minima per column gene of the block
+    __shared__ uint32_t asr[kLongCols];  // with filters: occurrences in the row gene of the shared k-mers
+    __shared__ uint32_t asc[kLongCols];  // and in the column gene
+    __shared__ uint32_t red[2 * (kLongThreads / kWave)];
+    __shared__ uint32_t tmp[kLongThreads / kWave + 1];
+    constexpr uint32_t NW = kLongThreads / kWave;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    for (uint32_t lr = blockIdx.x; lr < n_rows; lr += gridDim.x) {
+        uint32_t lo = 0, hi = n_segs;  // the last segment whose first row is <= lr (segments are non-empty)
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (segs[mid].first <= lr) lo = mid;
+            else hi = mid;
+        }
+        const DevLongSeg sg = segs[lo];
+        const DevTask &T = tasks[sg.task];
+        const DevDict &R = sg.dir == 0 ? T.a : T.b;
+        const DevDict &C = sg.dir == 0 ? T.b : T.a;
+        const uint32_t row = lr - sg.first;
+        const uint32_t grow = T.row_base[sg.dir] + row;
+        const uint32_t pos0 = WRITE ? bh_ptr[grow] : 0u;
+        if (WRITE && bh_ptr[grow + 1] - pos0 <= kSlab) continue;  // the slab copy placed this row
+        const bool filt = T.theta_d || T.tau_d;
+        const uint32_t nr = R.nwin[row];
+        const uint32_t e0 = R.mv_ptr[row], e1 = R.mv_ptr[row + 1];
+        const uint32_t ncols = C.n_genes;
+        const uint32_t nblk = (ncols + kLongCols - 1) / kLongCols;
+        // sums of column genes [c0, c0 + cn) into acc / asr / asc
+        auto accumulate = [&](uint32_t c0, uint32_t cn) {
+            for (uint32_t i = tid; i < cn; i += kLongThreads) {
+                acc[i] = 0;
+                if (filt) {
+                    asr[i] = 0;
+                    asc[i] = 0;
+                }
+            }
+            __syncthreads();
+            for (uint32_t e = e0 + tid; e < e1; e += kLongThreads) {
+                const uint64_t code = R.mv_code[e];
+                const uint32_t cr = R.mv_cnt[e];
+                const uint32_t b = bucket_of(code, C.k, C.lead, C.bits);
+                if (b >= C.n_buckets) continue;  // not a k-mer of the alphabet: in no index
+                const uint32_t end = C.ix_dir[b + 1];
+                uint32_t l = C.ix_dir[b], h = end;  // first entry of the code: entries ascend by (code, gene)
+                while (l < h) {
+                    const uint32_t mid = (l + h) >> 1;
+                    if (C.ix_code[mid] < code) l = mid + 1;
+                    else h = mid;
+                }
+                for (uint32_t i = l; i < end && C.ix_code[i] == code; ++i) {
+                    const uint32_t g = C.ix_gene[i] - c0;  // genes below c0 wrap past cn
+                    if (g >= cn) continue;
+                    const uint32_t cc = C.ix_cnt[i];
+                    atomicAdd(&acc[g], min(cr, cc));
+                    if (filt) {
+                        atomicAdd(&asr[g], cr);
+                        atomicAdd(&asc[g], cc);
+                    }
+                }
+            }
+            __syncthreads();
+        };
+        // (m, d) of column c0 + i of the block, m = 0 when the pair shares nothing or is filtered out
+        auto value = [&](uint32_t c0, uint32_t i, uint32_t *m, uint32_t *d) {
+            *m = acc[i];
+            *d = 0;
+            if (!*m) return;
+            const uint32_t nc = C.nwin[c0 + i];
+            if (filt && !candidate(T, nr, nc, asr[i], asc[i])) {
+                *m = 0;
+                return;
+            }
+            *d = nr + nc - *m;  // below 2^32: both window counts are at most PDP_MAX_WINDOWS_LONG
+        };
+        uint32_t bm = 0, bd = 1;
+        for (uint32_t blk = 0; blk < nblk; ++blk) {
+            const uint32_t c0 = blk * kLongCols, cn = min(kLongCols, ncols - c0);
+            accumulate(c0, cn);
+            for (uint32_t i = tid; i < cn; i += kLongThreads) {
+                uint32_t m, d;
+                value(c0, i, &m, &d);
+                if (m && j_greater(m, d, bm, bd)) {
+                    bm = m;
+                    bd = d;
+                }
+            }
+            __syncthreads();  // the next block clears the sums
+        }
+#pragma unroll
+        for (uint32_t o = kWave / 2; o > 0; o >>= 1) {
+            const uint32_t om = __shfl_xor(bm, o, kWave), od = __shfl_xor(bd, o, kWave);
+            if (j_greater(om, od, bm, bd)) {
+                bm = om;
+                bd = od;
+            }
+        }
+        if (lane == 0) {
+            red[w] = bm;
+            red[NW + w] = bd;
+        }
+        __syncthreads();
+        bm = 0;
+        bd = 1;
+        for (uint32_t v = 0; v < NW; ++v)
+            if (j_greater(red[v], red[NW + v], bm, bd)) {
+                bm = red[v];
+                bd = red[NW + v];
+            }
+        __syncthreads();
+        uint32_t pos = 0;  // ties so far, in column order
+        if (bm) {
+            for (uint32_t blk = 0; blk < nblk; ++blk) {
+                const uint32_t c0 = blk * kLongCols, cn = min(kLongCols, ncols - c0);
+                if (nblk > 1) accumulate(c0, cn);  // a single block still holds its sums
+                for (uint32_t i0 = 0; i0 < cn; i0 += kLongThreads) {
+                    const uint32_t i = i0 + tid;
+                    uint32_t m = 0, d = 0;
+                    if (i < cn) value(c0, i, &m, &d);
+                    const bool tie = m && j_equal(m, d, bm, bd);
+                    uint32_t total;
+                    const uint32_t p = pos + block_exclusive_scan<kLongThreads>(tie ? 1u : 0u, tmp, &total);
+                    if (tie) {
+                        if (WRITE) {
+                            const uint64_t q = uint64_t(pos0) + p;
+                            if (q < bh_cap) {
+                                bh_col[q] = c0 + i;
+                                bh_num[q] = m;
+                                bh_den[q] = d;
+                            }
+                        } else if (p < kSlab) {
+                            slab[static_cast<uint64_t>(grow) * kSlab + p] = make_uint4(c0 + i, m, d, 0);
+                        }
+                    }
+                    pos += total;
+                }
+                __syncthreads();  // the next block clears the sums
+            }
+        }
+        if (!WRITE && tid == 0) bh_ptr[grow] = pos;
+    }
+}
+
 // ------------------------------------------------------------------ host
 
 static uint32_t device_cus() {
@@ -1726,6 +1900,7 @@ uint64_t pair_ws_bytes(const PlanShape &p) {
     s += align_up(8 * colrows, A);                                  // column keys
     s += align_up(4 * colrows, A);                                  // big-row cursors
     s += align_up(16 * std::max<uint64_t>(p.colmax ? p.cand_cap : 0, 1), A);  // candidates
+    s += align_up(sizeof(DevLongSeg) * std::max<uint64_t>(p.n_long_segs, 1), A);
     return s;
 }
 
@@ -1763,6 +1938,7 @@ PairWs pair_ws_carve(void *ws, const PlanShape &p) {
     w.colcursor = reinterpret_cast<uint32_t *>(take(4 * colrows));
     w.cands = reinterpret_cast<uint4 *>(take(16 * std::max<uint64_t>(p.colmax ? p.cand_cap : 0, 1)));
     w.cand_count = reinterpret_cast<uint32_t *>(w.counters) + 6;
+    w.long_segs = reinterpret_cast<DevLongSeg *>(take(sizeof(DevLongSeg) * std::max<uint64_t>(p.n_long_segs, 1)));
     return w;
 }
 
@@ -1875,6 +2051,12 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
         hipLaunchKernelGGL(k_colmax_rows, dim3(col_grid), dim3(256), 0, s, cmx, bh->ptr, w.slab, st);
         PDP_TRY(hipGetLastError());
     }
+    const dim3 long_grid(std::min(p.long_rows, kLongGrid));
+    if (p.long_rows) {
+        hipLaunchKernelGGL(k_long_rows<false>, long_grid, dim3(kLongThreads), 0, s, w.tasks, w.long_segs, p.n_long_segs,
+                           p.long_rows, bh->ptr, w.slab, nullptr, nullptr, nullptr, 0);
+        PDP_TRY(hipGetLastError());
+    }
     PDP_TRY(mark(PDP_KERNEL_TILE_COUNT, false));
     PDP_TRY(launch_scan(bh->ptr, bh->ptr, p.bh_rows, w.partials, s));
     PDP_TRY(mark(PDP_KERNEL_TILE_WRITE, true));
@@ -1888,6 +2070,11 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
         hipLaunchKernelGGL(k_tile_write, dim3(g), dim3(kTileThreads), p.tile_lds, s, w.tasks, w.tiles, w.tile_rng, w.recs,
                            p.rec_cap, w.counters, lds_words, bh->ptr, bh->col, bh->num, bh->den, bh->capacity, w.overflow_tiles,
                            w.overflow_count);
+        PDP_TRY(hipGetLastError());
+    }
+    if (p.long_rows) {
+        hipLaunchKernelGGL(k_long_rows<true>, long_grid, dim3(kLongThreads), 0, s, w.tasks, w.long_segs, p.n_long_segs,
+                           p.long_rows, bh->ptr, nullptr, bh->col, bh->num, bh->den, bh->capacity);
         PDP_TRY(hipGetLastError());
     }
     if (p.colmax && p.bh_rows) {

@@ -111,6 +111,7 @@ struct ServeRequest {
     int32_t code = PDP_OK;
     uint32_t attempts = 0;
     uint64_t inc_cap = 0, bh_cap = 0, bbh_cap = 0;
+    uint32_t dict_flags = 0;  // PDP_DICT_LONG_GENES when a gene passes PDP_MAX_WINDOWS windows
     float h2d_ms = 0, build_ms = 0, pairs_ms = 0, d2h_ms = 0;  // device time of the last run
     // admission: the provisional plan and the footprint it gives are made once per run of the
     // request and kept while it waits for memory (cleared when a capacity retry grows it)
@@ -233,7 +234,7 @@ int32_t prepare_plan(pdp_server *S, ServeRequest *r) {
     int32_t rc = pdp_dict_size(r->n_genes, r->n_res, S->cfg.k, S->cfg.alphabet, &dict_bytes, &build_ws);
     if (rc == PDP_OK)
         rc = pdp_dict_bind(reinterpret_cast<void *>(uintptr_t(256)), dict_bytes, r->n_genes, r->n_res, S->cfg.k,
-                           S->cfg.alphabet, &r->dict);
+                           S->cfg.alphabet, r->dict_flags, &r->dict);
     if (rc == PDP_OK) rc = make_plan(S, r);
     if (rc == PDP_OK) r->foot_bytes = footprint(S, r, &r->foot_plan_ws);
     r->planned = rc == PDP_OK;
@@ -276,7 +277,7 @@ int32_t launch_request(pdp_server *S, ServeSlot &slot, ServeRequest *r, uint64_t
     // The dictionary now lives in this allocation: the admission plan, made with the
     // descriptor bound to a placeholder address, moves its pointers here.
     const pdp_dict placeholder = r->dict;
-    int32_t rc = pdp_dict_bind(dict_mem, arena, r->n_genes, r->n_res, S->cfg.k, S->cfg.alphabet, &r->dict);
+    int32_t rc = pdp_dict_bind(dict_mem, arena, r->n_genes, r->n_res, S->cfg.k, S->cfg.alphabet, r->dict_flags, &r->dict);
     if (rc) return rc;
     rc = r->plan ? plan_rebind(r->plan, &placeholder, &r->dict) : make_plan(S, r);
     if (rc) return rc;
@@ -574,9 +575,14 @@ int32_t pdp_server_submit(pdp_server *S, const uint8_t *residues, const uint64_t
     if (!S || !gene_off || (!residues && gene_off[n_genes])) return api_fail(PDP_E_INVAL, "pdp_server_submit: null argument");
     const double t_in = now_us(S->t0);  // the request's latency counts from here, planning included
     if (gene_off[0] != 0) return api_fail(PDP_E_INVAL, "pdp_server_submit: gene_off[0] must be 0");
-    for (uint32_t i = 0; i < n_genes; ++i)
+    uint64_t longest = 0;
+    for (uint32_t i = 0; i < n_genes; ++i) {
         if (gene_off[i + 1] < gene_off[i]) return api_fail(PDP_E_INVAL, "pdp_server_submit: offsets decrease at gene %u", i);
+        longest = std::max<uint64_t>(longest, gene_off[i + 1] - gene_off[i]);
+    }
     auto r = std::make_unique<ServeRequest>();
+    // a gene past the 16-bit window limit puts the request's pairs on the long-gene path
+    if (longest >= S->cfg.k && longest - S->cfg.k + 1 > PDP_MAX_WINDOWS) r->dict_flags = PDP_DICT_LONG_GENES;
     r->tag = tag;
     r->n_genes = n_genes;
     r->n_res = gene_off[n_genes];

@@ -75,12 +75,12 @@ def test_dict_size_validation():
         pdp.dict_size(10, 100, 6, "rna")
 
 
-def _fake_dict(n_genes, n_residues, k, base=1 << 20, alphabet="aa"):
+def _fake_dict(n_genes, n_residues, k, base=1 << 20, alphabet="aa", flags=0):
     """Binds a dictionary to a fake (never dereferenced) aligned address: binding and
     planning only do host arithmetic on the pointers."""
     arena, _ = pdp.dict_size(n_genes, n_residues, k, alphabet)
     d = B.pdp_dict()
-    B.check(pdp.lib().pdp_dict_bind(base, arena, n_genes, n_residues, k, B.alphabet_id(alphabet), C.byref(d)),
+    B.check(pdp.lib().pdp_dict_bind(base, arena, n_genes, n_residues, k, B.alphabet_id(alphabet), flags, C.byref(d)),
             "bind")
     return d
 
@@ -88,11 +88,14 @@ def _fake_dict(n_genes, n_residues, k, base=1 << 20, alphabet="aa"):
 def test_bind_checks_alignment_and_size():
     arena, _ = pdp.dict_size(10, 100, 3)
     d = B.pdp_dict()
-    assert pdp.lib().pdp_dict_bind(4096 + 8, arena, 10, 100, 3, 0, C.byref(d)) == pdp.PDP_E_INVAL
-    assert pdp.lib().pdp_dict_bind(4096, arena - 1, 10, 100, 3, 0, C.byref(d)) == pdp.PDP_E_WORKSPACE
-    assert pdp.lib().pdp_dict_bind(4096, arena, 10, 100, 3, 0, C.byref(d)) == 0
-    assert d.n_buckets == 20 ** 3 and d.capacity == 101 and d.lead == 3 and d.alphabet == 0
+    assert pdp.lib().pdp_dict_bind(4096 + 8, arena, 10, 100, 3, 0, 0, C.byref(d)) == pdp.PDP_E_INVAL
+    assert pdp.lib().pdp_dict_bind(4096, arena - 1, 10, 100, 3, 0, 0, C.byref(d)) == pdp.PDP_E_WORKSPACE
+    assert pdp.lib().pdp_dict_bind(4096, arena, 10, 100, 3, 0, 2, C.byref(d)) == pdp.PDP_E_INVAL  # unknown flag
+    assert pdp.lib().pdp_dict_bind(4096, arena, 10, 100, 3, 0, 0, C.byref(d)) == 0
+    assert d.n_buckets == 20 ** 3 and d.capacity == 101 and d.lead == 3 and d.alphabet == 0 and d.flags == 0
     assert d.nwin % 256 == 0 and d.ix_code > d.mv_code > d.nwin
+    assert pdp.lib().pdp_dict_bind(4096, arena, 10, 100, 3, 0, pdp.PDP_DICT_LONG_GENES, C.byref(d)) == 0
+    assert d.flags == pdp.PDP_DICT_LONG_GENES
 
 
 def test_bind_layout_per_alphabet():
@@ -162,6 +165,38 @@ def test_colmax_plan_has_tiles_for_one_direction():
     rc, h = _plan([(a, b, pdp.PDP_TASK_BBH)], pdp.params(two_pass=True))
     assert rc == 0
     L.pdp_plan_destroy(h)
+
+
+def test_long_gene_tasks_have_rows_but_no_join_or_tiles():
+    # a task naming a long-gene dictionary computes its rows on the long-gene path: no join
+    # items, no tiles, no column maxima; its rows keep their place in the output
+    a, b = _fake_dict(300, 90000, 5), _fake_dict(200, 60000, 5)
+    la = _fake_dict(300, 90000, 5, base=1 << 30, flags=pdp.PDP_DICT_LONG_GENES)
+    L = pdp.lib()
+    info = B.pdp_plan_info()
+    rc, h = _plan([(a, b, pdp.PDP_TASK_BBH)], pdp.params(tile_rows=16))
+    assert rc == 0 and L.pdp_plan_info_get(h, C.byref(info)) == 0
+    groups = info.join_groups
+    assert groups > 0 and info.tiles == 19 + 13 and info.long_rows == 0
+    L.pdp_plan_destroy(h)
+    for prm in (pdp.params(tile_rows=16), pdp.params(tile_rows=16, colmax=True)):
+        rc, h = _plan([(a, b, pdp.PDP_TASK_BBH), (la, b, pdp.PDP_TASK_BBH), (b, la, pdp.PDP_TASK_AB)], prm)
+        assert rc == 0 and L.pdp_plan_info_get(h, C.byref(info)) == 0
+        assert info.bh_rows == 500 + 500 + 200 and info.bbh_rows == 300 + 300
+        assert info.join_groups == groups  # the first task's items only
+        assert info.tiles == (19 + 13 if not prm.flags else 19)
+        assert info.long_rows == 300 + 200 + 200
+        rows = []
+        for t in range(3):
+            x, y, z = B.u32(), B.u32(), B.u32()
+            assert L.pdp_plan_rows(h, t, C.byref(x), C.byref(y), C.byref(z)) == 0
+            rows.append((x.value, y.value, z.value))
+        none = 2 ** 32 - 1
+        assert rows == [(0, 300, 0), (500, 800, 300), (1000, none, none)]
+        L.pdp_plan_destroy(h)
+    # a long-gene task needs no LDS room for a dense tile row of the column genome
+    big = _fake_dict(50000, 9 * 10 ** 6, 5, flags=pdp.PDP_DICT_LONG_GENES)
+    assert _plan([(a, big, pdp.PDP_TASK_AB)])[0] == 0
 
 
 def test_plan_rejects_bad_tasks():

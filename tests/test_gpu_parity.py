@@ -123,12 +123,17 @@ def test_dictionary_rejects_bad_residue():
     assert code == pdp.PDP_E_ALPHABET and where == 8
 
 
-def test_dictionary_rejects_too_many_windows():
-    say("window limit")
-    g = genome_from_strings(["A" * 70000, "MKV"])
+def test_dictionary_past_16_bit_windows():
+    # a gene of 69,998 windows: bound for long genes (from the host offsets), its one k-mer is
+    # counted 69,998 times; the pair path for such genomes is in test_gpu_long_genes.py
+    say("dictionary past the 16-bit window limit")
+    g = genome_from_strings(["A" * 70000, "MKV", "M" * 5 + "A" * 66000])
     d = pdp.Dictionary.build_from(g, 3)
-    code, needed, where = d.status()
-    assert code == pdp.PDP_E_LIMIT and where == 0 and needed == 70000 - 3 + 1
+    assert d.long_genes
+    d.check_status()
+    host = d.host()
+    check_dictionary(host, oracle.OracleGenome(g, 3))
+    assert int(host["mv_cnt"][0]) == 70000 - 3 + 1
 
 
 # ----------------------------------------------------------- best hits, BBH

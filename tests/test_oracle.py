@@ -188,6 +188,22 @@ def test_k1_is_weighted_jaccard_of_residue_counts(seed):
             assert oi.terms(a, oj, b) == (int(np.minimum(ha, hb).sum()), int(np.maximum(ha, hb).sum()))
 
 
+def test_counts_past_16_bits_closed_form():
+    # genes past 65535 windows: runs of one letter have one k-mer counted |g| - k + 1 times, and
+    # (AC)^n has two k-mers counted half as often each; the sums of Eq. jaccard_k then pass 2^16
+    k = 5
+    oi = _og(["A" * 70000, "AC" * 35000, "MKVLA"], k)
+    oj = _og(["A" * 68000, "CA" * 34000], k)
+    assert oi.terms(0, oj, 0) == (68000 - k + 1, 70000 - k + 1)
+    n1, n2 = 70000 - k + 1, 68000 - k + 1  # windows of (AC)^35000 and (CA)^34000, both even
+    assert oi.terms(1, oj, 1) == (n2, n1)  # each k-mer min(n1/2, n2/2) twice; maxima likewise
+    assert oi.terms(0, oj, 1) == (0, n1 + n2)
+    ab = oracle.bh(oi, oj, threads=2)
+    assert _bh_rows(ab) == [[(0, n2, n1)], [(1, n2, n1)], []]
+    sparse = oracle.bh_sparse(oi, oj)
+    assert _bh_rows(sparse) == _bh_rows(ab)
+
+
 @pytest.mark.parametrize("seed", range(10))
 def test_multiplicity_one_is_set_jaccard(seed):
     rng = random.Random(50 + seed)
