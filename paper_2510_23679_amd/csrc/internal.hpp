@@ -26,7 +26,7 @@ constexpr uint32_t kIxBinSlots = 2048;       // counting-sort slots of a bin (bu
 constexpr uint32_t kIxMaxBins = 8192;        // coarse bins per genome at most (LDS histogram)
 constexpr uint32_t kJoinLdsCap = 1024;       // target index entries staged in LDS per join sub-range
 constexpr uint32_t kJoinLdsCapP = 2048;      // the same for dictionaries with packed 32-bit keys
-constexpr uint32_t kJoinDirCap = 1024;       // leading-letter buckets per join item (sub-ranges x buckets)
+constexpr uint32_t kJoinDirCap = 512;        // leading-letter buckets per join item (sub-ranges x buckets)
 constexpr uint32_t kJoinTileCap = 1024;      // accumulation tiles per task (one LDS counter each in the join)
 constexpr uint32_t kTileMaxRows = 256;       // rows per accumulation tile (8-bit row field of a record)
 constexpr uint32_t kDefaultTileShift = 6;    // 64 rows per tile unless tuned

@@ -472,13 +472,16 @@ __global__ __launch_bounds__(kJoinThreads) void k_join_persistent(const DevTask 
 // fallback flag and stops the item; the count pass, the scan and the write pass then
 // lay out every record again (when the flag is clear they exit at once).
 constexpr uint32_t kFuseUnroll = 4;
+// The LDS of a work-group sets how many fit a CU (the join waits on memory, so more work-groups
+// hide more of it): the target side's multiplicities are not staged but read from the index when
+// a record is written (their cache lines were just read by the staging of the keys), and items
+// span at most 512 buckets; about 17 KiB, nine work-groups per CU.
 struct JoinLdsFused {
     DevTask task;
     uint32_t adir[kJoinDirCap + 1];
     uint32_t bdir[kJoinDirCap + 1];
     uint64_t bcode[kJoinLdsCap];  // staged target codes, or kJoinLdsCapP packed keys
     uint32_t bgene[kJoinLdsCap];  // staged target genes, or the query entries' buckets (16 bits each)
-    uint16_t bcnt[kJoinLdsCapP];
     uint32_t found, next, drop;
 };
 // followed in dynamic LDS by two words per tile of the task: the batch's record count and
@@ -510,7 +513,7 @@ __device__ __forceinline__ void fused_load(const DevDict &A, uint32_t base, uint
 }
 
 // Query entries [a0, a1) against the target entries from b0 on (nbe of them): packed keys bk
-// or codes bc with genes bg, counts bn, all indexed relative to b0; bdir is the item's slice
+// or codes bc with genes bg, counts bn (the index's own array), all indexed relative to b0; bdir is the item's slice
 // of the target directory (index bucket - bl), adir the query's.  abk (packed, optional) holds
 // each query entry's bucket.  Returns false, uniformly, when a region overflowed.
 template <bool PACKED, typename CN>
@@ -634,25 +637,20 @@ __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, boo
     return true;
 }
 
-// Target entries [b0, b0 + nbe) of a packed dictionary into LDS (keys, 16-bit counts), in
+// Target keys [b0, b0 + nbe) of a packed dictionary into LDS, in
 // ITERS rounds of the work-group with every load issued before the first store.
 template <uint32_t ITERS>
-__device__ __forceinline__ void stage_packed(const DevDict &B, uint32_t b0, uint32_t nbe, uint32_t *bkey,
-                                             uint16_t *bcnt) {
-    uint32_t kv[ITERS], cv[ITERS];
+__device__ __forceinline__ void stage_packed(const DevDict &B, uint32_t b0, uint32_t nbe, uint32_t *bkey) {
+    uint32_t kv[ITERS];
 #pragma unroll
     for (uint32_t it = 0; it < ITERS; ++it) {
         const uint32_t i = threadIdx.x + it * kJoinThreads;
         kv[it] = i < nbe ? B.ix_key[b0 + i] : 0u;
-        cv[it] = i < nbe ? B.ix_cnt[b0 + i] : 0u;
     }
 #pragma unroll
     for (uint32_t it = 0; it < ITERS; ++it) {
         const uint32_t i = threadIdx.x + it * kJoinThreads;
-        if (i < nbe) {
-            bkey[i] = kv[it];
-            bcnt[i] = static_cast<uint16_t>(cv[it]);
-        }
+        if (i < nbe) bkey[i] = kv[it];
     }
 }
 
@@ -713,15 +711,15 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
                 fused_load<true>(T.a, a0, a1, r);  // in flight while the target side is staged
                 // a typical sub-range stages at most half the stage: half the unrolled iterations
                 if (nbe <= kJoinLdsCapP / 2)
-                    stage_packed<kJoinLdsCapP / 2 / kJoinThreads>(T.b, b0, nbe, bkey, L.bcnt);
+                    stage_packed<kJoinLdsCapP / 2 / kJoinThreads>(T.b, b0, nbe, bkey);
                 else
-                    stage_packed<kJoinLdsCapP / kJoinThreads>(T.b, b0, nbe, bkey, L.bcnt);
+                    stage_packed<kJoinLdsCapP / kJoinThreads>(T.b, b0, nbe, bkey);
                 if (abk)
                     for (uint32_t u = s0 - bl + threadIdx.x; u < s1 - bl; u += kJoinThreads)
                         for (uint32_t i = L.adir[u]; i < L.adir[u + 1]; ++i) abk[i - a0] = static_cast<uint16_t>(u);
                 __syncthreads();
                 ok = fused_range<true>(T, r, true, a0, a1, abk, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, nullptr, bkey,
-                                       nullptr, L.bcnt, L.bdir, tcount, tcur, &L.drop, fill, tiles, fallback, recs);
+                                       nullptr, T.b.ix_cnt + b0, L.bdir, tcount, tcur, &L.drop, fill, tiles, fallback, recs);
                 __syncthreads();  // the staged arrays take the next sub-range
             } else {
                 ok = fused_range<true>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, nullptr,
@@ -732,11 +730,10 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
             for (uint32_t i = threadIdx.x; i < nbe; i += kJoinThreads) {
                 L.bcode[i] = T.b.ix_code[b0 + i];
                 L.bgene[i] = T.b.ix_gene[b0 + i];
-                L.bcnt[i] = static_cast<uint16_t>(T.b.ix_cnt[b0 + i]);
             }
             __syncthreads();
             ok = fused_range<false>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, L.bcode,
-                                    nullptr, L.bgene, L.bcnt, L.bdir, tcount, tcur, &L.drop, fill, tiles, fallback,
+                                    nullptr, L.bgene, T.b.ix_cnt + b0, L.bdir, tcount, tcur, &L.drop, fill, tiles, fallback,
                                     recs);
             __syncthreads();
         } else {
