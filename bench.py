@@ -60,6 +60,10 @@ def parse():
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                    help="measured HBM traffic per kernel (from rocprofv3 counters), used when its source hash matches")
     p.add_argument("--two-pass", action="store_true", help="join in two passes (count, then write)")
+    p.add_argument("--long-path", action="store_true",
+                   help="bind every dictionary for long genes, so every task takes the long-gene path (one "
+                        "work-group per best-hit row, sums from the index); the roofline entry is then the "
+                        "tile_count group, which holds that path's count launch")
     p.add_argument("--join-entries", type=int, default=0, help="index entries per join sub-range (0: default)")
     p.add_argument("--persistent", action="store_true", help="persistent join and tile kernels")
     p.add_argument("--tile-rows", type=int, default=0, help="rows per accumulation tile (0: default; allpairs, serving)")
@@ -671,7 +675,10 @@ def main():
 
     # residues and offsets resident in HBM before anything is timed
     dev = [pdp.DeviceGenome.of(g) for g in ds.genomes]
-    batch = pdp.DictionaryBatch(dev, k)  # every dictionary in one pdp_dict_build_many
+    # every dictionary in one pdp_dict_build_many
+    batch = pdp.DictionaryBatch(dev, k, long_genes=True if args.long_path else None)
+    if args.long_path and args.kernel == "join":
+        args.kernel = "tile_count"  # no join runs on the long-gene path
     dicts = batch.dicts
     batch.build()
     tasks = pdp.all_pairs_tasks(dicts)
@@ -682,7 +689,7 @@ def main():
 
     prm = pdp.params(theta=frac(args.theta), tau=frac(args.tau), colmax=args.colmax, two_pass=args.two_pass,
                      join_entries=args.join_entries, persistent=args.persistent, tile_rows=args.tile_rows)
-    explicit = args.join_entries or args.persistent or args.tile_rows or args.colmax or args.two_pass
+    explicit = args.join_entries or args.persistent or args.tile_rows or args.colmax or args.two_pass or args.long_path
     if not args.no_tune and not explicit:
         # the launch shape for this workload, picked by the library's autotuner before anything is timed
         cands = None if args.tune_all else [pdp.params(tile_rows=tr, colmax=cm, theta=frac(args.theta), tau=frac(args.tau))
@@ -819,12 +826,14 @@ def main():
                    "genes": int(sum(genes)), "k": k, "genome_pairs": len(pairs),
                    "gene_pairs": gene_pairs, "kmer_entries": int(sum(entries)), "best_hits": bh_nnz, "bbh_pairs": bbh_n,
                    "filters": {"theta": args.theta, "tau": args.tau},
-                   "column_maxima": bool(prm.flags & B.PDP_PARAM_COLMAX)},
+                   "column_maxima": bool(prm.flags & B.PDP_PARAM_COLMAX),
+                   "pair_path": "long-gene path (every dictionary bound for long genes)" if args.long_path
+                   else "default"},
         "roofline": roofline,
         "params": tuned if tuned is not None else ("defaults" if not explicit
                                                    else {"join_entries": args.join_entries, "persistent": args.persistent,
                                                          "tile_rows": args.tile_rows, "column_maxima": args.colmax,
-                                                         "two_pass": args.two_pass}),
+                                                         "two_pass": args.two_pass, "long_path": args.long_path}),
         "breakdown": breakdown,
     }
     del runner, res, batch, dicts, dev

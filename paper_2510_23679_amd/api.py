@@ -185,10 +185,14 @@ class Dictionary:
 class DictionaryBatch:
     """Many dictionaries built by one pdp_dict_build_many call per build()."""
 
-    def __init__(self, genomes: Sequence[DeviceGenome], k, ws: Optional[Workspace] = None):
+    def __init__(self, genomes: Sequence[DeviceGenome], k, ws: Optional[Workspace] = None,
+                 long_genes: Optional[bool] = None):
+        """long_genes: bind every dictionary for long genes (True), none (False), or each one that
+        holds a gene past PDP_MAX_WINDOWS windows (None)."""
         ks = list(k) if isinstance(k, (list, tuple)) else [int(k)] * len(genomes)
         self.genomes = list(genomes)
-        self.dicts = [Dictionary(g.n_genes, g.n_residues, kk, g.alphabet, long_genes=g.long_genes(kk))
+        self.dicts = [Dictionary(g.n_genes, g.n_residues, kk, g.alphabet,
+                                 long_genes=g.long_genes(kk) if long_genes is None else long_genes)
                       for g, kk in zip(self.genomes, ks)]
         n = len(self.genomes)
         self._g = (B.pdp_genome * n)(*[g.struct() for g in self.genomes])

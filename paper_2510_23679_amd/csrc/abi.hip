@@ -393,6 +393,15 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     // (and the persistent kernels' counters) take the long items early.
     // each tile's expected records, the estimate rec_est sums: a region of the one-pass join each
     std::vector<uint64_t> tile_est;
+    {
+        uint64_t n_items = 0, n_tiles = 0;
+        for (const DevTask &d : caller) {
+            n_items += d.n_chunks;
+            n_tiles += uint64_t(d.tiles_n[0]) + d.tiles_n[1];
+        }
+        P->tiles.reserve(n_tiles);
+        tile_est.reserve(n_tiles);
+    }
     uint32_t join_tiles = 1;
     std::vector<uint32_t> by_cost(n_tasks);
     for (uint32_t t = 0; t < n_tasks; ++t) by_cost[t] = t;
@@ -405,20 +414,6 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         DevTask d = caller[t];
         d.chunk_base = static_cast<uint32_t>(chunks);
         chunks += d.n_chunks;
-        {  // the task's join items: bucket ranges of bpw * subs buckets
-            const uint64_t span = uint64_t(d.bpw) * d.subs;
-            for (uint32_t c = 0; c < d.n_chunks; ++c) {
-                DevItem it;
-                const uint64_t bl = c * span;
-                it.adir = d.a.ix_dir + bl;
-                it.bdir = d.b.ix_dir + bl;
-                it.task = i;
-                it.n_buckets = static_cast<uint32_t>(std::min<uint64_t>(d.a.n_buckets - bl, span));
-                it.bl = static_cast<uint32_t>(bl);
-                it.reserved = 0;
-                P->items.push_back(it);
-            }
-        }
         d.cell_base = static_cast<uint32_t>(cells);
         uint32_t tile_local = 0;
         const uint64_t dir_est = (tasks[t].a->capacity + tasks[t].b->capacity) / 8 + 4096;
@@ -453,20 +448,40 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         if (chunks > UINT32_MAX || P->tiles.size() >= UINT32_MAX)
             return bail(fail(PDP_E_LIMIT, "plan too large for 32-bit indices"));
     }
-    {  // the one-pass join's items by leading-letter range across tasks (each range as a fraction of
-       // its task's buckets), tasks in processing order within a range: the items in flight read
-       // the same stretch of each genome's index (see the join kernel's XCD mapping)
-        std::vector<uint64_t> key(P->items.size());
-        for (size_t x = 0; x < P->items.size(); ++x) {
-            const DevItem &it = P->items[x];
-            key[x] = (static_cast<uint64_t>(it.bl) << 32) / P->tasks[it.task].a.n_buckets;
+    {  // the one-pass join's items: each task's bucket ranges of bpw * subs buckets, ordered by range
+       // across tasks (a range's first bucket as a fraction of its task's buckets, in kSteps steps),
+       // tasks in processing order within a step, so that the items in flight read the same stretch
+       // of each genome's index (see the join kernel's XCD mapping).  A counting sort, generating
+       // every item once in its place.
+        constexpr uint32_t kSteps = 4096;
+        auto step_of = [](uint64_t bl, uint64_t mult) {
+            const uint64_t x = static_cast<uint64_t>((static_cast<unsigned __int128>(bl) * mult) >> 32);
+            return static_cast<uint32_t>(std::min<uint64_t>(x, kSteps - 1));
+        };
+        std::vector<uint32_t> start(kSteps + 1, 0);
+        std::vector<uint64_t> mult(P->tasks.size());
+        for (size_t i = 0; i < P->tasks.size(); ++i) {
+            const DevTask &d = P->tasks[i];
+            mult[i] = (static_cast<uint64_t>(kSteps) << 32) / std::max<uint32_t>(d.a.n_buckets, 1);
+            const uint64_t span = uint64_t(d.bpw) * d.subs;
+            for (uint32_t c = 0; c < d.n_chunks; ++c) ++start[step_of(c * span, mult[i]) + 1];
         }
-        std::vector<uint32_t> idx(P->items.size());
-        for (size_t x = 0; x < idx.size(); ++x) idx[x] = static_cast<uint32_t>(x);
-        std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return key[x] < key[y]; });
-        std::vector<DevItem> sorted(P->items.size());
-        for (size_t x = 0; x < idx.size(); ++x) sorted[x] = P->items[idx[x]];
-        P->items.swap(sorted);
+        for (uint32_t b = 0; b < kSteps; ++b) start[b + 1] += start[b];
+        P->items.resize(chunks);
+        for (size_t i = 0; i < P->tasks.size(); ++i) {
+            const DevTask &d = P->tasks[i];
+            const uint64_t span = uint64_t(d.bpw) * d.subs;
+            for (uint32_t c = 0; c < d.n_chunks; ++c) {
+                const uint64_t bl = c * span;
+                DevItem &it = P->items[start[step_of(bl, mult[i])]++];
+                it.adir = d.a.ix_dir + bl;
+                it.bdir = d.b.ix_dir + bl;
+                it.task = static_cast<uint32_t>(i);
+                it.n_buckets = static_cast<uint32_t>(std::min<uint64_t>(d.a.n_buckets - bl, span));
+                it.bl = static_cast<uint32_t>(bl);
+                it.reserved = 0;
+            }
+        }
     }
     P->shape.n_tasks = n_tasks;
     P->shape.total_chunks = static_cast<uint32_t>(chunks);

@@ -2007,9 +2007,11 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
             PDP_TRY(mark(PDP_KERNEL_JOIN, false));
             PDP_TRY(mark(PDP_KERNEL_JOIN_BACKUP, true));
         }
-    } else {
+    } else {  // no join items (every task on the long-gene path): empty intervals for the join timers
         PDP_TRY(mark(PDP_KERNEL_JOIN, true));
         PDP_TRY(mark(PDP_KERNEL_JOIN, false));
+        PDP_TRY(mark(PDP_KERNEL_BUCKET, true));
+        PDP_TRY(mark(PDP_KERNEL_BUCKET, false));
         PDP_TRY(mark(PDP_KERNEL_JOIN_BACKUP, true));
         PDP_TRY(launch_fill_u32(w.tile_off, uint64_t(p.total_tiles) + 1, 0u, s));
     }

@@ -139,3 +139,21 @@ def test_mixed_plan_long_and_default_tasks():
     info = runner.plan.info
     assert info.long_rows > 0 and info.join_groups > 0
     compare(gens, 5, runner.results())
+
+
+def test_kernel_timers_on_a_plan_without_join_items():
+    # every kernel group of the timer hook reads back on a plan whose tasks all take the
+    # long-gene path (no join items, no tiles)
+    say("kernel timers, long-gene plan")
+    gens = long_genomes("aa", seed=3)
+    _, runner = run_pair(gens, 5)
+    assert runner.plan.info.join_groups == 0 and runner.plan.info.tiles == 0
+    for name, kid in pdp.binding.KERNELS.items():
+        runner.plan.timer_start(kid, 2)
+        runner.launch()
+        runner.launch()
+        ms, n = runner.plan.timer_read()
+        runner.plan.timer_stop()
+        assert n == 2 and ms >= 0.0, name
+    torch.cuda.synchronize()
+    compare(gens, 5, runner.results())
