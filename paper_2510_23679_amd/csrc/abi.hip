@@ -513,6 +513,7 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
     P->shape.cand_cap = any_colmax ? P->shape.rec_cap : 0;
     P->shape.n_long_segs = static_cast<uint32_t>(P->long_segs.size());
     P->shape.long_rows = static_cast<uint32_t>(long_rows);  // at most the best-hit rows, below 2^32
+    P->shape.long_lds = (filt ? 3u : 1u) * kLongCols * 4u;
     P->persistent = (prm.flags & PDP_PARAM_PERSISTENT) != 0;
     P->ws_bytes = pair_ws_bytes(P->shape);
     *out = P;

@@ -39,6 +39,7 @@ constexpr uint32_t kHashMax = kHashSlots * 3 / 4;  // records one table pass tak
 constexpr uint32_t kDefaultLdsBudget = 8 * kTileCap;
 constexpr uint32_t kMaxTileLds = 160 * 1024 - 4096;  // gfx950 LDS per work-group, less the static part
 constexpr uint32_t kSlab = 4;                // best hits per row kept by the first tile pass
+constexpr uint32_t kLongCols = 4096;         // long-gene path: column genes per LDS block (one word per sum)
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -220,6 +221,7 @@ struct PlanShape {
     uint64_t cand_cap;              // column candidates the scratch holds (colmax: rec_cap)
     uint32_t n_long_segs;           // long-gene path: segments and rows
     uint32_t long_rows;
+    uint32_t long_lds;              // long-gene path: LDS bytes of a work-group (one or three sums per column)
 };
 // Records the message that pdp_last_error() returns on this thread; returns code.
 int32_t api_fail(int32_t code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));

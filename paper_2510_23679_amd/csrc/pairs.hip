@@ -1666,8 +1666,7 @@ __global__ __launch_bounds__(256) void k_bbh_pair(uint32_t rows, const uint32_t 
 // count in bh_ptr, as the tiles do; WRITE = true writes the rows with more than kSlab ties
 // straight into the CSR output after the scan.
 constexpr uint32_t kLongThreads = 256;
-constexpr uint32_t kLongCols = 4096;   // column genes per LDS block: three 32-bit sums each, 48 KiB
-constexpr uint32_t kLongGrid = 1024;   // work-groups at most; each takes rows in turn
+constexpr uint32_t kLongGrid = 4096;   // work-groups at most; each takes rows in turn
 
 template <bool WRITE>
 __global__ __launch_bounds__(kLongThreads) void k_long_rows(const DevTask *__restrict__ tasks,
@@ -1676,11 +1675,13 @@ __global__ __launch_bounds__(kLongThreads) void k_long_rows(const DevTask *__res
                                                             uint4 *__restrict__ slab, uint32_t *__restrict__ bh_col,
                                                             uint32_t *__restrict__ bh_num, uint32_t *__restrict__ bh_den,
                                                             uint64_t bh_cap) {
-    __shared__ uint32_t acc[kLongCols];  // sum of minima per column gene of the block
-    __shared__ uint32_t asr[kLongCols];  // with filters: occurrences in the row gene of the shared k-mers
-    __shared__ uint32_t asc[kLongCols];  // and in the column gene
+    // dynamic LDS: the sums of minima per column gene of the block, and with filters the
+    // occurrences in the row gene and in the column gene of the shared k-mers (kLongCols each)
+    extern __shared__ uint32_t long_lds[];
+    uint32_t *acc = long_lds;
+    uint32_t *asr = long_lds + kLongCols;
+    uint32_t *asc = long_lds + 2 * kLongCols;
     __shared__ uint32_t red[2 * (kLongThreads / kWave)];
-    __shared__ uint32_t tmp[kLongThreads / kWave + 1];
     constexpr uint32_t NW = kLongThreads / kWave;
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     for (uint32_t lr = blockIdx.x; lr < n_rows; lr += gridDim.x) {
@@ -1790,28 +1791,46 @@ __global__ __launch_bounds__(kLongThreads) void k_long_rows(const DevTask *__res
             for (uint32_t blk = 0; blk < nblk; ++blk) {
                 const uint32_t c0 = blk * kLongCols, cn = min(kLongCols, ncols - c0);
                 if (nblk > 1) accumulate(c0, cn);  // a single block still holds its sums
-                for (uint32_t i0 = 0; i0 < cn; i0 += kLongThreads) {
-                    const uint32_t i = i0 + tid;
+                // wave w takes a contiguous quarter of the block's columns: it counts its ties,
+                // then, after one barrier, emits them from its offset in column order
+                const uint32_t q = (cn + NW - 1) / NW, lo = min(cn, w * q), hi = min(cn, lo + q);
+                uint32_t mine = 0;
+                for (uint32_t i0 = lo; i0 < hi; i0 += kWave) {
+                    const uint32_t i = i0 + lane;
                     uint32_t m = 0, d = 0;
-                    if (i < cn) value(c0, i, &m, &d);
+                    if (i < hi) value(c0, i, &m, &d);
+                    mine += static_cast<uint32_t>(__popcll(__ballot(m && j_equal(m, d, bm, bd))));
+                }
+                if (lane == 0) red[w] = mine;
+                __syncthreads();
+                uint32_t at = pos, total = 0;
+                for (uint32_t v = 0; v < NW; ++v) {
+                    if (v < w) at += red[v];
+                    total += red[v];
+                }
+                for (uint32_t i0 = lo; i0 < hi; i0 += kWave) {
+                    const uint32_t i = i0 + lane;
+                    uint32_t m = 0, d = 0;
+                    if (i < hi) value(c0, i, &m, &d);
                     const bool tie = m && j_equal(m, d, bm, bd);
-                    uint32_t total;
-                    const uint32_t p = pos + block_exclusive_scan<kLongThreads>(tie ? 1u : 0u, tmp, &total);
+                    const uint64_t mask = __ballot(tie);
+                    const uint32_t p = at + mask_below(mask);
                     if (tie) {
                         if (WRITE) {
-                            const uint64_t q = uint64_t(pos0) + p;
-                            if (q < bh_cap) {
-                                bh_col[q] = c0 + i;
-                                bh_num[q] = m;
-                                bh_den[q] = d;
+                            const uint64_t dst = uint64_t(pos0) + p;
+                            if (dst < bh_cap) {
+                                bh_col[dst] = c0 + i;
+                                bh_num[dst] = m;
+                                bh_den[dst] = d;
                             }
                         } else if (p < kSlab) {
                             slab[static_cast<uint64_t>(grow) * kSlab + p] = make_uint4(c0 + i, m, d, 0);
                         }
                     }
-                    pos += total;
+                    at += static_cast<uint32_t>(__popcll(mask));
                 }
-                __syncthreads();  // the next block clears the sums
+                pos += total;
+                __syncthreads();  // the next block clears the sums and the counts
             }
         }
         if (!WRITE && tid == 0) bh_ptr[grow] = pos;
@@ -2052,7 +2071,7 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
     }
     const dim3 long_grid(std::min(p.long_rows, kLongGrid));
     if (p.long_rows) {
-        hipLaunchKernelGGL(k_long_rows<false>, long_grid, dim3(kLongThreads), 0, s, w.tasks, w.long_segs, p.n_long_segs,
+        hipLaunchKernelGGL(k_long_rows<false>, long_grid, dim3(kLongThreads), p.long_lds, s, w.tasks, w.long_segs, p.n_long_segs,
                            p.long_rows, bh->ptr, w.slab, nullptr, nullptr, nullptr, 0);
         PDP_TRY(hipGetLastError());
     }
@@ -2072,7 +2091,7 @@ hipError_t launch_pairs(const PlanShape &p, const PairWs &w, pdp_bh_out *bh, pdp
         PDP_TRY(hipGetLastError());
     }
     if (p.long_rows) {
-        hipLaunchKernelGGL(k_long_rows<true>, long_grid, dim3(kLongThreads), 0, s, w.tasks, w.long_segs, p.n_long_segs,
+        hipLaunchKernelGGL(k_long_rows<true>, long_grid, dim3(kLongThreads), p.long_lds, s, w.tasks, w.long_segs, p.n_long_segs,
                            p.long_rows, bh->ptr, nullptr, bh->col, bh->num, bh->den, bh->capacity);
         PDP_TRY(hipGetLastError());
     }
