@@ -64,6 +64,19 @@ __device__ __forceinline__ uint32_t bucket_of(uint64_t code, uint32_t k, uint32_
     return b;
 }
 
+// Loads and stores issued as global (not flat) accesses, for pointers read out of memory (a
+// table in LDS or device memory) whose address space the compiler cannot infer: a flat access
+// also waits on the LDS counter, so it serialises with the kernel's LDS traffic.  Only for
+// pointers into device memory.
+template <typename T>
+__device__ __forceinline__ T load_global(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ void store_global(T *p, T v) {
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+
 __device__ __forceinline__ uint32_t lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }

@@ -277,8 +277,8 @@ __device__ __forceinline__ void mv_wave_gene(const DevBuild &B, const uint8_t *s
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) {
         if (!((hmask >> e) & 1u)) continue;
-        slot_code[r] = key_code<B20>(key[e], k);
-        slot_cnt[r] = static_cast<uint32_t>(hp[r + 1]) - hp[r];
+        store_global(slot_code + r, key_code<B20>(key[e], k));
+        store_global(slot_cnt + r, static_cast<uint32_t>(hp[r + 1]) - hp[r]);
         ++r;
     }
     *cnt_out = total;
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kMvThreads) void k_mv_wave(const DevBuild *__restri
 #pragma unroll
         for (uint32_t it = 0; it < 4; ++it) {
             const uint32_t p = base + lane + it * kWave;
-            res[it] = p < len ? B.res[o + p] : 'A';
+            res[it] = p < len ? load_global(B.res + o + p) : 'A';
         }
 #pragma unroll
         for (uint32_t it = 0; it < 4; ++it) {
@@ -426,7 +426,7 @@ __device__ __forceinline__ void mid_gene(const DevBuild &B, uint32_t G, uint64_t
 #pragma unroll
         for (uint32_t it = 0; it < 4; ++it) {
             const uint32_t p = base + it * kMvThreads + tid;
-            res[it] = p < len ? B.res[o + p] : 'A';
+            res[it] = p < len ? load_global(B.res + o + p) : 'A';
         }
 #pragma unroll
         for (uint32_t it = 0; it < 4; ++it) {
@@ -472,8 +472,8 @@ __device__ __forceinline__ void mid_gene(const DevBuild &B, uint32_t G, uint64_t
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) {
         if (!((hmask >> e) & 1u)) continue;
-        slot_code[r] = key_code<B20>(key[e], k);
-        slot_cnt[r] = static_cast<uint32_t>(hp[r + 1]) - hp[r];
+        store_global(slot_code + r, key_code<B20>(key[e], k));
+        store_global(slot_cnt + r, static_cast<uint32_t>(hp[r + 1]) - hp[r]);
         ++r;
     }
     if (tid == 0) dcnt[G] = total;
@@ -580,8 +580,8 @@ __global__ __launch_bounds__(kWave) void k_mv_compact(const DevBuild *__restrict
         if (g + 1 == B.n_genes) B.mv_ptr[g + 1] = p + d;
     }
     for (uint32_t e = threadIdx.x; e < d; e += kWave) {
-        B.mv_code[p + e] = B.slot_code[o + e];
-        B.mv_cnt[p + e] = B.slot_cnt[o + e];
+        store_global(B.mv_code + p + e, load_global(B.slot_code + o + e));
+        store_global(B.mv_cnt + p + e, load_global(B.slot_cnt + o + e));
         ent_gene[gptr[G] + e] = g;
     }
 }
@@ -637,7 +637,7 @@ __global__ __launch_bounds__(256) void k_ix_hist(const DevBuild *__restrict__ ta
 #pragma unroll
         for (uint32_t q = 0; q < kIxBatch; ++q) {
             const uint32_t e = base + q * 256 + threadIdx.x;
-            c[q] = e < e1 ? B.mv_code[e] : 0ull;
+            c[q] = e < e1 ? load_global(B.mv_code + e) : 0ull;
         }
 #pragma unroll
         for (uint32_t q = 0; q < kIxBatch; ++q)
@@ -705,7 +705,7 @@ __global__ __launch_bounds__(kIxPlaceThreads) void k_ix_place(const DevBuild *__
 #pragma unroll
     for (uint32_t q = 0; q < kIxPerThread; ++q) {
         const uint32_t e = e0 + q * kIxPlaceThreads + threadIdx.x;
-        c[q] = e < e1 ? B.mv_code[e] : 0ull;
+        c[q] = e < e1 ? load_global(B.mv_code + e) : 0ull;
     }
 #pragma unroll
     for (uint32_t q = 0; q < kIxPerThread; ++q)
@@ -724,7 +724,7 @@ __global__ __launch_bounds__(kIxPlaceThreads) void k_ix_place(const DevBuild *__
             const uint32_t e = e0 + (q0 + q) * kIxPlaceThreads + threadIdx.x;
             const bool v = e < e1;
             gn[q] = v ? ent_gene[gbase + e] : 0u;
-            ct[q] = v ? B.mv_cnt[e] : 0u;
+            ct[q] = v ? load_global(B.mv_cnt + e) : 0u;
         }
 #pragma unroll
         for (uint32_t q = 0; q < kIxBatch; ++q) {
@@ -734,7 +734,10 @@ __global__ __launch_bounds__(kIxPlaceThreads) void k_ix_place(const DevBuild *__
             // one record per entry: a single scattered store instead of three
             R r;
             to_rec(B, make_uint4(static_cast<uint32_t>(code), static_cast<uint32_t>(code >> 32), gn[q], ct[q]), &r);
-            reinterpret_cast<R *>(B.ix_tmp)[pos] = r;
+            if constexpr (sizeof(R) == 8)  // as one 64-bit word, through a global (not flat) store
+                store_global(reinterpret_cast<uint64_t *>(B.ix_tmp) + pos, (static_cast<uint64_t>(r.y) << 32) | r.x);
+            else
+                reinterpret_cast<R *>(B.ix_tmp)[pos] = r;
         }
     }
 }
@@ -787,10 +790,10 @@ template <typename R>
 __device__ __forceinline__ void put_entry(const DevBuild &B, uint32_t pos, const R &v) {
     const uint64_t c = rec_code5(B, v);
     const uint32_t g = rec_gene(v);
-    B.ix_code[pos] = c;
-    B.ix_gene[pos] = g;
-    B.ix_cnt[pos] = rec_cnt(v);
-    if (B.key_shift) B.ix_key[pos] = entry_key(B, c, g);
+    store_global(B.ix_code + pos, c);
+    store_global(B.ix_gene + pos, g);
+    store_global(B.ix_cnt + pos, rec_cnt(v));
+    if (B.key_shift) store_global(B.ix_key + pos, entry_key(B, c, g));
 }
 template <typename R>
 __device__ __forceinline__ bool rec_less(const R &a, const R &b) {
@@ -870,7 +873,12 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
 #pragma unroll
         for (uint32_t q = 0; q < kIxPer; ++q) {  // every load issued before the first atomic
             const uint32_t i = q * 256 + threadIdx.x;
-            r[q] = i < n ? tmp[lo + i] : R{};
+            if constexpr (sizeof(R) == 8) {  // one 64-bit word, through a global (not flat) load
+                const uint64_t w = i < n ? load_global(reinterpret_cast<const uint64_t *>(tmp) + lo + i) : 0ull;
+                r[q] = R{static_cast<uint32_t>(w), static_cast<uint32_t>(w >> 32)};
+            } else {
+                r[q] = i < n ? tmp[lo + i] : R{};
+            }
         }
 #pragma unroll
         for (uint32_t q = 0; q < kIxPer; ++q) {
@@ -905,7 +913,7 @@ __global__ __launch_bounds__(256) void k_ix_sort_bin(const DevBuild *__restrict_
             if (i < n) s_rec[s_bstart[bk[q]] + slot[q]] = r[q];
         }
         __syncthreads();
-        for (uint32_t b = threadIdx.x; b < nbb; b += 256) B.ix_dir[b0 + b] = lo + s_bstart[b << B.xb];
+        for (uint32_t b = threadIdx.x; b < nbb; b += 256) store_global(B.ix_dir + b0 + b, lo + s_bstart[b << B.xb]);
         for (uint32_t b = threadIdx.x; b < nslot; b += 256) {
             const uint32_t st = s_bstart[b], size = s_bstart[b + 1] - st;
             if (size <= kIxSmallBucket) {

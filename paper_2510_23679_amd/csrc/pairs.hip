@@ -502,13 +502,13 @@ __device__ __forceinline__ void fused_load(const DevDict &A, uint32_t base, uint
         const uint32_t i = base + q * kJoinThreads + threadIdx.x;
         const bool v = i < a1;
         if constexpr (PACKED) {
-            r.key[q] = v ? A.ix_key[i] : 0u;
+            r.key[q] = v ? load_global(A.ix_key + i) : 0u;
             r.ag[q] = 0u;
         } else {
-            r.code[q] = v ? A.ix_code[i] : ~0ull;
-            r.ag[q] = v ? A.ix_gene[i] : 0u;
+            r.code[q] = v ? load_global(A.ix_code + i) : ~0ull;
+            r.ag[q] = v ? load_global(A.ix_gene + i) : 0u;
         }
-        r.an[q] = v ? A.ix_cnt[i] : 0u;
+        r.an[q] = v ? load_global(A.ix_cnt + i) : 0u;
     }
 }
 
@@ -623,13 +623,13 @@ __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, boo
                 const uint32_t o = atomicAdd(&tcur[a >> s0], m[q]);
                 const uint32_t rl = (a & ((1u << s0) - 1u)) << 24;
                 for (uint32_t t = 0; t < m[q]; ++t)
-                    recs[o + t] = make_uint2(rl | gene_at(p[q] + t), na | (static_cast<uint32_t>(bn[p[q] + t]) << 16));
+                    recs[o + t] = make_uint2(rl | gene_at(p[q] + t), na | (load_global(bn + p[q] + t) << 16));
             }
             if (ba) {
                 for (uint32_t t = 0; t < m[q]; ++t) {
                     const uint32_t g = gene_at(p[q] + t);
                     const uint32_t o = atomicAdd(&tcur[t1 + (g >> s1)], 1u);
-                    recs[o] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | a, static_cast<uint32_t>(bn[p[q] + t]) | (na << 16));
+                    recs[o] = make_uint2(((g & ((1u << s1) - 1u)) << 24) | a, load_global(bn + p[q] + t) | (na << 16));
                 }
             }
         }
@@ -645,7 +645,7 @@ __device__ __forceinline__ void stage_packed(const DevDict &B, uint32_t b0, uint
 #pragma unroll
     for (uint32_t it = 0; it < ITERS; ++it) {
         const uint32_t i = threadIdx.x + it * kJoinThreads;
-        kv[it] = i < nbe ? B.ix_key[b0 + i] : 0u;
+        kv[it] = i < nbe ? load_global(B.ix_key + b0 + i) : 0u;
     }
 #pragma unroll
     for (uint32_t it = 0; it < ITERS; ++it) {
@@ -674,8 +674,8 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
 #pragma unroll
         for (uint32_t k = 0; k < kIters; ++k) {
             const uint32_t i = threadIdx.x + k * kJoinThreads;
-            da[k] = i <= it.n_buckets ? it.adir[i] : 0u;
-            db[k] = i <= it.n_buckets ? it.bdir[i] : 0u;
+            da[k] = i <= it.n_buckets ? load_global(it.adir + i) : 0u;
+            db[k] = i <= it.n_buckets ? load_global(it.bdir + i) : 0u;
         }
         for (uint32_t t = threadIdx.x; t < join_tiles; t += kJoinThreads) tcount[t] = 0;
         // an item that starts after another one overflowed has nothing left to do
