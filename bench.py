@@ -53,7 +53,8 @@ def parse():
                         "sources, in the launch shape given by --workload/--alphabet/--tile-rows/--colmax/--two-pass, "
                         "and print a markdown table")
     p.add_argument("--no-tune", action="store_true",
-                   help="library defaults instead of the autotuner's pick of tile height and column maxima")
+                   help="library defaults instead of the autotuner's pick of tile height, column maxima and "
+                        "join sub-range size")
     p.add_argument("--tune-all", action="store_true",
                    help="the autotuner's whole built-in grid (tile height x sub-range size x persistence x column "
                         "maxima) instead of tile height x column maxima")
@@ -330,7 +331,7 @@ def counters_to_traffic(args) -> None:
                          "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)}
     tr.setdefault("workloads", {})[wl_key] = {
         "shape": {"tile_rows": int(args.tile_rows or 64), "column_maxima": bool(args.colmax),
-                  "two_pass": bool(args.two_pass)},
+                  "join_entries": int(args.join_entries or 512), "two_pass": bool(args.two_pass)},
         "kernels": groups}
     with open(args.traffic, "w") as f:
         json.dump(tr, f, indent=1)
@@ -424,7 +425,8 @@ def run_batched(args):
                 cap = int(sizing.plan.info.inc_capacity)
                 del sizing
                 cands = [pdp.params(inc_capacity=cap, tile_rows=tr, join_entries=je, persistent=pe, colmax=cm)
-                         for tr in (64, 128) for je in (256, 512, 1024) for pe in (False, True) for cm in (False, True)]
+                         for tr in (64, 128) for je in (256, 512, 768, 1024) for pe in (False, True)
+                         for cm in (False, True)]
                 best, tres = pdp.autotune(tasks, cands, reps=2, stream=stream)
                 tuned = {"tile_rows": int(best.tile_rows), "join_entries": int(best.join_entries),
                          "persistent": bool(best.flags & B.PDP_PARAM_PERSISTENT),
@@ -692,8 +694,9 @@ def main():
     explicit = args.join_entries or args.persistent or args.tile_rows or args.colmax or args.two_pass or args.long_path
     if not args.no_tune and not explicit:
         # the launch shape for this workload, picked by the library's autotuner before anything is timed
-        cands = None if args.tune_all else [pdp.params(tile_rows=tr, colmax=cm, theta=frac(args.theta), tau=frac(args.tau))
-                                            for tr in (64, 128) for cm in (False, True)]
+        cands = None if args.tune_all else [pdp.params(tile_rows=tr, colmax=cm, join_entries=je, theta=frac(args.theta),
+                                                       tau=frac(args.tau))
+                                            for tr in (64, 128) for cm in (False, True) for je in (0, 768)]
         best, tres = pdp.autotune(tasks, cands, reps=3, base=prm)
         prm = best
         tuned = {"autotuned": True, "tile_rows": int(best.tile_rows), "join_entries": int(best.join_entries),
@@ -777,7 +780,7 @@ def main():
     traffic, measured = None, None
     wl_key = ("large" if large else "allpairs") + ("_nt" if nt else "")
     shape = {"tile_rows": int(prm.tile_rows or 64), "column_maxima": bool(prm.flags & B.PDP_PARAM_COLMAX),
-             "two_pass": two_pass}
+             "join_entries": int(prm.join_entries or 512), "two_pass": two_pass}
     try:
         with open(args.traffic) as f:
             tr = json.load(f)

@@ -398,7 +398,7 @@ void pdp_graph_destroy(pdp_graph *graph);
  * planned for the given tasks, run once to warm up and then reps times between
  * two HIP events; the fastest candidate whose runs end with a clean status is
  * returned.  candidates NULL: a built-in grid of tile heights (32, 64, 128
- * rows), join sub-range sizes (256, 512, 1024 entries), persistent on/off and
+ * rows), join sub-range sizes (256, 512, 768, 1024 entries), persistent on/off and
  * column maxima on/off (PDP_PARAM_COLMAX).  bh/bbh/status as
  * for pdp_plan_launch (their rows do not depend on the parameters); ws of
  * pdp_autotune_ws_size bytes.  Synchronises the stream.

@@ -1033,9 +1033,9 @@ __device__ __forceinline__ void tile_sorted(const DevTile &tl, const DevTask &T,
     // (both at most 16 bits), the rows' go to S.nr
     for (uint32_t r = threadIdx.x; r < u; r += kTileThreads) {
         const uint32_t c = ucol[r] & 0xFFFFFFu;
-        msum[r] |= (c < C.n_genes ? C.nwin[c] : 0u) << 16;  // a column past the genome is never a row's
+        msum[r] |= (c < C.n_genes ? load_global(C.nwin + c) : 0u) << 16;  // a column past the genome is never a row's
     }
-    for (uint32_t rl = threadIdx.x; rl < tl.nrows; rl += kTileThreads) S.nr[rl] = R.nwin[tl.row0 + rl];
+    for (uint32_t rl = threadIdx.x; rl < tl.nrows; rl += kTileThreads) S.nr[rl] = load_global(R.nwin + tl.row0 + rl);
     __syncthreads();
     for (uint32_t rl = w; rl < tl.nrows; rl += NW) {
         const uint32_t len = S.rowlen[rl];
@@ -1077,7 +1077,7 @@ __device__ __forceinline__ void tile_dense(const DevTile &tl, const DevTask &T, 
     const uint32_t NA = filt ? 3 : 1;     // sums per column: minima (+ row and column occurrences)
     const uint32_t cw_words = (W + 3) & ~3u;
     uint16_t *cw = reinterpret_cast<uint16_t *>(lds);
-    for (uint32_t c = threadIdx.x; c < ncols; c += kTileThreads) cw[c] = static_cast<uint16_t>(C.nwin[c]);
+    for (uint32_t c = threadIdx.x; c < ncols; c += kTileThreads) cw[c] = static_cast<uint16_t>(load_global(C.nwin + c));
     uint32_t *acc_base = lds + cw_words;
     const uint32_t G = (lds_words - cw_words) / (NA * W + WB);  // rows per pass, at least 1 by plan
     const uint32_t wave = threadIdx.x / kWave;
@@ -1114,7 +1114,7 @@ __device__ __forceinline__ void tile_dense(const DevTile &tl, const DevTask &T, 
             // a lane walks one bitmap word, so lane chunks of 64 words stay in column order
             const uint32_t lane = lane_id();
             const uint32_t grow = T.row_base[tl.dir] + row;
-            const uint32_t nr = R.nwin[row];
+            const uint32_t nr = load_global(R.nwin + row);
             // sum of minima of column 2*wd + h, or 0 when the pair is filtered out
             auto mval = [&](uint32_t wd, uint32_t h) -> uint32_t {
                 const uint32_t sh = h << 4;
@@ -1230,7 +1230,7 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
     for (uint32_t rl = g0 + threadIdx.x; rl < g1; rl += kTileThreads) {
         S.best[rl] = 0;
         S.ties[rl] = 0;
-        S.nr[rl] = R.nwin[tl.row0 + rl];
+        S.nr[rl] = load_global(R.nwin + tl.row0 + rl);
     }
     __syncthreads();
     const uint32_t ncols = C.n_genes;
@@ -1268,7 +1268,7 @@ __device__ __forceinline__ void tile_hashed(const DevTile &tl, const DevTask &T,
 #pragma unroll
     for (uint32_t q = 0; q < kSlotsPer; ++q) {
         const uint32_t key = hk[q * kTileThreads + threadIdx.x];
-        ncw[q] = key ? C.nwin[(key - 1) & 0xFFFFFFu] : 0u;
+        ncw[q] = key ? load_global(C.nwin + ((key - 1) & 0xFFFFFFu)) : 0u;
     }
 #pragma unroll
     for (uint32_t q = 0; q < kSlotsPer; ++q) {
@@ -1700,8 +1700,8 @@ __global__ __launch_bounds__(kLongThreads) void k_long_rows(const DevTask *__res
         const uint32_t pos0 = WRITE ? bh_ptr[grow] : 0u;
         if (WRITE && bh_ptr[grow + 1] - pos0 <= kSlab) continue;  // the slab copy placed this row
         const bool filt = T.theta_d || T.tau_d;
-        const uint32_t nr = R.nwin[row];
-        const uint32_t e0 = R.mv_ptr[row], e1 = R.mv_ptr[row + 1];
+        const uint32_t nr = load_global(R.nwin + row);
+        const uint32_t e0 = load_global(R.mv_ptr + row), e1 = load_global(R.mv_ptr + row + 1);
         const uint32_t ncols = C.n_genes;
         const uint32_t nblk = (ncols + kLongCols - 1) / kLongCols;
         // sums of column genes [c0, c0 + cn) into acc / asr / asc
@@ -1715,21 +1715,21 @@ __global__ __launch_bounds__(kLongThreads) void k_long_rows(const DevTask *__res
             }
             __syncthreads();
             for (uint32_t e = e0 + tid; e < e1; e += kLongThreads) {
-                const uint64_t code = R.mv_code[e];
-                const uint32_t cr = R.mv_cnt[e];
+                const uint64_t code = load_global(R.mv_code + e);
+                const uint32_t cr = load_global(R.mv_cnt + e);
                 const uint32_t b = bucket_of(code, C.k, C.lead, C.bits);
                 if (b >= C.n_buckets) continue;  // not a k-mer of the alphabet: in no index
-                const uint32_t end = C.ix_dir[b + 1];
-                uint32_t l = C.ix_dir[b], h = end;  // first entry of the code: entries ascend by (code, gene)
+                const uint32_t end = load_global(C.ix_dir + b + 1);
+                uint32_t l = load_global(C.ix_dir + b), h = end;  // first entry of the code: entries ascend by (code, gene)
                 while (l < h) {
                     const uint32_t mid = (l + h) >> 1;
-                    if (C.ix_code[mid] < code) l = mid + 1;
+                    if (load_global(C.ix_code + mid) < code) l = mid + 1;
                     else h = mid;
                 }
-                for (uint32_t i = l; i < end && C.ix_code[i] == code; ++i) {
-                    const uint32_t g = C.ix_gene[i] - c0;  // genes below c0 wrap past cn
+                for (uint32_t i = l; i < end && load_global(C.ix_code + i) == code; ++i) {
+                    const uint32_t g = load_global(C.ix_gene + i) - c0;  // genes below c0 wrap past cn
                     if (g >= cn) continue;
-                    const uint32_t cc = C.ix_cnt[i];
+                    const uint32_t cc = load_global(C.ix_cnt + i);
                     atomicAdd(&acc[g], min(cr, cc));
                     if (filt) {
                         atomicAdd(&asr[g], cr);
@@ -1744,7 +1744,7 @@ __global__ __launch_bounds__(kLongThreads) void k_long_rows(const DevTask *__res
             *m = acc[i];
             *d = 0;
             if (!*m) return;
-            const uint32_t nc = C.nwin[c0 + i];
+            const uint32_t nc = load_global(C.nwin + c0 + i);
             if (filt && !candidate(T, nr, nc, asr[i], asc[i])) {
                 *m = 0;
                 return;

@@ -64,7 +64,7 @@ void pdp_graph_destroy(pdp_graph *g) {
 static std::vector<pdp_params> default_candidates() {
     std::vector<pdp_params> c;
     const uint32_t rows[] = {32, 64, 128};
-    const uint32_t join[] = {256, 512, 1024};
+    const uint32_t join[] = {256, 512, 768, 1024};
     for (uint32_t colmax = 0; colmax < 2; ++colmax)
         for (uint32_t persistent = 0; persistent < 2; ++persistent)
             for (uint32_t r : rows)

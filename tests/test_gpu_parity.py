@@ -398,8 +398,10 @@ def test_full_size_family_model_complete():
     dicts = [pdp.Dictionary.build_from(g, k) for g in ds.genomes]
     rng = np.random.default_rng(7)
     # the launch shapes the benchmark's autotuner chooses between
-    for prm in (pdp.params(), pdp.params(colmax=True), pdp.params(colmax=True, tile_rows=128)):
-        say("full-size 10 x 3000 workload, k =", k, "column maxima", bool(prm.flags & 2), "tile rows", prm.tile_rows)
+    for prm in (pdp.params(), pdp.params(colmax=True), pdp.params(colmax=True, tile_rows=128),
+                pdp.params(colmax=True, join_entries=768)):
+        say("full-size 10 x 3000 workload, k =", k, "column maxima", bool(prm.flags & 2), "tile rows", prm.tile_rows,
+            "join entries", prm.join_entries)
         runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts), prm)
         runner.run()
         res = runner.results()
@@ -425,7 +427,8 @@ def test_full_size_large_workload_complete():
     dicts.check_status()
     # the default launch shape and the one the benchmark's autotuner picks on this workload
     results = []
-    for prm in (pdp.params(), pdp.params(colmax=True, tile_rows=128)):
+    for prm in (pdp.params(), pdp.params(colmax=True, tile_rows=128),
+                pdp.params(colmax=True, tile_rows=128, join_entries=768)):
         runner = pdp.PairRunner(pdp.all_pairs_tasks(dicts.dicts), prm)
         runner.run()
         results.append(runner.results())
@@ -433,7 +436,7 @@ def test_full_size_large_workload_complete():
     del dicts
     og = oracle.genomes(ds.genomes, k)
     want = oracle.all_pairs_sparse(og, ds.pairs())
-    say("sparse oracle done; comparing 1225 pairs in two launch shapes")
+    say("sparse oracle done; comparing 1225 pairs in three launch shapes")
     ties = 0
     for t, (i, j) in enumerate(ds.pairs()):
         w = want.pop((i, j))
