@@ -157,3 +157,49 @@ def test_kernel_timers_on_a_plan_without_join_items():
         assert n == 2 and ms >= 0.0, name
     torch.cuda.synchronize()
     compare(gens, 5, runner.results())
+
+
+def test_pdp_bh_and_noalloc_on_long_genes():
+    # the single-pair entry points on long-gene dictionaries: pdp_bh with a workspace and the
+    # no-allocation form agree with each other and with the oracle
+    say("pdp_bh and pdp_bh_noalloc on a long-gene pair")
+    a, b = long_genomes("aa", seed=13)
+    da, db = pdp.Dictionary.build_from(a, 5), pdp.Dictionary.build_from(b, 5)
+    want = oracle.bh(oracle.OracleGenome(a, 5), oracle.OracleGenome(b, 5))
+    for fn in (pdp.bh, pdp.bh_noalloc):
+        check_bh(fn(da, db).host(), want)
+
+
+def test_served_request_with_a_long_gene():
+    # the server binds a request's dictionary for long genes when one of its genes passes the
+    # 16-bit window limit; its pairs with every resident then take the long-gene path
+    say("serving: a request with a 70,000-letter gene against 3 residents")
+    rng = random.Random(21)
+    L = LETTERS["aa"]
+    res_genomes = [genome_from_strings(["".join(rng.choice(L) for _ in range(rng.randint(40, 400)))
+                                        for _ in range(120)]) for _ in range(3)]
+    residents = [pdp.Dictionary.build_from(g, 5) for g in res_genomes]
+    a, _ = long_genomes("aa", seed=17)
+    short = genome_from_strings(["".join(rng.choice(L) for _ in range(rng.randint(40, 400))) for _ in range(80)])
+    arrivals = [a, short]
+    srv = pdp.Server(residents, 1 << 30, slots=2)
+    out = {}
+    try:
+        for j, g in enumerate(arrivals):
+            srv.submit(g, j)
+        while len(out) < len(arrivals):
+            for d in srv.poll(8, wait_us=200000):
+                out[d.tag] = (d, srv.fetch(d.tag))
+                srv.release(d.tag)
+    finally:
+        srv.close()
+    og_res = [oracle.OracleGenome(g, 5) for g in res_genomes]
+    for j, g in enumerate(arrivals):
+        d, res = out[j]
+        assert d.code == 0 and res.code == 0
+        q = oracle.OracleGenome(g, 5)
+        for r, og in enumerate(og_res):
+            ab, ba = oracle.bh(q, og), oracle.bh(og, q)
+            check_bh(res.best_hits(r, 0), ab)
+            check_bh(res.best_hits(r, 1), ba)
+            check_bbh(res.bbh_pairs(r), oracle.bbh(ab, ba))
