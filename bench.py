@@ -94,6 +94,8 @@ def parse():
     p.add_argument("--serve-no-colmax", action="store_true",
                    help="serving: the residents' best hits from their own rows instead of column maxima")
     p.add_argument("--serve-tile-rows", type=int, default=128, help="serving: rows per accumulation tile")
+    p.add_argument("--serve-join-entries", type=int, default=0,
+                   help="serving: index entries per join sub-range (0: the library default, 512)")
     return p.parse_args()
 
 
@@ -540,7 +542,8 @@ def serve_stream(args, wl, arrivals):
     batch.check_status()
     res_genes = sum(d.n_genes for d in batch.dicts)
     srv = pdp.Server(batch.dicts, int(args.budget_gb * (1 << 30)), slots=args.slots,
-                     prm=pdp.params(tile_rows=args.serve_tile_rows, colmax=not args.serve_no_colmax))
+                     prm=pdp.params(tile_rows=args.serve_tile_rows, colmax=not args.serve_no_colmax,
+                                    join_entries=args.serve_join_entries))
 
     def drain(want, done):
         while len(done) < want:
@@ -628,6 +631,7 @@ def run_serving(args):
            "data": "synthetic", "config": {"workload": lat.pop("workload"), "slots": args.slots,
                                             "budget_gb": args.budget_gb, "offered_load": args.load,
                                             "tile_rows": args.serve_tile_rows,
+                                            "join_entries": args.serve_join_entries or 512,
                                             "column_maxima": not args.serve_no_colmax},
            "latency": lat, "host_generation_s": round(gen_s, 1)}
     print(json.dumps(out), flush=True)
