@@ -480,7 +480,9 @@ struct JoinLdsFused {
     DevTask task;
     uint32_t adir[kJoinDirCap + 1];
     uint32_t bdir[kJoinDirCap + 1];
-    uint64_t bcode[kJoinLdsCap];  // staged target codes, or kJoinLdsCapP packed keys
+    // staged target codes, or kJoinLdsCapP packed keys; the last word pairs are spare: the
+    // packed search reads up to two keys past the end of a run
+    uint64_t bcode[kJoinLdsCap + 2];
     uint32_t bgene[kJoinLdsCap];  // staged target genes, or the query entries' buckets (16 bits each)
     uint32_t found, next, drop;
 };
@@ -515,8 +517,9 @@ __device__ __forceinline__ void fused_load(const DevDict &A, uint32_t base, uint
 // Query entries [a0, a1) against the target entries from b0 on (nbe of them): packed keys bk
 // or codes bc with genes bg, counts bn (the index's own array), all indexed relative to b0; bdir is the item's slice
 // of the target directory (index bucket - bl), adir the query's.  abk (packed, optional) holds
-// each query entry's bucket.  Returns false, uniformly, when a region overflowed.
-template <bool PACKED, typename CN>
+// each query entry's bucket.  STAGED: the packed keys bk are in LDS, with two readable words
+// past the last one.  Returns false, uniformly, when a region overflowed.
+template <bool PACKED, bool STAGED, typename CN>
 __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, bool loaded, uint32_t a0, uint32_t a1,
                                             const uint16_t *abk, uint32_t jlo, uint32_t jhi, const uint32_t *adir,
                                             uint32_t bl, uint32_t b0, uint32_t nbe, const uint64_t *bc,
@@ -562,14 +565,42 @@ __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, boo
                     u = lo;
                 }
                 const uint32_t end = min(bdir[u + 1] - b0, nbe);
-                uint32_t lo = min(bdir[u] - b0, end), hi = end;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if ((bk[mid] >> shb) < want) lo = mid + 1;
-                    else hi = mid;
+                uint32_t lo = min(bdir[u] - b0, end), n = 0;
+                if constexpr (STAGED) {
+                    // target keys with the query's tail lie in [wlo, whi], whatever their gene
+                    const uint32_t wlo = want << shb, whi = wlo | mskb;
+                    // halving without an early exit: the first key >= wlo stays in [lo, lo + len]
+                    // (positions as byte offsets: one shift-and-add forms a probe's address)
+                    const char *bkb = reinterpret_cast<const char *>(bk);
+                    uint32_t len = end - lo, lob = lo * 4u;
+                    while (len > 1) {
+                        const uint32_t half = len >> 1, pb = lob + half * 4u;
+                        lob = *reinterpret_cast<const uint32_t *>(bkb + pb) < wlo ? pb : lob;
+                        len -= half;
+                    }
+                    lo = lob >> 2;
+                    // it is lo or lo + 1; the equal run mostly holds 0 or 1 keys, so three keys
+                    // are read at once (those at or past end are not used)
+                    const uint32_t k0 = bk[lo], k1 = bk[lo + 1], k2 = bk[lo + 2];
+                    const bool step = len && k0 < wlo;
+                    lo += step;
+                    const uint32_t c0 = step ? k1 : k0, c1 = step ? k2 : k1;
+                    if (lo < end && c0 <= whi) {
+                        n = 1;
+                        if (lo + 1 < end && c1 <= whi) {
+                            n = 2;
+                            while (lo + n < end && bk[lo + n] <= whi) ++n;
+                        }
+                    }
+                } else {
+                    uint32_t hi = end;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if ((bk[mid] >> shb) < want) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    while (lo + n < end && (bk[lo + n] >> shb) == want) ++n;
                 }
-                uint32_t n = 0;
-                while (lo + n < end && (bk[lo + n] >> shb) == want) ++n;
                 p[q] = lo;
                 m[q] = n;
             } else {
@@ -718,11 +749,11 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
                     for (uint32_t u = s0 - bl + threadIdx.x; u < s1 - bl; u += kJoinThreads)
                         for (uint32_t i = L.adir[u]; i < L.adir[u + 1]; ++i) abk[i - a0] = static_cast<uint16_t>(u);
                 __syncthreads();
-                ok = fused_range<true>(T, r, true, a0, a1, abk, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, nullptr, bkey,
+                ok = fused_range<true, true>(T, r, true, a0, a1, abk, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, nullptr, bkey,
                                        nullptr, T.b.ix_cnt + b0, L.bdir, tcount, tcur, &L.drop, fill, tiles, fallback, recs);
                 __syncthreads();  // the staged arrays take the next sub-range
             } else {
-                ok = fused_range<true>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, nullptr,
+                ok = fused_range<true, false>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, nullptr,
                                        T.b.ix_key + b0, nullptr, T.b.ix_cnt + b0, L.bdir, tcount, tcur, &L.drop, fill,
                                        tiles, fallback, recs);
             }
@@ -732,12 +763,12 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
                 L.bgene[i] = T.b.ix_gene[b0 + i];
             }
             __syncthreads();
-            ok = fused_range<false>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, L.bcode,
+            ok = fused_range<false, false>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, L.bcode,
                                     nullptr, L.bgene, T.b.ix_cnt + b0, L.bdir, tcount, tcur, &L.drop, fill, tiles, fallback,
                                     recs);
             __syncthreads();
         } else {
-            ok = fused_range<false>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe,
+            ok = fused_range<false, false>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe,
                                     T.b.ix_code + b0, nullptr, T.b.ix_gene + b0, T.b.ix_cnt + b0, L.bdir, tcount, tcur,
                                     &L.drop, fill, tiles, fallback, recs);
         }
