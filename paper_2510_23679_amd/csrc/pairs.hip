@@ -483,7 +483,7 @@ struct JoinLdsFused {
     // staged target codes, or kJoinLdsCapP packed keys; the last word pairs are spare: the
     // packed search reads up to two keys past the end of a run
     uint64_t bcode[kJoinLdsCap + 2];
-    uint32_t bgene[kJoinLdsCap];  // staged target genes, or the query entries' buckets (16 bits each)
+    uint32_t bgene[kJoinLdsCap];  // staged target genes (64-bit codes)
     uint32_t found, next, drop;
 };
 // followed in dynamic LDS by two words per tile of the task: the batch's record count and
@@ -494,17 +494,45 @@ struct JoinLdsFused {
 struct FusedBatch {
     uint64_t code[kFuseUnroll];
     uint32_t key[kFuseUnroll];
+    uint32_t clo[kFuseUnroll];  // low word of the code, packed keys with query buckets from codes
     uint32_t ag[kFuseUnroll], an[kFuseUnroll];
 };
 
+// Query buckets from codes.  Within an item (fewer than kJoinDirCap buckets from its first, bl) a
+// packed query entry's bucket follows from the low 32 bits of its code, with no directory
+// search.  Amino acids (base-20 buckets): the last three leading letters, whole in the low word
+// when the tail takes at most 17 bits, give the bucket mod 8000.  Nucleotides (2-bit letters,
+// base-4 buckets): the low 9 bits of the bucket, there when the tail takes at most 23 bits.
+// Otherwise (kQbSearch) each entry's bucket is searched in the item's directory.  (Filling a
+// table of the query entries' buckets from the directory, one thread per bucket, cost the join
+// 4% more: the fill waits for the longest bucket of each wave.)
+constexpr uint32_t kQbSearch = 0, kQbAmino = 1, kQbNucleotide = 2;
+static_assert(kJoinDirCap <= 512, "an item's buckets are told apart by 9 bits (nucleotides), mod 8000 (amino acids)");
+__device__ __forceinline__ uint32_t query_bucket_mode(const DevDict &A) {
+    const uint32_t tb = A.bits * (A.k - A.lead);
+    if (A.bits == 5) return tb <= 17 ? kQbAmino : kQbSearch;
+    return tb <= 23 ? kQbNucleotide : kQbSearch;
+}
+// The item-relative bucket of a query entry whose code's low word is clo (tb tail bits).
+__device__ __forceinline__ uint32_t query_bucket(uint32_t mode, uint32_t clo, uint32_t tb, uint32_t bl) {
+    const uint32_t x = clo >> tb;  // leading letters, the last one lowest
+    if (mode == kQbAmino) {
+        const uint32_t m = (x & 31u) + ((x >> 5) & 31u) * 20u + ((x >> 10) & 31u) * 400u;  // bucket mod 8000
+        const uint32_t c = bl % 8000u;
+        return m >= c ? m - c : m + 8000u - c;
+    }
+    return (x - bl) & 511u;
+}
+
 template <bool PACKED>
-__device__ __forceinline__ void fused_load(const DevDict &A, uint32_t base, uint32_t a1, FusedBatch &r) {
+__device__ __forceinline__ void fused_load(const DevDict &A, uint32_t base, uint32_t a1, uint32_t qmode, FusedBatch &r) {
 #pragma unroll
     for (uint32_t q = 0; q < kFuseUnroll; ++q) {
         const uint32_t i = base + q * kJoinThreads + threadIdx.x;
         const bool v = i < a1;
         if constexpr (PACKED) {
             r.key[q] = v ? load_global(A.ix_key + i) : 0u;
+            r.clo[q] = v ? load_global(reinterpret_cast<const uint32_t *>(A.ix_code + i)) : 0u;
             r.ag[q] = 0u;
         } else {
             r.code[q] = v ? load_global(A.ix_code + i) : ~0ull;
@@ -516,12 +544,13 @@ __device__ __forceinline__ void fused_load(const DevDict &A, uint32_t base, uint
 
 // Query entries [a0, a1) against the target entries from b0 on (nbe of them): packed keys bk
 // or codes bc with genes bg, counts bn (the index's own array), all indexed relative to b0; bdir is the item's slice
-// of the target directory (index bucket - bl), adir the query's.  abk (packed, optional) holds
-// each query entry's bucket.  STAGED: the packed keys bk are in LDS, with two readable words
-// past the last one.  Returns false, uniformly, when a region overflowed.
+// of the target directory (index bucket - bl), adir the query's.  Packed: qmode says how a query
+// entry's bucket is found (query_bucket_mode), qtb is the query's tail bits.  STAGED: the packed
+// keys bk are in LDS, with two readable words past the last one.  Returns false, uniformly, when
+// a region overflowed.
 template <bool PACKED, bool STAGED, typename CN>
 __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, bool loaded, uint32_t a0, uint32_t a1,
-                                            const uint16_t *abk, uint32_t jlo, uint32_t jhi, const uint32_t *adir,
+                                            uint32_t qmode, uint32_t qtb, uint32_t jlo, uint32_t jhi, const uint32_t *adir,
                                             uint32_t bl, uint32_t b0, uint32_t nbe, const uint64_t *bc,
                                             const uint32_t *bk, const uint32_t *bg, const CN *bn, const uint32_t *bdir,
                                             uint32_t *tcount, uint32_t *tcur, uint32_t *drop,
@@ -538,7 +567,7 @@ __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, boo
         else return bg[j];
     };
     for (uint32_t base = a0; base < a1; base += U * kJoinThreads) {
-        if (!loaded || base != a0) fused_load<PACKED>(T.a, base, a1, r);
+        if (!loaded || base != a0) fused_load<PACKED>(T.a, base, a1, qmode, r);
         uint32_t p[U], m[U];
         // search: the first target entry of the query's k-mer inside its bucket, and the run length
         // (packed keys compare their 32-bit tails, codes their 64 bits)
@@ -553,8 +582,8 @@ __device__ __forceinline__ bool fused_range(const DevTask &T, FusedBatch &r, boo
                 r.ag[q] = key & mska;
                 const uint32_t want = key >> sha;
                 uint32_t u;
-                if (abk) {
-                    u = abk[i - a0];
+                if (qmode != kQbSearch) {
+                    u = query_bucket(qmode, r.clo[q], qtb, bl);
                 } else {  // the last directory slot in [jlo, jhi) with adir <= i
                     uint32_t lo = jlo, hi = jhi;
                     while (hi - lo > 1) {
@@ -726,6 +755,9 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
     const uint32_t bl = it.bl;
     const uint32_t bh = bl + it.n_buckets;
     const bool packed = T.a.key_shift && T.b.key_shift;
+    // the same in every lane: scalar registers (as values read from LDS they would take vector ones)
+    const uint32_t qmode = __builtin_amdgcn_readfirstlane(packed ? query_bucket_mode(T.a) : kQbSearch);
+    const uint32_t qtb = __builtin_amdgcn_readfirstlane(T.a.bits * (T.a.k - T.a.lead));
     const bool skip = L.drop != 0;
     for (uint32_t s0 = bl; s0 < bh && !skip; s0 += T.bpw) {
         const uint32_t s1 = min(bh, s0 + T.bpw);
@@ -738,24 +770,21 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
         if (packed) {
             uint32_t *bkey = reinterpret_cast<uint32_t *>(L.bcode);  // packed keys take the code stage
             if (nbe <= kJoinLdsCapP) {
-                uint16_t *abk = a1 - a0 <= kJoinLdsCapP ? reinterpret_cast<uint16_t *>(L.bgene) : nullptr;
-                fused_load<true>(T.a, a0, a1, r);  // in flight while the target side is staged
+                fused_load<true>(T.a, a0, a1, qmode, r);  // in flight while the target side is staged
                 // a typical sub-range stages at most half the stage: half the unrolled iterations
                 if (nbe <= kJoinLdsCapP / 2)
                     stage_packed<kJoinLdsCapP / 2 / kJoinThreads>(T.b, b0, nbe, bkey);
                 else
                     stage_packed<kJoinLdsCapP / kJoinThreads>(T.b, b0, nbe, bkey);
-                if (abk)
-                    for (uint32_t u = s0 - bl + threadIdx.x; u < s1 - bl; u += kJoinThreads)
-                        for (uint32_t i = L.adir[u]; i < L.adir[u + 1]; ++i) abk[i - a0] = static_cast<uint16_t>(u);
                 __syncthreads();
-                ok = fused_range<true, true>(T, r, true, a0, a1, abk, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, nullptr, bkey,
-                                       nullptr, T.b.ix_cnt + b0, L.bdir, tcount, tcur, &L.drop, fill, tiles, fallback, recs);
+                ok = fused_range<true, true>(T, r, true, a0, a1, qmode, qtb, s0 - bl, s1 - bl, L.adir, bl, b0, nbe,
+                                             nullptr, bkey, nullptr, T.b.ix_cnt + b0, L.bdir, tcount, tcur, &L.drop,
+                                             fill, tiles, fallback, recs);
                 __syncthreads();  // the staged arrays take the next sub-range
             } else {
-                ok = fused_range<true, false>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, nullptr,
-                                       T.b.ix_key + b0, nullptr, T.b.ix_cnt + b0, L.bdir, tcount, tcur, &L.drop, fill,
-                                       tiles, fallback, recs);
+                ok = fused_range<true, false>(T, r, false, a0, a1, qmode, qtb, s0 - bl, s1 - bl, L.adir, bl, b0, nbe,
+                                              nullptr, T.b.ix_key + b0, nullptr, T.b.ix_cnt + b0, L.bdir, tcount, tcur,
+                                              &L.drop, fill, tiles, fallback, recs);
             }
         } else if (nbe <= kJoinLdsCap) {
             for (uint32_t i = threadIdx.x; i < nbe; i += kJoinThreads) {
@@ -763,14 +792,14 @@ __device__ __forceinline__ void fused_chunk(uint32_t chunk, const DevTask *__res
                 L.bgene[i] = T.b.ix_gene[b0 + i];
             }
             __syncthreads();
-            ok = fused_range<false, false>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe, L.bcode,
-                                    nullptr, L.bgene, T.b.ix_cnt + b0, L.bdir, tcount, tcur, &L.drop, fill, tiles, fallback,
-                                    recs);
+            ok = fused_range<false, false>(T, r, false, a0, a1, kQbSearch, qtb, s0 - bl, s1 - bl, L.adir, bl, b0, nbe,
+                                           L.bcode, nullptr, L.bgene, T.b.ix_cnt + b0, L.bdir, tcount, tcur, &L.drop,
+                                           fill, tiles, fallback, recs);
             __syncthreads();
         } else {
-            ok = fused_range<false, false>(T, r, false, a0, a1, nullptr, s0 - bl, s1 - bl, L.adir, bl, b0, nbe,
-                                    T.b.ix_code + b0, nullptr, T.b.ix_gene + b0, T.b.ix_cnt + b0, L.bdir, tcount, tcur,
-                                    &L.drop, fill, tiles, fallback, recs);
+            ok = fused_range<false, false>(T, r, false, a0, a1, kQbSearch, qtb, s0 - bl, s1 - bl, L.adir, bl, b0, nbe,
+                                           T.b.ix_code + b0, nullptr, T.b.ix_gene + b0, T.b.ix_cnt + b0, L.bdir,
+                                           tcount, tcur, &L.drop, fill, tiles, fallback, recs);
         }
         if (!ok) break;  // uniform: every thread read the same drop flag after a barrier
     }

@@ -157,6 +157,20 @@ def test_family_model_small_all_pairs(k):
     compare_all(ds.genomes, k, res)
 
 
+# The join finds a packed query entry's bucket from the low word of its code when the tail leaves
+# enough leading letters there (amino acids up to k = 7, nucleotides up to 23 tail bits), and by a
+# search of the item's directory otherwise: both sides of each limit, both alphabets, with and
+# without column maxima.
+@pytest.mark.parametrize("alphabet,k,genes", [("aa", 7, 300), ("aa", 8, 300), ("nt", 20, 250), ("nt", 21, 200)])
+@pytest.mark.parametrize("colmax", [False, True])
+def test_query_bucket_modes(alphabet, k, genes, colmax):
+    say("query buckets:", alphabet, "k =", k, genes, "genes x 3 genomes, column maxima", colmax)
+    ds = make_config(2, genomes=3, genes=genes, alphabet=alphabet)
+    dicts, res = run_all(ds.genomes, k, pdp.params(colmax=colmax))
+    assert all(d.d.key_shift > 0 for d in dicts)  # packed keys: the join path under test
+    compare_all(ds.genomes, k, res)
+
+
 def test_paralog_ties():
     say("paralog copies (exact ties), 3 genomes")
     ds = make_config(3, genomes=3, genes_lo=300, genes_hi=500, core=150)
