@@ -935,10 +935,13 @@ struct ColWs {
     uint64_t cap;
 };
 
-// Key of J = m/d that orders values exactly: floor(m * 2^42 / d).  Distinct values differ by
-// at least 1/(d1 d2) > 2^-42 (d < 2^17), so their keys differ; equal values share a key.
+// Key of J = m/d that orders values exactly: the bits of the correctly rounded double m / d.
+// Distinct values differ by at least 1/(d1 d2) > 2^-34 (d < 2^17), far more than the rounding
+// error (2^-53 relative, values at most 1), so their quotients keep their order; equal values
+// round alike; positive doubles order as their bit patterns.  (An integer key floor(m 2^42 / d)
+// orders them too, but its 64-bit division is a long instruction sequence per pair.)
 __device__ __forceinline__ unsigned long long colmax_key(uint32_t m, uint32_t d) {
-    return (static_cast<unsigned long long>(m) << 42) / d;
+    return static_cast<unsigned long long>(__double_as_longlong(static_cast<double>(m) / static_cast<double>(d)));
 }
 
 // Raises the column's running maximum by the pair's key; true when the pair is at or above
