@@ -331,10 +331,12 @@ def counters_to_traffic(args) -> None:
     tr["source_hash"] = source_hash()
     tr["calibration"] = {"kernel": "elementwise int32 copy (1 GiB read, 1 GiB written)",
                          "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)}
-    tr.setdefault("workloads", {})[wl_key] = {
-        "shape": {"tile_rows": int(args.tile_rows or 64), "column_maxima": bool(args.colmax),
-                  "join_entries": int(args.join_entries or 512), "two_pass": bool(args.two_pass)},
-        "kernels": groups}
+    # one entry per launch shape of the workload (the autotuner may pick any of them)
+    shape = {"tile_rows": int(args.tile_rows or 64), "column_maxima": bool(args.colmax),
+             "join_entries": int(args.join_entries or 512), "two_pass": bool(args.two_pass)}
+    entries = tr.setdefault("workloads", {}).get(wl_key, [])
+    entries = [e for e in (entries if isinstance(entries, list) else [entries]) if e.get("shape") != shape]
+    tr["workloads"][wl_key] = entries + [{"shape": shape, "kernels": groups}]
     with open(args.traffic, "w") as f:
         json.dump(tr, f, indent=1)
         f.write("\n")
@@ -788,10 +790,11 @@ def main():
     try:
         with open(args.traffic) as f:
             tr = json.load(f)
-        wl_tr = tr.get("workloads", {}).get(wl_key, {})
+        wl_tr = tr.get("workloads", {}).get(wl_key, [])
+        wl_tr = next((e for e in (wl_tr if isinstance(wl_tr, list) else [wl_tr]) if e.get("shape") == shape), {})
         kernels = wl_tr.get("kernels", {})
         # counters hold for these kernels in the launch shape they were taken in
-        if tr.get("source_hash") == source_hash() and args.kernel in kernels and wl_tr.get("shape") == shape:
+        if tr.get("source_hash") == source_hash() and args.kernel in kernels:
             traffic = kernels[args.kernel]["hbm_bytes_per_launch"]
             measured = dict(zip(("achieved", "frac"), _frac(traffic, avg_kernel_ms)))
     except (OSError, ValueError):
