@@ -310,15 +310,24 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         if (!flags) return bail(fail(PDP_E_INVAL, "task %u: no output selected", t));
         DevTask &d = caller[t];
         std::memset(&d, 0, sizeof(d));
-        d.a = dev_dict(tk.a);
-        d.b = dev_dict(tk.b);
         const bool long_task = ((tk.a->flags | tk.b->flags) & PDP_DICT_LONG_GENES) != 0;
         is_long[t] = long_task ? 1 : 0;
+        // The join searches every entry of its query genome (the task's a) in the other one, so
+        // the smaller genome (by entry capacity) takes that side: the task then holds the caller's
+        // genomes swapped, with its directions swapped alike (kTaskSwapped); output rows keep the
+        // caller's layout.
+        const bool swap = !long_task && tk.b->capacity < tk.a->capacity;
+        const pdp_dict *qa = swap ? tk.b : tk.a, *qb = swap ? tk.a : tk.b;
+        const uint32_t dflags = swap ? (flags & PDP_TASK_BBH) | ((flags & PDP_TASK_AB) ? PDP_TASK_BA : 0u) |
+                                           ((flags & PDP_TASK_BA) ? PDP_TASK_AB : 0u)
+                                     : flags;
+        d.a = dev_dict(qa);
+        d.b = dev_dict(qb);
         // column maxima: b's best hits from the AB tiles' columns, records for one direction
         const bool colmax =
             !long_task && (prm.flags & PDP_PARAM_COLMAX) && (flags & PDP_TASK_AB) && (flags & PDP_TASK_BA);
         any_colmax |= colmax;
-        d.flags = colmax ? (flags & ~PDP_TASK_BA) | kTaskColmax : flags;
+        d.flags = (colmax ? (dflags & ~PDP_TASK_BA) | kTaskColmax : dflags) | (swap ? kTaskSwapped : 0u);
         d.theta_n = prm.theta_num;
         d.theta_d = prm.theta_den;
         d.tau_n = prm.tau_num;
@@ -335,20 +344,23 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         d.bpw = static_cast<uint32_t>(bpw);
         d.subs = static_cast<uint32_t>(subs);
         d.n_chunks = long_task ? 0u : static_cast<uint32_t>((nb + bpw * subs - 1) / (bpw * subs));
+        // output rows in the caller's orientation: a's genes (AB), then b's (BA)
+        uint32_t orow[2] = {UINT32_MAX, UINT32_MAX};
+        for (uint32_t odir = 0; odir < 2; ++odir) {
+            if (!(flags & (1u << odir))) continue;
+            orow[odir] = static_cast<uint32_t>(bh_rows);
+            bh_rows += (odir == 0 ? tk.a : tk.b)->n_genes;
+        }
         uint32_t ndirs = 0;
-        for (uint32_t dir = 0; dir < 2; ++dir) {
-            d.row_base[dir] = UINT32_MAX;
+        for (uint32_t dir = 0; dir < 2; ++dir) {  // the task's own directions from here on
+            d.row_base[dir] = orow[swap ? 1 - dir : dir];
             d.tile_shift[dir] = base_shift;
             d.tiles_n[dir] = 0;
-            if (!(flags & (1u << dir))) continue;
-            if ((dir == 1 && colmax) || long_task) {  // rows in the output, no tiles and no records of their own
-                d.row_base[dir] = static_cast<uint32_t>(bh_rows);
-                bh_rows += (dir == 0 ? tk.a : tk.b)->n_genes;
-                continue;
-            }
+            if (!(dflags & (1u << dir))) continue;
+            if ((dir == 1 && colmax) || long_task) continue;  // rows in the output, no tiles and no records of their own
             ++ndirs;
-            const pdp_dict *R = dir == 0 ? tk.a : tk.b;
-            const pdp_dict *C = dir == 0 ? tk.b : tk.a;
+            const pdp_dict *R = dir == 0 ? qa : qb;
+            const pdp_dict *C = dir == 0 ? qb : qa;
             // a tile whose records overflow the LDS sort is summed densely: the column genome's
             // window counts (16 bits each) and at least one row of packed 16-bit sums plus its
             // touched-word bitmap must fit
@@ -364,8 +376,6 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
             if (!prm.tile_rows && R->n_genes && R->capacity / R->n_genes > 512) d.tile_shift[dir] = kDefaultTileShift - 1;
             d.tiles_n[dir] = static_cast<uint32_t>((uint64_t(R->n_genes) + (1u << d.tile_shift[dir]) - 1) >>
                                                    d.tile_shift[dir]);
-            d.row_base[dir] = static_cast<uint32_t>(bh_rows);
-            bh_rows += R->n_genes;
         }
         // the join keeps one LDS counter per tile of the task: taller tiles when there are too many
         while (d.tiles_n[0] + d.tiles_n[1] > kJoinTileCap) {
@@ -375,7 +385,7 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
                                  kTileMaxRows));
             const uint32_t dir = can0 && (!can1 || d.tiles_n[0] >= d.tiles_n[1]) ? 0 : 1;
             ++d.tile_shift[dir];
-            const uint32_t nrows = dir == 0 ? tk.a->n_genes : tk.b->n_genes;
+            const uint32_t nrows = dir == 0 ? qa->n_genes : qb->n_genes;
             d.tiles_n[dir] = static_cast<uint32_t>((uint64_t(nrows) + (1u << d.tile_shift[dir]) - 1) >> d.tile_shift[dir]);
         }
         d.bbh_row_base = static_cast<uint32_t>(bbh_rows);
@@ -384,8 +394,8 @@ int32_t pdp_plan_create(const pdp_task *tasks, uint32_t n_tasks, const pdp_param
         // direction covers the family workloads with room; more needs a capacity retry
         rec_est += ndirs * ((tk.a->capacity + tk.b->capacity) / 8 + 4096);
         cost[t] = tk.a->capacity + tk.b->capacity;
-        P->ab_row.push_back(d.row_base[0]);
-        P->ba_row.push_back(d.row_base[1]);
+        P->ab_row.push_back(orow[0]);
+        P->ba_row.push_back(orow[1]);
         P->bbh_row.push_back((flags & PDP_TASK_BBH) ? d.bbh_row_base : UINT32_MAX);
         if (bh_rows >= UINT32_MAX) return bail(fail(PDP_E_LIMIT, "plan too large for 32-bit indices"));
     }

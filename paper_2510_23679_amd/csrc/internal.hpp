@@ -92,6 +92,9 @@ struct DevDict {
 // DevTask.flags: PDP_TASK_AB / PDP_TASK_BA select the join's record directions; a task whose
 // BA best hits come from the column maxima of its AB tiles has kTaskColmax instead of BA.
 constexpr uint32_t kTaskColmax = 8u;
+// DevTask.flags: a and b hold the caller's b and a (the smaller genome queries the join); the
+// directions (flags, tile fields, row bases) are the task's own, BBH rows keep the caller's a.
+constexpr uint32_t kTaskSwapped = 16u;
 
 struct DevTask {
     DevDict a, b;

@@ -1676,9 +1676,11 @@ __global__ __launch_bounds__(256) void k_bbh(const DevTask *__restrict__ tasks, 
     }
     if (WRITE && grow == 0 && out_ptr[bbh_rows] > cap) raise_status(st, PDP_E_CAPACITY, out_ptr[bbh_rows], 2);
     const DevTask &T = tasks[find_bbh_task(tasks, order, n_tasks, grow)];
-    const uint32_t a = grow - T.bbh_row_base;
-    bbh_row<WRITE>(a, grow, T.row_base[0] + a, T.row_base[1], T.b.n_genes, bh_ptr, bh_col, bh_num, bh_den, bh_cap, bh_ptr,
-                   bh_col, bh_cap, out_ptr, out_a, out_b, out_num, out_den, cap);
+    const uint32_t a = grow - T.bbh_row_base;  // a gene of the caller's a
+    const bool sw = T.flags & kTaskSwapped;    // the caller's a is the task's b
+    const uint32_t ab_base = T.row_base[sw ? 1 : 0], ba_base = T.row_base[sw ? 0 : 1];
+    bbh_row<WRITE>(a, grow, ab_base + a, ba_base, sw ? T.a.n_genes : T.b.n_genes, bh_ptr, bh_col, bh_num, bh_den, bh_cap,
+                   bh_ptr, bh_col, bh_cap, out_ptr, out_a, out_b, out_num, out_den, cap);
 }
 
 // pdp_bbh: the two best-hit outputs are the caller's.  A total past an output's capacity

@@ -148,15 +148,20 @@ def test_plan_layout():
 
 
 def test_colmax_plan_has_tiles_for_one_direction():
-    # column maxima: a task asking for both directions gets tiles (and records) for a's rows
-    # only, while b's rows keep their place in the output
+    # column maxima: a task asking for both directions gets tiles (and records) for one genome's
+    # rows only, the smaller one's (it queries the join), while the other's rows keep their place
+    # in the output
     a, b = _fake_dict(300, 90000, 5), _fake_dict(200, 60000, 5)
     L = pdp.lib()
     info = B.pdp_plan_info()
     rc, h = _plan([(a, b, pdp.PDP_TASK_BBH), (b, a, pdp.PDP_TASK_BA)], pdp.params(tile_rows=16, colmax=True))
     assert rc == 0 and L.pdp_plan_info_get(h, C.byref(info)) == 0
     assert info.bh_rows == 300 + 200 + 300 and info.bbh_rows == 300
-    assert info.tiles == 19 + 19  # a's rows of the BBH task, a's rows (as b) of the BA task
+    assert info.tiles == 13 + 19  # b's rows of the BBH task, a's rows (as b) of the BA task
+    L.pdp_plan_destroy(h)
+    rc, h = _plan([(b, a, pdp.PDP_TASK_BBH)], pdp.params(tile_rows=16, colmax=True))
+    assert rc == 0 and L.pdp_plan_info_get(h, C.byref(info)) == 0
+    assert info.tiles == 13 and info.bbh_rows == 200  # the same pair in the other order: b's rows again
     L.pdp_plan_destroy(h)
     bad = pdp.params()
     bad.flags = 8
@@ -165,6 +170,30 @@ def test_colmax_plan_has_tiles_for_one_direction():
     rc, h = _plan([(a, b, pdp.PDP_TASK_BBH)], pdp.params(two_pass=True))
     assert rc == 0
     L.pdp_plan_destroy(h)
+
+
+def test_smaller_genome_queries_the_join_in_the_callers_layout():
+    # the genome with fewer entries takes the join's query side whichever the caller named first;
+    # output rows (and the BBH rows, the caller's a) keep the caller's orientation
+    a, b = _fake_dict(300, 90000, 5), _fake_dict(200, 60000, 5)
+    L = pdp.lib()
+    info = B.pdp_plan_info()
+    none = 2 ** 32 - 1
+    for tasks, tiles, rows in (([(a, b, pdp.PDP_TASK_AB)], 19, [(0, none, none)]),
+                               ([(a, b, pdp.PDP_TASK_BA)], 13, [(none, 0, none)]),
+                               ([(b, a, pdp.PDP_TASK_AB | pdp.PDP_TASK_BA)], 13 + 19, [(0, 200, none)]),
+                               ([(a, b, pdp.PDP_TASK_BBH), (b, a, pdp.PDP_TASK_BBH)], 2 * (19 + 13),
+                                [(0, 300, 0), (500, 700, 300)])):
+        rc, h = _plan(tasks, pdp.params(tile_rows=16))
+        assert rc == 0 and L.pdp_plan_info_get(h, C.byref(info)) == 0
+        assert info.tiles == tiles
+        got = []
+        for t in range(len(tasks)):
+            x, y, z = B.u32(), B.u32(), B.u32()
+            assert L.pdp_plan_rows(h, t, C.byref(x), C.byref(y), C.byref(z)) == 0
+            got.append((x.value, y.value, z.value))
+        assert got == rows
+        L.pdp_plan_destroy(h)
 
 
 def test_long_gene_tasks_have_rows_but_no_join_or_tiles():
@@ -184,7 +213,7 @@ def test_long_gene_tasks_have_rows_but_no_join_or_tiles():
         assert rc == 0 and L.pdp_plan_info_get(h, C.byref(info)) == 0
         assert info.bh_rows == 500 + 500 + 200 and info.bbh_rows == 300 + 300
         assert info.join_groups == groups  # the first task's items only
-        assert info.tiles == (19 + 13 if not prm.flags else 19)
+        assert info.tiles == (19 + 13 if not prm.flags else 13)  # column maxima: the smaller genome's rows
         assert info.long_rows == 300 + 200 + 200
         rows = []
         for t in range(3):

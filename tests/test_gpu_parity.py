@@ -171,6 +171,23 @@ def test_query_bucket_modes(alphabet, k, genes, colmax):
     compare_all(ds.genomes, k, res)
 
 
+# The genome with fewer entries queries the join whichever the caller names first (the plan
+# swaps the task internally): both orders of a pair of unequal genomes, each with BH both ways
+# and BBH, and pdp_bh with either genome as the query, against the oracle.
+@pytest.mark.parametrize("colmax", [False, True])
+def test_both_orders_of_unequal_genomes(colmax):
+    say("both orders of an unequal pair, column maxima", colmax)
+    ds = make_config(3, genomes=2, genes_lo=150, genes_hi=450, core=120)
+    g0, g1 = ds.genomes
+    assert abs(int(g0.offsets[-1]) - int(g1.offsets[-1])) > 1000  # unequal, so one order swaps
+    pairs = [(0, 1), (1, 0)]
+    dicts, res = run_all(ds.genomes, 5, pdp.params(colmax=colmax), pairs=pairs)
+    compare_all(ds.genomes, 5, res, pairs=pairs)
+    og = [oracle.OracleGenome(g, 5) for g in ds.genomes]
+    for q, tg in ((0, 1), (1, 0)):
+        check_bh(pdp.bh(dicts[q], dicts[tg]).host(), oracle.bh(og[q], og[tg]))
+
+
 def test_paralog_ties():
     say("paralog copies (exact ties), 3 genomes")
     ds = make_config(3, genomes=3, genes_lo=300, genes_hi=500, core=150)
