@@ -213,11 +213,13 @@ def test_random_tiny_with_ties(seed):
     compare_all(gens, k, res)
 
 
-def test_genome_without_genes():
-    say("empty genome")
+@pytest.mark.parametrize("colmax", [False, True])
+def test_genome_without_genes(colmax):
+    # the empty genome is the smaller one, so it takes the join's query side (the task swaps)
+    say("empty genome, column maxima", colmax)
     a = genome_from_strings(["MKVLA", "MKVIA"])
     b = genome_from_strings([])
-    _, res = run_all([a, b], 2)
+    _, res = run_all([a, b], 2, pdp.params(colmax=colmax))
     ptr, col, _, _ = res.best_hits(0, 0)
     assert list(ptr) == [0, 0, 0] and len(col) == 0
     assert len(res.best_hits(0, 1)[0]) == 1
