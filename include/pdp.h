@@ -260,9 +260,10 @@ typedef struct pdp_params {
 #define PDP_PARAM_PERSISTENT 1u
 /* Column maxima (Alg. 3: a gene of the second genome takes as best hits the
  * rows at the maximum of its column of S): for a task that asks for both
- * directions, the best hits of b's genes come from the column maxima of the
- * similarities computed for a's genes, so the join emits shared-k-mer records
- * for one direction only.  Results are identical to the default.  The column
+ * directions, the best hits of one genome's genes come from the column maxima
+ * of the similarities computed for the other's (the genome with fewer k-mer
+ * entries, the join's query side), so the join emits shared-k-mer records for
+ * one direction only.  Results are identical to the default.  The column
  * candidates share the record capacity (PDP_E_CAPACITY with where = 0). */
 #define PDP_PARAM_COLMAX 2u
 /* The shared-k-mer join in two passes (count, then write) instead of one.  By
@@ -306,7 +307,10 @@ typedef struct pdp_plan_info {
 
 /* Builds a plan for n_tasks tasks.  Best-hit rows of the combined output are
  * laid out task by task: first a's genes (if AB), then b's genes (if BA); BBH
- * rows are a's genes of every task with PDP_TASK_BBH, task by task.
+ * rows are a's genes of every task with PDP_TASK_BBH, task by task.  Inside a
+ * task the join searches the entries of the genome with fewer k-mer entries
+ * (by dictionary capacity) in the other's index, whichever the caller named
+ * first; the outputs keep the caller's orientation.
  * pdp_plan_rows gives each task's first row in both outputs.  A task that
  * names a dictionary bound with PDP_DICT_LONG_GENES has no join items and no
  * tiles: its rows take the long-gene path (and PDP_PARAM_COLMAX does not apply
